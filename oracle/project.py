@@ -1,0 +1,309 @@
+"""EWA projection of 3-D Gaussians into one view, and its adjoint
+(oracle, test infrastructure).
+
+What is computed follows the 3DGS primitive of Sec. 3.1 (Eq. 1: alpha is
+the opacity times the Gaussian evaluated with its projected covariance)
+and the inputs the normal map and unbiased depth need (Sec. 3.3, Eqs. 6-7,
+PGSR strategy).  Constants the paper leaves unstated are fixed here:
+
+  * camera: p = R mu + t (OpenCV frame), culled unless p_z > z_near;
+  * 2-D mean u = fx p_x / p_z + cx, w = fy p_y / p_z + cy;
+  * Jacobian J of the perspective map with x/z, y/z clamped to 1.3 times
+    the half field of view; Sigma_2 = J R Sigma R^T J^T + 0.3 I;
+  * conic = Sigma_2^{-1}; radius r = ceil(3 sqrt(lambda_max(Sigma_2)));
+  * pixel box: the pixels whose centre lies within r of the 2-D mean in
+    both axes, clipped to the image; culled if empty;
+  * depth key = IEEE binary32 bits of p_z rounded to nearest;
+  * normal: the rotated axis of the smallest scale, in the camera frame,
+    turned to face the camera; plane distance d = -n . p (>= 0);
+  * colour: explicit Gaussians use max(0, SH(dir) k + 0.5) with dir the
+    unit vector from the camera centre to mu; anchor Gaussians use the
+    decoded colour.
+
+Decision values (p, u, w, the box, the depth key) are computed in float64
+with the fixed operation order written below, which the GPU path repeats
+exactly; the continuous attributes are computed in float64 here.
+"""
+import numpy as np
+
+from . import sh as shmod
+
+DILATION = 0.3
+GUARD = 1.3
+FRAG = 1e-5          # relative margin below which a decision is fragile
+
+
+def view_arrays(view):
+    """float64 copies of a view's float32 parameters and its camera centre
+    c = -R^T t (fixed order: ((R0j t0 + R1j t1) + R2j t2))."""
+    R = np.asarray(view.R, np.float32).reshape(3, 3).astype(np.float64)
+    t = np.asarray(view.t, np.float32).reshape(3).astype(np.float64)
+    c = np.array([-((R[0, j] * t[0] + R[1, j] * t[1]) + R[2, j] * t[2]) for j in range(3)])
+    f = lambda v: float(np.float32(v))   # noqa: E731
+    return dict(R=R, t=t, c=c, W=int(view.width), H=int(view.height),
+                fx=f(view.fx), fy=f(view.fy), cx=f(view.cx), cy=f(view.cy),
+                z_near=f(view.z_near),
+                bg=np.asarray(view.bg, np.float32).astype(np.float64))
+
+
+def camera_point(R, t, m):
+    """p_i = ((R_i0 m_0 + R_i1 m_1) + R_i2 m_2) + t_i, float64, no fused ops."""
+    return np.stack([((R[i, 0] * m[:, 0] + R[i, 1] * m[:, 1]) + R[i, 2] * m[:, 2]) + t[i]
+                     for i in range(3)], axis=1)
+
+
+def quat_to_rot(qn):
+    """Rotation matrix of a unit quaternion (w, x, y, z): (N, 3, 3)."""
+    w, x, y, z = qn[:, 0], qn[:, 1], qn[:, 2], qn[:, 3]
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1),
+    ], 1)
+
+
+def quat_to_rot_backward(qn, dR):
+    """Adjoint of quat_to_rot: dR (N,3,3) -> d qn (N,4)."""
+    w, x, y, z = qn[:, 0], qn[:, 1], qn[:, 2], qn[:, 3]
+    g = dR
+    dw = 2 * (-z * g[:, 0, 1] + y * g[:, 0, 2] + z * g[:, 1, 0] - x * g[:, 1, 2]
+              - y * g[:, 2, 0] + x * g[:, 2, 1])
+    dx = 2 * (y * g[:, 0, 1] + z * g[:, 0, 2] + y * g[:, 1, 0] - 2 * x * g[:, 1, 1]
+              - w * g[:, 1, 2] + z * g[:, 2, 0] + w * g[:, 2, 1] - 2 * x * g[:, 2, 2])
+    dy = 2 * (-2 * y * g[:, 0, 0] + x * g[:, 0, 1] + w * g[:, 0, 2] + x * g[:, 1, 0]
+              + z * g[:, 1, 2] - w * g[:, 2, 0] + z * g[:, 2, 1] - 2 * y * g[:, 2, 2])
+    dz = 2 * (-2 * z * g[:, 0, 0] - w * g[:, 0, 1] + x * g[:, 0, 2] + w * g[:, 1, 0]
+              - 2 * z * g[:, 1, 1] + y * g[:, 1, 2] + x * g[:, 2, 0] + y * g[:, 2, 1])
+    return np.stack([dw, dx, dy, dz], 1)
+
+
+def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0):
+    """Project N Gaussians into one view.
+
+    mu: (N,3) float64 centres (for explicit Gaussians the float32 inputs
+    widened; for anchors x + O*l evaluated in float64).  scales (N,3),
+    quats (N,4) raw (w,x,y,z), opacity (N,).  Colour is either given
+    (N,3) or evaluated from sh (N,K,3).  tile = (tw, th).
+
+    Returns a dict of per-Gaussian arrays; `valid` marks the splats that
+    survive culling and touch at least one tile.
+    """
+    V = view_arrays(view)
+    R, t, c = V["R"], V["t"], V["c"]
+    W, H, fx, fy, cx, cy = V["W"], V["H"], V["fx"], V["fy"], V["cx"], V["cy"]
+    tw, th = tile
+    mu = np.asarray(mu, np.float64)
+    n = mu.shape[0]
+    s = np.asarray(scales, np.float64)
+    q = np.asarray(quats, np.float64)
+    o = np.asarray(opacity, np.float64)
+
+    # ---- decision values, float64, fixed order --------------------------
+    p = camera_point(R, t, mu)
+    front = p[:, 2] > V["z_near"]
+    pz = np.where(front, p[:, 2], 1.0)
+    u = (fx * p[:, 0]) / pz + cx
+    w = (fy * p[:, 1]) / pz + cy
+    zbits = p[:, 2].astype(np.float32).view(np.uint32)
+
+    # ---- EWA covariance --------------------------------------------------
+    lim_x = (GUARD * W) / (2.0 * fx)
+    lim_y = (GUARD * H) / (2.0 * fy)
+    rx, ry = p[:, 0] / pz, p[:, 1] / pz
+    clamp_x = (rx < -lim_x) | (rx > lim_x)
+    clamp_y = (ry < -lim_y) | (ry > lim_y)
+    txz = np.clip(rx, -lim_x, lim_x) * pz
+    tyz = np.clip(ry, -lim_y, lim_y) * pz
+    T0 = (fx / pz)[:, None] * R[0][None] - (fx * txz / pz ** 2)[:, None] * R[2][None]
+    T1 = (fy / pz)[:, None] * R[1][None] - (fy * tyz / pz ** 2)[:, None] * R[2][None]
+    qnorm = np.maximum(np.linalg.norm(q, axis=1), 1e-12)
+    qn = q / qnorm[:, None]
+    Rq = quat_to_rot(qn)
+    M = Rq * s[:, None, :]
+    V0 = np.einsum("nj,njk->nk", T0, M)
+    V1 = np.einsum("nj,njk->nk", T1, M)
+    A = np.sum(V0 * V0, 1) + DILATION
+    B = np.sum(V0 * V1, 1)
+    Cc = np.sum(V1 * V1, 1) + DILATION
+    det = A * Cc - B * B
+    ok = front & (det > 0)
+    dets = np.where(ok, det, 1.0)
+    conic = np.stack([Cc / dets, -B / dets, A / dets], 1)
+    mid = 0.5 * (A + Cc)
+    half = 0.5 * (A - Cc)
+    lam = mid + np.sqrt(half * half + B * B)
+    r3 = 3.0 * np.sqrt(lam)
+    r3 = np.where(ok, r3, 0.0)
+    r = np.ceil(np.minimum(r3, 1 << 20))
+    frag_r = ok & (np.abs(r3 - np.round(r3)) < FRAG * np.maximum(r3, 1.0))
+
+    # ---- pixel box (exact given r) ---------------------------------------
+    x_lo = np.ceil(u - (r + 0.5))
+    x_hi = np.floor(u + (r - 0.5))
+    y_lo = np.ceil(w - (r + 0.5))
+    y_hi = np.floor(w + (r - 0.5))
+    x_lo = np.clip(np.where(ok, x_lo, W), 0, W).astype(np.int64)
+    x_hi = np.clip(np.where(ok, x_hi, -1), -1, W - 1).astype(np.int64)
+    y_lo = np.clip(np.where(ok, y_lo, H), 0, H).astype(np.int64)
+    y_hi = np.clip(np.where(ok, y_hi, -1), -1, H - 1).astype(np.int64)
+    valid = ok & (x_lo <= x_hi) & (y_lo <= y_hi)
+
+    # ---- normal and plane distance (PGSR, Eqs. 6-7) ---------------------
+    Rc = np.einsum("ij,njk->nik", R, Rq)
+    jstar = np.argmin(s, axis=1)
+    nvec = Rc[np.arange(n), :, jstar]
+    ndp = np.sum(nvec * p, 1)
+    sign = np.where(ndp > 0, -1.0, 1.0)
+    nvec = nvec * sign[:, None]
+    d = -np.sum(nvec * p, 1)
+    ssort = np.sort(s, axis=1)
+    frag_axis = (ssort[:, 1] - ssort[:, 0]) < FRAG * ssort[:, 0]
+    frag_flip = np.abs(ndp) < FRAG * np.linalg.norm(p, axis=1)
+
+    # ---- colour ----------------------------------------------------------
+    frag_colour = np.zeros(n, bool)
+    dirs = None
+    if colour is None:
+        k = np.asarray(sh, np.float64)
+        dv = mu - c[None]
+        dn = np.linalg.norm(dv, axis=1)
+        dirs = dv / dn[:, None]
+        Y = shmod.basis(dirs, sh_degree)
+        raw = np.einsum("nk,nkc->nc", Y, k) + 0.5
+        rgb = np.maximum(raw, 0.0)
+        frag_colour = np.any(np.abs(raw) < FRAG, 1)
+    else:
+        raw = np.asarray(colour, np.float64)
+        rgb = raw
+
+    # ---- tiles -------------------------------------------------------------
+    TX = -(-W // tw)
+    TY = -(-H // th)
+    tx0, tx1 = x_lo // tw, x_hi // tw
+    ty0, ty1 = y_lo // th, y_hi // th
+    count = np.where(valid, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
+
+    return dict(
+        n=n, valid=valid, p=p, u=u, w=w, zbits=zbits, conic=conic, r=r.astype(np.int64),
+        box=np.stack([x_lo, x_hi, y_lo, y_hi], 1), opacity=o, rgb=rgb, raw_rgb=raw,
+        normal=nvec, d=d, sign=sign, jstar=jstar,
+        tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, TX=TX, TY=TY,
+        frag_value=valid & (frag_r | frag_axis | frag_flip),
+        frag_grad=valid & (frag_colour | clamp_x | clamp_y
+                           | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)
+                           | (np.abs(np.abs(ry) - lim_y) < FRAG * lim_y)),
+        # intermediates for the adjoint
+        _s=s, _q=q, _qn=qn, _qnorm=qnorm, _Rq=Rq, _M=M, _T0=T0, _T1=T1, _V0=V0, _V1=V1,
+        _A=A, _B=B, _C=Cc, _det=dets, _pz=pz, _txz=txz, _tyz=tyz,
+        _clamp_x=clamp_x, _clamp_y=clamp_y, _lim=(lim_x, lim_y), _dirs=dirs,
+        _mu=mu, _view=V, _sh_degree=sh_degree,
+        _sh=(None if sh is None else np.asarray(sh, np.float64)),
+    )
+
+
+def project_backward(P, g):
+    """Adjoint of `project`.
+
+    g: dict of per-splat gradients (N rows) with keys mean2d (N,2),
+    conic (N,3), opacity (N,), rgb (N,3), d (N,), normal (N,3).
+    Returns dict with mu (N,3), scales (N,3), quats (N,4) (raw quaternion),
+    opacity (N,), and either sh (N,K,3) (explicit) or rgb (N,3) (given
+    colour, before any clamp).
+    """
+    V = P["_view"]
+    R = V["R"]
+    fx, fy = V["fx"], V["fy"]
+    n = P["n"]
+    valid = P["valid"][:, None]
+    z = lambda a: np.where(valid if a.ndim == 2 else P["valid"], a, 0.0)  # noqa: E731
+    dmean = z(np.asarray(g["mean2d"], np.float64))
+    dconic = z(np.asarray(g["conic"], np.float64))
+    dop = z(np.asarray(g["opacity"], np.float64))
+    drgb = z(np.asarray(g["rgb"], np.float64))
+    dd = z(np.asarray(g["d"], np.float64))
+    dnorm = z(np.asarray(g["normal"], np.float64))
+
+    p, pz = P["p"], P["_pz"]
+    dp = np.zeros((n, 3))
+    # 2-D mean
+    dp[:, 0] += dmean[:, 0] * fx / pz
+    dp[:, 1] += dmean[:, 1] * fy / pz
+    dp[:, 2] += -dmean[:, 0] * fx * p[:, 0] / pz ** 2 - dmean[:, 1] * fy * p[:, 1] / pz ** 2
+
+    # conic -> Sigma_2 entries (A, B, C)
+    A, B, Cc, det = P["_A"], P["_B"], P["_C"], P["_det"]
+    dca, dcb, dcc = dconic[:, 0], dconic[:, 1], dconic[:, 2]
+    dA = dcc / det
+    dB = -dcb / det
+    dC = dca / det
+    ddet = -(dca * Cc + dcc * A) / det ** 2 + dcb * B / det ** 2
+    dA += ddet * Cc
+    dC += ddet * A
+    dB += -2.0 * B * ddet
+    V0, V1 = P["_V0"], P["_V1"]
+    dV0 = 2 * dA[:, None] * V0 + dB[:, None] * V1
+    dV1 = 2 * dC[:, None] * V1 + dB[:, None] * V0
+    M, T0, T1 = P["_M"], P["_T0"], P["_T1"]
+    dT0 = np.einsum("nk,njk->nj", dV0, M)
+    dT1 = np.einsum("nk,njk->nj", dV1, M)
+    dM = T0[:, :, None] * dV0[:, None, :] + T1[:, :, None] * dV1[:, None, :]
+
+    # T rows -> p (through 1/z and the clamped x/z, y/z)
+    txz, tyz = P["_txz"], P["_tyz"]
+    a0 = np.sum(dT0 * R[0][None], 1)
+    b0 = np.sum(dT0 * R[2][None], 1)
+    a1 = np.sum(dT1 * R[1][None], 1)
+    b1 = np.sum(dT1 * R[2][None], 1)
+    dpz = -a0 * fx / pz ** 2 - a1 * fy / pz ** 2
+    dpz += b0 * 2 * fx * txz / pz ** 3 + b1 * 2 * fy * tyz / pz ** 3
+    dtx = -b0 * fx / pz ** 2
+    dty = -b1 * fy / pz ** 2
+    lim_x, lim_y = P["_lim"]
+    rx, ry = p[:, 0] / pz, p[:, 1] / pz
+    cxm, cym = P["_clamp_x"], P["_clamp_y"]
+    dp[:, 0] += np.where(cxm, 0.0, dtx)
+    dp[:, 1] += np.where(cym, 0.0, dty)
+    dpz += np.where(cxm, dtx * np.clip(rx, -lim_x, lim_x), 0.0)
+    dpz += np.where(cym, dty * np.clip(ry, -lim_y, lim_y), 0.0)
+    dp[:, 2] += dpz
+
+    # M = Rq diag(s)
+    s, Rq = P["_s"], P["_Rq"]
+    ds = np.sum(dM * Rq, 1)
+    dRq = dM * s[:, None, :]
+
+    # normal and plane distance: n = sign * R Rq[:, j*], d = -n.p
+    nvec = P["normal"]
+    dn_tot = dnorm - dd[:, None] * p
+    dp += -dd[:, None] * nvec
+    col = np.einsum("ji,nj->ni", R, dn_tot) * P["sign"][:, None]
+    dRq[np.arange(n), :, P["jstar"]] += col
+
+    # colour
+    out = {}
+    mu = P["_mu"]
+    dmu = np.einsum("ji,nj->ni", R, dp)
+    if P["_sh"] is not None:
+        raw = P["raw_rgb"]
+        geff = np.where(raw > 0, drgb, 0.0)
+        dirs = P["_dirs"]
+        Y = shmod.basis(dirs, P["_sh_degree"])
+        out["sh"] = Y[:, :, None] * geff[:, None, :]
+        dY = shmod.basis_grad(dirs, P["_sh_degree"])
+        ddir = np.einsum("nc,nkc,nkj->nj", geff, P["_sh"], dY)
+        dv = mu - V["c"][None]
+        dn_ = np.linalg.norm(dv, axis=1)
+        proj = ddir - dirs * np.sum(dirs * ddir, 1, keepdims=True)
+        dmu += proj / dn_[:, None]
+    else:
+        out["rgb"] = drgb
+
+    # quaternion: qn = q / |q|
+    qn, qnorm = P["_qn"], P["_qnorm"]
+    dqn = quat_to_rot_backward(qn, dRq)
+    dq = (dqn - qn * np.sum(qn * dqn, 1, keepdims=True)) / qnorm[:, None]
+
+    out.update(mu=dmu * valid, scales=ds * valid, quats=dq * valid, opacity=dop)
+    if "sh" in out:
+        out["sh"] = out["sh"] * valid[:, :, None]
+    return out

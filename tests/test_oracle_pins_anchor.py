@@ -1,0 +1,156 @@
+"""Pins of the oracle's anchor selection and decoder (CPU only)."""
+import math
+
+import numpy as np
+
+from oracle import anchors, pipeline
+from synth import scenes
+
+
+class _A:
+    pass
+
+
+def _anchor_scene(x, level, d_max, F=None, n=10):
+    a = len(x)
+    s = _A()
+    s.x = np.asarray(x, np.float32)
+    s.level = np.asarray(level, np.uint8)
+    s.d_max = d_max
+    s.l = np.full((a, 3), 0.5, np.float32)
+    s.O = np.zeros((a, n, 3), np.float32)
+    s.F = np.zeros((a, 32), np.float32) if F is None else np.asarray(F, np.float32)
+    s.W1_bits = np.zeros((36, 32), np.uint16)
+    s.W2_bits = np.zeros((32, 11 * n), np.uint16)
+    s.b1 = np.zeros(32, np.float32)
+    s.b2 = np.zeros(11 * n, np.float32)
+    s.n_levels = 4
+    return s
+
+
+def test_lod_rule_matches_log2_definition():
+    """level <= clamp(floor(log2(d_max / dist)), 0, K-1), evaluated with
+    math.log2 on anchors away from the level boundaries."""
+    rng = np.random.default_rng(1)
+    view = scenes.look_at((0.0, 0.0, 50.0), (0.0, 0.0, 0.0), 64, 64, fov_deg=120)
+    a = 4000
+    x = np.stack([rng.uniform(-20, 20, a), rng.uniform(-20, 20, a), rng.uniform(-45, 10, a)], 1)
+    level = rng.integers(0, 4, a)
+    sc = _anchor_scene(x, level, 400.0)
+    rows, offs = anchors.select(sc, [view])
+    got = np.zeros(a, bool)
+    got[rows[:, 1]] = True
+    c = -view.R.astype(np.float64).T @ view.t.astype(np.float64)
+    checked = 0
+    for i in range(a):
+        xi = sc.x[i].astype(np.float64)
+        pc = view.R.astype(np.float64) @ xi + view.t
+        gx = 1.3 * 64 / (2 * view.fx)
+        inside = pc[2] > 0.2 and abs(pc[0]) <= gx * pc[2] and abs(pc[1]) <= gx * pc[2]
+        dist = math.dist(xi, c)
+        y = math.log2(400.0 / dist)
+        if abs(y - round(y)) < 1e-6:
+            continue
+        lhat = min(max(math.floor(y), 0), 3)
+        assert got[i] == (inside and level[i] <= lhat), i
+        checked += 1
+    assert checked > 3900
+    assert 0 < got.sum() < a
+    # rows are in (view, anchor) order
+    assert np.all(np.diff(rows[:, 1]) > 0)
+
+
+def test_frustum_test_on_constructed_points():
+    view = scenes.look_at((0.0, 0.0, 10.0), (0.0, 0.0, 0.0), 100, 50, yaw_hint=0.0)
+    # camera looks down -z; right = +x (yaw 0), down = -y.  tan(half fov x) = 0.5 * 100 / fx
+    fx = view.fx
+    gx = 1.3 * 100 / (2 * fx)
+    gy = 1.3 * 50 / (2 * fx)
+    z = 10.0
+    pts = [(0, 0, 0), (0.99 * gx * z, 0, 0), (1.01 * gx * z, 0, 0), (0, 0.99 * gy * z, 0),
+           (0, -1.01 * gy * z, 0), (0, 0, 9.9), (0, 0, 10.5)]
+    expect = [True, True, False, True, False, False, False]
+    sc = _anchor_scene(pts, [0] * len(pts), 1e6)
+    rows, _ = anchors.select(sc, [view])
+    got = np.zeros(len(pts), bool)
+    got[rows[:, 1]] = True
+    # (0,0,9.9) is 0.1 in front of the camera, inside z_near = 0.2
+    assert got.tolist() == expect
+
+
+def test_decoder_hand_example():
+    """One anchor seen from straight above at distance 5 (d_max = 10):
+    d~ = (0, 0, 1), Delta = 0.5.  Hand-set weights route F_0 = 2, d~_z and
+    Delta through three hidden units; the decoded attributes are worked out
+    by hand below (Eq. 4, decoder layout: 11 outputs per Gaussian)."""
+    n = 10
+    F = np.zeros((1, 32), np.float32)
+    F[0, 0] = 2.0
+    sc = _anchor_scene([(1.0, 2.0, 0.0)], [0], 10.0, F=F, n=n)
+    sc.l = np.array([[0.5, 0.25, 1.0]], np.float32)
+    sc.O = np.zeros((1, n, 3), np.float32)
+    sc.O[0, 3] = (1.0, -2.0, 0.5)
+    W1 = np.zeros((36, 32), np.float32)
+    W1[0, 0] = 1.0          # h0 = F_0 = 2
+    W1[34, 1] = 1.0         # h1 = d~_z = 1 (camera above)
+    W1[35, 2] = 1.0         # h2 = relu(Delta - 0.25) = 0.25
+    W1[0, 3] = -1.0         # h3 = relu(-F_0) = 0
+    b1 = np.zeros(32, np.float32)
+    b1[2] = -0.25
+    W2 = np.zeros((32, 11 * n), np.float32)
+    W2[0, 1] = 1.0          # rgb_r logit = h0 = 2
+    W2[1, 2] = -2.0         # rgb_g logit = -2 h1 = -2
+    W2[2, 4] = 4.0          # scale_x logit = 4 h2 = 1
+    W2[3, 6] = 5.0          # scale_z logit = 5 h3 = 0
+    W2[1, 7] = 1.0          # quat w = h1 = 1
+    W2[0, 11 * 3 + 0] = 0.5   # Gaussian 3 opacity logit = 0.5 h0 = 1
+    b2 = np.zeros(11 * n, np.float32)
+    for k in range(1, n):
+        b2[11 * k + 8] = 1.0   # Gaussians 1..9: quat = (0, 1, 0, 0)
+    sc.W1_bits = scenes.bf16_bits(W1)
+    sc.W2_bits = scenes.bf16_bits(W2)
+    sc.b1, sc.b2 = b1, b2
+    view = scenes.look_at((1.0, 2.0, 5.0), (1.0, 2.0, 0.0), 32, 32, yaw_hint=0.3)
+    rows, _ = anchors.select(sc, [view])
+    assert rows.tolist() == [[0, 0]]
+    D = anchors.decode(sc, [view], rows)
+    sg = lambda v: 1.0 / (1.0 + math.exp(-v))   # noqa: E731
+    np.testing.assert_allclose(D["opacity"][0], 0.5, atol=1e-15)
+    np.testing.assert_allclose(D["rgb"][0], [sg(2.0), sg(-2.0), 0.5], atol=1e-15)
+    np.testing.assert_allclose(D["scales"][0], [0.5 * sg(1.0), 0.25 * 0.5, 0.5], atol=1e-15)
+    np.testing.assert_allclose(D["quats"][0], [1.0, 0, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(D["opacity"][3], sg(1.0), atol=1e-15)
+    np.testing.assert_allclose(D["quats"][5], [0, 1.0, 0, 0], atol=1e-15)
+    # mu_k = x + O_k * l (elementwise)
+    np.testing.assert_allclose(D["mu"][3], [1.0 + 0.5, 2.0 - 0.5, 0.0 + 0.5], atol=1e-15)
+    np.testing.assert_allclose(D["mu"][0], [1.0, 2.0, 0.0], atol=1e-15)
+
+
+def test_bf16_feature_rounding_is_the_only_decoder_quantisation():
+    """With emulate_bf16 the decoded attributes differ from pure float64 only
+    through the bfloat16 rounding of F; with bf16-exact features the two
+    agree to float64 rounding.  The size of the bf16 effect on a random
+    scene is reported (stated, not a pin)."""
+    wl = scenes.make_small_anchor(3, n_anchor=40)
+    sc = wl.scene
+    rows, _ = anchors.select(sc, wl.views)
+    D1 = anchors.decode(sc, wl.views, rows, emulate_bf16=True)
+    D0 = anchors.decode(sc, wl.views, rows, emulate_bf16=False)
+    rel = np.max(np.abs(D1["rgb"] - D0["rgb"]))
+    assert 1e-6 < rel < 5e-2
+    sc.F = scenes.bf16_value(scenes.bf16_bits(sc.F))
+    D2 = anchors.decode(sc, wl.views, rows, emulate_bf16=True)
+    D3 = anchors.decode(sc, wl.views, rows, emulate_bf16=False)
+    for k in ("rgb", "scales", "opacity", "quats"):
+        np.testing.assert_allclose(D2[k], D3[k], rtol=1e-14, atol=1e-15)
+
+
+def test_anchor_render_runs_and_respects_invariants():
+    wl = scenes.make_small_anchor(5)
+    r = pipeline.render_anchor(wl.scene, wl.views)
+    for img in r.images:
+        assert img["T"].min() >= 1e-4
+        assert img["alpha"].max() < 1.0
+    assert r.rows.shape[0] > 0
+    # each view renders only its own rows
+    assert r.row_off[-1] == r.rows.shape[0]
