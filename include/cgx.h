@@ -1,0 +1,244 @@
+/*
+ * cgx.h -- C ABI of libcgx, a batched differentiable RGB-D-N Gaussian
+ * rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * What it computes (CityGS-X, arXiv 2503.23044):
+ *   - voxel anchors with a feature F in R^32, scaling l in R^3, position x
+ *     and n offsets O in R^{n x 3} are decoded by a shared MLP into n
+ *     Gaussians each, mu_k = x + O_k * l (Sec. 3.2, Eq. 4); the level of
+ *     detail is picked by observation distance (Sec. 3.1) and only voxels
+ *     that intersect a view are decoded (Sec. 3.3);
+ *   - or explicit 3-D Gaussians with spherical-harmonic colour are given;
+ *   - every view of a batch (up to 32 views, Sec. 3.3) is cut into tiles
+ *     (16x16 patches, Sec. 3.3), the Gaussians are sorted per tile by depth
+ *     (the reordering pi of Eq. 5) and blended front to back into the
+ *     colour image (Eqs. 1, 5), the normal map (Eq. 6) and the blended
+ *     plane-distance map D with the unbiased depth D / (N . K^-1 p~)
+ *     (Eq. 7);
+ *   - the backward pass returns the gradients of a loss through all of it,
+ *     either from given output gradients or from the batch L1 loss of
+ *     Eq. 8 computed in the same launch chain.
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers unless a comment says host.
+ *     The library never allocates device memory: the caller passes one
+ *     workspace buffer whose size cgx_workspace_size reports.  Results
+ *     and the forward state kept for the backward pass live in it.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue
+ *     work and return; nothing synchronises except cgx_read_info and
+ *     cgx_debug_copy.
+ *   - Every call returns a cgx_status; no exception crosses the ABI.
+ *     cgx_last_error returns a message for the last failing call on the
+ *     context.  Invalid arguments are detected on the host before any
+ *     launch.
+ *   - Data-dependent sizes (active anchors, visible splats, tile pairs)
+ *     are bounded by the capacities in cgx_capacity.  A launch chain that
+ *     would exceed one clamps every write to the capacity, records the
+ *     size it needed in the workspace and skips the remaining work; the
+ *     next cgx_read_info returns CGX_ERR_CAPACITY with the needed sizes.
+ *   - Layouts: views are packed in order; view v's pixels start at
+ *     pix_off[v] = sum_{u<v} W_u H_u.  Per-pixel images are planar per
+ *     view: a C-channel image of view v occupies C * W_v * H_v floats
+ *     starting at C * pix_off[v], channel-major, rows of W_v pixels.
+ */
+#ifndef CGX_H
+#define CGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGX_ABI_VERSION 1
+#define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
+#define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
+#define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
+#define CGX_MLP_HIDDEN 32
+#define CGX_GAUSS_OUT 11       /* per Gaussian: opacity 1, rgb 3, scale 3, quaternion 4 */
+#define CGX_MAX_OFFSETS 16
+
+typedef enum cgx_status {
+  CGX_OK = 0,
+  CGX_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad enum */
+  CGX_ERR_UNSUPPORTED = 2,   /* e.g. SH degree > 3, tile shape not compiled */
+  CGX_ERR_CAPACITY = 3,      /* a capacity was exceeded; see cgx_run_info */
+  CGX_ERR_HIP = 4,           /* a HIP runtime call failed */
+  CGX_ERR_WORKSPACE = 5      /* workspace smaller than cgx_workspace_size */
+} cgx_status;
+
+typedef struct cgx_ctx cgx_ctx;
+
+/* Pinhole camera, OpenCV frame (x right, y down, z forward).  A world
+ * point X maps to p = R X + t; pixel (i, j) has its centre at
+ * (i + 0.5, j + 0.5); u = fx p_x / p_z + cx.  Host memory. */
+typedef struct cgx_view {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];        /* world -> camera rotation, row-major */
+  float t[3];
+  float z_near;      /* splats and anchors with p_z <= z_near are culled */
+  float bg[3];       /* background colour, added with the final transmittance */
+} cgx_view;
+
+enum { CGX_SCENE_EXPLICIT = 0, CGX_SCENE_ANCHOR = 1 };
+
+/* Explicit Gaussians (device arrays, N-major):
+ *   means [N][3], scales [N][3] (> 0), quats [N][4] (w, x, y, z; normalised
+ *   inside), opacity [N] in (0, 1), sh [N][(deg+1)^2][3].
+ * Colour = max(0, sum_i Y_i(dir) sh_i + 0.5), dir = unit vector from the
+ * camera centre to the mean; real orthonormal SH basis, no Condon-Shortley
+ * phase, index l*l + l + m. */
+typedef struct cgx_explicit_scene {
+  int64_t n;
+  int32_t sh_degree;            /* 0..3 */
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const float* sh;
+} cgx_explicit_scene;
+
+/* Voxel anchors (Sec. 3.2, Eq. 4; device arrays, anchor-major):
+ *   x [A][3], l [A][3], O [A][n][3], F [A][32] float32, level [A] uint8
+ *   (0 = coarsest).  Decoder: W1 [36][32] and W2 [32][11 n] as bfloat16 bit
+ *   patterns (input-major: out = in . W + b), b1 [32], b2 [11 n] float32.
+ * Anchor a is active in view v when level[a] == 0 or
+ *   |x_a - c_v|^2 4^level[a] <= d_max^2 (that is, level[a] <=
+ *   floor(log2(d_max / |x_a - c_v|)), clamped to [0, K-1]), and its centre
+ *   passes the frustum test p_z > z_near, |p_x| <= 1.3 W/(2 fx) p_z,
+ *   |p_y| <= 1.3 H/(2 fy) p_z; both in float64.
+ * Decoder input z0 = [bf16(F), (c_v - x_a)/|c_v - x_a|, |c_v - x_a|/d_max],
+ *   z1 = relu(z0 W1 + b1), z2 = z1 W2 + b2; Gaussian k reads z2[11k..11k+10]
+ *   as opacity = sigmoid, rgb = sigmoid, scale = l * sigmoid, quaternion
+ *   (normalised at projection); mu_k = x + O_k * l. */
+typedef struct cgx_anchor_scene {
+  int64_t n_anchor;
+  int32_t n_offsets;            /* n, 1..16 */
+  int32_t n_levels;             /* K */
+  float d_max;
+  const float* x;
+  const float* l;
+  const float* O;
+  const float* F;
+  const uint8_t* level;
+  const uint16_t* W1;
+  const float* b1;
+  const uint16_t* W2;
+  const float* b2;
+} cgx_anchor_scene;
+
+typedef struct cgx_scene {
+  int32_t kind;                 /* CGX_SCENE_EXPLICIT or CGX_SCENE_ANCHOR */
+  cgx_explicit_scene ex;
+  cgx_anchor_scene an;
+} cgx_scene;
+
+/* Per-pixel images (device, planar per view as described above).
+ *   rgb 3 channels, depth = unbiased depth D^ (Eq. 7; 0 where the blended
+ *   normal is not facing the ray), plane_d = blended distance D (Eq. 7),
+ *   normal 3 channels (camera frame, Eq. 6), alpha = 1 - final
+ *   transmittance.  Any pointer may be NULL on output except where noted. */
+typedef struct cgx_images {
+  float* rgb;
+  float* depth;
+  float* plane_d;
+  float* normal;
+  float* alpha;
+} cgx_images;
+
+/* Gradients (device), same layouts as the scene arrays; W1 / W2 gradients
+ * are float32 [36][32] and [32][11 n].  The backward call overwrites them. */
+typedef struct cgx_grads {
+  float* means; float* scales; float* quats; float* opacity; float* sh;
+  float* x; float* l; float* O; float* F;
+  float* W1; float* b1; float* W2; float* b2;
+} cgx_grads;
+
+/* Upper bounds of the data-dependent sizes.  Zero = the safe bound
+ * (n_views * n_anchor rows; n_views * N or 16 n_rows splats; for pairs
+ * there is no safe bound and zero means 8 x splats). */
+typedef struct cgx_capacity {
+  int64_t max_rows;     /* active (view, anchor) rows */
+  int64_t max_splats;   /* splat slots (explicit: n_views * N) */
+  int64_t max_pairs;    /* (tile, splat) pairs */
+} cgx_capacity;
+
+typedef struct cgx_run_info {
+  int64_t n_rows;       /* active anchor rows (anchor scenes) */
+  int64_t n_splats;     /* splat slots projected */
+  int64_t n_pairs;      /* (tile, splat) pairs sorted */
+  int32_t overflow;     /* bit 0 rows, bit 1 splats, bit 2 pairs */
+  int32_t reserved;
+  int64_t need_rows, need_splats, need_pairs;
+  double loss;          /* L1 loss of the last fused call */
+  uint64_t entries_fwd; /* sum over pixels of list entries walked forward */
+  uint64_t entries_bwd; /* sum over pixels of list entries walked backward */
+  int64_t n_tiles;
+  int64_t n_pixels;
+} cgx_run_info;
+
+/* Library version (CGX_ABI_VERSION). */
+int32_t cgx_abi_version(void);
+
+/* Create a context bound to HIP device `device` with tile shape
+ * tile_w x tile_h (16 x 16 is the paper's patch; 8x8, 16x8, 32x8 also
+ * compiled).  Returns CGX_ERR_UNSUPPORTED for other shapes. */
+int32_t cgx_create(cgx_ctx** out, int32_t device, int32_t tile_w, int32_t tile_h);
+int32_t cgx_destroy(cgx_ctx* ctx);
+
+/* Message of the last error on ctx (a static string if ctx is NULL). */
+const char* cgx_last_error(const cgx_ctx* ctx);
+
+/* Bytes of workspace for this batch, scene and capacity (host arithmetic,
+ * no device work).  views: host array of n_views. */
+int32_t cgx_workspace_size(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const cgx_scene* scene, const cgx_capacity* cap, size_t* bytes);
+
+/* Forward render: fills `out` (every non-NULL image) and the forward
+ * state in `workspace` that cgx_render_backward reads. */
+int32_t cgx_render_forward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const cgx_scene* scene, const cgx_capacity* cap,
+                           void* workspace, size_t workspace_bytes,
+                           const cgx_images* out, void* stream);
+
+/* Backward pass after cgx_render_forward with the same arguments and an
+ * untouched workspace.  `out` holds the forward images (plane_d and normal
+ * are required), `grad_out` the loss gradients w.r.t. them (NULL pointers =
+ * zero gradient).  Writes the gradients of the scene's inputs. */
+int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                            const cgx_scene* scene, const cgx_capacity* cap,
+                            void* workspace, size_t workspace_bytes,
+                            const cgx_images* out, const cgx_images* grad_out,
+                            const cgx_grads* grads, void* stream);
+
+/* One launch chain: forward, the batch L1 loss of Eq. 8 against `target`
+ * (rgb, depth and normal, weights w[0..2]; per-image mean over pixels,
+ * averaged over the batch, sign(0) = 0) and the backward pass.  loss_dev:
+ * one float on the device receiving the loss (may be NULL). */
+int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                              const cgx_scene* scene, const cgx_capacity* cap,
+                              void* workspace, size_t workspace_bytes,
+                              const cgx_images* target, const float* w3_host,
+                              const cgx_images* out, const cgx_grads* grads,
+                              float* loss_dev, void* stream);
+
+/* Synchronise `stream` and read the counters of the last chain enqueued on
+ * this workspace.  Returns CGX_ERR_CAPACITY if a capacity was exceeded. */
+int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run_info* info);
+
+/* Debug / parity access (synchronises): copies to HOST buffers the sorted
+ * pairs (keys as tile id and depth bits, values = splat slot), per-tile
+ * [start, end) ranges, the active rows (anchor scenes, as (view, anchor)
+ * int32 pairs) and the per-splat tile counts.  Each pointer may be NULL;
+ * sizes are taken from cgx_read_info. */
+int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream,
+                       uint32_t* tile_ids, uint32_t* depth_bits, uint32_t* slots,
+                       uint32_t* ranges, int32_t* rows, uint32_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGX_H */

@@ -150,6 +150,8 @@ def composite_tile(S, ent, I, J, view_arrays):
     rgb = wgt @ S["rgb"][ent] if ne else np.zeros((npx, 3))
     D = wgt @ S["d"][ent] if ne else np.zeros(npx)
     N = wgt @ S["normal"][ent] if ne else np.zeros((npx, 3))
+    # magnitude of the blend (sum of |terms|), the scale float32 error follows
+    Nabs = wgt @ np.abs(S["normal"][ent]) if ne else np.zeros((npx, 3))
     last = (np.where(inc.any(axis=1), ne - np.argmax(inc[:, ::-1], axis=1), 0) if ne
             else np.zeros(npx, np.int64))
     walked = np.minimum(stop + 1, ne)
@@ -180,7 +182,7 @@ def composite_tile(S, ent, I, J, view_arrays):
     dhat = np.where(keep, D / np.where(keep, sdot, 1.0), 0.0)
     frag |= (acc > 0) & (np.abs(sdot - DHAT_GUARD * acc)
                          < 10 * FRAG_ALPHA * np.maximum(np.abs(sdot), DHAT_GUARD * acc))
-    return dict(rgb=rgb, D=D, N=N, alpha=acc, dhat=dhat, T=T_final, last=last,
+    return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, T=T_final, last=last,
                 walked=walked, frag=frag, frag_grad=frag_grad | frag, inc=inc,
                 keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)
 
@@ -193,7 +195,8 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
     for v, view in enumerate(views):
         W, H = int(view.width), int(view.height)
         img = dict(rgb=np.zeros((3, H * W)), depth=np.zeros(H * W), D=np.zeros(H * W),
-                   normal=np.zeros((3, H * W)), alpha=np.zeros(H * W), T=np.ones(H * W),
+                   normal=np.zeros((3, H * W)), normal_abs=np.zeros((3, H * W)),
+                   alpha=np.zeros(H * W), T=np.ones(H * W),
                    last=np.zeros(H * W, np.int64), walked=np.zeros(H * W, np.int64),
                    frag=np.zeros(H * W, bool), frag_grad=np.zeros(H * W, bool),
                    covered=np.zeros(H * W, bool), tiles={})
@@ -213,6 +216,7 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
         img["depth"][pix] = R["dhat"]
         img["D"][pix] = R["D"]
         img["normal"][:, pix] = R["N"].T
+        img["normal_abs"][:, pix] = R["Nabs"].T
         img["alpha"][pix] = R["alpha"]
         img["T"][pix] = R["T"]
         img["last"][pix] = R["last"]

@@ -1,0 +1,299 @@
+"""ctypes binding of libcgx (include/cgx.h) with the same names, plus a
+small object wrapper and a torch.autograd.Function.
+
+Argument marshalling only: every step of the rasterizer runs in the HIP
+kernels of libcgx.so.  PyTorch provides device memory and the stream.
+Importing this module never falls back to anything else: if the library
+is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgx.so")
+
+CGX_OK = 0
+CGX_ERR_INVALID_ARG = 1
+CGX_ERR_UNSUPPORTED = 2
+CGX_ERR_CAPACITY = 3
+CGX_ERR_HIP = 4
+CGX_ERR_WORKSPACE = 5
+CGX_SCENE_EXPLICIT = 0
+CGX_SCENE_ANCHOR = 1
+STATUS_NAMES = {0: "CGX_OK", 1: "CGX_ERR_INVALID_ARG", 2: "CGX_ERR_UNSUPPORTED",
+                3: "CGX_ERR_CAPACITY", 4: "CGX_ERR_HIP", 5: "CGX_ERR_WORKSPACE"}
+
+
+class cgx_view(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("z_near", C.c_float), ("bg", C.c_float * 3)]
+
+
+class cgx_explicit_scene(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p),
+                ("scales", C.c_void_p), ("quats", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+class cgx_anchor_scene(C.Structure):
+    _fields_ = [("n_anchor", C.c_int64), ("n_offsets", C.c_int32), ("n_levels", C.c_int32),
+                ("d_max", C.c_float), ("x", C.c_void_p), ("l", C.c_void_p), ("O", C.c_void_p),
+                ("F", C.c_void_p), ("level", C.c_void_p), ("W1", C.c_void_p), ("b1", C.c_void_p),
+                ("W2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class cgx_scene(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ex", cgx_explicit_scene), ("an", cgx_anchor_scene)]
+
+
+class cgx_images(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("plane_d", C.c_void_p),
+                ("normal", C.c_void_p), ("alpha", C.c_void_p)]
+
+
+class cgx_grads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("means", "scales", "quats", "opacity", "sh", "x", "l", "O",
+                                          "F", "W1", "b1", "W2", "b2")]
+
+
+class cgx_capacity(C.Structure):
+    _fields_ = [("max_rows", C.c_int64), ("max_splats", C.c_int64), ("max_pairs", C.c_int64)]
+
+
+class cgx_run_info(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_splats", C.c_int64), ("n_pairs", C.c_int64),
+                ("overflow", C.c_int32), ("reserved", C.c_int32), ("need_rows", C.c_int64),
+                ("need_splats", C.c_int64), ("need_pairs", C.c_int64), ("loss", C.c_double),
+                ("entries_fwd", C.c_uint64), ("entries_bwd", C.c_uint64), ("n_tiles", C.c_int64),
+                ("n_pixels", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcgx.so and declare every entry point.  Raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcgx.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    sig = {
+        "cgx_abi_version": (C.c_int32, []),
+        "cgx_create": (C.c_int32, [C.POINTER(P), C.c_int32, C.c_int32, C.c_int32]),
+        "cgx_destroy": (C.c_int32, [P]),
+        "cgx_last_error": (C.c_char_p, [P]),
+        "cgx_workspace_size": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, C.POINTER(cgx_scene),
+                                           C.POINTER(cgx_capacity), C.POINTER(C.c_size_t)]),
+        "cgx_render_forward": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, C.POINTER(cgx_scene),
+                                           C.POINTER(cgx_capacity), P, C.c_size_t,
+                                           C.POINTER(cgx_images), P]),
+        "cgx_render_backward": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, C.POINTER(cgx_scene),
+                                            C.POINTER(cgx_capacity), P, C.c_size_t,
+                                            C.POINTER(cgx_images), C.POINTER(cgx_images),
+                                            C.POINTER(cgx_grads), P]),
+        "cgx_render_fwd_bwd_l1": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
+                                              C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
+                                              C.c_size_t, C.POINTER(cgx_images),
+                                              C.POINTER(C.c_float), C.POINTER(cgx_images),
+                                              C.POINTER(cgx_grads), P, P]),
+        "cgx_read_info": (C.c_int32, [P, P, P, C.POINTER(cgx_run_info)]),
+        "cgx_debug_copy": (C.c_int32, [P, P, P, P, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class CgxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# --------------------------------------------------------------------------
+# thin wrappers, same names as the C ABI
+# --------------------------------------------------------------------------
+def cgx_abi_version():
+    return load_library().cgx_abi_version()
+
+
+def cgx_create(device=0, tile_w=16, tile_h=16):
+    lib = load_library()
+    h = C.c_void_p()
+    rc = lib.cgx_create(C.byref(h), device, tile_w, tile_h)
+    if rc != CGX_OK:
+        raise CgxError(rc, "cgx_create")
+    return h
+
+
+def cgx_destroy(ctx):
+    return load_library().cgx_destroy(ctx)
+
+
+def cgx_last_error(ctx):
+    m = load_library().cgx_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(ctx, rc, what):
+    if rc != CGX_OK:
+        raise CgxError(rc, f"{what}: {cgx_last_error(ctx)}")
+
+
+def make_views(views) -> "C.Array":
+    """Pack view objects (attributes width, height, fx, fy, cx, cy, R, t,
+    z_near, bg) or dicts into a host cgx_view array."""
+    arr = (cgx_view * len(views))()
+    for i, v in enumerate(views):
+        g = (lambda k: v[k]) if isinstance(v, dict) else (lambda k: getattr(v, k))
+        arr[i].width = int(g("width"))
+        arr[i].height = int(g("height"))
+        arr[i].fx, arr[i].fy = float(g("fx")), float(g("fy"))
+        arr[i].cx, arr[i].cy = float(g("cx")), float(g("cy"))
+        R = np.asarray(g("R"), np.float32).reshape(9)
+        t = np.asarray(g("t"), np.float32).reshape(3)
+        for k in range(9):
+            arr[i].R[k] = float(R[k])
+        for k in range(3):
+            arr[i].t[k] = float(t[k])
+        arr[i].z_near = float(g("z_near"))
+        bg = np.asarray(g("bg"), np.float32).reshape(3)
+        for k in range(3):
+            arr[i].bg[k] = float(bg[k])
+    return arr
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_scene(scene: dict) -> cgx_scene:
+    """scene: dict of device tensors.  Explicit: kind=0, means, scales, quats,
+    opacity, sh, sh_degree.  Anchor: kind=1, x, l, O, F, level (uint8), W1,
+    W2 (int16 tensors holding bfloat16 bits), b1, b2, n_levels, d_max."""
+    s = cgx_scene()
+    s.kind = int(scene["kind"])
+    if s.kind == CGX_SCENE_EXPLICIT:
+        s.ex.n = int(scene["means"].shape[0])
+        s.ex.sh_degree = int(scene["sh_degree"])
+        for k in ("means", "scales", "quats", "opacity", "sh"):
+            setattr(s.ex, k, _ptr(scene[k]))
+    else:
+        s.an.n_anchor = int(scene["x"].shape[0])
+        s.an.n_offsets = int(scene["O"].shape[1])
+        s.an.n_levels = int(scene["n_levels"])
+        s.an.d_max = float(scene["d_max"])
+        for k in ("x", "l", "O", "F", "level", "W1", "b1", "W2", "b2"):
+            setattr(s.an, k, _ptr(scene[k]))
+    return s
+
+
+def make_images(d) -> cgx_images:
+    im = cgx_images()
+    if d is not None:
+        for k in ("rgb", "depth", "plane_d", "normal", "alpha"):
+            setattr(im, k, _ptr(d.get(k)))
+    return im
+
+
+def make_grads(d) -> cgx_grads:
+    g = cgx_grads()
+    for k in ("means", "scales", "quats", "opacity", "sh", "x", "l", "O", "F", "W1", "b1", "W2", "b2"):
+        setattr(g, k, _ptr(d.get(k)))
+    return g
+
+
+def make_capacity(cap) -> cgx_capacity:
+    c = cgx_capacity()
+    if cap:
+        c.max_rows = int(cap.get("max_rows", 0))
+        c.max_splats = int(cap.get("max_splats", 0))
+        c.max_pairs = int(cap.get("max_pairs", 0))
+    return c
+
+
+def cgx_workspace_size(ctx, views, scene, cap=None):
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene) if isinstance(scene, dict) else scene
+    n = C.c_size_t()
+    rc = lib.cgx_workspace_size(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                C.byref(n))
+    _check(ctx, rc, "cgx_workspace_size")
+    return n.value
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def cgx_render_forward(ctx, views, scene, cap, ws, out):
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    im = make_images(out)
+    rc = lib.cgx_render_forward(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(im), _stream())
+    _check(ctx, rc, "cgx_render_forward")
+
+
+def cgx_render_backward(ctx, views, scene, cap, ws, out, grad_out, grads):
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    rc = lib.cgx_render_backward(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(make_images(out)),
+                                 C.byref(make_images(grad_out)), C.byref(make_grads(grads)),
+                                 _stream())
+    _check(ctx, rc, "cgx_render_backward")
+
+
+def cgx_render_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grads, loss_dev=None):
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    w = (C.c_float * 3)(*[float(x) for x in weights])
+    rc = lib.cgx_render_fwd_bwd_l1(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   C.byref(make_images(target)), w, C.byref(make_images(out)),
+                                   C.byref(make_grads(grads)), _ptr(loss_dev), _stream())
+    _check(ctx, rc, "cgx_render_fwd_bwd_l1")
+
+
+def cgx_read_info(ctx, ws, raise_on_capacity=True):
+    lib = load_library()
+    info = cgx_run_info()
+    rc = lib.cgx_read_info(ctx, C.c_void_p(ws.data_ptr()), _stream(), C.byref(info))
+    if rc not in (CGX_OK, CGX_ERR_CAPACITY) or (rc == CGX_ERR_CAPACITY and raise_on_capacity):
+        _check(ctx, rc, "cgx_read_info")
+    return {f: getattr(info, f) for f, _ in cgx_run_info._fields_}
+
+
+def cgx_debug_copy(ctx, ws):
+    lib = load_library()
+    info = cgx_read_info(ctx, ws)
+    P, T = info["n_pairs"], info["n_tiles"]
+    R, S = info["n_rows"], info["n_splats"]
+    tiles = np.zeros(P, np.uint32)
+    zb = np.zeros(P, np.uint32)
+    slots = np.zeros(P, np.uint32)
+    ranges = np.zeros((T, 2), np.uint32)
+    rows = np.zeros((R, 2), np.int32)
+    counts = np.zeros(S, np.uint32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)   # noqa: E731
+    rc = lib.cgx_debug_copy(ctx, C.c_void_p(ws.data_ptr()), _stream(), p(tiles), p(zb), p(slots),
+                            p(ranges), p(rows), p(counts))
+    _check(ctx, rc, "cgx_debug_copy")
+    return dict(tile=tiles, zbits=zb, slot=slots, ranges=ranges, rows=rows, counts=counts, info=info)

@@ -1,0 +1,589 @@
+// C-ABI entry points of libcgx: argument validation, workspace layout and
+// the launch chain of the rasterizer (everything runs on the caller's
+// stream; the library allocates no device memory).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "cgx_common.h"
+
+using namespace cgx;
+
+struct cgx_ctx {
+  int device;
+  int tw, th;
+  std::string err;
+};
+
+static const char* g_static_err = "no context";
+
+static int32_t fail(cgx_ctx* c, int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_OK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, CGX_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+static bool tile_supported(int tw, int th) {
+  return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) ||
+         (tw == 32 && th == 8);
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------
+// validation and layout
+// ---------------------------------------------------------------------
+static int32_t check_views(cgx_ctx* c, const cgx_view* views, int32_t B) {
+  if (!views) return fail(c, CGX_ERR_INVALID_ARG, "views is NULL");
+  if (B < 1 || B > CGX_MAX_VIEWS)
+    return fail(c, CGX_ERR_INVALID_ARG, "n_views = %d outside 1..%d", B, CGX_MAX_VIEWS);
+  int64_t px = 0;
+  for (int i = 0; i < B; ++i) {
+    const cgx_view& v = views[i];
+    if (v.width < 1 || v.height < 1 || v.width > 65535 || v.height > 65535)
+      return fail(c, CGX_ERR_INVALID_ARG, "view %d: size %dx%d outside 1..65535", i, v.width,
+                  v.height);
+    if (!(v.fx > 0.f) || !(v.fy > 0.f) || !std::isfinite(v.fx) || !std::isfinite(v.fy) ||
+        !std::isfinite(v.cx) || !std::isfinite(v.cy))
+      return fail(c, CGX_ERR_INVALID_ARG, "view %d: bad intrinsics", i);
+    if (!(v.z_near > 0.f) || !std::isfinite(v.z_near))
+      return fail(c, CGX_ERR_INVALID_ARG, "view %d: z_near must be > 0", i);
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(v.R[k])) return fail(c, CGX_ERR_INVALID_ARG, "view %d: R not finite", i);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(v.t[k])) return fail(c, CGX_ERR_INVALID_ARG, "view %d: t not finite", i);
+    px += (int64_t)v.width * v.height;
+  }
+  if (px > (int64_t)INT32_MAX) return fail(c, CGX_ERR_INVALID_ARG, "batch has more than 2^31 pixels");
+  return CGX_OK;
+}
+
+static int32_t check_scene(cgx_ctx* c, const cgx_scene* s, int32_t B) {
+  if (!s) return fail(c, CGX_ERR_INVALID_ARG, "scene is NULL");
+  if (s->kind == CGX_SCENE_EXPLICIT) {
+    const cgx_explicit_scene& e = s->ex;
+    if (e.n < 0) return fail(c, CGX_ERR_INVALID_ARG, "explicit scene: n < 0");
+    if (e.sh_degree < 0 || e.sh_degree > 3)
+      return fail(c, CGX_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", e.sh_degree);
+    if (e.n > 0 && (!e.means || !e.scales || !e.quats || !e.opacity || !e.sh))
+      return fail(c, CGX_ERR_INVALID_ARG, "explicit scene: NULL array");
+    if ((int64_t)e.n * B > (int64_t)INT32_MAX)
+      return fail(c, CGX_ERR_INVALID_ARG, "n * n_views exceeds 2^31 splat slots");
+    return CGX_OK;
+  }
+  if (s->kind == CGX_SCENE_ANCHOR) {
+    const cgx_anchor_scene& a = s->an;
+    if (a.n_anchor < 0) return fail(c, CGX_ERR_INVALID_ARG, "anchor scene: n_anchor < 0");
+    if (a.n_offsets < 1 || a.n_offsets > CGX_MAX_OFFSETS)
+      return fail(c, CGX_ERR_UNSUPPORTED, "n_offsets %d not in 1..%d", a.n_offsets, CGX_MAX_OFFSETS);
+    if (a.n_offsets != 10)
+      return fail(c, CGX_ERR_UNSUPPORTED, "this build decodes n_offsets = 10 Gaussians per anchor");
+    if (a.n_levels < 1 || a.n_levels > 16)
+      return fail(c, CGX_ERR_INVALID_ARG, "n_levels %d not in 1..16", a.n_levels);
+    if (!(a.d_max > 0.f) || !std::isfinite(a.d_max))
+      return fail(c, CGX_ERR_INVALID_ARG, "d_max must be > 0");
+    if (a.n_anchor > 0 && (!a.x || !a.l || !a.O || !a.F || !a.level || !a.W1 || !a.b1 || !a.W2 || !a.b2))
+      return fail(c, CGX_ERR_INVALID_ARG, "anchor scene: NULL array");
+    if ((int64_t)a.n_anchor * B > (int64_t)INT32_MAX)
+      return fail(c, CGX_ERR_INVALID_ARG, "n_anchor * n_views exceeds 2^31");
+    return CGX_OK;
+  }
+  return fail(c, CGX_ERR_INVALID_ARG, "unknown scene kind %d", s->kind);
+}
+
+static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const cgx_scene* s,
+                           const cgx_capacity* cap, Layout& L) {
+  int32_t rc = check_views(c, views, B);
+  if (rc) return rc;
+  rc = check_scene(c, s, B);
+  if (rc) return rc;
+  memset(&L, 0, sizeof(L));
+  int64_t tiles = 0, px = 0;
+  for (int i = 0; i < B; ++i) {
+    tiles += (int64_t)((views[i].width + c->tw - 1) / c->tw) * ((views[i].height + c->th - 1) / c->th);
+    px += (int64_t)views[i].width * views[i].height;
+  }
+  L.n_tiles = tiles;
+  L.n_pixels = px;
+  const cgx_capacity zero = {0, 0, 0};
+  const cgx_capacity& C = cap ? *cap : zero;
+  if (C.max_rows < 0 || C.max_splats < 0 || C.max_pairs < 0)
+    return fail(c, CGX_ERR_INVALID_ARG, "negative capacity");
+  if (s->kind == CGX_SCENE_EXPLICIT) {
+    L.max_rows = 0;
+    L.max_splats = (int64_t)s->ex.n * B;
+  } else {
+    const int64_t safe = (int64_t)s->an.n_anchor * B;
+    L.max_rows = C.max_rows ? std::min<int64_t>(C.max_rows, safe) : safe;
+    L.max_splats = L.max_rows * s->an.n_offsets;
+  }
+  if (L.max_splats > (int64_t)INT32_MAX)
+    return fail(c, CGX_ERR_INVALID_ARG, "splat capacity exceeds 2^31");
+  L.max_pairs = C.max_pairs ? C.max_pairs : std::max<int64_t>(8 * L.max_splats, 1024);
+  if (L.max_pairs > (int64_t)0x7FFFFFFF) L.max_pairs = 0x7FFFFFFF;
+  int bits = 1;
+  while ((int64_t(1) << bits) < tiles) ++bits;
+  L.tile_bits = bits;
+  L.n_passes = 4 + (bits + kRadixBits - 1) / kRadixBits;
+  L.final_buf = L.n_passes & 1;
+
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.counters = take(sizeof(Counters));   // first: status reads need only the pointer
+  L.views = take(sizeof(ViewDev) * B);
+  L.scan_part = take(sizeof(unsigned long long) * kScanBlocks);
+  L.rows = take(sizeof(int2) * (size_t)L.max_rows);
+  L.row_off = take(sizeof(uint32_t) * (B + 1));
+  L.splats = take(sizeof(Splat) * (size_t)L.max_splats);
+  L.counts = take(sizeof(uint32_t) * (size_t)L.max_splats);
+  L.offsets = take(sizeof(uint32_t) * (size_t)L.max_splats);
+  for (int b = 0; b < 2; ++b) {
+    L.keys_hi[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+    L.keys_lo[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+    L.vals[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+  }
+  L.hist = take(sizeof(uint32_t) * kRadix * kSortBlocks);
+  L.ranges = take(sizeof(uint2) * (size_t)tiles);
+  L.px_T = take(sizeof(float) * (size_t)px);
+  L.px_last = take(sizeof(uint32_t) * (size_t)px);
+  L.sgrad = take(sizeof(SplatGrad) * (size_t)L.max_splats);
+  L.dz = take(s->kind == CGX_SCENE_ANCHOR ? anchor_scratch_bytes(L.max_rows) : 1);
+  L.total = o;
+  return CGX_OK;
+}
+
+static void build_views(cgx_ctx* c, const cgx_view* views, int32_t B, ViewDev* out) {
+#pragma clang fp contract(off)
+  int tile_off = 0, pix_off = 0;
+  for (int i = 0; i < B; ++i) {
+    const cgx_view& v = views[i];
+    ViewDev& d = out[i];
+    memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 9; ++k) d.R[k] = v.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = v.t[k];
+    d.fx = v.fx;
+    d.fy = v.fy;
+    d.cx = v.cx;
+    d.cy = v.cy;
+    d.z_near = v.z_near;
+    for (int k = 0; k < 3; ++k) d.bg[k] = v.bg[k];
+    for (int j = 0; j < 3; ++j) {
+      const double a = (double)v.R[0 * 3 + j] * (double)v.t[0];
+      const double b = (double)v.R[1 * 3 + j] * (double)v.t[1];
+      const double e = (double)v.R[2 * 3 + j] * (double)v.t[2];
+      d.c[j] = -((a + b) + e);
+    }
+    d.gx = (kGuard * (double)v.width) / (2.0 * (double)v.fx);
+    d.gy = (kGuard * (double)v.height) / (2.0 * (double)v.fy);
+    d.lim_x = (float)d.gx;
+    d.lim_y = (float)d.gy;
+    d.W = v.width;
+    d.H = v.height;
+    d.TX = (v.width + c->tw - 1) / c->tw;
+    d.TY = (v.height + c->th - 1) / c->th;
+    d.tile_off = tile_off;
+    d.pix_off = pix_off;
+    tile_off += d.TX * d.TY;
+    pix_off += v.width * v.height;
+  }
+}
+
+struct Ptrs {
+  ViewDev* views;
+  Counters* ctr;
+  unsigned long long* part;
+  int2* rows;
+  uint32_t* row_off;
+  Splat* splats;
+  uint32_t* counts;
+  uint32_t* offsets;
+  uint32_t* khi[2];
+  uint32_t* klo[2];
+  uint32_t* val[2];
+  uint32_t* hist;
+  uint2* ranges;
+  float* px_T;
+  uint32_t* px_last;
+  SplatGrad* sgrad;
+  float* dz;
+};
+
+static Ptrs pointers(void* ws, const Layout& L) {
+  Ptrs p;
+  p.views = at<ViewDev>(ws, L.views);
+  p.ctr = at<Counters>(ws, L.counters);
+  p.part = at<unsigned long long>(ws, L.scan_part);
+  p.rows = at<int2>(ws, L.rows);
+  p.row_off = at<uint32_t>(ws, L.row_off);
+  p.splats = at<Splat>(ws, L.splats);
+  p.counts = at<uint32_t>(ws, L.counts);
+  p.offsets = at<uint32_t>(ws, L.offsets);
+  for (int b = 0; b < 2; ++b) {
+    p.khi[b] = at<uint32_t>(ws, L.keys_hi[b]);
+    p.klo[b] = at<uint32_t>(ws, L.keys_lo[b]);
+    p.val[b] = at<uint32_t>(ws, L.vals[b]);
+  }
+  p.hist = at<uint32_t>(ws, L.hist);
+  p.ranges = at<uint2>(ws, L.ranges);
+  p.px_T = at<float>(ws, L.px_T);
+  p.px_last = at<uint32_t>(ws, L.px_last);
+  p.sgrad = at<SplatGrad>(ws, L.sgrad);
+  p.dz = at<float>(ws, L.dz);
+  return p;
+}
+
+// ---------------------------------------------------------------------
+// launch chains
+// ---------------------------------------------------------------------
+static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const cgx_scene* s,
+                             const Layout& L, void* ws, const cgx_images* out, hipStream_t st) {
+  Ptrs P = pointers(ws, L);
+  ViewDev host[CGX_MAX_VIEWS];
+  build_views(c, views, B, host);
+  for (int i = 0; i < B; i += kViewsPerUpload) {
+    ViewPack pack;
+    memset(&pack, 0, sizeof(pack));
+    const int cnt = std::min(kViewsPerUpload, B - i);
+    for (int k = 0; k < cnt; ++k) pack.v[k] = host[i + k];
+    launch_upload_views(pack, cnt, P.views + i, st);
+  }
+  const bool expl = s->kind == CGX_SCENE_EXPLICIT;
+  WsHeader h;
+  memset(&h, 0, sizeof(h));
+  h.total = L.total;
+  h.keys_hi = L.keys_hi[L.final_buf];
+  h.keys_lo = L.keys_lo[L.final_buf];
+  h.vals = L.vals[L.final_buf];
+  h.ranges = L.ranges;
+  h.rows = L.rows;
+  h.counts = L.counts;
+  h.n_tiles = L.n_tiles;
+  h.n_pixels = L.n_pixels;
+  h.max_rows = L.max_rows;
+  h.max_splats = L.max_splats;
+  h.max_pairs = L.max_pairs;
+  h.n_views = B;
+  h.kind = s->kind;
+  launch_init_counters(P.ctr, expl ? (uint32_t)L.max_splats : 0u, h, st);
+  const uint32_t n_slots = (uint32_t)L.max_splats;
+  if (expl) {
+    launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, st);
+  } else {
+    launch_select_anchors(P.views, B, s->an, P.part, P.rows, P.row_off, (uint32_t)L.max_rows,
+                          P.ctr, st);
+    launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
+                          P.splats, P.counts, P.ctr, st);
+  }
+  const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
+  launch_scan_counts(P.counts, P.offsets, P.part, n_dev, n_slots, (uint32_t)L.max_pairs, P.ctr, st);
+  launch_duplicate(P.views, P.splats, P.counts, P.offsets, n_dev, n_slots,
+                   expl ? 1 : s->an.n_offsets, expl ? nullptr : P.rows, 0,
+                   expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
+                   (uint32_t)L.max_pairs, P.khi[0], P.klo[0], P.val[0], st);
+  int fb = launch_radix_sort(P.khi, P.klo, P.val, P.ctr, P.hist, L.tile_bits,
+                             (uint32_t)L.max_pairs, st);
+  (void)fb;
+  launch_fill_u32(reinterpret_cast<uint32_t*>(P.ranges), 0u, 2 * (size_t)L.n_tiles, st);
+  launch_ranges(P.khi[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
+
+  RasterArgs a;
+  memset(&a, 0, sizeof(a));
+  a.views = P.views;
+  a.B = B;
+  a.splats = P.splats;
+  a.vals = P.val[L.final_buf];
+  a.ranges = P.ranges;
+  a.n_tiles = (uint32_t)L.n_tiles;
+  a.n_slots = (uint32_t)L.max_splats;
+  a.rgb = out->rgb;
+  a.depth = out->depth;
+  a.plane_d = out->plane_d;
+  a.normal = out->normal;
+  a.alpha = out->alpha;
+  a.px_T = P.px_T;
+  a.px_last = P.px_last;
+  a.ctr = P.ctr;
+  launch_raster_forward(a, c->tw, c->th, st);
+  HIP_OK(c, hipGetLastError());
+  return CGX_OK;
+}
+
+__global__ void k_zero_sgrad(SplatGrad* g, const uint32_t* counts, const uint32_t* n_dev,
+                             uint32_t n_host) {
+  uint32_t n = n_dev ? *n_dev : n_host;
+  if (n > n_host) n = n_host;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (counts[i] == 0) continue;
+    float4* p = reinterpret_cast<float4*>(&g[i]);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    p[0] = z;
+    p[1] = z;
+    p[2] = z;
+    p[3] = z;
+  }
+}
+
+__global__ void k_copy_loss(const Counters* c, float* dst) {
+  if (threadIdx.x == 0) *dst = c->loss;
+}
+
+static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const cgx_scene* s,
+                              const Layout& L, void* ws, const cgx_images* out,
+                              const cgx_images* gout, const cgx_images* target, const float* w3,
+                              const cgx_grads* g, hipStream_t st) {
+  Ptrs P = pointers(ws, L);
+  const bool expl = s->kind == CGX_SCENE_EXPLICIT;
+  const uint32_t n_slots = (uint32_t)L.max_splats;
+  const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
+  {
+    uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_slots, 256), 16384));
+    hipLaunchKernelGGL(k_zero_sgrad, dim3(blocks), dim3(256), 0, st, P.sgrad, P.counts, n_dev,
+                       n_slots);
+  }
+  RasterArgs a;
+  memset(&a, 0, sizeof(a));
+  a.views = P.views;
+  a.B = B;
+  a.splats = P.splats;
+  a.vals = P.val[L.final_buf];
+  a.ranges = P.ranges;
+  a.n_tiles = (uint32_t)L.n_tiles;
+  a.n_slots = (uint32_t)L.max_splats;
+  a.rgb = out->rgb;
+  a.depth = out->depth;
+  a.plane_d = out->plane_d;
+  a.normal = out->normal;
+  a.alpha = out->alpha;
+  a.px_T = P.px_T;
+  a.px_last = P.px_last;
+  a.ctr = P.ctr;
+  if (target) {
+    a.l1 = 1;
+    a.t_rgb = target->rgb;
+    a.t_depth = target->depth;
+    a.t_normal = target->normal;
+    a.w_rgb = w3[0];
+    a.w_depth = w3[1];
+    a.w_normal = w3[2];
+  } else if (gout) {
+    a.g_rgb = gout->rgb;
+    a.g_depth = gout->depth;
+    a.g_plane = gout->plane_d;
+    a.g_normal = gout->normal;
+    a.g_alpha = gout->alpha;
+  }
+  a.sgrad = P.sgrad;
+  launch_raster_backward(a, c->tw, c->th, st);
+  if (expl) {
+    launch_project_explicit_backward(P.views, B, s->ex, P.counts, P.sgrad, *g, st);
+  } else {
+    launch_decode_project_backward(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, P.counts,
+                                   P.sgrad, P.ctr, *g, P.dz, st);
+  }
+  HIP_OK(c, hipGetLastError());
+  return CGX_OK;
+}
+
+static int32_t set_device(cgx_ctx* c) {
+  int cur = -1;
+  HIP_OK(c, hipGetDevice(&cur));
+  if (cur != c->device) HIP_OK(c, hipSetDevice(c->device));
+  return CGX_OK;
+}
+
+// ---------------------------------------------------------------------
+// exported ABI
+// ---------------------------------------------------------------------
+extern "C" {
+
+int32_t cgx_abi_version(void) { return CGX_ABI_VERSION; }
+
+int32_t cgx_create(cgx_ctx** out, int32_t device, int32_t tile_w, int32_t tile_h) {
+  if (!out) return CGX_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!tile_supported(tile_w, tile_h)) return CGX_ERR_UNSUPPORTED;
+  if (device < 0) return CGX_ERR_INVALID_ARG;
+  cgx_ctx* c = new cgx_ctx();
+  c->device = device;
+  c->tw = tile_w;
+  c->th = tile_h;
+  *out = c;
+  return CGX_OK;
+}
+
+int32_t cgx_destroy(cgx_ctx* ctx) {
+  delete ctx;
+  return CGX_OK;
+}
+
+const char* cgx_last_error(const cgx_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_static_err;
+}
+
+int32_t cgx_workspace_size(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const cgx_scene* scene, const cgx_capacity* cap, size_t* bytes) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!bytes) return fail(ctx, CGX_ERR_INVALID_ARG, "bytes is NULL");
+  Layout L;
+  int32_t rc = make_layout(ctx, views, n_views, scene, cap, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return CGX_OK;
+}
+
+static int32_t common_checks(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                             const cgx_scene* scene, const cgx_capacity* cap, void* ws,
+                             size_t ws_bytes, Layout& L) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = make_layout(ctx, views, n_views, scene, cap, L);
+  if (rc) return rc;
+  if (!ws) return fail(ctx, CGX_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < L.total)
+    return fail(ctx, CGX_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  return set_device(ctx);
+}
+
+int32_t cgx_render_forward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                           size_t workspace_bytes, const cgx_images* out, void* stream) {
+  Layout L;
+  int32_t rc = common_checks(ctx, views, n_views, scene, cap, workspace, workspace_bytes, L);
+  if (rc) return rc;
+  if (!out) return fail(ctx, CGX_ERR_INVALID_ARG, "out is NULL");
+  return forward_chain(ctx, views, n_views, scene, L, workspace, out, (hipStream_t)stream);
+}
+
+int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                            const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                            size_t workspace_bytes, const cgx_images* out,
+                            const cgx_images* grad_out, const cgx_grads* grads, void* stream) {
+  Layout L;
+  int32_t rc = common_checks(ctx, views, n_views, scene, cap, workspace, workspace_bytes, L);
+  if (rc) return rc;
+  if (!out || !out->plane_d || !out->normal)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "backward needs the forward plane_d and normal images");
+  if (!grads) return fail(ctx, CGX_ERR_INVALID_ARG, "grads is NULL");
+  if (grad_out && grad_out->depth == nullptr && grad_out->rgb == nullptr &&
+      grad_out->normal == nullptr && grad_out->plane_d == nullptr && grad_out->alpha == nullptr)
+    grad_out = nullptr;
+  if (scene->kind == CGX_SCENE_ANCHOR &&
+      (!grads->x || !grads->l || !grads->O || !grads->F || !grads->W1 || !grads->b1 ||
+       !grads->W2 || !grads->b2))
+    return fail(ctx, CGX_ERR_INVALID_ARG, "anchor backward needs every gradient buffer");
+  cgx_images zero_g;
+  memset(&zero_g, 0, sizeof(zero_g));
+  return backward_chain(ctx, views, n_views, scene, L, workspace, out,
+                        grad_out ? grad_out : &zero_g, nullptr, nullptr, grads,
+                        (hipStream_t)stream);
+}
+
+int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                              const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                              size_t workspace_bytes, const cgx_images* target,
+                              const float* w3_host, const cgx_images* out,
+                              const cgx_grads* grads, float* loss_dev, void* stream) {
+  Layout L;
+  int32_t rc = common_checks(ctx, views, n_views, scene, cap, workspace, workspace_bytes, L);
+  if (rc) return rc;
+  if (!target || !target->rgb || !target->depth || !target->normal)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "L1 targets rgb, depth and normal are required");
+  if (!out || !out->rgb || !out->depth || !out->normal || !out->plane_d)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "fused call needs rgb, depth, plane_d and normal outputs");
+  if (!grads) return fail(ctx, CGX_ERR_INVALID_ARG, "grads is NULL");
+  if (scene->kind == CGX_SCENE_ANCHOR &&
+      (!grads->x || !grads->l || !grads->O || !grads->F || !grads->W1 || !grads->b1 ||
+       !grads->W2 || !grads->b2))
+    return fail(ctx, CGX_ERR_INVALID_ARG, "anchor backward needs every gradient buffer");
+  const float ones[3] = {1.f, 1.f, 1.f};
+  const float* w = w3_host ? w3_host : ones;
+  hipStream_t st = (hipStream_t)stream;
+  rc = forward_chain(ctx, views, n_views, scene, L, workspace, out, st);
+  if (rc) return rc;
+  rc = backward_chain(ctx, views, n_views, scene, L, workspace, out, nullptr, target, w, grads, st);
+  if (rc) return rc;
+  if (loss_dev) {
+    Ptrs P = pointers(workspace, L);
+    hipLaunchKernelGGL(k_copy_loss, dim3(1), dim3(kWave), 0, st, P.ctr, loss_dev);
+    HIP_OK(ctx, hipGetLastError());
+  }
+  return CGX_OK;
+}
+
+static int32_t read_counters(cgx_ctx* ctx, const void* workspace, void* stream, Counters& h) {
+  int32_t rc = set_device(ctx);
+  if (rc) return rc;
+  HIP_OK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  HIP_OK(ctx, hipMemcpy(&h, workspace, sizeof(Counters), hipMemcpyDeviceToHost));
+  if (h.hdr.total == 0) return fail(ctx, CGX_ERR_INVALID_ARG, "workspace holds no launch chain");
+  return CGX_OK;
+}
+
+int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run_info* info) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!workspace || !info) return fail(ctx, CGX_ERR_INVALID_ARG, "NULL argument");
+  Counters h;
+  int32_t rc = read_counters(ctx, workspace, stream, h);
+  if (rc) return rc;
+  memset(info, 0, sizeof(*info));
+  info->n_rows = h.n_rows;
+  info->n_splats = h.n_splats;
+  info->n_pairs = h.n_pairs;
+  info->overflow = (int32_t)h.overflow;
+  info->need_rows = (int64_t)h.need_rows;
+  info->need_splats = (int64_t)h.need_splats;
+  info->need_pairs = (int64_t)h.need_pairs;
+  info->loss = h.loss;
+  info->entries_fwd = h.entries_fwd;
+  info->entries_bwd = h.entries_bwd;
+  info->n_tiles = h.hdr.n_tiles;
+  info->n_pixels = h.hdr.n_pixels;
+  if (h.overflow)
+    return fail(ctx, CGX_ERR_CAPACITY,
+                "capacity exceeded (flags %u): needs rows %llu, splats %llu, pairs %llu",
+                h.overflow, h.need_rows, h.need_splats, h.need_pairs);
+  return CGX_OK;
+}
+
+int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream, uint32_t* tile_ids,
+                       uint32_t* depth_bits, uint32_t* slots, uint32_t* ranges, int32_t* rows,
+                       uint32_t* counts) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!workspace) return fail(ctx, CGX_ERR_INVALID_ARG, "workspace is NULL");
+  Counters h;
+  int32_t rc = read_counters(ctx, workspace, stream, h);
+  if (rc) return rc;
+  const char* base = reinterpret_cast<const char*>(workspace);
+  const size_t P = h.n_pairs;
+  if (tile_ids && P) HIP_OK(ctx, hipMemcpy(tile_ids, base + h.hdr.keys_hi, 4 * P, hipMemcpyDeviceToHost));
+  if (depth_bits && P) HIP_OK(ctx, hipMemcpy(depth_bits, base + h.hdr.keys_lo, 4 * P, hipMemcpyDeviceToHost));
+  if (slots && P) HIP_OK(ctx, hipMemcpy(slots, base + h.hdr.vals, 4 * P, hipMemcpyDeviceToHost));
+  if (ranges && h.hdr.n_tiles)
+    HIP_OK(ctx, hipMemcpy(ranges, base + h.hdr.ranges, 8 * (size_t)h.hdr.n_tiles, hipMemcpyDeviceToHost));
+  if (rows && h.n_rows) HIP_OK(ctx, hipMemcpy(rows, base + h.hdr.rows, 8 * (size_t)h.n_rows, hipMemcpyDeviceToHost));
+  if (counts && h.n_splats)
+    HIP_OK(ctx, hipMemcpy(counts, base + h.hdr.counts, 4 * (size_t)h.n_splats, hipMemcpyDeviceToHost));
+  return CGX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+// Internal definitions shared by the HIP translation units of libcgx.
+//
+// Device data layout (all inside the caller's workspace buffer):
+//   ViewDev[B]        per-view constants, uploaded through kernel arguments
+//   Counters          device-side sizes, overflow flags, loss, statistics
+//   rows[R]           active (view, anchor) rows, int2, (view, anchor) order
+//   Splat[S]          one 64-byte record per splat slot (gathered by the
+//                     raster kernels through the sorted values, so a record
+//                     is one cache-line fetch rather than 16 strided ones)
+//   counts/offsets    tiles touched per slot and their exclusive scan
+//   keys/values       (tile id, depth bits) pairs and slots, double-buffered
+//   ranges[T]         [start, end) of every global tile in the sorted pairs
+//   px_T, px_last     8 bytes of forward state per pixel (final
+//                     transmittance, last contributing list index); the
+//                     backward pass re-walks each tile's list instead of
+//                     keeping per-pixel lists
+//   SplatGrad[S]      per-slot gradient accumulators (atomics)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cgx.h"
+
+namespace cgx {
+
+constexpr int kWave = 64;
+constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
+constexpr int kSortBlocks = 512;    // fixed grid of the radix-sort passes
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;       // keys per thread per sort tile
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kDilation = 0.3f;
+constexpr double kGuard = 1.3;
+constexpr float kDhatGuard = 1e-3f;
+
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float z_near;
+  float bg[3];
+  float lim_x, lim_y;     // guard band of the EWA Jacobian (float32)
+  double c[3];            // camera centre -R^T t (float64)
+  double gx, gy;          // frustum limits 1.3 W / (2 f) (float64)
+  int32_t W, H, TX, TY;
+  int32_t tile_off, pix_off;
+};
+
+// Offsets of the workspace regions, written into the counter block by the
+// first kernel of a chain so that status and debug reads need only the
+// workspace pointer.
+struct WsHeader {
+  uint64_t total;
+  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts;
+  int64_t n_tiles, n_pixels, max_rows, max_splats, max_pairs;
+  int32_t n_views, kind;
+};
+
+struct Counters {
+  WsHeader hdr;
+  uint32_t n_rows;
+  uint32_t n_splats;
+  uint32_t n_pairs;
+  uint32_t overflow;           // bit 0 rows, bit 1 splats, bit 2 pairs
+  unsigned long long need_rows;
+  unsigned long long need_splats;
+  unsigned long long need_pairs;
+  unsigned long long entries_fwd;
+  unsigned long long entries_bwd;
+  float loss;
+  uint32_t pad[3];
+};
+
+// 64-byte splat record.  power = pa dx^2 + pb dx dy + pc dy^2 with
+// (pa, pb, pc) = (-a/2, -b, -c/2) of the conic (exact scalings).
+struct alignas(16) Splat {
+  float u, w;
+  float pa, pb, pc;
+  float op;
+  float cr, cg, cb;
+  float d;
+  float nx, ny, nz;
+  uint32_t bx;                 // x_lo | x_hi << 16 (pixel box, inclusive)
+  uint32_t by;                 // y_lo | y_hi << 16
+  uint32_t zbits;
+};
+static_assert(sizeof(Splat) == 64, "splat record is one 64-byte line");
+
+// Per-slot gradient accumulator: du, dw, dpa, dpb, dpc, dop, dcr, dcg,
+// dcb, dd, dnx, dny, dnz, 3 unused.
+struct alignas(16) SplatGrad {
+  float g[16];
+};
+
+// Views are uploaded through kernel arguments, 8 at a time (graph-safe,
+// no host-to-device copies).
+constexpr int kViewsPerUpload = 8;
+struct ViewPack {
+  ViewDev v[kViewsPerUpload];
+};
+
+struct Layout {
+  size_t views, counters, scan_part, rows, row_off, splats, counts, offsets;
+  size_t keys_hi[2], keys_lo[2], vals[2];
+  size_t hist, ranges, px_T, px_last, sgrad, dz;
+  size_t total;
+  int64_t max_rows, max_splats, max_pairs;
+  int64_t n_tiles, n_pixels;
+  int tile_bits;
+  int n_passes;
+  int final_buf;               // buffer holding the sorted pairs
+};
+
+template <typename T>
+__host__ __device__ inline T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+// ---------------------------------------------------------------------
+// float64 decision values.  Contraction is off so that every operation
+// rounds exactly once, in the order written; the CPU reference takes the
+// same decisions with the same operations.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ void camera_point64(const ViewDev& V, double m0, double m1, double m2,
+                                               double& p0, double& p1, double& p2) {
+#pragma clang fp contract(off)
+  p0 = (((double)V.R[0] * m0 + (double)V.R[1] * m1) + (double)V.R[2] * m2) + (double)V.t[0];
+  p1 = (((double)V.R[3] * m0 + (double)V.R[4] * m1) + (double)V.R[5] * m2) + (double)V.t[1];
+  p2 = (((double)V.R[6] * m0 + (double)V.R[7] * m1) + (double)V.R[8] * m2) + (double)V.t[2];
+}
+
+__device__ __forceinline__ double pixel_coord64(double f, double p, double z, double c) {
+#pragma clang fp contract(off)
+  return (f * p) / z + c;
+}
+
+__device__ __forceinline__ double box_lo64(double u, double r) {
+#pragma clang fp contract(off)
+  return ceil(u - (r + 0.5));
+}
+
+__device__ __forceinline__ double box_hi64(double u, double r) {
+#pragma clang fp contract(off)
+  return floor(u + (r - 0.5));
+}
+
+// ---------------------------------------------------------------------
+// The per-(pixel, splat) opacity shared by the forward and backward raster
+// kernels: one function so both compile to the same instruction sequence
+// and take the same decisions.  Returns alpha (0 when skipped) and the
+// unclamped product o * exp(power) in raw.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ float splat_alpha(float pa, float pb, float pc, float op, float dx,
+                                             float dy, float& raw, float& g) {
+#pragma clang fp contract(off)
+  float power = __builtin_fmaf(pa * dx, dx, __builtin_fmaf(pc * dy, dy, (pb * dx) * dy));
+  if (power > 0.0f) {
+    raw = 0.0f;
+    g = 0.0f;
+    return 0.0f;
+  }
+  g = __expf(power);
+  raw = op * g;
+  float a = raw < kAlphaMax ? raw : kAlphaMax;
+  return a >= kAlphaMin ? a : 0.0f;
+}
+
+// Sum of a float over the 64 lanes of a wave, result valid in lane 63.
+// Row-local shifts accumulate each 16-lane row into its lane 15, then the
+// row broadcasts of lane 15 and lane 31 carry the row totals to lane 63.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  int x;
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true);  // row_shr:1
+  v += __int_as_float(x);
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true);  // row_shr:2
+  v += __int_as_float(x);
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true);  // row_shr:4
+  v += __int_as_float(x);
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true);  // row_shr:8
+  v += __int_as_float(x);
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false); // row_bcast:15
+  v += __int_as_float(x);
+  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false); // row_bcast:31
+  v += __int_as_float(x);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// float atomic add without return (global_atomic_add_f32).
+__device__ __forceinline__ void atomic_add_f32(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ----------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ----------------------------------------------------------------------
+void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s);
+
+// device-wide exclusive scan of counts[0..n) (n from *n_dev if non-null,
+// else n_host) into offsets clamped to cap; total -> *total, overflow bit
+void launch_scan_counts(const uint32_t* counts, uint32_t* offsets, unsigned long long* part,
+                        const uint32_t* n_dev, uint32_t n_host, uint32_t cap, Counters* ctr,
+                        hipStream_t s);
+
+void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
+                             int tw, int th, Splat* splats, uint32_t* counts, hipStream_t s);
+void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                           unsigned long long* part, int2* rows, uint32_t* row_off,
+                           uint32_t max_rows, Counters* ctr, hipStream_t s);
+void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                           const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
+                           uint32_t* counts, Counters* ctr, hipStream_t s);
+
+void launch_duplicate(const ViewDev* views, const Splat* splats, const uint32_t* counts,
+                      const uint32_t* offsets, const uint32_t* n_slots_dev, uint32_t n_slots_host,
+                      int n_offsets_per_row, const int2* rows, int views_are_row_major,
+                      uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* keys_hi,
+                      uint32_t* keys_lo, uint32_t* vals, hipStream_t s);
+
+// returns the index (0/1) of the buffer holding the result
+int launch_radix_sort(uint32_t* keys_hi[2], uint32_t* keys_lo[2], uint32_t* vals[2],
+                      const Counters* ctr, uint32_t* hist, int tile_bits, uint32_t cap,
+                      hipStream_t s);
+
+void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
+                   uint32_t cap, hipStream_t s);
+
+struct RasterArgs {
+  const ViewDev* views;
+  int B;
+  const Splat* splats;
+  const uint32_t* vals;
+  const uint2* ranges;
+  uint32_t n_tiles;
+  uint32_t n_slots;            // capacity of the splat table (slot bound)
+  float* rgb;
+  float* depth;
+  float* plane_d;
+  float* normal;
+  float* alpha;
+  float* px_T;
+  uint32_t* px_last;
+  Counters* ctr;
+  // backward
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_plane;
+  const float* g_normal;
+  const float* g_alpha;
+  const float* t_rgb;          // L1 targets (fused mode)
+  const float* t_depth;
+  const float* t_normal;
+  float w_rgb, w_depth, w_normal;
+  int l1;                      // 1: seed from L1 against targets
+  SplatGrad* sgrad;
+};
+void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s);
+void launch_raster_backward(const RasterArgs& a, int tw, int th, hipStream_t s);
+
+void launch_project_explicit_backward(const ViewDev* views, int B, const cgx_explicit_scene& sc,
+                                      const uint32_t* counts, const SplatGrad* sgrad,
+                                      const cgx_grads& g, hipStream_t s);
+void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                                    const int2* rows, uint32_t max_rows, const uint32_t* counts,
+                                    const SplatGrad* sgrad, const Counters* ctr,
+                                    const cgx_grads& g, float* scratch, hipStream_t s);
+size_t anchor_scratch_bytes(int64_t max_rows);
+void launch_zero_f32(float* p, size_t n, hipStream_t s);
+
+}  // namespace cgx

@@ -1,0 +1,511 @@
+// Voxel-anchor path: a0 active-anchor selection (LoD by observation
+// distance and frustum test, order-preserving compaction), a1 decode of
+// each active (view, anchor) row into n Gaussians fused with their
+// projection (a2), and a10 the decoder adjoint with a deterministic
+// reduction of the weight gradients.
+#include "cgx_project.h"
+
+namespace cgx {
+
+constexpr int kIn = CGX_MLP_IN;          // 36
+constexpr int kHid = CGX_MLP_HIDDEN;     // 32
+constexpr int kGo = CGX_GAUSS_OUT;       // 11
+constexpr int kNOff = 10;                // Gaussians per anchor in this build
+constexpr int kOut = kNOff * kGo;        // 110
+constexpr int kRowScratch = kIn + kHid + kHid + kOut;   // z0, z1, dz1, dz2 per row
+constexpr int kWGrad = kIn * kHid + kHid * kOut + kHid + kOut;   // 4814
+
+// ---------------------------------------------------------------------
+// a0: decisions in float64, fixed operation order, contraction off
+// ---------------------------------------------------------------------
+__device__ __forceinline__ bool anchor_active(const ViewDev& V, const float* X, const uint8_t* level,
+                                              uint32_t a, double dmax2) {
+#pragma clang fp contract(off)
+  const double x0 = X[3 * a], x1 = X[3 * a + 1], x2 = X[3 * a + 2];
+  const double d0 = V.c[0] - x0, d1 = V.c[1] - x1, d2 = V.c[2] - x2;
+  const double dist2 = (d0 * d0 + d1 * d1) + d2 * d2;
+  const int lv = level[a];
+  const bool lod = (lv == 0) || (dist2 * (double)(1ull << (2 * lv)) <= dmax2);
+  if (!lod) return false;
+  double p0, p1, p2;
+  camera_point64(V, x0, x1, x2, p0, p1, p2);
+  return (p2 > (double)V.z_near) && (fabs(p0) <= V.gx * p2) && (fabs(p1) <= V.gy * p2);
+}
+
+__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& b0, uint64_t& b1) {
+  const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+  b0 = (uint64_t)blockIdx.x * per;
+  b1 = b0 + per < n ? b0 + per : n;
+  if (b0 > n) b0 = n;
+}
+
+template <typename T>
+__device__ T block_incl_scan256(T v, T* lw, T& total) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) lw[wave] = v;
+  __syncthreads();
+  T carry = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) carry += lw[w];
+    tot += lw[w];
+  }
+  __syncthreads();
+  total = tot;
+  return v + carry;
+}
+
+__global__ __launch_bounds__(256) void k_select_count(const ViewDev* __restrict__ views, int B,
+                                                      cgx_anchor_scene sc,
+                                                      unsigned long long* part) {
+  __shared__ unsigned long long lw[4];
+  const uint64_t A = (uint64_t)sc.n_anchor;
+  const double dmax2 = (double)sc.d_max * (double)sc.d_max;
+  uint64_t b0, b1;
+  chunk_range(A * (uint64_t)B, b0, b1);
+  unsigned long long cnt = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+    const int v = (int)(i / A);
+    cnt += anchor_active(views[v], sc.x, sc.level, (uint32_t)(i - (uint64_t)v * A), dmax2);
+  }
+  unsigned long long tot;
+  block_incl_scan256<unsigned long long>(cnt, lw, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_select_top(unsigned long long* part, uint32_t max_rows,
+                                                     int n_off, uint32_t* row_off, int B,
+                                                     Counters* ctr) {
+  __shared__ unsigned long long lw[16];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  unsigned long long v0 = part[threadIdx.x], v = v0;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    unsigned long long y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) lw[wave] = v;
+  __syncthreads();
+  unsigned long long carry = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) carry += lw[w];
+    tot += lw[w];
+  }
+  part[threadIdx.x] = carry + v - v0;
+  if (threadIdx.x == 0) {
+    const uint32_t n = (uint32_t)(tot < max_rows ? tot : max_rows);
+    ctr->need_rows = tot;
+    ctr->n_rows = n;
+    ctr->n_splats = n * (uint32_t)n_off;
+    ctr->need_splats = tot * (unsigned long long)n_off;
+    if (tot > max_rows) ctr->overflow |= 1u;
+    row_off[B] = n;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_select_write(const ViewDev* __restrict__ views, int B,
+                                                      cgx_anchor_scene sc,
+                                                      const unsigned long long* part,
+                                                      int2* __restrict__ rows,
+                                                      uint32_t* __restrict__ row_off,
+                                                      uint32_t max_rows) {
+  __shared__ unsigned long long lw[4];
+  const uint64_t A = (uint64_t)sc.n_anchor;
+  const double dmax2 = (double)sc.d_max * (double)sc.d_max;
+  uint64_t b0, b1;
+  chunk_range(A * (uint64_t)B, b0, b1);
+  unsigned long long carry = part[blockIdx.x];
+  for (uint64_t base = b0; base < b1; base += 256) {
+    const uint64_t i = base + threadIdx.x;
+    int v = 0;
+    uint32_t a = 0;
+    unsigned long long f = 0;
+    if (i < b1) {
+      v = (int)(i / A);
+      a = (uint32_t)(i - (uint64_t)v * A);
+      f = anchor_active(views[v], sc.x, sc.level, a, dmax2);
+    }
+    unsigned long long tot;
+    const unsigned long long inc = block_incl_scan256<unsigned long long>(f, lw, tot);
+    if (i < b1) {
+      const unsigned long long pos = carry + inc - f;
+      if (a == 0) row_off[v] = (uint32_t)(pos < max_rows ? pos : max_rows);
+      if (f && pos < max_rows) rows[pos] = make_int2(v, (int)a);
+    }
+    carry += tot;
+  }
+}
+
+void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                           unsigned long long* part, int2* rows, uint32_t* row_off,
+                           uint32_t max_rows, Counters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_count, dim3(kScanBlocks), dim3(256), 0, s, views, B, sc, part);
+  hipLaunchKernelGGL(k_select_top, dim3(1), dim3(kScanBlocks), 0, s, part, max_rows, sc.n_offsets,
+                     row_off, B, ctr);
+  hipLaunchKernelGGL(k_select_write, dim3(kScanBlocks), dim3(256), 0, s, views, B, sc,
+                     (const unsigned long long*)part, rows, row_off, max_rows);
+}
+
+// ---------------------------------------------------------------------
+// shared decoder pieces
+// ---------------------------------------------------------------------
+__device__ __forceinline__ float bf16_round(float x) {
+  // round to nearest, ties to even, on the float32 bit pattern
+  uint32_t u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+struct DecIn {
+  float z0[kIn];
+  float dist;
+};
+
+// z0 = [bf16(F), (c - x)/|c - x|, |c - x|/d_max]
+__device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor_scene& sc,
+                                              uint32_t a, DecIn& d) {
+  const float4* F4 = reinterpret_cast<const float4*>(sc.F + (size_t)a * CGX_FEAT_DIM);
+#pragma unroll
+  for (int q = 0; q < CGX_FEAT_DIM / 4; ++q) {
+    const float4 f = F4[q];
+    d.z0[4 * q + 0] = bf16_round(f.x);
+    d.z0[4 * q + 1] = bf16_round(f.y);
+    d.z0[4 * q + 2] = bf16_round(f.z);
+    d.z0[4 * q + 3] = bf16_round(f.w);
+  }
+  const float e0 = (float)(V.c[0] - (double)sc.x[3 * a]);
+  const float e1 = (float)(V.c[1] - (double)sc.x[3 * a + 1]);
+  const float e2 = (float)(V.c[2] - (double)sc.x[3 * a + 2]);
+  d.dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+  const float il = 1.0f / d.dist;
+  d.z0[32] = e0 * il;
+  d.z0[33] = e1 * il;
+  d.z0[34] = e2 * il;
+  d.z0[35] = d.dist / sc.d_max;
+}
+
+struct DecW {
+  float W1[kIn * kHid];
+  float W2[kHid * kOut];
+  float b1[kHid];
+  float b2[kOut];
+};
+
+__device__ __forceinline__ void load_weights(DecW& w, const cgx_anchor_scene& sc) {
+  for (int i = threadIdx.x; i < kIn * kHid; i += blockDim.x) w.W1[i] = bf16_to_f32(sc.W1[i]);
+  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x) w.W2[i] = bf16_to_f32(sc.W2[i]);
+  for (int i = threadIdx.x; i < kHid; i += blockDim.x) w.b1[i] = sc.b1[i];
+  for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
+}
+
+__device__ __forceinline__ void hidden(const DecW& w, const float* z0, float* pre1) {
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) pre1[j] = w.b1[j];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) {
+    const float zi = z0[i];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) pre1[j] += zi * w.W1[i * kHid + j];
+  }
+}
+
+__device__ __forceinline__ void gaussian_out(const DecW& w, const float* z1, int k, float* z2) {
+#pragma unroll
+  for (int m = 0; m < kGo; ++m) z2[m] = w.b2[k * kGo + m];
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+    const float zj = z1[j];
+#pragma unroll
+    for (int m = 0; m < kGo; ++m) z2[m] += zj * w.W2[j * kOut + k * kGo + m];
+  }
+}
+
+// decoded attributes of Gaussian k of a row, in projection form
+__device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uint32_t a, int k,
+                                                 const float* z2, ProjIn& in, float* sig_s) {
+#pragma clang fp contract(off)
+  const float* X = sc.x + 3 * (size_t)a;
+  const float* L = sc.l + 3 * (size_t)a;
+  const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
+  in.m0 = (double)X[0] + (double)O[0] * (double)L[0];
+  in.m1 = (double)X[1] + (double)O[1] * (double)L[1];
+  in.m2 = (double)X[2] + (double)O[2] * (double)L[2];
+  in.op = sigmoidf(z2[0]);
+  in.col[0] = sigmoidf(z2[1]);
+  in.col[1] = sigmoidf(z2[2]);
+  in.col[2] = sigmoidf(z2[3]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    sig_s[c] = sigmoidf(z2[4 + c]);
+    in.s[c] = L[c] * sig_s[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) in.q[c] = z2[7 + c];
+}
+
+// ---------------------------------------------------------------------
+// a1 + a2: decode and project, one thread per row
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_decode_project(const ViewDev* __restrict__ views,
+                                                        cgx_anchor_scene sc,
+                                                        const int2* __restrict__ rows,
+                                                        const Counters* ctr, int tw, int th,
+                                                        Splat* __restrict__ splats,
+                                                        uint32_t* __restrict__ counts) {
+  __shared__ DecW w;
+  load_weights(w, sc);
+  __syncthreads();
+  const uint32_t n_rows = ctr->n_rows;
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows) return;
+  const int2 row = rows[r];
+  const ViewDev& V = views[row.x];
+  const uint32_t a = (uint32_t)row.y;
+  DecIn d;
+  decoder_input(V, sc, a, d);
+  float z1[kHid];
+  hidden(w, d.z0, z1);
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) z1[j] = fmaxf(z1[j], 0.0f);
+  for (int k = 0; k < kNOff; ++k) {
+    float z2[kGo];
+    gaussian_out(w, z1, k, z2);
+    ProjIn in;
+    float sig_s[3];
+    decoded_gaussian(sc, a, k, z2, in, sig_s);
+    Splat o;
+    const uint32_t slot = r * kNOff + k;
+    const uint32_t cnt = project_splat(V, in, tw, th, o);
+    counts[slot] = cnt;
+    if (cnt) splats[slot] = o;
+  }
+}
+
+void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                           const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
+                           uint32_t* counts, Counters* ctr, hipStream_t s) {
+  (void)B;
+  const uint32_t blocks = div_up(max_rows, 256);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_decode_project, dim3(blocks), dim3(256), 0, s, views, sc, rows,
+                     (const Counters*)ctr, tw, th, splats, counts);
+}
+
+// ---------------------------------------------------------------------
+// a10: per-row adjoint.  Writes the row's z0, z1, dz1, dz2 to scratch for
+// the weight-gradient reduction and adds the anchor gradients (x, l, O, F)
+// atomically (an anchor has one row per view that selects it).
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_decode_bwd_rows(const ViewDev* __restrict__ views,
+                                                         cgx_anchor_scene sc,
+                                                         const int2* __restrict__ rows,
+                                                         const Counters* ctr,
+                                                         const uint32_t* __restrict__ counts,
+                                                         const SplatGrad* __restrict__ sgrad,
+                                                         float* __restrict__ scratch, cgx_grads gr) {
+  __shared__ DecW w;
+  load_weights(w, sc);
+  __syncthreads();
+  const uint32_t n_rows = ctr->n_rows;
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows) return;
+  const int2 row = rows[r];
+  const ViewDev& V = views[row.x];
+  const uint32_t a = (uint32_t)row.y;
+  DecIn d;
+  decoder_input(V, sc, a, d);
+  float pre1[kHid], z1[kHid], dz1[kHid];
+  hidden(w, d.z0, pre1);
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+    z1[j] = fmaxf(pre1[j], 0.0f);
+    dz1[j] = 0.0f;
+  }
+  float* rs = scratch + (size_t)r * kRowScratch;
+  const float* L = sc.l + 3 * (size_t)a;
+  float dx[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+  for (int k = 0; k < kNOff; ++k) {
+    const uint32_t slot = r * kNOff + k;
+    float dz2[kGo];
+#pragma unroll
+    for (int m = 0; m < kGo; ++m) dz2[m] = 0.0f;
+    if (counts[slot]) {
+      float z2[kGo];
+      gaussian_out(w, z1, k, z2);
+      ProjIn in;
+      float sig_s[3];
+      decoded_gaussian(sc, a, k, z2, in, sig_s);
+      float gg[16];
+      const float4* gp = reinterpret_cast<const float4*>(&sgrad[slot]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 t = gp[q];
+        gg[4 * q] = t.x; gg[4 * q + 1] = t.y; gg[4 * q + 2] = t.z; gg[4 * q + 3] = t.w;
+      }
+      ProjState st;
+      project_state(V, in, st);
+      float dmu[3], ds[3], dq[4];
+      project_backward(V, in, st, gg, dmu, ds, dq);
+      dz2[0] = gg[5] * in.op * (1.0f - in.op);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dz2[1 + c] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);
+        dz2[4 + c] = ds[c] * L[c] * sig_s[c] * (1.0f - sig_s[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dz2[7 + c] = dq[c];
+      const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
+      float* gO = gr.O + ((size_t)a * kNOff + k) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dl[c] += ds[c] * sig_s[c] + dmu[c] * O[c];
+        dx[c] += dmu[c];
+        atomic_add_f32(gO + c, dmu[c] * L[c]);
+      }
+#pragma unroll
+      for (int j = 0; j < kHid; ++j) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int m = 0; m < kGo; ++m) acc += dz2[m] * w.W2[j * kOut + k * kGo + m];
+        dz1[j] += acc;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kGo; ++m) rs[kIn + 2 * kHid + k * kGo + m] = dz2[m];
+  }
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) dz1[j] = pre1[j] > 0.0f ? dz1[j] : 0.0f;
+  float dz0[kIn];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) acc += dz1[j] * w.W1[i * kHid + j];
+    dz0[i] = acc;
+  }
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) rs[i] = d.z0[i];
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+    rs[kIn + j] = z1[j];
+    rs[kIn + kHid + j] = dz1[j];
+  }
+  float* gF = gr.F + (size_t)a * CGX_FEAT_DIM;
+#pragma unroll
+  for (int i = 0; i < CGX_FEAT_DIM; ++i) atomic_add_f32(gF + i, dz0[i]);
+  // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max
+  const float* dir = d.z0 + 32;
+  const float dd = dz0[32] * dir[0] + dz0[33] * dir[1] + dz0[34] * dir[2];
+  const float il = 1.0f / d.dist;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float ddelta = (dz0[32 + c] - dir[c] * dd) * il + dz0[35] / sc.d_max * dir[c];
+    dx[c] -= ddelta;
+    atomic_add_f32(gr.x + 3 * (size_t)a + c, dx[c]);
+    atomic_add_f32(gr.l + 3 * (size_t)a + c, dl[c]);
+  }
+}
+
+// Weight gradients: each block sums a contiguous chunk of rows into one
+// partial of 4814 values (W1, W2, b1, b2); a second kernel adds the partials
+// in a fixed order.
+constexpr int kRedBlocks = 256;
+constexpr int kRedRows = 32;
+
+__global__ __launch_bounds__(256) void k_wgrad_partial(const float* __restrict__ scratch,
+                                                       const Counters* ctr,
+                                                       float* __restrict__ partial) {
+  __shared__ float rowbuf[kRedRows * kRowScratch];
+  const uint32_t n = ctr->n_rows;
+  uint64_t b0, b1;
+  chunk_range(n, b0, b1);
+  constexpr int NO = (kWGrad + 255) / 256;
+  float acc[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q) acc[q] = 0.0f;
+  for (uint64_t base = b0; base < b1; base += kRedRows) {
+    const int nr = (int)((b1 - base) < (uint64_t)kRedRows ? (b1 - base) : (uint64_t)kRedRows);
+    for (int i = threadIdx.x; i < nr * kRowScratch; i += 256)
+      rowbuf[i] = scratch[base * kRowScratch + i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+      const int o = threadIdx.x + 256 * q;
+      if (o >= kWGrad) continue;
+      int ia, ib;
+      if (o < kIn * kHid) {               // dW1[i][j] = z0[i] dz1[j]
+        ia = o / kHid;
+        ib = kIn + kHid + o % kHid;
+      } else if (o < kIn * kHid + kHid * kOut) {   // dW2[j][c] = z1[j] dz2[c]
+        const int t = o - kIn * kHid;
+        ia = kIn + t / kOut;
+        ib = kIn + 2 * kHid + t % kOut;
+      } else if (o < kIn * kHid + kHid * kOut + kHid) {   // db1[j] = dz1[j]
+        ia = -1;
+        ib = kIn + kHid + (o - kIn * kHid - kHid * kOut);
+      } else {                                            // db2[c] = dz2[c]
+        ia = -1;
+        ib = kIn + 2 * kHid + (o - kIn * kHid - kHid * kOut - kHid);
+      }
+      float s = 0.0f;
+      for (int rr = 0; rr < nr; ++rr) {
+        const float* rw = rowbuf + rr * kRowScratch;
+        s += (ia >= 0 ? rw[ia] : 1.0f) * rw[ib];
+      }
+      acc[q] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int o = threadIdx.x + 256 * q;
+    if (o < kWGrad) partial[(size_t)blockIdx.x * kWGrad + o] = acc[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ partial, int nb,
+                                                     cgx_grads gr) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= kWGrad) return;
+  float s = 0.0f;
+  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * kWGrad + o];
+  if (o < kIn * kHid) gr.W1[o] = s;
+  else if (o < kIn * kHid + kHid * kOut) gr.W2[o - kIn * kHid] = s;
+  else if (o < kIn * kHid + kHid * kOut + kHid) gr.b1[o - kIn * kHid - kHid * kOut] = s;
+  else gr.b2[o - kIn * kHid - kHid * kOut - kHid] = s;
+}
+
+size_t anchor_scratch_bytes(int64_t max_rows) {
+  return sizeof(float) * ((size_t)max_rows * kRowScratch + (size_t)kRedBlocks * kWGrad);
+}
+
+void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
+                                    const int2* rows, uint32_t max_rows, const uint32_t* counts,
+                                    const SplatGrad* sgrad, const Counters* ctr,
+                                    const cgx_grads& g, float* scratch, hipStream_t s) {
+  (void)B;
+  const size_t A = (size_t)sc.n_anchor;
+  launch_zero_f32(g.x, 3 * A, s);
+  launch_zero_f32(g.l, 3 * A, s);
+  launch_zero_f32(g.O, 3 * A * kNOff, s);
+  launch_zero_f32(g.F, A * CGX_FEAT_DIM, s);
+  const uint32_t blocks = div_up(max_rows, 256);
+  float* partial = scratch + (size_t)max_rows * kRowScratch;
+  if (blocks)
+    hipLaunchKernelGGL(k_decode_bwd_rows, dim3(blocks), dim3(256), 0, s, views, sc, rows, ctr,
+                       counts, sgrad, scratch, g);
+  hipLaunchKernelGGL(k_wgrad_partial, dim3(kRedBlocks), dim3(256), 0, s, (const float*)scratch,
+                     ctr, partial);
+  hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 256)), dim3(256), 0, s,
+                     (const float*)partial, kRedBlocks, g);
+}
+
+}  // namespace cgx

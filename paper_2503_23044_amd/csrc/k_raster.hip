@@ -1,0 +1,345 @@
+// a6 forward and a8 backward rasterization, with the a7 L1 seed fused into
+// the backward prologue.
+//
+// One wave per tile: a TW x TH tile is covered by 64 lanes, each owning
+// PPL = TW*TH/64 pixels of one column (rows y0, y0 + 64/TW, ...).  Splat
+// records of the tile's sorted list are staged 64 at a time in LDS (one
+// 64-byte gather per lane) and every lane walks them front to back for its
+// pixels.  A wave stops as soon as a ballot shows that all its pixels have
+// saturated.  The forward pass keeps 8 bytes per pixel (final
+// transmittance, last contributing list index); the backward pass re-walks
+// the same list from that index towards the front, recovering the
+// transmittance by division, and reduces each splat's 13 gradient values
+// across the wave with DPP before one lane adds them atomically.
+#include "cgx_common.h"
+
+namespace cgx {
+
+__device__ __forceinline__ int find_view(const ViewDev* views, int B, uint32_t tile) {
+  int v = 0;
+  for (int i = 1; i < B; ++i)
+    if ((uint32_t)views[i].tile_off <= tile) v = i;
+  return v;
+}
+
+__device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
+  const float4* s = reinterpret_cast<const float4*>(src);
+  float4* d = reinterpret_cast<float4*>(dst);
+  float4 a = s[0], b = s[1], c = s[2], e = s[3];
+  d[0] = a;
+  d[1] = b;
+  d[2] = c;
+  d[3] = e;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
+  constexpr int PPL = TW * TH / kWave;
+  constexpr int RS = kWave / TW;
+  __shared__ Splat sh[kWave];
+  const uint32_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int v = find_view(a.views, a.B, tile);
+  const ViewDev& V = a.views[v];
+  const int local = (int)tile - V.tile_off;
+  const int tx = local % V.TX, ty = local / V.TX;
+  const int x = tx * TW + (lane % TW);
+  const int y0 = ty * TH + (lane / TW);
+  const float px = (float)x + 0.5f;
+  const bool vx = x < V.W;
+
+  float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
+  uint32_t last[PPL], walked[PPL];
+  bool done[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    T[k] = 1.0f;
+    C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
+    last[k] = 0;
+    walked[k] = 0;
+    done[k] = !(vx && (y0 + k * RS) < V.H);
+  }
+  const uint2 rg = a.ranges[tile];
+  const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
+
+  for (uint32_t base = start; base < end; base += kWave) {
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) live |= !done[k];
+    if (__ballot(live) == 0) break;
+    const uint32_t n = (end - base) < (uint32_t)kWave ? (end - base) : (uint32_t)kWave;
+    if ((uint32_t)lane < n) {
+      const uint32_t slot = a.vals[base + lane];
+      if (slot < a.n_slots) load_splat(&sh[lane], &a.splats[slot]);
+      else sh[lane].bx = 0xFFFFu;     // empty box: never drawn
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < n; ++j) {
+      const Splat& s = sh[j];
+      const int xlo = s.bx & 0xFFFF, xhi = s.bx >> 16;
+      const int ylo = s.by & 0xFFFF, yhi = s.by >> 16;
+      if (x < xlo || x > xhi) continue;
+      const float dx = s.u - px;
+      const uint32_t idx = base - start + j + 1;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        const int y = y0 + k * RS;
+        if (done[k] || y < ylo || y > yhi) continue;
+        const float dy = s.w - ((float)y + 0.5f);
+        float raw, g;
+        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, g);
+        if (alpha == 0.0f) continue;
+        const float Tn = T[k] * (1.0f - alpha);
+        if (Tn < kTMin) {
+          done[k] = true;
+          walked[k] = idx;
+          continue;
+        }
+        const float w = alpha * T[k];
+        C0[k] += w * s.cr;
+        C1[k] += w * s.cg;
+        C2[k] += w * s.cb;
+        D[k] += w * s.d;
+        N0[k] += w * s.nx;
+        N1[k] += w * s.ny;
+        N2[k] += w * s.nz;
+        T[k] = Tn;
+        last[k] = idx;
+      }
+    }
+    __syncthreads();
+  }
+
+  const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
+  uint32_t walked_sum = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int y = y0 + k * RS;
+    if (!(vx && y < V.H)) continue;
+    if (walked[k] == 0) walked[k] = end - start;
+    walked_sum += walked[k];
+    const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
+    const float r = C0[k] + T[k] * V.bg[0];
+    const float g = C1[k] + T[k] * V.bg[1];
+    const float b = C2[k] + T[k] * V.bg[2];
+    const float acc = 1.0f - T[k];
+    const float rx = ((float)x + 0.5f - V.cx) / V.fx;
+    const float ry = ((float)y + 0.5f - V.cy) / V.fy;
+    const float sd = -(N0[k] * rx + N1[k] * ry + N2[k]);
+    const float dh = sd > kDhatGuard * acc ? D[k] / sd : 0.0f;
+    const size_t pv = (size_t)V.pix_off;
+    if (a.rgb) {
+      a.rgb[3 * pv + p] = r;
+      a.rgb[3 * pv + HW + p] = g;
+      a.rgb[3 * pv + 2 * HW + p] = b;
+    }
+    if (a.depth) a.depth[pv + p] = dh;
+    if (a.plane_d) a.plane_d[pv + p] = D[k];
+    if (a.normal) {
+      a.normal[3 * pv + p] = N0[k];
+      a.normal[3 * pv + HW + p] = N1[k];
+      a.normal[3 * pv + 2 * HW + p] = N2[k];
+    }
+    if (a.alpha) a.alpha[pv + p] = acc;
+    a.px_T[pv + p] = T[k];
+    a.px_last[pv + p] = last[k];
+  }
+  // statistics: list entries walked, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) walked_sum += __shfl_xor(walked_sum, o, kWave);
+  if (lane == 0 && walked_sum)
+    atomicAdd(&a.ctr->entries_fwd, (unsigned long long)walked_sum);
+}
+
+__device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+
+template <int TW, int TH>
+__global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
+  constexpr int PPL = TW * TH / kWave;
+  constexpr int RS = kWave / TW;
+  __shared__ Splat sh[kWave];
+  __shared__ uint32_t sslot[kWave];
+  const uint32_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int v = find_view(a.views, a.B, tile);
+  const ViewDev& V = a.views[v];
+  const int local = (int)tile - V.tile_off;
+  const int tx = local % V.TX, ty = local / V.TX;
+  const int x = tx * TW + (lane % TW);
+  const int y0 = ty * TH + (lane / TW);
+  const float px = (float)x + 0.5f;
+  const bool vx = x < V.W;
+  const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
+  const size_t pv = (size_t)V.pix_off;
+  const float inv_px = 1.0f / ((float)a.B * (float)HW);
+
+  float T[PPL], S[PPL], GC0[PPL], GC1[PPL], GC2[PPL], GD[PPL], GN0[PPL], GN1[PPL], GN2[PPL];
+  uint32_t last[PPL];
+  float loss = 0.0f;
+  uint32_t maxlast = 0, sumlast = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int y = y0 + k * RS;
+    last[k] = 0;
+    T[k] = 1.0f;
+    S[k] = GC0[k] = GC1[k] = GC2[k] = GD[k] = GN0[k] = GN1[k] = GN2[k] = 0.0f;
+    if (!(vx && y < V.H)) continue;
+    const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
+    const float Tf = a.px_T[pv + p];
+    last[k] = a.px_last[pv + p];
+    float gc[3] = {0, 0, 0}, gh = 0, gd = 0, gn[3] = {0, 0, 0}, ga = 0;
+    const float n0 = a.normal[3 * pv + p], n1 = a.normal[3 * pv + HW + p],
+                n2 = a.normal[3 * pv + 2 * HW + p];
+    const float Dp = a.plane_d[pv + p];
+    if (a.l1) {
+      for (int c = 0; c < 3; ++c) {
+        const float e = a.rgb[3 * pv + c * HW + p] - a.t_rgb[3 * pv + c * HW + p];
+        gc[c] = a.w_rgb * inv_px * sgnf(e);
+        loss += a.w_rgb * inv_px * fabsf(e);
+      }
+      const float ed = a.depth[pv + p] - a.t_depth[pv + p];
+      gh = a.w_depth * inv_px * sgnf(ed);
+      loss += a.w_depth * inv_px * fabsf(ed);
+      const float nn[3] = {n0, n1, n2};
+      for (int c = 0; c < 3; ++c) {
+        const float e = nn[c] - a.t_normal[3 * pv + c * HW + p];
+        gn[c] = a.w_normal * inv_px * sgnf(e);
+        loss += a.w_normal * inv_px * fabsf(e);
+      }
+    } else {
+      if (a.g_rgb)
+        for (int c = 0; c < 3; ++c) gc[c] = a.g_rgb[3 * pv + c * HW + p];
+      if (a.g_depth) gh = a.g_depth[pv + p];
+      if (a.g_plane) gd = a.g_plane[pv + p];
+      if (a.g_normal)
+        for (int c = 0; c < 3; ++c) gn[c] = a.g_normal[3 * pv + c * HW + p];
+      if (a.g_alpha) ga = a.g_alpha[pv + p];
+    }
+    // unbiased depth D^ = D / s, s = -N . ray, kept where s > 1e-3 alpha
+    const float rx = ((float)x + 0.5f - V.cx) / V.fx;
+    const float ry = ((float)y + 0.5f - V.cy) / V.fy;
+    const float sd = -(n0 * rx + n1 * ry + n2);
+    if (sd > kDhatGuard * (1.0f - Tf)) {
+      const float is = 1.0f / sd;
+      gd += gh * is;
+      const float q = gh * Dp * is * is;
+      gn[0] += q * rx;
+      gn[1] += q * ry;
+      gn[2] += q;
+    }
+    GC0[k] = gc[0]; GC1[k] = gc[1]; GC2[k] = gc[2];
+    GD[k] = gd;
+    GN0[k] = gn[0]; GN1[k] = gn[1]; GN2[k] = gn[2];
+    T[k] = Tf;
+    const float dT = V.bg[0] * gc[0] + V.bg[1] * gc[1] + V.bg[2] * gc[2] - ga;
+    S[k] = Tf * dT;
+    maxlast = last[k] > maxlast ? last[k] : maxlast;
+    sumlast += last[k];
+  }
+  if (a.l1) {
+    float l = loss;
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, kWave);
+    if (lane == 0 && l != 0.0f) atomic_add_f32(&a.ctr->loss, l);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t m = __shfl_xor(maxlast, o, kWave);
+    maxlast = m > maxlast ? m : maxlast;
+    sumlast += __shfl_xor(sumlast, o, kWave);
+  }
+  if (lane == 0 && sumlast) atomicAdd(&a.ctr->entries_bwd, (unsigned long long)sumlast);
+
+  const uint32_t start = a.ranges[tile].x;
+  for (int hi = (int)maxlast; hi > 0; hi -= kWave) {
+    const int lo = hi - kWave > 0 ? hi - kWave : 0;
+    const int n = hi - lo;
+    if (lane < n) {
+      const uint32_t slot = a.vals[start + lo + lane];
+      const bool ok = slot < a.n_slots;
+      sslot[lane] = ok ? slot : 0u;
+      if (ok) load_splat(&sh[lane], &a.splats[slot]);
+      else sh[lane].bx = 0xFFFFu;     // empty box: never drawn
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+      const Splat& s = sh[j];
+      const uint32_t idx = (uint32_t)(lo + j);   // 0-based list index
+      const int xlo = s.bx & 0xFFFF, xhi = s.bx >> 16;
+      const int ylo = s.by & 0xFFFF, yhi = s.by >> 16;
+      const bool inx = x >= xlo && x <= xhi;
+      const float dx = s.u - px;
+      float g[13];
+#pragma unroll
+      for (int i = 0; i < 13; ++i) g[i] = 0.0f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        const int y = y0 + k * RS;
+        if (!inx || idx >= last[k] || y < ylo || y > yhi) continue;
+        const float dy = s.w - ((float)y + 0.5f);
+        float raw, G;
+        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, G);
+        if (alpha == 0.0f) continue;
+        const float om = 1.0f - alpha;
+        const float rom = __builtin_amdgcn_rcpf(om);
+        const float Tk = T[k] * rom;
+        const float w = alpha * Tk;
+        const float val = s.cr * GC0[k] + s.cg * GC1[k] + s.cb * GC2[k] + s.d * GD[k] +
+                          s.nx * GN0[k] + s.ny * GN1[k] + s.nz * GN2[k];
+        const float da = Tk * val - S[k] * rom;
+        S[k] += w * val;
+        T[k] = Tk;
+        g[6] += w * GC0[k];
+        g[7] += w * GC1[k];
+        g[8] += w * GC2[k];
+        g[9] += w * GD[k];
+        g[10] += w * GN0[k];
+        g[11] += w * GN1[k];
+        g[12] += w * GN2[k];
+        if (raw < kAlphaMax) {
+          g[5] += da * G;
+          const float dpw = da * s.op * G;
+          g[0] += dpw * (2.0f * s.pa * dx + s.pb * dy);
+          g[1] += dpw * (2.0f * s.pc * dy + s.pb * dx);
+          g[2] += dpw * dx * dx;
+          g[3] += dpw * dx * dy;
+          g[4] += dpw * dy * dy;
+        }
+        any = true;
+      }
+      if (__ballot(any) == 0) continue;
+      float* dst = a.sgrad[sslot[j]].g;
+#pragma unroll
+      for (int i = 0; i < 13; ++i) {
+        const float r = wave_sum_lane63(g[i]);
+        if (lane == kWave - 1 && r != 0.0f) atomic_add_f32(dst + i, r);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int TW, int TH>
+static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+}
+template <int TW, int TH>
+static void launch_bwd_t(const RasterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+}
+
+void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s) {
+  if (a.n_tiles == 0) return;
+  if (tw == 16 && th == 16) launch_fwd_t<16, 16>(a, s);
+  else if (tw == 8 && th == 8) launch_fwd_t<8, 8>(a, s);
+  else if (tw == 16 && th == 8) launch_fwd_t<16, 8>(a, s);
+  else if (tw == 32 && th == 8) launch_fwd_t<32, 8>(a, s);
+}
+
+void launch_raster_backward(const RasterArgs& a, int tw, int th, hipStream_t s) {
+  if (a.n_tiles == 0) return;
+  if (tw == 16 && th == 16) launch_bwd_t<16, 16>(a, s);
+  else if (tw == 8 && th == 8) launch_bwd_t<8, 8>(a, s);
+  else if (tw == 16 && th == 8) launch_bwd_t<16, 8>(a, s);
+  else if (tw == 32 && th == 8) launch_bwd_t<32, 8>(a, s);
+}
+
+}  // namespace cgx

@@ -1,0 +1,157 @@
+// Small utility kernels: view upload, fills, counters, the device-wide
+// exclusive scan of per-splat tile counts (pair offsets, a3) and the tile
+// ranges of the sorted pairs (a5).
+#include "cgx_common.h"
+
+namespace cgx {
+
+__global__ void k_upload_views(ViewPack pack, int count, ViewDev* dst) {
+  int i = threadIdx.x;
+  if (i < count) dst[i] = pack.v[i];
+}
+
+void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_upload_views, dim3(1), dim3(kWave), 0, s, pack, count, dst);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = value;
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
+}
+
+void launch_zero_f32(float* p, size_t n, hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(p), 0u, n, s);
+}
+
+__global__ void k_init_counters(Counters* c, uint32_t n_splats, WsHeader h) {
+  if (threadIdx.x == 0) {
+    Counters z = {};
+    z.hdr = h;
+    z.n_splats = n_splats;
+    *c = z;
+  }
+}
+
+void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(kWave), 0, s, c, n_splats_host, h);
+}
+
+// ---------------------------------------------------------------------
+// block-wide inclusive scan of one value per thread (256 threads)
+// ---------------------------------------------------------------------
+template <typename T>
+__device__ T block_inclusive_scan(T v, T* lds_waves, T& block_total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) lds_waves[wave] = v;
+  __syncthreads();
+  T carry = 0, total = 0;
+  for (int w = 0; w < nw; ++w) {
+    T x = lds_waves[w];
+    if (w < wave) carry += x;
+    total += x;
+  }
+  __syncthreads();
+  block_total = total;
+  return v + carry;
+}
+
+// phase 1: per-block sums of counts over a contiguous chunk
+__global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, const uint32_t* n_dev,
+                                                      uint32_t n_host, unsigned long long* part) {
+  __shared__ unsigned long long lw[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  if (n > n_host) n = n_host;
+  uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  uint64_t b0 = (uint64_t)blockIdx.x * chunk;
+  uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  unsigned long long sum = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) sum += counts[i];
+  unsigned long long tot;
+  block_inclusive_scan<unsigned long long>(sum, lw, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// phase 2: exclusive scan of the block sums (one block of 1024 threads)
+__global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, uint32_t cap,
+                                                   Counters* ctr) {
+  __shared__ unsigned long long lw[16];
+  unsigned long long v = part[threadIdx.x];
+  unsigned long long tot;
+  unsigned long long inc = block_inclusive_scan<unsigned long long>(v, lw, tot);
+  part[threadIdx.x] = inc - v;
+  if (threadIdx.x == 0) {
+    ctr->need_pairs = tot;
+    ctr->n_pairs = (uint32_t)(tot < cap ? tot : cap);
+    if (tot > cap) ctr->overflow |= 4u;
+  }
+}
+
+// phase 3: scan within each chunk, offsets clamped to cap
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, uint32_t* offsets,
+                                                    const uint32_t* n_dev, uint32_t n_host,
+                                                    const unsigned long long* part, uint32_t cap) {
+  __shared__ unsigned long long lw[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  if (n > n_host) n = n_host;
+  uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  uint64_t b0 = (uint64_t)blockIdx.x * chunk;
+  uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  unsigned long long carry = part[blockIdx.x];
+  for (uint64_t base = b0; base < b1; base += blockDim.x) {
+    uint64_t i = base + threadIdx.x;
+    unsigned long long c = i < b1 ? counts[i] : 0ull;
+    unsigned long long tot;
+    unsigned long long inc = block_inclusive_scan<unsigned long long>(c, lw, tot);
+    if (i < b1) {
+      unsigned long long off = carry + inc - c;
+      offsets[i] = (uint32_t)(off < cap ? off : cap);
+    }
+    carry += tot;
+  }
+}
+
+void launch_scan_counts(const uint32_t* counts, uint32_t* offsets, unsigned long long* part,
+                        const uint32_t* n_dev, uint32_t n_host, uint32_t cap, Counters* ctr,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, n_dev, n_host,
+                     part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, part, cap, ctr);
+  hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, counts, offsets, n_dev,
+                     n_host, (const unsigned long long*)part, cap);
+}
+
+// ---------------------------------------------------------------------
+// a5: [start, end) of each global tile in the sorted pairs
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys_hi, const Counters* ctr,
+                                                uint2* ranges, uint32_t n_tiles) {
+  uint32_t P = ctr->n_pairs;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+    uint32_t t = keys_hi[i];
+    if (t >= n_tiles) continue;
+    if (i == 0 || keys_hi[i - 1] != t) ranges[t].x = i;
+    if (i == P - 1 || keys_hi[i + 1] != t) ranges[t].y = i + 1;
+  }
+}
+
+void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
+                   uint32_t cap, hipStream_t s) {
+  uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 8192));
+  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, keys_hi, ctr, ranges, n_tiles);
+}
+
+}  // namespace cgx

@@ -1,0 +1,204 @@
+"""Object wrapper over the C ABI: device tensors in, images and gradients
+out, with workspace sizing and capacity growth, and a torch.autograd.Function.
+
+All work runs in libcgx.so on torch's current stream; this module only
+allocates tensors and marshals pointers.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+IMAGE_CHANNELS = {"rgb": 3, "depth": 1, "plane_d": 1, "normal": 3, "alpha": 1}
+
+
+def explicit_scene(means, scales, quats, opacity, sh, sh_degree, device="cuda"):
+    """Device tensors of an explicit-Gaussian scene (float32, contiguous)."""
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)  # noqa: E731
+    return dict(kind=B.CGX_SCENE_EXPLICIT, means=f(means), scales=f(scales), quats=f(quats),
+                opacity=f(opacity), sh=f(sh), sh_degree=int(sh_degree))
+
+
+def anchor_scene(x, l, O, F, level, W1_bits, b1, W2_bits, b2, n_levels, d_max, device="cuda"):
+    """Device tensors of a voxel-anchor scene; decoder weights as bfloat16
+    bit patterns (held in int16 tensors)."""
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)  # noqa: E731
+    bits = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.uint16).view(np.int16), device=device)  # noqa: E731
+    return dict(kind=B.CGX_SCENE_ANCHOR, x=f(x), l=f(l), O=f(O), F=f(F),
+                level=torch.as_tensor(np.ascontiguousarray(level, np.uint8), device=device),
+                W1=bits(W1_bits), b1=f(b1), W2=bits(W2_bits), b2=f(b2),
+                n_levels=int(n_levels), d_max=float(d_max))
+
+
+def scene_from(obj, device="cuda"):
+    """Build the device scene from a generator scene object."""
+    if hasattr(obj, "means"):
+        return explicit_scene(obj.means, obj.scales, obj.quats, obj.opacity, obj.sh, obj.sh_degree, device)
+    return anchor_scene(obj.x, obj.l, obj.O, obj.F, obj.level, obj.W1_bits, obj.b1, obj.W2_bits,
+                        obj.b2, obj.n_levels, obj.d_max, device)
+
+
+def pixel_offsets(views):
+    sizes = [int(v.width) * int(v.height) if not isinstance(v, dict) else int(v["width"]) * int(v["height"])
+             for v in views]
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def split_image(flat, views, channels):
+    """Per-view [C, H, W] views of a packed planar image."""
+    off = pixel_offsets(views)
+    out = []
+    for i, v in enumerate(views):
+        W = int(v.width) if not isinstance(v, dict) else int(v["width"])
+        H = int(v.height) if not isinstance(v, dict) else int(v["height"])
+        out.append(flat[channels * off[i]: channels * off[i + 1]].view(channels, H, W))
+    return out
+
+
+def grad_buffers(scene, device="cuda"):
+    if scene["kind"] == B.CGX_SCENE_EXPLICIT:
+        return {k: torch.zeros_like(scene[k]) for k in ("means", "scales", "quats", "opacity", "sh")}
+    g = {k: torch.zeros_like(scene[k]) for k in ("x", "l", "O", "F", "b1", "b2")}
+    g["W1"] = torch.zeros(scene["W1"].shape, dtype=torch.float32, device=device)
+    g["W2"] = torch.zeros(scene["W2"].shape, dtype=torch.float32, device=device)
+    return g
+
+
+class Renderer:
+    """One rasterizer context (device, tile shape) with its workspace."""
+
+    def __init__(self, device: int = 0, tile=(16, 16)):
+        self.device = device
+        self.tile = tuple(tile)
+        self.ctx = B.cgx_create(device, tile[0], tile[1])
+        self.ws = None
+        self.cap = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                B.cgx_destroy(self.ctx)
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def ensure_workspace(self, views, scene, cap=None):
+        cap = dict(cap or self.cap)
+        n = B.cgx_workspace_size(self.ctx, views, scene, cap)
+        n = (n + 255) // 256 * 256
+        if self.ws is None or self.ws.numel() < n:
+            self.ws = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self.cap = cap
+        return self.ws
+
+    def alloc_images(self, views):
+        P = int(pixel_offsets(views)[-1])
+        dev = f"cuda:{self.device}"
+        return {k: torch.empty(c * P, dtype=torch.float32, device=dev) for k, c in IMAGE_CHANNELS.items()}
+
+    def _grow(self, info):
+        cap = dict(self.cap)
+        if info["overflow"] & 4:
+            cap["max_pairs"] = int(info["need_pairs"] * 1.25) + 1024
+        if info["overflow"] & 1:
+            cap["max_rows"] = int(info["need_rows"] * 1.25) + 64
+        self.cap = cap
+
+    def forward(self, views, scene, out=None, check=True):
+        """Render; returns the packed images.  With check, reads the status
+        (synchronises) and re-runs with larger capacities on overflow."""
+        for _ in range(4):
+            ws = self.ensure_workspace(views, scene)
+            out = out if out is not None else self.alloc_images(views)
+            B.cgx_render_forward(self.ctx, views, scene, self.cap, ws, out)
+            if not check:
+                return out
+            info = B.cgx_read_info(self.ctx, ws, raise_on_capacity=False)
+            if not info["overflow"]:
+                self.last_info = info
+                return out
+            self._grow(info)
+        raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
+
+    def backward(self, views, scene, out, grad_out, grads=None):
+        grads = grads if grads is not None else grad_buffers(scene, f"cuda:{self.device}")
+        B.cgx_render_backward(self.ctx, views, scene, self.cap, self.ws, out, grad_out, grads)
+        return grads
+
+    def fwd_bwd_l1(self, views, scene, target, weights=(1.0, 1.0, 1.0), out=None, grads=None,
+                   loss=None, check=True):
+        for _ in range(4):
+            ws = self.ensure_workspace(views, scene)
+            out = out if out is not None else self.alloc_images(views)
+            grads = grads if grads is not None else grad_buffers(scene, f"cuda:{self.device}")
+            B.cgx_render_fwd_bwd_l1(self.ctx, views, scene, self.cap, ws, target, weights, out,
+                                    grads, loss)
+            if not check:
+                return out, grads
+            info = B.cgx_read_info(self.ctx, ws, raise_on_capacity=False)
+            if not info["overflow"]:
+                self.last_info = info
+                return out, grads
+            self._grow(info)
+        raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
+
+    def info(self):
+        return B.cgx_read_info(self.ctx, self.ws)
+
+    def debug(self):
+        return B.cgx_debug_copy(self.ctx, self.ws)
+
+
+_EXPLICIT_KEYS = ("means", "scales", "quats", "opacity", "sh")
+
+
+class RenderExplicit(torch.autograd.Function):
+    """Differentiable render of explicit Gaussians: returns the packed
+    (rgb, depth, plane_d, normal, alpha) images; the backward pass runs the
+    library's reverse-order rasterizer and projection adjoint."""
+
+    @staticmethod
+    def forward(ctx, renderer, views, sh_degree, means, scales, quats, opacity, sh):
+        scene = dict(kind=B.CGX_SCENE_EXPLICIT, means=means.contiguous(), scales=scales.contiguous(),
+                     quats=quats.contiguous(), opacity=opacity.contiguous(), sh=sh.contiguous(),
+                     sh_degree=sh_degree)
+        out = renderer.forward(views, scene)
+        ctx.renderer, ctx.views, ctx.scene, ctx.out = renderer, views, scene, out
+        return out["rgb"], out["depth"], out["plane_d"], out["normal"], out["alpha"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_plane, g_normal, g_alpha):
+        c = lambda t: None if t is None else t.contiguous()   # noqa: E731
+        gout = dict(rgb=c(g_rgb), depth=c(g_depth), plane_d=c(g_plane), normal=c(g_normal),
+                    alpha=c(g_alpha))
+        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout)
+        return (None, None, None) + tuple(grads[k] for k in _EXPLICIT_KEYS)
+
+
+_ANCHOR_KEYS = ("x", "l", "O", "F", "b1", "b2")
+
+
+class RenderAnchor(torch.autograd.Function):
+    """Differentiable render of voxel anchors (decoder weights W1, W2 are
+    bfloat16 bit tensors; their gradients are returned through the float
+    tensors passed as W1_like / W2_like)."""
+
+    @staticmethod
+    def forward(ctx, renderer, views, meta, x, l, O, F, b1, b2, W1f, W2f):
+        scene = dict(kind=B.CGX_SCENE_ANCHOR, x=x.contiguous(), l=l.contiguous(), O=O.contiguous(),
+                     F=F.contiguous(), level=meta["level"], W1=meta["W1"], W2=meta["W2"],
+                     b1=b1.contiguous(), b2=b2.contiguous(), n_levels=meta["n_levels"],
+                     d_max=meta["d_max"])
+        out = renderer.forward(views, scene)
+        ctx.renderer, ctx.views, ctx.scene, ctx.out = renderer, views, scene, out
+        return out["rgb"], out["depth"], out["plane_d"], out["normal"], out["alpha"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_plane, g_normal, g_alpha):
+        c = lambda t: None if t is None else t.contiguous()   # noqa: E731
+        gout = dict(rgb=c(g_rgb), depth=c(g_depth), plane_d=c(g_plane), normal=c(g_normal),
+                    alpha=c(g_alpha))
+        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout)
+        return (None, None, None) + tuple(grads[k] for k in _ANCHOR_KEYS) + (grads["W1"], grads["W2"])
