@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of the batched differentiable RGB-D-N rasterizer on one MI355X.
+
+Workload C2: 200,000 voxel anchors x 10 Gaussians (2M Gaussians) over a
+200 x 200 x 50 m synthetic city block, a batch of 8 views of uneven
+resolution (960x540 .. 1920x1080) with per-view LoD.  One step is one fused
+launch chain: anchor selection, decode + projection, tile binning, the
+64-bit (tile | depth) sort, forward compositing of RGB / D / N / alpha with
+the unbiased depth, the L1 loss of Eq. 8 against seeded targets, the
+reverse-order backward raster and the projection / decoder adjoint.  Inputs
+are resident in HBM before the timed region.
+
+Prints one JSON line: fwd+bwd Mpixels/s (value), the batched vs per-view
+speedup, the roofline of the dominant kernel (timed with HIP events on the
+launch stream inside the timed region) and the FP64 oracle timed on a
+bounded sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# published MI355X peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic work per evaluated (pixel, splat) pair, counted from the
+# method's arithmetic (the design doc lists the terms)
+FLOPS_FWD_PER_EVAL = 29
+FLOPS_BWD_PER_EVAL = 70
+SORT_BYTES_PER_PAIR_PASS = 24     # read + write of key (8 B) and value (4 B)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--config", type=int, default=2)
+    p.add_argument("--tile", type=str, default="16x16")
+    p.add_argument("--no-per-view", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-tiles", type=int, default=400)
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_leg(args, wl):
+    import numpy as np
+    import torch
+
+    from paper_2503_23044_amd import binding as B
+    from paper_2503_23044_amd import render
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    dev = "cuda:0"
+    sc = render.scene_from(wl.scene, dev)
+    cat = lambda xs: torch.as_tensor(np.concatenate([x.ravel() for x in xs]), device=dev)  # noqa: E731
+    tgt = dict(rgb=cat(wl.targets["rgb"]), depth=cat(wl.targets["depth"]),
+               normal=cat(wl.targets["normal"]))
+    w3 = (1.0, 1.0, 1.0)
+    rd = render.Renderer(0, (tw, th))
+    loss = torch.zeros(1, device=dev)
+    # capacity discovery (grows the pair / row capacity on overflow)
+    out, grads = rd.fwd_bwd_l1(wl.views, sc, tgt, w3, loss=loss)
+    torch.cuda.synchronize()
+    info0 = dict(rd.last_info)
+    log(f"[bench] rows {info0['n_rows']} splats {info0['n_splats']} pairs {info0['n_pairs']} "
+        f"loss {info0['loss']:.6f} workspace {rd.ws.numel() / 2**30:.2f} GiB")
+    for _ in range(args.warmup):
+        rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done")
+
+    B.cgx_timing_enable(rd.ctx, 16 * args.steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = B.cgx_timing_read(rd.ctx)
+    B.cgx_timing_enable(rd.ctx, 0)
+    info = rd.info()      # raises if a capacity was exceeded inside the timed region
+    ms = (t1 - t0) / args.steps * 1e3
+    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step")
+    for k, (t, c) in phases.items():
+        if c:
+            log(f"[bench]   {k:12s} {t / c:8.3f} ms x {c // args.steps} per step")
+
+    per_view_ms = None
+    if not args.no_per_view and len(wl.views) > 1:
+        rv = render.Renderer(0, (tw, th))
+        rv.cap = dict(rd.cap)
+        offs = render.pixel_offsets(wl.views)
+        singles = []
+        for v, view in enumerate(wl.views):
+            a, b = int(offs[v]), int(offs[v + 1])
+            t1v = dict(rgb=tgt["rgb"][3 * a:3 * b], depth=tgt["depth"][a:b], normal=tgt["normal"][3 * a:3 * b])
+            singles.append(([view], t1v))
+        bufs = []
+        for views1, t1v in singles:
+            o1, g1 = rv.fwd_bwd_l1(views1, sc, t1v, w3, loss=loss)
+            bufs.append((o1, g1))
+        torch.cuda.synchronize()
+        for _ in range(2):
+            for (views1, t1v), (o1, g1) in zip(singles, bufs):
+                rv.fwd_bwd_l1(views1, sc, t1v, w3, out=o1, grads=g1, loss=loss, check=False)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for (views1, t1v), (o1, g1) in zip(singles, bufs):
+                rv.fwd_bwd_l1(views1, sc, t1v, w3, out=o1, grads=g1, loss=loss, check=False)
+        torch.cuda.synchronize()
+        per_view_ms = (time.perf_counter() - t0) / reps * 1e3
+        log(f"[bench] per-view loop: {per_view_ms:.3f} ms per batch ({len(wl.views)} calls)")
+    return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms, peak_bytes=torch.cuda.max_memory_allocated())
+
+
+def roofline(res, steps):
+    info, ph = res["info"], res["phases"]
+    cands = []
+    t, c = ph["raster_bwd"]
+    if c:
+        d = t / c * 1e-3
+        fl = info["evals_bwd"] * FLOPS_BWD_PER_EVAL if "evals_bwd" in info else info["entries_bwd"] * FLOPS_BWD_PER_EVAL
+        cands.append((t / steps, dict(kernel="raster_bwd", bound="alu", achieved=fl / d / 1e12,
+                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")))
+    t, c = ph["raster_fwd"]
+    if c:
+        d = t / c * 1e-3
+        fl = info["evals_fwd"] * FLOPS_FWD_PER_EVAL if "evals_fwd" in info else info["entries_fwd"] * FLOPS_FWD_PER_EVAL
+        cands.append((t / steps, dict(kernel="raster_fwd", bound="alu", achieved=fl / d / 1e12,
+                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")))
+    t, c = ph["sort"]
+    if c:
+        d = t / c * 1e-3
+        passes = info.get("sort_passes", 6)
+        by = info["n_pairs"] * SORT_BYTES_PER_PAIR_PASS * passes
+        cands.append((t / steps, dict(kernel="sort", bound="hbm", achieved=by / d / 1e9,
+                                      peak=PEAK_HBM_GBS, unit="GB/s")))
+    if not cands:
+        return None
+    cands.sort(key=lambda x: -x[0])
+    r = cands[0][1]
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    return r
+
+
+def cpu_baseline(wl, n_sample_tiles):
+    """The FP64 oracle on a bounded sample of the workload: view 0 only;
+    selection, decode, projection and sort of all of view 0, compositing and
+    its adjoint on a seeded sample of view 0's tiles, the projection and
+    decoder adjoint of all of view 0; the tile part is scaled to all of
+    view 0's tiles.  One thread (BLAS pinned to 1)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import anchors as oanc
+    from oracle import pipeline as opipe
+    from oracle import project as oprj
+    from oracle import raster as oras
+
+    views = wl.views[:1]
+    sc = wl.scene
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        layout = oras.batch_layout(views, (16, 16))
+        rows, offs = oanc.select(sc, views)
+        D = oanc.decode(sc, views, rows)
+        S = oprj.project(D["mu"], D["scales"], D["quats"], D["opacity"], views[0], (16, 16),
+                         colour=D["rgb"])
+        srt = oras.bin_and_sort([S], layout)
+        t_fixed = time.perf_counter() - t0
+        n_tiles = int(layout["tile_off"][-1])
+        rng = np.random.default_rng(1234)
+        sample = np.sort(rng.choice(n_tiles, min(n_sample_tiles, n_tiles), replace=False))
+        varr = [oprj.view_arrays(views[0])]
+        t0 = time.perf_counter()
+        imgs = oras.render_images([S], views, layout, srt, varr, keep_tiles=sample)
+        tg = {k: [wl.targets[k][0]] for k in ("rgb", "depth", "normal")}
+        L, og = oras.l1_seed(imgs, tg)
+        sg = oras.composite_backward([S], views, imgs, og, varr)
+        t_tiles = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pg = oprj.project_backward(S, sg[0])
+        gparts = {k: pg[k] for k in ("mu", "scales", "quats", "opacity", "rgb")}
+        oanc.decode_backward(sc, D, gparts)
+        t_fixed += time.perf_counter() - t0
+    px = int(views[0].width) * int(views[0].height)
+    t_est = t_fixed + t_tiles * n_tiles / len(sample)
+    return dict(value=px / t_est / 1e6, unit="Mpixels/s", cores=1, kind="oracle",
+                sample=(f"view 0 of C2 ({views[0].width}x{views[0].height}, {rows.shape[0]} rows): "
+                        f"select/decode/project/sort and the projection+decoder adjoint in full "
+                        f"({t_fixed:.1f} s), compositing + L1 + compositing adjoint on {len(sample)} "
+                        f"of {n_tiles} tiles ({t_tiles:.1f} s) scaled to all tiles; float64 NumPy, "
+                        f"1 thread"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    from synth import scenes
+    t0 = time.perf_counter()
+    wl = scenes.make(args.config)
+    log(f"[bench] workload {wl.name}: {len(wl.views)} views, {wl.pixels} pixels "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    res = gpu_leg(args, wl)
+    pixels = wl.pixels
+    value = pixels / (res["ms"] * 1e-3) / 1e6
+    line = {
+        "metric": "fwd+bwd Mpixels/s, 2M Gaussians, batch-8 views; batched vs per-view speedup",
+        "value": round(value, 3),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2: 200,000 voxel anchors x 10 Gaussians (2M), 200x200x50 m city "
+                               "block, 8 views 960x540..1920x1080, per-view LoD, fused fwd+L1+bwd",
+                   "views": len(wl.views), "pixels": pixels, "tile": args.tile,
+                   "rows": res["info"]["n_rows"], "pairs": res["info"]["n_pairs"]},
+        "batched_vs_per_view": (round(res["per_view_ms"] / res["ms"], 3) if res["per_view_ms"] else None),
+        "per_view_ms": (round(res["per_view_ms"], 4) if res["per_view_ms"] else None),
+        "phases_ms": {k: round(t / max(args.steps, 1), 4) for k, (t, c) in res["phases"].items() if c},
+        "peak_hbm_gib": round(res["peak_bytes"] / 2**30, 3),
+        "roofline": roofline(res, args.steps),
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tiles)
+        log(f"[bench] cpu baseline took {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,10 @@ typedef struct cgx_run_info {
   uint64_t entries_bwd; /* sum over pixels of list entries walked backward */
   int64_t n_tiles;
   int64_t n_pixels;
+  uint64_t evals_fwd;   /* (pixel, splat) opacity evaluations, forward */
+  uint64_t evals_bwd;   /* (pixel, splat) opacity evaluations, backward */
+  int32_t sort_passes;  /* 8-bit radix passes of the last sort */
+  int32_t reserved2;
 } cgx_run_info;
 
 /* Library version (CGX_ABI_VERSION). */
@@ -236,6 +240,30 @@ int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run
 int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream,
                        uint32_t* tile_ids, uint32_t* depth_bits, uint32_t* slots,
                        uint32_t* ranges, int32_t* rows, uint32_t* counts);
+
+/* Phases of a launch chain, for cgx_timing_read. */
+enum {
+  CGX_PHASE_SELECT = 0,      /* a0 anchor selection and compaction */
+  CGX_PHASE_PROJECT = 1,     /* a1 + a2 decode / projection */
+  CGX_PHASE_SCAN = 2,        /* a3 scan of per-splat tile counts */
+  CGX_PHASE_DUPLICATE = 3,   /* a3 pair emission */
+  CGX_PHASE_SORT = 4,        /* a4 radix sort */
+  CGX_PHASE_RANGES = 5,      /* a5 tile ranges */
+  CGX_PHASE_RASTER_FWD = 6,  /* a6 forward raster */
+  CGX_PHASE_RASTER_BWD = 7,  /* a7 + a8 L1 seed and backward raster */
+  CGX_PHASE_PROJECT_BWD = 8, /* a9 (+ a10 per row) adjoint */
+  CGX_PHASE_WGRAD = 9,       /* a10 decoder weight-gradient reduction */
+  CGX_N_PHASES = 10
+};
+
+/* Per-phase timing with HIP events recorded on the launch stream.
+ * cgx_timing_enable(ctx, n) starts recording into a pool of n (begin, end)
+ * event pairs (0 disables); cgx_timing_read synchronises on the recorded
+ * events, returns per-phase total milliseconds and launch counts, and
+ * restarts the pool.  Recording adds no synchronisation to the chain. */
+int32_t cgx_timing_enable(cgx_ctx* ctx, int32_t n_records);
+int32_t cgx_timing_read(cgx_ctx* ctx, double* ms_per_phase, int32_t* count_per_phase,
+                        int32_t n_phases);
 
 #ifdef __cplusplus
 }

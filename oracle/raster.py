@@ -31,6 +31,7 @@ T_MIN = 1e-4
 DHAT_GUARD = 1e-3
 FRAG_ALPHA = 1e-5
 FRAG_T = 1e-4
+FRAG_SIGN = 1e-5
 
 
 # --------------------------------------------------------------------------
@@ -264,6 +265,12 @@ def l1_seed(images, targets, weights=(1.0, 1.0, 1.0)):
         grads.append(dict(rgb=weights[0] * sc * np.sign(er), depth=weights[1] * sc * np.sign(ed),
                           normal=weights[2] * sc * np.sign(en), D=np.zeros(npx),
                           alpha=np.zeros(npx)))
+        # sign(out - target) is a decision: a pixel whose output lies within
+        # FRAG_SIGN of its target may take the other sign in float32
+        if "frag_grad" in img:
+            near = ((np.abs(er) < FRAG_SIGN).any(axis=0) | (np.abs(ed) < FRAG_SIGN)
+                    | (np.abs(en) < FRAG_SIGN).any(axis=0))
+            img["frag_grad"] = img["frag_grad"] | near
     return L, grads
 
 

@@ -70,7 +70,8 @@ class cgx_run_info(C.Structure):
                 ("overflow", C.c_int32), ("reserved", C.c_int32), ("need_rows", C.c_int64),
                 ("need_splats", C.c_int64), ("need_pairs", C.c_int64), ("loss", C.c_double),
                 ("entries_fwd", C.c_uint64), ("entries_bwd", C.c_uint64), ("n_tiles", C.c_int64),
-                ("n_pixels", C.c_int64)]
+                ("n_pixels", C.c_int64), ("evals_fwd", C.c_uint64), ("evals_bwd", C.c_uint64),
+                ("sort_passes", C.c_int32), ("reserved2", C.c_int32)]
 
 
 _lib = None
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH):
                                               C.POINTER(cgx_grads), P, P]),
         "cgx_read_info": (C.c_int32, [P, P, P, C.POINTER(cgx_run_info)]),
         "cgx_debug_copy": (C.c_int32, [P, P, P, P, P, P, P, P, P]),
+        "cgx_timing_enable": (C.c_int32, [P, C.c_int32]),
+        "cgx_timing_read": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -297,3 +300,19 @@ def cgx_debug_copy(ctx, ws):
                             p(ranges), p(rows), p(counts))
     _check(ctx, rc, "cgx_debug_copy")
     return dict(tile=tiles, zbits=zb, slot=slots, ranges=ranges, rows=rows, counts=counts, info=info)
+
+
+PHASES = ["select", "project", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
+          "project_bwd", "wgrad"]
+
+
+def cgx_timing_enable(ctx, n_records):
+    _check(ctx, load_library().cgx_timing_enable(ctx, int(n_records)), "cgx_timing_enable")
+
+
+def cgx_timing_read(ctx):
+    n = len(PHASES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int32 * n)()
+    _check(ctx, load_library().cgx_timing_read(ctx, ms, cnt, n), "cgx_timing_read")
+    return {PHASES[i]: (ms[i], cnt[i]) for i in range(n)}

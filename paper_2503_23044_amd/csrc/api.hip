@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "cgx_common.h"
 
@@ -17,7 +18,27 @@ struct cgx_ctx {
   int device;
   int tw, th;
   std::string err;
+  // phase timing: a pool of (begin, end) event pairs recorded on the stream
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_phase;
+  int ev_next = 0;
+  int ev_cap = 0;
+  int open_phase = -1;
 };
+
+static void phase_begin(cgx_ctx* c, int phase, hipStream_t s) {
+  if (c->ev_cap == 0 || c->ev_next >= c->ev_cap) return;
+  hipEventRecord(c->ev[2 * c->ev_next], s);
+  c->ev_phase[c->ev_next] = phase;
+  c->open_phase = phase;
+}
+
+static void phase_end(cgx_ctx* c, hipStream_t s) {
+  if (c->ev_cap == 0 || c->ev_next >= c->ev_cap || c->open_phase < 0) return;
+  hipEventRecord(c->ev[2 * c->ev_next + 1], s);
+  ++c->ev_next;
+  c->open_phase = -1;
+}
 
 static const char* g_static_err = "no context";
 
@@ -283,27 +304,42 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.max_pairs = L.max_pairs;
   h.n_views = B;
   h.kind = s->kind;
+  h.sort_passes = L.n_passes;
   launch_init_counters(P.ctr, expl ? (uint32_t)L.max_splats : 0u, h, st);
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
+    phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, st);
+    phase_end(c, st);
   } else {
+    phase_begin(c, CGX_PHASE_SELECT, st);
     launch_select_anchors(P.views, B, s->an, P.part, P.rows, P.row_off, (uint32_t)L.max_rows,
                           P.ctr, st);
+    phase_end(c, st);
+    phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
                           P.splats, P.counts, P.ctr, st);
+    phase_end(c, st);
   }
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
+  phase_begin(c, CGX_PHASE_SCAN, st);
   launch_scan_counts(P.counts, P.offsets, P.part, n_dev, n_slots, (uint32_t)L.max_pairs, P.ctr, st);
+  phase_end(c, st);
+  phase_begin(c, CGX_PHASE_DUPLICATE, st);
   launch_duplicate(P.views, P.splats, P.counts, P.offsets, n_dev, n_slots,
                    expl ? 1 : s->an.n_offsets, expl ? nullptr : P.rows, 0,
                    expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
                    (uint32_t)L.max_pairs, P.khi[0], P.klo[0], P.val[0], st);
+  phase_end(c, st);
+  phase_begin(c, CGX_PHASE_SORT, st);
   int fb = launch_radix_sort(P.khi, P.klo, P.val, P.ctr, P.hist, L.tile_bits,
                              (uint32_t)L.max_pairs, st);
   (void)fb;
+  phase_end(c, st);
+  phase_begin(c, CGX_PHASE_RANGES, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(P.ranges), 0u, 2 * (size_t)L.n_tiles, st);
   launch_ranges(P.khi[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
+  phase_end(c, st);
 
   RasterArgs a;
   memset(&a, 0, sizeof(a));
@@ -322,7 +358,9 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.px_T = P.px_T;
   a.px_last = P.px_last;
   a.ctr = P.ctr;
+  phase_begin(c, CGX_PHASE_RASTER_FWD, st);
   launch_raster_forward(a, c->tw, c->th, st);
+  phase_end(c, st);
   HIP_OK(c, hipGetLastError());
   return CGX_OK;
 }
@@ -392,13 +430,17 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
     a.g_alpha = gout->alpha;
   }
   a.sgrad = P.sgrad;
+  phase_begin(c, CGX_PHASE_RASTER_BWD, st);
   launch_raster_backward(a, c->tw, c->th, st);
+  phase_end(c, st);
+  phase_begin(c, CGX_PHASE_PROJECT_BWD, st);
   if (expl) {
     launch_project_explicit_backward(P.views, B, s->ex, P.counts, P.sgrad, *g, st);
   } else {
     launch_decode_project_backward(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, P.counts,
                                    P.sgrad, P.ctr, *g, P.dz, st);
   }
+  phase_end(c, st);
   HIP_OK(c, hipGetLastError());
   return CGX_OK;
 }
@@ -430,8 +472,52 @@ int32_t cgx_create(cgx_ctx** out, int32_t device, int32_t tile_w, int32_t tile_h
   return CGX_OK;
 }
 
+static void free_events(cgx_ctx* c) {
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_phase.clear();
+  c->ev_cap = c->ev_next = 0;
+}
+
 int32_t cgx_destroy(cgx_ctx* ctx) {
+  if (ctx) free_events(ctx);
   delete ctx;
+  return CGX_OK;
+}
+
+int32_t cgx_timing_enable(cgx_ctx* ctx, int32_t n_records) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (n_records < 0 || n_records > (1 << 20))
+    return fail(ctx, CGX_ERR_INVALID_ARG, "n_records %d outside 0..2^20", n_records);
+  int32_t rc = set_device(ctx);
+  if (rc) return rc;
+  free_events(ctx);
+  ctx->ev.resize(2 * (size_t)n_records);
+  ctx->ev_phase.assign(n_records, -1);
+  for (auto& e : ctx->ev) HIP_OK(ctx, hipEventCreate(&e));
+  ctx->ev_cap = n_records;
+  ctx->ev_next = 0;
+  return CGX_OK;
+}
+
+int32_t cgx_timing_read(cgx_ctx* ctx, double* ms, int32_t* count, int32_t n_phases) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!ms || !count || n_phases < 1) return fail(ctx, CGX_ERR_INVALID_ARG, "bad output arrays");
+  for (int i = 0; i < n_phases; ++i) {
+    ms[i] = 0.0;
+    count[i] = 0;
+  }
+  for (int i = 0; i < ctx->ev_next; ++i) {
+    HIP_OK(ctx, hipEventSynchronize(ctx->ev[2 * i + 1]));
+    float t = 0.f;
+    HIP_OK(ctx, hipEventElapsedTime(&t, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+    const int p = ctx->ev_phase[i];
+    if (p >= 0 && p < n_phases) {
+      ms[p] += t;
+      count[p] += 1;
+    }
+  }
+  ctx->ev_next = 0;
   return CGX_OK;
 }
 
@@ -558,6 +644,9 @@ int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run
   info->entries_bwd = h.entries_bwd;
   info->n_tiles = h.hdr.n_tiles;
   info->n_pixels = h.hdr.n_pixels;
+  info->evals_fwd = h.evals_fwd;
+  info->evals_bwd = h.evals_bwd;
+  info->sort_passes = h.hdr.sort_passes;
   if (h.overflow)
     return fail(ctx, CGX_ERR_CAPACITY,
                 "capacity exceeded (flags %u): needs rows %llu, splats %llu, pairs %llu",

@@ -61,6 +61,7 @@ struct WsHeader {
   uint64_t keys_hi, keys_lo, vals, ranges, rows, counts;
   int64_t n_tiles, n_pixels, max_rows, max_splats, max_pairs;
   int32_t n_views, kind;
+  int32_t sort_passes, pad;
 };
 
 struct Counters {
@@ -74,6 +75,8 @@ struct Counters {
   unsigned long long need_pairs;
   unsigned long long entries_fwd;
   unsigned long long entries_bwd;
+  unsigned long long evals_fwd;   // (pixel, splat) pairs whose opacity was evaluated
+  unsigned long long evals_bwd;
   float loss;
   uint32_t pad[3];
 };

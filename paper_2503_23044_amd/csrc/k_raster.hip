@@ -61,6 +61,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   }
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
+  uint32_t evals = 0;
 
   for (uint32_t base = start; base < end; base += kWave) {
     bool live = false;
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
         const float dy = s.w - ((float)y + 0.5f);
         float raw, g;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, g);
+        ++evals;
         if (alpha == 0.0f) continue;
         const float Tn = T[k] * (1.0f - alpha);
         if (Tn < kTMin) {
@@ -144,10 +146,13 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     a.px_T[pv + p] = T[k];
     a.px_last[pv + p] = last[k];
   }
-  // statistics: list entries walked, one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) walked_sum += __shfl_xor(walked_sum, o, kWave);
-  if (lane == 0 && walked_sum)
-    atomicAdd(&a.ctr->entries_fwd, (unsigned long long)walked_sum);
+  // statistics: list entries walked and opacity evaluations, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    walked_sum += __shfl_xor(walked_sum, o, kWave);
+    evals += __shfl_xor(evals, o, kWave);
+  }
+  if (lane == 0 && walked_sum) atomicAdd(&a.ctr->entries_fwd, (unsigned long long)walked_sum);
+  if (lane == 0 && evals) atomicAdd(&a.ctr->evals_fwd, (unsigned long long)evals);
 }
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
@@ -248,6 +253,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   if (lane == 0 && sumlast) atomicAdd(&a.ctr->entries_bwd, (unsigned long long)sumlast);
 
   const uint32_t start = a.ranges[tile].x;
+  uint32_t evals = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= kWave) {
     const int lo = hi - kWave > 0 ? hi - kWave : 0;
     const int n = hi - lo;
@@ -277,6 +283,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         const float dy = s.w - ((float)y + 0.5f);
         float raw, G;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, G);
+        ++evals;
         if (alpha == 0.0f) continue;
         const float om = 1.0f - alpha;
         const float rom = __builtin_amdgcn_rcpf(om);
@@ -315,6 +322,8 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     }
     __syncthreads();
   }
+  for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, kWave);
+  if (lane == 0 && evals) atomicAdd(&a.ctr->evals_bwd, (unsigned long long)evals);
 }
 
 template <int TW, int TH>

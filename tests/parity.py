@@ -112,3 +112,112 @@ def compare_sort_anchor(dbg, r, n_off):
     assert got.shape == ref.shape, (got.shape, ref.shape)
     np.testing.assert_array_equal(got, ref)
     return int((~keep_g).sum())
+
+
+# ---------------------------------------------------------------------------
+# gradients: 1e-4 relative where the element is well conditioned
+# ---------------------------------------------------------------------------
+SENS_EPS = 2.0 ** -24      # relative input perturbation of float32 rounding size
+SENS_K = 16.0              # float32 rounding events the GPU chain may accumulate per input one
+GRAD_NORM_RTOL = 1e-4
+
+
+def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=None):
+    """|got - ref| <= rtol * max(|ref|, floor * max|ref|) + slack, where delta
+    is a dict {"sens": d, "frag": f}: d is how far the FP64 oracle's own
+    gradient moves when every float input is perturbed at float32 rounding
+    size (the element's conditioning) and f is the share of the element that
+    comes from pixels with a fragile decision; slack = SENS_K d + 2 f.  The
+    norm-wise relative error must also stay <= GRAD_NORM_RTOL."""
+    if isinstance(delta, dict):
+        delta = SENS_K * np.asarray(delta["sens"], np.float64) + 2.0 * np.asarray(delta["frag"], np.float64)
+    else:
+        delta = SENS_K * np.asarray(delta, np.float64)
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    d = np.asarray(delta, np.float64).ravel()
+    assert got.shape == ref.shape == d.shape, (name, got.shape, ref.shape, d.shape)
+    ex = np.zeros(ref.shape, bool) if exclude is None else np.asarray(exclude, bool).ravel()
+    keep = ~ex
+    scale = np.max(np.abs(ref[keep])) if keep.any() else 0.0
+    tol = rtol * np.maximum(np.abs(ref), floor * scale) + d
+    err = np.abs(got - ref)
+    bad = (err > tol) & keep
+    assert np.all(np.isfinite(got[keep])), f"{name}: non-finite values"
+    rel = np.max(err[keep] / np.maximum(np.abs(ref[keep]), floor * scale + 1e-300)) if keep.any() else 0.0
+    nrm = np.linalg.norm(ref[keep])
+    nrel = float(np.linalg.norm((got - ref)[keep]) / nrm) if nrm > 0 else float(np.linalg.norm(got[keep]))
+    cond = int((d > rtol * np.maximum(np.abs(ref), floor * scale))[keep].sum())
+    print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, excluded "
+          f"{int(ex.sum())}/{ref.size}, ill-conditioned {cond}", flush=True)
+    if bad.any():
+        i = np.argmax(np.where(bad, err / np.maximum(tol, 1e-300), 0))
+        raise AssertionError(f"{name}: {int(bad.sum())}/{keep.sum()} elements out of tolerance; "
+                             f"worst idx {i}: got {got[i]!r} ref {ref[i]!r} tol {tol[i]:.3g} "
+                             f"delta {d[i]:.3g}")
+    assert nrel <= GRAD_NORM_RTOL, f"{name}: norm-wise relative error {nrel:.3g}"
+    return rel
+
+
+def _without_fragile(r, og):
+    """Output gradients with the pixels of fragile decisions zeroed."""
+    out = []
+    for img, g in zip(r.images, og):
+        m = img["frag_grad"]
+        h = {}
+        for k, a in g.items():
+            a = np.array(a, np.float64, copy=True)
+            if a.ndim == 2:
+                a[:, m] = 0.0
+            else:
+                a[m] = 0.0
+            h[k] = a
+        out.append(h)
+    return out
+
+
+def _perturbed(a, rng):
+    a = np.asarray(a)
+    if a.dtype.kind != "f":
+        return a
+    return (a.astype(np.float64) * (1.0 + SENS_EPS * rng.standard_normal(a.shape)))
+
+
+def explicit_sensitivity(scene, views, og, tile=(16, 16), seed=4321):
+    """|g(inputs) - g(inputs perturbed at float32 rounding size)| of the
+    oracle, per gradient element (explicit scenes)."""
+    import copy
+
+    from oracle import pipeline
+    rng = np.random.default_rng(seed)
+    r0 = pipeline.render_explicit(scene, views, tile=tile)
+    g0, _ = pipeline.backward(r0, og, scene)
+    sc = copy.copy(scene)
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        setattr(sc, k, _perturbed(getattr(scene, k), rng))
+    r1 = pipeline.render_explicit(sc, views, tile=tile)
+    g1, _ = pipeline.backward(r1, og, sc)
+    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), scene)
+    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
+            for k in ("means", "scales", "quats", "opacity", "sh")}
+
+
+def anchor_sensitivity(scene, views, og, tile=(16, 16), seed=4321):
+    """Same for anchor scenes (features, offsets, positions, scalings,
+    biases and the decoder weights' values)."""
+    import copy
+
+    from oracle import pipeline
+    rng = np.random.default_rng(seed)
+    r0 = pipeline.render_anchor(scene, views, tile=tile)
+    g0, _ = pipeline.backward(r0, og, scene)
+    sc = copy.copy(scene)
+    for k in ("x", "l", "O", "b1", "b2"):
+        setattr(sc, k, _perturbed(getattr(scene, k), rng))
+    sc.W1_exact = _perturbed(scene.W1, rng)
+    sc.W2_exact = _perturbed(scene.W2, rng)
+    r1 = pipeline.render_anchor(sc, views, tile=tile)
+    g1, _ = pipeline.backward(r1, og, sc)
+    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), scene)
+    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
+            for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}

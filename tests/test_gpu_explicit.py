@@ -9,7 +9,8 @@ import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import check_close, compare_images, compare_sort_explicit
+from tests.parity import (check_grad, compare_images, compare_sort_explicit,
+                          explicit_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -28,14 +29,11 @@ def _run_forward(R, wl, tile=(16, 16)):
     return rd, sc, out
 
 
-def _explicit_grads_check(gr, ref, frag, sh_degree, report=None):
+def _explicit_grads_check(gr, ref, frag, sh_degree, delta, report=None):
     ex = frag
-    check_close("d_means", gr["means"].cpu().numpy(), ref["means"], np.repeat(ex, 3), report=report)
-    check_close("d_scales", gr["scales"].cpu().numpy(), ref["scales"], np.repeat(ex, 3), report=report)
-    check_close("d_quats", gr["quats"].cpu().numpy(), ref["quats"], np.repeat(ex, 4), report=report)
-    check_close("d_opacity", gr["opacity"].cpu().numpy(), ref["opacity"], ex, report=report)
     K = (sh_degree + 1) ** 2
-    check_close("d_sh", gr["sh"].cpu().numpy(), ref["sh"], np.repeat(ex, 3 * K), report=report)
+    for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 3 * K)):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(ex, c), delta[k], report=report)
 
 
 def test_c0_forward_and_sort(R):
@@ -68,17 +66,8 @@ def test_c0_fused_l1_backward(R):
     L, og = pipeline.output_grads_l1(r, wl.targets)
     ref, _ = pipeline.backward(r, og, wl.scene)
     assert abs(loss.item() - L) <= 1e-4 * abs(L)
-    # sign(out - target) is itself a decision: pixels whose output is within
-    # 1e-5 of the target are fragile for the gradient
-    near = []
-    for img, b in zip(r.images, range(len(r.images))):
-        m = np.zeros(img["depth"].size, bool)
-        for key, c in (("rgb", 3), ("depth", 1), ("normal", 3)):
-            t = np.asarray(wl.targets[key][b], np.float64).reshape(c, -1)
-            m |= np.any(np.abs(img[key].reshape(c, -1) - t) < 1e-5, axis=0)
-        near.append(m)
-    assert sum(int(m.sum()) for m in near) == 0
-    _explicit_grads_check(gr, ref, ref["frag"], 0)
+    delta = explicit_sensitivity(wl.scene, wl.views, og)
+    _explicit_grads_check(gr, ref, ref["frag"], 0, delta)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
@@ -96,6 +85,7 @@ def test_small_explicit_sh3_tiles_backward(R, tile):
     rng = np.random.default_rng(77)
     L, og = pipeline.output_grads_linear(r, rng)
     ref, _ = pipeline.backward(r, og, wl.scene)
+    delta = explicit_sensitivity(wl.scene, wl.views, og, tile=tile)
     gout = {}
     for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
                          ("normal", "normal", 3), ("alpha", "alpha", 1)):
@@ -103,7 +93,7 @@ def test_small_explicit_sh3_tiles_backward(R, tile):
                                     device="cuda")
     gr = rd.backward(wl.views, sc, out, gout)
     torch.cuda.synchronize()
-    _explicit_grads_check(gr, ref, ref["frag"], 3)
+    _explicit_grads_check(gr, ref, ref["frag"], 3, delta)
 
 
 def test_two_views_ragged_background(R):
@@ -122,6 +112,7 @@ def test_two_views_ragged_background(R):
     rng = np.random.default_rng(78)
     L, og = pipeline.output_grads_linear(r, rng)
     ref, _ = pipeline.backward(r, og, wl.scene)
+    delta = explicit_sensitivity(wl.scene, views, og)
     gout = {}
     for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
                          ("normal", "normal", 3), ("alpha", "alpha", 1)):
@@ -129,7 +120,7 @@ def test_two_views_ragged_background(R):
                                     device="cuda")
     gr = rd.backward(views, sc, out, gout)
     torch.cuda.synchronize()
-    _explicit_grads_check(gr, ref, ref["frag"], 1)
+    _explicit_grads_check(gr, ref, ref["frag"], 1, delta)
 
 
 def test_degenerate_scenes(R):
