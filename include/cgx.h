@@ -241,6 +241,24 @@ int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream,
                        uint32_t* tile_ids, uint32_t* depth_bits, uint32_t* slots,
                        uint32_t* ranges, int32_t* rows, uint32_t* counts);
 
+/* hipGraph of the fused chain (Sec. 3.3 batch rendering as one launch).
+ * cgx_graph_capture_fwd_bwd_l1 records exactly the launches of
+ * cgx_render_fwd_bwd_l1 with these arguments on `stream` (which must not be
+ * the null stream) and instantiates them; every pointer, capacity and view
+ * is baked in, so the buffers must stay allocated while the graph lives.
+ * cgx_graph_launch replays it on any stream; counters and the loss are
+ * reset by the graph itself, and capacity overflow is read as usual with
+ * cgx_read_info.  Phase timing is not recorded inside a graph. */
+typedef struct cgx_graph cgx_graph;
+int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                     const cgx_scene* scene, const cgx_capacity* cap,
+                                     void* workspace, size_t workspace_bytes,
+                                     const cgx_images* target, const float* w3_host,
+                                     const cgx_images* out, const cgx_grads* grads,
+                                     float* loss_dev, void* stream, cgx_graph** graph);
+int32_t cgx_graph_launch(cgx_graph* graph, void* stream);
+int32_t cgx_graph_destroy(cgx_graph* graph);
+
 /* Phases of a launch chain, for cgx_timing_read. */
 enum {
   CGX_PHASE_SELECT = 0,      /* a0 anchor selection and compaction */

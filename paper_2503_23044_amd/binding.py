@@ -107,6 +107,13 @@ def load_library(path: str = LIB_PATH):
                                               C.POINTER(cgx_grads), P, P]),
         "cgx_read_info": (C.c_int32, [P, P, P, C.POINTER(cgx_run_info)]),
         "cgx_debug_copy": (C.c_int32, [P, P, P, P, P, P, P, P, P]),
+        "cgx_graph_capture_fwd_bwd_l1": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
+                                                     C.POINTER(cgx_scene), C.POINTER(cgx_capacity),
+                                                     P, C.c_size_t, C.POINTER(cgx_images),
+                                                     C.POINTER(C.c_float), C.POINTER(cgx_images),
+                                                     C.POINTER(cgx_grads), P, P, C.POINTER(P)]),
+        "cgx_graph_launch": (C.c_int32, [P, P]),
+        "cgx_graph_destroy": (C.c_int32, [P]),
         "cgx_timing_enable": (C.c_int32, [P, C.c_int32]),
         "cgx_timing_read": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]),
     }
@@ -316,3 +323,31 @@ def cgx_timing_read(ctx):
     cnt = (C.c_int32 * n)()
     _check(ctx, load_library().cgx_timing_read(ctx, ms, cnt, n), "cgx_timing_read")
     return {PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def cgx_graph_capture_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grads,
+                                 loss_dev, stream):
+    """Capture the fused chain on `stream` (a torch.cuda.Stream, not the
+    default stream) into a graph handle."""
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    w = (C.c_float * 3)(*[float(x) for x in weights])
+    g = C.c_void_p()
+    rc = lib.cgx_graph_capture_fwd_bwd_l1(ctx, va, len(views), C.byref(sc),
+                                          C.byref(make_capacity(cap)), C.c_void_p(ws.data_ptr()),
+                                          ws.numel(), C.byref(make_images(target)), w,
+                                          C.byref(make_images(out)), C.byref(make_grads(grads)),
+                                          _ptr(loss_dev), C.c_void_p(stream.cuda_stream), C.byref(g))
+    _check(ctx, rc, "cgx_graph_capture_fwd_bwd_l1")
+    return g
+
+
+def cgx_graph_launch(graph, stream):
+    rc = load_library().cgx_graph_launch(graph, C.c_void_p(stream.cuda_stream))
+    if rc != CGX_OK:
+        raise CgxError(rc, "cgx_graph_launch")
+
+
+def cgx_graph_destroy(graph):
+    return load_library().cgx_graph_destroy(graph)

@@ -160,8 +160,9 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   int bits = 1;
   while ((int64_t(1) << bits) < tiles) ++bits;
   L.tile_bits = bits;
-  L.n_passes = 4 + (bits + kRadixBits - 1) / kRadixBits;
-  L.final_buf = L.n_passes & 1;
+  L.n_passes = sort_passes(32) + sort_passes(bits);
+  L.vis_buf = sort_passes(32) & 1;
+  L.final_buf = sort_passes(bits) & 1;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -178,11 +179,14 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.counts = take(sizeof(uint32_t) * (size_t)L.max_splats);
   L.offsets = take(sizeof(uint32_t) * (size_t)L.max_splats);
   for (int b = 0; b < 2; ++b) {
-    L.keys_hi[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
-    L.keys_lo[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
-    L.vals[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+    L.vkey[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
+    L.vslot[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
   }
-  L.hist = take(sizeof(uint32_t) * kRadix * kSortBlocks);
+  for (int b = 0; b < 2; ++b) {
+    L.pkey[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+    L.pval[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+  }
+  L.hist = take(sizeof(uint32_t) * sort_hist_words());
   L.ranges = take(sizeof(uint2) * (size_t)tiles);
   L.px_T = take(sizeof(float) * (size_t)px);
   L.px_last = take(sizeof(uint32_t) * (size_t)px);
@@ -237,9 +241,10 @@ struct Ptrs {
   Splat* splats;
   uint32_t* counts;
   uint32_t* offsets;
-  uint32_t* khi[2];
-  uint32_t* klo[2];
-  uint32_t* val[2];
+  uint32_t* vkey[2];
+  uint32_t* vslot[2];
+  uint32_t* pkey[2];
+  uint32_t* pval[2];
   uint32_t* hist;
   uint2* ranges;
   float* px_T;
@@ -259,9 +264,10 @@ static Ptrs pointers(void* ws, const Layout& L) {
   p.counts = at<uint32_t>(ws, L.counts);
   p.offsets = at<uint32_t>(ws, L.offsets);
   for (int b = 0; b < 2; ++b) {
-    p.khi[b] = at<uint32_t>(ws, L.keys_hi[b]);
-    p.klo[b] = at<uint32_t>(ws, L.keys_lo[b]);
-    p.val[b] = at<uint32_t>(ws, L.vals[b]);
+    p.vkey[b] = at<uint32_t>(ws, L.vkey[b]);
+    p.vslot[b] = at<uint32_t>(ws, L.vslot[b]);
+    p.pkey[b] = at<uint32_t>(ws, L.pkey[b]);
+    p.pval[b] = at<uint32_t>(ws, L.pval[b]);
   }
   p.hist = at<uint32_t>(ws, L.hist);
   p.ranges = at<uint2>(ws, L.ranges);
@@ -291,9 +297,10 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   WsHeader h;
   memset(&h, 0, sizeof(h));
   h.total = L.total;
-  h.keys_hi = L.keys_hi[L.final_buf];
-  h.keys_lo = L.keys_lo[L.final_buf];
-  h.vals = L.vals[L.final_buf];
+  h.keys_hi = L.pkey[L.final_buf];
+  h.keys_lo = L.pkey[1 - L.final_buf];   // scratch after the sort: depth bits for debug copies
+  h.vals = L.pval[L.final_buf];
+  h.splats = L.splats;
   h.ranges = L.ranges;
   h.rows = L.rows;
   h.counts = L.counts;
@@ -322,23 +329,32 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
     phase_end(c, st);
   }
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
+  // low 32 bits of the (tile | depth) keys: visible splats sorted by depth
   phase_begin(c, CGX_PHASE_SCAN, st);
-  launch_scan_counts(P.counts, P.offsets, P.part, n_dev, n_slots, (uint32_t)L.max_pairs, P.ctr, st);
-  phase_end(c, st);
-  phase_begin(c, CGX_PHASE_DUPLICATE, st);
-  launch_duplicate(P.views, P.splats, P.counts, P.offsets, n_dev, n_slots,
-                   expl ? 1 : s->an.n_offsets, expl ? nullptr : P.rows, 0,
-                   expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
-                   (uint32_t)L.max_pairs, P.khi[0], P.klo[0], P.val[0], st);
+  launch_compact_visible(P.counts, P.splats, n_dev, n_slots, P.part, P.ctr, P.vkey[0], P.vslot[0],
+                         st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
-  int fb = launch_radix_sort(P.khi, P.klo, P.val, P.ctr, P.hist, L.tile_bits,
-                             (uint32_t)L.max_pairs, st);
-  (void)fb;
+  const int vb = launch_sort_kv(P.vkey, P.vslot, &P.ctr->n_visible, n_slots, P.hist, 32, st);
   phase_end(c, st);
+  // pair offsets in depth order, pair emission, then the tile-id bits
+  phase_begin(c, CGX_PHASE_DUPLICATE, st);
+  launch_scan_counts(P.counts, P.vslot[vb], P.offsets, P.part, &P.ctr->n_visible, n_slots,
+                     (uint32_t)L.max_pairs, P.ctr, st);
+  launch_emit_pairs(P.views, P.splats, P.vslot[vb], P.offsets, P.ctr, expl ? 1 : s->an.n_offsets,
+                    expl ? nullptr : P.rows,
+                    expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
+                    (uint32_t)L.max_pairs, P.pkey[0], P.pval[0], st);
+  phase_end(c, st);
+  phase_begin(c, CGX_PHASE_SORT, st);
+  const int fb = launch_sort_kv(P.pkey, P.pval, &P.ctr->n_pairs, (uint32_t)L.max_pairs, P.hist,
+                                L.tile_bits, st);
+  phase_end(c, st);
+  (void)vb;
+  (void)fb;
   phase_begin(c, CGX_PHASE_RANGES, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(P.ranges), 0u, 2 * (size_t)L.n_tiles, st);
-  launch_ranges(P.khi[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
+  launch_ranges(P.pkey[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
   phase_end(c, st);
 
   RasterArgs a;
@@ -346,7 +362,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.views = P.views;
   a.B = B;
   a.splats = P.splats;
-  a.vals = P.val[L.final_buf];
+  a.vals = P.pval[L.final_buf];
   a.ranges = P.ranges;
   a.n_tiles = (uint32_t)L.n_tiles;
   a.n_slots = (uint32_t)L.max_splats;
@@ -402,7 +418,7 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   a.views = P.views;
   a.B = B;
   a.splats = P.splats;
-  a.vals = P.val[L.final_buf];
+  a.vals = P.pval[L.final_buf];
   a.ranges = P.ranges;
   a.n_tiles = (uint32_t)L.n_tiles;
   a.n_slots = (uint32_t)L.max_splats;
@@ -625,6 +641,64 @@ static int32_t read_counters(cgx_ctx* ctx, const void* workspace, void* stream, 
   return CGX_OK;
 }
 
+struct cgx_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                     const cgx_scene* scene, const cgx_capacity* cap,
+                                     void* workspace, size_t workspace_bytes,
+                                     const cgx_images* target, const float* w3_host,
+                                     const cgx_images* out, const cgx_grads* grads,
+                                     float* loss_dev, void* stream, cgx_graph** graph) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!graph) return fail(ctx, CGX_ERR_INVALID_ARG, "graph is NULL");
+  *graph = nullptr;
+  if (!stream) return fail(ctx, CGX_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+  Layout L;
+  int32_t rc = common_checks(ctx, views, n_views, scene, cap, workspace, workspace_bytes, L);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // events are not recorded inside a graph
+  const int saved_cap = ctx->ev_cap;
+  ctx->ev_cap = 0;
+  HIP_OK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  rc = cgx_render_fwd_bwd_l1(ctx, views, n_views, scene, cap, workspace, workspace_bytes, target,
+                             w3_host, out, grads, loss_dev, stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  ctx->ev_cap = saved_cap;
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, CGX_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  cgx_graph* out_g = new cgx_graph();
+  out_g->graph = g;
+  e = hipGraphInstantiate(&out_g->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    delete out_g;
+    return fail(ctx, CGX_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *graph = out_g;
+  return CGX_OK;
+}
+
+int32_t cgx_graph_launch(cgx_graph* graph, void* stream) {
+  if (!graph || !graph->exec) return CGX_ERR_INVALID_ARG;
+  return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? CGX_OK : CGX_ERR_HIP;
+}
+
+int32_t cgx_graph_destroy(cgx_graph* graph) {
+  if (!graph) return CGX_OK;
+  if (graph->exec) hipGraphExecDestroy(graph->exec);
+  if (graph->graph) hipGraphDestroy(graph->graph);
+  delete graph;
+  return CGX_OK;
+}
+
 int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run_info* info) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   if (!workspace || !info) return fail(ctx, CGX_ERR_INVALID_ARG, "NULL argument");
@@ -665,7 +739,17 @@ int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream, uint32
   const char* base = reinterpret_cast<const char*>(workspace);
   const size_t P = h.n_pairs;
   if (tile_ids && P) HIP_OK(ctx, hipMemcpy(tile_ids, base + h.hdr.keys_hi, 4 * P, hipMemcpyDeviceToHost));
-  if (depth_bits && P) HIP_OK(ctx, hipMemcpy(depth_bits, base + h.hdr.keys_lo, 4 * P, hipMemcpyDeviceToHost));
+  if (depth_bits && P) {
+    // gather each sorted pair's depth bits from its splat into free scratch
+    char* wbase = const_cast<char*>(base);
+    launch_gather_depth(reinterpret_cast<const uint32_t*>(base + h.hdr.vals),
+                        reinterpret_cast<const Splat*>(base + h.hdr.splats),
+                        reinterpret_cast<const Counters*>(base), (uint32_t)h.hdr.max_splats,
+                        (uint32_t)h.hdr.max_pairs, reinterpret_cast<uint32_t*>(wbase + h.hdr.keys_lo),
+                        (hipStream_t)stream);
+    HIP_OK(ctx, hipStreamSynchronize((hipStream_t)stream));
+    HIP_OK(ctx, hipMemcpy(depth_bits, base + h.hdr.keys_lo, 4 * P, hipMemcpyDeviceToHost));
+  }
   if (slots && P) HIP_OK(ctx, hipMemcpy(slots, base + h.hdr.vals, 4 * P, hipMemcpyDeviceToHost));
   if (ranges && h.hdr.n_tiles)
     HIP_OK(ctx, hipMemcpy(ranges, base + h.hdr.ranges, 8 * (size_t)h.hdr.n_tiles, hipMemcpyDeviceToHost));

@@ -30,8 +30,7 @@ constexpr int kSortBlocks = 512;    // fixed grid of the radix-sort passes
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;       // keys per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxRadixBits = 9;    // digit width bound of the LSD passes
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
@@ -58,7 +57,7 @@ struct ViewDev {
 // workspace pointer.
 struct WsHeader {
   uint64_t total;
-  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts;
+  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts, splats;
   int64_t n_tiles, n_pixels, max_rows, max_splats, max_pairs;
   int32_t n_views, kind;
   int32_t sort_passes, pad;
@@ -70,6 +69,8 @@ struct Counters {
   uint32_t n_splats;
   uint32_t n_pairs;
   uint32_t overflow;           // bit 0 rows, bit 1 splats, bit 2 pairs
+  uint32_t n_visible;          // splats that touch at least one tile
+  uint32_t pad0;
   unsigned long long need_rows;
   unsigned long long need_splats;
   unsigned long long need_pairs;
@@ -111,13 +112,15 @@ struct ViewPack {
 
 struct Layout {
   size_t views, counters, scan_part, rows, row_off, splats, counts, offsets;
-  size_t keys_hi[2], keys_lo[2], vals[2];
+  size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
+  size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
   size_t total;
   int64_t max_rows, max_splats, max_pairs;
   int64_t n_tiles, n_pixels;
   int tile_bits;
-  int n_passes;
+  int n_passes;                // radix passes: depth (splats) + tile id (pairs)
+  int vis_buf;                 // buffer holding the depth-sorted visible splats
   int final_buf;               // buffer holding the sorted pairs
 };
 
@@ -211,11 +214,27 @@ void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStrea
 void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s);
 
-// device-wide exclusive scan of counts[0..n) (n from *n_dev if non-null,
-// else n_host) into offsets clamped to cap; total -> *total, overflow bit
-void launch_scan_counts(const uint32_t* counts, uint32_t* offsets, unsigned long long* part,
-                        const uint32_t* n_dev, uint32_t n_host, uint32_t cap, Counters* ctr,
-                        hipStream_t s);
+// device-wide exclusive scan of counts[idx[i]] (idx may be NULL) for
+// i < n (n from *n_dev if non-null, else n_host) into offsets clamped to
+// cap; the total becomes the pair count (overflow bit 2 above cap)
+void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
+                        unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
+                        uint32_t cap, Counters* ctr, hipStream_t s);
+void launch_compact_visible(const uint32_t* counts, const Splat* splats, const uint32_t* n_dev,
+                            uint32_t n_host, unsigned long long* part, Counters* ctr,
+                            uint32_t* vkey, uint32_t* vslot, hipStream_t s);
+void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
+                       const uint32_t* voff, const Counters* ctr, int n_per_row, const int2* rows,
+                       uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
+                       uint32_t* pval, hipStream_t s);
+void launch_gather_depth(const uint32_t* pval, const Splat* splats, const Counters* ctr,
+                         uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
+size_t sort_hist_words();
+int sort_passes(int bits);
+// stable LSD sort of 32-bit keys with 32-bit values on bits [0, bits);
+// returns the buffer index holding the result
+int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, uint32_t cap,
+                   uint32_t* hist, int bits, hipStream_t s);
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
                              int tw, int th, Splat* splats, uint32_t* counts, hipStream_t s);
@@ -226,16 +245,6 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
                            uint32_t* counts, Counters* ctr, hipStream_t s);
 
-void launch_duplicate(const ViewDev* views, const Splat* splats, const uint32_t* counts,
-                      const uint32_t* offsets, const uint32_t* n_slots_dev, uint32_t n_slots_host,
-                      int n_offsets_per_row, const int2* rows, int views_are_row_major,
-                      uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* keys_hi,
-                      uint32_t* keys_lo, uint32_t* vals, hipStream_t s);
-
-// returns the index (0/1) of the buffer holding the result
-int launch_radix_sort(uint32_t* keys_hi[2], uint32_t* keys_lo[2], uint32_t* vals[2],
-                      const Counters* ctr, uint32_t* hist, int tile_bits, uint32_t cap,
-                      hipStream_t s);
 
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
                    uint32_t cap, hipStream_t s);

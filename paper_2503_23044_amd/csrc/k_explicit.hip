@@ -1,5 +1,5 @@
-// Explicit Gaussians: projection with spherical-harmonic colour (a2), its
-// adjoint (a9), and the pair emission (a3) shared with the anchor path.
+// Explicit Gaussians: projection with spherical-harmonic colour (a2) and
+// its adjoint (a9).
 #include "cgx_project.h"
 
 namespace cgx {
@@ -224,56 +224,6 @@ void launch_project_explicit_backward(const ViewDev* views, int B, const cgx_exp
     case 2: hipLaunchKernelGGL(k_project_explicit_bwd<2>, dim3(blocks), dim3(256), 0, s, views, B, sc, counts, sgrad, g); break;
     default: hipLaunchKernelGGL(k_project_explicit_bwd<3>, dim3(blocks), dim3(256), 0, s, views, B, sc, counts, sgrad, g); break;
   }
-}
-
-// ---------------------------------------------------------------------
-// a3: emit one (tile id, depth bits, slot) pair per tile a splat touches,
-// tiles in row-major order, at the splat's scanned offset.
-// ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_duplicate(const ViewDev* __restrict__ views,
-                                                   const Splat* __restrict__ splats,
-                                                   const uint32_t* __restrict__ counts,
-                                                   const uint32_t* __restrict__ offsets,
-                                                   const uint32_t* n_slots_dev, uint32_t n_slots_host,
-                                                   int n_per_row, const int2* __restrict__ rows,
-                                                   uint32_t N_explicit, int tw, int th, uint32_t cap,
-                                                   uint32_t* __restrict__ khi, uint32_t* __restrict__ klo,
-                                                   uint32_t* __restrict__ kval) {
-  uint32_t n = n_slots_dev ? *n_slots_dev : n_slots_host;
-  if (n > n_slots_host) n = n_slots_host;
-  for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n;
-       slot += gridDim.x * blockDim.x) {
-    const uint32_t cnt = counts[slot];
-    if (cnt == 0) continue;
-    const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
-    const ViewDev& V = views[v];
-    const Splat& sp = splats[slot];
-    const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
-    const int y_lo = sp.by & 0xFFFF, y_hi = sp.by >> 16;
-    const int tx0 = x_lo / tw, tx1 = x_hi / tw, ty0 = y_lo / th, ty1 = y_hi / th;
-    uint32_t off = offsets[slot];
-    for (int ty = ty0; ty <= ty1; ++ty) {
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (off >= cap) return;
-        khi[off] = (uint32_t)(V.tile_off + ty * V.TX + tx);
-        klo[off] = sp.zbits;
-        kval[off] = slot;
-        ++off;
-      }
-    }
-  }
-}
-
-void launch_duplicate(const ViewDev* views, const Splat* splats, const uint32_t* counts,
-                      const uint32_t* offsets, const uint32_t* n_slots_dev, uint32_t n_slots_host,
-                      int n_offsets_per_row, const int2* rows, int views_are_row_major,
-                      uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* keys_hi,
-                      uint32_t* keys_lo, uint32_t* vals, hipStream_t s) {
-  (void)views_are_row_major;
-  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_slots_host, 256), 16384));
-  hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, s, views, splats, counts, offsets,
-                     n_slots_dev, n_slots_host, n_offsets_per_row, rows, N_explicit, tw, th, cap,
-                     keys_hi, keys_lo, vals);
 }
 
 }  // namespace cgx

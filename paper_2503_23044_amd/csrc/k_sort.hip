@@ -1,220 +1,447 @@
-// a4: stable LSD radix sort of (tile id | depth bits) 64-bit keys with
-// 32-bit values (splat slots), over the significant bits only: 32 bits of
-// depth, then ceil(log2(tiles)) bits of tile id, 8 bits per pass.
+// a3 + a4: binning and the (tile | depth) radix sort.
 //
-// The key is held as two 32-bit planes (hi = global tile id, lo = float32
-// depth bits) so that a pass reads only the plane its digit comes from in
-// the histogram step.  Each pass is reduce-then-scan over a fixed grid:
-//   upsweep    per-block digit histograms of a contiguous chunk
-//   scan       exclusive scan of the digit-major histogram table
-//   downsweep  per 2048-key tile: wave-level digit matching with 8 ballots
-//              gives each key its stable rank, keys are staged in LDS in
-//              digit order and written out in coalesced runs.
-// The pair count is read on the device, so the same launches serve any
-// count up to the capacity (and can be captured in a graph).
+// The order the rasterizer needs is that of the 64-bit keys
+// (global tile id << 32 | float32 depth bits) with ties in emission order
+// (slot order).  An LSD radix sort processes the low 32 bits first; since
+// every pair emitted by one splat carries that splat's depth bits, those
+// passes are run once per visible splat instead of once per pair:
+//   1. visible splats (tile count > 0) are compacted in slot order with
+//      their depth bits as keys;
+//   2. a stable 32-bit LSD sort orders them by depth bits (ties stay in slot
+//      order);
+//   3. pairs are emitted in that order (load-balanced: one thread per pair);
+//   4. a stable LSD sort of the pairs on the significant bits of the tile id
+//      finishes the 64-bit sort.
+// The result is bit-identical to sorting the 64-bit keys of all pairs.
+//
+// The sort itself is reduce-then-scan per pass over a fixed grid, counts
+// read on the device: per-block digit histograms, a coalesced per-digit
+// scan, and a downsweep where each 2048-key tile is ranked with wave-level
+// digit matching (one ballot per digit bit), staged in LDS in digit order
+// and written out in coalesced runs.
 #include "cgx_common.h"
 
 namespace cgx {
 
-__device__ __forceinline__ void chunk_of(uint32_t P, uint32_t& b0, uint32_t& b1) {
-  uint32_t per = (P + gridDim.x - 1) / gridDim.x;
+__device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t& b0, uint32_t& b1) {
+  uint32_t per = (n + gridDim.x - 1) / gridDim.x;
   per = (per + kSortTile - 1) / kSortTile * kSortTile;
-  uint64_t s = (uint64_t)blockIdx.x * per;
-  uint64_t e = s + per;
-  b0 = (uint32_t)(s < P ? s : P);
-  b1 = (uint32_t)(e < P ? e : P);
+  const uint64_t s = (uint64_t)blockIdx.x * per;
+  const uint64_t e = s + per;
+  b0 = (uint32_t)(s < n ? s : n);
+  b1 = (uint32_t)(e < n ? e : n);
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(const uint32_t* word,
-                                                               const Counters* ctr,
-                                                               uint32_t* hist, int shift) {
-  __shared__ uint32_t h[kSortThreads / kWave][kRadix];
+__device__ __forceinline__ uint32_t clamp_count(const uint32_t* n_dev, uint32_t cap) {
+  const uint32_t n = *n_dev;
+  return n < cap ? n : cap;
+}
+
+template <int BITS>
+__global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(const uint32_t* __restrict__ keys,
+                                                               const uint32_t* n_dev, uint32_t cap,
+                                                               uint32_t* __restrict__ hist,
+                                                               int shift) {
+  constexpr int R = 1 << BITS;
+  constexpr int NW = kSortThreads / kWave;
+  __shared__ uint32_t h[NW][R];
   const int wave = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < (kSortThreads / kWave) * kRadix; i += kSortThreads)
-    (&h[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < NW * R; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   uint32_t b0, b1;
-  chunk_of(ctr->n_pairs, b0, b1);
-  for (uint32_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
-    uint32_t d = (word[i] >> shift) & (kRadix - 1);
-    atomicAdd(&h[wave][d], 1u);
-  }
+  sort_chunk(clamp_count(n_dev, cap), b0, b1);
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += kSortThreads)
+    atomicAdd(&h[wave][(keys[i] >> shift) & (R - 1)], 1u);
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+  for (int d = threadIdx.x; d < R; d += kSortThreads) {
     uint32_t s = 0;
 #pragma unroll
-    for (int w = 0; w < kSortThreads / kWave; ++w) s += h[w][d];
+    for (int w = 0; w < NW; ++w) s += h[w][d];
     hist[(size_t)d * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// exclusive scan of n entries in place, one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* hist, int n) {
-  __shared__ uint32_t lw[16];
-  const int per = n / 1024;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  uint32_t* p = hist + (size_t)threadIdx.x * per;
-  uint32_t s = 0;
-  for (int i = 0; i < per; ++i) s += p[i];
-  uint32_t v = s;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t y = __shfl_up(v, o, kWave);
-    if (lane >= o) v += y;
-  }
-  if (lane == kWave - 1) lw[wave] = v;
-  __syncthreads();
+// per digit: exclusive scan over the blocks (one workgroup per digit), and
+// the digit's total
+__global__ __launch_bounds__(256) void k_sort_scan_digit(uint32_t* __restrict__ hist, int nb,
+                                                         uint32_t* __restrict__ totals) {
+  __shared__ uint32_t lw[4];
+  const int d = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t* p = hist + (size_t)d * nb;
   uint32_t carry = 0;
-  for (int w = 0; w < wave; ++w) carry += lw[w];
-  uint32_t run = carry + v - s;
-  for (int i = 0; i < per; ++i) {
-    uint32_t c = p[i];
-    p[i] = run;
-    run += c;
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + threadIdx.x;
+    const uint32_t c = i < nb ? p[i] : 0u;
+    uint32_t v = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(v, o, kWave);
+      if (lane >= o) v += y;
+    }
+    if (lane == kWave - 1) lw[wave] = v;
+    __syncthreads();
+    uint32_t wc = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) wc += lw[w];
+      tot += lw[w];
+    }
+    if (i < nb) p[i] = carry + wc + v - c;
+    carry += tot;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) totals[d] = carry;
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(
-    const uint32_t* __restrict__ khi, const uint32_t* __restrict__ klo,
-    const uint32_t* __restrict__ kval, uint32_t* __restrict__ ohi, uint32_t* __restrict__ olo,
-    uint32_t* __restrict__ oval, const uint32_t* __restrict__ hist, const Counters* ctr, int shift,
-    int from_hi, uint32_t cap) {
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals, const uint32_t* n_dev, uint32_t cap, int shift) {
+  constexpr int R = 1 << BITS;
   constexpr int NW = kSortThreads / kWave;
-  constexpr int SEG = kWave * kSortItems;   // keys per wave per tile
-  __shared__ uint32_t s_hi[kSortTile];
-  __shared__ uint32_t s_lo[kSortTile];
+  constexpr int SEG = kWave * kSortItems;
+  __shared__ uint32_t s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
-  __shared__ uint32_t wave_cnt[NW][kRadix];
-  __shared__ uint32_t digit_base[kRadix];
-  __shared__ uint32_t tile_start[kRadix];
+  __shared__ uint32_t wave_cnt[NW][R];
+  __shared__ uint32_t digit_base[R];
+  __shared__ uint32_t tile_start[R];
   __shared__ uint32_t lw[NW];
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  for (int d = threadIdx.x; d < kRadix; d += kSortThreads)
-    digit_base[d] = hist[(size_t)d * gridDim.x + blockIdx.x];
-
+  // digit bases: exclusive scan of the digit totals plus this block's offset
+  {
+    uint32_t carry = 0;
+    for (int base = 0; base < R; base += kSortThreads) {
+      const int d = base + threadIdx.x;
+      const uint32_t c = d < R ? totals[d] : 0u;
+      uint32_t v = c;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(v, o, kWave);
+        if (lane >= o) v += y;
+      }
+      if (lane == kWave - 1) lw[wave] = v;
+      __syncthreads();
+      uint32_t wc = 0, tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        if (w < wave) wc += lw[w];
+        tot += lw[w];
+      }
+      if (d < R) digit_base[d] = carry + wc + v - c + hist[(size_t)d * gridDim.x + blockIdx.x];
+      carry += tot;
+      __syncthreads();
+    }
+  }
   uint32_t b0, b1;
-  chunk_of(ctr->n_pairs, b0, b1);
+  sort_chunk(clamp_count(n_dev, cap), b0, b1);
   __syncthreads();
 
   for (uint32_t tb = b0; tb < b1; tb += kSortTile) {
-    for (int d = lane; d < kRadix; d += kWave) wave_cnt[wave][d] = 0;
+    for (int d = lane; d < R; d += kWave) wave_cnt[wave][d] = 0;
     __syncthreads();
-
-    uint32_t rhi[kSortItems], rlo[kSortItems], rval[kSortItems], rank[kSortItems];
+    uint32_t rkey[kSortItems], rval[kSortItems], rank[kSortItems];
     int rdig[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-      uint32_t idx = tb + wave * SEG + it * kWave + lane;
-      bool valid = idx < b1;
-      uint32_t h = 0, l = 0, v = 0;
+      const uint32_t idx = tb + wave * SEG + it * kWave + lane;
+      const bool valid = idx < b1;
+      uint32_t k = 0, v = 0;
       if (valid) {
-        h = khi[idx];
-        l = klo[idx];
-        v = kval[idx];
+        k = kin[idx];
+        v = vin[idx];
       }
-      int d = (int)(((from_hi ? h : l) >> shift) & (kRadix - 1));
+      const int d = (int)((k >> shift) & (R - 1));
       uint64_t peers = __ballot(valid);
 #pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
-        bool bit = (d >> b) & 1;
-        uint64_t m = __ballot(valid && bit);
+      for (int b = 0; b < BITS; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t m = __ballot(valid && bit);
         peers &= bit ? m : ~m;
       }
-      uint32_t prev = valid ? wave_cnt[wave][d] : 0;
-      uint32_t below = (uint32_t)__popcll(peers & lt_mask);
-      // the lowest peer publishes the new count after every peer has read
-      bool leader = valid && below == 0;
+      const uint32_t prev = valid ? wave_cnt[wave][d] : 0u;
+      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
       __builtin_amdgcn_wave_barrier();
-      if (leader) wave_cnt[wave][d] = prev + (uint32_t)__popcll(peers);
+      if (valid && below == 0) wave_cnt[wave][d] = prev + (uint32_t)__popcll(peers);
       __builtin_amdgcn_wave_barrier();
-      rhi[it] = h;
-      rlo[it] = l;
+      rkey[it] = k;
       rval[it] = v;
       rdig[it] = valid ? d : -1;
       rank[it] = prev + below;
     }
     __syncthreads();
-
-    // per digit: offsets of each wave within the tile, and the digit total
-    uint32_t total = 0;
-    if (threadIdx.x < kRadix) {
-      int d = threadIdx.x;
-      uint32_t run = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        uint32_t c = wave_cnt[w][d];
-        wave_cnt[w][d] = run;
-        run += c;
-      }
-      total = run;
-    }
-    // exclusive scan of the digit totals across the block (256 digits)
-    uint32_t v = total;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      uint32_t y = __shfl_up(v, o, kWave);
-      if (lane >= o) v += y;
-    }
-    if (lane == kWave - 1) lw[wave] = v;
-    __syncthreads();
+    // per digit: offsets of the waves inside the tile and the digit start
     uint32_t carry = 0;
-    for (int w = 0; w < wave; ++w) carry += lw[w];
-    if (threadIdx.x < kRadix) tile_start[threadIdx.x] = carry + v - total;
-    __syncthreads();
-
+    for (int base = 0; base < R; base += kSortThreads) {
+      const int d = base + threadIdx.x;
+      uint32_t run = 0;
+      if (d < R) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = wave_cnt[w][d];
+          wave_cnt[w][d] = run;
+          run += c;
+        }
+      }
+      uint32_t v = run;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(v, o, kWave);
+        if (lane >= o) v += y;
+      }
+      if (lane == kWave - 1) lw[wave] = v;
+      __syncthreads();
+      uint32_t wc = 0, tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        if (w < wave) wc += lw[w];
+        tot += lw[w];
+      }
+      if (d < R) tile_start[d] = carry + wc + v - run;
+      carry += tot;
+      __syncthreads();
+    }
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-      int d = rdig[it];
+      const int d = rdig[it];
       if (d >= 0) {
-        uint32_t pos = tile_start[d] + wave_cnt[wave][d] + rank[it];
-        if (pos >= (uint32_t)kSortTile) continue;   // cannot happen for consistent ranks
-        s_hi[pos] = rhi[it];
-        s_lo[pos] = rlo[it];
-        s_val[pos] = rval[it];
+        const uint32_t pos = tile_start[d] + wave_cnt[wave][d] + rank[it];
+        if (pos < (uint32_t)kSortTile) {   // always, for consistent ranks
+          s_key[pos] = rkey[it];
+          s_val[pos] = rval[it];
+        }
       }
     }
     __syncthreads();
-
-    uint32_t n_valid = (b1 - tb) < (uint32_t)kSortTile ? (b1 - tb) : (uint32_t)kSortTile;
+    const uint32_t n_valid = (b1 - tb) < (uint32_t)kSortTile ? (b1 - tb) : (uint32_t)kSortTile;
     for (uint32_t j = threadIdx.x; j < n_valid; j += kSortThreads) {
-      uint32_t h = s_hi[j], l = s_lo[j];
-      int d = (int)(((from_hi ? h : l) >> shift) & (kRadix - 1));
-      uint32_t g = digit_base[d] + (j - tile_start[d]);
-      if (g < cap) {   // always true for a consistent histogram
-        ohi[g] = h;
-        olo[g] = l;
-        oval[g] = s_val[j];
+      const uint32_t k = s_key[j];
+      const int d = (int)((k >> shift) & (R - 1));
+      const uint32_t g = digit_base[d] + (j - tile_start[d]);
+      if (g < cap) {   // always, for a consistent histogram
+        kout[g] = k;
+        vout[g] = s_val[j];
       }
     }
     __syncthreads();
-    if (threadIdx.x < kRadix) digit_base[threadIdx.x] += total;
+    // advance each digit's base by its count in this tile
+    for (int d = threadIdx.x; d < R; d += kSortThreads) {
+      const uint32_t next = (d + 1 < R) ? tile_start[d + 1] : n_valid;
+      digit_base[d] += next - tile_start[d];
+    }
     __syncthreads();
   }
 }
 
-int launch_radix_sort(uint32_t* keys_hi[2], uint32_t* keys_lo[2], uint32_t* vals[2],
-                      const Counters* ctr, uint32_t* hist, int tile_bits, uint32_t cap,
-                      hipStream_t s) {
-  int src = 0;
-  const int hi_passes = (tile_bits + kRadixBits - 1) / kRadixBits;
-  for (int pass = 0; pass < 4 + hi_passes; ++pass) {
-    const int from_hi = pass >= 4;
-    const int shift = (from_hi ? pass - 4 : pass) * kRadixBits;
-    const uint32_t* word = from_hi ? keys_hi[src] : keys_lo[src];
-    hipLaunchKernelGGL(k_sort_upsweep, dim3(kSortBlocks), dim3(kSortThreads), 0, s, word, ctr,
-                       hist, shift);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, kRadix * kSortBlocks);
-    hipLaunchKernelGGL(k_sort_downsweep, dim3(kSortBlocks), dim3(kSortThreads), 0, s,
-                       keys_hi[src], keys_lo[src], vals[src], keys_hi[1 - src], keys_lo[1 - src],
-                       vals[1 - src], hist, ctr, shift, from_hi, cap);
+template <int BITS>
+static void one_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                     const uint32_t* n_dev, uint32_t cap, uint32_t* hist, int shift, hipStream_t s) {
+  constexpr int R = 1 << BITS;
+  uint32_t* totals = hist + (size_t)R * kSortBlocks;
+  hipLaunchKernelGGL(k_sort_upsweep<BITS>, dim3(kSortBlocks), dim3(kSortThreads), 0, s,
+                     (const uint32_t*)kin, n_dev, cap, hist, shift);
+  hipLaunchKernelGGL(k_sort_scan_digit, dim3(R), dim3(256), 0, s, hist, kSortBlocks, totals);
+  hipLaunchKernelGGL(k_sort_downsweep<BITS>, dim3(kSortBlocks), dim3(kSortThreads), 0, s,
+                     (const uint32_t*)kin, (const uint32_t*)vin, kout, vout,
+                     (const uint32_t*)hist, (const uint32_t*)totals, n_dev, cap, shift);
+}
+
+size_t sort_hist_words() { return (size_t)(1 << kMaxRadixBits) * (kSortBlocks + 1); }
+
+int sort_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; }
+
+int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, uint32_t cap,
+                   uint32_t* hist, int bits, hipStream_t s) {
+  // split the significant bits into equal digits of at most kMaxRadixBits
+  const int passes = sort_passes(bits);
+  const int width = (bits + passes - 1) / passes;
+  int src = 0, shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    switch (width) {
+      case 9: one_pass<9>(keys[src], vals[src], keys[1 - src], vals[1 - src], n_dev, cap, hist, shift, s); break;
+      case 8: one_pass<8>(keys[src], vals[src], keys[1 - src], vals[1 - src], n_dev, cap, hist, shift, s); break;
+      case 7: one_pass<7>(keys[src], vals[src], keys[1 - src], vals[1 - src], n_dev, cap, hist, shift, s); break;
+      case 6: one_pass<6>(keys[src], vals[src], keys[1 - src], vals[1 - src], n_dev, cap, hist, shift, s); break;
+      default: one_pass<5>(keys[src], vals[src], keys[1 - src], vals[1 - src], n_dev, cap, hist, shift, s); break;
+    }
+    shift += width;
     src = 1 - src;
   }
   return src;
+}
+
+// ---------------------------------------------------------------------
+// 1: compact the visible splats (count > 0) in slot order, key = depth bits
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vis_partial(const uint32_t* __restrict__ counts,
+                                                     const uint32_t* n_dev, uint32_t n_host,
+                                                     unsigned long long* part) {
+  __shared__ uint32_t lw[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  if (n > n_host) n = n_host;
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * per;
+  const uint64_t b1 = b0 + per < n ? b0 + per : n;
+  uint32_t c = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += 256) c += counts[i] != 0u;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if ((threadIdx.x & 63) == 0) lw[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = lw[0] + lw[1] + lw[2] + lw[3];
+}
+
+__global__ __launch_bounds__(1024) void k_vis_top(unsigned long long* part, Counters* ctr) {
+  __shared__ unsigned long long lw[16];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const unsigned long long v0 = part[threadIdx.x];
+  unsigned long long v = v0;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) lw[wave] = v;
+  __syncthreads();
+  unsigned long long carry = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) carry += lw[w];
+    tot += lw[w];
+  }
+  part[threadIdx.x] = carry + v - v0;
+  if (threadIdx.x == 0) ctr->n_visible = (uint32_t)tot;
+}
+
+__global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ counts,
+                                                   const Splat* __restrict__ splats,
+                                                   const uint32_t* n_dev, uint32_t n_host,
+                                                   const unsigned long long* part,
+                                                   uint32_t* __restrict__ vkey,
+                                                   uint32_t* __restrict__ vslot) {
+  __shared__ uint32_t lw[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  if (n > n_host) n = n_host;
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * per;
+  const uint64_t b1 = b0 + per < n ? b0 + per : n;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint64_t carry = part[blockIdx.x];
+  for (uint64_t base = b0; base < b1; base += 256) {
+    const uint64_t i = base + threadIdx.x;
+    const bool f = i < b1 && counts[i] != 0u;
+    const uint64_t m = __ballot(f);
+    const uint32_t below = (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) lw[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t wc = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) wc += lw[w];
+      tot += lw[w];
+    }
+    if (f) {
+      const uint64_t pos = carry + wc + below;
+      vkey[pos] = splats[i].zbits;
+      vslot[pos] = (uint32_t)i;
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+void launch_compact_visible(const uint32_t* counts, const Splat* splats, const uint32_t* n_dev,
+                            uint32_t n_host, unsigned long long* part, Counters* ctr,
+                            uint32_t* vkey, uint32_t* vslot, hipStream_t s) {
+  hipLaunchKernelGGL(k_vis_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, n_dev, n_host, part);
+  hipLaunchKernelGGL(k_vis_top, dim3(1), dim3(kScanBlocks), 0, s, part, ctr);
+  hipLaunchKernelGGL(k_vis_write, dim3(kScanBlocks), dim3(256), 0, s, counts, splats, n_dev,
+                     n_host, (const unsigned long long*)part, vkey, vslot);
+}
+
+// ---------------------------------------------------------------------
+// 3: one thread per pair.  A block covers 1024 consecutive pairs; the
+// visible splats they belong to (at most 1025, every count is >= 1) are
+// found by two binary searches and their offsets staged in LDS, where each
+// pair finds its splat.
+// ---------------------------------------------------------------------
+constexpr int kDupPairs = 1024;
+
+__device__ __forceinline__ uint32_t upper_bound_g(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_emit_pairs(
+    const ViewDev* __restrict__ views, const Splat* __restrict__ splats,
+    const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff, const Counters* ctr,
+    int n_per_row, const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
+    uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  __shared__ uint32_t s_off[kDupPairs + 1];
+  __shared__ uint32_t s_j[2];
+  const uint32_t P = ctr->n_pairs;
+  const uint32_t nv = ctr->n_visible;
+  const uint32_t p0 = blockIdx.x * kDupPairs;
+  if (p0 >= P) return;
+  const uint32_t p1 = p0 + kDupPairs < P ? p0 + kDupPairs : P;
+  if (threadIdx.x == 0) s_j[0] = upper_bound_g(voff, nv, p0) - 1;
+  if (threadIdx.x == 1) s_j[1] = upper_bound_g(voff, nv, p1 - 1) - 1;
+  __syncthreads();
+  const uint32_t j0 = s_j[0], j1 = s_j[1];
+  // every visible splat has at least one pair, so m <= kDupPairs + 1
+  const uint32_t m = (j1 - j0 + 1) <= (uint32_t)kDupPairs + 1 ? (j1 - j0 + 1) : (uint32_t)kDupPairs + 1;
+  for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) s_off[t] = voff[j0 + t];
+  __syncthreads();
+  for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_off[mid] <= i) lo = mid + 1;
+      else hi = mid;
+    }
+    const uint32_t jl = lo - 1;
+    const uint32_t slot = vslot[j0 + jl];
+    const uint32_t k = i - s_off[jl];
+    const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
+    const ViewDev& V = views[v];
+    const Splat& sp = splats[slot];
+    const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
+    const int y_lo = sp.by & 0xFFFF;
+    const int tx0 = x_lo / tw, nx = x_hi / tw - tx0 + 1;
+    const int ty0 = y_lo / th;
+    const int tx = tx0 + (int)(k % (uint32_t)nx), ty = ty0 + (int)(k / (uint32_t)nx);
+    pkey[i] = (uint32_t)(V.tile_off + ty * V.TX + tx);
+    pval[i] = slot;
+  }
+}
+
+void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
+                       const uint32_t* voff, const Counters* ctr, int n_per_row, const int2* rows,
+                       uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
+                       uint32_t* pval, hipStream_t s) {
+  const uint32_t blocks = std::max<uint32_t>(1, div_up(cap, kDupPairs));
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, vslot, voff, ctr,
+                     n_per_row, rows, N_explicit, tw, th, pkey, pval);
+}
+
+// depth bits of every sorted pair (for the debug copy only)
+__global__ void k_gather_depth(const uint32_t* __restrict__ pval, const Splat* __restrict__ splats,
+                               const Counters* ctr, uint32_t n_slots, uint32_t* __restrict__ out) {
+  const uint32_t P = ctr->n_pairs;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+    const uint32_t s = pval[i];
+    out[i] = s < n_slots ? splats[s].zbits : 0u;
+  }
+}
+
+void launch_gather_depth(const uint32_t* pval, const Splat* splats, const Counters* ctr,
+                         uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s) {
+  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 8192));
+  hipLaunchKernelGGL(k_gather_depth, dim3(blocks), dim3(256), 0, s, pval, splats, ctr, n_slots, out);
 }
 
 }  // namespace cgx

@@ -70,8 +70,9 @@ __device__ T block_inclusive_scan(T v, T* lds_waves, T& block_total) {
 }
 
 // phase 1: per-block sums of counts over a contiguous chunk
-__global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, const uint32_t* n_dev,
-                                                      uint32_t n_host, unsigned long long* part) {
+__global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, const uint32_t* idx,
+                                                      const uint32_t* n_dev, uint32_t n_host,
+                                                      unsigned long long* part) {
   __shared__ unsigned long long lw[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, co
   uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   unsigned long long sum = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) sum += counts[i];
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) sum += counts[idx ? idx[i] : i];
   unsigned long long tot;
   block_inclusive_scan<unsigned long long>(sum, lw, tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -101,7 +102,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, uin
 }
 
 // phase 3: scan within each chunk, offsets clamped to cap
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, uint32_t* offsets,
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, const uint32_t* idx,
+                                                    uint32_t* offsets,
                                                     const uint32_t* n_dev, uint32_t n_host,
                                                     const unsigned long long* part, uint32_t cap) {
   __shared__ unsigned long long lw[4];
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, uint
   unsigned long long carry = part[blockIdx.x];
   for (uint64_t base = b0; base < b1; base += blockDim.x) {
     uint64_t i = base + threadIdx.x;
-    unsigned long long c = i < b1 ? counts[i] : 0ull;
+    unsigned long long c = i < b1 ? counts[idx ? idx[i] : i] : 0ull;
     unsigned long long tot;
     unsigned long long inc = block_inclusive_scan<unsigned long long>(c, lw, tot);
     if (i < b1) {
@@ -124,14 +126,14 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, uint
   }
 }
 
-void launch_scan_counts(const uint32_t* counts, uint32_t* offsets, unsigned long long* part,
-                        const uint32_t* n_dev, uint32_t n_host, uint32_t cap, Counters* ctr,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, n_dev, n_host,
-                     part);
+void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
+                        unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
+                        uint32_t cap, Counters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, n_dev,
+                     n_host, part);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, part, cap, ctr);
-  hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, counts, offsets, n_dev,
-                     n_host, (const unsigned long long*)part, cap);
+  hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, offsets,
+                     n_dev, n_host, (const unsigned long long*)part, cap);
 }
 
 // ---------------------------------------------------------------------

@@ -145,9 +145,11 @@ def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=No
     bad = (err > tol) & keep
     assert np.all(np.isfinite(got[keep])), f"{name}: non-finite values"
     rel = np.max(err[keep] / np.maximum(np.abs(ref[keep]), floor * scale + 1e-300)) if keep.any() else 0.0
-    nrm = np.linalg.norm(ref[keep])
-    nrel = float(np.linalg.norm((got - ref)[keep]) / nrm) if nrm > 0 else float(np.linalg.norm(got[keep]))
-    cond = int((d > rtol * np.maximum(np.abs(ref), floor * scale))[keep].sum())
+    # norm-wise error over the elements whose conditioning allows 1e-4
+    wc = keep & (d <= rtol * np.maximum(np.abs(ref), floor * scale))
+    nrm = np.linalg.norm(ref[wc])
+    nrel = float(np.linalg.norm((got - ref)[wc]) / nrm) if nrm > 0 else float(np.linalg.norm(got[wc]))
+    cond = int((keep & ~wc).sum())
     print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, excluded "
           f"{int(ex.sum())}/{ref.size}, ill-conditioned {cond}", flush=True)
     if bad.any():
