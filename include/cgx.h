@@ -187,8 +187,8 @@ typedef struct cgx_run_info {
 int32_t cgx_abi_version(void);
 
 /* Create a context bound to HIP device `device` with tile shape
- * tile_w x tile_h (16 x 16 is the paper's patch; 8x8, 16x8, 32x8 also
- * compiled).  Returns CGX_ERR_UNSUPPORTED for other shapes. */
+ * tile_w x tile_h (16 x 16 is the paper's patch; 8x8, 16x8, 32x8 and 32x16
+ * are also compiled).  Returns CGX_ERR_UNSUPPORTED for other shapes. */
 int32_t cgx_create(cgx_ctx** out, int32_t device, int32_t tile_w, int32_t tile_h);
 int32_t cgx_destroy(cgx_ctx* ctx);
 

@@ -61,7 +61,7 @@ static int32_t fail(cgx_ctx* c, int32_t code, const char* fmt, ...) {
 
 static bool tile_supported(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) ||
-         (tw == 32 && th == 8);
+         (tw == 32 && th == 8) || (tw == 32 && th == 16);
 }
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -325,7 +325,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
     phase_end(c, st);
     phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
-                          P.splats, P.counts, P.ctr, st);
+                          P.splats, P.counts, P.ctr, P.dz, st);
     phase_end(c, st);
   }
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;

@@ -243,7 +243,7 @@ void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& 
                            uint32_t max_rows, Counters* ctr, hipStream_t s);
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, Counters* ctr, hipStream_t s);
+                           uint32_t* counts, Counters* ctr, float* row_scratch, hipStream_t s);
 
 
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,

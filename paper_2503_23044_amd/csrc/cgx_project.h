@@ -98,11 +98,15 @@ __device__ __forceinline__ void proj_normal(const ViewDev& V, const ProjIn& in, 
   const float* R = V.R;
   int j = (in.s[0] <= in.s[1] && in.s[0] <= in.s[2]) ? 0 : (in.s[1] <= in.s[2] ? 1 : 2);
   st.jstar = j;
+  // column j of Rq as an arithmetic blend (a select of array elements would
+  // be turned into a dynamically indexed load from scratch memory)
+  const float w0 = j == 0 ? 1.0f : 0.0f, w1 = j == 1 ? 1.0f : 0.0f, w2 = j == 2 ? 1.0f : 0.0f;
+  float a[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) a[m] = w0 * st.Rq[m * 3 + 0] + w1 * st.Rq[m * 3 + 1] + w2 * st.Rq[m * 3 + 2];
   float n[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-    n[i] = R[i * 3 + 0] * st.Rq[0 * 3 + j] + R[i * 3 + 1] * st.Rq[1 * 3 + j] +
-           R[i * 3 + 2] * st.Rq[2 * 3 + j];
+  for (int i = 0; i < 3; ++i) n[i] = R[i * 3 + 0] * a[0] + R[i * 3 + 1] * a[1] + R[i * 3 + 2] * a[2];
   float ndp = n[0] * st.p[0] + n[1] * st.p[1] + n[2] * st.p[2];
   st.sign = ndp > 0.0f ? -1.0f : 1.0f;
 #pragma unroll
@@ -230,9 +234,14 @@ __device__ __forceinline__ void project_backward(const ViewDev& V, const ProjIn&
 #pragma unroll
   for (int i = 0; i < 3; ++i) dp[i] += -dd * st.n[i];
   const int j = st.jstar;
+  const float w0 = j == 0 ? 1.0f : 0.0f, w1 = j == 1 ? 1.0f : 0.0f, w2 = j == 2 ? 1.0f : 0.0f;
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-    dRq[i * 3 + j] += st.sign * (R[0 * 3 + i] * dn[0] + R[1 * 3 + i] * dn[1] + R[2 * 3 + i] * dn[2]);
+  for (int i = 0; i < 3; ++i) {
+    const float cdn = st.sign * (R[0 * 3 + i] * dn[0] + R[1 * 3 + i] * dn[1] + R[2 * 3 + i] * dn[2]);
+    dRq[i * 3 + 0] += w0 * cdn;
+    dRq[i * 3 + 1] += w1 * cdn;
+    dRq[i * 3 + 2] += w2 * cdn;
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i) dmu[i] = R[0 * 3 + i] * dp[0] + R[1 * 3 + i] * dp[1] + R[2 * 3 + i] * dp[2];
 

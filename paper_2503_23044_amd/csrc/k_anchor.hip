@@ -206,28 +206,6 @@ __device__ __forceinline__ void load_weights(DecW& w, const cgx_anchor_scene& sc
   for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
 }
 
-__device__ __forceinline__ void hidden(const DecW& w, const float* z0, float* pre1) {
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) pre1[j] = w.b1[j];
-#pragma unroll
-  for (int i = 0; i < kIn; ++i) {
-    const float zi = z0[i];
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) pre1[j] += zi * w.W1[i * kHid + j];
-  }
-}
-
-__device__ __forceinline__ void gaussian_out(const DecW& w, const float* z1, int k, float* z2) {
-#pragma unroll
-  for (int m = 0; m < kGo; ++m) z2[m] = w.b2[k * kGo + m];
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-    const float zj = z1[j];
-#pragma unroll
-    for (int m = 0; m < kGo; ++m) z2[m] += zj * w.W2[j * kOut + k * kGo + m];
-  }
-}
-
 // decoded attributes of Gaussian k of a row, in projection form
 __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uint32_t a, int k,
                                                  const float* z2, ProjIn& in, float* sig_s) {
@@ -252,65 +230,285 @@ __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uin
 }
 
 // ---------------------------------------------------------------------
-// a1 + a2: decode and project, one thread per row
+// a1 + a2 on MFMA.  One wave decodes 64 rows as four 16-row groups with
+// v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32 accumulation):
+//   layer 1: [bf16(F) | 3-term bf16 split of (d~, Delta)] (K = 64) x W1'
+//            (64 x 32: W1's feature rows, then its last four rows once per
+//            split term), 2 k-steps x 2 column tiles;
+//   layer 2: 3-term bf16 split of z1 (K = 96) x [W2; W2; W2] (96 x 112),
+//            3 k-steps x 7 column tiles.
+// A value x is carried as h + m + l with h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m) (residual below 2^-26 |x|), so only the features
+// take a bfloat16 rounding; the rest keeps float32 accuracy.  The 16 x 112
+// output tile of a group is staged in LDS and its 160 (row, Gaussian)
+// items are projected by the wave.
+//
+// Fragment layout of the 16x16x32 bf16 MFMA (lane l): A holds row l % 16,
+// k = 8 (l / 16) .. +7; B holds column l % 16, the same k; C holds column
+// l % 16, rows 4 (l / 16) .. +3.
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_decode_project(const ViewDev* __restrict__ views,
-                                                        cgx_anchor_scene sc,
-                                                        const int2* __restrict__ rows,
-                                                        const Counters* ctr, int tw, int th,
-                                                        Splat* __restrict__ splats,
-                                                        uint32_t* __restrict__ counts) {
-  __shared__ DecW w;
-  load_weights(w, sc);
-  __syncthreads();
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+constexpr int kK1 = 64;    // layer-1 reduction (padded)
+constexpr int kK2 = 96;    // layer-2 reduction: 3 split terms of 32
+constexpr int kN2 = 112;   // layer-2 columns (110 padded)
+
+__device__ __forceinline__ uint16_t bf16_bits_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ void split3(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  h = bf16_bits_rne(x);
+  const float r1 = x - bf16_to_f32(h);
+  m = bf16_bits_rne(r1);
+  const float r2 = r1 - bf16_to_f32(m);
+  l = bf16_bits_rne(r2);
+}
+
+struct MfmaLds {
+  uint16_t w1t[kHid][kK1];      // B of layer 1, column-major (n, k)
+  uint16_t w2t[kN2][kK2];       // B of layer 2, column-major (n, k)
+  float b1[kHid];
+  float b2[kN2];
+  uint16_t a1[64][kK1];         // A of layer 1 for the wave's 64 rows
+  uint16_t a2[64][kK2];         // A of layer 2
+  float z2[16][kN2 + 1];        // one group's outputs (+1 pad against bank conflicts)
+};
+
+__device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  bf16x8_t r;
+  r[0] = __builtin_bit_cast(__bf16, (uint16_t)(u.x & 0xFFFF));
+  r[1] = __builtin_bit_cast(__bf16, (uint16_t)(u.x >> 16));
+  r[2] = __builtin_bit_cast(__bf16, (uint16_t)(u.y & 0xFFFF));
+  r[3] = __builtin_bit_cast(__bf16, (uint16_t)(u.y >> 16));
+  r[4] = __builtin_bit_cast(__bf16, (uint16_t)(u.z & 0xFFFF));
+  r[5] = __builtin_bit_cast(__bf16, (uint16_t)(u.z >> 16));
+  r[6] = __builtin_bit_cast(__bf16, (uint16_t)(u.w & 0xFFFF));
+  r[7] = __builtin_bit_cast(__bf16, (uint16_t)(u.w >> 16));
+  return r;
+}
+
+__global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __restrict__ views,
+                                                            cgx_anchor_scene sc,
+                                                            const int2* __restrict__ rows,
+                                                            const Counters* ctr, int tw, int th,
+                                                            Splat* __restrict__ splats,
+                                                            uint32_t* __restrict__ counts,
+                                                            float* __restrict__ row_scratch) {
+  __shared__ MfmaLds L;
+  const int lane = threadIdx.x;
   const uint32_t n_rows = ctr->n_rows;
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
-  const int2 row = rows[r];
-  const ViewDev& V = views[row.x];
-  const uint32_t a = (uint32_t)row.y;
-  DecIn d;
-  decoder_input(V, sc, a, d);
-  float z1[kHid];
-  hidden(w, d.z0, z1);
+  const uint32_t r0 = blockIdx.x * 64;
+  if (r0 >= n_rows) return;
+
+  // weights, transposed to (column, k) so that a lane's 8 k-values are contiguous
+  for (int i = lane; i < kHid * kK1; i += 64) {
+    const int n = i / kK1, k = i % kK1;
+    uint16_t v = 0;
+    if (k < 32) v = sc.W1[k * kHid + n];
+    else if (k < 44) v = sc.W1[(32 + (k - 32) % 4) * kHid + n];
+    L.w1t[n][k] = v;
+  }
+  for (int i = lane; i < kN2 * kK2; i += 64) {
+    const int n = i / kK2, k = i % kK2;
+    L.w2t[n][k] = n < kOut ? sc.W2[(k % kHid) * kOut + n] : (uint16_t)0;
+  }
+  for (int i = lane; i < kHid; i += 64) L.b1[i] = sc.b1[i];
+  for (int i = lane; i < kN2; i += 64) L.b2[i] = i < kOut ? sc.b2[i] : 0.0f;
+
+  // layer-1 operands of this lane's row
+  const uint32_t r = r0 + lane;
+  {
+    uint16_t* a = L.a1[lane];
+    if (r < n_rows) {
+      const int2 row = rows[r];
+      const ViewDev& V = views[row.x];
+      DecIn d;
+      decoder_input(V, sc, (uint32_t)row.y, d);
 #pragma unroll
-  for (int j = 0; j < kHid; ++j) z1[j] = fmaxf(z1[j], 0.0f);
-  for (int k = 0; k < kNOff; ++k) {
-    float z2[kGo];
-    gaussian_out(w, z1, k, z2);
-    ProjIn in;
-    float sig_s[3];
-    decoded_gaussian(sc, a, k, z2, in, sig_s);
-    Splat o;
-    const uint32_t slot = r * kNOff + k;
-    const uint32_t cnt = project_splat(V, in, tw, th, o);
-    counts[slot] = cnt;
-    if (cnt) splats[slot] = o;
+      for (int i = 0; i < 32; ++i) a[i] = bf16_bits_rne(d.z0[i]);   // exact: z0[i] is bf16
+#pragma unroll
+      for (int i = 0; i < 4; ++i) split3(d.z0[32 + i], a[32 + i], a[36 + i], a[40 + i]);
+#pragma unroll
+      for (int i = 44; i < kK1; ++i) a[i] = 0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kK1; ++i) a[i] = 0;
+    }
+  }
+  __syncthreads();
+
+  const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  // layer 1 -> z1 (fp32), split into three bf16 terms for layer 2
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const bf16x8_t av = load8(&L.a1[g * 16 + col][ks * 32 + kq]);
+        const bf16x8_t bv = load8(&L.w1t[t * 16 + col][ks * 32 + kq]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      }
+      const int n = t * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float z = fmaxf(acc[i] + L.b1[n], 0.0f);
+        uint16_t h, m, lo;
+        split3(z, h, m, lo);
+        uint16_t* a2 = L.a2[g * 16 + rq + i];
+        a2[n] = h;
+        a2[32 + n] = m;
+        a2[64 + n] = lo;
+        // z1 kept for the adjoint (relu' = z1 > 0)
+        const uint32_t rr = r0 + g * 16 + rq + i;
+        if (rr < n_rows) row_scratch[(size_t)rr * kRowScratch + kIn + n] = z;
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int t = 0; t < kN2 / 16; ++t) {
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 3; ++ks) {
+        const bf16x8_t av = load8(&L.a2[g * 16 + col][ks * 32 + kq]);
+        const bf16x8_t bv = load8(&L.w2t[t * 16 + col][ks * 32 + kq]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      }
+      const int n = t * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) L.z2[rq + i][n] = acc[i] + L.b2[n];
+    }
+    __syncthreads();
+    for (int item = lane; item < 16 * kNOff; item += 64) {
+      const int rl = item / kNOff, k = item % kNOff;
+      const uint32_t rr = r0 + g * 16 + rl;
+      if (rr >= n_rows) continue;
+      const int2 row = rows[rr];
+      const ViewDev& V = views[row.x];
+      float z2[kGo];
+#pragma unroll
+      for (int m = 0; m < kGo; ++m) z2[m] = L.z2[rl][k * kGo + m];
+      ProjIn in;
+      float sig_s[3];
+      decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
+      Splat o;
+      const uint32_t slot = rr * kNOff + k;
+      const uint32_t cnt = project_splat(V, in, tw, th, o);
+      counts[slot] = cnt;
+      if (cnt) splats[slot] = o;
+    }
+    __syncthreads();
   }
 }
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, Counters* ctr, hipStream_t s) {
+                           uint32_t* counts, Counters* ctr, float* row_scratch, hipStream_t s) {
   (void)B;
-  const uint32_t blocks = div_up(max_rows, 256);
+  const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
-  hipLaunchKernelGGL(k_decode_project, dim3(blocks), dim3(256), 0, s, views, sc, rows,
-                     (const Counters*)ctr, tw, th, splats, counts);
+  hipLaunchKernelGGL(k_decode_project_mfma, dim3(blocks), dim3(64), 0, s, views, sc, rows,
+                     (const Counters*)ctr, tw, th, splats, counts, row_scratch);
 }
 
 // ---------------------------------------------------------------------
-// a10: per-row adjoint.  Writes the row's z0, z1, dz1, dz2 to scratch for
-// the weight-gradient reduction and adds the anchor gradients (x, l, O, F)
-// atomically (an anchor has one row per view that selects it).
+// a10, part 1: one thread per (row, Gaussian).  Recomputes the Gaussian's
+// decoder outputs from the row's z1 (kept by the forward pass), runs the
+// projection adjoint, writes dz2 for the row's 11 outputs of this Gaussian
+// and adds the anchor gradients of x, l and O atomically (an anchor has
+// one row per view that selects it).
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_decode_bwd_rows(const ViewDev* __restrict__ views,
-                                                         cgx_anchor_scene sc,
-                                                         const int2* __restrict__ rows,
-                                                         const Counters* ctr,
-                                                         const uint32_t* __restrict__ counts,
-                                                         const SplatGrad* __restrict__ sgrad,
-                                                         float* __restrict__ scratch, cgx_grads gr) {
+struct DecW2 {
+  float W2[kHid * kOut];
+  float b2[kOut];
+};
+
+__global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restrict__ views,
+                                                          cgx_anchor_scene sc,
+                                                          const int2* __restrict__ rows,
+                                                          const Counters* ctr,
+                                                          const uint32_t* __restrict__ counts,
+                                                          const SplatGrad* __restrict__ sgrad,
+                                                          float* __restrict__ scratch, cgx_grads gr) {
+  __shared__ DecW2 w;
+  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x) w.W2[i] = bf16_to_f32(sc.W2[i]);
+  for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
+  __syncthreads();
+  const uint32_t n_rows = ctr->n_rows;
+  const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t r = item / kNOff;
+  const int k = (int)(item - r * kNOff);
+  if (r >= n_rows) return;
+  float* rs = scratch + (size_t)r * kRowScratch;
+  float* dz2 = rs + kIn + 2 * kHid + k * kGo;
+  const uint32_t slot = item;
+  if (counts[slot] == 0) {
+#pragma unroll
+    for (int m = 0; m < kGo; ++m) dz2[m] = 0.0f;
+    return;
+  }
+  const int2 row = rows[r];
+  const ViewDev& V = views[row.x];
+  const uint32_t a = (uint32_t)row.y;
+  float z2[kGo];
+#pragma unroll
+  for (int m = 0; m < kGo; ++m) z2[m] = w.b2[k * kGo + m];
+  for (int j = 0; j < kHid; ++j) {
+    const float zj = rs[kIn + j];
+#pragma unroll
+    for (int m = 0; m < kGo; ++m) z2[m] += zj * w.W2[j * kOut + k * kGo + m];
+  }
+  ProjIn in;
+  float sig_s[3];
+  decoded_gaussian(sc, a, k, z2, in, sig_s);
+  float gg[16];
+  const float4* gp = reinterpret_cast<const float4*>(&sgrad[slot]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 t = gp[q];
+    gg[4 * q] = t.x; gg[4 * q + 1] = t.y; gg[4 * q + 2] = t.z; gg[4 * q + 3] = t.w;
+  }
+  ProjState st;
+  project_state(V, in, st);
+  float dmu[3], ds[3], dq[4];
+  project_backward(V, in, st, gg, dmu, ds, dq);
+  const float* L = sc.l + 3 * (size_t)a;
+  const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
+  dz2[0] = gg[5] * in.op * (1.0f - in.op);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    dz2[1 + c] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);
+    dz2[4 + c] = ds[c] * L[c] * sig_s[c] * (1.0f - sig_s[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) dz2[7 + c] = dq[c];
+  float* gO = gr.O + ((size_t)a * kNOff + k) * 3;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    atomic_add_f32(gO + c, dmu[c] * L[c]);
+    atomic_add_f32(gr.x + 3 * (size_t)a + c, dmu[c]);
+    atomic_add_f32(gr.l + 3 * (size_t)a + c, ds[c] * sig_s[c] + dmu[c] * O[c]);
+  }
+}
+
+// ---------------------------------------------------------------------
+// a10, part 2: one thread per row.  dz1 = (dz2 W2^T) * [z1 > 0],
+// dz0 = dz1 W1^T -> dF and dx (through the view direction and relative
+// distance); z0 and dz1 are kept for the weight-gradient reduction.
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
+                                                        cgx_anchor_scene sc,
+                                                        const int2* __restrict__ rows,
+                                                        const Counters* ctr,
+                                                        float* __restrict__ scratch, cgx_grads gr) {
   __shared__ DecW w;
   load_weights(w, sc);
   __syncthreads();
@@ -320,97 +518,42 @@ __global__ __launch_bounds__(256) void k_decode_bwd_rows(const ViewDev* __restri
   const int2 row = rows[r];
   const ViewDev& V = views[row.x];
   const uint32_t a = (uint32_t)row.y;
-  DecIn d;
-  decoder_input(V, sc, a, d);
-  float pre1[kHid], z1[kHid], dz1[kHid];
-  hidden(w, d.z0, pre1);
+  float* rs = scratch + (size_t)r * kRowScratch;
+  const float* dz2 = rs + kIn + 2 * kHid;
+  float dz1[kHid];
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) dz1[j] = 0.0f;
+  for (int c = 0; c < kOut; ++c) {
+    const float g = dz2[c];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) dz1[j] += g * w.W2[j * kOut + c];
+  }
 #pragma unroll
   for (int j = 0; j < kHid; ++j) {
-    z1[j] = fmaxf(pre1[j], 0.0f);
-    dz1[j] = 0.0f;
+    dz1[j] = rs[kIn + j] > 0.0f ? dz1[j] : 0.0f;
+    rs[kIn + kHid + j] = dz1[j];
   }
-  float* rs = scratch + (size_t)r * kRowScratch;
-  const float* L = sc.l + 3 * (size_t)a;
-  float dx[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
-  for (int k = 0; k < kNOff; ++k) {
-    const uint32_t slot = r * kNOff + k;
-    float dz2[kGo];
+  DecIn d;
+  decoder_input(V, sc, a, d);
 #pragma unroll
-    for (int m = 0; m < kGo; ++m) dz2[m] = 0.0f;
-    if (counts[slot]) {
-      float z2[kGo];
-      gaussian_out(w, z1, k, z2);
-      ProjIn in;
-      float sig_s[3];
-      decoded_gaussian(sc, a, k, z2, in, sig_s);
-      float gg[16];
-      const float4* gp = reinterpret_cast<const float4*>(&sgrad[slot]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 t = gp[q];
-        gg[4 * q] = t.x; gg[4 * q + 1] = t.y; gg[4 * q + 2] = t.z; gg[4 * q + 3] = t.w;
-      }
-      ProjState st;
-      project_state(V, in, st);
-      float dmu[3], ds[3], dq[4];
-      project_backward(V, in, st, gg, dmu, ds, dq);
-      dz2[0] = gg[5] * in.op * (1.0f - in.op);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        dz2[1 + c] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);
-        dz2[4 + c] = ds[c] * L[c] * sig_s[c] * (1.0f - sig_s[c]);
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dz2[7 + c] = dq[c];
-      const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
-      float* gO = gr.O + ((size_t)a * kNOff + k) * 3;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        dl[c] += ds[c] * sig_s[c] + dmu[c] * O[c];
-        dx[c] += dmu[c];
-        atomic_add_f32(gO + c, dmu[c] * L[c]);
-      }
-#pragma unroll
-      for (int j = 0; j < kHid; ++j) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int m = 0; m < kGo; ++m) acc += dz2[m] * w.W2[j * kOut + k * kGo + m];
-        dz1[j] += acc;
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kGo; ++m) rs[kIn + 2 * kHid + k * kGo + m] = dz2[m];
-  }
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) dz1[j] = pre1[j] > 0.0f ? dz1[j] : 0.0f;
-  float dz0[kIn];
-#pragma unroll
+  for (int i = 0; i < kIn; ++i) rs[i] = d.z0[i];
+  float* gF = gr.F + (size_t)a * CGX_FEAT_DIM;
+  float dz0[4];
   for (int i = 0; i < kIn; ++i) {
     float acc = 0.0f;
 #pragma unroll
     for (int j = 0; j < kHid; ++j) acc += dz1[j] * w.W1[i * kHid + j];
-    dz0[i] = acc;
+    if (i < CGX_FEAT_DIM) atomic_add_f32(gF + i, acc);
+    else dz0[i - CGX_FEAT_DIM] = acc;
   }
-#pragma unroll
-  for (int i = 0; i < kIn; ++i) rs[i] = d.z0[i];
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-    rs[kIn + j] = z1[j];
-    rs[kIn + kHid + j] = dz1[j];
-  }
-  float* gF = gr.F + (size_t)a * CGX_FEAT_DIM;
-#pragma unroll
-  for (int i = 0; i < CGX_FEAT_DIM; ++i) atomic_add_f32(gF + i, dz0[i]);
-  // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max
+  // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
   const float* dir = d.z0 + 32;
-  const float dd = dz0[32] * dir[0] + dz0[33] * dir[1] + dz0[34] * dir[2];
+  const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
   const float il = 1.0f / d.dist;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float ddelta = (dz0[32 + c] - dir[c] * dd) * il + dz0[35] / sc.d_max * dir[c];
-    dx[c] -= ddelta;
-    atomic_add_f32(gr.x + 3 * (size_t)a + c, dx[c]);
-    atomic_add_f32(gr.l + 3 * (size_t)a + c, dl[c]);
+    const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
+    atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
   }
 }
 
@@ -497,11 +640,15 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
   launch_zero_f32(g.l, 3 * A, s);
   launch_zero_f32(g.O, 3 * A * kNOff, s);
   launch_zero_f32(g.F, A * CGX_FEAT_DIM, s);
-  const uint32_t blocks = div_up(max_rows, 256);
   float* partial = scratch + (size_t)max_rows * kRowScratch;
-  if (blocks)
-    hipLaunchKernelGGL(k_decode_bwd_rows, dim3(blocks), dim3(256), 0, s, views, sc, rows, ctr,
+  const uint32_t gblocks = div_up((uint64_t)max_rows * kNOff, 256);
+  if (gblocks)
+    hipLaunchKernelGGL(k_decode_bwd_gauss, dim3(gblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        counts, sgrad, scratch, g);
+  const uint32_t rblocks = div_up(max_rows, 256);
+  if (rblocks)
+    hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
+                       scratch, g);
   hipLaunchKernelGGL(k_wgrad_partial, dim3(kRedBlocks), dim3(256), 0, s, (const float*)scratch,
                      ctr, partial);
   hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 256)), dim3(256), 0, s,

@@ -341,6 +341,7 @@ void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s) {
   else if (tw == 8 && th == 8) launch_fwd_t<8, 8>(a, s);
   else if (tw == 16 && th == 8) launch_fwd_t<16, 8>(a, s);
   else if (tw == 32 && th == 8) launch_fwd_t<32, 8>(a, s);
+  else if (tw == 32 && th == 16) launch_fwd_t<32, 16>(a, s);
 }
 
 void launch_raster_backward(const RasterArgs& a, int tw, int th, hipStream_t s) {
@@ -349,6 +350,7 @@ void launch_raster_backward(const RasterArgs& a, int tw, int th, hipStream_t s) 
   else if (tw == 8 && th == 8) launch_bwd_t<8, 8>(a, s);
   else if (tw == 16 && th == 8) launch_bwd_t<16, 8>(a, s);
   else if (tw == 32 && th == 8) launch_bwd_t<32, 8>(a, s);
+  else if (tw == 32 && th == 16) launch_bwd_t<32, 16>(a, s);
 }
 
 }  // namespace cgx
