@@ -27,7 +27,7 @@ def render_explicit(scene, views, tile=(16, 16), keep_tiles=None):
                         sh=scene.sh, sh_degree=scene.sh_degree)
         splats.append(S)
         varr.append(prj.view_arrays(view))
-    srt = ras.bin_and_sort(splats, layout)
+    srt = ras.bin_and_sort(splats, layout, keep_tiles)
     imgs = ras.render_images(splats, views, layout, srt, varr, keep_tiles)
     r = Result()
     r.kind, r.layout, r.splats, r.sorted, r.images, r.varr, r.views = (
@@ -52,7 +52,7 @@ def render_anchor(scene, views, tile=(16, 16), emulate_bf16=True, keep_tiles=Non
         S["frag_grad"] = S["frag_grad"] | (S["valid"] & rfr)
         splats.append(S)
         varr.append(prj.view_arrays(view))
-    srt = ras.bin_and_sort(splats, layout)
+    srt = ras.bin_and_sort(splats, layout, keep_tiles)
     imgs = ras.render_images(splats, views, layout, srt, varr, keep_tiles)
     r = Result()
     r.kind, r.layout, r.splats, r.sorted, r.images, r.varr, r.views = (

@@ -50,15 +50,39 @@ def batch_layout(views, tile):
 # --------------------------------------------------------------------------
 # a3-a5: binning and sort
 # --------------------------------------------------------------------------
-def bin_and_sort(splats_per_view, layout):
+def _bin_sample(splats_per_view, layout, keep_tiles):
+    """Entries of the global tiles in keep_tiles only (a bounded sample of a
+    large workload): for each such tile, every valid splat whose tile
+    rectangle contains it."""
+    gt_all, zb_all, v_all, g_all = [], [], [], []
+    for gtile in sorted(int(t) for t in keep_tiles):
+        v = int(np.searchsorted(layout["tile_off"], gtile, side="right") - 1)
+        local = gtile - int(layout["tile_off"][v])
+        tx, ty = local % layout["TX"][v], local // layout["TX"][v]
+        S = splats_per_view[v]
+        t = S["tiles"]
+        m = S["valid"] & (t[:, 0] <= tx) & (t[:, 1] >= tx) & (t[:, 2] <= ty) & (t[:, 3] >= ty)
+        idx = np.nonzero(m)[0]
+        gt_all.append(np.full(idx.size, gtile, np.int64))
+        zb_all.append(S["zbits"][idx])
+        v_all.append(np.full(idx.size, v, np.int64))
+        g_all.append(idx.astype(np.int64))
+    return gt_all, zb_all, v_all, g_all
+
+
+def bin_and_sort(splats_per_view, layout, keep_tiles=None):
     """Emit one (global tile, depth bits, view, gid) entry per (splat, tile
     touched) and sort lexicographically.
 
     splats_per_view[v] is the dict from project.project for view v; the gid
     of a splat is its row index in that dict.  Returns dict with sorted
     arrays gtile (int64), zbits (uint32), view, gid, and ranges
-    (n_tiles, 2) = [start, end) per global tile.
+    (n_tiles, 2) = [start, end) per global tile.  With keep_tiles, only the
+    entries of those tiles are produced (other tiles have empty ranges).
     """
+    if keep_tiles is not None:
+        gt_all, zb_all, v_all, g_all = _bin_sample(splats_per_view, layout, keep_tiles)
+        return _sort_entries(gt_all, zb_all, v_all, g_all, layout)
     gt_all, zb_all, v_all, g_all = [], [], [], []
     for v, S in enumerate(splats_per_view):
         idx = np.nonzero(S["valid"])[0]
@@ -77,8 +101,12 @@ def bin_and_sort(splats_per_view, layout):
         zb_all.append(S["zbits"][idx][rep])
         v_all.append(np.full(rep.size, v, np.int64))
         g_all.append(idx[rep].astype(np.int64))
+    return _sort_entries(gt_all, zb_all, v_all, g_all, layout)
+
+
+def _sort_entries(gt_all, zb_all, v_all, g_all, layout):
     n_tiles = int(layout["tile_off"][-1])
-    if not gt_all:
+    if not gt_all or sum(a.size for a in gt_all) == 0:
         e = np.zeros(0, np.int64)
         return dict(gtile=e, zbits=e.astype(np.uint32), view=e, gid=e,
                     ranges=np.zeros((n_tiles, 2), np.int64))

@@ -178,6 +178,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.splats = take(sizeof(Splat) * (size_t)L.max_splats);
   L.counts = take(sizeof(uint32_t) * (size_t)L.max_splats);
   L.offsets = take(sizeof(uint32_t) * (size_t)L.max_splats);
+  L.zkey = take(sizeof(uint32_t) * (size_t)L.max_splats);
   for (int b = 0; b < 2; ++b) {
     L.vkey[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
     L.vslot[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
@@ -241,6 +242,7 @@ struct Ptrs {
   Splat* splats;
   uint32_t* counts;
   uint32_t* offsets;
+  uint32_t* zkey;
   uint32_t* vkey[2];
   uint32_t* vslot[2];
   uint32_t* pkey[2];
@@ -263,6 +265,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
   p.splats = at<Splat>(ws, L.splats);
   p.counts = at<uint32_t>(ws, L.counts);
   p.offsets = at<uint32_t>(ws, L.offsets);
+  p.zkey = at<uint32_t>(ws, L.zkey);
   for (int b = 0; b < 2; ++b) {
     p.vkey[b] = at<uint32_t>(ws, L.vkey[b]);
     p.vslot[b] = at<uint32_t>(ws, L.vslot[b]);
@@ -300,7 +303,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.keys_hi = L.pkey[L.final_buf];
   h.keys_lo = L.pkey[1 - L.final_buf];   // scratch after the sort: depth bits for debug copies
   h.vals = L.pval[L.final_buf];
-  h.splats = L.splats;
+  h.zkey = L.zkey;
   h.ranges = L.ranges;
   h.rows = L.rows;
   h.counts = L.counts;
@@ -316,7 +319,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
     phase_begin(c, CGX_PHASE_PROJECT, st);
-    launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, st);
+    launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, P.zkey, st);
     phase_end(c, st);
   } else {
     phase_begin(c, CGX_PHASE_SELECT, st);
@@ -325,13 +328,13 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
     phase_end(c, st);
     phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
-                          P.splats, P.counts, P.ctr, P.dz, st);
+                          P.splats, P.counts, P.zkey, P.ctr, P.dz, st);
     phase_end(c, st);
   }
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
   // low 32 bits of the (tile | depth) keys: visible splats sorted by depth
   phase_begin(c, CGX_PHASE_SCAN, st);
-  launch_compact_visible(P.counts, P.splats, n_dev, n_slots, P.part, P.ctr, P.vkey[0], P.vslot[0],
+  launch_compact_visible(P.counts, P.zkey, n_dev, n_slots, P.part, P.ctr, P.vkey[0], P.vslot[0],
                          st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
@@ -743,7 +746,7 @@ int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream, uint32
     // gather each sorted pair's depth bits from its splat into free scratch
     char* wbase = const_cast<char*>(base);
     launch_gather_depth(reinterpret_cast<const uint32_t*>(base + h.hdr.vals),
-                        reinterpret_cast<const Splat*>(base + h.hdr.splats),
+                        reinterpret_cast<const uint32_t*>(base + h.hdr.zkey),
                         reinterpret_cast<const Counters*>(base), (uint32_t)h.hdr.max_splats,
                         (uint32_t)h.hdr.max_pairs, reinterpret_cast<uint32_t*>(wbase + h.hdr.keys_lo),
                         (hipStream_t)stream);

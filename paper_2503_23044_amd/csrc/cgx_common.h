@@ -33,6 +33,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxRadixBits = 9;    // digit width bound of the LSD passes
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kLnAlphaMin = -5.541263545158426f;   // log(1/255)
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kDilation = 0.3f;
@@ -57,7 +58,7 @@ struct ViewDev {
 // workspace pointer.
 struct WsHeader {
   uint64_t total;
-  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts, splats;
+  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts, zkey;
   int64_t n_tiles, n_pixels, max_rows, max_splats, max_pairs;
   int32_t n_views, kind;
   int32_t sort_passes, pad;
@@ -83,17 +84,19 @@ struct Counters {
 };
 
 // 64-byte splat record.  power = pa dx^2 + pb dx dy + pc dy^2 with
-// (pa, pb, pc) = (-a/2, -b, -c/2) of the conic (exact scalings).
+// (pa, pb, pc) = (-a/2, -b, -c/2) of the conic (exact scalings); the raw
+// opacity is exp(power + lno) with lno = log(o), so alpha < 1/255 is decided
+// before the exponential.  The depth key lives in its own array.
 struct alignas(16) Splat {
   float u, w;
   float pa, pb, pc;
-  float op;
+  float lno;
   float cr, cg, cb;
   float d;
   float nx, ny, nz;
   uint32_t bx;                 // x_lo | x_hi << 16 (pixel box, inclusive)
   uint32_t by;                 // y_lo | y_hi << 16
-  uint32_t zbits;
+  float inv_o;                 // 1 / o
 };
 static_assert(sizeof(Splat) == 64, "splat record is one 64-byte line");
 
@@ -111,7 +114,7 @@ struct ViewPack {
 };
 
 struct Layout {
-  size_t views, counters, scan_part, rows, row_off, splats, counts, offsets;
+  size_t views, counters, scan_part, rows, row_off, splats, counts, offsets, zkey;
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
@@ -163,19 +166,18 @@ __device__ __forceinline__ double box_hi64(double u, double r) {
 // and take the same decisions.  Returns alpha (0 when skipped) and the
 // unclamped product o * exp(power) in raw.
 // ---------------------------------------------------------------------
-__device__ __forceinline__ float splat_alpha(float pa, float pb, float pc, float op, float dx,
-                                             float dy, float& raw, float& g) {
+__device__ __forceinline__ float splat_alpha(float pa, float pb, float pc, float lno, float dx,
+                                             float dy, float& raw) {
 #pragma clang fp contract(off)
-  float power = __builtin_fmaf(pa * dx, dx, __builtin_fmaf(pc * dy, dy, (pb * dx) * dy));
-  if (power > 0.0f) {
+  const float power = __builtin_fmaf(pa * dx, dx, __builtin_fmaf(pc * dy, dy, (pb * dx) * dy));
+  const float q = power + lno;
+  // alpha = o exp(power) >= 1/255  <=>  power + log(o) >= log(1/255)
+  if (power > 0.0f || !(q >= kLnAlphaMin)) {
     raw = 0.0f;
-    g = 0.0f;
     return 0.0f;
   }
-  g = __expf(power);
-  raw = op * g;
-  float a = raw < kAlphaMax ? raw : kAlphaMax;
-  return a >= kAlphaMin ? a : 0.0f;
+  raw = __expf(q);
+  return raw < kAlphaMax ? raw : kAlphaMax;
 }
 
 // Sum of a float over the 64 lanes of a wave, result valid in lane 63.
@@ -220,14 +222,14 @@ void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
                         uint32_t cap, Counters* ctr, hipStream_t s);
-void launch_compact_visible(const uint32_t* counts, const Splat* splats, const uint32_t* n_dev,
+void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s);
 void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
                        const uint32_t* voff, const Counters* ctr, int n_per_row, const int2* rows,
                        uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
                        uint32_t* pval, hipStream_t s);
-void launch_gather_depth(const uint32_t* pval, const Splat* splats, const Counters* ctr,
+void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
 size_t sort_hist_words();
 int sort_passes(int bits);
@@ -237,13 +239,15 @@ int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, 
                    uint32_t* hist, int bits, hipStream_t s);
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
-                             int tw, int th, Splat* splats, uint32_t* counts, hipStream_t s);
+                             int tw, int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
+                             hipStream_t s);
 void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            unsigned long long* part, int2* rows, uint32_t* row_off,
                            uint32_t max_rows, Counters* ctr, hipStream_t s);
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, Counters* ctr, float* row_scratch, hipStream_t s);
+                           uint32_t* counts, uint32_t* zkey, Counters* ctr, float* row_scratch,
+                           hipStream_t s);
 
 
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,

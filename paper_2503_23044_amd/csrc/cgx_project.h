@@ -117,7 +117,7 @@ __device__ __forceinline__ void proj_normal(const ViewDev& V, const ProjIn& in, 
 // a2: full projection into a splat record; returns the number of tiles
 // touched (0 = culled).
 __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn& in, int tw,
-                                                  int th, Splat& o) {
+                                                  int th, Splat& o, uint32_t& zbits) {
   double p0, p1, p2;
   camera_point64(V, in.m0, in.m1, in.m2, p0, p1, p2);
   if (!(p2 > (double)V.z_near)) return 0;
@@ -148,7 +148,8 @@ __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn
   o.pa = -0.5f * (st.C * idet);
   o.pb = st.B * idet;            // -b with b = -B/det
   o.pc = -0.5f * (st.A * idet);
-  o.op = in.op;
+  o.lno = __logf(in.op);
+  o.inv_o = 1.0f / in.op;
   o.cr = in.col[0];
   o.cg = in.col[1];
   o.cb = in.col[2];
@@ -158,7 +159,7 @@ __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn
   o.nz = st.n[2];
   o.bx = (uint32_t)x_lo | ((uint32_t)x_hi << 16);
   o.by = (uint32_t)y_lo | ((uint32_t)y_hi << 16);
-  o.zbits = __float_as_uint((float)p2);
+  zbits = __float_as_uint((float)p2);
   const int tx0 = x_lo / tw, tx1 = x_hi / tw, ty0 = y_lo / th, ty1 = y_hi / th;
   return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }

@@ -297,6 +297,7 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
                                                             const Counters* ctr, int tw, int th,
                                                             Splat* __restrict__ splats,
                                                             uint32_t* __restrict__ counts,
+                                                            uint32_t* __restrict__ zkey,
                                                             float* __restrict__ row_scratch) {
   __shared__ MfmaLds L;
   const int lane = threadIdx.x;
@@ -400,10 +401,14 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
       float sig_s[3];
       decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
       Splat o;
+      uint32_t zb = 0;
       const uint32_t slot = rr * kNOff + k;
-      const uint32_t cnt = project_splat(V, in, tw, th, o);
+      const uint32_t cnt = project_splat(V, in, tw, th, o, zb);
       counts[slot] = cnt;
-      if (cnt) splats[slot] = o;
+      if (cnt) {
+        splats[slot] = o;
+        zkey[slot] = zb;
+      }
     }
     __syncthreads();
   }
@@ -411,12 +416,13 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, Counters* ctr, float* row_scratch, hipStream_t s) {
+                           uint32_t* counts, uint32_t* zkey, Counters* ctr, float* row_scratch,
+                           hipStream_t s) {
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_decode_project_mfma, dim3(blocks), dim3(64), 0, s, views, sc, rows,
-                     (const Counters*)ctr, tw, th, splats, counts, row_scratch);
+                     (const Counters*)ctr, tw, th, splats, counts, zkey, row_scratch);
 }
 
 // ---------------------------------------------------------------------

@@ -87,8 +87,8 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
         const int y = y0 + k * RS;
         if (done[k] || y < ylo || y > yhi) continue;
         const float dy = s.w - ((float)y + 0.5f);
-        float raw, g;
-        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, g);
+        float raw;
+        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
         ++evals;
         if (alpha == 0.0f) continue;
         const float Tn = T[k] * (1.0f - alpha);
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         const int y = y0 + k * RS;
         if (!inx || idx >= last[k] || y < ylo || y > yhi) continue;
         const float dy = s.w - ((float)y + 0.5f);
-        float raw, G;
-        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.op, dx, dy, raw, G);
+        float raw;
+        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
         ++evals;
         if (alpha == 0.0f) continue;
         const float om = 1.0f - alpha;
@@ -302,8 +302,8 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         g[11] += w * GN1[k];
         g[12] += w * GN2[k];
         if (raw < kAlphaMax) {
-          g[5] += da * G;
-          const float dpw = da * s.op * G;
+          g[5] += da * (raw * s.inv_o);       // d alpha / d o = exp(power)
+          const float dpw = da * raw;         // d alpha / d power = o exp(power)
           g[0] += dpw * (2.0f * s.pa * dx + s.pb * dy);
           g[1] += dpw * (2.0f * s.pc * dy + s.pb * dx);
           g[2] += dpw * dx * dx;
@@ -312,8 +312,18 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         }
         any = true;
       }
-      if (__ballot(any) == 0) continue;
+      const uint64_t who = __ballot(any);
+      if (who == 0) continue;
       float* dst = a.sgrad[sslot[j]].g;
+      if ((who & (who - 1)) == 0) {
+        // a single contributing lane adds its own values: no reduction needed
+        if (any) {
+#pragma unroll
+          for (int i = 0; i < 13; ++i)
+            if (g[i] != 0.0f) atomic_add_f32(dst + i, g[i]);
+        }
+        continue;
+      }
 #pragma unroll
       for (int i = 0; i < 13; ++i) {
         const float r = wave_sum_lane63(g[i]);

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_vis_top(unsigned long long* part, Coun
 }
 
 __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ counts,
-                                                   const Splat* __restrict__ splats,
+                                                   const uint32_t* __restrict__ zkey,
                                                    const uint32_t* n_dev, uint32_t n_host,
                                                    const unsigned long long* part,
                                                    uint32_t* __restrict__ vkey,
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
     }
     if (f) {
       const uint64_t pos = carry + wc + below;
-      vkey[pos] = splats[i].zbits;
+      vkey[pos] = zkey[i];
       vslot[pos] = (uint32_t)i;
     }
     carry += tot;
@@ -349,12 +349,12 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
   }
 }
 
-void launch_compact_visible(const uint32_t* counts, const Splat* splats, const uint32_t* n_dev,
+void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s) {
   hipLaunchKernelGGL(k_vis_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, n_dev, n_host, part);
   hipLaunchKernelGGL(k_vis_top, dim3(1), dim3(kScanBlocks), 0, s, part, ctr);
-  hipLaunchKernelGGL(k_vis_write, dim3(kScanBlocks), dim3(256), 0, s, counts, splats, n_dev,
+  hipLaunchKernelGGL(k_vis_write, dim3(kScanBlocks), dim3(256), 0, s, counts, zkey, n_dev,
                      n_host, (const unsigned long long*)part, vkey, vslot);
 }
 
@@ -429,19 +429,19 @@ void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t
 }
 
 // depth bits of every sorted pair (for the debug copy only)
-__global__ void k_gather_depth(const uint32_t* __restrict__ pval, const Splat* __restrict__ splats,
+__global__ void k_gather_depth(const uint32_t* __restrict__ pval, const uint32_t* __restrict__ zkey,
                                const Counters* ctr, uint32_t n_slots, uint32_t* __restrict__ out) {
   const uint32_t P = ctr->n_pairs;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
     const uint32_t s = pval[i];
-    out[i] = s < n_slots ? splats[s].zbits : 0u;
+    out[i] = s < n_slots ? zkey[s] : 0u;
   }
 }
 
-void launch_gather_depth(const uint32_t* pval, const Splat* splats, const Counters* ctr,
+void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s) {
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 8192));
-  hipLaunchKernelGGL(k_gather_depth, dim3(blocks), dim3(256), 0, s, pval, splats, ctr, n_slots, out);
+  hipLaunchKernelGGL(k_gather_depth, dim3(blocks), dim3(256), 0, s, pval, zkey, ctr, n_slots, out);
 }
 
 }  // namespace cgx

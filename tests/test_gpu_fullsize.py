@@ -1,0 +1,168 @@
+"""GPU parity at the full benchmark shapes, on a seeded sample of tiles.
+
+The whole workload is rendered on the GPU in the benchmark's launch
+configuration; the oracle selects, decodes and projects everything but bins,
+sorts and composites only the sampled tiles.  The backward pass is driven
+by a linear loss that is non-zero only on the sampled tiles' pixels, so
+every gradient the GPU returns comes from pixels the oracle also computes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pipeline
+from synth import scenes
+from tests.parity import check_close, check_grad, oracle_images_packed, oracle_mask_packed
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_tiles(layout, n, seed):
+    rng = np.random.default_rng(seed)
+    total = int(layout["tile_off"][-1])
+    return np.sort(rng.choice(total, min(n, total), replace=False))
+
+
+def _masked_linear_grads(r, rng):
+    """Linear-loss output gradients, zero outside the composited tiles."""
+    out = []
+    for img in r.images:
+        npx = img["depth"].size
+        m = img["covered"]
+        g = dict(rgb=rng.standard_normal((3, npx)) * m, depth=rng.standard_normal(npx) * m,
+                 D=rng.standard_normal(npx) * m, normal=rng.standard_normal((3, npx)) * m,
+                 alpha=rng.standard_normal(npx) * m)
+        out.append(g)
+    return out
+
+
+def _to_device(og):
+    d = {}
+    for key, okey in (("rgb", "rgb"), ("depth", "depth"), ("plane_d", "D"), ("normal", "normal"),
+                      ("alpha", "alpha")):
+        d[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
+                                 device="cuda")
+    return d
+
+
+def _compare_sampled(out, r, keep):
+    """Images on the sampled tiles' pixels only."""
+    for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
+                         ("normal", "normal", 3), ("alpha", "alpha", 1)):
+        got = out[key].cpu().numpy()
+        ref = oracle_images_packed(r, okey, c)
+        cov = oracle_mask_packed(r, "covered", c)
+        frag = oracle_mask_packed(r, "frag", c)
+        mag = oracle_images_packed(r, "normal_abs", 3)[cov] if key == "normal" else None
+        check_close(key, got[cov], ref[cov], frag[cov], mag=mag)
+
+
+def _compare_sorted_sample(dbg, r, keep, slot_to_view_gid):
+    n_checked = 0
+    for t in keep:
+        g0, g1 = dbg["ranges"][t]
+        o0, o1 = r.sorted["ranges"][t]
+        slots = dbg["slot"][g0:g1].astype(np.int64)
+        v, gid = slot_to_view_gid(slots)
+        frag_g = np.array([r.splats[a]["frag_value"][b] for a, b in zip(v, gid)], bool)
+        ov, og = r.sorted["view"][o0:o1], r.sorted["gid"][o0:o1]
+        frag_o = np.array([r.splats[a]["frag_value"][b] for a, b in zip(ov, og)], bool)
+        got = np.stack([dbg["zbits"][g0:g1].astype(np.int64), v, gid], 1)[~frag_g]
+        ref = np.stack([r.sorted["zbits"][o0:o1].astype(np.int64), ov, og], 1)[~frag_o]
+        np.testing.assert_array_equal(got, ref, err_msg=f"tile {t}")
+        assert np.all(dbg["tile"][g0:g1] == t)
+        n_checked += len(ref)
+    return n_checked
+
+
+def test_c2_full_size_sampled_tiles():
+    print("case: C2 full size, 24 sampled tiles", flush=True)
+    from paper_2503_23044_amd import render
+    wl = scenes.make_c2()
+    rd = render.Renderer(0, (16, 16))
+    sc = render.scene_from(wl.scene)
+    out = rd.forward(wl.views, sc)
+    torch.cuda.synchronize()
+    dbg = rd.debug()
+    layout = pipeline.ras.batch_layout(wl.views, (16, 16))
+    keep = _sample_tiles(layout, 24, seed=2024)
+    r = pipeline.render_anchor(wl.scene, wl.views, keep_tiles=keep)
+    np.testing.assert_array_equal(dbg["rows"].astype(np.int64), r.rows)
+    rows = r.rows
+
+    def s2vg(slots):
+        row, k = slots // 10, slots % 10
+        v = rows[row, 0]
+        return v, (row - r.row_off[v]) * 10 + k
+
+    n = _compare_sorted_sample(dbg, r, keep, s2vg)
+    assert n > 1000
+    _compare_sampled(out, r, keep)
+    rng = np.random.default_rng(7)
+    og = _masked_linear_grads(r, rng)
+    ref, _ = pipeline.backward(r, og, wl.scene)
+    gr = rd.backward(wl.views, sc, out, _to_device(og))
+    torch.cuda.synchronize()
+    d2 = _sampled_sensitivity_anchor(wl, keep, og)
+    fa = ref["frag"]
+    for k, c in (("x", 3), ("l", 3), ("O", 30), ("F", 32)):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c), d2[k])
+    for k in ("W1", "b1", "W2", "b2"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, d2[k])
+
+
+def _sampled_sensitivity_anchor(wl, keep, og):
+    import copy
+
+    from tests.parity import SENS_EPS, _perturbed, _without_fragile
+    rng = np.random.default_rng(4321)
+    r0 = pipeline.render_anchor(wl.scene, wl.views, keep_tiles=keep)
+    g0, _ = pipeline.backward(r0, og, wl.scene)
+    sc = copy.copy(wl.scene)
+    for k in ("x", "l", "O", "b1", "b2"):
+        setattr(sc, k, _perturbed(getattr(wl.scene, k), rng))
+    sc.W1_exact = _perturbed(wl.scene.W1, rng)
+    sc.W2_exact = _perturbed(wl.scene.W2, rng)
+    r1 = pipeline.render_anchor(sc, wl.views, keep_tiles=keep)
+    g1, _ = pipeline.backward(r1, og, sc)
+    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), wl.scene)
+    assert SENS_EPS > 0
+    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
+            for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
+
+
+def test_c1_full_size_sampled_tiles():
+    print("case: C1 full size (1M Gaussians, SH3, 1080p), 20 sampled tiles", flush=True)
+    from paper_2503_23044_amd import render
+    wl = scenes.make_c1()
+    rd = render.Renderer(0, (16, 16))
+    sc = render.scene_from(wl.scene)
+    out = rd.forward(wl.views, sc)
+    torch.cuda.synchronize()
+    dbg = rd.debug()
+    layout = pipeline.ras.batch_layout(wl.views, (16, 16))
+    keep = _sample_tiles(layout, 20, seed=2025)
+    r = pipeline.render_explicit(wl.scene, wl.views, keep_tiles=keep)
+    N = wl.scene.n
+    n = _compare_sorted_sample(dbg, r, keep, lambda s: (s // N, s % N))
+    assert n > 1000
+    _compare_sampled(out, r, keep)
+    rng = np.random.default_rng(8)
+    og = _masked_linear_grads(r, rng)
+    ref, _ = pipeline.backward(r, og, wl.scene)
+    gr = rd.backward(wl.views, sc, out, _to_device(og))
+    torch.cuda.synchronize()
+    import copy
+
+    from tests.parity import _perturbed, _without_fragile
+    rng2 = np.random.default_rng(4321)
+    sc2 = copy.copy(wl.scene)
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        setattr(sc2, k, _perturbed(getattr(wl.scene, k), rng2))
+    r1 = pipeline.render_explicit(sc2, wl.views, keep_tiles=keep)
+    g1, _ = pipeline.backward(r1, og, sc2)
+    g2, _ = pipeline.backward(r, _without_fragile(r, og), wl.scene)
+    fa = ref["frag"]
+    for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
+                   dict(sens=np.abs(ref[k] - g1[k]), frag=np.abs(ref[k] - g2[k])))
