@@ -163,6 +163,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.n_passes = sort_passes(32) + sort_passes(bits);
   L.vis_buf = sort_passes(32) & 1;
   L.final_buf = sort_passes(bits) & 1;
+  L.order_buf = sort_passes(16) & 1;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -189,6 +190,10 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   }
   L.hist = take(sizeof(uint32_t) * sort_hist_words());
   L.ranges = take(sizeof(uint2) * (size_t)tiles);
+  for (int b = 0; b < 2; ++b) {
+    L.tkey[b] = take(sizeof(uint32_t) * (size_t)tiles);
+    L.tord[b] = take(sizeof(uint32_t) * (size_t)tiles);
+  }
   L.px_T = take(sizeof(float) * (size_t)px);
   L.px_last = take(sizeof(uint32_t) * (size_t)px);
   L.sgrad = take(sizeof(SplatGrad) * (size_t)L.max_splats);
@@ -249,6 +254,8 @@ struct Ptrs {
   uint32_t* pval[2];
   uint32_t* hist;
   uint2* ranges;
+  uint32_t* tkey[2];
+  uint32_t* tord[2];
   float* px_T;
   uint32_t* px_last;
   SplatGrad* sgrad;
@@ -274,6 +281,10 @@ static Ptrs pointers(void* ws, const Layout& L) {
   }
   p.hist = at<uint32_t>(ws, L.hist);
   p.ranges = at<uint2>(ws, L.ranges);
+  for (int b = 0; b < 2; ++b) {
+    p.tkey[b] = at<uint32_t>(ws, L.tkey[b]);
+    p.tord[b] = at<uint32_t>(ws, L.tord[b]);
+  }
   p.px_T = at<float>(ws, L.px_T);
   p.px_last = at<uint32_t>(ws, L.px_last);
   p.sgrad = at<SplatGrad>(ws, L.sgrad);
@@ -358,6 +369,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   phase_begin(c, CGX_PHASE_RANGES, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(P.ranges), 0u, 2 * (size_t)L.n_tiles, st);
   launch_ranges(P.pkey[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
+  launch_tile_order(P.ranges, P.ctr, (uint32_t)L.n_tiles, P.tkey, P.tord, P.hist, st);
   phase_end(c, st);
 
   RasterArgs a;
@@ -367,6 +379,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.splats = P.splats;
   a.vals = P.pval[L.final_buf];
   a.ranges = P.ranges;
+  a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;
@@ -423,6 +436,7 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   a.splats = P.splats;
   a.vals = P.pval[L.final_buf];
   a.ranges = P.ranges;
+  a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;

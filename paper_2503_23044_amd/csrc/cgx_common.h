@@ -71,7 +71,7 @@ struct Counters {
   uint32_t n_pairs;
   uint32_t overflow;           // bit 0 rows, bit 1 splats, bit 2 pairs
   uint32_t n_visible;          // splats that touch at least one tile
-  uint32_t pad0;
+  uint32_t n_tiles;            // tiles of the batch (device copy for the tile-order sort)
   unsigned long long need_rows;
   unsigned long long need_splats;
   unsigned long long need_pairs;
@@ -118,6 +118,7 @@ struct Layout {
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
+  size_t tkey[2], tord[2];     // raster launch order: length keys and tile ids
   size_t total;
   int64_t max_rows, max_splats, max_pairs;
   int64_t n_tiles, n_pixels;
@@ -125,6 +126,7 @@ struct Layout {
   int n_passes;                // radix passes: depth (splats) + tile id (pairs)
   int vis_buf;                 // buffer holding the depth-sorted visible splats
   int final_buf;               // buffer holding the sorted pairs
+  int order_buf;               // buffer holding the raster launch order
 };
 
 template <typename T>
@@ -250,6 +252,11 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                            hipStream_t s);
 
 
+// Tile order for the raster launches: tiles by descending list length
+// (longest first), ties in tile order.  keys/order are double buffers of
+// n_tiles words; returns the buffer index holding the order.
+int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
+                      uint32_t* order[2], uint32_t* hist, hipStream_t s);
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
                    uint32_t cap, hipStream_t s);
 
@@ -259,6 +266,7 @@ struct RasterArgs {
   const Splat* splats;
   const uint32_t* vals;
   const uint2* ranges;
+  const uint32_t* order;       // launch position -> tile id
   uint32_t n_tiles;
   uint32_t n_slots;            // capacity of the splat table (slot bound)
   float* rgb;

@@ -37,7 +37,8 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
   constexpr int RS = kWave / TW;
   __shared__ Splat sh[kWave];
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = a.order[blockIdx.x];
+  if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
   const int v = find_view(a.views, a.B, tile);
   const ViewDev& V = a.views[v];
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   constexpr int RS = kWave / TW;
   __shared__ Splat sh[kWave];
   __shared__ uint32_t sslot[kWave];
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = a.order[blockIdx.x];
+  if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
   const int v = find_view(a.views, a.B, tile);
   const ViewDev& V = a.views[v];

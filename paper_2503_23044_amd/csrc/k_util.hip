@@ -35,6 +35,7 @@ __global__ void k_init_counters(Counters* c, uint32_t n_splats, WsHeader h) {
     Counters z = {};
     z.hdr = h;
     z.n_splats = n_splats;
+    z.n_tiles = (uint32_t)h.n_tiles;
     *c = z;
   }
 }
