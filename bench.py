@@ -40,7 +40,8 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--config", type=int, default=2)
-    p.add_argument("--tile", type=str, default="16x16")
+    p.add_argument("--tile", type=str, default="auto",
+                   help="tile shape WxH, or 'auto' to time every shape and keep the fastest")
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=400)
@@ -58,14 +59,21 @@ def gpu_leg(args, wl):
     from paper_2503_23044_amd import binding as B
     from paper_2503_23044_amd import render
 
-    tw, th = (int(x) for x in args.tile.split("x"))
     dev = "cuda:0"
     sc = render.scene_from(wl.scene, dev)
     cat = lambda xs: torch.as_tensor(np.concatenate([x.ravel() for x in xs]), device=dev)  # noqa: E731
     tgt = dict(rgb=cat(wl.targets["rgb"]), depth=cat(wl.targets["depth"]),
                normal=cat(wl.targets["normal"]))
     w3 = (1.0, 1.0, 1.0)
-    rd = render.Renderer(0, (tw, th))
+    tune_ms = None
+    if args.tile == "auto":
+        rd = render.Renderer(0, (16, 16))
+        (tw, th), tune_ms = rd.autotune(wl.views, sc, tgt, w3, reps=3)
+        log(f"[bench] autotuned tile {tw}x{th}: " +
+            ", ".join(f"{a}x{b} {m:.3f} ms" for (a, b), m in tune_ms.items()))
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        rd = render.Renderer(0, (tw, th))
     loss = torch.zeros(1, device=dev)
     # capacity discovery (grows the pair / row capacity on overflow)
     out, grads = rd.fwd_bwd_l1(wl.views, sc, tgt, w3, loss=loss)
@@ -121,7 +129,10 @@ def gpu_leg(args, wl):
         torch.cuda.synchronize()
         per_view_ms = (time.perf_counter() - t0) / reps * 1e3
         log(f"[bench] per-view loop: {per_view_ms:.3f} ms per batch ({len(wl.views)} calls)")
-    return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms, peak_bytes=torch.cuda.max_memory_allocated())
+    return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms,
+                peak_bytes=torch.cuda.max_memory_allocated(), tile=f"{tw}x{th}",
+                tune_ms=({f"{a}x{b}": round(m, 4) for (a, b), m in tune_ms.items()}
+                         if tune_ms else None))
 
 
 def roofline(res, steps):
@@ -234,7 +245,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "C2: 200,000 voxel anchors x 10 Gaussians (2M), 200x200x50 m city "
                                "block, 8 views 960x540..1920x1080, per-view LoD, fused fwd+L1+bwd",
-                   "views": len(wl.views), "pixels": pixels, "tile": args.tile,
+                   "views": len(wl.views), "pixels": pixels, "tile": res["tile"],
+                   "tile_autotune_ms": res["tune_ms"],
                    "rows": res["info"]["n_rows"], "pairs": res["info"]["n_pairs"]},
         "batched_vs_per_view": (round(res["per_view_ms"] / res["ms"], 3) if res["per_view_ms"] else None),
         "per_view_ms": (round(res["per_view_ms"], 4) if res["per_view_ms"] else None),

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 1
+#define CGX_ABI_VERSION 2
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -258,6 +258,29 @@ int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_
                                      float* loss_dev, void* stream, cgx_graph** graph);
 int32_t cgx_graph_launch(cgx_graph* graph, void* stream);
 int32_t cgx_graph_destroy(cgx_graph* graph);
+
+/* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
+ * images do not depend on the tile shape, only the speed does).  For each
+ * supported shape (in the order 16x16, 8x8, 16x8, 32x8, 32x16) that fits
+ * `workspace_bytes`, runs the fused chain of cgx_render_fwd_bwd_l1 once
+ * untimed and `reps` times timed with HIP events on `stream`, synchronising
+ * after each shape.  ms_per_shape[CGX_N_TILE_SHAPES] (host, may be NULL)
+ * receives the mean milliseconds per chain, or -1 for a shape whose
+ * workspace does not fit, or -2 for a shape whose run exceeded a capacity.
+ * On return *best_tw x *best_th is the fastest shape; the outputs, grads and
+ * loss hold that last shape's results, not necessarily the best one's.
+ * Returns CGX_ERR_CAPACITY if no shape ran within capacity, and
+ * CGX_ERR_WORKSPACE if no shape fits.  `ctx` gives the device and receives
+ * the error message; its own tile shape is neither used nor changed.
+ * Allocates no device memory. */
+#define CGX_N_TILE_SHAPES 5
+int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                            const cgx_scene* scene, const cgx_capacity* cap,
+                            void* workspace, size_t workspace_bytes,
+                            const cgx_images* target, const float* w3_host,
+                            const cgx_images* out, const cgx_grads* grads, float* loss_dev,
+                            int32_t reps, void* stream, int32_t* best_tw, int32_t* best_th,
+                            float* ms_per_shape);
 
 /* Phases of a launch chain, for cgx_timing_read. */
 enum {

@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
+CGX_ABI_VERSION = 2
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
 CGX_ERR_UNSUPPORTED = 2
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libcgx.so not built at {path}; run __graft_entry__.build()")
     lib = C.CDLL(path)
+    lib.cgx_abi_version.restype = C.c_int32
+    if lib.cgx_abi_version() != CGX_ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {lib.cgx_abi_version()}, the binding expects "
+                           f"{CGX_ABI_VERSION}; rebuild with __graft_entry__.build()")
     P = C.c_void_p
     sig = {
         "cgx_abi_version": (C.c_int32, []),
@@ -114,6 +119,13 @@ def load_library(path: str = LIB_PATH):
                                                      C.POINTER(cgx_grads), P, P, C.POINTER(P)]),
         "cgx_graph_launch": (C.c_int32, [P, P]),
         "cgx_graph_destroy": (C.c_int32, [P]),
+        "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
+                                            C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
+                                            C.c_size_t, C.POINTER(cgx_images),
+                                            C.POINTER(C.c_float), C.POINTER(cgx_images),
+                                            C.POINTER(cgx_grads), P, C.c_int32, P,
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_float)]),
         "cgx_timing_enable": (C.c_int32, [P, C.c_int32]),
         "cgx_timing_read": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]),
     }
@@ -280,6 +292,28 @@ def cgx_render_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grad
                                    C.byref(make_images(target)), w, C.byref(make_images(out)),
                                    C.byref(make_grads(grads)), _ptr(loss_dev), _stream())
     _check(ctx, rc, "cgx_render_fwd_bwd_l1")
+
+
+TILE_SHAPES = [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16)]
+
+
+def cgx_tune_tile_shape(ctx, views, scene, cap, ws, target, weights, out, grads, loss_dev=None,
+                        reps=3):
+    """Time the fused chain per tile shape; returns ((tw, th), {shape: ms})
+    with -1 for shapes whose workspace does not fit, -2 for capacity overflow."""
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    w = (C.c_float * 3)(*[float(x) for x in weights])
+    tw, th = C.c_int32(0), C.c_int32(0)
+    ms = (C.c_float * len(TILE_SHAPES))()
+    rc = lib.cgx_tune_tile_shape(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(),
+                                 C.byref(make_images(target)), w, C.byref(make_images(out)),
+                                 C.byref(make_grads(grads)), _ptr(loss_dev), int(reps), _stream(),
+                                 C.byref(tw), C.byref(th), ms)
+    _check(ctx, rc, "cgx_tune_tile_shape")
+    return (tw.value, th.value), {s: ms[i] for i, s in enumerate(TILE_SHAPES)}
 
 
 def cgx_read_info(ctx, ws, raise_on_capacity=True):

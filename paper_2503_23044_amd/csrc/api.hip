@@ -716,6 +716,71 @@ int32_t cgx_graph_destroy(cgx_graph* graph) {
   return CGX_OK;
 }
 
+int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                            const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                            size_t workspace_bytes, const cgx_images* target,
+                            const float* w3_host, const cgx_images* out, const cgx_grads* grads,
+                            float* loss_dev, int32_t reps, void* stream, int32_t* best_tw,
+                            int32_t* best_th, float* ms_per_shape) {
+  static const int kShapes[CGX_N_TILE_SHAPES][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 16}};
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!best_tw || !best_th) return fail(ctx, CGX_ERR_INVALID_ARG, "best_tw / best_th is NULL");
+  if (reps < 1 || reps > 1000) return fail(ctx, CGX_ERR_INVALID_ARG, "reps %d outside 1..1000", reps);
+  hipStream_t st = (hipStream_t)stream;
+  float best = -1.f;
+  int32_t last_rc = CGX_ERR_WORKSPACE;
+  for (int i = 0; i < CGX_N_TILE_SHAPES; ++i) {
+    if (ms_per_shape) ms_per_shape[i] = -1.f;
+    cgx_ctx c;
+    c.device = ctx->device;
+    c.tw = kShapes[i][0];
+    c.th = kShapes[i][1];
+    Layout L;
+    int32_t rc = make_layout(&c, views, n_views, scene, cap, L);
+    if (rc) return fail(ctx, rc, "%s", c.err.c_str());   // not shape-dependent
+    if (L.total > workspace_bytes) continue;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes, target,
+                               w3_host, out, grads, loss_dev, stream);
+    if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
+    Counters h;
+    rc = read_counters(&c, workspace, stream, h);
+    if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
+    if (h.overflow) {
+      if (ms_per_shape) ms_per_shape[i] = -2.f;
+      last_rc = CGX_ERR_CAPACITY;
+      continue;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) hipEventDestroy(e0);
+      return fail(ctx, CGX_ERR_HIP, "hipEventCreate failed");
+    }
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == CGX_OK; ++r)
+      rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes,
+                                 target, w3_host, out, grads, loss_dev, stream);
+    hipEventRecord(e1, st);
+    float ms = 0.f;
+    const hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
+    if (e != hipSuccess) return fail(ctx, CGX_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+    ms /= (float)reps;
+    if (ms_per_shape) ms_per_shape[i] = ms;
+    if (best < 0.f || ms < best) {
+      best = ms;
+      *best_tw = kShapes[i][0];
+      *best_th = kShapes[i][1];
+    }
+  }
+  if (best < 0.f)
+    return fail(ctx, last_rc, last_rc == CGX_ERR_CAPACITY ? "every tile shape exceeded a capacity"
+                                                          : "no tile shape fits the workspace");
+  return CGX_OK;
+}
+
 int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run_info* info) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   if (!workspace || !info) return fail(ctx, CGX_ERR_INVALID_ARG, "NULL argument");

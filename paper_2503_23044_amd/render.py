@@ -6,6 +6,9 @@ allocates tensors and marshals pointers.
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -64,6 +67,18 @@ def grad_buffers(scene, device="cuda"):
     g["W1"] = torch.zeros(scene["W1"].shape, dtype=torch.float32, device=device)
     g["W2"] = torch.zeros(scene["W2"].shape, dtype=torch.float32, device=device)
     return g
+
+
+def workload_key(views, scene):
+    """Signature of a workload for the tile-shape cache: scene kind and
+    size, SH degree, and the view resolutions."""
+    if scene["kind"] == B.CGX_SCENE_EXPLICIT:
+        head = f"explicit:n={scene['means'].shape[0]}:sh={scene['sh_degree']}"
+    else:
+        head = f"anchor:n={scene['x'].shape[0]}"
+    dim = lambda v, k: int(v[k] if isinstance(v, dict) else getattr(v, k))  # noqa: E731
+    res = ",".join(f"{dim(v, 'width')}x{dim(v, 'height')}" for v in views)
+    return f"{head}:views={res}"
 
 
 class Renderer:
@@ -143,6 +158,55 @@ class Renderer:
                 return out, grads
             self._grow(info)
         raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
+
+    def set_tile(self, tile):
+        tile = tuple(int(t) for t in tile)
+        if tile != self.tile:
+            ctx = B.cgx_create(self.device, tile[0], tile[1])
+            B.cgx_destroy(self.ctx)
+            self.ctx, self.tile = ctx, tile
+
+    def autotune(self, views, scene, target, weights=(1.0, 1.0, 1.0), reps=3, cache=None):
+        """Switch to the fastest tile shape for this workload, timed by
+        cgx_tune_tile_shape on the fused chain.  `cache` is an optional JSON
+        file keyed by the workload signature.  Returns (shape, {shape: ms}),
+        with an empty dict when the shape came from the cache."""
+        key = workload_key(views, scene)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tile(table[key])
+                return self.tile, {}
+        out, grads = self.fwd_bwd_l1(views, scene, target, weights)   # capacities for this shape
+        loss = torch.zeros(1, device=f"cuda:{self.device}")
+        for _ in range(4):
+            need = 0
+            for shape in B.TILE_SHAPES:
+                c = B.cgx_create(self.device, shape[0], shape[1])
+                try:
+                    need = max(need, B.cgx_workspace_size(c, views, scene, self.cap))
+                finally:
+                    B.cgx_destroy(c)
+            need = (need + 255) // 256 * 256
+            if self.ws is None or self.ws.numel() < need:
+                self.ws = None
+                self.ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+            best, ms = B.cgx_tune_tile_shape(self.ctx, views, scene, self.cap, self.ws, target,
+                                             weights, out, grads, loss, reps)
+            if all(v != -2.0 for v in ms.values()):
+                break
+            # a smaller tile shape exceeded the pair capacity: double it and time again
+            cap = dict(self.cap)
+            cap["max_pairs"] = 2 * max(int(cap.get("max_pairs", 0)), int(self.last_info["n_pairs"]), 1024)
+            self.cap = cap
+        self.set_tile(best)
+        if cache:
+            table[key] = list(best)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return self.tile, ms
 
     def info(self):
         return B.cgx_read_info(self.ctx, self.ws)
