@@ -204,6 +204,46 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Wave sum of 16 per-lane values, scattered over the lanes: on return lane l
+// holds the total of slot l & 15.  Within each 16-lane row, four halving
+// exchanges (partner lane = lane XOR 15, 7, 2, 1: row mirror, half-row
+// mirror and two quad permutations, all DPP) each send half of a lane's
+// partial sums to its partner and keep the other half; partner masks never
+// flip an earlier step's keep bit, so partners always hold the same slots.
+// The four rows are then summed with two cross-row exchanges.
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int lane) {
+  const bool f1 = (lane & 8) != 0, f2 = (lane & 4) != 0, f3 = (lane & 2) != 0,
+             f4 = (lane & 1) != 0;
+  float a[8], b[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float send = f1 ? g[i] : g[8 + i];
+    const float keep = f1 ? g[8 + i] : g[i];
+    a[i] = keep + dpp_read<0x140>(send);            // row_mirror: lane ^ 15
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float send = f2 ? a[i] : a[4 + i];
+    const float keep = f2 ? a[4 + i] : a[i];
+    b[i] = keep + dpp_read<0x141>(send);            // row_half_mirror: lane ^ 7
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = f3 ? b[i] : b[2 + i];
+    const float keep = f3 ? b[2 + i] : b[i];
+    c[i] = keep + dpp_read<0x4E>(send);             // quad_perm(2,3,0,1): lane ^ 2
+  }
+  float d = (f4 ? c[1] : c[0]) + dpp_read<0xB1>(f4 ? c[0] : c[1]);   // quad_perm(1,0,3,2)
+  d += __shfl_xor(d, 16, kWave);
+  d += __shfl_xor(d, 32, kWave);
+  return d;
+}
+
 // float atomic add without return (global_atomic_add_f32).
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -274,9 +274,9 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
       const int ylo = s.by & 0xFFFF, yhi = s.by >> 16;
       const bool inx = x >= xlo && x <= xhi;
       const float dx = s.u - px;
-      float g[13];
+      float g[16];
 #pragma unroll
-      for (int i = 0; i < 13; ++i) g[i] = 0.0f;
+      for (int i = 0; i < 16; ++i) g[i] = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
@@ -314,23 +314,11 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         }
         any = true;
       }
-      const uint64_t who = __ballot(any);
-      if (who == 0) continue;
-      float* dst = a.sgrad[sslot[j]].g;
-      if ((who & (who - 1)) == 0) {
-        // a single contributing lane adds its own values: no reduction needed
-        if (any) {
-#pragma unroll
-          for (int i = 0; i < 13; ++i)
-            if (g[i] != 0.0f) atomic_add_f32(dst + i, g[i]);
-        }
-        continue;
-      }
-#pragma unroll
-      for (int i = 0; i < 13; ++i) {
-        const float r = wave_sum_lane63(g[i]);
-        if (lane == kWave - 1 && r != 0.0f) atomic_add_f32(dst + i, r);
-      }
+      if (__ballot(any) == 0) continue;
+      // wave totals of the 13 terms land in lanes 0..12; one atomic
+      // instruction then adds them to the splat's 64-byte gradient record
+      const float r = wave_reduce_scatter16(g, lane);
+      if (lane < 13 && r != 0.0f) atomic_add_f32(a.sgrad[sslot[j]].g + lane, r);
     }
     __syncthreads();
   }
