@@ -45,6 +45,9 @@ def parse():
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=400)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
+                        "for scaling hardware byte counters)")
     return p.parse_args()
 
 
@@ -133,6 +136,21 @@ def gpu_leg(args, wl):
                 peak_bytes=torch.cuda.max_memory_allocated(), tile=f"{tw}x{th}",
                 tune_ms=({f"{a}x{b}": round(m, 4) for (a, b), m in tune_ms.items()}
                          if tune_ms else None))
+
+
+def copy_calibration(mib):
+    """Three device-to-device copies of `mib` MiB: each reads and writes
+    exactly mib MiB, which calibrates FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * 2**20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {mib} MiB")
+    del src, dst
 
 
 def roofline(res, steps):
@@ -227,6 +245,8 @@ def main():
     wl = scenes.make(args.config)
     log(f"[bench] workload {wl.name}: {len(wl.views)} views, {wl.pixels} pixels "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     res = gpu_leg(args, wl)
     pixels = wl.pixels
     value = pixels / (res["ms"] * 1e-3) / 1e6
