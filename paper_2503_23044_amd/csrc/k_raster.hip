@@ -1,16 +1,19 @@
 // a6 forward and a8 backward rasterization, with the a7 L1 seed fused into
 // the backward prologue.
 //
-// One wave per tile: a TW x TH tile is covered by 64 lanes, each owning
-// PPL = TW*TH/64 pixels of one column (rows y0, y0 + 64/TW, ...).  Splat
-// records of the tile's sorted list are staged 64 at a time in LDS (one
-// 64-byte gather per lane) and every lane walks them front to back for its
-// pixels.  A wave stops as soon as a ballot shows that all its pixels have
-// saturated.  The forward pass keeps 8 bytes per pixel (final
-// transmittance, last contributing list index); the backward pass re-walks
-// the same list from that index towards the front, recovering the
-// transmittance by division, and reduces each splat's 13 gradient values
-// across the wave with DPP before one lane adds them atomically.
+// One wave per tile.  A TW x TH tile is cut into PPL = TW*TH/64 sub-blocks
+// of 8 x 8 pixels; lane l owns pixel (l % 8, l / 8) of every sub-block.
+// Splat records of the tile's sorted list are staged 64 at a time in LDS
+// (one 64-byte gather per lane) and the wave walks them front to back.  For
+// each splat the pixel box is tested against every sub-block with scalar
+// (wave-uniform) compares, so sub-blocks the splat misses cost no vector
+// work and the lanes of a hit sub-block are mostly inside the box.  A wave
+// stops as soon as a ballot shows that all its pixels have saturated.  The
+// forward pass keeps 8 bytes per pixel (final transmittance, last
+// contributing list index); the backward pass re-walks the same list from
+// that index towards the front, recovering the transmittance by division,
+// and reduce-scatters each splat's 13 gradient terms across the wave so
+// that one 13-lane atomic instruction adds them to the splat's record.
 #include "cgx_common.h"
 
 namespace cgx {
@@ -32,22 +35,37 @@ __device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
   d[3] = e;
 }
 
+// 8 x 8 sub-block k of a tile: column k % (TW / 8), row k / (TW / 8)
+template <int TW>
+__device__ __forceinline__ int sub_x0(int tx, int k) { return tx * TW + (k % (TW / 8)) * 8; }
+template <int TW>
+__device__ __forceinline__ int sub_y0(int ty, int TH, int k) { return ty * TH + (k / (TW / 8)) * 8; }
+
+// pixel box (inclusive) of a staged splat, read as wave-uniform scalars
+struct Box {
+  int xlo, xhi, ylo, yhi;
+};
+__device__ __forceinline__ Box uniform_box(const Splat& s) {
+  const uint32_t bx = __builtin_amdgcn_readfirstlane(s.bx);
+  const uint32_t by = __builtin_amdgcn_readfirstlane(s.by);
+  return Box{(int)(bx & 0xFFFF), (int)(bx >> 16), (int)(by & 0xFFFF), (int)(by >> 16)};
+}
+__device__ __forceinline__ bool box_misses_block(const Box& b, int x0, int y0) {
+  return b.xhi < x0 || b.xlo > x0 + 7 || b.yhi < y0 || b.ylo > y0 + 7;
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
-  constexpr int RS = kWave / TW;
   __shared__ Splat sh[kWave];
   const uint32_t tile = a.order[blockIdx.x];
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
   const int v = find_view(a.views, a.B, tile);
   const ViewDev& V = a.views[v];
   const int local = (int)tile - V.tile_off;
   const int tx = local % V.TX, ty = local / V.TX;
-  const int x = tx * TW + (lane % TW);
-  const int y0 = ty * TH + (lane / TW);
-  const float px = (float)x + 0.5f;
-  const bool vx = x < V.W;
 
   float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
   uint32_t last[PPL], walked[PPL];
@@ -58,17 +76,19 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
     last[k] = 0;
     walked[k] = 0;
-    done[k] = !(vx && (y0 + k * RS) < V.H);
+    done[k] = !(sub_x0<TW>(tx, k) + lx < V.W && sub_y0<TW>(ty, TH, k) + ly < V.H);
   }
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
   uint32_t evals = 0;
 
   for (uint32_t base = start; base < end; base += kWave) {
-    bool live = false;
+    // sub-blocks with a live pixel (wave-uniform bit mask)
+    uint32_t live = 0;
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) live |= !done[k];
-    if (__ballot(live) == 0) break;
+    for (int k = 0; k < PPL; ++k)
+      if (__ballot(!done[k]) != 0) live |= 1u << k;
+    if (live == 0) break;
     const uint32_t n = (end - base) < (uint32_t)kWave ? (end - base) : (uint32_t)kWave;
     if ((uint32_t)lane < n) {
       const uint32_t slot = a.vals[base + lane];
@@ -78,15 +98,15 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     __syncthreads();
     for (uint32_t j = 0; j < n; ++j) {
       const Splat& s = sh[j];
-      const int xlo = s.bx & 0xFFFF, xhi = s.bx >> 16;
-      const int ylo = s.by & 0xFFFF, yhi = s.by >> 16;
-      if (x < xlo || x > xhi) continue;
-      const float dx = s.u - px;
+      const Box b = uniform_box(s);
       const uint32_t idx = base - start + j + 1;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        const int y = y0 + k * RS;
-        if (done[k] || y < ylo || y > yhi) continue;
+        const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
+        if (!(live & (1u << k)) || box_misses_block(b, x0, y0)) continue;
+        const int x = x0 + lx, y = y0 + ly;
+        if (done[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
+        const float dx = s.u - ((float)x + 0.5f);
         const float dy = s.w - ((float)y + 0.5f);
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
@@ -114,27 +134,27 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   }
 
   const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
+  const size_t pv = (size_t)V.pix_off;
   uint32_t walked_sum = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int y = y0 + k * RS;
-    if (!(vx && y < V.H)) continue;
+    const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
+    if (!(x < V.W && y < V.H)) continue;
     if (walked[k] == 0) walked[k] = end - start;
     walked_sum += walked[k];
     const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
     const float r = C0[k] + T[k] * V.bg[0];
     const float g = C1[k] + T[k] * V.bg[1];
-    const float b = C2[k] + T[k] * V.bg[2];
+    const float bl = C2[k] + T[k] * V.bg[2];
     const float acc = 1.0f - T[k];
     const float rx = ((float)x + 0.5f - V.cx) / V.fx;
     const float ry = ((float)y + 0.5f - V.cy) / V.fy;
     const float sd = -(N0[k] * rx + N1[k] * ry + N2[k]);
     const float dh = sd > kDhatGuard * acc ? D[k] / sd : 0.0f;
-    const size_t pv = (size_t)V.pix_off;
     if (a.rgb) {
       a.rgb[3 * pv + p] = r;
       a.rgb[3 * pv + HW + p] = g;
-      a.rgb[3 * pv + 2 * HW + p] = b;
+      a.rgb[3 * pv + 2 * HW + p] = bl;
     }
     if (a.depth) a.depth[pv + p] = dh;
     if (a.plane_d) a.plane_d[pv + p] = D[k];
@@ -156,25 +176,21 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   if (lane == 0 && evals) atomicAdd(&a.ctr->evals_fwd, (unsigned long long)evals);
 }
 
-__device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+__device__ __forceinline__ float sgnf(float e) { return e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f); }
 
 template <int TW, int TH>
 __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
-  constexpr int RS = kWave / TW;
   __shared__ Splat sh[kWave];
   __shared__ uint32_t sslot[kWave];
   const uint32_t tile = a.order[blockIdx.x];
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
   const int v = find_view(a.views, a.B, tile);
   const ViewDev& V = a.views[v];
   const int local = (int)tile - V.tile_off;
   const int tx = local % V.TX, ty = local / V.TX;
-  const int x = tx * TW + (lane % TW);
-  const int y0 = ty * TH + (lane / TW);
-  const float px = (float)x + 0.5f;
-  const bool vx = x < V.W;
   const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
   const size_t pv = (size_t)V.pix_off;
   const float inv_px = 1.0f / ((float)a.B * (float)HW);
@@ -182,14 +198,14 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   float T[PPL], S[PPL], GC0[PPL], GC1[PPL], GC2[PPL], GD[PPL], GN0[PPL], GN1[PPL], GN2[PPL];
   uint32_t last[PPL];
   float loss = 0.0f;
-  uint32_t maxlast = 0, sumlast = 0;
+  uint32_t sumlast = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int y = y0 + k * RS;
+    const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
     last[k] = 0;
     T[k] = 1.0f;
     S[k] = GC0[k] = GC1[k] = GC2[k] = GD[k] = GN0[k] = GN1[k] = GN2[k] = 0.0f;
-    if (!(vx && y < V.H)) continue;
+    if (!(x < V.W && y < V.H)) continue;
     const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
     const float Tf = a.px_T[pv + p];
     last[k] = a.px_last[pv + p];
@@ -239,7 +255,6 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     T[k] = Tf;
     const float dT = V.bg[0] * gc[0] + V.bg[1] * gc[1] + V.bg[2] * gc[2] - ga;
     S[k] = Tf * dT;
-    maxlast = last[k] > maxlast ? last[k] : maxlast;
     sumlast += last[k];
   }
   if (a.l1) {
@@ -247,11 +262,20 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, kWave);
     if (lane == 0 && l != 0.0f) atomic_add_f32(&a.ctr->loss, l);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t m = __shfl_xor(maxlast, o, kWave);
-    maxlast = m > maxlast ? m : maxlast;
-    sumlast += __shfl_xor(sumlast, o, kWave);
+  // per sub-block: the largest last-contributor index (wave-uniform)
+  uint32_t blast[PPL];
+  uint32_t maxlast = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    uint32_t m = last[k];
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t q = __shfl_xor(m, o, kWave);
+      m = q > m ? q : m;
+    }
+    blast[k] = __builtin_amdgcn_readfirstlane(m);
+    maxlast = blast[k] > maxlast ? blast[k] : maxlast;
   }
+  for (int o = 32; o > 0; o >>= 1) sumlast += __shfl_xor(sumlast, o, kWave);
   if (lane == 0 && sumlast) atomicAdd(&a.ctr->entries_bwd, (unsigned long long)sumlast);
 
   const uint32_t start = a.ranges[tile].x;
@@ -269,19 +293,19 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const Splat& s = sh[j];
+      const Box b = uniform_box(s);
       const uint32_t idx = (uint32_t)(lo + j);   // 0-based list index
-      const int xlo = s.bx & 0xFFFF, xhi = s.bx >> 16;
-      const int ylo = s.by & 0xFFFF, yhi = s.by >> 16;
-      const bool inx = x >= xlo && x <= xhi;
-      const float dx = s.u - px;
       float g[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) g[i] = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        const int y = y0 + k * RS;
-        if (!inx || idx >= last[k] || y < ylo || y > yhi) continue;
+        const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
+        if (idx >= blast[k] || box_misses_block(b, x0, y0)) continue;
+        const int x = x0 + lx, y = y0 + ly;
+        if (idx >= last[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
+        const float dx = s.u - ((float)x + 0.5f);
         const float dy = s.w - ((float)y + 0.5f);
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
