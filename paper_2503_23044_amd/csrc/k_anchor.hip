@@ -563,60 +563,139 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
   }
 }
 
-// Weight gradients: each block sums a contiguous chunk of rows into one
-// partial of 4814 values (W1, W2, b1, b2); a second kernel adds the partials
-// in a fixed order.
+// Weight gradients on MFMA: dW1 = Z0^T dZ1 (36 x 32) and dW2 = Z1^T dZ2
+// (32 x 110), reductions over the rows.  Each block (one wave) owns a
+// contiguous chunk of rows and walks it 32 rows (one MFMA k-step) at a
+// time: the chunk's z0, z1, dz1 and dz2 are split into three bf16 terms
+// (h + m + l, as in the forward decode) and staged transposed in LDS, and
+// the six products h*h, h*m, m*h, h*l, l*h, m*m (the dropped ones are below
+// 2^-26 relative) accumulate in fp32.  The biases' gradients are plain
+// column sums.  Every block writes one partial of 4814 values; a second
+// kernel adds the partials in a fixed order (deterministic).
 constexpr int kRedBlocks = 256;
-constexpr int kRedRows = 32;
+constexpr int kWR = 32;          // rows per MFMA k-step
+constexpr int kM1 = 48;          // dW1 rows (36 padded)
+constexpr int kN2w = 112;        // dW2 columns (110 padded)
 
-__global__ __launch_bounds__(256) void k_wgrad_partial(const float* __restrict__ scratch,
-                                                       const Counters* ctr,
-                                                       float* __restrict__ partial) {
-  __shared__ float rowbuf[kRedRows * kRowScratch];
+struct WgradLds {
+  uint16_t z0t[3][kM1][kWR];     // A of dW1: (i, r) per split term
+  uint16_t dz1t[3][kHid][kWR];   // B of dW1: (j, r)
+  uint16_t z1t[3][kHid][kWR];    // A of dW2: (j, r)
+  uint16_t dz2t[3][kN2w][kWR];   // B of dW2: (c, r)
+};
+
+__global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scratch,
+                                                  const Counters* ctr,
+                                                  float* __restrict__ partial) {
+  __shared__ WgradLds L;
+  const int lane = threadIdx.x;
   const uint32_t n = ctr->n_rows;
   uint64_t b0, b1;
   chunk_range(n, b0, b1);
-  constexpr int NO = (kWGrad + 255) / 256;
-  float acc[NO];
+  const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  f32x4_t acc1[3][2], acc2[2][7];
 #pragma unroll
-  for (int q = 0; q < NO; ++q) acc[q] = 0.0f;
-  for (uint64_t base = b0; base < b1; base += kRedRows) {
-    const int nr = (int)((b1 - base) < (uint64_t)kRedRows ? (b1 - base) : (uint64_t)kRedRows);
-    for (int i = threadIdx.x; i < nr * kRowScratch; i += 256)
-      rowbuf[i] = scratch[base * kRowScratch + i];
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc1[m][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < 7; ++t) acc2[m][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // bias gradients: lane owns columns lane, lane + 64, lane + 128 of [dz1 | dz2]
+  float bsum[3] = {0.f, 0.f, 0.f};
+
+  for (uint64_t base = b0; base < b1; base += kWR) {
+    const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
+    const float* src = scratch + base * kRowScratch;
+    // stage: element e of the chunk is (row e / kRowScratch, value e % kRowScratch)
+    for (int e = lane; e < kWR * kRowScratch; e += 64) {
+      const int r = e / kRowScratch, q = e - r * kRowScratch;
+      const float x = r < nr ? src[e] : 0.0f;
+      uint16_t h, m, l;
+      split3(x, h, m, l);
+      if (q < kIn) {
+        L.z0t[0][q][r] = h; L.z0t[1][q][r] = m; L.z0t[2][q][r] = l;
+      } else if (q < kIn + kHid) {
+        const int j = q - kIn;
+        L.z1t[0][j][r] = h; L.z1t[1][j][r] = m; L.z1t[2][j][r] = l;
+      } else if (q < kIn + 2 * kHid) {
+        const int j = q - kIn - kHid;
+        L.dz1t[0][j][r] = h; L.dz1t[1][j][r] = m; L.dz1t[2][j][r] = l;
+      } else {
+        const int c = q - kIn - 2 * kHid;
+        L.dz2t[0][c][r] = h; L.dz2t[1][c][r] = m; L.dz2t[2][c][r] = l;
+      }
+    }
+    for (int e = lane; e < 3 * (kM1 - kIn) * kWR; e += 64) {      // zero padding rows of z0t
+      const int t = e / ((kM1 - kIn) * kWR), rem = e % ((kM1 - kIn) * kWR);
+      L.z0t[t][kIn + rem / kWR][rem % kWR] = 0;
+    }
+    for (int e = lane; e < 3 * (kN2w - kOut) * kWR; e += 64) {    // and padding columns of dz2t
+      const int t = e / ((kN2w - kOut) * kWR), rem = e % ((kN2w - kOut) * kWR);
+      L.dz2t[t][kOut + rem / kWR][rem % kWR] = 0;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int c = lane + 64 * cc;
+      if (c < kHid + kOut) {
+        const int off = kIn + kHid + c;
+        float sum = 0.0f;
+        for (int r = 0; r < nr; ++r) sum += src[(size_t)r * kRowScratch + off];
+        bsum[cc] += sum;
+      }
+    }
     __syncthreads();
+    // six split products (ta, tb): the A term index and the B term index
 #pragma unroll
-    for (int q = 0; q < NO; ++q) {
-      const int o = threadIdx.x + 256 * q;
-      if (o >= kWGrad) continue;
-      int ia, ib;
-      if (o < kIn * kHid) {               // dW1[i][j] = z0[i] dz1[j]
-        ia = o / kHid;
-        ib = kIn + kHid + o % kHid;
-      } else if (o < kIn * kHid + kHid * kOut) {   // dW2[j][c] = z1[j] dz2[c]
-        const int t = o - kIn * kHid;
-        ia = kIn + t / kOut;
-        ib = kIn + 2 * kHid + t % kOut;
-      } else if (o < kIn * kHid + kHid * kOut + kHid) {   // db1[j] = dz1[j]
-        ia = -1;
-        ib = kIn + kHid + (o - kIn * kHid - kHid * kOut);
-      } else {                                            // db2[c] = dz2[c]
-        ia = -1;
-        ib = kIn + 2 * kHid + (o - kIn * kHid - kHid * kOut - kHid);
+    for (int pr = 0; pr < 6; ++pr) {
+      const int ta = pr == 2 ? 1 : (pr == 4 ? 2 : (pr == 5 ? 1 : 0));
+      const int tb = pr == 1 ? 1 : (pr == 3 ? 2 : (pr == 5 ? 1 : 0));
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const bf16x8_t bv = load8(&L.dz1t[tb][t * 16 + col][kq]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const bf16x8_t av = load8(&L.z0t[ta][m * 16 + col][kq]);
+          acc1[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc1[m][t], 0, 0, 0);
+        }
       }
-      float s = 0.0f;
-      for (int rr = 0; rr < nr; ++rr) {
-        const float* rw = rowbuf + rr * kRowScratch;
-        s += (ia >= 0 ? rw[ia] : 1.0f) * rw[ib];
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const bf16x8_t bv = load8(&L.dz2t[tb][t * 16 + col][kq]);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const bf16x8_t av = load8(&L.z1t[ta][m * 16 + col][kq]);
+          acc2[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc2[m][t], 0, 0, 0);
+        }
       }
-      acc[q] += s;
     }
     __syncthreads();
   }
+  // partial layout: W1 (i, j) row-major, W2 (j, c) row-major, b1, b2
+  float* out = partial + (size_t)blockIdx.x * kWGrad;
 #pragma unroll
-  for (int q = 0; q < NO; ++q) {
-    const int o = threadIdx.x + 256 * q;
-    if (o < kWGrad) partial[(size_t)blockIdx.x * kWGrad + o] = acc[q];
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ii = m * 16 + rq + i, j = t * 16 + col;
+        if (ii < kIn) out[ii * kHid + j] = acc1[m][t][i];
+      }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = m * 16 + rq + i, c = t * 16 + col;
+        if (c < kOut) out[kIn * kHid + j * kOut + c] = acc2[m][t][i];
+      }
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const int c = lane + 64 * cc;
+    if (c < kHid + kOut) out[kIn * kHid + kHid * kOut + c] = bsum[cc];
   }
 }
 
@@ -655,8 +734,8 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
   if (rblocks)
     hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        scratch, g);
-  hipLaunchKernelGGL(k_wgrad_partial, dim3(kRedBlocks), dim3(256), 0, s, (const float*)scratch,
-                     ctr, partial);
+  hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(64), 0, s, (const float*)scratch, ctr,
+                     partial);
   hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 256)), dim3(256), 0, s,
                      (const float*)partial, kRedBlocks, g);
 }
