@@ -259,6 +259,28 @@ int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_
 int32_t cgx_graph_launch(cgx_graph* graph, void* stream);
 int32_t cgx_graph_destroy(cgx_graph* graph);
 
+/* Batch-level geometric loss (Sec. 3.4, Eq. 10).  Views are paired as
+ * (0, 1), (2, 3), ...; in each pair the second view is the reference: for
+ * each of its `n_patch` patch centres (device int32 (x, y), pair-major:
+ * centres[2 * (pair * n_patch + k) + {0, 1}]) the 7 x 7 patch around it is
+ * compared by normalised cross-correlation, on the mean of the RGB
+ * channels, with the first view's image sampled bilinearly through the
+ * plane-induced homography of the reference's rendered normal and plane
+ * distance at the centre (the first view is under stop-gradient).  A patch
+ * that leaves the reference image, has plane distance <= 0 at its centre,
+ * or warps behind or outside the first view adds nothing.
+ *   loss = weight / (n_pairs * n_patch) * sum over valid patches (1 - NCC)
+ * is ADDED to *loss_dev (device, may be NULL) and dloss/drgb is ADDED to
+ * grad_rgb (device, the planar packed rgb layout of cgx_images); pass that
+ * buffer as grad_out->rgb of cgx_render_backward.  `images` holds the rgb,
+ * normal and plane_d outputs of the forward call made on `workspace` with
+ * these views (its view table is read).  An odd last view is unpaired.
+ * Overlapping patches accumulate with float atomics. */
+int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                     const void* workspace, const cgx_images* images,
+                     const int32_t* centres, int32_t n_patch, float weight,
+                     float* grad_rgb, float* loss_dev, void* stream);
+
 /* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
  * images do not depend on the tile shape, only the speed does).  For each
  * supported shape (in the order 16x16, 8x8, 16x8, 32x8, 32x16) that fits

@@ -119,6 +119,8 @@ def load_library(path: str = LIB_PATH):
                                                      C.POINTER(cgx_grads), P, P, C.POINTER(P)]),
         "cgx_graph_launch": (C.c_int32, [P, P]),
         "cgx_graph_destroy": (C.c_int32, [P]),
+        "cgx_ncc_loss": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, C.POINTER(cgx_images), P,
+                                     C.c_int32, C.c_float, P, P, P]),
         "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
                                             C.c_size_t, C.POINTER(cgx_images),
@@ -292,6 +294,17 @@ def cgx_render_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grad
                                    C.byref(make_images(target)), w, C.byref(make_images(out)),
                                    C.byref(make_grads(grads)), _ptr(loss_dev), _stream())
     _check(ctx, rc, "cgx_render_fwd_bwd_l1")
+
+
+def cgx_ncc_loss(ctx, views, ws, images, centres, n_patch, weight, grad_rgb, loss_dev=None):
+    """Eq. 10 loss on the forward images held in `images` (rgb, normal,
+    plane_d); ADDS dloss/drgb into grad_rgb and the loss into loss_dev."""
+    lib = load_library()
+    va = make_views(views)
+    rc = lib.cgx_ncc_loss(ctx, va, len(views), C.c_void_p(ws.data_ptr()), C.byref(make_images(images)),
+                          _ptr(centres), int(n_patch), float(weight), _ptr(grad_rgb), _ptr(loss_dev),
+                          _stream())
+    _check(ctx, rc, "cgx_ncc_loss")
 
 
 TILE_SHAPES = [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16)]

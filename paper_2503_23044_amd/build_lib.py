@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgx.so")
-SOURCES = ["api.hip", "k_util.hip", "k_sort.hip", "k_explicit.hip", "k_anchor.hip", "k_raster.hip"]
+SOURCES = ["api.hip", "k_util.hip", "k_sort.hip", "k_explicit.hip", "k_anchor.hip", "k_raster.hip",
+           "k_loss.hip"]
 ARCH = os.environ.get("CGX_OFFLOAD_ARCH", "gfx950")
 
 

@@ -716,6 +716,32 @@ int32_t cgx_graph_destroy(cgx_graph* graph) {
   return CGX_OK;
 }
 
+int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views, const void* workspace,
+                     const cgx_images* images, const int32_t* centres, int32_t n_patch,
+                     float weight, float* grad_rgb, float* loss_dev, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_views(ctx, views, n_views);
+  if (rc) return rc;
+  if (n_views < 2) return fail(ctx, CGX_ERR_INVALID_ARG, "the loss needs at least one view pair");
+  if (n_patch < 0 || (int64_t)n_patch * (n_views / 2) > (int64_t)INT32_MAX)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "n_patch %d out of range", n_patch);
+  if (!std::isfinite(weight)) return fail(ctx, CGX_ERR_INVALID_ARG, "weight is not finite");
+  if (!workspace || !images || !images->rgb || !images->normal || !images->plane_d || !grad_rgb)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace, rgb, normal, plane_d and grad_rgb are required");
+  if (n_patch > 0 && !centres) return fail(ctx, CGX_ERR_INVALID_ARG, "centres is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  // the view table follows the counter block (the first two workspace regions)
+  const ViewDev* vt = reinterpret_cast<const ViewDev*>(
+      reinterpret_cast<const char*>(workspace) + align_up(sizeof(Counters)));
+  launch_ncc_loss(vt, n_views, images->rgb, images->normal, images->plane_d, centres, n_patch,
+                  weight, grad_rgb, loss_dev, (hipStream_t)stream);
+  HIP_OK(ctx, hipGetLastError());
+  return CGX_OK;
+}
+
 int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                             const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
                             size_t workspace_bytes, const cgx_images* target,

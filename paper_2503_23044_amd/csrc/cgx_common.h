@@ -342,5 +342,8 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
                                     const cgx_grads& g, float* scratch, hipStream_t s);
 size_t anchor_scratch_bytes(int64_t max_rows);
 void launch_zero_f32(float* p, size_t n, hipStream_t s);
+void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const float* normal,
+                     const float* plane_d, const int32_t* centres, int n_patch, float weight,
+                     float* grad_rgb, float* loss, hipStream_t s);
 
 }  // namespace cgx

@@ -208,6 +208,21 @@ class Renderer:
                 json.dump(table, f, indent=1, sort_keys=True)
         return self.tile, ms
 
+    def ncc_loss(self, views, out, centres, weight=1.0, grad_rgb=None, loss=None):
+        """Batch geometric loss (Eq. 10) of the last forward's images `out`;
+        centres is an int32 device tensor (n_views // 2, n_patch, 2) of patch
+        centres in each pair's second view.  Returns (grad_rgb, loss): the
+        gradient is added to grad_rgb (zeros when not given)."""
+        dev = f"cuda:{self.device}"
+        if grad_rgb is None:
+            grad_rgb = torch.zeros_like(out["rgb"])
+        if loss is None:
+            loss = torch.zeros(1, device=dev)
+        c = centres.to(device=dev, dtype=torch.int32).contiguous()
+        n_patch = int(c.shape[1]) if c.dim() == 3 else int(c.numel() // 2 // max(len(views) // 2, 1))
+        B.cgx_ncc_loss(self.ctx, views, self.ws, out, c, n_patch, weight, grad_rgb, loss)
+        return grad_rgb, loss
+
     def info(self):
         return B.cgx_read_info(self.ctx, self.ws)
 

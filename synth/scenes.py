@@ -513,3 +513,45 @@ def make_small_anchor(seed, n_anchor=60, n_views=2, sizes=((40, 32), (24, 36)),
     wl = Workload(f"small_anchor{seed}", scene, views)
     wl.targets = make_targets(wl, seed=2000 + seed, depth_range=(2.0, 6.0))
     return wl
+
+
+def make_view_pairs(seed, n=3000, n_pairs=2, width=96, height=80) -> Workload:
+    """Explicit Gaussians on a tilted, slightly rough plane seen by pairs of
+    nearby cameras (views 2i, 2i+1), for the batch geometric loss: each
+    pair's views overlap in most of their pixels."""
+    rng = np.random.default_rng(seed)
+    uv = rng.uniform(-1.0, 1.0, (n, 2))
+    z = 0.25 * uv[:, 0] - 0.15 * uv[:, 1] + rng.normal(0.0, 0.02, n)
+    means = np.stack([uv[:, 0], uv[:, 1], z], 1).astype(np.float32)
+    scales = np.exp(rng.normal(-3.2, 0.3, (n, 3))).astype(np.float32)
+    scales[:, 2] *= 0.2                       # flat splats, normals along the plane's
+    quats = random_quats(rng, n) * 0.0
+    quats[:, 0] = 1.0
+    quats += rng.normal(0.0, 0.05, quats.shape).astype(np.float32)
+    opacity = sigmoid(rng.normal(1.5, 0.5, n)).astype(np.float32)
+    rgb = rng.uniform(0.0, 1.0, (n, 3))
+    _, _, _, sh = _explicit_attrs(rng, n, 0, rgb_dc=rgb)
+    scene = ExplicitScene(means, scales, quats.astype(np.float32), opacity, sh, 0)
+    views = []
+    for p in range(n_pairs):
+        base = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(2.6, 3.0)])
+        for _ in range(2):
+            pos = base + rng.normal(0.0, 0.06, 3)
+            views.append(look_at(pos, rng.uniform(-0.1, 0.1, 3), width, height, fov_deg=50.0,
+                                 yaw_hint=float(rng.uniform(0, 0.2))))
+    wl = Workload("pairs", scene, views)
+    wl.targets = make_targets(wl, seed=seed + 100, depth_range=(2.0, 3.5))
+    return wl
+
+
+def patch_centres(seed, views, n_patch, patch=7) -> np.ndarray:
+    """Uniform integer patch centres, (n_views // 2, n_patch, 2) as (x, y), in
+    each pair's second view, keeping the whole patch inside the image."""
+    rng = np.random.default_rng(seed)
+    h = patch // 2
+    out = np.zeros((len(views) // 2, n_patch, 2), np.int32)
+    for i in range(len(views) // 2):
+        v = views[2 * i + 1]
+        out[i, :, 0] = rng.integers(h, int(v.width) - h, n_patch)
+        out[i, :, 1] = rng.integers(h, int(v.height) - h, n_patch)
+    return out
