@@ -15,7 +15,10 @@ open:
     (global tile id << 32 | depth bits) over pairs emitted in splat order;
   * per pixel, walking the list: skip splats whose pixel box misses the
     pixel; power = -1/2 (a dx^2 + c dy^2) - b dx dy with dx = u - px,
-    dy = w - py at the pixel centre; alpha = min(0.99, o exp(power)); skip
+    dy = w - py at the pixel centre, where (u, w) is the 2-D mean rounded
+    to float32 (the paper fixes no precision; the compositor's input mean is
+    read as binary32, as the depth key is, because at 1080p and above its
+    rounding moves alpha by up to ~1e-4 relative); alpha = min(0.99, o exp(power)); skip
     alpha < 1/255; stop (without blending) when T (1 - alpha) < 1e-4;
   * the normal map stays in the camera frame and faces the camera, the
     plane distance is d = -n . p >= 0, and the unbiased depth is
@@ -32,6 +35,10 @@ DHAT_GUARD = 1e-3
 FRAG_ALPHA = 1e-5
 FRAG_T = 1e-4
 FRAG_SIGN = 1e-5
+# The compositor's 2-D mean is the float32 rounding of the float64 one.  The
+# finite-difference pins switch this off: rounding makes the image a step
+# function of the mean at the scale of those differences.
+MEAN_F32 = True
 
 
 # --------------------------------------------------------------------------
@@ -140,8 +147,13 @@ def _tile_pixels(view, layout, v, local_tile):
 
 
 def _tile_eval(S, ent, I, J):
-    """alpha matrix (pixels x entries) and the per-entry decisions."""
+    """alpha matrix (pixels x entries) and the per-entry decisions.  The
+    compositor takes the 2-D mean as float32 (the binary32 rounding of the
+    float64 projection, like the depth key); everything after is float64."""
     u, w = S["u"][ent], S["w"][ent]
+    if MEAN_F32:
+        u = u.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
     a, b, c = S["conic"][ent].T
     box = S["box"][ent]
     px = I[:, None] + 0.5

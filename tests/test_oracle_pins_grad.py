@@ -8,7 +8,15 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle import pipeline
+from oracle import raster as ras
 from synth import scenes
+
+
+@pytest.fixture(autouse=True)
+def _exact_means(monkeypatch):
+    """Finite differences need the exact (float64) 2-D mean in the
+    compositor; its float32 rounding is a step function at this scale."""
+    monkeypatch.setattr(ras, "MEAN_F32", False)
 
 
 def _signature(r):

@@ -150,7 +150,9 @@ def _brute_force(scene, view, rgb):
                 if not (x0 <= i <= x1 and y0 <= j <= y1):
                     continue
                 a, b, c = S["conic"][g]
-                dx, dy = S["u"][g] - (i + 0.5), S["w"][g] - (j + 0.5)
+                # the compositor's 2-D mean is binary32
+                dx = float(np.float32(S["u"][g])) - (i + 0.5)
+                dy = float(np.float32(S["w"][g])) - (j + 0.5)
                 pw = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
                 if pw > 0:
                     continue
