@@ -86,6 +86,9 @@ def ncc_loss(images, view_arrays, centres, patch=7, weight=1.0):
     oy, ox = np.mgrid[-h:h + 1, -h:h + 1]
     ox, oy = ox.ravel(), oy.ravel()
     grads = [np.zeros_like(np.asarray(im["rgb"], np.float64)) for im in images]
+    # per pixel, the sum of |terms| of its gradient (the scale of float32 error
+    # in a sum that nearly cancels when NCC is close to 1)
+    gmag = [np.zeros_like(g) for g in grads]
     valid = np.zeros((n_pairs, P), bool)
     fragile = np.zeros((n_pairs, P), bool)
     nccs = np.zeros((n_pairs, P))
@@ -133,6 +136,8 @@ def ncc_loss(images, view_arrays, centres, patch=7, weight=1.0):
             # d ncc / d a_j = B_j / den - sab sbb A_j / den^3 (sum B = 0)
             dn = Bc / den - sab * sbb * A / den ** 3
             ga = -scale * dn / 3.0
+            gm = scale * (np.abs(Bc / den) + np.abs(sab * sbb * A / den ** 3)) / 3.0
             for c in range(3):
                 np.add.at(grads[r][c], py * Wr + px, ga)
-    return loss, grads, dict(valid=valid, ncc=nccs, fragile=fragile)
+                np.add.at(gmag[r][c], py * Wr + px, gm)
+    return loss, grads, dict(valid=valid, ncc=nccs, fragile=fragile, gmag=gmag)

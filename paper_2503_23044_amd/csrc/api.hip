@@ -163,7 +163,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.n_passes = sort_passes(32) + sort_passes(bits);
   L.vis_buf = sort_passes(32) & 1;
   L.final_buf = sort_passes(bits) & 1;
-  L.order_buf = sort_passes(16) & 1;
+  L.order_buf = sort_passes(kTileOrderBits) & 1;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -381,6 +381,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.ranges = P.ranges;
   a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
+  a.band = tile_band((uint32_t)L.n_tiles);
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;
   a.depth = out->depth;
@@ -438,6 +439,7 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   a.ranges = P.ranges;
   a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
+  a.band = tile_band((uint32_t)L.n_tiles);
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;
   a.depth = out->depth;

@@ -292,9 +292,17 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                            hipStream_t s);
 
 
-// Tile order for the raster launches: tiles by descending list length
-// (longest first), ties in tile order.  keys/order are double buffers of
-// n_tiles words; returns the buffer index holding the order.
+// Raster launch order.  The batch's tiles (global id order: view-major,
+// row-major) are cut into kXcds contiguous bands of tile_band(n) tiles, one
+// per XCD: the dispatcher hands consecutive blocks to the XCDs in turn, so
+// block b runs on XCD b % kXcds, and it takes the (b / kXcds)-th tile of
+// band b % kXcds.  Each XCD's L2 then holds the splats and gradient records
+// of one spatially coherent band.  Inside a band, tiles go by descending list
+// length (longest first), ties in tile order.  keys/order are double
+// buffers of n_tiles words; returns the buffer index holding the order.
+constexpr int kXcds = 8;
+constexpr int kTileOrderBits = 16 + 3;   // band (3 bits) above the inverted list length
+inline uint32_t tile_band(uint32_t n_tiles) { return (n_tiles + kXcds - 1) / kXcds; }
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
                       uint32_t* order[2], uint32_t* hist, hipStream_t s);
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
@@ -306,8 +314,9 @@ struct RasterArgs {
   const Splat* splats;
   const uint32_t* vals;
   const uint2* ranges;
-  const uint32_t* order;       // launch position -> tile id
+  const uint32_t* order;       // position in the launch order -> tile id
   uint32_t n_tiles;
+  uint32_t band;               // tiles per XCD band (tile_band)
   uint32_t n_slots;            // capacity of the splat table (slot bound)
   float* rgb;
   float* depth;

@@ -566,23 +566,56 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
 // Weight gradients on MFMA: dW1 = Z0^T dZ1 (36 x 32) and dW2 = Z1^T dZ2
 // (32 x 110), reductions over the rows.  Each block (one wave) owns a
 // contiguous chunk of rows and walks it 32 rows (one MFMA k-step) at a
-// time: the chunk's z0, z1, dz1 and dz2 are split into three bf16 terms
-// (h + m + l, as in the forward decode) and staged transposed in LDS, and
-// the six products h*h, h*m, m*h, h*l, l*h, m*m (the dropped ones are below
-// 2^-26 relative) accumulate in fp32.  The biases' gradients are plain
-// column sums.  Every block writes one partial of 4814 values; a second
-// kernel adds the partials in a fixed order (deterministic).
-constexpr int kRedBlocks = 256;
+// time: the chunk's z0, z1, dz1 and dz2 are staged transposed in LDS as
+// float32, and each fragment is split on load into three bf16 terms
+// (h + m + l, as in the forward decode); the six products h*h, h*m, m*h,
+// h*l, l*h, m*m (the dropped ones are below 2^-26 relative) accumulate in
+// fp32.  The biases' gradients are column sums of the staged values.  Every
+// block writes one partial of 4814 values; k_wgrad_final adds the partials
+// in a fixed order (deterministic).
+constexpr int kRedBlocks = 1024;
 constexpr int kWR = 32;          // rows per MFMA k-step
 constexpr int kM1 = 48;          // dW1 rows (36 padded)
 constexpr int kN2w = 112;        // dW2 columns (110 padded)
 
 struct WgradLds {
-  uint16_t z0t[3][kM1][kWR];     // A of dW1: (i, r) per split term
-  uint16_t dz1t[3][kHid][kWR];   // B of dW1: (j, r)
-  uint16_t z1t[3][kHid][kWR];    // A of dW2: (j, r)
-  uint16_t dz2t[3][kN2w][kWR];   // B of dW2: (c, r)
+  float z0t[kM1][kWR + 4];       // A of dW1: (i, r); rows padded against bank conflicts
+  float dz1t[kHid][kWR + 4];     // B of dW1: (j, r)
+  float z1t[kHid][kWR + 4];      // A of dW2: (j, r)
+  float dz2t[kN2w][kWR + 4];     // B of dW2: (c, r)
 };
+
+struct Split8 {
+  bf16x8_t t[3];
+};
+
+// 8 consecutive float32 -> three bf16x8 terms h, m, l
+__device__ __forceinline__ Split8 split8(const float* p) {
+  Split8 o;
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint16_t h, m, l;
+    split3(v[i], h, m, l);
+    o.t[0][i] = __builtin_bit_cast(__bf16, h);
+    o.t[1][i] = __builtin_bit_cast(__bf16, m);
+    o.t[2][i] = __builtin_bit_cast(__bf16, l);
+  }
+  return o;
+}
+
+// the six split products (A term, B term) kept
+__device__ __forceinline__ f32x4_t mfma_split6(const Split8& A, const Split8& B, f32x4_t acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[0], B.t[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[0], B.t[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[1], B.t[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[0], B.t[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[2], B.t[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[1], B.t[1], acc, 0, 0, 0);
+  return acc;
+}
 
 __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scratch,
                                                   const Counters* ctr,
@@ -604,71 +637,52 @@ __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scr
     for (int t = 0; t < 7; ++t) acc2[m][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   // bias gradients: lane owns columns lane, lane + 64, lane + 128 of [dz1 | dz2]
   float bsum[3] = {0.f, 0.f, 0.f};
+  // zero the padding rows once (never written by the staging)
+  for (int e = lane; e < (kM1 - kIn) * kWR; e += 64) L.z0t[kIn + e / kWR][e % kWR] = 0.0f;
+  for (int e = lane; e < (kN2w - kOut) * kWR; e += 64) L.dz2t[kOut + e / kWR][e % kWR] = 0.0f;
 
   for (uint64_t base = b0; base < b1; base += kWR) {
     const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
-    const float* src = scratch + base * kRowScratch;
-    // stage: element e of the chunk is (row e / kRowScratch, value e % kRowScratch)
-    for (int e = lane; e < kWR * kRowScratch; e += 64) {
-      const int r = e / kRowScratch, q = e - r * kRowScratch;
-      const float x = r < nr ? src[e] : 0.0f;
-      uint16_t h, m, l;
-      split3(x, h, m, l);
-      if (q < kIn) {
-        L.z0t[0][q][r] = h; L.z0t[1][q][r] = m; L.z0t[2][q][r] = l;
-      } else if (q < kIn + kHid) {
-        const int j = q - kIn;
-        L.z1t[0][j][r] = h; L.z1t[1][j][r] = m; L.z1t[2][j][r] = l;
-      } else if (q < kIn + 2 * kHid) {
-        const int j = q - kIn - kHid;
-        L.dz1t[0][j][r] = h; L.dz1t[1][j][r] = m; L.dz1t[2][j][r] = l;
-      } else {
-        const int c = q - kIn - 2 * kHid;
-        L.dz2t[0][c][r] = h; L.dz2t[1][c][r] = m; L.dz2t[2][c][r] = l;
+    const float2* src = reinterpret_cast<const float2*>(scratch + base * kRowScratch);
+    // stage: element pair e of the chunk holds values 2e, 2e + 1 (a row has an
+    // even count, so a pair never straddles two rows)
+    constexpr int kPairs = kWR * kRowScratch / 2;
+#pragma unroll 4
+    for (int e = lane; e < kPairs; e += 64) {
+      const int r = (2 * e) / kRowScratch, q0 = 2 * e - r * kRowScratch;
+      const float2 x = r < nr ? src[e] : float2{0.0f, 0.0f};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = q0 + h;
+        const float v = h ? x.y : x.x;
+        if (q < kIn) L.z0t[q][r] = v;
+        else if (q < kIn + kHid) L.z1t[q - kIn][r] = v;
+        else if (q < kIn + 2 * kHid) L.dz1t[q - kIn - kHid][r] = v;
+        else L.dz2t[q - kIn - 2 * kHid][r] = v;
       }
     }
-    for (int e = lane; e < 3 * (kM1 - kIn) * kWR; e += 64) {      // zero padding rows of z0t
-      const int t = e / ((kM1 - kIn) * kWR), rem = e % ((kM1 - kIn) * kWR);
-      L.z0t[t][kIn + rem / kWR][rem % kWR] = 0;
-    }
-    for (int e = lane; e < 3 * (kN2w - kOut) * kWR; e += 64) {    // and padding columns of dz2t
-      const int t = e / ((kN2w - kOut) * kWR), rem = e % ((kN2w - kOut) * kWR);
-      L.dz2t[t][kOut + rem / kWR][rem % kWR] = 0;
-    }
+    __syncthreads();
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       const int c = lane + 64 * cc;
       if (c < kHid + kOut) {
-        const int off = kIn + kHid + c;
+        const float* row = c < kHid ? L.dz1t[c] : L.dz2t[c - kHid];
         float sum = 0.0f;
-        for (int r = 0; r < nr; ++r) sum += src[(size_t)r * kRowScratch + off];
+        for (int r = 0; r < kWR; ++r) sum += row[r];
         bsum[cc] += sum;
       }
     }
-    __syncthreads();
-    // six split products (ta, tb): the A term index and the B term index
 #pragma unroll
-    for (int pr = 0; pr < 6; ++pr) {
-      const int ta = pr == 2 ? 1 : (pr == 4 ? 2 : (pr == 5 ? 1 : 0));
-      const int tb = pr == 1 ? 1 : (pr == 3 ? 2 : (pr == 5 ? 1 : 0));
+    for (int t = 0; t < 2; ++t) {
+      const Split8 bv = split8(&L.dz1t[t * 16 + col][kq]);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const bf16x8_t bv = load8(&L.dz1t[tb][t * 16 + col][kq]);
+      for (int m = 0; m < 3; ++m) acc1[m][t] = mfma_split6(split8(&L.z0t[m * 16 + col][kq]), bv, acc1[m][t]);
+    }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const bf16x8_t av = load8(&L.z0t[ta][m * 16 + col][kq]);
-          acc1[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc1[m][t], 0, 0, 0);
-        }
-      }
+    for (int m = 0; m < 2; ++m) {
+      const Split8 av = split8(&L.z1t[m * 16 + col][kq]);
 #pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const bf16x8_t bv = load8(&L.dz2t[tb][t * 16 + col][kq]);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const bf16x8_t av = load8(&L.z1t[ta][m * 16 + col][kq]);
-          acc2[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc2[m][t], 0, 0, 0);
-        }
-      }
+      for (int t = 0; t < 7; ++t) acc2[m][t] = mfma_split6(av, split8(&L.dz2t[t * 16 + col][kq]), acc2[m][t]);
     }
     __syncthreads();
   }
@@ -699,16 +713,27 @@ __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scr
   }
 }
 
+// Sum of the block partials: a block reduces 32 outputs; thread (o, g) adds
+// partials g, g + 8, g + 16, ... of output o, then the 8 group sums are
+// added in group order (fixed order, deterministic).
 __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ partial, int nb,
                                                      cgx_grads gr) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= kWGrad) return;
+  __shared__ float red[8][33];
+  const int ol = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int o = blockIdx.x * 32 + ol;
   float s = 0.0f;
-  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * kWGrad + o];
-  if (o < kIn * kHid) gr.W1[o] = s;
-  else if (o < kIn * kHid + kHid * kOut) gr.W2[o - kIn * kHid] = s;
-  else if (o < kIn * kHid + kHid * kOut + kHid) gr.b1[o - kIn * kHid - kHid * kOut] = s;
-  else gr.b2[o - kIn * kHid - kHid * kOut - kHid] = s;
+  if (o < kWGrad)
+    for (int b = g; b < nb; b += 8) s += partial[(size_t)b * kWGrad + o];
+  red[g][ol] = s;
+  __syncthreads();
+  if (g != 0 || o >= kWGrad) return;
+  float t = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t += red[k][ol];
+  if (o < kIn * kHid) gr.W1[o] = t;
+  else if (o < kIn * kHid + kHid * kOut) gr.W2[o - kIn * kHid] = t;
+  else if (o < kIn * kHid + kHid * kOut + kHid) gr.b1[o - kIn * kHid - kHid * kOut] = t;
+  else gr.b2[o - kIn * kHid - kHid * kOut - kHid] = t;
 }
 
 size_t anchor_scratch_bytes(int64_t max_rows) {
@@ -736,7 +761,7 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
                        scratch, g);
   hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(64), 0, s, (const float*)scratch, ctr,
                      partial);
-  hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 32)), dim3(256), 0, s,
                      (const float*)partial, kRedBlocks, g);
 }
 

@@ -35,6 +35,15 @@ __device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
   d[3] = e;
 }
 
+// tile of this block: block b runs on XCD b % kXcds and takes the next tile
+// of that XCD's band of the launch order (n_tiles when past the band's end)
+__device__ __forceinline__ uint32_t launch_tile(const RasterArgs& a) {
+  const uint32_t x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  const uint32_t lo = x * a.band;
+  const uint32_t hi = lo + a.band < a.n_tiles ? lo + a.band : a.n_tiles;
+  return lo + i < hi ? a.order[lo + i] : a.n_tiles;
+}
+
 // 8 x 8 sub-block k of a tile: column k % (TW / 8), row k / (TW / 8)
 template <int TW>
 __device__ __forceinline__ int sub_x0(int tx, int k) { return tx * TW + (k % (TW / 8)) * 8; }
@@ -58,7 +67,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
   __shared__ Splat sh[kWave];
-  const uint32_t tile = a.order[blockIdx.x];
+  const uint32_t tile = launch_tile(a);
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
   __shared__ Splat sh[kWave];
   __shared__ uint32_t sslot[kWave];
-  const uint32_t tile = a.order[blockIdx.x];
+  const uint32_t tile = launch_tile(a);
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
@@ -352,11 +361,11 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
 
 template <int TW, int TH>
 static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(kXcds * a.band), dim3(kWave), 0, s, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(kXcds * a.band), dim3(kWave), 0, s, a);
 }
 
 void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s) {

@@ -449,16 +449,16 @@ void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Count
 namespace cgx {
 
 // ---------------------------------------------------------------------
-// raster launch order: longest tile lists first, so that the long tiles
-// start early and the tail of the launch holds only short ones
+// raster launch order: one contiguous band of tiles per XCD, longest tile
+// lists first inside each band
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
-                                                   uint32_t* __restrict__ keys,
+                                                   uint32_t band, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ order) {
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
     const uint2 r = ranges[t];
     const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
-    keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
+    keys[t] = ((t / band) << 16) | (0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu));
     order[t] = t;
   }
 }
@@ -466,8 +466,9 @@ __global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ran
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
                       uint32_t* order[2], uint32_t* hist, hipStream_t s) {
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_tiles, 256), 4096));
-  hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(256), 0, s, ranges, n_tiles, keys[0], order[0]);
-  return launch_sort_kv(keys, order, &ctr->n_tiles, n_tiles, hist, 16, s);
+  hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(256), 0, s, ranges, n_tiles,
+                     std::max<uint32_t>(tile_band(n_tiles), 1), keys[0], order[0]);
+  return launch_sort_kv(keys, order, &ctr->n_tiles, n_tiles, hist, kTileOrderBits, s);
 }
 
 }  // namespace cgx

@@ -131,6 +131,26 @@ def _sampled_sensitivity_anchor(wl, keep, og):
             for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
 
 
+def _sens_two_draws(render, scene, views, keep, og, keys, ref):
+    """Conditioning of each gradient element: the larger response of the
+    oracle's gradient to two independent float32-size perturbations of every
+    float input (one draw can miss an element's worst direction)."""
+    import copy
+
+    from tests.parity import _perturbed
+    out = None
+    for seed in (4321, 8765):
+        rng = np.random.default_rng(seed)
+        sc = copy.copy(scene)
+        for k in keys:
+            setattr(sc, k, _perturbed(getattr(scene, k), rng))
+        r1 = render(sc, views, keep_tiles=keep)
+        g1, _ = pipeline.backward(r1, og, sc)
+        d = {k: np.abs(ref[k] - g1[k]) for k in ref if k != "frag"}
+        out = d if out is None else {k: np.maximum(out[k], d[k]) for k in d}
+    return out
+
+
 def test_c1_full_size_sampled_tiles():
     print("case: C1 full size (1M Gaussians, SH3, 1080p), 20 sampled tiles", flush=True)
     from paper_2503_23044_amd import render
@@ -152,17 +172,11 @@ def test_c1_full_size_sampled_tiles():
     ref, _ = pipeline.backward(r, og, wl.scene)
     gr = rd.backward(wl.views, sc, out, _to_device(og))
     torch.cuda.synchronize()
-    import copy
-
-    from tests.parity import _perturbed, _without_fragile
-    rng2 = np.random.default_rng(4321)
-    sc2 = copy.copy(wl.scene)
-    for k in ("means", "scales", "quats", "opacity", "sh"):
-        setattr(sc2, k, _perturbed(getattr(wl.scene, k), rng2))
-    r1 = pipeline.render_explicit(sc2, wl.views, keep_tiles=keep)
-    g1, _ = pipeline.backward(r1, og, sc2)
+    from tests.parity import _without_fragile
+    sens = _sens_two_draws(pipeline.render_explicit, wl.scene, wl.views, keep, og,
+                           ("means", "scales", "quats", "opacity", "sh"), ref)
     g2, _ = pipeline.backward(r, _without_fragile(r, og), wl.scene)
     fa = ref["frag"]
     for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)):
         check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
-                   dict(sens=np.abs(ref[k] - g1[k]), frag=np.abs(ref[k] - g2[k])))
+                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))

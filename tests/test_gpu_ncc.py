@@ -66,7 +66,10 @@ def test_ncc_kernel_on_oracle_images():
     n_frag = int(info["fragile"].sum())
     scale = weight / (len(wl.views) // 2 * centres.shape[1])
     assert abs(loss.item() - loss_ref) <= 1e-5 * weight + 2 * scale * n_frag, (loss.item(), loss_ref)
-    check_close("d_rgb (NCC)", g.cpu().numpy(), _to_planar(g_ref), _fragile_pixels(r32, centres, info))
+    # the two terms of d NCC / d a nearly cancel when NCC is close to 1: the
+    # float32 error follows the sum of |terms| (as for the normal map)
+    check_close("d_rgb (NCC)", g.cpu().numpy(), _to_planar(g_ref), _fragile_pixels(r32, centres, info),
+                mag=_to_planar(info["gmag"]))
     # accumulation: a second call adds the same amounts
     g2, loss2 = rd.ncc_loss(wl.views, imgs, torch.as_tensor(centres), weight, grad_rgb=g.clone(), loss=loss.clone())
     torch.cuda.synchronize()
