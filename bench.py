@@ -84,6 +84,8 @@ def gpu_leg(args, wl):
     info0 = dict(rd.last_info)
     log(f"[bench] rows {info0['n_rows']} splats {info0['n_splats']} pairs {info0['n_pairs']} "
         f"loss {info0['loss']:.6f} workspace {rd.ws.numel() / 2**30:.2f} GiB")
+    log(f"[bench] per step: list entries walked fwd {info0['entries_fwd']} bwd {info0['entries_bwd']}, "
+        f"opacity evaluations fwd {info0['evals_fwd']} bwd {info0['evals_bwd']}")
     for _ in range(args.warmup):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()

@@ -32,6 +32,7 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
 DHAT_GUARD = 1e-3
+DHAT_COND = 20.0
 FRAG_ALPHA = 1e-5
 FRAG_T = 1e-4
 FRAG_SIGN = 1e-5
@@ -223,6 +224,11 @@ def composite_tile(S, ent, I, J, view_arrays):
     dhat = np.where(keep, D / np.where(keep, sdot, 1.0), 0.0)
     frag |= (acc > 0) & (np.abs(sdot - DHAT_GUARD * acc)
                          < 10 * FRAG_ALPHA * np.maximum(np.abs(sdot), DHAT_GUARD * acc))
+    # grazing incidence: s = -N . ray cancels terms DHAT_COND times its size;
+    # float32 then loses more than four bits of s, and D^'s adjoint (1/s^2)
+    # doubles that, so the pixel's gradients are not resolved to 1e-4
+    sabs = np.sum(Nabs * np.abs(ray), 1)
+    frag_grad = frag_grad | (keep & (sabs > DHAT_COND * np.abs(sdot)))
     return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, T=T_final, last=last,
                 walked=walked, frag=frag, frag_grad=frag_grad | frag, inc=inc,
                 keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)

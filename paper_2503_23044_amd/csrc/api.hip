@@ -194,6 +194,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
     L.tkey[b] = take(sizeof(uint32_t) * (size_t)tiles);
     L.tord[b] = take(sizeof(uint32_t) * (size_t)tiles);
   }
+  L.bstart = take(sizeof(uint32_t) * ((size_t)L.max_pairs / kDupPairs + 2));
   L.px_T = take(sizeof(float) * (size_t)px);
   L.px_last = take(sizeof(uint32_t) * (size_t)px);
   L.sgrad = take(sizeof(SplatGrad) * (size_t)L.max_splats);
@@ -256,6 +257,7 @@ struct Ptrs {
   uint2* ranges;
   uint32_t* tkey[2];
   uint32_t* tord[2];
+  uint32_t* bstart;
   float* px_T;
   uint32_t* px_last;
   SplatGrad* sgrad;
@@ -285,6 +287,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
     p.tkey[b] = at<uint32_t>(ws, L.tkey[b]);
     p.tord[b] = at<uint32_t>(ws, L.tord[b]);
   }
+  p.bstart = at<uint32_t>(ws, L.bstart);
   p.px_T = at<float>(ws, L.px_T);
   p.px_last = at<uint32_t>(ws, L.px_last);
   p.sgrad = at<SplatGrad>(ws, L.sgrad);
@@ -354,8 +357,9 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   // pair offsets in depth order, pair emission, then the tile-id bits
   phase_begin(c, CGX_PHASE_DUPLICATE, st);
   launch_scan_counts(P.counts, P.vslot[vb], P.offsets, P.part, &P.ctr->n_visible, n_slots,
-                     (uint32_t)L.max_pairs, P.ctr, st);
-  launch_emit_pairs(P.views, P.splats, P.vslot[vb], P.offsets, P.ctr, expl ? 1 : s->an.n_offsets,
+                     (uint32_t)L.max_pairs, P.ctr, P.bstart, st);
+  launch_emit_pairs(P.views, P.splats, P.vslot[vb], P.offsets, P.bstart, P.ctr,
+                    expl ? 1 : s->an.n_offsets,
                     expl ? nullptr : P.rows,
                     expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
                     (uint32_t)L.max_pairs, P.pkey[0], P.pval[0], st);
@@ -381,7 +385,6 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.ranges = P.ranges;
   a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
-  a.band = tile_band((uint32_t)L.n_tiles);
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;
   a.depth = out->depth;
@@ -439,7 +442,6 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   a.ranges = P.ranges;
   a.order = P.tord[L.order_buf];
   a.n_tiles = (uint32_t)L.n_tiles;
-  a.band = tile_band((uint32_t)L.n_tiles);
   a.n_slots = (uint32_t)L.max_splats;
   a.rgb = out->rgb;
   a.depth = out->depth;

@@ -26,7 +26,7 @@ namespace cgx {
 
 constexpr int kWave = 64;
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
-constexpr int kSortBlocks = 512;    // fixed grid of the radix-sort passes
+constexpr int kSortBlocks = 2048;   // largest grid of a radix-sort pass
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;       // keys per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -119,6 +119,7 @@ struct Layout {
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
   size_t tkey[2], tord[2];     // raster launch order: length keys and tile ids
+  size_t bstart;               // first visible splat of each pair-emission block
   size_t total;
   int64_t max_rows, max_splats, max_pairs;
   int64_t n_tiles, n_pixels;
@@ -258,17 +259,23 @@ void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStrea
 void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s);
 
+// Pairs handled by one block of the pair emission.
+constexpr int kDupPairs = 1024;
+
 // device-wide exclusive scan of counts[idx[i]] (idx may be NULL) for
 // i < n (n from *n_dev if non-null, else n_host) into offsets clamped to
-// cap; the total becomes the pair count (overflow bit 2 above cap)
+// cap; the total becomes the pair count (overflow bit 2 above cap).  With
+// bstart, also records for every emission block b (first pair b * kDupPairs
+// below cap) the index i whose pair range holds that first pair.
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
-                        uint32_t cap, Counters* ctr, hipStream_t s);
+                        uint32_t cap, Counters* ctr, uint32_t* bstart, hipStream_t s);
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s);
 void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
-                       const uint32_t* voff, const Counters* ctr, int n_per_row, const int2* rows,
+                       const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
+                       int n_per_row, const int2* rows,
                        uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
                        uint32_t* pval, hipStream_t s);
 void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
@@ -292,17 +299,11 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                            hipStream_t s);
 
 
-// Raster launch order.  The batch's tiles (global id order: view-major,
-// row-major) are cut into kXcds contiguous bands of tile_band(n) tiles, one
-// per XCD: the dispatcher hands consecutive blocks to the XCDs in turn, so
-// block b runs on XCD b % kXcds, and it takes the (b / kXcds)-th tile of
-// band b % kXcds.  Each XCD's L2 then holds the splats and gradient records
-// of one spatially coherent band.  Inside a band, tiles go by descending list
-// length (longest first), ties in tile order.  keys/order are double
-// buffers of n_tiles words; returns the buffer index holding the order.
-constexpr int kXcds = 8;
-constexpr int kTileOrderBits = 16 + 3;   // band (3 bits) above the inverted list length
-inline uint32_t tile_band(uint32_t n_tiles) { return (n_tiles + kXcds - 1) / kXcds; }
+// Raster launch order: tiles by descending list length (longest first),
+// ties in tile order; the raster kernels map block i to the i-th tile of it.
+// keys/order are double buffers of n_tiles words; returns the buffer index
+// holding the order.
+constexpr int kTileOrderBits = 16;
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
                       uint32_t* order[2], uint32_t* hist, hipStream_t s);
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
@@ -316,7 +317,6 @@ struct RasterArgs {
   const uint2* ranges;
   const uint32_t* order;       // position in the launch order -> tile id
   uint32_t n_tiles;
-  uint32_t band;               // tiles per XCD band (tile_band)
   uint32_t n_slots;            // capacity of the splat table (slot bound)
   float* rgb;
   float* depth;

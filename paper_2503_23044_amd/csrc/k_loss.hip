@@ -12,7 +12,9 @@
 // reference frame, H = K_s (R_rel - t_rel n^T / d) K_r^-1 on pixel centres.
 // The source intensity (mean of RGB) is sampled bilinearly; sums over the
 // patch are wave reductions; each lane adds its pixel's gradient with
-// float atomics (patches may overlap).  A patch is skipped when any pixel
+// float atomics (patches may overlap).  The per-patch arithmetic is
+// float64: a low-contrast patch subtracts nearly equal intensities, and the
+// work (a few thousand patches) is negligible next to the rasterizer.  A patch is skipped when any pixel
 // leaves the reference image, d <= 0, a warped centre falls behind the
 // source camera or outside its sampling range [0, W-1] x [0, H-1].
 #include "cgx_common.h"
@@ -21,15 +23,16 @@ namespace cgx {
 
 constexpr int kPatch = 7;
 constexpr int kPatchPx = kPatch * kPatch;
-constexpr float kNccEps = 1e-8f;
+constexpr double kNccEps = 1e-8;
 
-__device__ __forceinline__ float wave_sum(float v) {
+__device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
 
-__device__ __forceinline__ float gray_at(const float* rgb, size_t pv, uint32_t HW, uint32_t p) {
-  return (rgb[3 * pv + p] + rgb[3 * pv + HW + p] + rgb[3 * pv + 2 * HW + p]) * (1.0f / 3.0f);
+__device__ __forceinline__ double gray_at(const float* rgb, size_t pv, uint32_t HW, uint32_t p) {
+  return ((double)rgb[3 * pv + p] + (double)rgb[3 * pv + HW + p] + (double)rgb[3 * pv + 2 * HW + p]) /
+         3.0;
 }
 
 __global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ views,
@@ -88,28 +91,28 @@ __global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ 
   }
   if (__ballot(mine && !ok) != 0) return;
 
-  float a = 0.0f, b = 0.0f;
+  double a = 0.0, b = 0.0;
   if (mine) {
     a = gray_at(rgb, pvr, HWr, (uint32_t)y * (uint32_t)Vr.W + (uint32_t)x);
     int x0 = (int)floor(sx), y0 = (int)floor(sy);
     x0 = x0 < Vs.W - 2 ? x0 : Vs.W - 2;
     y0 = y0 < Vs.H - 2 ? y0 : Vs.H - 2;
-    const float fx = (float)(sx - x0), fy = (float)(sy - y0);
+    const double fx = sx - x0, fy = sy - y0;
     const uint32_t p00 = (uint32_t)y0 * (uint32_t)Vs.W + (uint32_t)x0;
-    const float g00 = gray_at(rgb, pvs, HWs, p00), g01 = gray_at(rgb, pvs, HWs, p00 + 1);
-    const float g10 = gray_at(rgb, pvs, HWs, p00 + Vs.W), g11 = gray_at(rgb, pvs, HWs, p00 + Vs.W + 1);
-    b = (1.0f - fy) * ((1.0f - fx) * g00 + fx * g01) + fy * ((1.0f - fx) * g10 + fx * g11);
+    const double g00 = gray_at(rgb, pvs, HWs, p00), g01 = gray_at(rgb, pvs, HWs, p00 + 1);
+    const double g10 = gray_at(rgb, pvs, HWs, p00 + Vs.W), g11 = gray_at(rgb, pvs, HWs, p00 + Vs.W + 1);
+    b = (1.0 - fy) * ((1.0 - fx) * g00 + fx * g01) + fy * ((1.0 - fx) * g10 + fx * g11);
   }
-  const float ma = wave_sum(a) * (1.0f / kPatchPx), mb = wave_sum(b) * (1.0f / kPatchPx);
-  const float A = mine ? a - ma : 0.0f, Bc = mine ? b - mb : 0.0f;
-  const float sab = wave_sum(A * Bc), saa = wave_sum(A * A), sbb = wave_sum(Bc * Bc);
-  const float den = sqrtf(saa * sbb + kNccEps);
-  const float ncc = sab / den;
-  if (lane == 0 && loss) atomic_add_f32(loss, scale * (1.0f - ncc));
+  const double ma = wave_sum(a) / kPatchPx, mb = wave_sum(b) / kPatchPx;
+  const double A = mine ? a - ma : 0.0, Bc = mine ? b - mb : 0.0;
+  const double sab = wave_sum(A * Bc), saa = wave_sum(A * A), sbb = wave_sum(Bc * Bc);
+  const double den = sqrt(saa * sbb + kNccEps);
+  const double ncc = sab / den;
+  if (lane == 0 && loss) atomic_add_f32(loss, (float)(scale * (1.0 - ncc)));
   if (mine) {
     // d NCC / d a_j = B_j / den - sab sbb A_j / den^3 (the B's sum to zero)
-    const float dn = Bc / den - sab * sbb * A / (den * den * den);
-    const float ga = -scale * dn * (1.0f / 3.0f);
+    const double dn = Bc / den - sab * sbb * A / (den * den * den);
+    const float ga = (float)(-(double)scale * dn / 3.0);
     if (ga != 0.0f) {
       const uint32_t p = (uint32_t)y * (uint32_t)Vr.W + (uint32_t)x;
       atomic_add_f32(grad_rgb + 3 * pvr + p, ga);

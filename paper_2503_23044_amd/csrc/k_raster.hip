@@ -35,13 +35,9 @@ __device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
   d[3] = e;
 }
 
-// tile of this block: block b runs on XCD b % kXcds and takes the next tile
-// of that XCD's band of the launch order (n_tiles when past the band's end)
+// tile of this block in the launch order
 __device__ __forceinline__ uint32_t launch_tile(const RasterArgs& a) {
-  const uint32_t x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
-  const uint32_t lo = x * a.band;
-  const uint32_t hi = lo + a.band < a.n_tiles ? lo + a.band : a.n_tiles;
-  return lo + i < hi ? a.order[lo + i] : a.n_tiles;
+  return blockIdx.x < a.n_tiles ? a.order[blockIdx.x] : a.n_tiles;
 }
 
 // 8 x 8 sub-block k of a tile: column k % (TW / 8), row k / (TW / 8)
@@ -361,11 +357,11 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
 
 template <int TW, int TH>
 static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(kXcds * a.band), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(kXcds * a.band), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
 }
 
 void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s) {

@@ -50,8 +50,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(const uint32_t* _
   __syncthreads();
   uint32_t b0, b1;
   sort_chunk(clamp_count(n_dev, cap), b0, b1);
-  for (uint32_t i = b0 + threadIdx.x; i < b1; i += kSortThreads)
-    atomicAdd(&h[wave][(keys[i] >> shift) & (R - 1)], 1u);
+  // kSortItems keys per thread per step, loads issued before the LDS adds
+  for (uint32_t base = b0; base < b1; base += kSortTile) {
+    uint32_t d[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+      const uint32_t i = base + it * kSortThreads + threadIdx.x;
+      d[it] = i < b1 ? (keys[i] >> shift) & (R - 1) : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it)
+      if (d[it] != 0xFFFFFFFFu) atomicAdd(&h[wave][d[it]], 1u);
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < R; d += kSortThreads) {
     uint32_t s = 0;
@@ -240,10 +250,14 @@ static void one_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vou
                      const uint32_t* n_dev, uint32_t cap, uint32_t* hist, int shift, hipStream_t s) {
   constexpr int R = 1 << BITS;
   uint32_t* totals = hist + (size_t)R * kSortBlocks;
-  hipLaunchKernelGGL(k_sort_upsweep<BITS>, dim3(kSortBlocks), dim3(kSortThreads), 0, s,
+  // grid sized to the capacity: about 8 tiles of 2048 keys per block for
+  // large sorts (several blocks per CU to hide latency), fewer blocks for
+  // small ones; the count itself is read on the device
+  const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(kSortBlocks, div_up(cap, 4 * kSortTile)));
+  hipLaunchKernelGGL(k_sort_upsweep<BITS>, dim3(nb), dim3(kSortThreads), 0, s,
                      (const uint32_t*)kin, n_dev, cap, hist, shift);
-  hipLaunchKernelGGL(k_sort_scan_digit, dim3(R), dim3(256), 0, s, hist, kSortBlocks, totals);
-  hipLaunchKernelGGL(k_sort_downsweep<BITS>, dim3(kSortBlocks), dim3(kSortThreads), 0, s,
+  hipLaunchKernelGGL(k_sort_scan_digit, dim3(R), dim3(256), 0, s, hist, (int)nb, totals);
+  hipLaunchKernelGGL(k_sort_downsweep<BITS>, dim3(nb), dim3(kSortThreads), 0, s,
                      (const uint32_t*)kin, (const uint32_t*)vin, kout, vout,
                      (const uint32_t*)hist, (const uint32_t*)totals, n_dev, cap, shift);
 }
@@ -359,41 +373,29 @@ void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const 
 }
 
 // ---------------------------------------------------------------------
-// 3: one thread per pair.  A block covers 1024 consecutive pairs; the
-// visible splats they belong to (at most 1025, every count is >= 1) are
-// found by two binary searches and their offsets staged in LDS, where each
-// pair finds its splat.
+// 3: one thread per pair.  A block covers kDupPairs consecutive pairs; the
+// visible splats they belong to run from bstart[b] (recorded by the offset
+// scan) to bstart[b + 1] (or the last visible splat), at most
+// kDupPairs + 2 since every count is >= 1; their offsets are staged in LDS,
+// where each pair finds its splat by binary search.
 // ---------------------------------------------------------------------
-constexpr int kDupPairs = 1024;
-
-__device__ __forceinline__ uint32_t upper_bound_g(const uint32_t* a, uint32_t n, uint32_t x) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(256) void k_emit_pairs(
     const ViewDev* __restrict__ views, const Splat* __restrict__ splats,
-    const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff, const Counters* ctr,
-    int n_per_row, const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
+    const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff,
+    const uint32_t* __restrict__ bstart, const Counters* ctr, int n_per_row,
+    const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-  __shared__ uint32_t s_off[kDupPairs + 1];
-  __shared__ uint32_t s_j[2];
+  __shared__ uint32_t s_off[kDupPairs + 2];
   const uint32_t P = ctr->n_pairs;
   const uint32_t nv = ctr->n_visible;
   const uint32_t p0 = blockIdx.x * kDupPairs;
-  if (p0 >= P) return;
+  if (p0 >= P || nv == 0) return;
   const uint32_t p1 = p0 + kDupPairs < P ? p0 + kDupPairs : P;
-  if (threadIdx.x == 0) s_j[0] = upper_bound_g(voff, nv, p0) - 1;
-  if (threadIdx.x == 1) s_j[1] = upper_bound_g(voff, nv, p1 - 1) - 1;
-  __syncthreads();
-  const uint32_t j0 = s_j[0], j1 = s_j[1];
-  // every visible splat has at least one pair, so m <= kDupPairs + 1
-  const uint32_t m = (j1 - j0 + 1) <= (uint32_t)kDupPairs + 1 ? (j1 - j0 + 1) : (uint32_t)kDupPairs + 1;
+  const uint32_t j0 = bstart[blockIdx.x];
+  const uint32_t j1r = p1 < P ? bstart[blockIdx.x + 1] : nv - 1;
+  const uint32_t j1 = j1r < nv ? j1r : nv - 1;
+  const uint32_t span = j1 >= j0 ? j1 - j0 + 1 : 1;
+  const uint32_t m = span <= (uint32_t)kDupPairs + 2 ? span : (uint32_t)kDupPairs + 2;
   for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) s_off[t] = voff[j0 + t];
   __syncthreads();
   for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
       if (s_off[mid] <= i) lo = mid + 1;
       else hi = mid;
     }
-    const uint32_t jl = lo - 1;
+    const uint32_t jl = lo > 0 ? lo - 1 : 0;
     const uint32_t slot = vslot[j0 + jl];
     const uint32_t k = i - s_off[jl];
     const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
@@ -420,12 +422,12 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
 }
 
 void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
-                       const uint32_t* voff, const Counters* ctr, int n_per_row, const int2* rows,
-                       uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
-                       uint32_t* pval, hipStream_t s) {
+                       const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
+                       int n_per_row, const int2* rows, uint32_t N_explicit, int tw, int th,
+                       uint32_t cap, uint32_t* pkey, uint32_t* pval, hipStream_t s) {
   const uint32_t blocks = std::max<uint32_t>(1, div_up(cap, kDupPairs));
-  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, vslot, voff, ctr,
-                     n_per_row, rows, N_explicit, tw, th, pkey, pval);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, vslot, voff,
+                     bstart, ctr, n_per_row, rows, N_explicit, tw, th, pkey, pval);
 }
 
 // depth bits of every sorted pair (for the debug copy only)
@@ -449,16 +451,18 @@ void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Count
 namespace cgx {
 
 // ---------------------------------------------------------------------
-// raster launch order: one contiguous band of tiles per XCD, longest tile
-// lists first inside each band
+// raster launch order: longest tile lists first, so that the long tiles
+// start early and the tail of the launch holds only short ones.  (Giving
+// each XCD a spatial band of tiles cuts the backward pass's L2 misses but
+// leaves the XCDs unevenly loaded, which costs more than it saves.)
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
-                                                   uint32_t band, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ order) {
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
     const uint2 r = ranges[t];
     const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
-    keys[t] = ((t / band) << 16) | (0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu));
+    keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
     order[t] = t;
   }
 }
@@ -466,8 +470,7 @@ __global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ran
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
                       uint32_t* order[2], uint32_t* hist, hipStream_t s) {
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_tiles, 256), 4096));
-  hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(256), 0, s, ranges, n_tiles,
-                     std::max<uint32_t>(tile_band(n_tiles), 1), keys[0], order[0]);
+  hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(256), 0, s, ranges, n_tiles, keys[0], order[0]);
   return launch_sort_kv(keys, order, &ctr->n_tiles, n_tiles, hist, kTileOrderBits, s);
 }
 

@@ -106,7 +106,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, uin
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, const uint32_t* idx,
                                                     uint32_t* offsets,
                                                     const uint32_t* n_dev, uint32_t n_host,
-                                                    const unsigned long long* part, uint32_t cap) {
+                                                    const unsigned long long* part, uint32_t cap,
+                                                    uint32_t* bstart) {
   __shared__ unsigned long long lw[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -122,6 +123,12 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
     if (i < b1) {
       unsigned long long off = carry + inc - c;
       offsets[i] = (uint32_t)(off < cap ? off : cap);
+      if (bstart && c) {
+        // emission blocks whose first pair falls in [off, off + c)
+        const unsigned long long end = off + c < cap ? off + c : cap;
+        for (unsigned long long b = (off + kDupPairs - 1) / kDupPairs; b * kDupPairs < end; ++b)
+          bstart[b] = (uint32_t)i;
+      }
     }
     carry += tot;
   }
@@ -129,12 +136,12 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
 
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
-                        uint32_t cap, Counters* ctr, hipStream_t s) {
+                        uint32_t cap, Counters* ctr, uint32_t* bstart, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, n_dev,
                      n_host, part);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, part, cap, ctr);
   hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, offsets,
-                     n_dev, n_host, (const unsigned long long*)part, cap);
+                     n_dev, n_host, (const unsigned long long*)part, cap, bstart);
 }
 
 // ---------------------------------------------------------------------
