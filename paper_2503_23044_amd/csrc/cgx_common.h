@@ -28,7 +28,7 @@ constexpr int kWave = 64;
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
 constexpr int kSortBlocks = 2048;   // largest grid of a radix-sort pass
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;       // keys per thread per sort tile
+constexpr int kSortItems = 16;      // keys per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxRadixBits = 9;    // digit width bound of the LSD passes
 

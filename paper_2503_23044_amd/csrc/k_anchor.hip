@@ -445,10 +445,13 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
                                                           const SplatGrad* __restrict__ sgrad,
                                                           float* __restrict__ scratch, cgx_grads gr) {
   __shared__ DecW2 w;
+  const uint32_t n_rows = ctr->n_rows;
+  // the grid covers the row capacity: blocks past the active rows leave
+  // before staging the weights
+  if ((uint64_t)blockIdx.x * blockDim.x >= (uint64_t)n_rows * kNOff) return;
   for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x) w.W2[i] = bf16_to_f32(sc.W2[i]);
   for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
   __syncthreads();
-  const uint32_t n_rows = ctr->n_rows;
   const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = item / kNOff;
   const int k = (int)(item - r * kNOff);
@@ -516,9 +519,10 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
                                                         const Counters* ctr,
                                                         float* __restrict__ scratch, cgx_grads gr) {
   __shared__ DecW w;
+  const uint32_t n_rows = ctr->n_rows;
+  if ((uint64_t)blockIdx.x * blockDim.x >= n_rows) return;   // past the active rows
   load_weights(w, sc);
   __syncthreads();
-  const uint32_t n_rows = ctr->n_rows;
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rows) return;
   const int2 row = rows[r];

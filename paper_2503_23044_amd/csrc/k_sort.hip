@@ -16,7 +16,7 @@
 //
 // The sort itself is reduce-then-scan per pass over a fixed grid, counts
 // read on the device: per-block digit histograms, a coalesced per-digit
-// scan, and a downsweep where each 2048-key tile is ranked with wave-level
+// scan, and a downsweep where each 4096-key tile is ranked with wave-level
 // digit matching (one ballot per digit bit), staged in LDS in digit order
 // and written out in coalesced runs.
 #include "cgx_common.h"
@@ -250,10 +250,10 @@ static void one_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vou
                      const uint32_t* n_dev, uint32_t cap, uint32_t* hist, int shift, hipStream_t s) {
   constexpr int R = 1 << BITS;
   uint32_t* totals = hist + (size_t)R * kSortBlocks;
-  // grid sized to the capacity: about 8 tiles of 2048 keys per block for
-  // large sorts (several blocks per CU to hide latency), fewer blocks for
-  // small ones; the count itself is read on the device
-  const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(kSortBlocks, div_up(cap, 4 * kSortTile)));
+  // grid sized to the capacity, one sort tile per block at least, at most
+  // kSortBlocks blocks (several per CU); the count itself is read on the
+  // device
+  const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(kSortBlocks, div_up(cap, kSortTile)));
   hipLaunchKernelGGL(k_sort_upsweep<BITS>, dim3(nb), dim3(kSortThreads), 0, s,
                      (const uint32_t*)kin, n_dev, cap, hist, shift);
   hipLaunchKernelGGL(k_sort_scan_digit, dim3(R), dim3(256), 0, s, hist, (int)nb, totals);
