@@ -16,7 +16,9 @@ launch stream inside the timed region) and the FP64 oracle timed on a
 bounded sample on the host cores.
 """
 import argparse
+import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -31,7 +33,7 @@ PEAK_FP32_TFLOPS = 157.3
 # method's arithmetic (the design doc lists the terms)
 FLOPS_FWD_PER_EVAL = 29
 FLOPS_BWD_PER_EVAL = 70
-SORT_BYTES_PER_PAIR_PASS = 24     # read + write of key (8 B) and value (4 B)
+SORT_BYTES_PER_ELEM_PASS = 16     # read + write of a 32-bit key and a 32-bit value
 
 
 def parse():
@@ -40,11 +42,12 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--config", type=int, default=2)
-    p.add_argument("--tile", type=str, default="auto",
-                   help="tile shape WxH, or 'auto' to time every shape and keep the fastest")
+    p.add_argument("--tile", type=str, default="16x16",
+                   help="tile shape WxH (16x16 is the paper's patch), or 'auto' to time every "
+                        "compiled shape with the autotuner and keep the fastest")
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-tiles", type=int, default=400)
+    p.add_argument("--cpu-sample-tiles", type=int, default=1000)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
                         "for scaling hardware byte counters)")
@@ -155,6 +158,33 @@ def copy_calibration(mib):
     del src, dst
 
 
+PROFILE_BYTES = os.path.join(ROOT, "profiles", "c2_fused_step_hbm_bytes.md")
+KERNEL_SOURCES = ("paper_2503_23044_amd/csrc/k_raster.hip", "paper_2503_23044_amd/csrc/cgx_common.h")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` (e.g. 'k_raster_bwd<16, 16>') from the
+    committed FETCH_SIZE / WRITE_SIZE summary, or None when there is none or
+    it was taken from other raster sources than the ones built now."""
+    if not os.path.exists(PROFILE_BYTES):
+        return None
+    digest = kernel_source_digest()
+    with open(PROFILE_BYTES) as f:
+        for line in f:
+            m = re.match(r"traffic: kernel=(.+?) read_bytes=(\d+) write_bytes=(\d+) source=(\w+)", line.strip())
+            if m and m.group(1) == kernel and m.group(4) == digest:
+                return int(m.group(2)) + int(m.group(3))
+    return None
+
+
 def roofline(res, steps):
     info, ph = res["info"], res["phases"]
     cands = []
@@ -172,9 +202,11 @@ def roofline(res, steps):
                                       peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")))
     t, c = ph["sort"]
     if c:
-        d = t / c * 1e-3
-        passes = info.get("sort_passes", 6)
-        by = info["n_pairs"] * SORT_BYTES_PER_PAIR_PASS * passes
+        # both sorts of a step: 4 passes over the visible splats' depth keys,
+        # sort_passes over the pairs' tile ids; each pass reads and writes a
+        # key and a value
+        d = t / steps * 1e-3
+        by = SORT_BYTES_PER_ELEM_PASS * (4 * info["n_visible"] + info["sort_passes"] * info["n_pairs"])
         cands.append((t / steps, dict(kernel="sort", bound="hbm", achieved=by / d / 1e9,
                                       peak=PEAK_HBM_GBS, unit="GB/s")))
     if not cands:
@@ -182,7 +214,8 @@ def roofline(res, steps):
     cands.sort(key=lambda x: -x[0])
     r = cands[0][1]
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    tw, th = res["tile"].split("x")
+    r["traffic"] = profiled_traffic(f"k_{r['kernel']}<{tw}, {th}>") if r["kernel"].startswith("raster") else None
     return r
 
 

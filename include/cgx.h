@@ -179,8 +179,8 @@ typedef struct cgx_run_info {
   int64_t n_pixels;
   uint64_t evals_fwd;   /* (pixel, splat) opacity evaluations, forward */
   uint64_t evals_bwd;   /* (pixel, splat) opacity evaluations, backward */
-  int32_t sort_passes;  /* 8-bit radix passes of the last sort */
-  int32_t reserved2;
+  int32_t sort_passes;  /* radix passes over the pairs (tile-id digits) */
+  int32_t n_visible;    /* splats with at least one pair (depth-sorted, 32 bits) */
 } cgx_run_info;
 
 /* Library version (CGX_ABI_VERSION). */

@@ -72,7 +72,7 @@ class cgx_run_info(C.Structure):
                 ("need_splats", C.c_int64), ("need_pairs", C.c_int64), ("loss", C.c_double),
                 ("entries_fwd", C.c_uint64), ("entries_bwd", C.c_uint64), ("n_tiles", C.c_int64),
                 ("n_pixels", C.c_int64), ("evals_fwd", C.c_uint64), ("evals_bwd", C.c_uint64),
-                ("sort_passes", C.c_int32), ("reserved2", C.c_int32)]
+                ("sort_passes", C.c_int32), ("n_visible", C.c_int32)]
 
 
 _lib = None

@@ -328,7 +328,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.max_pairs = L.max_pairs;
   h.n_views = B;
   h.kind = s->kind;
-  h.sort_passes = L.n_passes;
+  h.sort_passes = sort_passes(L.tile_bits);   // passes over the pairs
   launch_init_counters(P.ctr, expl ? (uint32_t)L.max_splats : 0u, h, st);
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
@@ -833,6 +833,7 @@ int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run
   info->evals_fwd = h.evals_fwd;
   info->evals_bwd = h.evals_bwd;
   info->sort_passes = h.hdr.sort_passes;
+  info->n_visible = (int32_t)h.n_visible;
   if (h.overflow)
     return fail(ctx, CGX_ERR_CAPACITY,
                 "capacity exceeded (flags %u): needs rows %llu, splats %llu, pairs %llu",
