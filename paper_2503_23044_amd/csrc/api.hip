@@ -371,7 +371,6 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   (void)vb;
   (void)fb;
   phase_begin(c, CGX_PHASE_RANGES, st);
-  launch_fill_u32(reinterpret_cast<uint32_t*>(P.ranges), 0u, 2 * (size_t)L.n_tiles, st);
   launch_ranges(P.pkey[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
   launch_tile_order(P.ranges, P.ctr, (uint32_t)L.n_tiles, P.tkey, P.tord, P.hist, st);
   phase_end(c, st);

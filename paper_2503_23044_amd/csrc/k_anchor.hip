@@ -509,61 +509,77 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
 }
 
 // ---------------------------------------------------------------------
-// a10, part 2: one thread per row.  dz1 = (dz2 W2^T) * [z1 > 0],
-// dz0 = dz1 W1^T -> dF and dx (through the view direction and relative
-// distance); z0 and dz1 are kept for the weight-gradient reduction.
+// a10, part 2: 32 threads per row, 8 rows per block.  Thread j of a row
+// forms dz1[j] = (dz2 W2^T)[j] * [z1[j] > 0] from the row's dz2 staged in
+// LDS, then dz0[j] = (dz1 W1^T)[j] for the 32 features (-> dF) and, in
+// threads 0..3, the four direction / distance inputs, which one thread
+// takes back to dx.  z0 and dz1 are kept for the weight-gradient reduction.
 // ---------------------------------------------------------------------
+constexpr int kMlpRows = 8;
+
 __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
                                                         cgx_anchor_scene sc,
                                                         const int2* __restrict__ rows,
                                                         const Counters* ctr,
                                                         float* __restrict__ scratch, cgx_grads gr) {
   __shared__ DecW w;
+  __shared__ float s_dz2[kMlpRows][kOut];
+  __shared__ float s_dz1[kMlpRows][kHid];
+  __shared__ float s_tail[kMlpRows][4];
   const uint32_t n_rows = ctr->n_rows;
-  if ((uint64_t)blockIdx.x * blockDim.x >= n_rows) return;   // past the active rows
+  const uint32_t r0 = blockIdx.x * kMlpRows;
+  if (r0 >= n_rows) return;                    // the grid covers the row capacity
   load_weights(w, sc);
+  for (int e = threadIdx.x; e < kMlpRows * kOut; e += blockDim.x) {
+    const int rr = e / kOut, c = e - rr * kOut;
+    s_dz2[rr][c] = r0 + rr < n_rows ? scratch[(size_t)(r0 + rr) * kRowScratch + kIn + 2 * kHid + c]
+                                    : 0.0f;
+  }
   __syncthreads();
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
-  const int2 row = rows[r];
-  const ViewDev& V = views[row.x];
-  const uint32_t a = (uint32_t)row.y;
+  const int rl = threadIdx.x / kHid, j = threadIdx.x % kHid;
+  const uint32_t r = r0 + rl;
+  const bool live = r < n_rows;
   float* rs = scratch + (size_t)r * kRowScratch;
-  const float* dz2 = rs + kIn + 2 * kHid;
-  float dz1[kHid];
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) dz1[j] = 0.0f;
-  for (int c = 0; c < kOut; ++c) {
-    const float g = dz2[c];
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) dz1[j] += g * w.W2[j * kOut + c];
-  }
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-    dz1[j] = rs[kIn + j] > 0.0f ? dz1[j] : 0.0f;
-    rs[kIn + kHid + j] = dz1[j];
-  }
-  DecIn d;
-  decoder_input(V, sc, a, d);
-#pragma unroll
-  for (int i = 0; i < kIn; ++i) rs[i] = d.z0[i];
-  float* gF = gr.F + (size_t)a * CGX_FEAT_DIM;
-  float dz0[4];
-  for (int i = 0; i < kIn; ++i) {
+  if (live) {
     float acc = 0.0f;
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) acc += dz1[j] * w.W1[i * kHid + j];
-    if (i < CGX_FEAT_DIM) atomic_add_f32(gF + i, acc);
-    else dz0[i - CGX_FEAT_DIM] = acc;
+    for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kOut + c];
+    acc = rs[kIn + j] > 0.0f ? acc : 0.0f;
+    s_dz1[rl][j] = acc;
+    rs[kIn + kHid + j] = acc;
   }
-  // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
-  const float* dir = d.z0 + 32;
-  const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
-  const float il = 1.0f / d.dist;
+  __syncthreads();
+  uint32_t a = 0;
+  if (live) {
+    a = (uint32_t)rows[r].y;
+    rs[j] = bf16_round(sc.F[(size_t)a * CGX_FEAT_DIM + j]);    // z0 feature part
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kHid + k];
+    atomic_add_f32(gr.F + (size_t)a * CGX_FEAT_DIM + j, acc);
+    if (j < 4) {
+      float t = 0.0f;
+#pragma unroll 8
+      for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kHid + k];
+      s_tail[rl][j] = t;
+    }
+  }
+  __syncthreads();
+  if (live && j == 0) {
+    const ViewDev& V = views[rows[r].x];
+    DecIn d;
+    decoder_input(V, sc, a, d);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
-    atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
+    for (int i = CGX_FEAT_DIM; i < kIn; ++i) rs[i] = d.z0[i];
+    // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
+    const float* dir = d.z0 + 32;
+    const float* dz0 = s_tail[rl];
+    const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
+    const float il = 1.0f / d.dist;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
+      atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
+    }
   }
 }
 
@@ -759,7 +775,7 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
   if (gblocks)
     hipLaunchKernelGGL(k_decode_bwd_gauss, dim3(gblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        counts, sgrad, scratch, g);
-  const uint32_t rblocks = div_up(max_rows, 256);
+  const uint32_t rblocks = div_up(max_rows, kMlpRows);
   if (rblocks)
     hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        scratch, g);

@@ -147,20 +147,32 @@ void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* o
 // ---------------------------------------------------------------------
 // a5: [start, end) of each global tile in the sorted pairs
 // ---------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// one thread per tile: its pairs are [lower_bound(t), lower_bound(t + 1))
+// of the tile-sorted keys; an empty tile gets [0, 0)
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys_hi, const Counters* ctr,
                                                 uint2* ranges, uint32_t n_tiles) {
-  uint32_t P = ctr->n_pairs;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-    uint32_t t = keys_hi[i];
-    if (t >= n_tiles) continue;
-    if (i == 0 || keys_hi[i - 1] != t) ranges[t].x = i;
-    if (i == P - 1 || keys_hi[i + 1] != t) ranges[t].y = i + 1;
+  const uint32_t P = ctr->n_pairs;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
+    const uint32_t s = lower_bound_u32(keys_hi, P, t);
+    const uint32_t e = s < P && keys_hi[s] == t ? lower_bound_u32(keys_hi + s, P - s, t + 1) + s : s;
+    ranges[t] = e > s ? make_uint2(s, e) : make_uint2(0u, 0u);
   }
 }
 
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
                    uint32_t cap, hipStream_t s) {
-  uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 8192));
+  (void)cap;
+  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_tiles, 256), 8192));
   hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, keys_hi, ctr, ranges, n_tiles);
 }
 
