@@ -509,13 +509,15 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
 }
 
 // ---------------------------------------------------------------------
-// a10, part 2: 32 threads per row, 8 rows per block.  Thread j of a row
-// forms dz1[j] = (dz2 W2^T)[j] * [z1[j] > 0] from the row's dz2 staged in
-// LDS, then dz0[j] = (dz1 W1^T)[j] for the 32 features (-> dF) and, in
-// threads 0..3, the four direction / distance inputs, which one thread
-// takes back to dx.  z0 and dz1 are kept for the weight-gradient reduction.
+// a10, part 2: 32 threads per row, 8 rows at a time, 64 rows per block
+// (one weight staging).  Thread j of a row forms dz1[j] = (dz2 W2^T)[j] *
+// [z1[j] > 0] from the row's dz2 staged in LDS, then dz0[j] = (dz1 W1^T)[j]
+// for the 32 features (-> dF) and, in threads 0..3, the four direction /
+// distance inputs, which one thread takes back to dx.  z0 and dz1 are kept
+// for the weight-gradient reduction.
 // ---------------------------------------------------------------------
-constexpr int kMlpRows = 8;
+constexpr int kMlpRows = 8;      // rows in flight per block (32 threads each)
+constexpr int kMlpGroups = 8;    // row groups per block, sharing one weight staging
 
 __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
                                                         cgx_anchor_scene sc,
@@ -527,59 +529,65 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
   __shared__ float s_dz1[kMlpRows][kHid];
   __shared__ float s_tail[kMlpRows][4];
   const uint32_t n_rows = ctr->n_rows;
-  const uint32_t r0 = blockIdx.x * kMlpRows;
-  if (r0 >= n_rows) return;                    // the grid covers the row capacity
+  const uint32_t rb = blockIdx.x * (kMlpRows * kMlpGroups);
+  if (rb >= n_rows) return;                    // the grid covers the row capacity
   load_weights(w, sc);
-  for (int e = threadIdx.x; e < kMlpRows * kOut; e += blockDim.x) {
-    const int rr = e / kOut, c = e - rr * kOut;
-    s_dz2[rr][c] = r0 + rr < n_rows ? scratch[(size_t)(r0 + rr) * kRowScratch + kIn + 2 * kHid + c]
-                                    : 0.0f;
-  }
-  __syncthreads();
   const int rl = threadIdx.x / kHid, j = threadIdx.x % kHid;
-  const uint32_t r = r0 + rl;
-  const bool live = r < n_rows;
-  float* rs = scratch + (size_t)r * kRowScratch;
-  if (live) {
-    float acc = 0.0f;
-    for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kOut + c];
-    acc = rs[kIn + j] > 0.0f ? acc : 0.0f;
-    s_dz1[rl][j] = acc;
-    rs[kIn + kHid + j] = acc;
-  }
-  __syncthreads();
-  uint32_t a = 0;
-  if (live) {
-    a = (uint32_t)rows[r].y;
-    rs[j] = bf16_round(sc.F[(size_t)a * CGX_FEAT_DIM + j]);    // z0 feature part
-    float acc = 0.0f;
-#pragma unroll 8
-    for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kHid + k];
-    atomic_add_f32(gr.F + (size_t)a * CGX_FEAT_DIM + j, acc);
-    if (j < 4) {
-      float t = 0.0f;
-#pragma unroll 8
-      for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kHid + k];
-      s_tail[rl][j] = t;
+  for (int grp = 0; grp < kMlpGroups; ++grp) {
+    const uint32_t r0 = rb + grp * kMlpRows;
+    if (r0 >= n_rows) break;                   // uniform over the block
+    for (int e = threadIdx.x; e < kMlpRows * kOut; e += blockDim.x) {
+      const int rr = e / kOut, c = e - rr * kOut;
+      s_dz2[rr][c] = r0 + rr < n_rows
+                         ? scratch[(size_t)(r0 + rr) * kRowScratch + kIn + 2 * kHid + c]
+                         : 0.0f;
     }
-  }
-  __syncthreads();
-  if (live && j == 0) {
-    const ViewDev& V = views[rows[r].x];
-    DecIn d;
-    decoder_input(V, sc, a, d);
-#pragma unroll
-    for (int i = CGX_FEAT_DIM; i < kIn; ++i) rs[i] = d.z0[i];
-    // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
-    const float* dir = d.z0 + 32;
-    const float* dz0 = s_tail[rl];
-    const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
-    const float il = 1.0f / d.dist;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
-      atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
+    __syncthreads();
+    const uint32_t r = r0 + rl;
+    const bool live = r < n_rows;
+    float* rs = scratch + (size_t)r * kRowScratch;
+    if (live) {
+      float acc = 0.0f;
+      for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kOut + c];
+      acc = rs[kIn + j] > 0.0f ? acc : 0.0f;
+      s_dz1[rl][j] = acc;
+      rs[kIn + kHid + j] = acc;
     }
+    __syncthreads();
+    uint32_t a = 0;
+    if (live) {
+      a = (uint32_t)rows[r].y;
+      rs[j] = bf16_round(sc.F[(size_t)a * CGX_FEAT_DIM + j]);    // z0 feature part
+      float acc = 0.0f;
+#pragma unroll 8
+      for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kHid + k];
+      atomic_add_f32(gr.F + (size_t)a * CGX_FEAT_DIM + j, acc);
+      if (j < 4) {
+        float t = 0.0f;
+#pragma unroll 8
+        for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kHid + k];
+        s_tail[rl][j] = t;
+      }
+    }
+    __syncthreads();
+    if (live && j == 0) {
+      const ViewDev& V = views[rows[r].x];
+      DecIn d;
+      decoder_input(V, sc, a, d);
+#pragma unroll
+      for (int i = CGX_FEAT_DIM; i < kIn; ++i) rs[i] = d.z0[i];
+      // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
+      const float* dir = d.z0 + 32;
+      const float* dz0 = s_tail[rl];
+      const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
+      const float il = 1.0f / d.dist;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
+        atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -593,7 +601,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
 // fp32.  The biases' gradients are column sums of the staged values.  Every
 // block writes one partial of 4814 values; k_wgrad_final adds the partials
 // in a fixed order (deterministic).
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 512;
 constexpr int kWR = 32;          // rows per MFMA k-step
 constexpr int kM1 = 48;          // dW1 rows (36 padded)
 constexpr int kN2w = 112;        // dW2 columns (110 padded)
@@ -775,7 +783,7 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
   if (gblocks)
     hipLaunchKernelGGL(k_decode_bwd_gauss, dim3(gblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        counts, sgrad, scratch, g);
-  const uint32_t rblocks = div_up(max_rows, kMlpRows);
+  const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
   if (rblocks)
     hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
                        scratch, g);

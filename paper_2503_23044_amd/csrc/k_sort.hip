@@ -398,13 +398,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
   const uint32_t m = span <= (uint32_t)kDupPairs + 2 ? span : (uint32_t)kDupPairs + 2;
   for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) s_off[t] = voff[j0 + t];
   __syncthreads();
-  // kDupPairs / 256 pairs per thread, unrolled so that the dependent loads
-  // (slot -> row -> view, slot -> pixel box) of the pairs overlap
-  constexpr int kPer = kDupPairs / 256;
-  uint32_t slot[kPer], kk[kPer];
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const uint32_t i = p0 + it * 256 + threadIdx.x;
+  for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
     uint32_t lo = 0, hi = m;
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -412,34 +406,18 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
       else hi = mid;
     }
     const uint32_t jl = lo > 0 ? lo - 1 : 0;
-    slot[it] = i < p1 ? vslot[j0 + jl] : 0u;
-    kk[it] = i - s_off[jl];
-  }
-  int view[kPer];
-  uint2 box[kPer];
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const uint32_t i = p0 + it * 256 + threadIdx.x;
-    view[it] = 0;
-    box[it] = make_uint2(0u, 0u);
-    if (i < p1) {
-      view[it] = rows ? rows[slot[it] / n_per_row].x : (int)(slot[it] / N_explicit);
-      box[it] = make_uint2(splats[slot[it]].bx, splats[slot[it]].by);
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const uint32_t i = p0 + it * 256 + threadIdx.x;
-    if (i >= p1) continue;
-    const ViewDev& V = views[view[it]];
-    const int x_lo = box[it].x & 0xFFFF, x_hi = box[it].x >> 16;
-    const int y_lo = box[it].y & 0xFFFF;
+    const uint32_t slot = vslot[j0 + jl];
+    const uint32_t k = i - s_off[jl];
+    const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
+    const ViewDev& V = views[v];
+    const Splat& sp = splats[slot];
+    const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
+    const int y_lo = sp.by & 0xFFFF;
     const int tx0 = x_lo / tw, nx = x_hi / tw - tx0 + 1;
     const int ty0 = y_lo / th;
-    const uint32_t k = kk[it];
     const int tx = tx0 + (int)(k % (uint32_t)nx), ty = ty0 + (int)(k / (uint32_t)nx);
     pkey[i] = (uint32_t)(V.tile_off + ty * V.TX + tx);
-    pval[i] = slot[it];
+    pval[i] = slot;
   }
 }
 
