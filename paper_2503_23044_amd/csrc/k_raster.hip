@@ -55,19 +55,8 @@ __device__ __forceinline__ Box uniform_box(const Splat& s) {
   const uint32_t by = __builtin_amdgcn_readfirstlane(s.by);
   return Box{(int)(bx & 0xFFFF), (int)(bx >> 16), (int)(by & 0xFFFF), (int)(by >> 16)};
 }
-// Lanes of the 8 x 8 sub-block at (x0, y0) whose pixel lies in the box:
-// bit 8 r + c for column c, row r (lane l owns pixel (l % 8, l / 8)).
-// All operands are wave-uniform, so this is scalar work.
-__device__ __forceinline__ uint64_t block_box_mask(const Box& b, int x0, int y0) {
-  const int cx0 = b.xlo - x0 > 0 ? b.xlo - x0 : 0, cx1 = b.xhi - x0 < 7 ? b.xhi - x0 : 7;
-  const int cy0 = b.ylo - y0 > 0 ? b.ylo - y0 : 0, cy1 = b.yhi - y0 < 7 ? b.yhi - y0 : 7;
-  if (cx0 > cx1 || cy0 > cy1) return 0ull;
-  uint64_t m = ((2ull << cx1) - (1ull << cx0)) & 0xFFull;     // columns cx0..cx1 of one row
-  m |= m << 8;
-  m |= m << 16;
-  m |= m << 32;                                               // ... of every row
-  const uint64_t hi = cy1 == 7 ? 0ull : (1ull << (8 * (cy1 + 1)));
-  return m & (hi - (1ull << (8 * cy0)));                      // rows cy0..cy1
+__device__ __forceinline__ bool box_misses_block(const Box& b, int x0, int y0) {
+  return b.xhi < x0 || b.xlo > x0 + 7 || b.yhi < y0 || b.ylo > y0 + 7;
 }
 
 template <int TW, int TH>
@@ -119,17 +108,14 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
-        if (!(live & (1u << k))) continue;
-        const uint64_t bm = block_box_mask(b, x0, y0);
-        if (bm == 0ull) continue;
-        const bool in = ((bm >> lane) & 1ull) && !done[k];
-        evals += (uint32_t)__popcll(__ballot(in));
-        if (!in) continue;
+        if (!(live & (1u << k)) || box_misses_block(b, x0, y0)) continue;
         const int x = x0 + lx, y = y0 + ly;
+        if (done[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
         const float dx = s.u - ((float)x + 0.5f);
         const float dy = s.w - ((float)y + 0.5f);
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
+        ++evals;
         if (alpha == 0.0f) continue;
         const float Tn = T[k] * (1.0f - alpha);
         if (Tn < kTMin) {
@@ -186,9 +172,11 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     a.px_T[pv + p] = T[k];
     a.px_last[pv + p] = last[k];
   }
-  // statistics: list entries walked and opacity evaluations (the latter is
-  // already a wave total), one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) walked_sum += __shfl_xor(walked_sum, o, kWave);
+  // statistics: list entries walked and opacity evaluations, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    walked_sum += __shfl_xor(walked_sum, o, kWave);
+    evals += __shfl_xor(evals, o, kWave);
+  }
   if (lane == 0 && walked_sum) atomicAdd(&a.ctr->entries_fwd, (unsigned long long)walked_sum);
   if (lane == 0 && evals) atomicAdd(&a.ctr->evals_fwd, (unsigned long long)evals);
 }
@@ -319,17 +307,14 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
-        if (idx >= blast[k]) continue;
-        const uint64_t bm = block_box_mask(b, x0, y0);
-        if (bm == 0ull) continue;
-        const bool in = ((bm >> lane) & 1ull) && idx < last[k];
-        evals += (uint32_t)__popcll(__ballot(in));
-        if (!in) continue;
+        if (idx >= blast[k] || box_misses_block(b, x0, y0)) continue;
         const int x = x0 + lx, y = y0 + ly;
+        if (idx >= last[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
         const float dx = s.u - ((float)x + 0.5f);
         const float dy = s.w - ((float)y + 0.5f);
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
+        ++evals;
         if (alpha == 0.0f) continue;
         const float om = 1.0f - alpha;
         const float rom = __builtin_amdgcn_rcpf(om);
@@ -366,6 +351,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     }
     __syncthreads();
   }
+  for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, kWave);
   if (lane == 0 && evals) atomicAdd(&a.ctr->evals_bwd, (unsigned long long)evals);
 }
 
