@@ -89,10 +89,11 @@ def gpu_leg(args, wl):
         f"loss {info0['loss']:.6f} workspace {rd.ws.numel() / 2**30:.2f} GiB")
     log(f"[bench] per step: list entries walked fwd {info0['entries_fwd']} bwd {info0['entries_bwd']}, "
         f"opacity evaluations fwd {info0['evals_fwd']} bwd {info0['evals_bwd']}")
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done")
+    log(f"[bench] warmup {args.warmup} done; capacities {rd.cap}, workspace {rd.ws.numel() / 2**30:.2f} GiB")
+    torch.cuda.reset_peak_memory_stats()
 
     B.cgx_timing_enable(rd.ctx, 16 * args.steps + 16)
     torch.cuda.synchronize()

@@ -100,10 +100,13 @@ class Renderer:
 
     # ------------------------------------------------------------------
     def ensure_workspace(self, views, scene, cap=None):
+        if cap is None and getattr(self, "_next_cap", None) is not None:
+            cap, self._next_cap = self._next_cap, None
         cap = dict(cap or self.cap)
         n = B.cgx_workspace_size(self.ctx, views, scene, cap)
         n = (n + 255) // 256 * 256
-        if self.ws is None or self.ws.numel() < n:
+        if self.ws is None or self.ws.numel() < n or self.ws.numel() > 2 * n:
+            self.ws = None
             self.ws = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
         self.cap = cap
         return self.ws
@@ -121,6 +124,22 @@ class Renderer:
             cap["max_rows"] = int(info["need_rows"] * 1.25) + 64
         self.cap = cap
 
+    def _fit(self, info, scene):
+        """After a run within capacity: capacities more than 4x what it
+        needed are brought down to 1.25x for the NEXT forward call (the
+        kernels' grids and the workspace are sized by them; the state of the
+        run just made stays valid for its backward).  A later run that needs
+        more overflows and grows them again."""
+        cap = dict(self.cap)
+        want_pairs = int(info["n_pairs"] * 1.25) + 1024
+        if cap.get("max_pairs", 0) == 0 or cap["max_pairs"] > 4 * want_pairs:
+            cap["max_pairs"] = want_pairs
+        if scene["kind"] == B.CGX_SCENE_ANCHOR:
+            want_rows = int(info["n_rows"] * 1.25) + 64
+            if cap.get("max_rows", 0) == 0 or cap["max_rows"] > 4 * want_rows:
+                cap["max_rows"] = want_rows
+        self._next_cap = cap if cap != self.cap else None
+
     def forward(self, views, scene, out=None, check=True):
         """Render; returns the packed images.  With check, reads the status
         (synchronises) and re-runs with larger capacities on overflow."""
@@ -133,6 +152,7 @@ class Renderer:
             info = B.cgx_read_info(self.ctx, ws, raise_on_capacity=False)
             if not info["overflow"]:
                 self.last_info = info
+                self._fit(info, scene)
                 return out
             self._grow(info)
         raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
@@ -155,6 +175,7 @@ class Renderer:
             info = B.cgx_read_info(self.ctx, ws, raise_on_capacity=False)
             if not info["overflow"]:
                 self.last_info = info
+                self._fit(info, scene)
                 return out, grads
             self._grow(info)
         raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
