@@ -102,6 +102,7 @@ def gpu_leg(args, wl):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    peak_bytes = torch.cuda.max_memory_allocated()      # the batched step's own peak
     phases = B.cgx_timing_read(rd.ctx)
     B.cgx_timing_enable(rd.ctx, 0)
     info = rd.info()      # raises if a capacity was exceeded inside the timed region
@@ -139,7 +140,7 @@ def gpu_leg(args, wl):
         per_view_ms = (time.perf_counter() - t0) / reps * 1e3
         log(f"[bench] per-view loop: {per_view_ms:.3f} ms per batch ({len(wl.views)} calls)")
     return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms,
-                peak_bytes=torch.cuda.max_memory_allocated(), tile=f"{tw}x{th}",
+                peak_bytes=peak_bytes, tile=f"{tw}x{th}",
                 tune_ms=({f"{a}x{b}": round(m, 4) for (a, b), m in tune_ms.items()}
                          if tune_ms else None))
 
