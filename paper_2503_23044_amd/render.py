@@ -99,10 +99,23 @@ class Renderer:
             pass
 
     # ------------------------------------------------------------------
+    # first-call capacities: a run that needs more overflows, reports what it
+    # needed, and is repeated with grown capacities
+    FIRST_ROWS = 1 << 22
+    FIRST_PAIRS = 1 << 26
+
     def ensure_workspace(self, views, scene, cap=None):
         if cap is None and getattr(self, "_next_cap", None) is not None:
             cap, self._next_cap = self._next_cap, None
         cap = dict(cap or self.cap)
+        if not cap:
+            if scene["kind"] == B.CGX_SCENE_ANCHOR:
+                rows = min(int(scene["x"].shape[0]) * len(views), self.FIRST_ROWS)
+                splats = rows * int(scene["O"].shape[1])
+                cap = dict(max_rows=rows)
+            else:
+                splats = int(scene["means"].shape[0]) * len(views)
+            cap["max_pairs"] = min(max(8 * splats, 1024), self.FIRST_PAIRS)
         n = B.cgx_workspace_size(self.ctx, views, scene, cap)
         n = (n + 255) // 256 * 256
         if self.ws is None or self.ws.numel() < n or self.ws.numel() > 2 * n:

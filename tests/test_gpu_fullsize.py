@@ -180,3 +180,141 @@ def test_c1_full_size_sampled_tiles():
     for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)):
         check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
                    dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
+
+
+def _view0_compare(out, r, W, H):
+    """Images of view 0 (the first planes of the packed outputs) on the
+    pixels of the oracle's sampled tiles."""
+    n = W * H
+    view0 = {k: out[k][:c * n] for k, c in (("rgb", 3), ("depth", 1), ("plane_d", 1), ("normal", 3),
+                                          ("alpha", 1))}
+    _compare_sampled(view0, r, None)
+
+
+def _grads_view0(r, n_total, rng):
+    """Masked linear output gradients on view 0's sampled tiles, zero on the
+    other views, packed for the whole batch."""
+    og = _masked_linear_grads(r, rng)
+    g = og[0]
+    n0 = g["depth"].size
+    pad = n_total - n0
+    z3 = lambda a: np.concatenate([a, np.zeros((3, pad))], 1)  # noqa: E731
+    z1 = lambda a: np.concatenate([a, np.zeros(pad)])  # noqa: E731
+    dev = dict(rgb=z3(g["rgb"]), depth=z1(g["depth"]), plane_d=z1(g["D"]), normal=z3(g["normal"]),
+               alpha=z1(g["alpha"]))
+    dev = {k: torch.as_tensor(v.ravel().astype(np.float32), device="cuda") for k, v in dev.items()}
+    return og, dev
+
+
+def _anchor_view0_case(wl, rd, sc, out, n_tiles, seed, tile=(16, 16)):
+    """Sort, images and gradients of view 0 on sampled tiles against the
+    single-view oracle (views are independent: view 0's rows, pairs and
+    pixels are its own; anchor gradients get only view 0's share because
+    the output gradients vanish elsewhere)."""
+    v0 = wl.views[0]
+    dbg = rd.debug()
+    layout = pipeline.ras.batch_layout([v0], tile)
+    keep = _sample_tiles(layout, n_tiles, seed=seed)
+    r = pipeline.render_anchor(wl.scene, [v0], tile=tile, keep_tiles=keep)
+    rows_gpu = dbg["rows"].astype(np.int64)
+    rows0 = rows_gpu[rows_gpu[:, 0] == 0]
+    np.testing.assert_array_equal(rows0, r.rows)
+
+    def s2vg(slots):
+        row, k = slots // 10, slots % 10
+        v = rows_gpu[row, 0]
+        assert np.all(v == 0)
+        return v, (row - 0) * 10 + k       # view 0's rows come first
+
+    n = _compare_sorted_sample(dbg, r, keep, s2vg)
+    assert n > 500
+    _view0_compare(out, r, v0.width, v0.height)
+    og, gdev = _grads_view0(r, int(out["depth"].numel()), np.random.default_rng(seed + 1))
+    ref, _ = pipeline.backward(r, og, wl.scene)
+    gr = rd.backward(wl.views, sc, out, gdev)
+    torch.cuda.synchronize()
+    from tests.parity import _without_fragile
+    sens = _anchor_sens_two_draws(wl.scene, [v0], keep, og, tile, ref)
+    g2, _ = pipeline.backward(r, _without_fragile(r, og), wl.scene)
+    fa = ref["frag"]
+    for k, c in (("x", 3), ("l", 3), ("O", 30), ("F", 32)):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
+                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
+    for k in ("W1", "b1", "W2", "b2"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None,
+                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
+
+
+def _anchor_sens_two_draws(scene, views, keep, og, tile, ref):
+    """Conditioning of the anchor gradients: the larger response of the
+    oracle's gradient to two independent float32-size perturbations of every
+    float input, decoder weights included."""
+    import copy
+
+    from tests.parity import _perturbed
+    out = None
+    for seed in (4321, 8765):
+        rng = np.random.default_rng(seed)
+        sc = copy.copy(scene)
+        for k in ("x", "l", "O", "b1", "b2"):
+            setattr(sc, k, _perturbed(getattr(scene, k), rng))
+        sc.W1_exact = _perturbed(scene.W1, rng)
+        sc.W2_exact = _perturbed(scene.W2, rng)
+        r1 = pipeline.render_anchor(sc, views, tile=tile, keep_tiles=keep)
+        g1, _ = pipeline.backward(r1, og, sc)
+        d = {k: np.abs(ref[k] - g1[k]) for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
+        out = d if out is None else {k: np.maximum(out[k], d[k]) for k in d}
+    return out
+
+
+def test_c3_full_size_sampled_tiles():
+    print("case: C3 full size (600k anchors, 4 views 3840x2160), 16 sampled tiles of view 0", flush=True)
+    from paper_2503_23044_amd import render
+    wl = scenes.make_c3()
+    rd = render.Renderer(0, (16, 16))
+    sc = render.scene_from(wl.scene)
+    out = rd.forward(wl.views, sc)
+    torch.cuda.synchronize()
+    info = rd.info()
+    print(f"  rows {info['n_rows']} pairs {info['n_pairs']}", flush=True)
+    _anchor_view0_case(wl, rd, sc, out, 16, seed=2030)
+
+
+def test_c4_graph_autotuned_sampled_tiles():
+    print("case: C4 full size (2M anchors, 16 views 1600x1200), autotuned tile, graph replay", flush=True)
+    from paper_2503_23044_amd import binding as B
+    from paper_2503_23044_amd import render
+    wl = scenes.make_c4()
+    sc = render.scene_from(wl.scene)
+    cat = lambda xs: torch.as_tensor(np.concatenate([x.ravel() for x in xs]), device="cuda")  # noqa: E731
+    tgt = dict(rgb=cat(wl.targets["rgb"]), depth=cat(wl.targets["depth"]), normal=cat(wl.targets["normal"]))
+    rd = render.Renderer(0, (16, 16))
+    tile, ms = rd.autotune(wl.views, sc, tgt, reps=1)
+    print(f"  autotuned tile {tile}: {ms}", flush=True)
+    loss = torch.zeros(1, device="cuda")
+    out, gr = rd.fwd_bwd_l1(wl.views, sc, tgt, loss=loss)      # eager, fits the capacities
+    out, gr = rd.fwd_bwd_l1(wl.views, sc, tgt, out=out, grads=gr, loss=loss)
+    torch.cuda.synchronize()
+    ref_out = {k: v.clone() for k, v in out.items()}
+    ref_gr = {k: v.clone() for k, v in gr.items()}
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = B.cgx_graph_capture_fwd_bwd_l1(rd.ctx, wl.views, sc, rd.cap, rd.ws, tgt, (1.0, 1.0, 1.0),
+                                           out, gr, loss, side)
+    side.synchronize()
+    try:
+        for v in list(out.values()) + list(gr.values()):
+            v.fill_(float("nan"))
+        torch.cuda.synchronize()
+        B.cgx_graph_launch(g, side)
+        side.synchronize()
+        assert B.cgx_read_info(rd.ctx, rd.ws)["overflow"] == 0
+        for k in ref_out:
+            assert torch.equal(out[k], ref_out[k]), k
+        for k in ref_gr:
+            a, b = gr[k].double(), ref_gr[k].double()
+            assert float((a - b).norm() / max(float(b.norm()), 1e-30)) < 1e-5, k
+    finally:
+        B.cgx_graph_destroy(g)
+    # the replayed images against the oracle, view 0, in the tuned tile shape
+    _anchor_view0_case(wl, rd, sc, out, 16, seed=2040, tile=tuple(tile))
