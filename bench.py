@@ -47,7 +47,7 @@ def parse():
                         "compiled shape with the autotuner and keep the fastest")
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-tiles", type=int, default=1000)
+    p.add_argument("--cpu-sample-tiles", type=int, default=4000)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
                         "for scaling hardware byte counters)")

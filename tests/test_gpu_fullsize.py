@@ -198,7 +198,8 @@ def _grads_view0(r, n_total, rng):
     g = og[0]
     n0 = g["depth"].size
     pad = n_total - n0
-    z3 = lambda a: np.concatenate([a, np.zeros((3, pad))], 1)  # noqa: E731
+    # the packed layout is view-major: view 0's planes, then the other views'
+    z3 = lambda a: np.concatenate([np.asarray(a).ravel(), np.zeros(3 * pad)])  # noqa: E731
     z1 = lambda a: np.concatenate([a, np.zeros(pad)])  # noqa: E731
     dev = dict(rgb=z3(g["rgb"]), depth=z1(g["depth"]), plane_d=z1(g["D"]), normal=z3(g["normal"]),
                alpha=z1(g["alpha"]))
