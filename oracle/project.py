@@ -189,6 +189,7 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
         normal=nvec, d=d, sign=sign, jstar=jstar,
         tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, TX=TX, TY=TY,
         frag_value=valid & (frag_r | frag_axis | frag_flip),
+        frag_ring=valid & frag_r, frag_geom=valid & (frag_axis | frag_flip),
         frag_grad=valid & (frag_colour | clamp_x | clamp_y
                            | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)
                            | (np.abs(np.abs(ry) - lim_y) < FRAG * lim_y)),

@@ -205,12 +205,18 @@ def composite_tile(S, ent, I, J, view_arrays):
     frag |= near_a.any(axis=1)
     near_t = use & upto & (np.abs(Tp_all / T_MIN - 1.0) < FRAG_T)
     frag |= near_t.any(axis=1)
+    frag_geom = np.zeros(npx, bool)
     if ne:
-        sv = S["frag_value"][ent]
+        # a fragile radius ceiling moves the box edge by one pixel: the ring
+        # between the box shrunk and grown by one; a fragile normal axis or
+        # orientation changes the splat's normal and plane distance
         box = S["box"][ent]
-        near_box = ((I[:, None] >= box[None, :, 0] - 1) & (I[:, None] <= box[None, :, 1] + 1)
-                    & (J[:, None] >= box[None, :, 2] - 1) & (J[:, None] <= box[None, :, 3] + 1))
-        frag |= (near_box & sv[None] & upto).any(axis=1)
+        grown = ((I[:, None] >= box[None, :, 0] - 1) & (I[:, None] <= box[None, :, 1] + 1)
+                 & (J[:, None] >= box[None, :, 2] - 1) & (J[:, None] <= box[None, :, 3] + 1))
+        shrunk = ((I[:, None] >= box[None, :, 0] + 1) & (I[:, None] <= box[None, :, 1] - 1)
+                  & (J[:, None] >= box[None, :, 2] + 1) & (J[:, None] <= box[None, :, 3] - 1))
+        frag |= (grown & ~shrunk & S["frag_ring"][ent][None] & upto).any(axis=1)
+        frag_geom = (grown & S["frag_geom"][ent][None] & upto).any(axis=1)
     frag_grad = frag | (inc & (np.abs(E["raw"] / ALPHA_MAX - 1.0) < FRAG_ALPHA)).any(axis=1)
     if ne:
         frag_grad |= (inc & S["frag_grad"][ent][None]).any(axis=1)
@@ -230,7 +236,8 @@ def composite_tile(S, ent, I, J, view_arrays):
     sabs = np.sum(Nabs * np.abs(ray), 1)
     frag_grad = frag_grad | (keep & (sabs > DHAT_COND * np.abs(sdot)))
     return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, T=T_final, last=last,
-                walked=walked, frag=frag, frag_grad=frag_grad | frag, inc=inc,
+                walked=walked, frag=frag, frag_geom=frag_geom,
+                frag_grad=frag_grad | frag | frag_geom, inc=inc,
                 keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)
 
 
@@ -245,7 +252,8 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
                    normal=np.zeros((3, H * W)), normal_abs=np.zeros((3, H * W)),
                    alpha=np.zeros(H * W), T=np.ones(H * W),
                    last=np.zeros(H * W, np.int64), walked=np.zeros(H * W, np.int64),
-                   frag=np.zeros(H * W, bool), frag_grad=np.zeros(H * W, bool),
+                   frag=np.zeros(H * W, bool), frag_geom=np.zeros(H * W, bool),
+                   frag_grad=np.zeros(H * W, bool),
                    covered=np.zeros(H * W, bool), tiles={})
         out.append(img)
     n_tiles_total = int(layout["tile_off"][-1])
@@ -269,24 +277,34 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
         img["last"][pix] = R["last"]
         img["walked"][pix] = R["walked"]
         img["frag"][pix] = R["frag"]
+        img["frag_geom"][pix] = R["frag_geom"]
         img["frag_grad"][pix] = R["frag_grad"]
         img["covered"][pix] = True
         img["tiles"][gtile] = (ent, I, J, pix, R)
-    # a splat whose radius ceiling, normal axis or orientation is fragile may
-    # reach one pixel further on the GPU: flag its box grown by one pixel
+    # a splat with a fragile radius ceiling may reach one pixel further or
+    # shorter on the GPU: flag the ring between its box shrunk and grown by
+    # one pixel; one with a fragile normal axis or orientation has another
+    # normal and plane distance there: flag its grown box for the geometric
+    # outputs (normal, D, unbiased depth); both for the gradients
     for v, view in enumerate(views):
         S = splats_per_view[v]
         W, H = int(view.width), int(view.height)
         img = out[v]
         for i in np.nonzero(S["frag_value"])[0]:
-            x0, x1, y0, y1 = S["box"][i]
-            x0, y0 = max(x0 - 1, 0), max(y0 - 1, 0)
-            x1, y1 = min(x1 + 1, W - 1), min(y1 + 1, H - 1)
+            bx0, bx1, by0, by1 = (int(t) for t in S["box"][i])
+            x0, y0 = max(bx0 - 1, 0), max(by0 - 1, 0)
+            x1, y1 = min(bx1 + 1, W - 1), min(by1 + 1, H - 1)
             if x0 > x1 or y0 > y1:
                 continue
-            blk = (np.arange(y0, y1 + 1)[:, None] * W + np.arange(x0, x1 + 1)[None]).ravel()
-            img["frag"][blk] = True
+            xs, ys = np.arange(x0, x1 + 1), np.arange(y0, y1 + 1)
+            blk = (ys[:, None] * W + xs[None]).ravel()
             img["frag_grad"][blk] = True
+            if S["frag_geom"][i]:
+                img["frag_geom"][blk] = True
+            if S["frag_ring"][i]:
+                inner = (((xs[None] >= bx0 + 1) & (xs[None] <= bx1 - 1))
+                         & ((ys[:, None] >= by0 + 1) & (ys[:, None] <= by1 - 1))).ravel()
+                img["frag"][blk[~inner]] = True
     return out
 
 

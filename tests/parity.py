@@ -65,8 +65,20 @@ def compare_images(out, r, report=None):
     for k, (ok, c) in chans.items():
         g = out[k].detach().cpu().numpy() if hasattr(out[k], "detach") else out[k]
         mag = oracle_images_packed(r, "normal_abs", 3) if k == "normal" else None
-        check_close(k, g, oracle_images_packed(r, ok, c), oracle_mask_packed(r, "frag", c),
+        check_close(k, g, oracle_images_packed(r, ok, c), image_fragile(r, k, c),
                     report=report, mag=mag)
+
+
+GEOMETRIC = ("normal", "plane_d", "depth")
+
+
+def image_fragile(r, key, channels):
+    """Packed mask of pixels with a fragile decision for output `key`: the
+    geometric outputs also exclude pixels whose splat normal is fragile."""
+    m = oracle_mask_packed(r, "frag", channels)
+    if key in GEOMETRIC:
+        m = m | oracle_mask_packed(r, "frag_geom", channels)
+    return m
 
 
 def compare_sort_explicit(dbg, r, N):

@@ -12,7 +12,8 @@ import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import check_close, check_grad, oracle_images_packed, oracle_mask_packed
+from tests.parity import (check_close, check_grad, image_fragile, oracle_images_packed,
+                          oracle_mask_packed)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +53,7 @@ def _compare_sampled(out, r, keep):
         got = out[key].cpu().numpy()
         ref = oracle_images_packed(r, okey, c)
         cov = oracle_mask_packed(r, "covered", c)
-        frag = oracle_mask_packed(r, "frag", c)
+        frag = image_fragile(r, key, c)
         mag = oracle_images_packed(r, "normal_abs", 3)[cov] if key == "normal" else None
         check_close(key, got[cov], ref[cov], frag[cov], mag=mag)
 
