@@ -161,7 +161,9 @@ def copy_calibration(mib):
 
 
 PROFILE_BYTES = os.path.join(ROOT, "profiles", "c2_fused_step_hbm_bytes.md")
-KERNEL_SOURCES = ("paper_2503_23044_amd/csrc/k_raster.hip", "paper_2503_23044_amd/csrc/cgx_common.h")
+# the raster kernels and what decides their input (the pixel boxes)
+KERNEL_SOURCES = ("paper_2503_23044_amd/csrc/k_raster.hip", "paper_2503_23044_amd/csrc/cgx_common.h",
+                  "paper_2503_23044_amd/csrc/cgx_project.h")
 
 
 def kernel_source_digest():

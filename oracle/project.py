@@ -11,8 +11,12 @@ PGSR strategy).  Constants the paper leaves unstated are fixed here:
   * Jacobian J of the perspective map with x/z, y/z clamped to 1.3 times
     the half field of view; Sigma_2 = J R Sigma R^T J^T + 0.3 I;
   * conic = Sigma_2^{-1}; radius r = ceil(3 sqrt(lambda_max(Sigma_2)));
-  * pixel box: the pixels whose centre lies within r of the 2-D mean in
-    both axes, clipped to the image; culled if empty;
+  * pixel box: the pixels whose centre lies within r_x = min(r, e_x) of the
+    2-D mean in x and r_y = min(r, e_y) in y, clipped to the image; culled
+    if empty.  e_x = sqrt(2 ln(255 o) Sigma_2,xx) (e_y with Sigma_2,yy) is
+    the reach along each axis of the ellipse where o exp(power) >= 1/255,
+    so every pixel the compositor could draw inside the 3-sigma square is
+    kept; a splat with o < 1/255 draws nothing;
   * depth key = IEEE binary32 bits of p_z rounded to nearest;
   * normal: the rotated axis of the smallest scale, in the camera frame,
     turned to face the camera; plane distance d = -n . p (>= 0);
@@ -77,13 +81,17 @@ def quat_to_rot_backward(qn, dR):
     return np.stack([dw, dx, dy, dz], 1)
 
 
-def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0):
+def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0,
+            opacity_exact=True):
     """Project N Gaussians into one view.
 
     mu: (N,3) float64 centres (for explicit Gaussians the float32 inputs
     widened; for anchors x + O*l evaluated in float64).  scales (N,3),
     quats (N,4) raw (w,x,y,z), opacity (N,).  Colour is either given
-    (N,3) or evaluated from sh (N,K,3).  tile = (tw, th).
+    (N,3) or evaluated from sh (N,K,3).  tile = (tw, th).  opacity_exact:
+    the GPU sees the same opacity (an input) rather than one it decoded
+    itself in float32 (anchor Gaussians), which widens the fragile margin
+    of the opacity-aware box.
 
     Returns a dict of per-Gaussian arrays; `valid` marks the splats that
     survive culling and touch at least one tile.
@@ -137,11 +145,33 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     r = np.ceil(np.minimum(r3, 1 << 20))
     frag_r = ok & (np.abs(r3 - np.round(r3)) < FRAG * np.maximum(r3, 1.0))
 
-    # ---- pixel box (exact given r) ---------------------------------------
-    x_lo = np.ceil(u - (r + 0.5))
-    x_hi = np.floor(u + (r - 0.5))
-    y_lo = np.ceil(w - (r + 0.5))
-    y_hi = np.floor(w + (r - 0.5))
+    # ---- opacity-aware reach per axis -------------------------------------
+    tau = np.log(np.maximum(255.0 * o, 1e-300))
+    ok = ok & (tau >= 0.0)
+    frag_tau = np.abs(255.0 * o - 1.0) < FRAG
+    tau0 = np.maximum(tau, 0.0)
+    ex = np.sqrt(2.0 * tau0 * np.where(ok, A, 0.0))
+    ey = np.sqrt(2.0 * tau0 * np.where(ok, Cc, 0.0))
+    rxp = np.minimum(r, ex)
+    ryp = np.minimum(r, ey)
+
+    # ---- pixel box (exact given rx, ry) ----------------------------------
+    x_lo = np.ceil(u - (rxp + 0.5))
+    x_hi = np.floor(u + (rxp - 0.5))
+    y_lo = np.ceil(w - (ryp + 0.5))
+    y_hi = np.floor(w + (ryp - 0.5))
+    # a reach from the float32 covariance and opacity may move a box edge
+    # across a pixel centre: fragile when an edge is that close to one
+    # (relative error of the reach ~ dA/2A + (do/o)/(2 tau))
+    rel = FRAG + (0.0 if opacity_exact else FRAG / (2.0 * np.maximum(tau0, 1e-3)))
+    marg_x = rel * rxp + 1e-9
+    marg_y = rel * ryp + 1e-9
+    def _near_int(e, m):
+        return np.abs(e - np.round(e)) < m
+    frag_ext = ok & (((ex <= r) & (_near_int(u - (rxp + 0.5), marg_x) | _near_int(u + (rxp - 0.5), marg_x)))
+                     | ((ey <= r) & (_near_int(w - (ryp + 0.5), marg_y) | _near_int(w + (ryp - 0.5), marg_y)))
+                     | (np.abs(ex - r) < marg_x) | (np.abs(ey - r) < marg_y))
+    frag_r = frag_r | frag_ext | (front & (det > 0) & frag_tau)
     x_lo = np.clip(np.where(ok, x_lo, W), 0, W).astype(np.int64)
     x_hi = np.clip(np.where(ok, x_hi, -1), -1, W - 1).astype(np.int64)
     y_lo = np.clip(np.where(ok, y_lo, H), 0, H).astype(np.int64)
@@ -188,7 +218,7 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
         box=np.stack([x_lo, x_hi, y_lo, y_hi], 1), opacity=o, rgb=rgb, raw_rgb=raw,
         normal=nvec, d=d, sign=sign, jstar=jstar,
         tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, TX=TX, TY=TY,
-        frag_value=valid & (frag_r | frag_axis | frag_flip),
+        frag_value=(valid & (frag_r | frag_axis | frag_flip)) | (front & (det > 0) & frag_tau),
         frag_ring=valid & frag_r, frag_geom=valid & (frag_axis | frag_flip),
         frag_grad=valid & (frag_colour | clamp_x | clamp_y
                            | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)

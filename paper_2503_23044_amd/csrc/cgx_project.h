@@ -133,8 +133,16 @@ __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn
   const float lam = mid + sqrtf(half * half + st.B * st.B);
   const float r3 = 3.0f * sqrtf(lam);
   const double r = (double)ceilf(fminf(r3, 1048576.0f));
-  double xl = box_lo64(u64, r), xh = box_hi64(u64, r);
-  double yl = box_lo64(w64, r), yh = box_hi64(w64, r);
+  // Opacity-aware reach: o exp(power) >= 1/255 only where
+  // d^T Sigma2^-1 d <= 2 ln(255 o); that ellipse reaches sqrt(2 ln(255 o)
+  // Sigma2_xx) along x (Sigma2_yy along y).  The 3-sigma radius caps it; a
+  // splat with o < 1/255 draws nothing.
+  const double tau = log(255.0 * (double)in.op);
+  if (!(tau >= 0.0)) return 0;
+  const double rx = fmin(r, sqrt(2.0 * tau * (double)st.A));
+  const double ry = fmin(r, sqrt(2.0 * tau * (double)st.C));
+  double xl = box_lo64(u64, rx), xh = box_hi64(u64, rx);
+  double yl = box_lo64(w64, ry), yh = box_hi64(w64, ry);
   xl = fmin(fmax(xl, 0.0), (double)V.W);
   xh = fmin(fmax(xh, -1.0), (double)(V.W - 1));
   yl = fmin(fmax(yl, 0.0), (double)V.H);

@@ -169,22 +169,35 @@ def test_ewa_covariance_is_linearised_projection():
 
 
 def test_pixel_box_is_the_square_test():
-    """A pixel is inside a splat's box iff its centre is within r of the 2-D
-    mean on both axes (and it lies in the image)."""
+    """A pixel is inside a splat's box iff its centre is within r_x = min(r,
+    e_x) of the 2-D mean in x and r_y = min(r, e_y) in y (and it lies in the
+    image), with e_x = sqrt(2 ln(255 o) Sigma_2,xx) computed here from the
+    inverted conic."""
     rng = np.random.default_rng(7)
     v = _V()
     n = 200
     mu = np.stack([rng.uniform(-1.5, 1.5, n), rng.uniform(-1.2, 1.2, n), rng.uniform(-1, 1, n)], 1)
     s = np.exp(rng.normal(-3, 0.6, (n, 3)))
     q = rng.standard_normal((n, 4))
-    P = project.project(mu, s, q, np.full(n, 0.5), v, (16, 16), colour=np.zeros((n, 3)))
+    o = rng.uniform(0.002, 1.0, n)
+    P = project.project(mu, s, q, o, v, (16, 16), colour=np.zeros((n, 3)))
     I, J = np.meshgrid(np.arange(v.width), np.arange(v.height))
     for i in range(n):
-        inside = ((np.abs(I + 0.5 - P["u"][i]) <= P["r"][i]) & (np.abs(J + 0.5 - P["w"][i]) <= P["r"][i]))
+        if o[i] < 1.0 / 255.0:
+            assert not P["valid"][i]
+            continue
+        S2 = np.linalg.inv(np.array([[P["conic"][i][0], P["conic"][i][1]],
+                                     [P["conic"][i][1], P["conic"][i][2]]]))
+        t = np.log(255.0 * o[i])
+        rx = min(P["r"][i], np.sqrt(2 * t * S2[0, 0]))
+        ry = min(P["r"][i], np.sqrt(2 * t * S2[1, 1]))
+        inside = ((np.abs(I + 0.5 - P["u"][i]) <= rx) & (np.abs(J + 0.5 - P["w"][i]) <= ry))
         x0, x1, y0, y1 = P["box"][i]
         box = (I >= x0) & (I <= x1) & (J >= y0) & (J <= y1)
         if P["p"][i, 2] <= 0.2:
             assert not P["valid"][i]
+            continue
+        if P["frag_value"][i]:
             continue
         np.testing.assert_array_equal(box, inside)
         assert P["valid"][i] == inside.any()
@@ -232,3 +245,31 @@ def test_normal_faces_camera_and_plane_distance():
         n_cam = V["R"] @ axis_w
         np.testing.assert_allclose(np.abs(P["normal"][i]), np.abs(n_cam), atol=1e-6)
         assert np.dot(P["normal"][i], P["p"][i]) <= 0
+
+
+def test_opacity_box_keeps_every_drawable_pixel():
+    """Brute force: inside the 3-sigma square, every pixel whose opacity
+    o exp(power) reaches 1/255 lies in the (opacity-aware) box, and the box
+    is never wider than the square."""
+    rng = np.random.default_rng(8)
+    v = _V()
+    n = 300
+    mu = np.stack([rng.uniform(-1.5, 1.5, n), rng.uniform(-1.2, 1.2, n), rng.uniform(-1, 1, n)], 1)
+    s = np.exp(rng.normal(-3, 0.8, (n, 3)))
+    q = rng.standard_normal((n, 4))
+    o = rng.uniform(0.003, 1.0, n)
+    P = project.project(mu, s, q, o, v, (16, 16), colour=np.zeros((n, 3)))
+    I, J = np.meshgrid(np.arange(v.width), np.arange(v.height))
+    tight = 0
+    for i in np.nonzero(P["valid"])[0]:
+        a, b, c = P["conic"][i]
+        dx, dy = P["u"][i] - (I + 0.5), P["w"][i] - (J + 0.5)
+        power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        drawn = (o[i] * np.exp(power) >= 1.0 / 255.0) & (power <= 0)
+        square = (np.abs(dx) <= P["r"][i]) & (np.abs(dy) <= P["r"][i])
+        x0, x1, y0, y1 = P["box"][i]
+        box = (I >= x0) & (I <= x1) & (J >= y0) & (J <= y1)
+        assert not (drawn & square & ~box).any(), i
+        assert not (box & ~square).any(), i
+        tight += int((square & ~box).sum())
+    assert tight > 0      # the box is strictly smaller for some splats
