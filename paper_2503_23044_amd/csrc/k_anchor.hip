@@ -12,7 +12,12 @@ constexpr int kHid = CGX_MLP_HIDDEN;     // 32
 constexpr int kGo = CGX_GAUSS_OUT;       // 11
 constexpr int kNOff = 10;                // Gaussians per anchor in this build
 constexpr int kOut = kNOff * kGo;        // 110
-constexpr int kRowScratch = kIn + kHid + kHid + kOut;   // z0, z1, dz1, dz2 per row
+// per row: z0, z1, dz1, dz2 (the weight-gradient operands), then z2 kept by
+// the forward decode for the Gaussian adjoint
+constexpr int kRowUsed = kIn + kHid + kHid + kOut;
+constexpr int kZ2 = kRowUsed;
+constexpr int kRowScratch = kRowUsed + kOut;
+static_assert(kRowUsed % 2 == 0 && kRowScratch % 2 == 0, "row scratch is read in float pairs");
 constexpr int kWGrad = kIn * kHid + kHid * kOut + kHid + kOut;   // 4814
 
 // ---------------------------------------------------------------------
@@ -169,6 +174,19 @@ struct DecIn {
   float dist;
 };
 
+// direction and distance inputs only: e = (c - x)/|c - x|, |c - x|
+__device__ __forceinline__ void decoder_dir(const ViewDev& V, const cgx_anchor_scene& sc, uint32_t a,
+                                            float e[3], float& dist) {
+  const float e0 = (float)(V.c[0] - (double)sc.x[3 * a]);
+  const float e1 = (float)(V.c[1] - (double)sc.x[3 * a + 1]);
+  const float e2 = (float)(V.c[2] - (double)sc.x[3 * a + 2]);
+  dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+  const float il = 1.0f / dist;
+  e[0] = e0 * il;
+  e[1] = e1 * il;
+  e[2] = e2 * il;
+}
+
 // z0 = [bf16(F), (c - x)/|c - x|, |c - x|/d_max]
 __device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor_scene& sc,
                                               uint32_t a, DecIn& d) {
@@ -181,14 +199,7 @@ __device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor
     d.z0[4 * q + 2] = bf16_round(f.z);
     d.z0[4 * q + 3] = bf16_round(f.w);
   }
-  const float e0 = (float)(V.c[0] - (double)sc.x[3 * a]);
-  const float e1 = (float)(V.c[1] - (double)sc.x[3 * a + 1]);
-  const float e2 = (float)(V.c[2] - (double)sc.x[3 * a + 2]);
-  d.dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-  const float il = 1.0f / d.dist;
-  d.z0[32] = e0 * il;
-  d.z0[33] = e1 * il;
-  d.z0[34] = e2 * il;
+  decoder_dir(V, sc, a, d.z0 + 32, d.dist);
   d.z0[35] = d.dist / sc.d_max;
 }
 
@@ -385,7 +396,12 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
       }
       const int n = t * 16 + col;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) L.z2[rq + i][n] = acc[i] + L.b2[n];
+      for (int i = 0; i < 4; ++i) {
+        const float z = acc[i] + L.b2[n];
+        L.z2[rq + i][n] = z;
+        const uint32_t rr = r0 + g * 16 + rq + i;
+        if (n < kOut && rr < n_rows) row_scratch[(size_t)rr * kRowScratch + kZ2 + n] = z;
+      }
     }
     __syncthreads();
     for (int item = lane; item < 16 * kNOff; item += 64) {
@@ -426,17 +442,12 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
 }
 
 // ---------------------------------------------------------------------
-// a10, part 1: one thread per (row, Gaussian).  Recomputes the Gaussian's
-// decoder outputs from the row's z1 (kept by the forward pass), runs the
-// projection adjoint, writes dz2 for the row's 11 outputs of this Gaussian
+// a10, part 1: one thread per (row, Gaussian).  Takes the Gaussian's
+// decoder outputs z2 kept by the forward decode, runs the projection
+// adjoint, writes dz2 for the row's 11 outputs of this Gaussian
 // and adds the anchor gradients of x, l and O atomically (an anchor has
 // one row per view that selects it).
 // ---------------------------------------------------------------------
-struct DecW2 {
-  float W2[kHid * kOut];
-  float b2[kOut];
-};
-
 __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restrict__ views,
                                                           cgx_anchor_scene sc,
                                                           const int2* __restrict__ rows,
@@ -444,14 +455,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
                                                           const uint32_t* __restrict__ counts,
                                                           const SplatGrad* __restrict__ sgrad,
                                                           float* __restrict__ scratch, cgx_grads gr) {
-  __shared__ DecW2 w;
   const uint32_t n_rows = ctr->n_rows;
-  // the grid covers the row capacity: blocks past the active rows leave
-  // before staging the weights
-  if ((uint64_t)blockIdx.x * blockDim.x >= (uint64_t)n_rows * kNOff) return;
-  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x) w.W2[i] = bf16_to_f32(sc.W2[i]);
-  for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
-  __syncthreads();
   const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = item / kNOff;
   const int k = (int)(item - r * kNOff);
@@ -469,12 +473,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   const uint32_t a = (uint32_t)row.y;
   float z2[kGo];
 #pragma unroll
-  for (int m = 0; m < kGo; ++m) z2[m] = w.b2[k * kGo + m];
-  for (int j = 0; j < kHid; ++j) {
-    const float zj = rs[kIn + j];
-#pragma unroll
-    for (int m = 0; m < kGo; ++m) z2[m] += zj * w.W2[j * kOut + k * kGo + m];
-  }
+  for (int m = 0; m < kGo; ++m) z2[m] = rs[kZ2 + k * kGo + m];     // kept by the forward decode
   ProjIn in;
   float sig_s[3];
   decoded_gaussian(sc, a, k, z2, in, sig_s);
@@ -517,7 +516,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
 // for the weight-gradient reduction.
 // ---------------------------------------------------------------------
 constexpr int kMlpRows = 8;      // rows in flight per block (32 threads each)
-constexpr int kMlpGroups = 8;    // row groups per block, sharing one weight staging
+constexpr int kMlpGroups = 4;    // row groups per block, sharing one weight staging
 
 __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
                                                         cgx_anchor_scene sc,
@@ -572,15 +571,16 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
     __syncthreads();
     if (live && j == 0) {
       const ViewDev& V = views[rows[r].x];
-      DecIn d;
-      decoder_input(V, sc, a, d);
-#pragma unroll
-      for (int i = CGX_FEAT_DIM; i < kIn; ++i) rs[i] = d.z0[i];
+      float dir[3], dist;
+      decoder_dir(V, sc, a, dir, dist);
+      rs[CGX_FEAT_DIM + 0] = dir[0];
+      rs[CGX_FEAT_DIM + 1] = dir[1];
+      rs[CGX_FEAT_DIM + 2] = dir[2];
+      rs[CGX_FEAT_DIM + 3] = dist / sc.d_max;
       // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
-      const float* dir = d.z0 + 32;
       const float* dz0 = s_tail[rl];
       const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
-      const float il = 1.0f / d.dist;
+      const float il = 1.0f / dist;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
@@ -671,14 +671,17 @@ __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scr
 
   for (uint64_t base = b0; base < b1; base += kWR) {
     const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
-    const float2* src = reinterpret_cast<const float2*>(scratch + base * kRowScratch);
-    // stage: element pair e of the chunk holds values 2e, 2e + 1 (a row has an
-    // even count, so a pair never straddles two rows)
-    constexpr int kPairs = kWR * kRowScratch / 2;
+    const float* src = scratch + base * kRowScratch;
+    // stage: element pair e of the chunk is values q0, q0 + 1 of row r, over
+    // the kRowUsed leading values of each row (even counts and strides, so a
+    // pair never straddles two rows and stays 8-byte aligned)
+    constexpr int kHalf = kRowUsed / 2;
+    constexpr int kPairs = kWR * kHalf;
 #pragma unroll 4
     for (int e = lane; e < kPairs; e += 64) {
-      const int r = (2 * e) / kRowScratch, q0 = 2 * e - r * kRowScratch;
-      const float2 x = r < nr ? src[e] : float2{0.0f, 0.0f};
+      const int r = e / kHalf, q0 = 2 * (e - r * kHalf);
+      const float2 x = r < nr ? *reinterpret_cast<const float2*>(src + (size_t)r * kRowScratch + q0)
+                              : float2{0.0f, 0.0f};
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = q0 + h;
