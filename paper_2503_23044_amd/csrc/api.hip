@@ -176,6 +176,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.scan_part = take(sizeof(unsigned long long) * kScanBlocks);
   L.rows = take(sizeof(int2) * (size_t)L.max_rows);
   L.row_off = take(sizeof(uint32_t) * (B + 1));
+  L.rinv = take(s->kind == CGX_SCENE_ANCHOR ? sizeof(uint32_t) * (size_t)s->an.n_anchor * B : 1);
   L.splats = take(sizeof(Splat) * (size_t)L.max_splats);
   L.counts = take(sizeof(uint32_t) * (size_t)L.max_splats);
   L.offsets = take(sizeof(uint32_t) * (size_t)L.max_splats);
@@ -245,6 +246,7 @@ struct Ptrs {
   unsigned long long* part;
   int2* rows;
   uint32_t* row_off;
+  uint32_t* rinv;
   Splat* splats;
   uint32_t* counts;
   uint32_t* offsets;
@@ -271,6 +273,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
   p.part = at<unsigned long long>(ws, L.scan_part);
   p.rows = at<int2>(ws, L.rows);
   p.row_off = at<uint32_t>(ws, L.row_off);
+  p.rinv = at<uint32_t>(ws, L.rinv);
   p.splats = at<Splat>(ws, L.splats);
   p.counts = at<uint32_t>(ws, L.counts);
   p.offsets = at<uint32_t>(ws, L.offsets);
@@ -337,8 +340,8 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
     phase_end(c, st);
   } else {
     phase_begin(c, CGX_PHASE_SELECT, st);
-    launch_select_anchors(P.views, B, s->an, P.part, P.rows, P.row_off, (uint32_t)L.max_rows,
-                          P.ctr, st);
+    launch_select_anchors(P.views, B, s->an, P.part, P.rows, P.row_off, P.rinv,
+                          (uint32_t)L.max_rows, P.ctr, st);
     phase_end(c, st);
     phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
@@ -473,8 +476,8 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   if (expl) {
     launch_project_explicit_backward(P.views, B, s->ex, P.counts, P.sgrad, *g, st);
   } else {
-    launch_decode_project_backward(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, P.counts,
-                                   P.sgrad, P.ctr, *g, P.dz, st);
+    launch_decode_project_backward(P.views, B, s->an, P.rows, P.rinv, (uint32_t)L.max_rows,
+                                   P.counts, P.sgrad, P.ctr, *g, P.dz, st);
   }
   phase_end(c, st);
   HIP_OK(c, hipGetLastError());

@@ -114,7 +114,7 @@ struct ViewPack {
 };
 
 struct Layout {
-  size_t views, counters, scan_part, rows, row_off, splats, counts, offsets, zkey;
+  size_t views, counters, scan_part, rows, row_off, rinv, splats, counts, offsets, zkey;
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
@@ -256,7 +256,6 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 // launchers (defined in the .hip files)
 // ----------------------------------------------------------------------
 void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStream_t s);
-void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s);
 
 // Pairs handled by one block of the pair emission.
@@ -292,7 +291,7 @@ void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_sce
                              hipStream_t s);
 void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            unsigned long long* part, int2* rows, uint32_t* row_off,
-                           uint32_t max_rows, Counters* ctr, hipStream_t s);
+                           uint32_t* rinv, uint32_t max_rows, Counters* ctr, hipStream_t s);
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
                            uint32_t* counts, uint32_t* zkey, Counters* ctr, float* row_scratch,
@@ -346,11 +345,11 @@ void launch_project_explicit_backward(const ViewDev* views, int B, const cgx_exp
                                       const uint32_t* counts, const SplatGrad* sgrad,
                                       const cgx_grads& g, hipStream_t s);
 void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
-                                    const int2* rows, uint32_t max_rows, const uint32_t* counts,
-                                    const SplatGrad* sgrad, const Counters* ctr,
-                                    const cgx_grads& g, float* scratch, hipStream_t s);
+                                    const int2* rows, const uint32_t* rinv, uint32_t max_rows,
+                                    const uint32_t* counts, const SplatGrad* sgrad,
+                                    const Counters* ctr, const cgx_grads& g, float* scratch,
+                                    hipStream_t s);
 size_t anchor_scratch_bytes(int64_t max_rows);
-void launch_zero_f32(float* p, size_t n, hipStream_t s);
 void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const float* normal,
                      const float* plane_d, const int32_t* centres, int n_patch, float weight,
                      float* grad_rgb, float* loss, hipStream_t s);

@@ -13,11 +13,17 @@ constexpr int kGo = CGX_GAUSS_OUT;       // 11
 constexpr int kNOff = 10;                // Gaussians per anchor in this build
 constexpr int kOut = kNOff * kGo;        // 110
 // per row: z0, z1, dz1, dz2 (the weight-gradient operands), then z2 kept by
-// the forward decode for the Gaussian adjoint
+// the forward decode for the Gaussian adjoint, then the row's terms of the
+// anchor gradients: per Gaussian d(mu) and the scale term (6 values), the
+// feature gradient (32) and the direction term of x (3)
 constexpr int kRowUsed = kIn + kHid + kHid + kOut;
 constexpr int kZ2 = kRowUsed;
-constexpr int kRowScratch = kRowUsed + kOut;
-static_assert(kRowUsed % 2 == 0 && kRowScratch % 2 == 0, "row scratch is read in float pairs");
+constexpr int kGSum = kZ2 + kOut;
+constexpr int kDF = kGSum + 6 * kNOff;
+constexpr int kDX = kDF + CGX_FEAT_DIM;
+constexpr int kRowScratch = kDX + 4;
+static_assert(kRowUsed % 2 == 0 && kRowScratch % 4 == 0, "row scratch is read in float pairs");
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 constexpr int kWGrad = kIn * kHid + kHid * kOut + kHid + kOut;   // 4814
 
 // ---------------------------------------------------------------------
@@ -117,6 +123,7 @@ __global__ __launch_bounds__(256) void k_select_write(const ViewDev* __restrict_
                                                       const unsigned long long* part,
                                                       int2* __restrict__ rows,
                                                       uint32_t* __restrict__ row_off,
+                                                      uint32_t* __restrict__ rinv,
                                                       uint32_t max_rows) {
   __shared__ unsigned long long lw[4];
   const uint64_t A = (uint64_t)sc.n_anchor;
@@ -139,7 +146,9 @@ __global__ __launch_bounds__(256) void k_select_write(const ViewDev* __restrict_
     if (i < b1) {
       const unsigned long long pos = carry + inc - f;
       if (a == 0) row_off[v] = (uint32_t)(pos < max_rows ? pos : max_rows);
-      if (f && pos < max_rows) rows[pos] = make_int2(v, (int)a);
+      const bool kept = f && pos < max_rows;
+      if (kept) rows[pos] = make_int2(v, (int)a);
+      rinv[i] = kept ? (uint32_t)pos : kNoRow;     // inverse map, index v * A + a
     }
     carry += tot;
   }
@@ -147,12 +156,12 @@ __global__ __launch_bounds__(256) void k_select_write(const ViewDev* __restrict_
 
 void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            unsigned long long* part, int2* rows, uint32_t* row_off,
-                           uint32_t max_rows, Counters* ctr, hipStream_t s) {
+                           uint32_t* rinv, uint32_t max_rows, Counters* ctr, hipStream_t s) {
   hipLaunchKernelGGL(k_select_count, dim3(kScanBlocks), dim3(256), 0, s, views, B, sc, part);
   hipLaunchKernelGGL(k_select_top, dim3(1), dim3(kScanBlocks), 0, s, part, max_rows, sc.n_offsets,
                      row_off, B, ctr);
   hipLaunchKernelGGL(k_select_write, dim3(kScanBlocks), dim3(256), 0, s, views, B, sc,
-                     (const unsigned long long*)part, rows, row_off, max_rows);
+                     (const unsigned long long*)part, rows, row_off, rinv, max_rows);
 }
 
 // ---------------------------------------------------------------------
@@ -203,18 +212,21 @@ __device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor
   d.z0[35] = d.dist / sc.d_max;
 }
 
-struct DecW {
-  float W1[kIn * kHid];
-  float W2[kHid * kOut];
-  float b1[kHid];
-  float b2[kOut];
+// decoder weights for the adjoint, float32 in LDS; rows padded to an odd
+// stride so that the 32 lanes of a row, which read 32 different weight rows
+// at the same column, hit 32 different banks
+constexpr int kW1s = kHid + 1;
+constexpr int kW2s = kOut + 1;
+struct DecWT {
+  float W1[kIn * kW1s];
+  float W2[kHid * kW2s];
 };
 
-__device__ __forceinline__ void load_weights(DecW& w, const cgx_anchor_scene& sc) {
-  for (int i = threadIdx.x; i < kIn * kHid; i += blockDim.x) w.W1[i] = bf16_to_f32(sc.W1[i]);
-  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x) w.W2[i] = bf16_to_f32(sc.W2[i]);
-  for (int i = threadIdx.x; i < kHid; i += blockDim.x) w.b1[i] = sc.b1[i];
-  for (int i = threadIdx.x; i < kOut; i += blockDim.x) w.b2[i] = sc.b2[i];
+__device__ __forceinline__ void load_weights(DecWT& w, const cgx_anchor_scene& sc) {
+  for (int i = threadIdx.x; i < kIn * kHid; i += blockDim.x)
+    w.W1[(i / kHid) * kW1s + i % kHid] = bf16_to_f32(sc.W1[i]);
+  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x)
+    w.W2[(i / kOut) * kW2s + i % kOut] = bf16_to_f32(sc.W2[i]);
 }
 
 // decoded attributes of Gaussian k of a row, in projection form
@@ -444,9 +456,9 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
 // ---------------------------------------------------------------------
 // a10, part 1: one thread per (row, Gaussian).  Takes the Gaussian's
 // decoder outputs z2 kept by the forward decode, runs the projection
-// adjoint, writes dz2 for the row's 11 outputs of this Gaussian
-// and adds the anchor gradients of x, l and O atomically (an anchor has
-// one row per view that selects it).
+// adjoint, writes dz2 for the row's 11 outputs of this Gaussian and keeps
+// the row's terms of the anchor gradients, d(mu) (which gives x and, times
+// l, the offset O) and d(mu) O + ds sigma(s) (which gives l), for part 3.
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restrict__ views,
                                                           cgx_anchor_scene sc,
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
                                                           const Counters* ctr,
                                                           const uint32_t* __restrict__ counts,
                                                           const SplatGrad* __restrict__ sgrad,
-                                                          float* __restrict__ scratch, cgx_grads gr) {
+                                                          float* __restrict__ scratch) {
   const uint32_t n_rows = ctr->n_rows;
   const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = item / kNOff;
@@ -462,10 +474,13 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   if (r >= n_rows) return;
   float* rs = scratch + (size_t)r * kRowScratch;
   float* dz2 = rs + kIn + 2 * kHid + k * kGo;
+  float* gs = rs + kGSum + 6 * k;
   const uint32_t slot = item;
   if (counts[slot] == 0) {
 #pragma unroll
     for (int m = 0; m < kGo; ++m) dz2[m] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) gs[m] = 0.0f;
     return;
   }
   const int2 row = rows[r];
@@ -490,6 +505,11 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   project_backward(V, in, st, gg, dmu, ds, dq);
   const float* L = sc.l + 3 * (size_t)a;
   const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    gs[c] = dmu[c];
+    gs[3 + c] = ds[c] * sig_s[c] + dmu[c] * O[c];
+  }
   dz2[0] = gg[5] * in.op * (1.0f - in.op);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -498,22 +518,15 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) dz2[7 + c] = dq[c];
-  float* gO = gr.O + ((size_t)a * kNOff + k) * 3;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    atomic_add_f32(gO + c, dmu[c] * L[c]);
-    atomic_add_f32(gr.x + 3 * (size_t)a + c, dmu[c]);
-    atomic_add_f32(gr.l + 3 * (size_t)a + c, ds[c] * sig_s[c] + dmu[c] * O[c]);
-  }
 }
 
 // ---------------------------------------------------------------------
-// a10, part 2: 32 threads per row, 8 rows at a time, 64 rows per block
+// a10, part 2: 32 threads per row, 8 rows at a time, 32 rows per block
 // (one weight staging).  Thread j of a row forms dz1[j] = (dz2 W2^T)[j] *
 // [z1[j] > 0] from the row's dz2 staged in LDS, then dz0[j] = (dz1 W1^T)[j]
-// for the 32 features (-> dF) and, in threads 0..3, the four direction /
-// distance inputs, which one thread takes back to dx.  z0 and dz1 are kept
-// for the weight-gradient reduction.
+// for the 32 features (the row's term of dF) and, in threads 0..3, the four
+// direction / distance inputs, which one thread takes back to the row's
+// term of dx.  z0 and dz1 are kept for the weight-gradient reduction.
 // ---------------------------------------------------------------------
 constexpr int kMlpRows = 8;      // rows in flight per block (32 threads each)
 constexpr int kMlpGroups = 4;    // row groups per block, sharing one weight staging
@@ -522,8 +535,8 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
                                                         cgx_anchor_scene sc,
                                                         const int2* __restrict__ rows,
                                                         const Counters* ctr,
-                                                        float* __restrict__ scratch, cgx_grads gr) {
-  __shared__ DecW w;
+                                                        float* __restrict__ scratch) {
+  __shared__ DecWT w;
   __shared__ float s_dz2[kMlpRows][kOut];
   __shared__ float s_dz1[kMlpRows][kHid];
   __shared__ float s_tail[kMlpRows][4];
@@ -547,7 +560,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
     float* rs = scratch + (size_t)r * kRowScratch;
     if (live) {
       float acc = 0.0f;
-      for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kOut + c];
+      for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kW2s + c];
       acc = rs[kIn + j] > 0.0f ? acc : 0.0f;
       s_dz1[rl][j] = acc;
       rs[kIn + kHid + j] = acc;
@@ -559,12 +572,12 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
       rs[j] = bf16_round(sc.F[(size_t)a * CGX_FEAT_DIM + j]);    // z0 feature part
       float acc = 0.0f;
 #pragma unroll 8
-      for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kHid + k];
-      atomic_add_f32(gr.F + (size_t)a * CGX_FEAT_DIM + j, acc);
+      for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kW1s + k];
+      rs[kDF + j] = acc;
       if (j < 4) {
         float t = 0.0f;
 #pragma unroll 8
-        for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kHid + k];
+        for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kW1s + k];
         s_tail[rl][j] = t;
       }
     }
@@ -584,10 +597,115 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
-        atomic_add_f32(gr.x + 3 * (size_t)a + c, -ddelta);
+        rs[kDX + c] = -ddelta;
       }
     }
     __syncthreads();
+  }
+}
+
+// a10, part 3: the anchor gradients, gathered (no atomics, no clearing
+// pass).  A one-wave block takes 8 consecutive anchors.  It reads the
+// inverse row map for all of them at once and lists their rows in LDS in
+// (anchor, view) order; then it walks the list 8 entries at a time, the
+// loads of all 8 in flight together, and adds each row's terms: lane j < 32
+// feature j, lanes 32..61 offset (k, c) = (t / 3, t % 3), t = j - 32, with
+// its scale-term partner, lanes 0..2 the direction term of x.  When the
+// anchor changes, x_c and l_c add the ten offsets' sums in k order and the
+// anchor is written.  Every sum runs in a fixed order, so the result is
+// deterministic.  Anchors no view selects get zeros.
+constexpr int kGatherPerWave = 8;
+constexpr int kGatherList = kGatherPerWave * CGX_MAX_VIEWS;
+constexpr int kGatherUnroll = 8;
+// list entry: row | anchor-in-wave << 29; rows number at most 2^31 / 10
+// (the splat slots, 10 per row, are capped at 2^31 - 1), below 2^29
+constexpr int kEntryShift = 29;
+constexpr uint32_t kEntryRow = (1u << kEntryShift) - 1;
+static_assert(kGatherPerWave <= (1 << (32 - kEntryShift)), "anchor index field");
+
+__global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int B,
+                                                       const uint32_t* __restrict__ rinv,
+                                                       const float* __restrict__ scratch,
+                                                       cgx_grads gr) {
+  __shared__ uint32_t s_e[kGatherList];
+  const uint32_t A = (uint32_t)sc.n_anchor;
+  const uint32_t a0 = blockIdx.x * kGatherPerWave;
+  if (a0 >= A) return;
+  const int j = threadIdx.x;
+  const int t = j - CGX_FEAT_DIM;
+  const bool off = t >= 0 && t < 3 * kNOff;
+  const int src = j < CGX_FEAT_DIM ? kDF + j : off ? kGSum + 6 * (t / 3) + t % 3 : kDF;
+  const int xs = kDX + (j < 3 ? j : 0);
+  // the wave's rows, (anchor, view) order
+  const int np = kGatherPerWave * B;
+  uint32_t n = 0;
+  for (int p0 = 0; p0 < np; p0 += kWave) {
+    const int p = p0 + j;
+    const int g = p / B, v = p - g * B;
+    uint32_t r = kNoRow;
+    if (p < np && a0 + g < A) r = rinv[(size_t)v * A + a0 + g];
+    const uint64_t m = __ballot(r != kNoRow);
+    if (r != kNoRow) s_e[n + __popcll(m & ((1ull << j) - 1))] = r | (uint32_t)g << kEntryShift;
+    n += (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  float acc = 0.0f, accl = 0.0f, accx = 0.0f;
+  int cur = -1;                                // anchor being summed (uniform)
+  uint32_t done = 0;
+  auto flush = [&]() {
+    const uint32_t a = a0 + (uint32_t)cur;
+    // x_c = sum_k d(mu)_{k,c} + direction term, l_c = sum_k scale terms
+    float gx = accx, gl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kNOff; ++k) {
+      const int from = CGX_FEAT_DIM + 3 * k + (j < 3 ? j : 0);
+      gx += __shfl(acc, from, kWave);
+      gl += __shfl(accl, from, kWave);
+    }
+    if (j < CGX_FEAT_DIM) gr.F[(size_t)a * CGX_FEAT_DIM + j] = acc;
+    else if (off) gr.O[(size_t)a * 3 * kNOff + t] = acc * sc.l[3 * (size_t)a + t % 3];
+    if (j < 3) {
+      gr.x[3 * (size_t)a + j] = gx;
+      gr.l[3 * (size_t)a + j] = gl;
+    }
+    done |= 1u << cur;
+  };
+  for (uint32_t i = 0; i < n; i += kGatherUnroll) {
+    uint32_t eg[kGatherUnroll];
+    float vs[kGatherUnroll], vl[kGatherUnroll], vx[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      // past the end: repeat entry i (loaded, never added)
+      const uint32_t e = __builtin_amdgcn_readfirstlane(s_e[i + u < n ? i + u : i]);
+      eg[u] = e >> kEntryShift;
+      const float* rs = scratch + (size_t)(e & kEntryRow) * kRowScratch;
+      vs[u] = rs[src];
+      vl[u] = rs[src + 3];
+      vx[u] = rs[xs];
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      if (i + u >= n) break;
+      if ((int)eg[u] != cur) {
+        if (cur >= 0) flush();
+        cur = (int)eg[u];
+        acc = accl = accx = 0.0f;
+      }
+      acc += vs[u];
+      accl += vl[u];
+      accx += vx[u];
+    }
+  }
+  if (cur >= 0) flush();
+  for (int g = 0; g < kGatherPerWave; ++g) {
+    const uint32_t a = a0 + g;
+    if ((done >> g & 1u) || a >= A) continue;
+    if (j < CGX_FEAT_DIM) gr.F[(size_t)a * CGX_FEAT_DIM + j] = 0.0f;
+    else if (off) gr.O[(size_t)a * 3 * kNOff + t] = 0.0f;
+    if (j < 3) {
+      gr.x[3 * (size_t)a + j] = 0.0f;
+      gr.l[3 * (size_t)a + j] = 0.0f;
+    }
   }
 }
 
@@ -772,24 +890,23 @@ size_t anchor_scratch_bytes(int64_t max_rows) {
 }
 
 void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
-                                    const int2* rows, uint32_t max_rows, const uint32_t* counts,
-                                    const SplatGrad* sgrad, const Counters* ctr,
-                                    const cgx_grads& g, float* scratch, hipStream_t s) {
-  (void)B;
-  const size_t A = (size_t)sc.n_anchor;
-  launch_zero_f32(g.x, 3 * A, s);
-  launch_zero_f32(g.l, 3 * A, s);
-  launch_zero_f32(g.O, 3 * A * kNOff, s);
-  launch_zero_f32(g.F, A * CGX_FEAT_DIM, s);
+                                    const int2* rows, const uint32_t* rinv, uint32_t max_rows,
+                                    const uint32_t* counts, const SplatGrad* sgrad,
+                                    const Counters* ctr, const cgx_grads& g, float* scratch,
+                                    hipStream_t s) {
   float* partial = scratch + (size_t)max_rows * kRowScratch;
   const uint32_t gblocks = div_up((uint64_t)max_rows * kNOff, 256);
   if (gblocks)
     hipLaunchKernelGGL(k_decode_bwd_gauss, dim3(gblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                       counts, sgrad, scratch, g);
+                       counts, sgrad, scratch);
   const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
   if (rblocks)
     hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                       scratch, g);
+                       scratch);
+  const uint32_t ablocks = div_up((uint64_t)sc.n_anchor, kGatherPerWave);
+  if (ablocks)
+    hipLaunchKernelGGL(k_anchor_grad, dim3(ablocks), dim3(kWave), 0, s, sc, B, rinv,
+                       (const float*)scratch, g);
   hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(64), 0, s, (const float*)scratch, ctr,
                      partial);
   hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 32)), dim3(256), 0, s,

@@ -1,4 +1,4 @@
-// Small utility kernels: view upload, fills, counters, the device-wide
+// Small utility kernels: view upload, counters, the device-wide
 // exclusive scan of per-splat tile counts (pair offsets, a3) and the tile
 // ranges of the sorted pairs (a5).
 #include "cgx_common.h"
@@ -12,22 +12,6 @@ __global__ void k_upload_views(ViewPack pack, int count, ViewDev* dst) {
 
 void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_upload_views, dim3(1), dim3(kWave), 0, s, pack, count, dst);
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = value;
-}
-
-void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
-  if (n == 0) return;
-  uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
-}
-
-void launch_zero_f32(float* p, size_t n, hipStream_t s) {
-  launch_fill_u32(reinterpret_cast<uint32_t*>(p), 0u, n, s);
 }
 
 __global__ void k_init_counters(Counters* c, uint32_t n_splats, WsHeader h) {
