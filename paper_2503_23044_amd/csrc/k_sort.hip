@@ -44,23 +44,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(const uint32_t* _
                                                                int shift) {
   constexpr int R = 1 << BITS;
   constexpr int NW = kSortThreads / kWave;
-  __shared__ uint32_t h[NW][R];
+  __shared__ uint32_t h[NW][R + 1];            // column R counts the keys past the end
   const int wave = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < NW * R; i += kSortThreads) (&h[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < NW * (R + 1); i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   uint32_t b0, b1;
   sort_chunk(clamp_count(n_dev, cap), b0, b1);
-  // kSortItems keys per thread per step, loads issued before the LDS adds
+  // kSortItems keys per thread per step, loaded one step ahead of the LDS
+  // adds; no branches: indices past the end read the chunk's last key
+  // (always in the buffer) and count in column R
+  const uint32_t last = b1 > 0 ? b1 - 1 : 0;
+  uint32_t nk[kSortItems];
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint32_t i = b0 + it * kSortThreads + threadIdx.x;
+    nk[it] = keys[i < last ? i : last];
+  }
   for (uint32_t base = b0; base < b1; base += kSortTile) {
     uint32_t d[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
       const uint32_t i = base + it * kSortThreads + threadIdx.x;
-      d[it] = i < b1 ? (keys[i] >> shift) & (R - 1) : 0xFFFFFFFFu;
+      d[it] = i < b1 ? (nk[it] >> shift) & (R - 1) : (uint32_t)R;
+    }
+    __builtin_amdgcn_sched_barrier(0);         // the digits above wait for nk, not the loads below
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+      const uint32_t inext = base + kSortTile + it * kSortThreads + threadIdx.x;
+      nk[it] = keys[inext < last ? inext : last];
     }
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it)
-      if (d[it] != 0xFFFFFFFFu) atomicAdd(&h[wave][d[it]], 1u);
+    for (int it = 0; it < kSortItems; ++it) atomicAdd(&h[wave][d[it]], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < R; d += kSortThreads) {
@@ -150,20 +164,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(
   sort_chunk(clamp_count(n_dev, cap), b0, b1);
   __syncthreads();
 
+  // a tile's keys and values are loaded while the previous tile is written
+  // out (the ranking is serialised by wave barriers, which loads do not
+  // cross)
+  uint32_t rkey[kSortItems], rval[kSortItems];
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint32_t idx = b0 + wave * SEG + it * kWave + lane;
+    rkey[it] = idx < b1 ? kin[idx] : 0u;
+    rval[it] = idx < b1 ? vin[idx] : 0u;
+  }
   for (uint32_t tb = b0; tb < b1; tb += kSortTile) {
     for (int d = lane; d < R; d += kWave) wave_cnt[wave][d] = 0;
-    __syncthreads();
-    uint32_t rkey[kSortItems], rval[kSortItems], rank[kSortItems];
+    uint32_t rank[kSortItems];
     int rdig[kSortItems];
+    __syncthreads();
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
       const uint32_t idx = tb + wave * SEG + it * kWave + lane;
       const bool valid = idx < b1;
-      uint32_t k = 0, v = 0;
-      if (valid) {
-        k = kin[idx];
-        v = vin[idx];
-      }
+      const uint32_t k = rkey[it];
       const int d = (int)((k >> shift) & (R - 1));
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -177,8 +197,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(
       __builtin_amdgcn_wave_barrier();
       if (valid && below == 0) wave_cnt[wave][d] = prev + (uint32_t)__popcll(peers);
       __builtin_amdgcn_wave_barrier();
-      rkey[it] = k;
-      rval[it] = v;
       rdig[it] = valid ? d : -1;
       rank[it] = prev + below;
     }
@@ -223,6 +241,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(
           s_val[pos] = rval[it];
         }
       }
+    }
+    // next tile
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+      const uint32_t idx = tb + kSortTile + wave * SEG + it * kWave + lane;
+      rkey[it] = idx < b1 ? kin[idx] : 0u;
+      rval[it] = idx < b1 ? vin[idx] : 0u;
     }
     __syncthreads();
     const uint32_t n_valid = (b1 - tb) < (uint32_t)kSortTile ? (b1 - tb) : (uint32_t)kSortTile;
