@@ -220,7 +220,10 @@ int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
 /* One launch chain: forward, the batch L1 loss of Eq. 8 against `target`
  * (rgb, depth and normal, weights w[0..2]; per-image mean over pixels,
  * averaged over the batch, sign(0) = 0) and the backward pass.  loss_dev:
- * one float on the device receiving the loss (may be NULL). */
+ * one float on the device receiving the loss (may be NULL).  The depth
+ * target is the filtered depth prior of Sec. 3.4, Step 2: a target depth
+ * that is not positive (or NaN) marks a pixel without a prior, which adds
+ * no depth loss and no depth gradient (the per-image mean still counts it). */
 int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                               const cgx_scene* scene, const cgx_capacity* cap,
                               void* workspace, size_t workspace_bytes,

@@ -314,7 +314,13 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
 def l1_seed(images, targets, weights=(1.0, 1.0, 1.0)):
     """L = (1/B) sum_b (1/(H_b W_b)) sum_px [w_rgb |C - C*|_1 + w_d |D^ - D^*|
     + w_n |N - N*|_1]; returns (L, per-view output gradients) with
-    sign(0) = 0.  The plane-distance map D and alpha get zero gradient."""
+    sign(0) = 0.  The plane-distance map D and alpha get zero gradient.
+
+    Depth prior mask (Sec. 3.4, Step 2): the depth target is the filtered
+    pseudo depth, which holds no value where the reprojection filter removed
+    it.  A target depth that is not positive (the zero of a filtered pixel)
+    or is NaN marks such a pixel: it adds no depth loss and no depth
+    gradient, and the per-image scale still counts every pixel."""
     B = len(images)
     L = 0.0
     grads = []
@@ -322,7 +328,10 @@ def l1_seed(images, targets, weights=(1.0, 1.0, 1.0)):
         npx = img["depth"].size
         sc = 1.0 / (B * npx)
         er = img["rgb"] - np.asarray(targets["rgb"][b], np.float64)
-        ed = img["depth"] - np.asarray(targets["depth"][b], np.float64)
+        td = np.asarray(targets["depth"][b], np.float64)
+        with np.errstate(invalid="ignore"):
+            keep = td > 0.0                        # False for NaN
+        ed = np.where(keep, img["depth"] - np.where(keep, td, 0.0), 0.0)
         en = img["normal"] - np.asarray(targets["normal"][b], np.float64)
         L += sc * (weights[0] * np.abs(er).sum() + weights[1] * np.abs(ed).sum()
                    + weights[2] * np.abs(en).sum())
@@ -332,7 +341,7 @@ def l1_seed(images, targets, weights=(1.0, 1.0, 1.0)):
         # sign(out - target) is a decision: a pixel whose output lies within
         # FRAG_SIGN of its target may take the other sign in float32
         if "frag_grad" in img:
-            near = ((np.abs(er) < FRAG_SIGN).any(axis=0) | (np.abs(ed) < FRAG_SIGN)
+            near = ((np.abs(er) < FRAG_SIGN).any(axis=0) | (keep & (np.abs(ed) < FRAG_SIGN))
                     | (np.abs(en) < FRAG_SIGN).any(axis=0))
             img["frag_grad"] = img["frag_grad"] | near
     return L, grads

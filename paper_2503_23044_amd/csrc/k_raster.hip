@@ -224,9 +224,14 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         gc[c] = a.w_rgb * inv_px * sgnf(e);
         loss += a.w_rgb * inv_px * fabsf(e);
       }
-      const float ed = a.depth[pv + p] - a.t_depth[pv + p];
-      gh = a.w_depth * inv_px * sgnf(ed);
-      loss += a.w_depth * inv_px * fabsf(ed);
+      // a target depth that is not positive (or NaN) marks a pixel the
+      // depth-prior filter removed: no depth term there
+      const float td = a.t_depth[pv + p];
+      if (td > 0.0f) {
+        const float ed = a.depth[pv + p] - td;
+        gh = a.w_depth * inv_px * sgnf(ed);
+        loss += a.w_depth * inv_px * fabsf(ed);
+      }
       const float nn[3] = {n0, n1, n2};
       for (int c = 0; c < 3; ++c) {
         const float e = nn[c] - a.t_normal[3 * pv + c * HW + p];

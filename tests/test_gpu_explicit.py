@@ -49,9 +49,23 @@ def test_c0_forward_and_sort(R):
     assert dbg["info"]["entries_fwd"] == walked
 
 
-def test_c0_fused_l1_backward(R):
-    print("case: C0 fused L1", flush=True)
+@pytest.mark.parametrize("masked", [False, True])
+def test_c0_fused_l1_backward(R, masked):
+    print(f"case: C0 fused L1 masked={masked}", flush=True)
     wl = scenes.make_c0()
+    if masked:
+        # depth-prior mask: pixels the filter removed carry a non-positive or
+        # NaN target depth and add no depth term
+        rng = np.random.default_rng(41)
+        dep = []
+        for t in wl.targets["depth"]:
+            t = np.array(t, np.float32)
+            u = rng.random(t.size)
+            t[u < 0.30] = 0.0
+            t[(u >= 0.30) & (u < 0.35)] = np.nan
+            t[(u >= 0.35) & (u < 0.40)] = -1.0
+            dep.append(t)
+        wl.targets["depth"] = dep
     rd = R.Renderer(0, (16, 16))
     sc = R.scene_from(wl.scene)
     P = wl.pixels

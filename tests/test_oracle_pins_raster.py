@@ -270,6 +270,57 @@ def test_l1_seed_hand_example():
         np.testing.assert_array_equal(gr["normal"], np.array(ex["normal"]))
 
 
+def _golden_l1(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        g = json.load(fh)
+    images = [dict(rgb=np.array(im["rgb"], float), depth=np.array(im["depth"], float),
+                   normal=np.array(im["normal"], float)) for im in g["images"]]
+    targets = dict(rgb=[np.array(t["rgb"], float) for t in g["targets"]],
+                   depth=[np.array(t["depth"], float) for t in g["targets"]],
+                   normal=[np.array(t["normal"], float) for t in g["targets"]])
+    return g, images, targets
+
+
+def test_l1_seed_depth_mask_hand_example():
+    """Sec. 3.4 Step 2: target depths that are not positive carry no prior;
+    worked out by hand in tests/golden/l1_seed_masked.json."""
+    g, images, targets = _golden_l1("l1_seed_masked.json")
+    L, grads = raster.l1_seed(images, targets)
+    assert abs(L - g["loss"]) < 1e-15
+    for gr, ex in zip(grads, g["grads"]):
+        for k in ("rgb", "depth", "normal"):
+            np.testing.assert_array_equal(gr[k], np.array(ex[k]))
+
+
+def test_l1_seed_nan_depth_is_masked():
+    """A NaN target depth acts as a masked pixel: same loss and gradients as
+    a zero target there, and the loss equals brute force over the kept
+    pixels only."""
+    rng = np.random.default_rng(3)
+    npx = 37
+    images = [dict(rgb=rng.random((3, npx)), depth=rng.uniform(1, 5, npx),
+                   normal=rng.standard_normal((3, npx)))]
+    td = rng.uniform(1, 5, npx)
+    drop = rng.random(npx) < 0.4
+    t0 = dict(rgb=[rng.random((3, npx))], depth=[np.where(drop, 0.0, td)],
+              normal=[rng.standard_normal((3, npx))])
+    tn = dict(rgb=t0["rgb"], depth=[np.where(drop, np.nan, td)], normal=t0["normal"])
+    L0, g0 = raster.l1_seed(images, t0, (0.5, 2.0, 0.25))
+    Ln, gn = raster.l1_seed(images, tn, (0.5, 2.0, 0.25))
+    assert L0 == Ln
+    for k in ("rgb", "depth", "normal"):
+        np.testing.assert_array_equal(g0[0][k], gn[0][k])
+    assert np.all(g0[0]["depth"][drop] == 0.0) and np.all(g0[0]["depth"][~drop] != 0.0)
+    im = images[0]
+    brute = 0.0
+    for p in range(npx):
+        brute += 0.5 * sum(abs(im["rgb"][c, p] - t0["rgb"][0][c, p]) for c in range(3))
+        brute += 0.25 * sum(abs(im["normal"][c, p] - t0["normal"][0][c, p]) for c in range(3))
+        if not drop[p]:
+            brute += 2.0 * abs(im["depth"][p] - td[p])
+    assert abs(L0 - brute / npx) < 1e-12
+
+
 def test_sampled_tiles_equal_full_render():
     """Binning and compositing a subset of tiles gives exactly the entries
     and pixels of those tiles in the full render (the bounded-sample mode
