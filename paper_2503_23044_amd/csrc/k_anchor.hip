@@ -25,6 +25,7 @@ constexpr int kRowScratch = kDX + 4;
 static_assert(kRowUsed % 2 == 0 && kRowScratch % 4 == 0, "row scratch is read in float pairs");
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 constexpr int kWGrad = kIn * kHid + kHid * kOut + kHid + kOut;   // 4814
+constexpr int kRedBlocks = 512;  // weight-gradient partials (one per reduction block)
 
 // ---------------------------------------------------------------------
 // a0: decisions in float64, fixed operation order, contraction off
@@ -222,11 +223,15 @@ struct DecWT {
   float W2[kHid * kW2s];
 };
 
-__device__ __forceinline__ void load_weights(DecWT& w, const cgx_anchor_scene& sc) {
-  for (int i = threadIdx.x; i < kIn * kHid; i += blockDim.x)
-    w.W1[(i / kHid) * kW1s + i % kHid] = bf16_to_f32(sc.W1[i]);
-  for (int i = threadIdx.x; i < kHid * kOut; i += blockDim.x)
-    w.W2[(i / kOut) * kW2s + i % kOut] = bf16_to_f32(sc.W2[i]);
+static_assert(sizeof(DecWT) % 16 == 0, "copied in 16-byte pieces");
+
+// block-wide copy of a weight image laid out in global memory by
+// k_prep_weights (16-byte pieces)
+template <typename T>
+__device__ __forceinline__ void copy_weights(T& dst, const T* src) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(&dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(T) / 16); i += blockDim.x) d[i] = s[i];
 }
 
 // decoded attributes of Gaussian k of a row, in projection form
@@ -262,9 +267,9 @@ __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uin
 //            3 k-steps x 7 column tiles.
 // A value x is carried as h + m + l with h = bf16(x), m = bf16(x - h),
 // l = bf16(x - h - m) (residual below 2^-26 |x|), so only the features
-// take a bfloat16 rounding; the rest keeps float32 accuracy.  The 16 x 112
-// output tile of a group is staged in LDS and its 160 (row, Gaussian)
-// items are projected by the wave.
+// take a bfloat16 rounding; the rest keeps float32 accuracy.  z1 and the
+// 110 outputs z2 go to the row's scratch (the adjoint reads them too), and
+// a second kernel projects the 10 Gaussians of every row, one thread each.
 //
 // Fragment layout of the 16x16x32 bf16 MFMA (lane l): A holds row l % 16,
 // k = 8 (l / 16) .. +7; B holds column l % 16, the same k; C holds column
@@ -290,14 +295,18 @@ __device__ __forceinline__ void split3(float x, uint16_t& h, uint16_t& m, uint16
   l = bf16_bits_rne(r2);
 }
 
-struct MfmaLds {
+struct DecWB {
   uint16_t w1t[kHid][kK1];      // B of layer 1, column-major (n, k)
   uint16_t w2t[kN2][kK2];       // B of layer 2, column-major (n, k)
   float b1[kHid];
   float b2[kN2];
+};
+static_assert(sizeof(DecWB) % 16 == 0, "copied in 16-byte pieces");
+
+struct MfmaLds {
+  DecWB w;
   uint16_t a1[64][kK1];         // A of layer 1 for the wave's 64 rows
   uint16_t a2[64][kK2];         // A of layer 2
-  float z2[16][kN2 + 1];        // one group's outputs (+1 pad against bank conflicts)
 };
 
 __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
@@ -314,34 +323,18 @@ __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
   return r;
 }
 
-__global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __restrict__ views,
-                                                            cgx_anchor_scene sc,
-                                                            const int2* __restrict__ rows,
-                                                            const Counters* ctr, int tw, int th,
-                                                            Splat* __restrict__ splats,
-                                                            uint32_t* __restrict__ counts,
-                                                            uint32_t* __restrict__ zkey,
-                                                            float* __restrict__ row_scratch) {
+__global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ views,
+                                                    cgx_anchor_scene sc,
+                                                    const int2* __restrict__ rows,
+                                                    const Counters* ctr,
+                                                    const DecWB* __restrict__ wimg,
+                                                    float* __restrict__ row_scratch) {
   __shared__ MfmaLds L;
   const int lane = threadIdx.x;
   const uint32_t n_rows = ctr->n_rows;
   const uint32_t r0 = blockIdx.x * 64;
   if (r0 >= n_rows) return;
-
-  // weights, transposed to (column, k) so that a lane's 8 k-values are contiguous
-  for (int i = lane; i < kHid * kK1; i += 64) {
-    const int n = i / kK1, k = i % kK1;
-    uint16_t v = 0;
-    if (k < 32) v = sc.W1[k * kHid + n];
-    else if (k < 44) v = sc.W1[(32 + (k - 32) % 4) * kHid + n];
-    L.w1t[n][k] = v;
-  }
-  for (int i = lane; i < kN2 * kK2; i += 64) {
-    const int n = i / kK2, k = i % kK2;
-    L.w2t[n][k] = n < kOut ? sc.W2[(k % kHid) * kOut + n] : (uint16_t)0;
-  }
-  for (int i = lane; i < kHid; i += 64) L.b1[i] = sc.b1[i];
-  for (int i = lane; i < kN2; i += 64) L.b2[i] = i < kOut ? sc.b2[i] : 0.0f;
+  copy_weights(L.w, wimg);
 
   // layer-1 operands of this lane's row
   const uint32_t r = r0 + lane;
@@ -375,13 +368,13 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         const bf16x8_t av = load8(&L.a1[g * 16 + col][ks * 32 + kq]);
-        const bf16x8_t bv = load8(&L.w1t[t * 16 + col][ks * 32 + kq]);
+        const bf16x8_t bv = load8(&L.w.w1t[t * 16 + col][ks * 32 + kq]);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
       }
       const int n = t * 16 + col;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float z = fmaxf(acc[i] + L.b1[n], 0.0f);
+        const float z = fmaxf(acc[i] + L.w.b1[n], 0.0f);
         uint16_t h, m, lo;
         split3(z, h, m, lo);
         uint16_t* a2 = L.a2[g * 16 + rq + i];
@@ -403,43 +396,110 @@ __global__ __launch_bounds__(64) void k_decode_project_mfma(const ViewDev* __res
 #pragma unroll
       for (int ks = 0; ks < 3; ++ks) {
         const bf16x8_t av = load8(&L.a2[g * 16 + col][ks * 32 + kq]);
-        const bf16x8_t bv = load8(&L.w2t[t * 16 + col][ks * 32 + kq]);
+        const bf16x8_t bv = load8(&L.w.w2t[t * 16 + col][ks * 32 + kq]);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
       }
       const int n = t * 16 + col;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float z = acc[i] + L.b2[n];
-        L.z2[rq + i][n] = z;
+        const float z = acc[i] + L.w.b2[n];
         const uint32_t rr = r0 + g * 16 + rq + i;
         if (n < kOut && rr < n_rows) row_scratch[(size_t)rr * kRowScratch + kZ2 + n] = z;
       }
     }
-    __syncthreads();
-    for (int item = lane; item < 16 * kNOff; item += 64) {
-      const int rl = item / kNOff, k = item % kNOff;
-      const uint32_t rr = r0 + g * 16 + rl;
-      if (rr >= n_rows) continue;
-      const int2 row = rows[rr];
-      const ViewDev& V = views[row.x];
-      float z2[kGo];
-#pragma unroll
-      for (int m = 0; m < kGo; ++m) z2[m] = L.z2[rl][k * kGo + m];
-      ProjIn in;
-      float sig_s[3];
-      decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
-      Splat o;
-      uint32_t zb = 0;
-      const uint32_t slot = rr * kNOff + k;
-      const uint32_t cnt = project_splat(V, in, tw, th, o, zb);
-      counts[slot] = cnt;
-      if (cnt) {
-        splats[slot] = o;
-        zkey[slot] = zb;
-      }
-    }
-    __syncthreads();
   }
+}
+
+// a1 activations + a2: one thread per (row, Gaussian) projects the decoded
+// Gaussian from the outputs z2 the decode kept in row scratch.
+__global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restrict__ views,
+                                                         cgx_anchor_scene sc,
+                                                         const int2* __restrict__ rows,
+                                                         const Counters* ctr, int tw, int th,
+                                                         const float* __restrict__ row_scratch,
+                                                         Splat* __restrict__ splats,
+                                                         uint32_t* __restrict__ counts,
+                                                         uint32_t* __restrict__ zkey) {
+  const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t r = item / kNOff;
+  const int k = (int)(item - r * kNOff);
+  if (r >= ctr->n_rows) return;
+  const int2 row = rows[r];
+  const ViewDev& V = views[row.x];
+  const float* zp = row_scratch + (size_t)r * kRowScratch + kZ2 + k * kGo;
+  float z2[kGo];
+#pragma unroll
+  for (int m = 0; m < kGo; ++m) z2[m] = zp[m];
+  ProjIn in;
+  float sig_s[3];
+  decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
+  Splat o;
+  uint32_t zb = 0;
+  const uint32_t cnt = project_splat(V, in, tw, th, o, zb);
+  counts[item] = cnt;
+  if (cnt) {
+    splats[item] = o;
+    zkey[item] = zb;
+  }
+}
+
+// The decoder weights in the layouts the decode and its adjoint stage in
+// LDS, written once per forward call:
+//   decode: W1 transposed to (column, k) with K = 64 (the feature rows,
+//   then the last four rows once per split term, zero padding), W2
+//   transposed to (column, k) with its 32 rows once per split term and
+//   zero columns 110..111, the biases (b2 zero-padded);
+//   adjoint: W1 and W2 as float32 rows at odd strides 33 and 111.
+constexpr int kPrepItems = kHid * kK1 + kN2 * kK2 + kHid + kN2 + kIn * kW1s + kHid * kW2s;
+
+__global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB* __restrict__ wb,
+                                                      DecWT* __restrict__ wt) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPrepItems; i += gridDim.x * blockDim.x) {
+    int j = i;
+    if (j < kHid * kK1) {
+      const int n = j / kK1, k = j % kK1;
+      uint16_t v = 0;
+      if (k < 32) v = sc.W1[k * kHid + n];
+      else if (k < 44) v = sc.W1[(32 + (k - 32) % 4) * kHid + n];
+      wb->w1t[n][k] = v;
+      continue;
+    }
+    j -= kHid * kK1;
+    if (j < kN2 * kK2) {
+      const int n = j / kK2, k = j % kK2;
+      wb->w2t[n][k] = n < kOut ? sc.W2[(k % kHid) * kOut + n] : (uint16_t)0;
+      continue;
+    }
+    j -= kN2 * kK2;
+    if (j < kHid) {
+      wb->b1[j] = sc.b1[j];
+      continue;
+    }
+    j -= kHid;
+    if (j < kN2) {
+      wb->b2[j] = j < kOut ? sc.b2[j] : 0.0f;
+      continue;
+    }
+    j -= kN2;
+    if (j < kIn * kW1s) {
+      const int r = j / kW1s, c = j % kW1s;
+      wt->W1[j] = c < kHid ? bf16_to_f32(sc.W1[r * kHid + c]) : 0.0f;
+      continue;
+    }
+    j -= kIn * kW1s;
+    const int r = j / kW2s, c = j % kW2s;
+    wt->W2[j] = c < kOut ? bf16_to_f32(sc.W2[r * kOut + c]) : 0.0f;
+  }
+}
+
+// weight images, after the row scratch and the weight-gradient partials
+static DecWB* decode_weights(float* scratch, uint32_t max_rows) {
+  return reinterpret_cast<DecWB*>(scratch + (size_t)max_rows * kRowScratch +
+                                  (size_t)kRedBlocks * kWGrad);
+}
+static DecWT* adjoint_weights(float* scratch, uint32_t max_rows) {
+  return reinterpret_cast<DecWT*>(reinterpret_cast<char*>(decode_weights(scratch, max_rows)) +
+                                  sizeof(DecWB));
 }
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
@@ -449,8 +509,14 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
-  hipLaunchKernelGGL(k_decode_project_mfma, dim3(blocks), dim3(64), 0, s, views, sc, rows,
-                     (const Counters*)ctr, tw, th, splats, counts, zkey, row_scratch);
+  DecWB* wb = decode_weights(row_scratch, max_rows);
+  hipLaunchKernelGGL(k_prep_weights, dim3(div_up(kPrepItems, 256)), dim3(256), 0, s, sc, wb,
+                     adjoint_weights(row_scratch, max_rows));
+  hipLaunchKernelGGL(k_decode_mfma, dim3(blocks), dim3(64), 0, s, views, sc, rows,
+                     (const Counters*)ctr, (const DecWB*)wb, row_scratch);
+  hipLaunchKernelGGL(k_project_decoded, dim3(div_up((uint64_t)max_rows * kNOff, 256)), dim3(256),
+                     0, s, views, sc, rows, (const Counters*)ctr, tw, th,
+                     (const float*)row_scratch, splats, counts, zkey);
 }
 
 // ---------------------------------------------------------------------
@@ -535,6 +601,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
                                                         cgx_anchor_scene sc,
                                                         const int2* __restrict__ rows,
                                                         const Counters* ctr,
+                                                        const DecWT* __restrict__ wimg,
                                                         float* __restrict__ scratch) {
   __shared__ DecWT w;
   __shared__ float s_dz2[kMlpRows][kOut];
@@ -543,7 +610,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
   const uint32_t n_rows = ctr->n_rows;
   const uint32_t rb = blockIdx.x * (kMlpRows * kMlpGroups);
   if (rb >= n_rows) return;                    // the grid covers the row capacity
-  load_weights(w, sc);
+  copy_weights(w, wimg);
   const int rl = threadIdx.x / kHid, j = threadIdx.x % kHid;
   for (int grp = 0; grp < kMlpGroups; ++grp) {
     const uint32_t r0 = rb + grp * kMlpRows;
@@ -710,16 +777,16 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
 }
 
 // Weight gradients on MFMA: dW1 = Z0^T dZ1 (36 x 32) and dW2 = Z1^T dZ2
-// (32 x 110), reductions over the rows.  Each block (one wave) owns a
+// (32 x 110), reductions over the rows.  Each block (four waves) owns a
 // contiguous chunk of rows and walks it 32 rows (one MFMA k-step) at a
 // time: the chunk's z0, z1, dz1 and dz2 are staged transposed in LDS as
-// float32, and each fragment is split on load into three bf16 terms
+// float32, each wave computes 5 of the 20 16x16 output tiles, and each
+// fragment is split on load into three bf16 terms
 // (h + m + l, as in the forward decode); the six products h*h, h*m, m*h,
 // h*l, l*h, m*m (the dropped ones are below 2^-26 relative) accumulate in
 // fp32.  The biases' gradients are column sums of the staged values.  Every
 // block writes one partial of 4814 values; k_wgrad_final adds the partials
 // in a fixed order (deterministic).
-constexpr int kRedBlocks = 512;
 constexpr int kWR = 32;          // rows per MFMA k-step
 constexpr int kM1 = 48;          // dW1 rows (36 padded)
 constexpr int kN2w = 112;        // dW2 columns (110 padded)
@@ -763,29 +830,46 @@ __device__ __forceinline__ f32x4_t mfma_split6(const Split8& A, const Split8& B,
   return acc;
 }
 
-__global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scratch,
-                                                  const Counters* ctr,
-                                                  float* __restrict__ partial) {
+constexpr int kWgWaves = 4;
+constexpr int kTiles1 = 3 * 2;   // dW1: 3 row tiles (36 rows padded to 48) x 2 column tiles
+constexpr int kTiles2 = 2 * 7;   // dW2: 2 row tiles x 7 column tiles (110 padded to 112)
+constexpr int kTilesPerWave = (kTiles1 + kTiles2) / kWgWaves;
+static_assert((kTiles1 + kTiles2) % kWgWaves == 0, "tiles split evenly over the waves");
+
+// output tile ti of the block: A rows from a, B columns from b (LDS rows)
+__device__ __forceinline__ void wgrad_tile(const WgradLds& L, int ti, int& m, int& t,
+                                           const float*& a, const float*& b, int col, int kq) {
+  if (ti < kTiles1) {
+    m = ti / 2;
+    t = ti % 2;
+    a = &L.z0t[m * 16 + col][kq];
+    b = &L.dz1t[t * 16 + col][kq];
+  } else {
+    m = (ti - kTiles1) / 7;
+    t = (ti - kTiles1) % 7;
+    a = &L.z1t[m * 16 + col][kq];
+    b = &L.dz2t[t * 16 + col][kq];
+  }
+}
+
+__global__ __launch_bounds__(kWgWaves * kWave) void k_wgrad_mfma(const float* __restrict__ scratch,
+                                                                const Counters* ctr,
+                                                                float* __restrict__ partial) {
   __shared__ WgradLds L;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const uint32_t n = ctr->n_rows;
   uint64_t b0, b1;
   chunk_range(n, b0, b1);
   const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
-  f32x4_t acc1[3][2], acc2[2][7];
+  f32x4_t acc[kTilesPerWave];
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
-#pragma unroll
-    for (int t = 0; t < 2; ++t) acc1[m][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int t = 0; t < 7; ++t) acc2[m][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  // bias gradients: lane owns columns lane, lane + 64, lane + 128 of [dz1 | dz2]
-  float bsum[3] = {0.f, 0.f, 0.f};
+  for (int q = 0; q < kTilesPerWave; ++q) acc[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // bias gradients: thread c < 142 owns column c of [dz1 | dz2]
+  float bsum = 0.0f;
   // zero the padding rows once (never written by the staging)
-  for (int e = lane; e < (kM1 - kIn) * kWR; e += 64) L.z0t[kIn + e / kWR][e % kWR] = 0.0f;
-  for (int e = lane; e < (kN2w - kOut) * kWR; e += 64) L.dz2t[kOut + e / kWR][e % kWR] = 0.0f;
+  for (int e = tid; e < (kM1 - kIn) * kWR; e += blockDim.x) L.z0t[kIn + e / kWR][e % kWR] = 0.0f;
+  for (int e = tid; e < (kN2w - kOut) * kWR; e += blockDim.x) L.dz2t[kOut + e / kWR][e % kWR] = 0.0f;
 
   for (uint64_t base = b0; base < b1; base += kWR) {
     const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
@@ -796,7 +880,7 @@ __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scr
     constexpr int kHalf = kRowUsed / 2;
     constexpr int kPairs = kWR * kHalf;
 #pragma unroll 4
-    for (int e = lane; e < kPairs; e += 64) {
+    for (int e = tid; e < kPairs; e += kWgWaves * kWave) {
       const int r = e / kHalf, q0 = 2 * (e - r * kHalf);
       const float2 x = r < nr ? *reinterpret_cast<const float2*>(src + (size_t)r * kRowScratch + q0)
                               : float2{0.0f, 0.0f};
@@ -811,55 +895,40 @@ __global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ scr
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const int c = lane + 64 * cc;
-      if (c < kHid + kOut) {
-        const float* row = c < kHid ? L.dz1t[c] : L.dz2t[c - kHid];
-        float sum = 0.0f;
-        for (int r = 0; r < kWR; ++r) sum += row[r];
-        bsum[cc] += sum;
-      }
+    if (tid < kHid + kOut) {
+      const float* row = tid < kHid ? L.dz1t[tid] : L.dz2t[tid - kHid];
+      float sum = 0.0f;
+      for (int r = 0; r < kWR; ++r) sum += row[r];
+      bsum += sum;
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const Split8 bv = split8(&L.dz1t[t * 16 + col][kq]);
-#pragma unroll
-      for (int m = 0; m < 3; ++m) acc1[m][t] = mfma_split6(split8(&L.z0t[m * 16 + col][kq]), bv, acc1[m][t]);
-    }
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const Split8 av = split8(&L.z1t[m * 16 + col][kq]);
-#pragma unroll
-      for (int t = 0; t < 7; ++t) acc2[m][t] = mfma_split6(av, split8(&L.dz2t[t * 16 + col][kq]), acc2[m][t]);
+    for (int q = 0; q < kTilesPerWave; ++q) {
+      int m, t;
+      const float *a, *b;
+      wgrad_tile(L, wave + kWgWaves * q, m, t, a, b, col, kq);
+      acc[q] = mfma_split6(split8(a), split8(b), acc[q]);
     }
     __syncthreads();
   }
   // partial layout: W1 (i, j) row-major, W2 (j, c) row-major, b1, b2
   float* out = partial + (size_t)blockIdx.x * kWGrad;
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
+  for (int q = 0; q < kTilesPerWave; ++q) {
+    const int ti = wave + kWgWaves * q;
+    int m, t;
+    const float *a, *b;
+    wgrad_tile(L, ti, m, t, a, b, col, kq);
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ii = m * 16 + rq + i, j = t * 16 + col;
-        if (ii < kIn) out[ii * kHid + j] = acc1[m][t][i];
+    for (int i = 0; i < 4; ++i) {
+      const int rr = m * 16 + rq + i, cc = t * 16 + col;
+      if (ti < kTiles1) {
+        if (rr < kIn) out[rr * kHid + cc] = acc[q][i];
+      } else if (cc < kOut) {
+        out[kIn * kHid + rr * kOut + cc] = acc[q][i];
       }
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int t = 0; t < 7; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = m * 16 + rq + i, c = t * 16 + col;
-        if (c < kOut) out[kIn * kHid + j * kOut + c] = acc2[m][t][i];
-      }
-#pragma unroll
-  for (int cc = 0; cc < 3; ++cc) {
-    const int c = lane + 64 * cc;
-    if (c < kHid + kOut) out[kIn * kHid + kHid * kOut + c] = bsum[cc];
+    }
   }
+  if (tid < kHid + kOut) out[kIn * kHid + kHid * kOut + tid] = bsum;
 }
 
 // Sum of the block partials: a block reduces 32 outputs; thread (o, g) adds
@@ -886,7 +955,8 @@ __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ p
 }
 
 size_t anchor_scratch_bytes(int64_t max_rows) {
-  return sizeof(float) * ((size_t)max_rows * kRowScratch + (size_t)kRedBlocks * kWGrad);
+  return sizeof(float) * ((size_t)max_rows * kRowScratch + (size_t)kRedBlocks * kWGrad) +
+         sizeof(DecWB) + sizeof(DecWT);
 }
 
 void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
@@ -902,12 +972,13 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
   const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
   if (rblocks)
     hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                       scratch);
+                       (const DecWT*)adjoint_weights(scratch, max_rows), scratch);
   const uint32_t ablocks = div_up((uint64_t)sc.n_anchor, kGatherPerWave);
   if (ablocks)
     hipLaunchKernelGGL(k_anchor_grad, dim3(ablocks), dim3(kWave), 0, s, sc, B, rinv,
                        (const float*)scratch, g);
-  hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(64), 0, s, (const float*)scratch, ctr,
+  hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(kWgWaves * kWave), 0, s,
+                     (const float*)scratch, ctr,
                      partial);
   hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 32)), dim3(256), 0, s,
                      (const float*)partial, kRedBlocks, g);
