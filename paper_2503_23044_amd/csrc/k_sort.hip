@@ -410,39 +410,55 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint32_t* __restrict__ bstart, const Counters* ctr, int n_per_row,
     const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-  __shared__ uint32_t s_off[kDupPairs + 2];
+  constexpr int M = kDupPairs + 2;
+  __shared__ uint32_t s_off[M];    // first pair of each visible splat of the block
+  __shared__ uint32_t s_slot[M];
+  __shared__ uint32_t s_base[M];   // global id of the splat's first tile
+  __shared__ uint32_t s_nx[M];     // tiles per row of its rectangle
+  __shared__ uint32_t s_TX[M];     // tiles per row of its view
   const uint32_t P = ctr->n_pairs;
   const uint32_t nv = ctr->n_visible;
-  const uint32_t p0 = blockIdx.x * kDupPairs;
-  if (p0 >= P || nv == 0) return;
-  const uint32_t p1 = p0 + kDupPairs < P ? p0 + kDupPairs : P;
-  const uint32_t j0 = bstart[blockIdx.x];
-  const uint32_t j1r = p1 < P ? bstart[blockIdx.x + 1] : nv - 1;
-  const uint32_t j1 = j1r < nv ? j1r : nv - 1;
-  const uint32_t span = j1 >= j0 ? j1 - j0 + 1 : 1;
-  const uint32_t m = span <= (uint32_t)kDupPairs + 2 ? span : (uint32_t)kDupPairs + 2;
-  for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) s_off[t] = voff[j0 + t];
-  __syncthreads();
-  for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-    uint32_t lo = 0, hi = m;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s_off[mid] <= i) lo = mid + 1;
-      else hi = mid;
+  if (nv == 0) return;
+  // one block of kDupPairs pairs per iteration
+  for (uint32_t blk = blockIdx.x; (uint64_t)blk * kDupPairs < P; blk += gridDim.x) {
+    const uint32_t p0 = blk * kDupPairs;
+    const uint32_t p1 = p0 + kDupPairs < P ? p0 + kDupPairs : P;
+    const uint32_t j0 = bstart[blk];
+    const uint32_t j1r = p1 < P ? bstart[blk + 1] : nv - 1;
+    const uint32_t j1 = j1r < nv ? j1r : nv - 1;
+    const uint32_t span = j1 >= j0 ? j1 - j0 + 1 : 1;
+    const uint32_t m = span <= (uint32_t)M ? span : (uint32_t)M;
+    // the block's splats, once: their pair offsets and tile rectangles
+    for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) {
+      const uint32_t slot = vslot[j0 + t];
+      const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
+      const ViewDev& V = views[v];
+      const Splat& sp = splats[slot];
+      const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
+      const int y_lo = sp.by & 0xFFFF;
+      const int tx0 = x_lo / tw, ty0 = y_lo / th;
+      s_off[t] = voff[j0 + t];
+      s_slot[t] = slot;
+      s_base[t] = (uint32_t)(V.tile_off + ty0 * V.TX + tx0);
+      s_nx[t] = (uint32_t)(x_hi / tw - tx0 + 1);
+      s_TX[t] = (uint32_t)V.TX;
     }
-    const uint32_t jl = lo > 0 ? lo - 1 : 0;
-    const uint32_t slot = vslot[j0 + jl];
-    const uint32_t k = i - s_off[jl];
-    const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
-    const ViewDev& V = views[v];
-    const Splat& sp = splats[slot];
-    const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
-    const int y_lo = sp.by & 0xFFFF;
-    const int tx0 = x_lo / tw, nx = x_hi / tw - tx0 + 1;
-    const int ty0 = y_lo / th;
-    const int tx = tx0 + (int)(k % (uint32_t)nx), ty = ty0 + (int)(k / (uint32_t)nx);
-    pkey[i] = (uint32_t)(V.tile_off + ty * V.TX + tx);
-    pval[i] = slot;
+    __syncthreads();
+    for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+      uint32_t lo = 0, hi = m;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= i) lo = mid + 1;
+        else hi = mid;
+      }
+      const uint32_t jl = lo > 0 ? lo - 1 : 0;
+      const uint32_t k = i - s_off[jl];
+      const uint32_t nx = s_nx[jl];
+      const uint32_t ty = k / nx;
+      pkey[i] = s_base[jl] + ty * s_TX[jl] + (k - ty * nx);
+      pval[i] = s_slot[jl];
+    }
+    __syncthreads();
   }
 }
 
@@ -450,7 +466,9 @@ void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t
                        const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
                        int n_per_row, const int2* rows, uint32_t N_explicit, int tw, int th,
                        uint32_t cap, uint32_t* pkey, uint32_t* pval, hipStream_t s) {
-  const uint32_t blocks = std::max<uint32_t>(1, div_up(cap, kDupPairs));
+  // the pair count is read on the device; the grid strides over blocks of
+  // kDupPairs pairs
+  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, kDupPairs), 4096));
   hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, vslot, voff,
                      bstart, ctr, n_per_row, rows, N_explicit, tw, th, pkey, pval);
 }
