@@ -74,14 +74,14 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
 
   float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
   uint32_t last[PPL], walked[PPL];
-  bool done[PPL];
+  uint32_t done[PPL];           // 0 / 1 (a bool array is packed into bytes)
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
     last[k] = 0;
     walked[k] = 0;
-    done[k] = !(sub_x0<TW>(tx, k) + lx < V.W && sub_y0<TW>(ty, TH, k) + ly < V.H);
+    done[k] = (sub_x0<TW>(tx, k) + lx < V.W && sub_y0<TW>(ty, TH, k) + ly < V.H) ? 0u : 1u;
   }
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
@@ -116,14 +116,17 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
         ++evals;
-        if (alpha == 0.0f) continue;
+        // selects rather than branches: a zero alpha leaves every sum and T
+        // unchanged (weight 0, T (1 - 0) = T); a pixel that would fall below
+        // the transmittance floor stops without taking the splat
         const float Tn = T[k] * (1.0f - alpha);
-        if (Tn < kTMin) {
-          done[k] = true;
+        const bool stop = Tn < kTMin;
+        const bool take = alpha != 0.0f && !stop;
+        if (stop) {
+          done[k] = 1u;
           walked[k] = idx;
-          continue;
         }
-        const float w = alpha * T[k];
+        const float w = take ? alpha * T[k] : 0.0f;
         C0[k] += w * s.cr;
         C1[k] += w * s.cg;
         C2[k] += w * s.cb;
@@ -131,8 +134,8 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
         N0[k] += w * s.nx;
         N1[k] += w * s.ny;
         N2[k] += w * s.nz;
-        T[k] = Tn;
-        last[k] = idx;
+        T[k] = take ? Tn : T[k];
+        last[k] = take ? idx : last[k];
       }
     }
     __syncthreads();
@@ -320,10 +323,12 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
         ++evals;
-        if (alpha == 0.0f) continue;
+        // selects rather than branches: a zero alpha (then raw = 0 too)
+        // leaves T, S and every gradient term unchanged
+        const bool hit = alpha != 0.0f;
         const float om = 1.0f - alpha;
         const float rom = __builtin_amdgcn_rcpf(om);
-        const float Tk = T[k] * rom;
+        const float Tk = hit ? T[k] * rom : T[k];
         const float w = alpha * Tk;
         const float val = s.cr * GC0[k] + s.cg * GC1[k] + s.cb * GC2[k] + s.d * GD[k] +
                           s.nx * GN0[k] + s.ny * GN1[k] + s.nz * GN2[k];
@@ -337,16 +342,16 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         g[10] += w * GN0[k];
         g[11] += w * GN1[k];
         g[12] += w * GN2[k];
-        if (raw < kAlphaMax) {
-          g[5] += da * (raw * s.inv_o);       // d alpha / d o = exp(power)
-          const float dpw = da * raw;         // d alpha / d power = o exp(power)
-          g[0] += dpw * (2.0f * s.pa * dx + s.pb * dy);
-          g[1] += dpw * (2.0f * s.pc * dy + s.pb * dx);
-          g[2] += dpw * dx * dx;
-          g[3] += dpw * dx * dy;
-          g[4] += dpw * dy * dy;
-        }
-        any = true;
+        // alpha clamped at kAlphaMax: no gradient through o or the power
+        const float dg = raw < kAlphaMax ? da : 0.0f;
+        g[5] += dg * (raw * s.inv_o);         // d alpha / d o = exp(power)
+        const float dpw = dg * raw;           // d alpha / d power = o exp(power)
+        g[0] += dpw * (2.0f * s.pa * dx + s.pb * dy);
+        g[1] += dpw * (2.0f * s.pc * dy + s.pb * dx);
+        g[2] += dpw * dx * dx;
+        g[3] += dpw * dx * dy;
+        g[4] += dpw * dy * dy;
+        any = any || hit;
       }
       if (__ballot(any) == 0) continue;
       // wave totals of the 13 terms land in lanes 0..12; one atomic
