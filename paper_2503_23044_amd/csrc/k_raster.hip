@@ -35,6 +35,9 @@ __device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
   d[3] = e;
 }
 
+// box-test column of a finished pixel: left of every pixel box
+constexpr int kDoneX = -(1 << 20);
+
 // tile of this block in the launch order
 __device__ __forceinline__ uint32_t launch_tile(const RasterArgs& a) {
   return blockIdx.x < a.n_tiles ? a.order[blockIdx.x] : a.n_tiles;
@@ -74,14 +77,21 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
 
   float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
   uint32_t last[PPL], walked[PPL];
-  uint32_t done[PPL];           // 0 / 1 (a bool array is packed into bytes)
+  // box-test column of each pixel; a finished pixel (saturated, or outside
+  // the image) gets kDoneX, which every pixel box excludes, so one compare
+  // serves both tests.  The pixel centres used by the blend are separate.
+  int xb[PPL];
+  float xc[PPL], yc[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
     last[k] = 0;
     walked[k] = 0;
-    done[k] = (sub_x0<TW>(tx, k) + lx < V.W && sub_y0<TW>(ty, TH, k) + ly < V.H) ? 0u : 1u;
+    const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
+    xb[k] = (x < V.W && y < V.H) ? x : kDoneX;
+    xc[k] = (float)x + 0.5f;
+    yc[k] = (float)y + 0.5f;
   }
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
@@ -92,7 +102,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     uint32_t live = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
-      if (__ballot(!done[k]) != 0) live |= 1u << k;
+      if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
     if (live == 0) break;
     const uint32_t n = (end - base) < (uint32_t)kWave ? (end - base) : (uint32_t)kWave;
     if ((uint32_t)lane < n) {
@@ -109,10 +119,10 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
       for (int k = 0; k < PPL; ++k) {
         const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
         if (!(live & (1u << k)) || box_misses_block(b, x0, y0)) continue;
-        const int x = x0 + lx, y = y0 + ly;
-        if (done[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
-        const float dx = s.u - ((float)x + 0.5f);
-        const float dy = s.w - ((float)y + 0.5f);
+        const int x = xb[k], y = y0 + ly;
+        if (x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
+        const float dx = s.u - xc[k];
+        const float dy = s.w - yc[k];
         float raw;
         const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
         ++evals;
@@ -123,7 +133,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
         const bool stop = Tn < kTMin;
         const bool take = alpha != 0.0f && !stop;
         if (stop) {
-          done[k] = 1u;
+          xb[k] = kDoneX;
           walked[k] = idx;
         }
         const float w = take ? alpha * T[k] : 0.0f;
