@@ -81,6 +81,85 @@ def quat_to_rot_backward(qn, dR):
     return np.stack([dw, dx, dy, dz], 1)
 
 
+MASK_TILES = 64     # boxes of 2 x 2 up to this many tiles carry a tile mask
+
+
+def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
+    """Tiles of the pixel box that the drawable ellipse reaches (reading of
+    the tile binning, Sec. 3.3; row f3's ellipse-tile culling): bit
+    r * nx + c for tile row r and tile column c of the box, for the splats in
+    `use` (boxes of at least two tile rows and columns and at most
+    MASK_TILES tiles; a one-row or one-column box spans the ellipse's full
+    extent along its other axis, so it keeps every tile).
+
+    With d = p - (u, w) and the 2-D covariance [[A, B], [B, C]], a pixel
+    centre p is drawable (alpha >= 1/255) iff d^T Sigma^-1 d <= 2 tau,
+    tau = log(255 o).  At a fixed dy that ellipse spans
+    dx in (B/C) dy -/+ sqrt((2 tau - dy^2 / C) det / C); over a strip of
+    pixel-centre rows its left edge is convex in dy, with the minimum at
+    the leftmost point dy = -B sqrt(2 tau / A) (the right edge mirrors it),
+    so the strip's x-extent is the edge at that dy clamped into the strip.
+    A tile of the row is kept iff the pixel-centre columns it shares with
+    the box meet that extent.  The test is continuous, so a tile with a
+    drawable pixel centre is never dropped.  Decisions are float64 in this
+    operation order (the GPU evaluates the same expressions); a comparison
+    closer than the float32 covariance can resolve (relative `rel`, times
+    the conditioning of det) marks the splat's tile set fragile.
+
+    Returns (mask uint64, fragile bool) per splat."""
+    n = u.size
+    mask = np.zeros(n, np.uint64)
+    frag = np.zeros(n, bool)
+    idx = np.nonzero(use)[0]
+    if idx.size == 0:
+        return mask, frag
+    u, w, A, B, C, tau = (np.asarray(a, np.float64)[idx] for a in (u, w, A, B, C, tau))
+    rel = np.broadcast_to(np.asarray(rel, np.float64), (n,))[idx]
+    xl_, xh_, yl_, yh_ = (np.asarray(a)[idx] for a in (x_lo, x_hi, y_lo, y_hi))
+    tx0, tx1, ty0, ty1 = xl_ // tw, xh_ // tw, yl_ // th, yh_ // th
+    nx, ny = tx1 - tx0 + 1, ty1 - ty0 + 1
+    det = A * C - B * B
+    t2 = 2.0 * tau
+    ic = 1.0 / C
+    ymax = np.sqrt(t2 * C)
+    k = B * ic
+    s = det * ic
+    ye = B * np.sqrt(t2 / A)
+    kappa = 1.0 + (A * C + B * B) / det
+    m = np.zeros(idx.size, np.uint64)
+    fr = np.zeros(idx.size, bool)
+    one = np.uint64(1)
+    for rr in range(int(ny.max())):
+        live = rr < ny
+        ty = ty0 + rr
+        r0 = np.maximum(ty * th, yl_)
+        r1 = np.minimum(ty * th + th - 1, yh_)
+        lo = (r0 + 0.5) - w
+        hi = (r1 + 0.5) - w
+        dym = rel * kappa * (ymax + 1.0) + 1e-9
+        fr |= live & ((np.abs(lo - ymax) < dym) | (np.abs(hi + ymax) < dym))
+        lo = np.maximum(lo, -ymax)
+        hi = np.minimum(hi, ymax)
+        row = live & (lo <= hi)
+        dl = np.minimum(np.maximum(-ye, lo), hi)
+        dr = np.minimum(np.maximum(ye, lo), hi)
+        xl = u + (k * dl - np.sqrt(np.maximum(t2 - dl * dl * ic, 0.0) * s))
+        xr = u + (k * dr + np.sqrt(np.maximum(t2 - dr * dr * ic, 0.0) * s))
+        marg = rel * kappa * (np.abs(xl - u) + np.abs(xr - u) + np.sqrt(t2 * A) + 1.0) + 1e-9
+        for cc in range(int(nx.max())):
+            on = row & (cc < nx)
+            tx = tx0 + cc
+            c0 = np.maximum(tx * tw, xl_)
+            c1 = np.minimum(tx * tw + tw - 1, xh_)
+            keep = on & ((c1 + 0.5) >= xl) & ((c0 + 0.5) <= xr)
+            fr |= on & ((np.abs((c1 + 0.5) - xl) < marg) | (np.abs(xr - (c0 + 0.5)) < marg))
+            bit = np.where(on, rr * nx + cc, 0).astype(np.uint64)
+            m |= np.where(keep, np.left_shift(one, bit), np.uint64(0))
+    mask[idx] = m
+    frag[idx] = fr
+    return mask, frag
+
+
 def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0,
             opacity_exact=True):
     """Project N Gaussians into one view.
@@ -211,14 +290,19 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     TY = -(-H // th)
     tx0, tx1 = x_lo // tw, x_hi // tw
     ty0, ty1 = y_lo // th, y_hi // th
-    count = np.where(valid, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
+    ntile = np.where(valid, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
+    small = valid & (ntile <= MASK_TILES) & (tx1 > tx0) & (ty1 > ty0)
+    tmask, frag_cull = tile_mask(u, w, A, B, Cc, tau0, x_lo, x_hi, y_lo, y_hi, tw, th, small, rel)
+    count = np.where(small, np.bitwise_count(tmask).astype(np.int64), ntile)
 
     return dict(
         n=n, valid=valid, p=p, u=u, w=w, zbits=zbits, conic=conic, r=r.astype(np.int64),
         box=np.stack([x_lo, x_hi, y_lo, y_hi], 1), opacity=o, rgb=rgb, raw_rgb=raw,
         normal=nvec, d=d, sign=sign, jstar=jstar,
-        tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, TX=TX, TY=TY,
-        frag_value=(valid & (frag_r | frag_axis | frag_flip)) | (front & (det > 0) & frag_tau),
+        tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, tmask=tmask, small=small,
+        TX=TX, TY=TY,
+        frag_value=(valid & (frag_r | frag_axis | frag_flip | frag_cull))
+        | (front & (det > 0) & frag_tau),
         frag_ring=valid & frag_r, frag_geom=valid & (frag_axis | frag_flip),
         frag_grad=valid & (frag_colour | clamp_x | clamp_y
                            | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)

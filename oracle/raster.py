@@ -70,6 +70,10 @@ def _bin_sample(splats_per_view, layout, keep_tiles):
         S = splats_per_view[v]
         t = S["tiles"]
         m = S["valid"] & (t[:, 0] <= tx) & (t[:, 1] >= tx) & (t[:, 2] <= ty) & (t[:, 3] >= ty)
+        # boxes of at most 64 tiles: only the tiles the drawable ellipse reaches
+        bit = np.where(m, (ty - t[:, 2]) * (t[:, 1] - t[:, 0] + 1) + (tx - t[:, 0]), 0)
+        hit = (np.right_shift(S["tmask"], np.minimum(bit, 63).astype(np.uint64)) & np.uint64(1)) != 0
+        m &= ~S["small"] | hit
         idx = np.nonzero(m)[0]
         gt_all.append(np.full(idx.size, gtile, np.int64))
         zb_all.append(S["zbits"][idx])
@@ -103,6 +107,11 @@ def bin_and_sort(splats_per_view, layout, keep_tiles=None):
         rep = np.repeat(np.arange(idx.size), cnt)
         first = np.repeat(np.cumsum(cnt) - cnt, cnt)
         k = np.arange(rep.size) - first
+        # boxes of at most 64 tiles: only the tiles the drawable ellipse reaches
+        hit = (np.right_shift(S["tmask"][idx][rep], np.minimum(k, 63).astype(np.uint64))
+               & np.uint64(1)) != 0
+        sel = ~S["small"][idx][rep] | hit
+        rep, k = rep[sel], k[sel]
         tx = tx0[rep] + k % nx[rep]
         ty = ty0[rep] + k // nx[rep]
         gt_all.append(layout["tile_off"][v] + ty * layout["TX"][v] + tx)

@@ -273,3 +273,67 @@ def test_opacity_box_keeps_every_drawable_pixel():
         assert not (box & ~square).any(), i
         tight += int((square & ~box).sum())
     assert tight > 0      # the box is strictly smaller for some splats
+
+
+def _rect_min_q(a, b, c, dx0, dx1, dy0, dy1):
+    """min of Q = a dx^2 + 2 b dx dy + c dy^2 (positive definite) over the
+    rectangle [dx0, dx1] x [dy0, dy1]: zero if it holds the origin, else the
+    least of the four edge minima (each a clamped 1-D parabola)."""
+    if dx0 <= 0.0 <= dx1 and dy0 <= 0.0 <= dy1:
+        return 0.0
+    best = np.inf
+    for x in (dx0, dx1):
+        y = min(max(-b * x / c, dy0), dy1)
+        best = min(best, a * x * x + 2 * b * x * y + c * y * y)
+    for y in (dy0, dy1):
+        x = min(max(-b * y / a, dx0), dx1)
+        best = min(best, a * x * x + 2 * b * x * y + c * y * y)
+    return best
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_tile_mask_is_ellipse_rectangle_overlap(tile):
+    """Ellipse-tile culling: for a box of 2 x 2 up to 64 tiles, bit r * nx + c is
+    set iff the pixel-centre rectangle the tile shares with the box meets the
+    drawable ellipse Q <= 2 ln(255 o) (checked through the conic by edge
+    minimisation, a different route from the strip extents), and every tile
+    holding a drawable pixel centre (brute force) keeps its bit; the culled
+    count is the number of set bits."""
+    tw, th = tile
+    rng = np.random.default_rng(31)
+    v = _V()
+    n = 300
+    mu = np.stack([rng.uniform(-1.5, 1.5, n), rng.uniform(-1.2, 1.2, n), rng.uniform(-1, 1, n)], 1)
+    s = np.exp(rng.normal(-2.6, 0.8, (n, 3)))
+    s[:, 0] *= np.exp(rng.uniform(0, 2.5, n))          # elongated splats
+    q = rng.standard_normal((n, 4))
+    o = rng.uniform(0.005, 1.0, n)
+    P = project.project(mu, s, q, o, v, tile, colour=np.zeros((n, 3)))
+    checked = culled = 0
+    for i in np.nonzero(P["small"])[0]:
+        a, b, c = P["conic"][i]
+        t2 = 2.0 * np.log(255.0 * o[i])
+        x_lo, x_hi, y_lo, y_hi = P["box"][i]
+        tx0, tx1, ty0, ty1 = P["tiles"][i]
+        nx = tx1 - tx0 + 1
+        bits = int(P["tmask"][i])
+        assert P["count"][i] == bin(bits).count("1")
+        for ty in range(ty0, ty1 + 1):
+            for tx in range(tx0, tx1 + 1):
+                bit = (bits >> ((ty - ty0) * nx + (tx - tx0))) & 1
+                c0, c1 = max(tx * tw, x_lo), min(tx * tw + tw - 1, x_hi)
+                r0, r1 = max(ty * th, y_lo), min(ty * th + th - 1, y_hi)
+                xs = np.arange(c0, c1 + 1) + 0.5 - P["u"][i]
+                ys = np.arange(r0, r1 + 1) + 0.5 - P["w"][i]
+                X, Y = np.meshgrid(xs, ys)
+                drawable = (a * X * X + 2 * b * X * Y + c * Y * Y <= t2).any()
+                if drawable:
+                    assert bit, (i, tx, ty)
+                qmin = _rect_min_q(a, b, c, c0 + 0.5 - P["u"][i], c1 + 0.5 - P["u"][i],
+                                   r0 + 0.5 - P["w"][i], r1 + 0.5 - P["w"][i])
+                if not P["frag_value"][i]:
+                    assert bit == (qmin <= t2), (i, tx, ty, qmin, t2)
+                checked += 1
+                culled += 1 - bit
+    assert checked > 500
+    assert culled > 0.05 * checked      # the ellipse leaves part of the box's tiles

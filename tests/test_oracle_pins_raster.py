@@ -190,8 +190,12 @@ def test_sort_matches_python_sorted():
     entries = []
     for g in np.nonzero(S["valid"])[0]:
         tx0, tx1, ty0, ty1 = S["tiles"][g]
+        nx = tx1 - tx0 + 1
         for ty in range(ty0, ty1 + 1):
             for tx in range(tx0, tx1 + 1):
+                bit = (ty - ty0) * nx + (tx - tx0)
+                if S["small"][g] and not (int(S["tmask"][g]) >> bit) & 1:
+                    continue      # a tile the drawable ellipse does not reach
                 entries.append((ty * lay["TX"][0] + tx, int(S["zbits"][g]), int(g)))
     entries.sort()
     got = list(zip(r.sorted["gtile"].tolist(), r.sorted["zbits"].tolist(), r.sorted["gid"].tolist()))
