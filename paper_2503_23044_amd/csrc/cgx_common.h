@@ -114,7 +114,7 @@ struct ViewPack {
 };
 
 struct Layout {
-  size_t views, counters, scan_part, rows, row_off, rinv, splats, counts, offsets, zkey;
+  size_t views, counters, scan_part, rows, row_off, rinv, splats, counts, offsets, zkey, tmask;
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
@@ -260,6 +260,14 @@ void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h
 
 // Pairs handled by one block of the pair emission.
 constexpr int kDupPairs = 1024;
+// pixel boxes of at least two tile rows and columns and at most kMaskTiles
+// tiles carry a mask of the tiles their drawable ellipse reaches; other boxes
+// keep every tile (a one-row or one-column box spans the ellipse's full
+// extent along its other axis)
+constexpr int kMaskTiles = 64;
+__host__ __device__ inline bool mask_box(int nx, int ny) {
+  return nx >= 2 && ny >= 2 && nx * ny <= kMaskTiles;
+}
 
 // device-wide exclusive scan of counts[idx[i]] (idx may be NULL) for
 // i < n (n from *n_dev if non-null, else n_host) into offsets clamped to
@@ -272,7 +280,8 @@ void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* o
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s);
-void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
+void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint64_t* tmask,
+                       const uint32_t* vslot,
                        const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
                        int n_per_row, const int2* rows,
                        uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
@@ -288,14 +297,14 @@ int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, 
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
                              int tw, int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
-                             hipStream_t s);
+                             uint64_t* tmask, hipStream_t s);
 void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            unsigned long long* part, int2* rows, uint32_t* row_off,
                            uint32_t* rinv, uint32_t max_rows, Counters* ctr, hipStream_t s);
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, uint32_t* zkey, Counters* ctr, float* row_scratch,
-                           hipStream_t s);
+                           uint32_t* counts, uint32_t* zkey, uint64_t* tmask, Counters* ctr,
+                           float* row_scratch, hipStream_t s);
 
 
 // Raster launch order: tiles by descending list length (longest first),

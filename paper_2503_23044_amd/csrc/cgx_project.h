@@ -114,10 +114,62 @@ __device__ __forceinline__ void proj_normal(const ViewDev& V, const ProjIn& in, 
   st.d = -(st.n[0] * st.p[0] + st.n[1] * st.p[1] + st.n[2] * st.p[2]);
 }
 
+// Tiles of the pixel box [x_lo, x_hi] x [y_lo, y_hi] that the drawable
+// ellipse reaches, for a box that mask_box accepts: bit r * nx + c for
+// tile row r, column c of the box.  With d = p - (u, w) and the 2-D
+// covariance [[A, B], [B, C]], a pixel centre is drawable iff
+// d^T Sigma^-1 d <= 2 tau.  At a fixed dy the ellipse spans
+// dx in (B/C) dy -/+ sqrt((2 tau - dy^2 / C) det / C); its left edge is
+// convex in dy with the minimum at dy = -B sqrt(2 tau / A) (the right edge
+// mirrors it), so a strip of pixel-centre rows reaches x in [xl, xr] with the
+// edges taken at those points clamped into the strip.  A tile is kept iff
+// its pixel-centre columns within the box meet [xl, xr].  Float64 in a fixed
+// order (the decisions are reproducible); the test is continuous, so a tile
+// with a drawable pixel centre is never dropped.
+
+__device__ inline uint64_t tile_mask(double u, double w, double A, double B, double C, double tau,
+                                     int x_lo, int x_hi, int y_lo, int y_hi, int tw, int th) {
+#pragma clang fp contract(off)
+  const int tx0 = x_lo / tw, tx1 = x_hi / tw, ty0 = y_lo / th, ty1 = y_hi / th;
+  const int nx = tx1 - tx0 + 1;
+  const double det = A * C - B * B;
+  const double t2 = 2.0 * tau;
+  const double ic = 1.0 / C;
+  const double ymax = sqrt(t2 * C);
+  const double k = B * ic;
+  const double s = det * ic;
+  const double ye = B * sqrt(t2 / A);
+  uint64_t m = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const int r0 = max(ty * th, y_lo), r1 = min(ty * th + th - 1, y_hi);
+    double lo = ((double)r0 + 0.5) - w, hi = ((double)r1 + 0.5) - w;
+    lo = fmax(lo, -ymax);
+    hi = fmin(hi, ymax);
+    if (!(lo <= hi)) continue;
+    const double dl = fmin(fmax(-ye, lo), hi), dr = fmin(fmax(ye, lo), hi);
+    const double xl = u + (k * dl - sqrt(fmax(t2 - dl * dl * ic, 0.0) * s));
+    const double xr = u + (k * dr + sqrt(fmax(t2 - dr * dr * ic, 0.0) * s));
+    // tile column tx (pixel columns c0..c1 inside the box) is kept iff
+    // c1 + 0.5 >= xl and c0 + 0.5 <= xr, i.e. c1 >= ceil(xl - 0.5) and
+    // c0 <= floor(xr - 0.5) (exact: the half shifts are exact at pixel
+    // scale), which holds for a contiguous run of columns
+    const double fl = ceil(xl - 0.5), fr = floor(xr - 0.5);
+    if (!(fl <= (double)x_hi && fr >= (double)x_lo)) continue;
+    const int cl = (int)fmax(fl, (double)x_lo), cr = (int)fmin(fr, (double)x_hi);
+    const int first = cl / tw, last = cr / tw;
+    if (first > last) continue;
+    const uint64_t run = (2ull << (last - first)) - 1ull;
+    m |= run << ((ty - ty0) * nx + (first - tx0));
+  }
+  return m;
+}
+
 // a2: full projection into a splat record; returns the number of tiles
-// touched (0 = culled).
+// touched (0 = culled).  tmask: the tiles kept (tile_mask) for a box that
+// mask_box accepts, else 0 (every tile of the box is kept).
 __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn& in, int tw,
-                                                  int th, Splat& o, uint32_t& zbits) {
+                                                  int th, Splat& o, uint32_t& zbits,
+                                                  uint64_t& tmask) {
   double p0, p1, p2;
   camera_point64(V, in.m0, in.m1, in.m2, p0, p1, p2);
   if (!(p2 > (double)V.z_near)) return 0;
@@ -169,7 +221,12 @@ __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn
   o.by = (uint32_t)y_lo | ((uint32_t)y_hi << 16);
   zbits = __float_as_uint((float)p2);
   const int tx0 = x_lo / tw, tx1 = x_hi / tw, ty0 = y_lo / th, ty1 = y_hi / th;
-  return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  const int ntile = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+  tmask = 0;
+  if (!mask_box(tx1 - tx0 + 1, ty1 - ty0 + 1)) return (uint32_t)ntile;
+  tmask = tile_mask(u64, w64, (double)st.A, (double)st.B, (double)st.C, tau, x_lo, x_hi, y_lo,
+                    y_hi, tw, th);
+  return (uint32_t)__popcll(tmask);
 }
 
 // Recompute the float32 projection state of a splat that was kept.

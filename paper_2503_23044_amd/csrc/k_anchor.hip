@@ -419,7 +419,8 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
                                                          const float* __restrict__ row_scratch,
                                                          Splat* __restrict__ splats,
                                                          uint32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ zkey) {
+                                                         uint32_t* __restrict__ zkey,
+                                                         uint64_t* __restrict__ tmask) {
   const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = item / kNOff;
   const int k = (int)(item - r * kNOff);
@@ -435,11 +436,13 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
   decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
   Splat o;
   uint32_t zb = 0;
-  const uint32_t cnt = project_splat(V, in, tw, th, o, zb);
+  uint64_t tm = 0;
+  const uint32_t cnt = project_splat(V, in, tw, th, o, zb, tm);
   counts[item] = cnt;
   if (cnt) {
     splats[item] = o;
     zkey[item] = zb;
+    tmask[item] = tm;
   }
 }
 
@@ -504,8 +507,8 @@ static DecWT* adjoint_weights(float* scratch, uint32_t max_rows) {
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, uint32_t* zkey, Counters* ctr, float* row_scratch,
-                           hipStream_t s) {
+                           uint32_t* counts, uint32_t* zkey, uint64_t* tmask, Counters* ctr,
+                           float* row_scratch, hipStream_t s) {
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
@@ -516,7 +519,7 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                      (const Counters*)ctr, (const DecWB*)wb, row_scratch);
   hipLaunchKernelGGL(k_project_decoded, dim3(div_up((uint64_t)max_rows * kNOff, 256)), dim3(256),
                      0, s, views, sc, rows, (const Counters*)ctr, tw, th,
-                     (const float*)row_scratch, splats, counts, zkey);
+                     (const float*)row_scratch, splats, counts, zkey, tmask);
 }
 
 // ---------------------------------------------------------------------

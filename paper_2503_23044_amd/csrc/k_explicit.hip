@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_project_explicit(const ViewDev* __restr
                                                           cgx_explicit_scene sc, int tw, int th,
                                                           Splat* __restrict__ splats,
                                                           uint32_t* __restrict__ counts,
-                                                          uint32_t* __restrict__ zkey) {
+                                                          uint32_t* __restrict__ zkey,
+                                                          uint64_t* __restrict__ tmask) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const uint64_t N = (uint64_t)sc.n;
   const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,24 +113,27 @@ __global__ __launch_bounds__(256) void k_project_explicit(const ViewDev* __restr
   }
   Splat o;
   uint32_t zb = 0;
-  uint32_t cnt = project_splat(V, in, tw, th, o, zb);
+  uint64_t tm = 0;
+  uint32_t cnt = project_splat(V, in, tw, th, o, zb, tm);
   counts[slot] = cnt;
   if (cnt) {
     splats[slot] = o;
     zkey[slot] = zb;
+    tmask[slot] = tm;
   }
 }
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc, int tw,
-                             int th, Splat* splats, uint32_t* counts, uint32_t* zkey, hipStream_t s) {
+                             int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
+                             uint64_t* tmask, hipStream_t s) {
   const uint64_t n = (uint64_t)sc.n * (uint64_t)B;
   const uint32_t blocks = div_up(n, 256);
   if (blocks == 0) return;
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_explicit<0>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey); break;
-    case 1: hipLaunchKernelGGL(k_project_explicit<1>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey); break;
-    case 2: hipLaunchKernelGGL(k_project_explicit<2>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey); break;
-    default: hipLaunchKernelGGL(k_project_explicit<3>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey); break;
+    case 0: hipLaunchKernelGGL(k_project_explicit<0>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
+    case 1: hipLaunchKernelGGL(k_project_explicit<1>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
+    case 2: hipLaunchKernelGGL(k_project_explicit<2>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
+    default: hipLaunchKernelGGL(k_project_explicit<3>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
   }
 }
 

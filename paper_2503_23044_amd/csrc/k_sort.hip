@@ -404,9 +404,31 @@ void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const 
 // kDupPairs + 2 since every count is >= 1; their offsets are staged in LDS,
 // where each pair finds its splat by binary search.
 // ---------------------------------------------------------------------
+// position of the k-th set bit (k from 0) of the 64-bit mask hi:lo; the mask
+// has more than k set bits
+__device__ __forceinline__ uint32_t kth_set_bit(uint32_t lo, uint32_t hi, uint32_t k) {
+  uint32_t pos = 0, w = lo;
+  const uint32_t c32 = __popc(lo);
+  if (k >= c32) {
+    k -= c32;
+    pos = 32;
+    w = hi;
+  }
+#pragma unroll
+  for (int half = 16; half >= 1; half >>= 1) {
+    const uint32_t c = __popc(w & ((1u << half) - 1u));
+    if (k >= c) {
+      k -= c;
+      pos += half;
+      w >>= half;
+    }
+  }
+  return pos;
+}
+
 __global__ __launch_bounds__(256) void k_emit_pairs(
     const ViewDev* __restrict__ views, const Splat* __restrict__ splats,
-    const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff,
+    const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff,
     const uint32_t* __restrict__ bstart, const Counters* ctr, int n_per_row,
     const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
@@ -414,8 +436,10 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
   __shared__ uint32_t s_off[M];    // first pair of each visible splat of the block
   __shared__ uint32_t s_slot[M];
   __shared__ uint32_t s_base[M];   // global id of the splat's first tile
-  __shared__ uint32_t s_nx[M];     // tiles per row of its rectangle
+  __shared__ uint32_t s_nx[M];     // tiles per row of its rectangle (| 1 << 16: masked)
   __shared__ uint32_t s_TX[M];     // tiles per row of its view
+  __shared__ uint32_t s_mlo[M];    // tile mask of a box of at most 64 tiles
+  __shared__ uint32_t s_mhi[M];
   const uint32_t P = ctr->n_pairs;
   const uint32_t nv = ctr->n_visible;
   if (nv == 0) return;
@@ -435,13 +459,18 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
       const ViewDev& V = views[v];
       const Splat& sp = splats[slot];
       const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
-      const int y_lo = sp.by & 0xFFFF;
+      const int y_lo = sp.by & 0xFFFF, y_hi = sp.by >> 16;
       const int tx0 = x_lo / tw, ty0 = y_lo / th;
+      const int nx = x_hi / tw - tx0 + 1, ny = y_hi / th - ty0 + 1;
+      const bool masked = mask_box(nx, ny);
+      const uint64_t m = masked ? tmask[slot] : 0ull;
       s_off[t] = voff[j0 + t];
       s_slot[t] = slot;
       s_base[t] = (uint32_t)(V.tile_off + ty0 * V.TX + tx0);
-      s_nx[t] = (uint32_t)(x_hi / tw - tx0 + 1);
+      s_nx[t] = (uint32_t)nx | (masked ? 1u << 16 : 0u);
       s_TX[t] = (uint32_t)V.TX;
+      s_mlo[t] = (uint32_t)m;
+      s_mhi[t] = (uint32_t)(m >> 32);
     }
     __syncthreads();
     for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
@@ -452,8 +481,11 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         else hi = mid;
       }
       const uint32_t jl = lo > 0 ? lo - 1 : 0;
-      const uint32_t k = i - s_off[jl];
-      const uint32_t nx = s_nx[jl];
+      uint32_t k = i - s_off[jl];
+      const uint32_t nxm = s_nx[jl];
+      const uint32_t nx = nxm & 0xFFFF;
+      // a masked box: the k-th kept tile is the k-th set bit (row-major)
+      if (nxm >> 16) k = kth_set_bit(s_mlo[jl], s_mhi[jl], k);
       const uint32_t ty = k / nx;
       pkey[i] = s_base[jl] + ty * s_TX[jl] + (k - ty * nx);
       pval[i] = s_slot[jl];
@@ -462,14 +494,15 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
   }
 }
 
-void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint32_t* vslot,
+void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint64_t* tmask,
+                       const uint32_t* vslot,
                        const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
                        int n_per_row, const int2* rows, uint32_t N_explicit, int tw, int th,
                        uint32_t cap, uint32_t* pkey, uint32_t* pval, hipStream_t s) {
   // the pair count is read on the device; the grid strides over blocks of
   // kDupPairs pairs
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, kDupPairs), 4096));
-  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, vslot, voff,
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, tmask, vslot, voff,
                      bstart, ctr, n_per_row, rows, N_explicit, tw, th, pkey, pval);
 }
 
