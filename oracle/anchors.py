@@ -20,6 +20,10 @@ view.  Readings of what the paper leaves open:
     Gaussian k the 11 values z2[11k : 11k+11] = (opacity, rgb, scale,
     quaternion) with o = sigmoid, rgb = sigmoid, s = l * sigmoid and the
     raw quaternion normalised at projection;
+  * opacity variant (row f3): o = tanh(z) with the Gaussians of o <= 0
+    masked out (the stream compaction of the masked-opacity decoders); a
+    masked Gaussian, like any with o < 1/255, draws nothing and gets no
+    tiles, so the mask needs no separate decision;
   * mu_k = x + O_k * l elementwise, in float64;
   * the feature F is rounded to bfloat16 (weights are given in bfloat16);
     every other decoder value is carried exactly (float64 here).
@@ -31,6 +35,8 @@ from .project import view_arrays
 
 GAUSS_OUT = 11
 FRAG = 1e-5
+OPACITY_SIGMOID = 0
+OPACITY_TANH_MASK = 1
 
 
 def select(scene, views):
@@ -106,7 +112,8 @@ def decode(scene, views, rows, emulate_bf16=True):
     l = np.asarray(scene.l, np.float64)[a]
     O = np.asarray(scene.O, np.float64)[a]
     mu = x[:, None, :] + O * l[:, None, :]
-    op = sigmoid(g[..., 0])
+    act = int(getattr(scene, "opacity_act", OPACITY_SIGMOID))
+    op = np.tanh(g[..., 0]) if act == OPACITY_TANH_MASK else sigmoid(g[..., 0])
     rgb = sigmoid(g[..., 1:4])
     ssig = sigmoid(g[..., 4:7])
     scales = l[:, None, :] * ssig
@@ -117,7 +124,7 @@ def decode(scene, views, rows, emulate_bf16=True):
         quats=quats.reshape(-1, 4), opacity=op.reshape(-1), rgb=rgb.reshape(-1, 3),
         frag_relu=frag_relu,
         _z0=z0, _pre1=pre1, _z1=z1, _z2=z2, _W1=W1, _W2=W2, _geo=geo, _l=l, _O=O,
-        _ssig=ssig, _op=op, _rgb=rgb)
+        _ssig=ssig, _op=op, _rgb=rgb, _act=act)
 
 
 def decode_backward(scene, D, g):
@@ -136,7 +143,7 @@ def decode_backward(scene, D, g):
     gc = np.asarray(g["rgb"], np.float64).reshape(r, n, 3)
     op, rgb, ssig, l, O = D["_op"], D["_rgb"], D["_ssig"], D["_l"], D["_O"]
     dz2 = np.zeros((r, n, GAUSS_OUT))
-    dz2[..., 0] = go * op * (1 - op)
+    dz2[..., 0] = go * ((1 - op * op) if D["_act"] == OPACITY_TANH_MASK else op * (1 - op))
     dz2[..., 1:4] = gc * rgb * (1 - rgb)
     dz2[..., 4:7] = gs * l[:, None, :] * ssig * (1 - ssig)
     dz2[..., 7:11] = gq

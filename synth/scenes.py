@@ -172,6 +172,7 @@ class AnchorScene:
     b2: np.ndarray          # (110,) f32
     n_levels: int
     d_max: float
+    opacity_act: int = 0    # 0: sigmoid; 1: tanh with non-positive opacities masked
 
     @property
     def n(self):
@@ -492,9 +493,11 @@ def make_small_explicit(seed, n=40, width=48, height=40, sh_degree=0,
 
 
 def make_small_anchor(seed, n_anchor=60, n_views=2, sizes=((40, 32), (24, 36)),
-                      d_max=12.0) -> Workload:
+                      d_max=12.0, opacity_act=0) -> Workload:
     """A small anchor scene with two LoD levels and views of different
-    sizes at different distances."""
+    sizes at different distances.  opacity_act = 1 selects the tanh opacity
+    with non-positive opacities masked; the opacity biases are then spread
+    around zero so that about half of the Gaussians are masked."""
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1.0, 1.0, (n_anchor, 3)).astype(np.float32)
     x[:, 2] *= 0.3
@@ -503,6 +506,10 @@ def make_small_anchor(seed, n_anchor=60, n_views=2, sizes=((40, 32), (24, 36)),
     scene = _anchor_attrs(rng, x, level, delta, d_max, n_levels=3)
     # keep the decoded Gaussians small relative to the views
     scene.O[:] = (scene.O * 0.8).astype(np.float32)
+    if opacity_act:
+        scene.opacity_act = int(opacity_act)
+        n_off = scene.O.shape[1]
+        scene.b2[0::11] = rng.normal(0.0, 0.8, n_off).astype(np.float32)
     views = []
     for i in range(n_views):
         W, H = sizes[i % len(sizes)]

@@ -106,8 +106,11 @@ def test_explicit_gradients_two_views_background():
     assert _check(sc, render, keys, 8, seed=8) >= 25
 
 
-def test_anchor_gradients_by_finite_differences():
-    wl = scenes.make_small_anchor(41, n_anchor=16)
+@pytest.mark.parametrize("act", [0, 1])
+def test_anchor_gradients_by_finite_differences(act):
+    """Decoder adjoint by central differences; act = 1 reads the opacity as
+    tanh with non-positive opacities masked (about half of them here)."""
+    wl = scenes.make_small_anchor(41, n_anchor=16, opacity_act=act)
     sc = wl.scene
     for k in ("x", "l", "O", "F", "b1", "b2"):
         setattr(sc, k, np.asarray(getattr(sc, k), np.float64).copy())

@@ -337,3 +337,30 @@ def test_tile_mask_is_ellipse_rectangle_overlap(tile):
                 culled += 1 - bit
     assert checked > 500
     assert culled > 0.05 * checked      # the ellipse leaves part of the box's tiles
+
+
+def test_tanh_opacity_masks_non_positive():
+    """Masked-opacity decoder variant: the same decoder outputs read as tanh
+    instead of sigmoid, and every Gaussian with tanh(z) <= 0 is culled (not
+    valid, no tiles) while the others project as they would with that
+    opacity."""
+    from oracle import anchors
+    from synth import scenes
+    wl = scenes.make_small_anchor(5, n_anchor=40, opacity_act=1)
+    sc = wl.scene
+    rows, _ = anchors.select(sc, wl.views)
+    D = anchors.decode(sc, wl.views, rows)
+    z = D["_z2"].reshape(rows.shape[0], -1, anchors.GAUSS_OUT)[..., 0].ravel()
+    np.testing.assert_array_equal(D["opacity"], np.tanh(z))
+    masked = z <= 0
+    assert 0.2 < masked.mean() < 0.8
+    v0 = rows[:, 0] == 0
+    sel = np.repeat(v0, D["n"])
+    P = project.project(D["mu"][sel], D["scales"][sel], D["quats"][sel], D["opacity"][sel],
+                        wl.views[0], (16, 16), colour=D["rgb"][sel])
+    assert not P["valid"][masked[sel]].any()
+    assert (P["count"][masked[sel]] == 0).all()
+    keep = ~masked[sel] & (D["opacity"][sel] >= 1.0 / 255.0)
+    P2 = project.project(D["mu"][sel][keep], D["scales"][sel][keep], D["quats"][sel][keep],
+                         D["opacity"][sel][keep], wl.views[0], (16, 16), colour=D["rgb"][sel][keep])
+    np.testing.assert_array_equal(P2["box"], P["box"][keep])
