@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 2
+#define CGX_ABI_VERSION 3
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -112,12 +112,18 @@ typedef struct cgx_explicit_scene {
  * Decoder input z0 = [bf16(F), (c_v - x_a)/|c_v - x_a|, |c_v - x_a|/d_max],
  *   z1 = relu(z0 W1 + b1), z2 = z1 W2 + b2; Gaussian k reads z2[11k..11k+10]
  *   as opacity = sigmoid, rgb = sigmoid, scale = l * sigmoid, quaternion
- *   (normalised at projection); mu_k = x + O_k * l. */
+ *   (normalised at projection); mu_k = x + O_k * l.
+ * opacity_act = CGX_OPACITY_TANH_MASK reads the opacity as tanh instead and
+ *   masks out (draws nothing of, gives no tiles and zero gradient to) the
+ *   Gaussians with opacity <= 0, the masked-opacity decoder variant; any
+ *   other value than the two is CGX_ERR_INVALID_ARG. */
+enum { CGX_OPACITY_SIGMOID = 0, CGX_OPACITY_TANH_MASK = 1 };
 typedef struct cgx_anchor_scene {
   int64_t n_anchor;
   int32_t n_offsets;            /* n, 1..16 */
   int32_t n_levels;             /* K */
   float d_max;
+  int32_t opacity_act;          /* CGX_OPACITY_SIGMOID or CGX_OPACITY_TANH_MASK */
   const float* x;
   const float* l;
   const float* O;

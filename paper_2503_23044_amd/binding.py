@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 2
+CGX_ABI_VERSION = 3
+OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
 CGX_ERR_UNSUPPORTED = 2
@@ -43,7 +44,8 @@ class cgx_explicit_scene(C.Structure):
 
 class cgx_anchor_scene(C.Structure):
     _fields_ = [("n_anchor", C.c_int64), ("n_offsets", C.c_int32), ("n_levels", C.c_int32),
-                ("d_max", C.c_float), ("x", C.c_void_p), ("l", C.c_void_p), ("O", C.c_void_p),
+                ("d_max", C.c_float), ("opacity_act", C.c_int32), ("x", C.c_void_p),
+                ("l", C.c_void_p), ("O", C.c_void_p),
                 ("F", C.c_void_p), ("level", C.c_void_p), ("W1", C.c_void_p), ("b1", C.c_void_p),
                 ("W2", C.c_void_p), ("b2", C.c_void_p)]
 
@@ -218,6 +220,7 @@ def make_scene(scene: dict) -> cgx_scene:
         s.an.n_offsets = int(scene["O"].shape[1])
         s.an.n_levels = int(scene["n_levels"])
         s.an.d_max = float(scene["d_max"])
+        s.an.opacity_act = int(scene.get("opacity_act", OPACITY_SIGMOID))
         for k in ("x", "l", "O", "F", "level", "W1", "b1", "W2", "b2"):
             setattr(s.an, k, _ptr(scene[k]))
     return s

@@ -114,6 +114,8 @@ static int32_t check_scene(cgx_ctx* c, const cgx_scene* s, int32_t B) {
       return fail(c, CGX_ERR_UNSUPPORTED, "n_offsets %d not in 1..%d", a.n_offsets, CGX_MAX_OFFSETS);
     if (a.n_offsets != 10)
       return fail(c, CGX_ERR_UNSUPPORTED, "this build decodes n_offsets = 10 Gaussians per anchor");
+    if (a.opacity_act != CGX_OPACITY_SIGMOID && a.opacity_act != CGX_OPACITY_TANH_MASK)
+      return fail(c, CGX_ERR_INVALID_ARG, "opacity_act %d is not a known activation", a.opacity_act);
     if (a.n_levels < 1 || a.n_levels > 16)
       return fail(c, CGX_ERR_INVALID_ARG, "n_levels %d not in 1..16", a.n_levels);
     if (!(a.d_max > 0.f) || !std::isfinite(a.d_max))

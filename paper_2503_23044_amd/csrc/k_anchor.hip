@@ -244,7 +244,8 @@ __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uin
   in.m0 = (double)X[0] + (double)O[0] * (double)L[0];
   in.m1 = (double)X[1] + (double)O[1] * (double)L[1];
   in.m2 = (double)X[2] + (double)O[2] * (double)L[2];
-  in.op = sigmoidf(z2[0]);
+  // masked variant: tanh, and o <= 0 fails the projection's o >= 1/255 test
+  in.op = sc.opacity_act == CGX_OPACITY_TANH_MASK ? tanhf(z2[0]) : sigmoidf(z2[0]);
   in.col[0] = sigmoidf(z2[1]);
   in.col[1] = sigmoidf(z2[2]);
   in.col[2] = sigmoidf(z2[3]);
@@ -579,7 +580,8 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
     gs[c] = dmu[c];
     gs[3 + c] = ds[c] * sig_s[c] + dmu[c] * O[c];
   }
-  dz2[0] = gg[5] * in.op * (1.0f - in.op);
+  dz2[0] = gg[5] * (sc.opacity_act == CGX_OPACITY_TANH_MASK ? 1.0f - in.op * in.op
+                                                            : in.op * (1.0f - in.op));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     dz2[1 + c] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);

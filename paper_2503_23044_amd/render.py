@@ -24,15 +24,17 @@ def explicit_scene(means, scales, quats, opacity, sh, sh_degree, device="cuda"):
                 opacity=f(opacity), sh=f(sh), sh_degree=int(sh_degree))
 
 
-def anchor_scene(x, l, O, F, level, W1_bits, b1, W2_bits, b2, n_levels, d_max, device="cuda"):
+def anchor_scene(x, l, O, F, level, W1_bits, b1, W2_bits, b2, n_levels, d_max, device="cuda",
+                 opacity_act=B.OPACITY_SIGMOID):
     """Device tensors of a voxel-anchor scene; decoder weights as bfloat16
-    bit patterns (held in int16 tensors)."""
+    bit patterns (held in int16 tensors).  opacity_act: B.OPACITY_SIGMOID or
+    B.OPACITY_TANH_MASK (tanh, non-positive opacities masked)."""
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)  # noqa: E731
     bits = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.uint16).view(np.int16), device=device)  # noqa: E731
     return dict(kind=B.CGX_SCENE_ANCHOR, x=f(x), l=f(l), O=f(O), F=f(F),
                 level=torch.as_tensor(np.ascontiguousarray(level, np.uint8), device=device),
                 W1=bits(W1_bits), b1=f(b1), W2=bits(W2_bits), b2=f(b2),
-                n_levels=int(n_levels), d_max=float(d_max))
+                n_levels=int(n_levels), d_max=float(d_max), opacity_act=int(opacity_act))
 
 
 def scene_from(obj, device="cuda"):
@@ -40,7 +42,8 @@ def scene_from(obj, device="cuda"):
     if hasattr(obj, "means"):
         return explicit_scene(obj.means, obj.scales, obj.quats, obj.opacity, obj.sh, obj.sh_degree, device)
     return anchor_scene(obj.x, obj.l, obj.O, obj.F, obj.level, obj.W1_bits, obj.b1, obj.W2_bits,
-                        obj.b2, obj.n_levels, obj.d_max, device)
+                        obj.b2, obj.n_levels, obj.d_max, device,
+                        getattr(obj, "opacity_act", B.OPACITY_SIGMOID))
 
 
 def pixel_offsets(views):

@@ -100,6 +100,11 @@ def test_workspace_size_validation(B):
         sc["d_max"] = 0.0
         assert _status(B, B.cgx_workspace_size, ctx, [_view()], sc) == "CGX_ERR_INVALID_ARG"
         assert _status(B, B.cgx_workspace_size, ctx, [_view()] * 33, _explicit()) == "CGX_ERR_INVALID_ARG"
+        sc = _anchor()
+        sc["opacity_act"] = 2
+        assert _status(B, B.cgx_workspace_size, ctx, [_view()], sc) == "CGX_ERR_INVALID_ARG"
+        sc["opacity_act"] = B.OPACITY_TANH_MASK
+        assert B.cgx_workspace_size(ctx, [_view()], sc) > 0
         assert B.cgx_workspace_size(ctx, [_view()], _anchor()) > 0
     finally:
         B.cgx_destroy(ctx)

@@ -31,6 +31,19 @@ def test_small_anchor_forward_backward(R, seed, tile):
     print(f"case: small anchor seed {seed} tile {tile}", flush=True)
     wl = scenes.make_small_anchor(seed, n_anchor=70, n_views=3,
                                   sizes=((40, 32), (24, 36), (33, 17)))
+    _anchor_fwd_bwd(R, wl, seed, tile)
+
+
+def test_small_anchor_tanh_masked_opacity(R):
+    """Masked-opacity decoder variant: tanh opacity, non-positive ones masked
+    (about half of the Gaussians here)."""
+    print("case: small anchor tanh masked opacity", flush=True)
+    wl = scenes.make_small_anchor(17, n_anchor=70, n_views=3,
+                                  sizes=((40, 32), (24, 36), (33, 17)), opacity_act=1)
+    _anchor_fwd_bwd(R, wl, 17, (16, 16))
+
+
+def _anchor_fwd_bwd(R, wl, seed, tile):
     rd = R.Renderer(0, tile)
     sc = R.scene_from(wl.scene)
     out = rd.forward(wl.views, sc)
