@@ -356,14 +356,23 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         const float dg = raw < kAlphaMax ? da : 0.0f;
         g[5] += dg * (raw * s.inv_o);         // d alpha / d o = exp(power)
         const float dpw = dg * raw;           // d alpha / d power = o exp(power)
-        g[0] += dpw * (2.0f * s.pa * dx + s.pb * dy);
-        g[1] += dpw * (2.0f * s.pc * dy + s.pb * dx);
-        g[2] += dpw * dx * dx;
-        g[3] += dpw * dx * dy;
-        g[4] += dpw * dy * dy;
+        // moments of dpw; the mean's terms take the splat's (uniform) conic
+        // once per splat below
+        const float px = dpw * dx, py = dpw * dy;
+        g[0] += px;
+        g[1] += py;
+        g[2] += px * dx;
+        g[3] += px * dy;
+        g[4] += py * dy;
         any = any || hit;
       }
       if (__ballot(any) == 0) continue;
+      {
+        // d power / d u = 2 pa dx + pb dy, d power / d w = 2 pc dy + pb dx
+        const float m0 = g[0], m1 = g[1];
+        g[0] = 2.0f * s.pa * m0 + s.pb * m1;
+        g[1] = 2.0f * s.pc * m1 + s.pb * m0;
+      }
       // wave totals of the 13 terms land in lanes 0..12; one atomic
       // instruction then adds them to the splat's 64-byte gradient record
       const float r = wave_reduce_scatter16(g, lane);
