@@ -354,10 +354,11 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         g[12] += w * GN2[k];
         // alpha clamped at kAlphaMax: no gradient through o or the power
         const float dg = raw < kAlphaMax ? da : 0.0f;
-        g[5] += dg * (raw * s.inv_o);         // d alpha / d o = exp(power)
         const float dpw = dg * raw;           // d alpha / d power = o exp(power)
-        // moments of dpw; the mean's terms take the splat's (uniform) conic
-        // once per splat below
+        // moments of dpw; the opacity term (d alpha / d o = exp(power) =
+        // dpw / o) and the mean's terms take the splat's uniform 1/o and
+        // conic once per splat below
+        g[5] += dpw;
         const float px = dpw * dx, py = dpw * dy;
         g[0] += px;
         g[1] += py;
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         const float m0 = g[0], m1 = g[1];
         g[0] = 2.0f * s.pa * m0 + s.pb * m1;
         g[1] = 2.0f * s.pc * m1 + s.pb * m0;
+        g[5] *= s.inv_o;
       }
       // wave totals of the 13 terms land in lanes 0..12; one atomic
       // instruction then adds them to the splat's 64-byte gradient record
