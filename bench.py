@@ -48,6 +48,12 @@ def parse():
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=4000)
+    p.add_argument("--no-ncc", action="store_true",
+                   help="skip the timing of the batch geometric loss (Eq. 10)")
+    p.add_argument("--ncc-patches", type=int, default=4096,
+                   help="7x7 patches per view pair in the geometric-loss timing")
+    p.add_argument("--ncc-only", action="store_true",
+                   help="time only the geometric loss and print its JSON object")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
                         "for scaling hardware byte counters)")
@@ -273,12 +279,49 @@ def cpu_baseline(wl, n_sample_tiles):
                         f"1 thread"))
 
 
+def ncc_leg(args):
+    """Timing of the batch geometric loss (Eq. 10, cgx_ncc_loss) on the C2
+    scene seen by 4 pairs of nearby 1920x1080 cameras: one forward render,
+    then the loss and its RGB gradient over args.ncc_patches patches per
+    pair, timed with HIP events over 20 launches."""
+    import torch
+
+    from paper_2503_23044_amd import render
+    from synth import scenes
+
+    wl = scenes.make_c2_pairs()
+    rd = render.Renderer(0, (16, 16))
+    sc = render.scene_from(wl.scene, "cuda:0")
+    out = rd.forward(wl.views, sc)
+    centres = torch.as_tensor(scenes.patch_centres(7, wl.views, args.ncc_patches), device="cuda:0")
+    grad, loss = rd.ncc_loss(wl.views, out, centres)
+    torch.cuda.synchronize()
+    loss.zero_()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rd.ncc_loss(wl.views, out, centres, grad_rgb=grad, loss=loss)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    patches = len(wl.views) // 2 * args.ncc_patches
+    log(f"[bench] geometric loss: {patches} patches in {ms * 1e3:.1f} us, loss {loss.item() / reps:.4f}")
+    return {"workload": "C2 scene, 4 pairs of nearby 1920x1080 views, 7x7 patches",
+            "patches": patches, "ms": round(ms, 4),
+            "Mpatches_per_s": round(patches / (ms * 1e-3) / 1e6, 2),
+            "loss": round(loss.item() / reps, 6)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               f"(the multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if args.ncc_only:
+        print(json.dumps({"ncc_loss": ncc_leg(args)}), flush=True)
+        return
     from synth import scenes
     t0 = time.perf_counter()
     wl = scenes.make(args.config)
@@ -313,6 +356,8 @@ def main():
         "peak_hbm_gib": round(res["peak_bytes"] / 2**30, 3),
         "roofline": roofline(res, args.steps),
     }
+    if not args.no_ncc:
+        line["ncc_loss"] = ncc_leg(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tiles)

@@ -408,6 +408,26 @@ def make_c2(seed: int = 2, n_anchor: int = 200_000, n_views: int = 8) -> Workloa
     return wl
 
 
+def make_c2_pairs(seed: int = 2, n_anchor: int = 200_000, n_pairs: int = 4) -> Workload:
+    """The C2 scene seen by n_pairs pairs of nearby 1920x1080 cameras (views
+    2i, 2i + 1 a few metres apart, aimed at the same point): the batch
+    pairing of the geometric loss's training step."""
+    scene = make_city_block(seed, n_anchor, 6.4)
+    rng = np.random.default_rng(20 + seed)
+    views = []
+    for _ in range(n_pairs):
+        ang = rng.uniform(0, 2 * np.pi)
+        rad = rng.uniform(80, 160)
+        h = rng.uniform(40, 120)
+        pos = np.array([100.0 + rad * np.cos(ang), 100.0 + rad * np.sin(ang), h])
+        tgt = (rng.uniform(70, 130), rng.uniform(70, 130), 0.0)
+        step = rng.normal(0.0, 1.0, 3)
+        step *= rng.uniform(2.0, 5.0) / np.linalg.norm(step)
+        views.append(look_at(tuple(pos), tgt, 1920, 1080))
+        views.append(look_at(tuple(pos + step), tgt, 1920, 1080))
+    return Workload("c2_pairs", scene, views)
+
+
 def make_c3(seed: int = 3, n_anchor: int = 600_000, n_views: int = 4) -> Workload:
     """C3: 600k anchors (6M Gaussians), 4 views at 3840x2160."""
     scene = make_city_block(seed, n_anchor, 4.0)
