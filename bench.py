@@ -54,6 +54,10 @@ def parse():
                    help="7x7 patches per view pair in the geometric-loss timing")
     p.add_argument("--ncc-only", action="store_true",
                    help="time only the geometric loss and print its JSON object")
+    p.add_argument("--no-depth", action="store_true",
+                   help="skip the timing of the depth-prior alignment and filter (Sec. 3.4)")
+    p.add_argument("--depth-only", action="store_true",
+                   help="time only the depth-prior steps and print their JSON object")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
                         "for scaling hardware byte counters)")
@@ -313,6 +317,52 @@ def ncc_leg(args):
             "loss": round(loss.item() / reps, 6)}
 
 
+def depth_prior_leg(args):
+    """Timing of the depth-prior steps (Sec. 3.4, Step 2): the per-view
+    scale / shift of a pseudo depth against 1M sparse points
+    (cgx_depth_prior_align) and the multi-view filter with tau_d = 1
+    (cgx_depth_prior_filter) over 4 pairs of nearby 1920x1080 views, each
+    timed with HIP events over 20 launches on the library's stream."""
+    import torch
+
+    import numpy as np
+
+    from paper_2503_23044_amd import binding as B
+    from paper_2503_23044_amd import render
+    from synth import scenes
+
+    t0 = time.perf_counter()
+    X = scenes.make_depth_prior()
+    log(f"[bench] depth prior inputs generated in {time.perf_counter() - t0:.1f} s")
+    rd = render.Renderer(0, (16, 16))
+    prior = torch.from_numpy(np.concatenate(X.prior)).cuda()
+    points = torch.from_numpy(X.points).cuda()
+    filtered, aligned, st = rd.depth_prior(X.views, prior, points, X.nearby)
+    torch.cuda.synchronize()
+    reps = 20
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_a = timed(lambda: B.cgx_depth_prior_align(rd.ctx, X.views, prior, points, rd.depth_ws, st,
+                                                 aligned))
+    ms_f = timed(lambda: B.cgx_depth_prior_filter(rd.ctx, X.views, aligned, X.nearby, 1.0, filtered))
+    px = sum(int(v.width) * int(v.height) for v in X.views)
+    kept = float((filtered > 0).sum().item()) / max(float((aligned > 0).sum().item()), 1.0)
+    log(f"[bench] depth prior: align {ms_a * 1e3:.1f} us, filter {ms_f * 1e3:.1f} us, {px} px, "
+        f"kept {kept:.3f}")
+    return {"workload": "4 pairs of nearby 1920x1080 views over a box city, 1M sparse points",
+            "pixels": px, "points": int(len(X.points)), "ms_align": round(ms_a, 4),
+            "ms_filter": round(ms_f, 4), "ms": round(ms_a + ms_f, 4),
+            "Mpixels_per_s": round(px / ((ms_a + ms_f) * 1e-3) / 1e6, 1), "kept": round(kept, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -321,6 +371,9 @@ def main():
         sys.exit(2)
     if args.ncc_only:
         print(json.dumps({"ncc_loss": ncc_leg(args)}), flush=True)
+        return
+    if args.depth_only:
+        print(json.dumps({"depth_prior": depth_prior_leg(args)}), flush=True)
         return
     from synth import scenes
     t0 = time.perf_counter()
@@ -358,6 +411,8 @@ def main():
     }
     if not args.no_ncc:
         line["ncc_loss"] = ncc_leg(args)
+    if not args.no_depth:
+        line["depth_prior"] = depth_prior_leg(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tiles)

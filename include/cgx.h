@@ -290,6 +290,47 @@ int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                      const int32_t* centres, int32_t n_patch, float weight,
                      float* grad_rgb, float* loss_dev, void* stream);
 
+/* Depth prior, step 1 of 2 (Sec. 3.4, Step 2): per-view scale s and shift
+ * t that bring a monocular pseudo depth to the scene through the sparse
+ * points.  `prior` (device float32) holds one z-depth map per view in the
+ * packed pixel layout (a value <= 0 or NaN means no prior at that pixel);
+ * `points` (device float32, n_points x 3, world frame) are the sparse
+ * points.  For view v every point with camera depth z > z_near whose
+ * projection (u, w) lies in [0, W) x [0, H) pairs its z with the prior d at
+ * pixel (floor u, floor w) if d > 0; (s, t) minimise sum (s d + t - z)^2
+ * over the pairs (the 2x2 normal equations in float64, sums reduced in a
+ * fixed order, so repeated calls give identical results); with fewer than
+ * two pairs or a singular system (s, t) = (1, 0).  Outputs:
+ * scale_shift[2 v + {0, 1}] = (s, t) (device float64) and aligned = s D + t
+ * where D > 0, else 0 (device float32, packed layout; may be the same
+ * buffer as prior).  `workspace` (device, 8-byte aligned) holds the partial
+ * sums: at least cgx_depth_align_workspace_size(n_views) bytes, contents
+ * not needed between calls.  Errors: CGX_ERR_INVALID_ARG for a bad view or
+ * a NULL pointer, CGX_ERR_WORKSPACE for a small workspace; nothing is
+ * launched then. */
+size_t cgx_depth_align_workspace_size(int32_t n_views);
+int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                              const float* prior, const float* points, int32_t n_points,
+                              void* workspace, size_t workspace_bytes, double* scale_shift,
+                              float* aligned, void* stream);
+
+/* Depth prior, step 2 of 2 (Sec. 3.4, Step 2; tau_d = 1 in Sec. 4):
+ * multi-view consistency filter.  For pixel p = (i + 1/2, j + 1/2) of view
+ * v with depth d > 0 (device float32, packed layout) and its nearby view
+ * u = nearby[v] (HOST int32 array of n_views entries; -1: no nearby view,
+ * every d > 0 kept): the point d K_v^-1 [p, 1] moves to camera u; if it is
+ * in front of u (z > z_near) and lands at q inside u's image, u's depth d_u
+ * at pixel floor(q) lifts q to d_u K_u^-1 [q, 1], which moves back to
+ * camera v; the pixel is kept iff d_u > 0, that point is in front of v and
+ * its projection p' satisfies |p' - p| < tau (pixels).  Cameras invert as
+ * X = R^T (x - t).  filtered = d where kept, else 0 (device float32,
+ * packed layout; must not alias depth).  Float64, contraction off, one
+ * fixed operation order.  Errors: CGX_ERR_INVALID_ARG for a bad view, a
+ * nearby entry that is not -1 or another view, tau <= 0 or aliasing. */
+int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                               const float* depth, const int32_t* nearby, float tau,
+                               float* filtered, void* stream);
+
 /* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
  * images do not depend on the tile shape, only the speed does).  For each
  * supported shape (in the order 16x16, 8x8, 16x8, 32x8, 32x16) that fits

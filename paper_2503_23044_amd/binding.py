@@ -123,6 +123,11 @@ def load_library(path: str = LIB_PATH):
         "cgx_graph_destroy": (C.c_int32, [P]),
         "cgx_ncc_loss": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, C.POINTER(cgx_images), P,
                                      C.c_int32, C.c_float, P, P, P]),
+        "cgx_depth_align_workspace_size": (C.c_size_t, [C.c_int32]),
+        "cgx_depth_prior_align": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P, C.c_int32, P,
+                                              C.c_size_t, P, P, P]),
+        "cgx_depth_prior_filter": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P,
+                                               C.POINTER(C.c_int32), C.c_float, P, P]),
         "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
                                             C.c_size_t, C.POINTER(cgx_images),
@@ -308,6 +313,34 @@ def cgx_ncc_loss(ctx, views, ws, images, centres, n_patch, weight, grad_rgb, los
                           _ptr(centres), int(n_patch), float(weight), _ptr(grad_rgb), _ptr(loss_dev),
                           _stream())
     _check(ctx, rc, "cgx_ncc_loss")
+
+
+def cgx_depth_align_workspace_size(n_views):
+    return int(load_library().cgx_depth_align_workspace_size(int(n_views)))
+
+
+def cgx_depth_prior_align(ctx, views, prior, points, ws, scale_shift, aligned):
+    """Per-view least-squares (s, t) of the packed float32 prior against the
+    float32 (N, 3) points; writes scale_shift (float64, 2 per view) and
+    aligned (float32, packed; may be prior itself)."""
+    lib = load_library()
+    va = make_views(views)
+    n = int(points.numel() // 3) if points is not None else 0
+    rc = lib.cgx_depth_prior_align(ctx, va, len(views), _ptr(prior), _ptr(points) if n else None, n,
+                                   C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                   _ptr(scale_shift), _ptr(aligned), _stream())
+    _check(ctx, rc, "cgx_depth_prior_align")
+
+
+def cgx_depth_prior_filter(ctx, views, depth, nearby, tau, filtered):
+    """Multi-view consistency filter of the packed float32 depth maps;
+    nearby is a host sequence (one view index or -1 per view)."""
+    lib = load_library()
+    va = make_views(views)
+    nb = (C.c_int32 * len(views))(*[int(x) for x in nearby])
+    rc = lib.cgx_depth_prior_filter(ctx, va, len(views), _ptr(depth), nb, float(tau), _ptr(filtered),
+                                    _stream())
+    _check(ctx, rc, "cgx_depth_prior_filter")
 
 
 TILE_SHAPES = [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16)]

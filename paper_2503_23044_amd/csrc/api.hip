@@ -754,6 +754,89 @@ int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views, const
   return CGX_OK;
 }
 
+static int pack_depth_cams(const cgx_view* views, int32_t n, const int32_t* nearby,
+                           DepthCamPack& P) {
+  memset(&P, 0, sizeof(P));
+  int64_t off = 0;
+  int max_pix = 0;
+  for (int i = 0; i < n; ++i) {
+    const cgx_view& v = views[i];
+    DepthCam& c = P.v[i];
+    memcpy(c.R, v.R, sizeof(c.R));
+    memcpy(c.t, v.t, sizeof(c.t));
+    c.fx = v.fx;
+    c.fy = v.fy;
+    c.cx = v.cx;
+    c.cy = v.cy;
+    c.z_near = v.z_near;
+    c.W = v.width;
+    c.H = v.height;
+    c.pix_off = (int32_t)off;
+    c.nearby = nearby ? nearby[i] : -1;
+    off += (int64_t)v.width * v.height;
+    max_pix = std::max(max_pix, v.width * v.height);
+  }
+  return max_pix;
+}
+
+size_t cgx_depth_align_workspace_size(int32_t n_views) {
+  return n_views < 1 ? 0 : depth_align_scratch_bytes(n_views);
+}
+
+int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                              const float* prior, const float* points, int32_t n_points,
+                              void* workspace, size_t workspace_bytes, double* scale_shift,
+                              float* aligned, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_views(ctx, views, n_views);
+  if (rc) return rc;
+  if (n_points < 0 || n_points > INT32_MAX / 3)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "n_points %d outside 0..%d", n_points, INT32_MAX / 3);
+  if (!prior || !scale_shift || !aligned || !workspace)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "prior, workspace, scale_shift and aligned are required");
+  if (n_points > 0 && !points) return fail(ctx, CGX_ERR_INVALID_ARG, "points is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(scale_shift) & 7) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "scale_shift must be 8-byte aligned");
+  if (workspace_bytes < depth_align_scratch_bytes(n_views))
+    return fail(ctx, CGX_ERR_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes,
+                depth_align_scratch_bytes(n_views));
+  rc = set_device(ctx);
+  if (rc) return rc;
+  DepthCamPack P;
+  const int max_pix = pack_depth_cams(views, n_views, nullptr, P);
+  launch_depth_align(P, n_views, max_pix, prior, points, n_points,
+                     reinterpret_cast<double*>(workspace), scale_shift, aligned, (hipStream_t)stream);
+  HIP_OK(ctx, hipGetLastError());
+  return CGX_OK;
+}
+
+int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                               const float* depth, const int32_t* nearby, float tau,
+                               float* filtered, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_views(ctx, views, n_views);
+  if (rc) return rc;
+  if (!depth || !filtered || !nearby)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "depth, nearby and filtered are required");
+  if (depth == filtered)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "filtered must not alias depth (nearby views are read)");
+  if (!(tau > 0.f) || !std::isfinite(tau)) return fail(ctx, CGX_ERR_INVALID_ARG, "tau must be > 0");
+  for (int i = 0; i < n_views; ++i)
+    if (nearby[i] < -1 || nearby[i] >= n_views || nearby[i] == i)
+      return fail(ctx, CGX_ERR_INVALID_ARG, "nearby[%d] = %d is not -1 or another view", i,
+                  nearby[i]);
+  rc = set_device(ctx);
+  if (rc) return rc;
+  DepthCamPack P;
+  const int max_pix = pack_depth_cams(views, n_views, nearby, P);
+  launch_depth_filter(P, n_views, max_pix, depth, (double)tau * (double)tau, filtered,
+                      (hipStream_t)stream);
+  HIP_OK(ctx, hipGetLastError());
+  return CGX_OK;
+}
+
 int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                             const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
                             size_t workspace_bytes, const cgx_images* target,

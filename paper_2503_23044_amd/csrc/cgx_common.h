@@ -363,4 +363,27 @@ void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const 
                      const float* plane_d, const int32_t* centres, int n_patch, float weight,
                      float* grad_rgb, float* loss, hipStream_t s);
 
+// Depth prior (Sec. 3.4, Step 2).  Cameras travel in the kernel arguments
+// (84 bytes each, a whole batch of 32 in 2.7 KB).
+struct DepthCam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, z_near;
+  int32_t W, H, pix_off;
+  int32_t nearby;              // view index of the nearby view, -1: none
+};
+struct DepthCamPack {
+  DepthCam v[CGX_MAX_VIEWS];
+};
+constexpr int kAlignBlocks = 64;         // partial sums per view
+constexpr int kAlignSums = 5;            // n, sum d, sum z, sum d^2, sum d z
+inline size_t depth_align_scratch_bytes(int n_views) {
+  return (size_t)n_views * kAlignBlocks * kAlignSums * sizeof(double);
+}
+void launch_depth_align(const DepthCamPack& cams, int n_views, int max_pix, const float* prior,
+                        const float* points, int n_points, double* partial, double* st,
+                        float* aligned, hipStream_t s);
+void launch_depth_filter(const DepthCamPack& cams, int n_views, int max_pix, const float* depth,
+                         double tau2, float* out, hipStream_t s);
+
 }  // namespace cgx

@@ -92,6 +92,7 @@ class Renderer:
         self.tile = tuple(tile)
         self.ctx = B.cgx_create(device, tile[0], tile[1])
         self.ws = None
+        self.depth_ws = None
         self.cap = {}
 
     def __del__(self):
@@ -259,6 +260,25 @@ class Renderer:
         n_patch = int(c.shape[1]) if c.dim() == 3 else int(c.numel() // 2 // max(len(views) // 2, 1))
         B.cgx_ncc_loss(self.ctx, views, self.ws, out, c, n_patch, weight, grad_rgb, loss)
         return grad_rgb, loss
+
+    def depth_prior(self, views, prior, points, nearby, tau=1.0, aligned=None, filtered=None):
+        """Depth prior of Sec. 3.4 (Step 2): per-view scale / shift of the
+        packed float32 pseudo-depth `prior` against the sparse float32 (N, 3)
+        `points`, then the multi-view filter with nearby[v] (or -1) at
+        tau_d = `tau` pixels.  Returns (filtered, aligned, scale_shift (B, 2)
+        float64)."""
+        dev = f"cuda:{self.device}"
+        nbytes = B.cgx_depth_align_workspace_size(len(views))
+        if self.depth_ws is None or self.depth_ws.numel() * 8 < nbytes:
+            self.depth_ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+        st = torch.empty(len(views), 2, dtype=torch.float64, device=dev)
+        if aligned is None:
+            aligned = torch.empty_like(prior)
+        if filtered is None:
+            filtered = torch.empty_like(prior)
+        B.cgx_depth_prior_align(self.ctx, views, prior, points, self.depth_ws, st, aligned)
+        B.cgx_depth_prior_filter(self.ctx, views, aligned, nearby, tau, filtered)
+        return filtered, aligned, st
 
     def info(self):
         return B.cgx_read_info(self.ctx, self.ws)

@@ -2,7 +2,10 @@
 
 This module only draws random inputs and places cameras; it holds none of
 the rasterizer's arithmetic (no projection, decoding, binning or
-compositing).  Both the FP64 oracle's tests and the GPU path's tests and
+compositing) and none of the depth prior's (no least squares, no
+re-projection): for the depth-prior inputs it ray-casts a scene of boxes to
+get the true depth that a monocular network would approximate, and turns
+that into a pseudo depth with an unknown scale and shift.  Both the FP64 oracle's tests and the GPU path's tests and
 benchmark consume the arrays it returns, so the two sides always see the
 same bytes.
 
@@ -582,3 +585,110 @@ def patch_centres(seed, views, n_patch, patch=7) -> np.ndarray:
         out[i, :, 0] = rng.integers(h, int(v.width) - h, n_patch)
         out[i, :, 1] = rng.integers(h, int(v.height) - h, n_patch)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Depth-prior inputs (Sec. 3.4, Step 2): dense pseudo depths known only up to
+# a per-view scale and shift, sparse points on the surfaces, nearby views.
+
+@dataclass
+class DepthPriorInputs:
+    views: list
+    prior: list             # per view (H*W,) f32 pseudo depth, 0 = no prior
+    points: np.ndarray      # (N, 3) f32 sparse points (surface samples + outliers)
+    nearby: list            # per view: index of its nearby view
+    depth: list             # per view (H*W,) f64 true z-depth, 0 = nothing hit
+    scale_shift: np.ndarray  # (B, 2) the (s, t) the prior was made with
+
+
+def raycast_boxes(view, boxes):
+    """True z-depth of every pixel of `view` on the ground plane z = 0 and
+    the axis-aligned boxes (cx, cy, sx, sy, h) standing on it; 0 where the
+    ray hits nothing.  Pixel rays are scaled to camera z = 1, so the ray
+    parameter of a hit is its z-depth."""
+    W, H = int(view.width), int(view.height)
+    R = np.asarray(view.R, np.float64)
+    t = np.asarray(view.t, np.float64)
+    c = -R.T @ t
+    J, I = np.divmod(np.arange(W * H), W)
+    dc = np.stack([(I + 0.5 - view.cx) / view.fx, (J + 0.5 - view.cy) / view.fy, np.ones(W * H)])
+    d = R.T @ dc                                                     # world ray directions
+    with np.errstate(divide="ignore", invalid="ignore"):
+        best = np.where(d[2] < 0, -c[2] / d[2], np.inf)
+        inv = 1.0 / d
+        for b in boxes:
+            lo = np.array([b[0] - b[2] / 2, b[1] - b[3] / 2, 0.0])
+            hi = np.array([b[0] + b[2] / 2, b[1] + b[3] / 2, b[4]])
+            t1 = (lo[:, None] - c[:, None]) * inv
+            t2 = (hi[:, None] - c[:, None]) * inv
+            tn = np.nanmax(np.minimum(t1, t2), axis=0)
+            tf = np.nanmin(np.maximum(t1, t2), axis=0)
+            hit = (tf >= tn) & (tn > 0)
+            best = np.where(hit & (tn < best), tn, best)
+    return np.where(np.isfinite(best), best, 0.0)
+
+
+def make_depth_prior(seed=5, n_pairs=4, width=1920, height=1080, n_points=1_000_000,
+                     n_boxes=40, outliers=0.05, noise=0.01, blob_frac=0.05, sizes=None):
+    """Pairs of nearby cameras (2-5 m apart, aimed at one point) over a
+    200x200 m block of boxes.  Per view the pseudo depth is
+    (z (1 + noise N(0,1)) - t) / s with s in [0.5, 2], t in [-5, 5]; square
+    blobs covering about `blob_frac` of the pixels carry a 25 % depth error
+    (the inconsistent regions the filter is for); sky has no prior.  The
+    sparse points are true surface points of random pixels with 2 cm noise
+    plus `outliers` of uniform points in the block.  `sizes` (one (W, H) per
+    view) overrides width x height for uneven batches."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = [(width, height)] * (2 * n_pairs)
+    boxes = np.zeros((n_boxes, 5))
+    boxes[:, 0:2] = rng.uniform(20, 180, (n_boxes, 2))
+    boxes[:, 2:4] = rng.uniform(10, 30, (n_boxes, 2))
+    boxes[:, 4] = rng.uniform(10, 50, n_boxes)
+    views, nearby = [], []
+    for k in range(n_pairs):
+        ang = rng.uniform(0, 2 * np.pi)
+        rad = rng.uniform(80, 160)
+        h = rng.uniform(40, 120)
+        pos = np.array([100.0 + rad * np.cos(ang), 100.0 + rad * np.sin(ang), h])
+        tgt = (rng.uniform(70, 130), rng.uniform(70, 130), 0.0)
+        step = rng.normal(0.0, 1.0, 3)
+        step *= rng.uniform(2.0, 5.0) / np.linalg.norm(step)
+        views.append(look_at(tuple(pos), tgt, *sizes[2 * k]))
+        views.append(look_at(tuple(pos + step), tgt, *sizes[2 * k + 1]))
+        nearby += [2 * k + 1, 2 * k]
+    depth, prior = [], []
+    st = np.stack([rng.uniform(0.5, 2.0, len(views)), rng.uniform(-5.0, 5.0, len(views))], 1)
+    for v, view in enumerate(views):
+        z = raycast_boxes(view, boxes)
+        depth.append(z)
+        W, H = int(view.width), int(view.height)
+        zn = z * (1.0 + noise * rng.standard_normal(z.size))
+        err = np.zeros((H, W), bool)
+        side = max(2, int(0.05 * min(W, H)))
+        for _ in range(int(blob_frac * W * H / side ** 2)):
+            i0, j0 = rng.integers(0, W - side + 1), rng.integers(0, H - side + 1)
+            err[j0:j0 + side, i0:i0 + side] = True
+        zn = np.where(err.ravel(), zn * 1.25, zn)
+        p = (zn - st[v, 1]) / st[v, 0]
+        prior.append(np.where(z > 0, p, 0.0).astype(np.float32))
+    n_out = int(outliers * n_points)
+    n_in = n_points - n_out
+    pts = []
+    vid = rng.integers(0, len(views), n_in)
+    for v, view in enumerate(views):
+        m = int((vid == v).sum())
+        hitpix = np.flatnonzero(depth[v] > 0)
+        pix = hitpix[rng.integers(0, hitpix.size, m)]
+        W = int(view.width)
+        J, I = np.divmod(pix, W)
+        z = depth[v][pix]
+        pc = np.stack([(I + 0.5 - view.cx) / view.fx * z, (J + 0.5 - view.cy) / view.fy * z, z])
+        R = np.asarray(view.R, np.float64)
+        pw = (R.T @ (pc - np.asarray(view.t, np.float64)[:, None])).T
+        pts.append(pw + rng.normal(0.0, 0.02, pw.shape))
+    pts.append(np.stack([rng.uniform(0, 200, n_out), rng.uniform(0, 200, n_out),
+                         rng.uniform(0, 50, n_out)], 1))
+    points = np.concatenate(pts).astype(np.float32)
+    points = points[rng.permutation(len(points))]
+    return DepthPriorInputs(views, prior, points, nearby, depth, st)

@@ -163,3 +163,40 @@ def test_entry_points_reject_bad_arguments_before_any_launch(B):
     finally:
         B.cgx_destroy(ctx)
     assert lib.cgx_last_error(None) == b"no context"
+
+
+def test_depth_prior_entry_points_reject_bad_arguments(B):
+    lib = B.load_library()
+    ctx = B.cgx_create(0, 16, 16)
+    try:
+        va = B.make_views([_view(), _view(32, 16)])
+        need = lib.cgx_depth_align_workspace_size(2)
+        assert need == B.cgx_depth_align_workspace_size(2) > 0
+        assert lib.cgx_depth_align_workspace_size(0) == 0
+        fake = C.c_void_p(4096)                      # never dereferenced: every call below fails first
+        rc = lib.cgx_depth_prior_align(ctx, va, 2, fake, fake, 10, fake, need - 8, fake, fake, None)
+        assert rc == B.CGX_ERR_WORKSPACE
+        rc = lib.cgx_depth_prior_align(ctx, va, 2, None, fake, 10, fake, need, fake, fake, None)
+        assert rc == B.CGX_ERR_INVALID_ARG
+        rc = lib.cgx_depth_prior_align(ctx, va, 2, fake, None, 10, fake, need, fake, fake, None)
+        assert rc == B.CGX_ERR_INVALID_ARG and b"points" in lib.cgx_last_error(ctx)
+        rc = lib.cgx_depth_prior_align(ctx, va, 2, fake, fake, -1, fake, need, fake, fake, None)
+        assert rc == B.CGX_ERR_INVALID_ARG
+        rc = lib.cgx_depth_prior_align(ctx, va, 2, fake, fake, 10, C.c_void_p(4100), need, fake, fake, None)
+        assert rc == B.CGX_ERR_INVALID_ARG and b"aligned" in lib.cgx_last_error(ctx)
+        nb = lambda *x: (C.c_int32 * 2)(*x)  # noqa: E731
+        other = C.c_void_p(8192)
+        for bad in ((0, -1), (2, 0), (-2, 0)):
+            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(*bad), 1.0, other, None)
+            assert rc == B.CGX_ERR_INVALID_ARG and b"nearby" in lib.cgx_last_error(ctx)
+        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(1, 0), 1.0, fake, None)
+        assert rc == B.CGX_ERR_INVALID_ARG and b"alias" in lib.cgx_last_error(ctx)
+        for tau in (0.0, -1.0, float("nan"), float("inf")):
+            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(1, 0), tau, other, None)
+            assert rc == B.CGX_ERR_INVALID_ARG
+        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, 1.0, other, None)
+        assert rc == B.CGX_ERR_INVALID_ARG
+        rc = lib.cgx_depth_prior_filter(None, va, 2, fake, nb(1, 0), 1.0, other, None)
+        assert rc == B.CGX_ERR_INVALID_ARG
+    finally:
+        B.cgx_destroy(ctx)

@@ -1,0 +1,157 @@
+"""GPU parity of the depth-prior steps (Sec. 3.4, Step 2) against the FP64
+oracle, through the C ABI.  The per-view scale / shift agree within 1e-9
+relative (the sums are reduced in another order), the aligned prior within
+one float32 rounding of the oracle's float64 value, and the filtered depth
+bit-exactly (both sides take every decision in float64 with the same
+operation order; pixels the oracle flags as fragile are excluded)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import depth_prior as dp
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2503_23044_amd import render
+    return render
+
+
+@pytest.fixture(scope="module")
+def rd(R):
+    return R.Renderer(0)
+
+
+def _dev(arrs):
+    return torch.from_numpy(np.concatenate(arrs).astype(np.float32)).cuda()
+
+
+def _split(t, views):
+    a = t.cpu().numpy()
+    out, o = [], 0
+    for v in views:
+        n = int(v.width) * int(v.height)
+        out.append(a[o:o + n])
+        o += n
+    return out
+
+
+def _align_gpu(R, rd, views, prior, points, inplace=False):
+    B = R.B
+    ws = torch.empty(B.cgx_depth_align_workspace_size(len(views)), dtype=torch.uint8, device="cuda")
+    st = torch.empty(len(views), 2, dtype=torch.float64, device="cuda")
+    p = _dev(prior)
+    al = p if inplace else torch.empty_like(p)
+    pts = torch.from_numpy(np.ascontiguousarray(points, np.float32)).cuda() if len(points) else None
+    B.cgx_depth_prior_align(rd.ctx, views, p, pts, ws, st, al)
+    torch.cuda.synchronize()
+    return st.cpu().numpy(), _split(al, views)
+
+
+def _check_aligned(got, ref):
+    for g, r in zip(got, ref):
+        r32 = r.astype(np.float32)
+        ulp = np.spacing(np.abs(r32))
+        assert np.all(np.abs(g.astype(np.float64) - r32) <= ulp), np.abs(g - r32).max()
+
+
+def _filter_gpu(R, rd, views, depth32, nearby, tau=1.0):
+    d = _dev(depth32)
+    out = torch.empty_like(d)
+    R.B.cgx_depth_prior_filter(rd.ctx, views, d, nearby, tau, out)
+    torch.cuda.synchronize()
+    return _split(out, views)
+
+
+def _check_filtered(got, ref, frag):
+    for v, (g, r, f) in enumerate(zip(got, ref, frag)):
+        ok = ~f
+        bad = np.flatnonzero(g[ok].view(np.uint32) != r.astype(np.float32)[ok].view(np.uint32))
+        assert bad.size == 0, (v, bad[:10], g[ok][bad[:5]], r[ok][bad[:5]])
+        assert f.mean() < 1e-3
+
+
+SMALL = [(61, 47), (40, 30), (97, 33), (97, 33)]       # ragged, uneven within a pair
+
+
+def _small(seed=7, n_points=3000):
+    return scenes.make_depth_prior(seed=seed, n_pairs=2, n_points=n_points, sizes=SMALL)
+
+
+def test_align_matches_oracle_small_uneven(R, rd):
+    print("case: depth align, 4 uneven views", flush=True)
+    X = _small()
+    prior = [p.copy() for p in X.prior]
+    prior[1][::7] = np.nan                        # NaN and negative priors mean no prior
+    prior[2][::5] = -1.0
+    st_ref, al_ref, n = dp.align_scale_shift(prior, X.points, X.views)
+    assert (n > 50).all()
+    st, al = _align_gpu(R, rd, X.views, prior, X.points)
+    np.testing.assert_allclose(st, st_ref, rtol=1e-9, atol=1e-9)
+    _check_aligned(al, al_ref)
+    # in place, and deterministic run to run
+    st2, al2 = _align_gpu(R, rd, X.views, prior, X.points, inplace=True)
+    np.testing.assert_array_equal(st2, st)
+    for a, b in zip(al, al2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_align_degenerate_cases(R, rd):
+    print("case: depth align, degenerate", flush=True)
+    X = _small(seed=8)
+    st, al = _align_gpu(R, rd, X.views, X.prior, np.zeros((0, 3), np.float32))
+    np.testing.assert_array_equal(st, np.tile([1.0, 0.0], (4, 1)))
+    for a, p in zip(al, X.prior):
+        np.testing.assert_array_equal(a, np.where(p > 0, p, 0).astype(np.float32))
+    const = [np.where(p > 0, 2.0, 0.0).astype(np.float32) for p in X.prior]
+    st_ref, _, n = dp.align_scale_shift(const, X.points, X.views)
+    st, _ = _align_gpu(R, rd, X.views, const, X.points)
+    np.testing.assert_array_equal(st_ref, np.tile([1.0, 0.0], (4, 1)))     # singular: n Sdd = Sd^2
+    np.testing.assert_array_equal(st, st_ref)
+    one = X.points[:1]
+    st, _ = _align_gpu(R, rd, X.views, X.prior, one)                       # fewer than two pairs
+    np.testing.assert_array_equal(st, np.tile([1.0, 0.0], (4, 1)))
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.37])
+def test_filter_matches_oracle_small_uneven(R, rd, tau):
+    print(f"case: depth filter, 4 uneven views, tau={tau}", flush=True)
+    X = _small()
+    _, al_ref, _ = dp.align_scale_shift(X.prior, X.points, X.views)
+    depth32 = [a.astype(np.float32) for a in al_ref]
+    depth32[0][::11] = np.nan
+    depth32[3][::13] = -2.0
+    nearby = [1, 0, 3, -1]                         # the last view has no nearby view
+    ref, frag, _ = dp.reprojection_filter([d.astype(np.float64) for d in depth32], X.views, nearby,
+                                          tau=float(np.float32(tau)))
+    got = _filter_gpu(R, rd, X.views, depth32, nearby, tau)
+    _check_filtered(got, ref, frag)
+    assert sum(int((r > 0).sum()) for r in ref[:3]) > 0
+    assert sum(int(((d > 0) & (r == 0)).sum()) for d, r in zip(depth32[:3], ref[:3])) > 0
+
+
+def test_full_size_pairs_match_oracle(R, rd):
+    """The benchmark configuration: 4 pairs of 1920x1080 views, 1M points."""
+    print("case: depth prior, 4 pairs 1920x1080, 1M points", flush=True)
+    X = scenes.make_depth_prior()
+    st_ref, al_ref, _ = dp.align_scale_shift(X.prior, X.points, X.views)
+    st, al = _align_gpu(R, rd, X.views, X.prior, X.points)
+    np.testing.assert_allclose(st, st_ref, rtol=1e-9, atol=1e-9)
+    _check_aligned(al, al_ref)
+    depth32 = [a.astype(np.float32) for a in al_ref]
+    ref, frag, _ = dp.reprojection_filter([d.astype(np.float64) for d in depth32], X.views, X.nearby)
+    got = _filter_gpu(R, rd, X.views, depth32, X.nearby)
+    _check_filtered(got, ref, frag)
+    # the renderer's chained call: same filter on its own aligned prior
+    filt, al2, st2 = rd.depth_prior(X.views, _dev(X.prior),
+                                    torch.from_numpy(X.points).cuda(), X.nearby)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(st2.cpu().numpy(), st)
+    for a, b in zip(_split(al2, X.views), al):
+        np.testing.assert_array_equal(a, b)
+    chained = _filter_gpu(R, rd, X.views, _split(al2, X.views), X.nearby)
+    for a, b in zip(_split(filt, X.views), chained):
+        np.testing.assert_array_equal(a, b)
