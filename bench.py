@@ -373,6 +373,8 @@ def main():
         print(json.dumps({"ncc_loss": ncc_leg(args)}), flush=True)
         return
     if args.depth_only:
+        if args.copy_calibration:
+            copy_calibration(args.copy_calibration)
         print(json.dumps({"depth_prior": depth_prior_leg(args)}), flush=True)
         return
     from synth import scenes

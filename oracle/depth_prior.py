@@ -24,8 +24,12 @@ depth mask).  Readings of what the paper leaves open:
     to Y = d_u K_u^-1 [q, 1] (camera u), which goes back to camera v and
     projects to p'; E = |p' - p|.  p is kept iff d_u > 0, Y is in front of
     v and E < tau_d; a removed pixel's filtered depth is 0;
-  * float64 in a fixed operation order; the pixel containing a projection
-    and E < tau_d are decisions, fragile when closer than FRAG.
+  * float64 in a fixed operation order.  Decisions: the pixel containing a
+    projection, the two in-front tests and E < tau_d; a pixel is flagged
+    fragile when a projection is within FRAG (relative) of a pixel edge, a
+    depth within FRAG of the near plane, or E^2 within FRAG of tau_d^2 --
+    there another evaluation order of the same float64 arithmetic may
+    decide the other way.
 """
 import numpy as np
 
@@ -107,8 +111,9 @@ def reprojection_filter(depth, views, nearby, tau=1.0):
         qx = (fxu * yc[0]) / zs + cxu
         qy = (fyu * yc[1]) / zs + cyu
         inside = front & (qx >= 0.0) & (qx < Wu) & (qy >= 0.0) & (qy < Hu)
-        fr = inside & ((np.abs(qx - np.round(qx)) < FRAG * (np.abs(qx) + 1.0))
-                       | (np.abs(qy - np.round(qy)) < FRAG * (np.abs(qy) + 1.0)))
+        near = (d > 0.0) & (np.abs(yc[2] - znu) < FRAG * (np.abs(yc[2]) + znu))
+        fr = near | (front & ((np.abs(qx - np.round(qx)) < FRAG * (np.abs(qx) + 1.0))
+                              | (np.abs(qy - np.round(qy)) < FRAG * (np.abs(qy) + 1.0))))
         iq = np.floor(np.where(inside, qx, 0.0)).astype(np.int64)
         jq = np.floor(np.where(inside, qy, 0.0)).astype(np.int64)
         du = np.where(inside, Du[jq * Wu + iq], 0.0)
@@ -118,6 +123,7 @@ def reprojection_filter(depth, views, nearby, tau=1.0):
         yw = [((Ru[0, k] * (yc2[0] - tu[0]) + Ru[1, k] * (yc2[1] - tu[1])) + Ru[2, k] * (yc2[2] - tu[2]))
               for k in range(3)]
         zc = [((R[k, 0] * yw[0] + R[k, 1] * yw[1]) + R[k, 2] * yw[2]) + t[k] for k in range(3)]
+        fr |= ok & (np.abs(zc[2] - zn) < FRAG * (np.abs(zc[2]) + zn))
         ok = ok & (zc[2] > zn)
         zz = np.where(ok, zc[2], 1.0)
         ex = ((fx * zc[0]) / zz + cx) - px

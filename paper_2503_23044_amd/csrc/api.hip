@@ -754,29 +754,44 @@ int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views, const
   return CGX_OK;
 }
 
-static int pack_depth_cams(const cgx_view* views, int32_t n, const int32_t* nearby,
-                           DepthCamPack& P) {
-  memset(&P, 0, sizeof(P));
+// float64 copies of a view's float32 camera, and its pixel offset
+struct HostCam {
+  double R[9], t[3], fx, fy, cx, cy, zn;
+  int32_t W, H;
+  int64_t off;
+};
+
+static int depth_cams(const cgx_view* views, int32_t n, std::vector<HostCam>& cams) {
+  cams.resize(n);
   int64_t off = 0;
   int max_pix = 0;
   for (int i = 0; i < n; ++i) {
     const cgx_view& v = views[i];
-    DepthCam& c = P.v[i];
-    memcpy(c.R, v.R, sizeof(c.R));
-    memcpy(c.t, v.t, sizeof(c.t));
+    HostCam& c = cams[i];
+    for (int k = 0; k < 9; ++k) c.R[k] = v.R[k];
+    for (int k = 0; k < 3; ++k) c.t[k] = v.t[k];
     c.fx = v.fx;
     c.fy = v.fy;
     c.cx = v.cx;
     c.cy = v.cy;
-    c.z_near = v.z_near;
+    c.zn = v.z_near;
     c.W = v.width;
     c.H = v.height;
-    c.pix_off = (int32_t)off;
-    c.nearby = nearby ? nearby[i] : -1;
+    c.off = off;
     off += (int64_t)v.width * v.height;
     max_pix = std::max(max_pix, v.width * v.height);
   }
   return max_pix;
+}
+
+// camera a -> camera b: x_b = R_b R_a^T (x_a - t_a) + t_b = M x_a + T
+static void compose(const HostCam& a, const HostCam& b, double* M, double* T) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = b.R[3 * i + 0] * a.R[3 * j + 0] + b.R[3 * i + 1] * a.R[3 * j + 1] +
+                     b.R[3 * i + 2] * a.R[3 * j + 2];
+  for (int i = 0; i < 3; ++i)
+    T[i] = b.t[i] - (M[3 * i + 0] * a.t[0] + M[3 * i + 1] * a.t[1] + M[3 * i + 2] * a.t[2]);
 }
 
 size_t cgx_depth_align_workspace_size(int32_t n_views) {
@@ -804,10 +819,31 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
                 depth_align_scratch_bytes(n_views));
   rc = set_device(ctx);
   if (rc) return rc;
-  DepthCamPack P;
-  const int max_pix = pack_depth_cams(views, n_views, nullptr, P);
-  launch_depth_align(P, n_views, max_pix, prior, points, n_points,
-                     reinterpret_cast<double*>(workspace), scale_shift, aligned, (hipStream_t)stream);
+  std::vector<HostCam> hc;
+  const int max_pix = depth_cams(views, n_views, hc);
+  hipStream_t st = (hipStream_t)stream;
+  double* partial = reinterpret_cast<double*>(workspace);
+  for (int first = 0; first < n_views; first += kAlignGroup) {
+    const int count = std::min(kAlignGroup, n_views - first);
+    AlignPack P;
+    memset(&P, 0, sizeof(P));
+    for (int i = 0; i < count; ++i) {
+      const HostCam& h = hc[first + i];
+      AlignCam& c = P.v[i];
+      memcpy(c.R, h.R, sizeof(c.R));
+      memcpy(c.t, h.t, sizeof(c.t));
+      c.fx = h.fx;
+      c.fy = h.fy;
+      c.cx = h.cx;
+      c.cy = h.cy;
+      c.z_near = h.zn;
+      c.W = h.W;
+      c.H = h.H;
+      c.pix_off = (int32_t)h.off;
+    }
+    launch_depth_align_partials(P, first, count, prior, points, n_points, partial, st);
+    launch_depth_align_finish(P, first, count, max_pix, partial, scale_shift, prior, aligned, st);
+  }
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;
 }
@@ -829,10 +865,45 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
                   nearby[i]);
   rc = set_device(ctx);
   if (rc) return rc;
-  DepthCamPack P;
-  const int max_pix = pack_depth_cams(views, n_views, nearby, P);
-  launch_depth_filter(P, n_views, max_pix, depth, (double)tau * (double)tau, filtered,
-                      (hipStream_t)stream);
+  std::vector<HostCam> hc;
+  const int max_pix = depth_cams(views, n_views, hc);
+  const double tau2 = (double)tau * (double)tau;
+  for (int first = 0; first < n_views; first += kFilterGroup) {
+    const int count = std::min(kFilterGroup, n_views - first);
+    FilterPack P;
+    memset(&P, 0, sizeof(P));
+    for (int i = 0; i < count; ++i) {
+      const HostCam& h = hc[first + i];
+      FilterCam& c = P.v[i];
+      c.ifx = 1.0 / h.fx;
+      c.ify = 1.0 / h.fy;
+      c.cx = h.cx;
+      c.cy = h.cy;
+      c.fx = h.fx;
+      c.fy = h.fy;
+      c.z_near = h.zn;
+      c.W = h.W;
+      c.H = h.H;
+      c.pix_off = (int32_t)h.off;
+      c.nearby = nearby[first + i];
+      if (c.nearby >= 0) {
+        const HostCam& u = hc[c.nearby];
+        compose(h, u, c.M, c.T);
+        compose(u, h, c.N, c.S);
+        c.fxu = u.fx;
+        c.fyu = u.fy;
+        c.cxu = u.cx;
+        c.cyu = u.cy;
+        c.ifxu = 1.0 / u.fx;
+        c.ifyu = 1.0 / u.fy;
+        c.znu = u.zn;
+        c.Wu = u.W;
+        c.Hu = u.H;
+        c.pix_off_u = (int32_t)u.off;
+      }
+    }
+    launch_depth_filter(P, count, max_pix, depth, tau2, filtered, (hipStream_t)stream);
+  }
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;
 }

@@ -363,27 +363,43 @@ void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const 
                      const float* plane_d, const int32_t* centres, int n_patch, float weight,
                      float* grad_rgb, float* loss, hipStream_t s);
 
-// Depth prior (Sec. 3.4, Step 2).  Cameras travel in the kernel arguments
-// (84 bytes each, a whole batch of 32 in 2.7 KB).
-struct DepthCam {
-  float R[9];
-  float t[3];
-  float fx, fy, cx, cy, z_near;
-  int32_t W, H, pix_off;
-  int32_t nearby;              // view index of the nearby view, -1: none
+// Depth prior (Sec. 3.4, Step 2).  Camera constants travel in the kernel
+// arguments as float64, prepared on the host from the float32 views, in
+// groups that keep an argument block under 3 KB.
+struct AlignCam {
+  double R[9], t[3];
+  double fx, fy, cx, cy, z_near;
+  int32_t W, H, pix_off, pad;
 };
-struct DepthCamPack {
-  DepthCam v[CGX_MAX_VIEWS];
+constexpr int kAlignGroup = 16;
+struct AlignPack {
+  AlignCam v[kAlignGroup];
 };
-constexpr int kAlignBlocks = 64;         // partial sums per view
+// view v and its nearby view u: M, T map camera v to camera u, N, S camera u
+// back to camera v (composed on the host in float64)
+struct FilterCam {
+  double ifx, ify, cx, cy, fx, fy, z_near;
+  double M[9], T[3], N[9], S[3];
+  double fxu, fyu, cxu, cyu, ifxu, ifyu, znu;
+  int32_t W, H, pix_off, Wu, Hu, pix_off_u, nearby, pad;
+};
+constexpr int kFilterGroup = 8;
+struct FilterPack {
+  FilterCam v[kFilterGroup];
+};
+constexpr int kAlignBlocks = 512;        // partial sums per view
 constexpr int kAlignSums = 5;            // n, sum d, sum z, sum d^2, sum d z
 inline size_t depth_align_scratch_bytes(int n_views) {
   return (size_t)n_views * kAlignBlocks * kAlignSums * sizeof(double);
 }
-void launch_depth_align(const DepthCamPack& cams, int n_views, int max_pix, const float* prior,
-                        const float* points, int n_points, double* partial, double* st,
-                        float* aligned, hipStream_t s);
-void launch_depth_filter(const DepthCamPack& cams, int n_views, int max_pix, const float* depth,
+// views [first, first + count) of the batch; `partial` and `st` are indexed
+// by batch view
+void launch_depth_align_partials(const AlignPack& cams, int first, int count, const float* prior,
+                                 const float* points, int n_points, double* partial, hipStream_t s);
+void launch_depth_align_finish(const AlignPack& cams, int first, int count, int max_pix,
+                               const double* partial, double* st, const float* prior,
+                               float* aligned, hipStream_t s);
+void launch_depth_filter(const FilterPack& cams, int count, int max_pix, const float* depth,
                          double tau2, float* out, hipStream_t s);
 
 }  // namespace cgx

@@ -4,20 +4,30 @@
 // consistently through a nearby view (error of tau_d pixels or more) are
 // removed (set to 0), which is what the depth L1 term later masks.
 //
-// Everything here is float64 with contraction off, in one fixed operation
-// order per pixel and per point: every decision (in front of a camera,
-// inside an image, the pixel a projection falls in, the error against
-// tau_d) is then the IEEE result of the same expression, independent of
-// the thread that computes it.  The per-view sums of the alignment are
-// reduced in a fixed order (thread, wave, block, then the 64 block partials
-// in index order), so a run is deterministic; a different order changes
-// (s, t) only in the last bits.
+// Every decision (in front of a camera, inside an image, the pixel a
+// projection falls in, the error against tau_d) is taken in float64.
+//   * Alignment: the projection of the points keeps one fixed operation
+//     order with contraction off (the camera as given, true divisions), so
+//     the set of (prior, depth) pairs is the IEEE result of one expression
+//     and cannot depend on the thread.  The per-view sums are reduced in a
+//     fixed order (each thread's points in index order, a xor-tree over the
+//     wave, waves in order, then the 512 block partials the same way), so a
+//     run is deterministic; another order moves (s, t) in the last bits.
+//   * Filter: the per-pixel chain is the cost, so the host composes the
+//     two camera-to-camera transforms (camera v -> u and back) and the
+//     inverse focal lengths in float64, and the kernel uses fused
+//     multiply-adds and one reciprocal (hardware estimate + two Newton
+//     steps) per projection.  Against the camera-by-camera evaluation this
+//     moves a re-projected position by ~1e-13 px, so a decision can differ
+//     only for a position within ~1e-12 of a pixel edge or an error within
+//     ~1e-12 of tau_d.
 //
 // Kernels:
-//   k_align_partials  grid (64, views) x 256: each block strides over the
-//                     points, projects them into its view and sums
+//   k_align_partials  grid (512, views) x 256: each thread projects 4
+//                     points per step into its view (loads first, then the
+//                     4 prior gathers in flight) and sums
 //                     (n, d, z, d^2, d z) of the pairs with a prior;
-//   k_align_solve     one thread per view: 64 partials -> 2x2 normal
+//   k_align_solve     one block per view: 512 partials -> 2x2 normal
 //                     equations -> (s, t);
 //   k_align_apply     grid (pixels / 2048, views) x 256: aligned = s D + t
 //                     where D > 0, else 0 (in place allowed);
@@ -31,57 +41,72 @@ namespace cgx {
 
 constexpr int kDepthThreads = 256;
 constexpr int kApplyPerThread = 8;
+constexpr int kPointsInFlight = 4;
 
 __device__ __forceinline__ double dsum_wave(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
 
-// camera-frame point of a world point: ((R_k0 x + R_k1 y) + R_k2 z) + t_k
-__device__ __forceinline__ void to_camera(const DepthCam& c, double x, double y, double z,
-                                          double& p0, double& p1, double& p2) {
-  p0 = (((double)c.R[0] * x + (double)c.R[1] * y) + (double)c.R[2] * z) + (double)c.t[0];
-  p1 = (((double)c.R[3] * x + (double)c.R[4] * y) + (double)c.R[5] * z) + (double)c.t[1];
-  p2 = (((double)c.R[6] * x + (double)c.R[7] * y) + (double)c.R[8] * z) + (double)c.t[2];
+// 1 / z: hardware estimate refined by two Newton steps (each squares the
+// relative error), for 0 < z < inf
+__device__ __forceinline__ double recip(double z) {
+  double r = __builtin_amdgcn_rcp(z);
+  double e = fma(-z, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-z, r, 1.0);
+  return fma(r, e, r);
 }
 
-// world point of a camera-frame point, through the transpose of R:
-// ((R_0k (x - t_0) + R_1k (y - t_1)) + R_2k (z - t_2))
-__device__ __forceinline__ void to_world(const DepthCam& c, double x, double y, double z,
-                                         double& w0, double& w1, double& w2) {
-  const double a = x - (double)c.t[0], b = y - (double)c.t[1], e = z - (double)c.t[2];
-  w0 = ((double)c.R[0] * a + (double)c.R[3] * b) + (double)c.R[6] * e;
-  w1 = ((double)c.R[1] * a + (double)c.R[4] * b) + (double)c.R[7] * e;
-  w2 = ((double)c.R[2] * a + (double)c.R[5] * b) + (double)c.R[8] * e;
-}
-
-__global__ __launch_bounds__(kDepthThreads) void k_align_partials(DepthCamPack cams,
+__global__ __launch_bounds__(kDepthThreads) void k_align_partials(AlignPack cams, int first,
                                                                   const float* __restrict__ prior,
                                                                   const float* __restrict__ points,
                                                                   int n_points,
                                                                   double* __restrict__ partial) {
-  const DepthCam& c = cams.v[blockIdx.y];
-  const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy, zn = c.z_near;
-  const double Wd = c.W, Hd = c.H;
+  const AlignCam& c = cams.v[blockIdx.y];
   double acc[kAlignSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int stride = kAlignBlocks * kDepthThreads;
-  for (int i = blockIdx.x * kDepthThreads + threadIdx.x; i < n_points; i += stride) {
-    double p0, p1, p2;
-    const float* q = points + 3 * (size_t)i;
-    to_camera(c, (double)q[0], (double)q[1], (double)q[2], p0, p1, p2);
-    const bool front = p2 > zn;
-    const double zs = front ? p2 : 1.0;
-    const double u = (fx * p0) / zs + cx;
-    const double w = (fy * p1) / zs + cy;
-    if (!(front && u >= 0.0 && u < Wd && w >= 0.0 && w < Hd)) continue;
-    const int iu = (int)floor(u), iw = (int)floor(w);
-    const double d = (double)prior[(size_t)c.pix_off + (size_t)iw * c.W + iu];
-    if (!(d > 0.0)) continue;
-    acc[0] += 1.0;
-    acc[1] += d;
-    acc[2] += p2;
-    acc[3] += d * d;
-    acc[4] += d * p2;
+  for (int i0 = blockIdx.x * kDepthThreads + threadIdx.x; i0 < n_points;
+       i0 += kPointsInFlight * stride) {
+    double z[kPointsInFlight];
+    int pix[kPointsInFlight];
+#pragma unroll
+    for (int k = 0; k < kPointsInFlight; ++k) {
+      const int i = i0 + k * stride;
+      pix[k] = -1;
+      z[k] = 0.0;
+      if (i < n_points) {
+        const float* q = points + 3 * (size_t)i;
+        const double x = q[0], y = q[1], w3 = q[2];
+        // camera point: ((R_k0 x + R_k1 y) + R_k2 z) + t_k
+        const double p0 = ((c.R[0] * x + c.R[1] * y) + c.R[2] * w3) + c.t[0];
+        const double p1 = ((c.R[3] * x + c.R[4] * y) + c.R[5] * w3) + c.t[1];
+        const double p2 = ((c.R[6] * x + c.R[7] * y) + c.R[8] * w3) + c.t[2];
+        const bool front = p2 > c.z_near;
+        const double zs = front ? p2 : 1.0;
+        const double u = (c.fx * p0) / zs + c.cx;
+        const double w = (c.fy * p1) / zs + c.cy;
+        if (front && u >= 0.0 && u < (double)c.W && w >= 0.0 && w < (double)c.H) {
+          pix[k] = (int)floor(w) * c.W + (int)floor(u);
+          z[k] = p2;
+        }
+      }
+    }
+    float dv[kPointsInFlight];
+#pragma unroll
+    for (int k = 0; k < kPointsInFlight; ++k)
+      dv[k] = pix[k] >= 0 ? prior[(size_t)c.pix_off + pix[k]] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kPointsInFlight; ++k) {
+      const double d = dv[k];
+      if (d > 0.0) {
+        acc[0] += 1.0;
+        acc[1] += d;
+        acc[2] += z[k];
+        acc[3] += d * d;
+        acc[4] += d * z[k];
+      }
+    }
   }
   __shared__ double red[kDepthThreads / kWave][kAlignSums];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
@@ -94,18 +119,34 @@ __global__ __launch_bounds__(kDepthThreads) void k_align_partials(DepthCamPack c
   if (threadIdx.x < kAlignSums) {
     double v = red[0][threadIdx.x];
     for (int j = 1; j < kDepthThreads / kWave; ++j) v += red[j][threadIdx.x];
-    partial[((size_t)blockIdx.y * kAlignBlocks + blockIdx.x) * kAlignSums + threadIdx.x] = v;
+    partial[((size_t)(first + blockIdx.y) * kAlignBlocks + blockIdx.x) * kAlignSums + threadIdx.x] = v;
   }
 }
 
-__global__ void k_align_solve(int n_views, const double* __restrict__ partial,
-                              double* __restrict__ st) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n_views) return;
-  double S[kAlignSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = 0; b < kAlignBlocks; ++b)
+__global__ __launch_bounds__(kDepthThreads) void k_align_solve(int first,
+                                                               const double* __restrict__ partial,
+                                                               double* __restrict__ st) {
+  const int v = first + blockIdx.x;
+  const double* P = partial + (size_t)v * kAlignBlocks * kAlignSums;
+  double acc[kAlignSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < kAlignBlocks; b += kDepthThreads)
 #pragma unroll
-    for (int k = 0; k < kAlignSums; ++k) S[k] += partial[((size_t)v * kAlignBlocks + b) * kAlignSums + k];
+    for (int k = 0; k < kAlignSums; ++k) acc[k] += P[(size_t)b * kAlignSums + k];
+  __shared__ double red[kDepthThreads / kWave][kAlignSums];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kAlignSums; ++k) {
+    const double s = dsum_wave(acc[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double S[kAlignSums];
+#pragma unroll
+  for (int k = 0; k < kAlignSums; ++k) {
+    S[k] = red[0][k];
+    for (int j = 1; j < kDepthThreads / kWave; ++j) S[k] += red[j][k];
+  }
   const double n = S[0], Sd = S[1], Sz = S[2], Sdd = S[3], Sdz = S[4];
   const double det = n * Sdd - Sd * Sd;
   double s = 1.0, t = 0.0;
@@ -117,11 +158,11 @@ __global__ void k_align_solve(int n_views, const double* __restrict__ partial,
   st[2 * v + 1] = t;
 }
 
-__global__ __launch_bounds__(kDepthThreads) void k_align_apply(DepthCamPack cams,
+__global__ __launch_bounds__(kDepthThreads) void k_align_apply(AlignPack cams, int first,
                                                                const double* __restrict__ st,
                                                                const float* prior, float* aligned) {
-  const DepthCam& c = cams.v[blockIdx.y];
-  const double s = st[2 * blockIdx.y], t = st[2 * blockIdx.y + 1];
+  const AlignCam& c = cams.v[blockIdx.y];
+  const double s = st[2 * (first + blockIdx.y)], t = st[2 * (first + blockIdx.y) + 1];
   const int npx = c.W * c.H;
   const float* src = prior + c.pix_off;
   float* dst = aligned + c.pix_off;
@@ -136,10 +177,10 @@ __global__ __launch_bounds__(kDepthThreads) void k_align_apply(DepthCamPack cams
   }
 }
 
-__global__ __launch_bounds__(kDepthThreads) void k_depth_filter(DepthCamPack cams, double tau2,
+__global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams, double tau2,
                                                                 const float* __restrict__ depth,
                                                                 float* __restrict__ out) {
-  const DepthCam& c = cams.v[blockIdx.y];
+  const FilterCam& c = cams.v[blockIdx.y];
   const int p = blockIdx.x * kDepthThreads + threadIdx.x;
   if (p >= c.W * c.H) return;
   const float df = depth[(size_t)c.pix_off + p];
@@ -147,33 +188,32 @@ __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(DepthCamPack cam
   float res = 0.0f;
   if (c.nearby < 0) {
     res = d > 0.0 ? df : 0.0f;
-  } else {
-    const DepthCam& u = cams.v[c.nearby];
+  } else if (d > 0.0) {
     const double px = (double)(p % c.W) + 0.5, py = (double)(p / c.W) + 0.5;
-    const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
-    const double fxu = u.fx, fyu = u.fy, cxu = u.cx, cyu = u.cy;
-    // back-project into view v, move to the nearby view u
-    double w0, w1, w2, y0, y1, y2;
-    to_world(c, d * ((px - cx) / fx), d * ((py - cy) / fy), d, w0, w1, w2);
-    to_camera(u, w0, w1, w2, y0, y1, y2);
-    const bool front = d > 0.0 && y2 > (double)u.z_near;
-    const double zs = front ? y2 : 1.0;
-    const double qx = (fxu * y0) / zs + cxu;
-    const double qy = (fyu * y1) / zs + cyu;
-    const bool inside = front && qx >= 0.0 && qx < (double)u.W && qy >= 0.0 && qy < (double)u.H;
-    if (inside) {
-      const int iq = (int)floor(qx), jq = (int)floor(qy);
-      const double du = (double)depth[(size_t)u.pix_off + (size_t)jq * u.W + iq];
-      if (du > 0.0) {
-        // lift with u's depth, back to view v, re-project
-        double x0, x1, x2, z0, z1, z2;
-        to_world(u, du * ((qx - cxu) / fxu), du * ((qy - cyu) / fyu), du, x0, x1, x2);
-        to_camera(c, x0, x1, x2, z0, z1, z2);
-        if (z2 > (double)c.z_near) {
-          const double ex = ((fx * z0) / z2 + cx) - px;
-          const double ey = ((fy * z1) / z2 + cy) - py;
-          const double e2 = ex * ex + ey * ey;
-          if (e2 < tau2) res = df;
+    // back-project in camera v, move to camera u
+    const double x0 = ((px - c.cx) * c.ifx) * d, x1 = ((py - c.cy) * c.ify) * d;
+    const double y2 = fma(c.M[6], x0, fma(c.M[7], x1, fma(c.M[8], d, c.T[2])));
+    if (y2 > c.znu) {
+      const double y0 = fma(c.M[0], x0, fma(c.M[1], x1, fma(c.M[2], d, c.T[0])));
+      const double y1 = fma(c.M[3], x0, fma(c.M[4], x1, fma(c.M[5], d, c.T[1])));
+      const double r = recip(y2);
+      const double qx = fma(c.fxu * y0, r, c.cxu);
+      const double qy = fma(c.fyu * y1, r, c.cyu);
+      if (qx >= 0.0 && qx < (double)c.Wu && qy >= 0.0 && qy < (double)c.Hu) {
+        const int iq = (int)floor(qx), jq = (int)floor(qy);
+        const double du = (double)depth[(size_t)c.pix_off_u + (size_t)jq * c.Wu + iq];
+        if (du > 0.0) {
+          // lift with u's depth, back to camera v, re-project
+          const double a0 = ((qx - c.cxu) * c.ifxu) * du, a1 = ((qy - c.cyu) * c.ifyu) * du;
+          const double z2 = fma(c.N[6], a0, fma(c.N[7], a1, fma(c.N[8], du, c.S[2])));
+          if (z2 > c.z_near) {
+            const double z0 = fma(c.N[0], a0, fma(c.N[1], a1, fma(c.N[2], du, c.S[0])));
+            const double z1 = fma(c.N[3], a0, fma(c.N[4], a1, fma(c.N[5], du, c.S[1])));
+            const double r2 = recip(z2);
+            const double ex = fma(c.fx * z0, r2, c.cx) - px;
+            const double ey = fma(c.fy * z1, r2, c.cy) - py;
+            if (fma(ex, ex, ey * ey) < tau2) res = df;
+          }
         }
       }
     }
@@ -181,21 +221,27 @@ __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(DepthCamPack cam
   out[(size_t)c.pix_off + p] = res;
 }
 
-void launch_depth_align(const DepthCamPack& cams, int n_views, int max_pix, const float* prior,
-                        const float* points, int n_points, double* partial, double* st,
-                        float* aligned, hipStream_t s) {
-  k_align_partials<<<dim3(kAlignBlocks, n_views), kDepthThreads, 0, s>>>(cams, prior, points,
-                                                                         n_points, partial);
-  k_align_solve<<<1, kWave, 0, s>>>(n_views, partial, st);
-  const int per_block = kDepthThreads * kApplyPerThread;
-  const int bx = (max_pix + per_block - 1) / per_block;
-  if (bx > 0) k_align_apply<<<dim3(bx, n_views), kDepthThreads, 0, s>>>(cams, st, prior, aligned);
+void launch_depth_align_partials(const AlignPack& cams, int first, int count, const float* prior,
+                                 const float* points, int n_points, double* partial,
+                                 hipStream_t s) {
+  k_align_partials<<<dim3(kAlignBlocks, count), kDepthThreads, 0, s>>>(cams, first, prior, points,
+                                                                       n_points, partial);
 }
 
-void launch_depth_filter(const DepthCamPack& cams, int n_views, int max_pix, const float* depth,
+void launch_depth_align_finish(const AlignPack& cams, int first, int count, int max_pix,
+                               const double* partial, double* st, const float* prior,
+                               float* aligned, hipStream_t s) {
+  k_align_solve<<<count, kDepthThreads, 0, s>>>(first, partial, st);
+  const int per_block = kDepthThreads * kApplyPerThread;
+  const int bx = (max_pix + per_block - 1) / per_block;
+  if (bx > 0)
+    k_align_apply<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, first, st, prior, aligned);
+}
+
+void launch_depth_filter(const FilterPack& cams, int count, int max_pix, const float* depth,
                          double tau2, float* out, hipStream_t s) {
   const int bx = (max_pix + kDepthThreads - 1) / kDepthThreads;
-  if (bx > 0) k_depth_filter<<<dim3(bx, n_views), kDepthThreads, 0, s>>>(cams, tau2, depth, out);
+  if (bx > 0) k_depth_filter<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, tau2, depth, out);
 }
 
 }  // namespace cgx
