@@ -322,7 +322,9 @@ def depth_prior_leg(args):
     scale / shift of a pseudo depth against 1M sparse points
     (cgx_depth_prior_align) and the multi-view filter with tau_d = 1
     (cgx_depth_prior_filter) over 4 pairs of nearby 1920x1080 views, each
-    timed with HIP events over 20 launches on the library's stream."""
+    timed with HIP events over 20 launches on the library's stream: the
+    step as the renderer runs it (the filter aligns the raw prior on the
+    fly), and, for reference, with the aligned image stored and re-read."""
     import torch
 
     import numpy as np
@@ -350,16 +352,24 @@ def depth_prior_leg(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # the step as the renderer runs it: (s, t) only, then the filter aligning on the fly
     ms_a = timed(lambda: B.cgx_depth_prior_align(rd.ctx, X.views, prior, points, rd.depth_ws, st,
-                                                 aligned))
-    ms_f = timed(lambda: B.cgx_depth_prior_filter(rd.ctx, X.views, aligned, X.nearby, 1.0, filtered))
+                                                 None))
+    ms_f = timed(lambda: B.cgx_depth_prior_filter(rd.ctx, X.views, prior, X.nearby, 1.0, filtered,
+                                                  scale_shift=st))
+    # with the aligned image written and filtered from memory
+    ms_a2 = timed(lambda: B.cgx_depth_prior_align(rd.ctx, X.views, prior, points, rd.depth_ws, st,
+                                                  aligned))
+    ms_f2 = timed(lambda: B.cgx_depth_prior_filter(rd.ctx, X.views, aligned, X.nearby, 1.0, filtered))
     px = sum(int(v.width) * int(v.height) for v in X.views)
     kept = float((filtered > 0).sum().item()) / max(float((aligned > 0).sum().item()), 1.0)
-    log(f"[bench] depth prior: align {ms_a * 1e3:.1f} us, filter {ms_f * 1e3:.1f} us, {px} px, "
-        f"kept {kept:.3f}")
+    log(f"[bench] depth prior: align {ms_a * 1e3:.1f} us, filter (aligning on the fly) "
+        f"{ms_f * 1e3:.1f} us; with the aligned image stored {ms_a2 * 1e3:.1f} + {ms_f2 * 1e3:.1f} us; "
+        f"{px} px, kept {kept:.3f}")
     return {"workload": "4 pairs of nearby 1920x1080 views over a box city, 1M sparse points",
             "pixels": px, "points": int(len(X.points)), "ms_align": round(ms_a, 4),
             "ms_filter": round(ms_f, 4), "ms": round(ms_a + ms_f, 4),
+            "ms_with_aligned_image": round(ms_a2 + ms_f2, 4),
             "Mpixels_per_s": round(px / ((ms_a + ms_f) * 1e-3) / 1e6, 1), "kept": round(kept, 4)}
 
 

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 3
+#define CGX_ABI_VERSION 4
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -303,7 +303,8 @@ int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
  * two pairs or a singular system (s, t) = (1, 0).  Outputs:
  * scale_shift[2 v + {0, 1}] = (s, t) (device float64) and aligned = s D + t
  * where D > 0, else 0 (device float32, packed layout; may be the same
- * buffer as prior).  `workspace` (device, 8-byte aligned) holds the partial
+ * buffer as prior, or NULL to skip writing it, e.g. when the filter below
+ * aligns on the fly).  `workspace` (device, 8-byte aligned) holds the partial
  * sums: at least cgx_depth_align_workspace_size(n_views) bytes, contents
  * not needed between calls.  Errors: CGX_ERR_INVALID_ARG for a bad view or
  * a NULL pointer, CGX_ERR_WORKSPACE for a small workspace; nothing is
@@ -324,12 +325,19 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
  * camera v; the pixel is kept iff d_u > 0, that point is in front of v and
  * its projection p' satisfies |p' - p| < tau (pixels).  Cameras invert as
  * X = R^T (x - t).  filtered = d where kept, else 0 (device float32,
- * packed layout; must not alias depth).  Float64, contraction off, one
- * fixed operation order.  Errors: CGX_ERR_INVALID_ARG for a bad view, a
- * nearby entry that is not -1 or another view, tau <= 0 or aliasing. */
+ * packed layout; must not alias depth).  With `scale_shift` NULL, `depth`
+ * holds the depths (e.g. the aligned output above).  With scale_shift the
+ * (s, t) of cgx_depth_prior_align (device float64, 2 per view), `depth`
+ * holds the raw prior and every value read is aligned first, to the same
+ * float32 value the align call would store, so the result is bit-identical
+ * to filtering the stored aligned image.  Decisions are float64; the
+ * camera-to-camera transforms are composed on the host, which moves a
+ * re-projected position by ~1e-13 px against a camera-by-camera
+ * evaluation.  Errors: CGX_ERR_INVALID_ARG for a bad view, a nearby entry
+ * that is not -1 or another view, tau <= 0, misalignment or aliasing. */
 int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
-                               const float* depth, const int32_t* nearby, float tau,
-                               float* filtered, void* stream);
+                               const float* depth, const double* scale_shift,
+                               const int32_t* nearby, float tau, float* filtered, void* stream);
 
 /* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
  * images do not depend on the tile shape, only the speed does).  For each

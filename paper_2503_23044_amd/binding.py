@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 3
+CGX_ABI_VERSION = 4
 OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
@@ -126,7 +126,7 @@ def load_library(path: str = LIB_PATH):
         "cgx_depth_align_workspace_size": (C.c_size_t, [C.c_int32]),
         "cgx_depth_prior_align": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P, C.c_int32, P,
                                               C.c_size_t, P, P, P]),
-        "cgx_depth_prior_filter": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P,
+        "cgx_depth_prior_filter": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
                                                C.POINTER(C.c_int32), C.c_float, P, P]),
         "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
@@ -332,14 +332,16 @@ def cgx_depth_prior_align(ctx, views, prior, points, ws, scale_shift, aligned):
     _check(ctx, rc, "cgx_depth_prior_align")
 
 
-def cgx_depth_prior_filter(ctx, views, depth, nearby, tau, filtered):
+def cgx_depth_prior_filter(ctx, views, depth, nearby, tau, filtered, scale_shift=None):
     """Multi-view consistency filter of the packed float32 depth maps;
-    nearby is a host sequence (one view index or -1 per view)."""
+    nearby is a host sequence (one view index or -1 per view).  With
+    scale_shift (float64 (B, 2) device), depth is the raw prior, aligned on
+    the fly."""
     lib = load_library()
     va = make_views(views)
     nb = (C.c_int32 * len(views))(*[int(x) for x in nearby])
-    rc = lib.cgx_depth_prior_filter(ctx, va, len(views), _ptr(depth), nb, float(tau), _ptr(filtered),
-                                    _stream())
+    rc = lib.cgx_depth_prior_filter(ctx, va, len(views), _ptr(depth), _ptr(scale_shift), nb, float(tau),
+                                    _ptr(filtered), _stream())
     _check(ctx, rc, "cgx_depth_prior_filter")
 
 

@@ -807,8 +807,8 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
   if (rc) return rc;
   if (n_points < 0 || n_points > INT32_MAX / 3)
     return fail(ctx, CGX_ERR_INVALID_ARG, "n_points %d outside 0..%d", n_points, INT32_MAX / 3);
-  if (!prior || !scale_shift || !aligned || !workspace)
-    return fail(ctx, CGX_ERR_INVALID_ARG, "prior, workspace, scale_shift and aligned are required");
+  if (!prior || !scale_shift || !workspace)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "prior, workspace and scale_shift are required");
   if (n_points > 0 && !points) return fail(ctx, CGX_ERR_INVALID_ARG, "points is NULL");
   if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0)
     return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
@@ -849,8 +849,8 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
 }
 
 int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
-                               const float* depth, const int32_t* nearby, float tau,
-                               float* filtered, void* stream) {
+                               const float* depth, const double* scale_shift,
+                               const int32_t* nearby, float tau, float* filtered, void* stream) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   int32_t rc = check_views(ctx, views, n_views);
   if (rc) return rc;
@@ -858,6 +858,8 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
     return fail(ctx, CGX_ERR_INVALID_ARG, "depth, nearby and filtered are required");
   if (depth == filtered)
     return fail(ctx, CGX_ERR_INVALID_ARG, "filtered must not alias depth (nearby views are read)");
+  if ((reinterpret_cast<uintptr_t>(scale_shift) & 7) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "scale_shift must be 8-byte aligned");
   if (!(tau > 0.f) || !std::isfinite(tau)) return fail(ctx, CGX_ERR_INVALID_ARG, "tau must be > 0");
   for (int i = 0; i < n_views; ++i)
     if (nearby[i] < -1 || nearby[i] >= n_views || nearby[i] == i)
@@ -884,6 +886,7 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
       c.z_near = h.zn;
       c.W = h.W;
       c.H = h.H;
+      c.iW = 1.0 / h.W;
       c.pix_off = (int32_t)h.off;
       c.nearby = nearby[first + i];
       if (c.nearby >= 0) {
@@ -902,7 +905,8 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
         c.pix_off_u = (int32_t)u.off;
       }
     }
-    launch_depth_filter(P, count, max_pix, depth, tau2, filtered, (hipStream_t)stream);
+    launch_depth_filter(P, first, count, max_pix, depth, scale_shift, tau2, filtered,
+                        (hipStream_t)stream);
   }
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;

@@ -381,6 +381,7 @@ struct FilterCam {
   double ifx, ify, cx, cy, fx, fy, z_near;
   double M[9], T[3], N[9], S[3];
   double fxu, fyu, cxu, cyu, ifxu, ifyu, znu;
+  double iW;                   // 1 / W
   int32_t W, H, pix_off, Wu, Hu, pix_off_u, nearby, pad;
 };
 constexpr int kFilterGroup = 8;
@@ -399,7 +400,10 @@ void launch_depth_align_partials(const AlignPack& cams, int first, int count, co
 void launch_depth_align_finish(const AlignPack& cams, int first, int count, int max_pix,
                                const double* partial, double* st, const float* prior,
                                float* aligned, hipStream_t s);
-void launch_depth_filter(const FilterPack& cams, int count, int max_pix, const float* depth,
-                         double tau2, float* out, hipStream_t s);
+// st (device, 2 per batch view) non-null: `depth` is the raw prior, aligned
+// on the fly
+void launch_depth_filter(const FilterPack& cams, int first, int count, int max_pix,
+                         const float* depth, const double* st, double tau2, float* out,
+                         hipStream_t s);
 
 }  // namespace cgx

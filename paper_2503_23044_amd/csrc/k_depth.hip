@@ -23,7 +23,7 @@
 //     ~1e-12 of tau_d.
 //
 // Kernels:
-//   k_align_partials  grid (512, views) x 256: each thread projects 4
+//   k_align_partials  grid 512 x views x 256 (view = block % views): each thread projects 4
 //                     points per step into its view (loads first, then the
 //                     4 prior gathers in flight) and sums
 //                     (n, d, z, d^2, d z) of the pairs with a prior;
@@ -32,7 +32,11 @@
 //   k_align_apply     grid (pixels / 2048, views) x 256: aligned = s D + t
 //                     where D > 0, else 0 (in place allowed);
 //   k_depth_filter    grid (pixels / 256, views) x 256: one pixel per
-//                     thread, a gather from the nearby view's depth.
+//                     thread, a gather from the nearby view's depth; given
+//                     the (s, t) of every view it reads the raw prior and
+//                     aligns both values on the fly (the same float32 values
+//                     k_align_apply would store), so the aligned image need
+//                     not be written and read back.
 #include "cgx_common.h"
 
 #pragma clang fp contract(off)
@@ -58,15 +62,27 @@ __device__ __forceinline__ double recip(double z) {
   return fma(r, e, r);
 }
 
+// the aligned depth s D + t of a stored value D (D <= 0 or NaN: 0), rounded
+// to float32 exactly as k_align_apply stores it
+__device__ __forceinline__ float aligned_value(float D, double s, double t) {
+  const double Dd = (double)D;
+  return Dd > 0.0 ? (float)(s * Dd + t) : 0.0f;
+}
+
 __global__ __launch_bounds__(kDepthThreads) void k_align_partials(AlignPack cams, int first,
+                                                                  int count,
                                                                   const float* __restrict__ prior,
                                                                   const float* __restrict__ points,
                                                                   int n_points,
                                                                   double* __restrict__ partial) {
-  const AlignCam& c = cams.v[blockIdx.y];
+  // workgroups go to the 8 XCDs round-robin by linear id, so taking the
+  // view as id % count keeps each view's blocks on the same XCD(s) and its
+  // prior image in that XCD's L2
+  const int view = blockIdx.x % count, blk = blockIdx.x / count;
+  const AlignCam& c = cams.v[view];
   double acc[kAlignSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int stride = kAlignBlocks * kDepthThreads;
-  for (int i0 = blockIdx.x * kDepthThreads + threadIdx.x; i0 < n_points;
+  for (int i0 = blk * kDepthThreads + threadIdx.x; i0 < n_points;
        i0 += kPointsInFlight * stride) {
     double z[kPointsInFlight];
     int pix[kPointsInFlight];
@@ -119,7 +135,7 @@ __global__ __launch_bounds__(kDepthThreads) void k_align_partials(AlignPack cams
   if (threadIdx.x < kAlignSums) {
     double v = red[0][threadIdx.x];
     for (int j = 1; j < kDepthThreads / kWave; ++j) v += red[j][threadIdx.x];
-    partial[((size_t)(first + blockIdx.y) * kAlignBlocks + blockIdx.x) * kAlignSums + threadIdx.x] = v;
+    partial[((size_t)(first + view) * kAlignBlocks + blk) * kAlignSums + threadIdx.x] = v;
   }
 }
 
@@ -171,25 +187,32 @@ __global__ __launch_bounds__(kDepthThreads) void k_align_apply(AlignPack cams, i
   for (int k = 0; k < kApplyPerThread; ++k) {
     const int p = base + k * kDepthThreads;
     if (p < npx) {
-      const double D = (double)src[p];
-      dst[p] = D > 0.0 ? (float)(s * D + t) : 0.0f;
+      dst[p] = aligned_value(src[p], s, t);
     }
   }
 }
 
-__global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams, double tau2,
+// st == nullptr: `depth` holds the depths; otherwise it holds the raw
+// prior and each value read is aligned with its view's (s, t) first
+__global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams, int first,
+                                                                double tau2,
                                                                 const float* __restrict__ depth,
+                                                                const double* __restrict__ st,
                                                                 float* __restrict__ out) {
   const FilterCam& c = cams.v[blockIdx.y];
   const int p = blockIdx.x * kDepthThreads + threadIdx.x;
   if (p >= c.W * c.H) return;
-  const float df = depth[(size_t)c.pix_off + p];
+  float df = depth[(size_t)c.pix_off + p];
+  if (st) df = aligned_value(df, st[2 * (first + blockIdx.y)], st[2 * (first + blockIdx.y) + 1]);
   const double d = (double)df;
   float res = 0.0f;
   if (c.nearby < 0) {
     res = d > 0.0 ? df : 0.0f;
   } else if (d > 0.0) {
-    const double px = (double)(p % c.W) + 0.5, py = (double)(p / c.W) + 0.5;
+    // row j = floor((p + 1/2) / W): the quotient stays >= 1/(2W) away from
+    // an integer, far above the rounding of one float64 multiply
+    const int j = (int)floor(((double)p + 0.5) * c.iW);
+    const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
     // back-project in camera v, move to camera u
     const double x0 = ((px - c.cx) * c.ifx) * d, x1 = ((py - c.cy) * c.ify) * d;
     const double y2 = fma(c.M[6], x0, fma(c.M[7], x1, fma(c.M[8], d, c.T[2])));
@@ -201,7 +224,9 @@ __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams,
       const double qy = fma(c.fyu * y1, r, c.cyu);
       if (qx >= 0.0 && qx < (double)c.Wu && qy >= 0.0 && qy < (double)c.Hu) {
         const int iq = (int)floor(qx), jq = (int)floor(qy);
-        const double du = (double)depth[(size_t)c.pix_off_u + (size_t)jq * c.Wu + iq];
+        float duf = depth[(size_t)c.pix_off_u + (size_t)jq * c.Wu + iq];
+        if (st) duf = aligned_value(duf, st[2 * c.nearby], st[2 * c.nearby + 1]);
+        const double du = (double)duf;
         if (du > 0.0) {
           // lift with u's depth, back to camera v, re-project
           const double a0 = ((qx - c.cxu) * c.ifxu) * du, a1 = ((qy - c.cyu) * c.ifyu) * du;
@@ -224,8 +249,8 @@ __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams,
 void launch_depth_align_partials(const AlignPack& cams, int first, int count, const float* prior,
                                  const float* points, int n_points, double* partial,
                                  hipStream_t s) {
-  k_align_partials<<<dim3(kAlignBlocks, count), kDepthThreads, 0, s>>>(cams, first, prior, points,
-                                                                       n_points, partial);
+  k_align_partials<<<kAlignBlocks * count, kDepthThreads, 0, s>>>(cams, first, count, prior,
+                                                                   points, n_points, partial);
 }
 
 void launch_depth_align_finish(const AlignPack& cams, int first, int count, int max_pix,
@@ -234,14 +259,16 @@ void launch_depth_align_finish(const AlignPack& cams, int first, int count, int 
   k_align_solve<<<count, kDepthThreads, 0, s>>>(first, partial, st);
   const int per_block = kDepthThreads * kApplyPerThread;
   const int bx = (max_pix + per_block - 1) / per_block;
-  if (bx > 0)
+  if (bx > 0 && aligned)
     k_align_apply<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, first, st, prior, aligned);
 }
 
-void launch_depth_filter(const FilterPack& cams, int count, int max_pix, const float* depth,
-                         double tau2, float* out, hipStream_t s) {
+void launch_depth_filter(const FilterPack& cams, int first, int count, int max_pix,
+                         const float* depth, const double* st, double tau2, float* out,
+                         hipStream_t s) {
   const int bx = (max_pix + kDepthThreads - 1) / kDepthThreads;
-  if (bx > 0) k_depth_filter<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, tau2, depth, out);
+  if (bx > 0)
+    k_depth_filter<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, first, tau2, depth, st, out);
 }
 
 }  // namespace cgx

@@ -261,21 +261,27 @@ class Renderer:
         B.cgx_ncc_loss(self.ctx, views, self.ws, out, c, n_patch, weight, grad_rgb, loss)
         return grad_rgb, loss
 
-    def depth_prior(self, views, prior, points, nearby, tau=1.0, aligned=None, filtered=None):
+    def depth_prior(self, views, prior, points, nearby, tau=1.0, aligned=None, filtered=None,
+                    keep_aligned=True):
         """Depth prior of Sec. 3.4 (Step 2): per-view scale / shift of the
         packed float32 pseudo-depth `prior` against the sparse float32 (N, 3)
         `points`, then the multi-view filter with nearby[v] (or -1) at
         tau_d = `tau` pixels.  Returns (filtered, aligned, scale_shift (B, 2)
-        float64)."""
+        float64); with keep_aligned=False the aligned image is not written
+        (None is returned for it) and the filter aligns on the fly."""
         dev = f"cuda:{self.device}"
         nbytes = B.cgx_depth_align_workspace_size(len(views))
         if self.depth_ws is None or self.depth_ws.numel() * 8 < nbytes:
             self.depth_ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
         st = torch.empty(len(views), 2, dtype=torch.float64, device=dev)
-        if aligned is None:
-            aligned = torch.empty_like(prior)
         if filtered is None:
             filtered = torch.empty_like(prior)
+        if not keep_aligned:
+            B.cgx_depth_prior_align(self.ctx, views, prior, points, self.depth_ws, st, None)
+            B.cgx_depth_prior_filter(self.ctx, views, prior, nearby, tau, filtered, scale_shift=st)
+            return filtered, None, st
+        if aligned is None:
+            aligned = torch.empty_like(prior)
         B.cgx_depth_prior_align(self.ctx, views, prior, points, self.depth_ws, st, aligned)
         B.cgx_depth_prior_filter(self.ctx, views, aligned, nearby, tau, filtered)
         return filtered, aligned, st

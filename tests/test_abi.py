@@ -187,16 +187,19 @@ def test_depth_prior_entry_points_reject_bad_arguments(B):
         nb = lambda *x: (C.c_int32 * 2)(*x)  # noqa: E731
         other = C.c_void_p(8192)
         for bad in ((0, -1), (2, 0), (-2, 0)):
-            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(*bad), 1.0, other, None)
+            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, nb(*bad), 1.0, other, None)
             assert rc == B.CGX_ERR_INVALID_ARG and b"nearby" in lib.cgx_last_error(ctx)
-        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(1, 0), 1.0, fake, None)
+        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, nb(1, 0), 1.0, fake, None)
         assert rc == B.CGX_ERR_INVALID_ARG and b"alias" in lib.cgx_last_error(ctx)
         for tau in (0.0, -1.0, float("nan"), float("inf")):
-            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, nb(1, 0), tau, other, None)
+            rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, nb(1, 0), tau, other, None)
             assert rc == B.CGX_ERR_INVALID_ARG
-        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, 1.0, other, None)
+        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, None, None, 1.0, other, None)
         assert rc == B.CGX_ERR_INVALID_ARG
-        rc = lib.cgx_depth_prior_filter(None, va, 2, fake, nb(1, 0), 1.0, other, None)
+        rc = lib.cgx_depth_prior_filter(ctx, va, 2, fake, C.c_void_p(4100), nb(1, 0), 1.0, other, None)
+        assert rc == B.CGX_ERR_INVALID_ARG and b"scale_shift" in lib.cgx_last_error(ctx)
+        assert rc == B.CGX_ERR_INVALID_ARG
+        rc = lib.cgx_depth_prior_filter(None, va, 2, fake, None, nb(1, 0), 1.0, other, None)
         assert rc == B.CGX_ERR_INVALID_ARG
     finally:
         B.cgx_destroy(ctx)

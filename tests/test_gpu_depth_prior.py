@@ -129,6 +129,25 @@ def test_filter_matches_oracle_small_uneven(R, rd, tau):
                                           tau=float(np.float32(tau)))
     got = _filter_gpu(R, rd, X.views, depth32, nearby, tau)
     _check_filtered(got, ref, frag)
+    # the same filter fed the raw prior and (s, t), aligning on the fly
+    st_ref = np.zeros((4, 2))
+    st_ref[:, 0] = 1.0
+    st_ref[1] = (1.7, -0.3)
+    raw = [d.copy() for d in depth32]
+    raw[1] = np.where(raw[1] > 0, ((raw[1].astype(np.float64) + 0.3) / 1.7), raw[1]).astype(np.float32)
+    ali = [d.copy() for d in raw]
+    ali[1] = np.where(raw[1] > 0, 1.7 * raw[1].astype(np.float64) - 0.3, 0.0).astype(np.float32)
+    ali[1][~(raw[1] > 0)] = 0.0
+    for k in (0, 2, 3):
+        ali[k] = np.where(raw[k] > 0, raw[k], 0.0).astype(np.float32)
+    d = _dev(raw)
+    out = torch.empty_like(d)
+    R.B.cgx_depth_prior_filter(rd.ctx, X.views, d, nearby, tau, out,
+                               scale_shift=torch.from_numpy(st_ref).cuda())
+    torch.cuda.synchronize()
+    ref2, frag2, _ = dp.reprojection_filter([a.astype(np.float64) for a in ali], X.views, nearby,
+                                            tau=float(np.float32(tau)))
+    _check_filtered(_split(out, X.views), ref2, frag2)
     assert sum(int((r > 0).sum()) for r in ref[:3]) > 0
     assert sum(int(((d > 0) & (r == 0)).sum()) for d, r in zip(depth32[:3], ref[:3])) > 0
 
@@ -154,4 +173,12 @@ def test_full_size_pairs_match_oracle(R, rd):
         np.testing.assert_array_equal(a, b)
     chained = _filter_gpu(R, rd, X.views, _split(al2, X.views), X.nearby)
     for a, b in zip(_split(filt, X.views), chained):
+        np.testing.assert_array_equal(a, b)
+    # aligning on the fly inside the filter gives the same bits
+    fused, none, st3 = rd.depth_prior(X.views, _dev(X.prior), torch.from_numpy(X.points).cuda(),
+                                      X.nearby, keep_aligned=False)
+    torch.cuda.synchronize()
+    assert none is None
+    np.testing.assert_array_equal(st3.cpu().numpy(), st)
+    for a, b in zip(_split(fused, X.views), chained):
         np.testing.assert_array_equal(a, b)
