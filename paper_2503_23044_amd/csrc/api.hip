@@ -784,14 +784,30 @@ static int depth_cams(const cgx_view* views, int32_t n, std::vector<HostCam>& ca
   return max_pix;
 }
 
-// camera a -> camera b: x_b = R_b R_a^T (x_a - t_a) + t_b = M x_a + T
-static void compose(const HostCam& a, const HostCam& b, double* M, double* T) {
+// pixel (with depth) of camera a -> K_b times the point in camera b:
+// x_b = R_b R_a^T (x_a - t_a) + t_b = M x_a + T with x_a = d K_a^-1 [p, 1],
+// so K_b x_b = d (K_b M K_a^-1) [p, 1] + K_b T
+static void compose(const HostCam& a, const HostCam& b, double* Hm, double* h0) {
+  double M[9], T[3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       M[3 * i + j] = b.R[3 * i + 0] * a.R[3 * j + 0] + b.R[3 * i + 1] * a.R[3 * j + 1] +
                      b.R[3 * i + 2] * a.R[3 * j + 2];
   for (int i = 0; i < 3; ++i)
     T[i] = b.t[i] - (M[3 * i + 0] * a.t[0] + M[3 * i + 1] * a.t[1] + M[3 * i + 2] * a.t[2]);
+  const double Kinv[9] = {1.0 / a.fx, 0.0, -a.cx / a.fx, 0.0, 1.0 / a.fy, -a.cy / a.fy, 0.0, 0.0, 1.0};
+  const double K[9] = {b.fx, 0.0, b.cx, 0.0, b.fy, b.cy, 0.0, 0.0, 1.0};
+  double MK[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      MK[3 * i + j] = M[3 * i + 0] * Kinv[0 * 3 + j] + M[3 * i + 1] * Kinv[1 * 3 + j] +
+                      M[3 * i + 2] * Kinv[2 * 3 + j];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      Hm[3 * i + j] = K[3 * i + 0] * MK[0 * 3 + j] + K[3 * i + 1] * MK[1 * 3 + j] +
+                      K[3 * i + 2] * MK[2 * 3 + j];
+    h0[i] = K[3 * i + 0] * T[0] + K[3 * i + 1] * T[1] + K[3 * i + 2] * T[2];
+  }
 }
 
 size_t cgx_depth_align_workspace_size(int32_t n_views) {
@@ -877,13 +893,7 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
     for (int i = 0; i < count; ++i) {
       const HostCam& h = hc[first + i];
       FilterCam& c = P.v[i];
-      c.ifx = 1.0 / h.fx;
-      c.ify = 1.0 / h.fy;
-      c.cx = h.cx;
-      c.cy = h.cy;
-      c.fx = h.fx;
-      c.fy = h.fy;
-      c.z_near = h.zn;
+      c.zn = h.zn;
       c.W = h.W;
       c.H = h.H;
       c.iW = 1.0 / h.W;
@@ -891,14 +901,8 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
       c.nearby = nearby[first + i];
       if (c.nearby >= 0) {
         const HostCam& u = hc[c.nearby];
-        compose(h, u, c.M, c.T);
-        compose(u, h, c.N, c.S);
-        c.fxu = u.fx;
-        c.fyu = u.fy;
-        c.cxu = u.cx;
-        c.cyu = u.cy;
-        c.ifxu = 1.0 / u.fx;
-        c.ifyu = 1.0 / u.fy;
+        compose(h, u, c.Hm, c.h0);
+        compose(u, h, c.Gm, c.g0);
         c.znu = u.zn;
         c.Wu = u.W;
         c.Hu = u.H;

@@ -375,13 +375,15 @@ constexpr int kAlignGroup = 16;
 struct AlignPack {
   AlignCam v[kAlignGroup];
 };
-// view v and its nearby view u: M, T map camera v to camera u, N, S camera u
-// back to camera v (composed on the host in float64)
+// view v and its nearby view u, composed on the host in float64: for a
+// pixel centre p of v with depth d, h = d (Hm [p, 1]) + h0 is K_u times the
+// point in camera u (h2 its depth in u); for a pixel position q of u with
+// u's depth e, g = e (Gm [q, 1]) + g0 is K_v times the lifted point in
+// camera v.  Hm = K_u R_u R_v^T K_v^-1, h0 = K_u (t_u - R_u R_v^T t_v), and
+// Gm, g0 the same with the views swapped.
 struct FilterCam {
-  double ifx, ify, cx, cy, fx, fy, z_near;
-  double M[9], T[3], N[9], S[3];
-  double fxu, fyu, cxu, cyu, ifxu, ifyu, znu;
-  double iW;                   // 1 / W
+  double Hm[9], h0[3], Gm[9], g0[3];
+  double znu, zn, iW;          // near planes of u and v, 1 / W_v
   int32_t W, H, pix_off, Wu, Hu, pix_off_u, nearby, pad;
 };
 constexpr int kFilterGroup = 8;

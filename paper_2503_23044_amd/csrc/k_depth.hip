@@ -13,14 +13,15 @@
 //     fixed order (each thread's points in index order, a xor-tree over the
 //     wave, waves in order, then the 512 block partials the same way), so a
 //     run is deterministic; another order moves (s, t) in the last bits.
-//   * Filter: the per-pixel chain is the cost, so the host composes the
-//     two camera-to-camera transforms (camera v -> u and back) and the
-//     inverse focal lengths in float64, and the kernel uses fused
+//   * Filter: the per-pixel chain is the cost, so the host composes, in
+//     float64, each direction's intrinsics and camera-to-camera transform
+//     into one 3x3 matrix and offset (pixel and depth of v -> K_u times the
+//     point in camera u, and back), and the kernel uses fused
 //     multiply-adds and one reciprocal (hardware estimate + two Newton
 //     steps) per projection.  Against the camera-by-camera evaluation this
-//     moves a re-projected position by ~1e-13 px, so a decision can differ
-//     only for a position within ~1e-12 of a pixel edge or an error within
-//     ~1e-12 of tau_d.
+//     moves a re-projected position by ~1e-12 px, so a decision can differ
+//     only for a position within ~1e-11 of a pixel edge, a depth that close
+//     to a near plane, or an error that close to tau_d.
 //
 // Kernels:
 //   k_align_partials  grid 512 x views x 256 (view = block % views): each thread projects 4
@@ -31,7 +32,7 @@
 //                     equations -> (s, t);
 //   k_align_apply     grid (pixels / 2048, views) x 256: aligned = s D + t
 //                     where D > 0, else 0 (in place allowed);
-//   k_depth_filter    grid (pixels / 256, views) x 256: one pixel per
+//   k_depth_filter    grid (pixels / 1024, views) x 256: four pixels per
 //                     thread, a gather from the nearby view's depth; given
 //                     the (s, t) of every view it reads the raw prior and
 //                     aligns both values on the fly (the same float32 values
@@ -46,6 +47,7 @@ namespace cgx {
 constexpr int kDepthThreads = 256;
 constexpr int kApplyPerThread = 8;
 constexpr int kPointsInFlight = 4;
+constexpr int kFilterPerThread = 4;
 
 __device__ __forceinline__ double dsum_wave(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -193,57 +195,105 @@ __global__ __launch_bounds__(kDepthThreads) void k_align_apply(AlignPack cams, i
 }
 
 // st == nullptr: `depth` holds the depths; otherwise it holds the raw
-// prior and each value read is aligned with its view's (s, t) first
+// prior and each value read is aligned with its view's (s, t) first.
+// Each thread takes kFilterPerThread pixels (stride 256) in stages -- all
+// depth loads, all forward halves, all gathers from the nearby view, all
+// back halves -- so that a wave keeps several loads in flight through each
+// of its two dependent memory trips.
 __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams, int first,
                                                                 double tau2,
                                                                 const float* __restrict__ depth,
                                                                 const double* __restrict__ st,
                                                                 float* __restrict__ out) {
   const FilterCam& c = cams.v[blockIdx.y];
-  const int p = blockIdx.x * kDepthThreads + threadIdx.x;
-  if (p >= c.W * c.H) return;
-  float df = depth[(size_t)c.pix_off + p];
-  if (st) df = aligned_value(df, st[2 * (first + blockIdx.y)], st[2 * (first + blockIdx.y) + 1]);
-  const double d = (double)df;
-  float res = 0.0f;
+  const int npx = c.W * c.H;
+  const int base = blockIdx.x * kDepthThreads * kFilterPerThread + threadIdx.x;
+  if (base >= npx) return;
+  const float* src = depth + c.pix_off;
+  float* dst = out + c.pix_off;
+  const bool al = st != nullptr;
+  double sv = 1.0, tv = 0.0, su = 1.0, tu = 0.0;
+  if (al) {
+    sv = st[2 * (first + blockIdx.y)];
+    tv = st[2 * (first + blockIdx.y) + 1];
+    if (c.nearby >= 0) {
+      su = st[2 * c.nearby];
+      tu = st[2 * c.nearby + 1];
+    }
+  }
+  float df[kFilterPerThread];
+#pragma unroll
+  for (int k = 0; k < kFilterPerThread; ++k) {
+    const int p = base + k * kDepthThreads;
+    df[k] = p < npx ? src[p] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kFilterPerThread; ++k)
+    if (al) df[k] = aligned_value(df[k], sv, tv);
   if (c.nearby < 0) {
-    res = d > 0.0 ? df : 0.0f;
-  } else if (d > 0.0) {
-    // row j = floor((p + 1/2) / W): the quotient stays >= 1/(2W) away from
-    // an integer, far above the rounding of one float64 multiply
-    const int j = (int)floor(((double)p + 0.5) * c.iW);
-    const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
-    // back-project in camera v, move to camera u
-    const double x0 = ((px - c.cx) * c.ifx) * d, x1 = ((py - c.cy) * c.ify) * d;
-    const double y2 = fma(c.M[6], x0, fma(c.M[7], x1, fma(c.M[8], d, c.T[2])));
-    if (y2 > c.znu) {
-      const double y0 = fma(c.M[0], x0, fma(c.M[1], x1, fma(c.M[2], d, c.T[0])));
-      const double y1 = fma(c.M[3], x0, fma(c.M[4], x1, fma(c.M[5], d, c.T[1])));
-      const double r = recip(y2);
-      const double qx = fma(c.fxu * y0, r, c.cxu);
-      const double qy = fma(c.fyu * y1, r, c.cyu);
-      if (qx >= 0.0 && qx < (double)c.Wu && qy >= 0.0 && qy < (double)c.Hu) {
-        const int iq = (int)floor(qx), jq = (int)floor(qy);
-        float duf = depth[(size_t)c.pix_off_u + (size_t)jq * c.Wu + iq];
-        if (st) duf = aligned_value(duf, st[2 * c.nearby], st[2 * c.nearby + 1]);
-        const double du = (double)duf;
-        if (du > 0.0) {
-          // lift with u's depth, back to camera v, re-project
-          const double a0 = ((qx - c.cxu) * c.ifxu) * du, a1 = ((qy - c.cyu) * c.ifyu) * du;
-          const double z2 = fma(c.N[6], a0, fma(c.N[7], a1, fma(c.N[8], du, c.S[2])));
-          if (z2 > c.z_near) {
-            const double z0 = fma(c.N[0], a0, fma(c.N[1], a1, fma(c.N[2], du, c.S[0])));
-            const double z1 = fma(c.N[3], a0, fma(c.N[4], a1, fma(c.N[5], du, c.S[1])));
-            const double r2 = recip(z2);
-            const double ex = fma(c.fx * z0, r2, c.cx) - px;
-            const double ey = fma(c.fy * z1, r2, c.cy) - py;
-            if (fma(ex, ex, ey * ey) < tau2) res = df;
-          }
+#pragma unroll
+    for (int k = 0; k < kFilterPerThread; ++k) {
+      const int p = base + k * kDepthThreads;
+      if (p < npx) dst[p] = df[k] > 0.0f ? df[k] : 0.0f;
+    }
+    return;
+  }
+  // forward half: pixel of v -> position q in u, and the pixel it falls in
+  double qx[kFilterPerThread], qy[kFilterPerThread];
+  int gi[kFilterPerThread];
+#pragma unroll
+  for (int k = 0; k < kFilterPerThread; ++k) {
+    const int p = base + k * kDepthThreads;
+    const double d = (double)df[k];
+    gi[k] = -1;
+    qx[k] = 0.0;
+    qy[k] = 0.0;
+    if (p < npx && d > 0.0) {
+      // row j = floor((p + 1/2) / W): the quotient stays >= 1/(2W) away
+      // from an integer, far above the rounding of one float64 multiply
+      const int j = (int)floor(((double)p + 0.5) * c.iW);
+      const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
+      // K_u times the point in camera u; its third component is the depth in u
+      const double h2 = fma(d, fma(c.Hm[6], px, fma(c.Hm[7], py, c.Hm[8])), c.h0[2]);
+      if (h2 > c.znu) {
+        const double h0 = fma(d, fma(c.Hm[0], px, fma(c.Hm[1], py, c.Hm[2])), c.h0[0]);
+        const double h1 = fma(d, fma(c.Hm[3], px, fma(c.Hm[4], py, c.Hm[5])), c.h0[1]);
+        const double r = recip(h2);
+        const double x = h0 * r, y = h1 * r;
+        if (x >= 0.0 && x < (double)c.Wu && y >= 0.0 && y < (double)c.Hu) {
+          gi[k] = (int)floor(y) * c.Wu + (int)floor(x);
+          qx[k] = x;
+          qy[k] = y;
         }
       }
     }
   }
-  out[(size_t)c.pix_off + p] = res;
+  float duf[kFilterPerThread];
+#pragma unroll
+  for (int k = 0; k < kFilterPerThread; ++k)
+    duf[k] = gi[k] >= 0 ? depth[(size_t)c.pix_off_u + gi[k]] : 0.0f;
+  // back half: lift q with u's depth, back to camera v (times K_v), re-project
+#pragma unroll
+  for (int k = 0; k < kFilterPerThread; ++k) {
+    const int p = base + k * kDepthThreads;
+    if (p >= npx) continue;
+    float res = 0.0f;
+    const double du = (double)(al ? aligned_value(duf[k], su, tu) : duf[k]);
+    if (gi[k] >= 0 && du > 0.0) {
+      const int j = (int)floor(((double)p + 0.5) * c.iW);
+      const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
+      const double g2 = fma(du, fma(c.Gm[6], qx[k], fma(c.Gm[7], qy[k], c.Gm[8])), c.g0[2]);
+      if (g2 > c.zn) {
+        const double g0 = fma(du, fma(c.Gm[0], qx[k], fma(c.Gm[1], qy[k], c.Gm[2])), c.g0[0]);
+        const double g1 = fma(du, fma(c.Gm[3], qx[k], fma(c.Gm[4], qy[k], c.Gm[5])), c.g0[1]);
+        const double r2 = recip(g2);
+        const double ex = fma(g0, r2, -px);
+        const double ey = fma(g1, r2, -py);
+        if (fma(ex, ex, ey * ey) < tau2) res = df[k];
+      }
+    }
+    dst[p] = res;
+  }
 }
 
 void launch_depth_align_partials(const AlignPack& cams, int first, int count, const float* prior,
@@ -266,7 +316,8 @@ void launch_depth_align_finish(const AlignPack& cams, int first, int count, int 
 void launch_depth_filter(const FilterPack& cams, int first, int count, int max_pix,
                          const float* depth, const double* st, double tau2, float* out,
                          hipStream_t s) {
-  const int bx = (max_pix + kDepthThreads - 1) / kDepthThreads;
+  const int per_block = kDepthThreads * kFilterPerThread;
+  const int bx = (max_pix + per_block - 1) / per_block;
   if (bx > 0)
     k_depth_filter<<<dim3(bx, count), kDepthThreads, 0, s>>>(cams, first, tau2, depth, st, out);
 }
