@@ -18,7 +18,7 @@ depth mask).  Readings of what the paper leaves open:
     pairs or a singular system leave (s, t) = (1, 0); the aligned prior is
     s D_p + t where D_p > 0 and 0 elsewhere;
   * re-projection error, for pixel p = (i + 1/2, j + 1/2) of view v with
-    depth d > 0 and its nearby view u: X = d K_v^-1 [p, 1] (camera v) is
+    a finite depth d > 0 and its nearby view u: X = d K_v^-1 [p, 1] (camera v) is
     moved to camera u; if it is in front (z > z_near) and projects to q
     inside u's image, the depth d_u of u at the pixel containing q lifts q
     to Y = d_u K_u^-1 [q, 1] (camera u), which goes back to camera v and
@@ -86,6 +86,11 @@ def reprojection_filter(depth, views, nearby, tau=1.0):
     z-depth maps; nearby[v]: index of the nearby view of view v (or -1: no
     filter, every pixel kept).  Returns (filtered list, fragile list,
     error list (inf where not reprojected))."""
+    with np.errstate(invalid="ignore", over="ignore"):     # inf / NaN depths are no depth
+        return _filter(depth, views, nearby, tau)
+
+
+def _filter(depth, views, nearby, tau):
     out, frag, errs = [], [], []
     cams = [_cam(v) for v in views]
     for v in range(len(views)):
@@ -106,7 +111,7 @@ def reprojection_filter(depth, views, nearby, tau=1.0):
         xw = [((R[0, k] * (xc[0] - t[0]) + R[1, k] * (xc[1] - t[1])) + R[2, k] * (xc[2] - t[2]))
               for k in range(3)]
         yc = [((Ru[k, 0] * xw[0] + Ru[k, 1] * xw[1]) + Ru[k, 2] * xw[2]) + tu[k] for k in range(3)]
-        front = (d > 0.0) & (yc[2] > znu)
+        front = (d > 0.0) & (d < np.inf) & (yc[2] > znu)
         zs = np.where(front, yc[2], 1.0)
         qx = (fxu * yc[0]) / zs + cxu
         qy = (fyu * yc[1]) / zs + cyu
@@ -117,7 +122,7 @@ def reprojection_filter(depth, views, nearby, tau=1.0):
         iq = np.floor(np.where(inside, qx, 0.0)).astype(np.int64)
         jq = np.floor(np.where(inside, qy, 0.0)).astype(np.int64)
         du = np.where(inside, Du[jq * Wu + iq], 0.0)
-        ok = inside & (du > 0.0)
+        ok = inside & (du > 0.0) & (du < np.inf)
         # camera u -> world -> camera v
         yc2 = [du * ((qx - cxu) / fxu), du * ((qy - cyu) / fyu), du]
         yw = [((Ru[0, k] * (yc2[0] - tu[0]) + Ru[1, k] * (yc2[1] - tu[1])) + Ru[2, k] * (yc2[2] - tu[2]))

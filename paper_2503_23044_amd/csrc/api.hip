@@ -906,6 +906,8 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
         c.znu = u.zn;
         c.Wu = u.W;
         c.Hu = u.H;
+        c.Wud = u.W;
+        c.Hud = u.H;
         c.pix_off_u = (int32_t)u.off;
       }
     }

@@ -384,6 +384,7 @@ struct AlignPack {
 struct FilterCam {
   double Hm[9], h0[3], Gm[9], g0[3];
   double znu, zn, iW;          // near planes of u and v, 1 / W_v
+  double Wud, Hud;             // W_u, H_u
   int32_t W, H, pix_off, Wu, Hu, pix_off_u, nearby, pad;
 };
 constexpr int kFilterGroup = 8;

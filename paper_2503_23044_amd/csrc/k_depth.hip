@@ -48,6 +48,7 @@ constexpr int kDepthThreads = 256;
 constexpr int kApplyPerThread = 8;
 constexpr int kPointsInFlight = 4;
 constexpr int kFilterPerThread = 4;
+constexpr double kInf = __builtin_inf();
 
 __device__ __forceinline__ double dsum_wave(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -238,61 +239,52 @@ __global__ __launch_bounds__(kDepthThreads) void k_depth_filter(FilterPack cams,
     }
     return;
   }
-  // forward half: pixel of v -> position q in u, and the pixel it falls in
+  // forward half, branch-free: pixel of v -> position q in u and the pixel
+  // it falls in (gi = -1: none)
+  double px[kFilterPerThread], py[kFilterPerThread];
   double qx[kFilterPerThread], qy[kFilterPerThread];
   int gi[kFilterPerThread];
 #pragma unroll
   for (int k = 0; k < kFilterPerThread; ++k) {
     const int p = base + k * kDepthThreads;
     const double d = (double)df[k];
-    gi[k] = -1;
-    qx[k] = 0.0;
-    qy[k] = 0.0;
-    if (p < npx && d > 0.0) {
-      // row j = floor((p + 1/2) / W): the quotient stays >= 1/(2W) away
-      // from an integer, far above the rounding of one float64 multiply
-      const int j = (int)floor(((double)p + 0.5) * c.iW);
-      const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
-      // K_u times the point in camera u; its third component is the depth in u
-      const double h2 = fma(d, fma(c.Hm[6], px, fma(c.Hm[7], py, c.Hm[8])), c.h0[2]);
-      if (h2 > c.znu) {
-        const double h0 = fma(d, fma(c.Hm[0], px, fma(c.Hm[1], py, c.Hm[2])), c.h0[0]);
-        const double h1 = fma(d, fma(c.Hm[3], px, fma(c.Hm[4], py, c.Hm[5])), c.h0[1]);
-        const double r = recip(h2);
-        const double x = h0 * r, y = h1 * r;
-        if (x >= 0.0 && x < (double)c.Wu && y >= 0.0 && y < (double)c.Hu) {
-          gi[k] = (int)floor(y) * c.Wu + (int)floor(x);
-          qx[k] = x;
-          qy[k] = y;
-        }
-      }
-    }
+    // row j = floor((p + 1/2) / W): the quotient stays >= 1/(2W) away
+    // from an integer, far above the rounding of one float64 multiply
+    const int j = (int)floor(((double)p + 0.5) * c.iW);
+    px[k] = (double)(p - j * c.W) + 0.5;
+    py[k] = (double)j + 0.5;
+    // K_u times the point in camera u; its third component is the depth in u
+    const double h2 = fma(d, fma(c.Hm[6], px[k], fma(c.Hm[7], py[k], c.Hm[8])), c.h0[2]);
+    const double h0 = fma(d, fma(c.Hm[0], px[k], fma(c.Hm[1], py[k], c.Hm[2])), c.h0[0]);
+    const double h1 = fma(d, fma(c.Hm[3], px[k], fma(c.Hm[4], py[k], c.Hm[5])), c.h0[1]);
+    const bool front = p < npx && d > 0.0 && d < kInf && h2 > c.znu;
+    const double r = recip(front ? h2 : 1.0);
+    const double x = h0 * r, y = h1 * r;
+    const bool inside = front && x >= 0.0 && x < c.Wud && y >= 0.0 && y < c.Hud;
+    gi[k] = inside ? (int)floor(y) * c.Wu + (int)floor(x) : -1;
+    qx[k] = x;
+    qy[k] = y;
   }
+  // gathers from the nearby view (index 0, in bounds, where there is none)
   float duf[kFilterPerThread];
 #pragma unroll
   for (int k = 0; k < kFilterPerThread; ++k)
-    duf[k] = gi[k] >= 0 ? depth[(size_t)c.pix_off_u + gi[k]] : 0.0f;
-  // back half: lift q with u's depth, back to camera v (times K_v), re-project
+    duf[k] = depth[(size_t)c.pix_off_u + (gi[k] >= 0 ? gi[k] : 0)];
+  // back half, branch-free: lift q with u's depth, back to camera v (times
+  // K_v), re-project
 #pragma unroll
   for (int k = 0; k < kFilterPerThread; ++k) {
     const int p = base + k * kDepthThreads;
-    if (p >= npx) continue;
-    float res = 0.0f;
     const double du = (double)(al ? aligned_value(duf[k], su, tu) : duf[k]);
-    if (gi[k] >= 0 && du > 0.0) {
-      const int j = (int)floor(((double)p + 0.5) * c.iW);
-      const double px = (double)(p - j * c.W) + 0.5, py = (double)j + 0.5;
-      const double g2 = fma(du, fma(c.Gm[6], qx[k], fma(c.Gm[7], qy[k], c.Gm[8])), c.g0[2]);
-      if (g2 > c.zn) {
-        const double g0 = fma(du, fma(c.Gm[0], qx[k], fma(c.Gm[1], qy[k], c.Gm[2])), c.g0[0]);
-        const double g1 = fma(du, fma(c.Gm[3], qx[k], fma(c.Gm[4], qy[k], c.Gm[5])), c.g0[1]);
-        const double r2 = recip(g2);
-        const double ex = fma(g0, r2, -px);
-        const double ey = fma(g1, r2, -py);
-        if (fma(ex, ex, ey * ey) < tau2) res = df[k];
-      }
-    }
-    dst[p] = res;
+    const double g2 = fma(du, fma(c.Gm[6], qx[k], fma(c.Gm[7], qy[k], c.Gm[8])), c.g0[2]);
+    const double g0 = fma(du, fma(c.Gm[0], qx[k], fma(c.Gm[1], qy[k], c.Gm[2])), c.g0[0]);
+    const double g1 = fma(du, fma(c.Gm[3], qx[k], fma(c.Gm[4], qy[k], c.Gm[5])), c.g0[1]);
+    const bool ok = gi[k] >= 0 && du > 0.0 && du < kInf && g2 > c.zn;
+    const double r2 = recip(ok ? g2 : 1.0);
+    const double ex = fma(g0, r2, -px[k]);
+    const double ey = fma(g1, r2, -py[k]);
+    const bool keep = ok && fma(ex, ex, ey * ey) < tau2;
+    if (p < npx) dst[p] = keep ? df[k] : 0.0f;
   }
 }
 

@@ -124,6 +124,7 @@ def test_filter_matches_oracle_small_uneven(R, rd, tau):
     depth32 = [a.astype(np.float32) for a in al_ref]
     depth32[0][::11] = np.nan
     depth32[3][::13] = -2.0
+    depth32[1][::17] = np.inf                      # an infinite depth is no depth
     nearby = [1, 0, 3, -1]                         # the last view has no nearby view
     ref, frag, _ = dp.reprojection_filter([d.astype(np.float64) for d in depth32], X.views, nearby,
                                           tau=float(np.float32(tau)))

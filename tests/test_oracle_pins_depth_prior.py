@@ -192,7 +192,8 @@ def test_filter_on_the_optical_axis_from_behind():
     pixel although the axis would re-project it onto itself."""
     views = _axis_pair()
     p = 20 * 48 + 24
-    for d1p, d0p, kept in ((5.0, 2.0, True), (1.0, 2.0, False), (5.0, 0.0, False)):
+    for d1p, d0p, kept in ((5.0, 2.0, True), (1.0, 2.0, False), (5.0, 0.0, False),
+                           (5.0, np.inf, False), (5.0, np.nan, False)):
         d1 = np.zeros(48 * 40)
         d1[p] = d1p
         d0 = np.zeros(48 * 40)
