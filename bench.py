@@ -58,6 +58,10 @@ def parse():
                    help="skip the timing of the depth-prior alignment and filter (Sec. 3.4)")
     p.add_argument("--depth-only", action="store_true",
                    help="time only the depth-prior steps and print their JSON object")
+    p.add_argument("--no-tsdf", action="store_true",
+                   help="skip the timing of the TSDF fusion (Sec. 4)")
+    p.add_argument("--tsdf-only", action="store_true",
+                   help="time only the TSDF fusion and print its JSON object")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run 3 plain device copies of MIB MiB (a known-traffic kernel "
                         "for scaling hardware byte counters)")
@@ -373,6 +377,51 @@ def depth_prior_leg(args):
             "Mpixels_per_s": round(px / ((ms_a + ms_f) * 1e-3) / 1e6, 1), "kept": round(kept, 4)}
 
 
+def tsdf_leg(args):
+    """Timing of the TSDF fusion (Sec. 4, mesh reconstruction;
+    cgx_tsdf_integrate): the z-depth and colour of 8 views over the box city
+    fused into a 512 x 512 x 128 grid of 0.4 m voxels (truncation 2 m), timed
+    with HIP events over 20 launches (each fuses all 8 views into the
+    growing volume).  Two resolutions of the same cameras: 1920x1080 (a
+    voxel spans about 4 pixels, so every depth / colour gather pulls its own
+    cache line) and 480x270 (pixel footprint about one voxel)."""
+    import numpy as np
+    import torch
+
+    from paper_2503_23044_amd import render
+    from synth import scenes
+
+    rd = render.Renderer(0, (16, 16))
+    dims = (512, 512, 128)
+    n = dims[0] * dims[1] * dims[2]
+    res = {}
+    for W, H in ((1920, 1080), (480, 270)):
+        X = scenes.make_depth_prior(n_points=100, sizes=[(W, H)] * 8)
+        rng = np.random.default_rng(60)
+        depth = torch.from_numpy(np.concatenate(X.depth).astype(np.float32)).cuda()
+        rgb = torch.from_numpy(np.concatenate([rng.uniform(0, 1, (3, int(v.width) * int(v.height)))
+                                               .astype(np.float32).reshape(-1) for v in X.views])).cuda()
+        vol = rd.tsdf_volume((-2.4, -2.4, -0.8), 0.4, dims, 2.0)
+        rd.tsdf_integrate(X.views, depth, vol, rgb=rgb)
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rd.tsdf_integrate(X.views, depth, vol, rgb=rgb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        seen = float((vol["weight"] > 0).float().mean().item())
+        log(f"[bench] tsdf fusion: 8 views of {W}x{H} into {n} voxels in {ms * 1e3:.1f} us "
+            f"({seen:.3f} of the voxels observed)")
+        res[f"{W}x{H}"] = {"ms": round(ms, 4), "Gvoxel_views_per_s": round(n * 8 / (ms * 1e-3) / 1e9, 2),
+                           "observed": round(seen, 4)}
+        del vol, depth, rgb
+    return {"workload": "8 views over a box city into a 512x512x128 grid of 0.4 m voxels",
+            "voxels": n, "views": 8, **res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -381,6 +430,11 @@ def main():
         sys.exit(2)
     if args.ncc_only:
         print(json.dumps({"ncc_loss": ncc_leg(args)}), flush=True)
+        return
+    if args.tsdf_only:
+        if args.copy_calibration:
+            copy_calibration(args.copy_calibration)
+        print(json.dumps({"tsdf_fusion": tsdf_leg(args)}), flush=True)
         return
     if args.depth_only:
         if args.copy_calibration:
@@ -425,6 +479,8 @@ def main():
         line["ncc_loss"] = ncc_leg(args)
     if not args.no_depth:
         line["depth_prior"] = depth_prior_leg(args)
+    if not args.no_tsdf:
+        line["tsdf_fusion"] = tsdf_leg(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tiles)

@@ -339,6 +339,49 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
                                const float* depth, const double* scale_shift,
                                const int32_t* nearby, float tau, float* filtered, void* stream);
 
+/* TSDF volume for the fusion of rendered depth and colour (Sec. 4, mesh
+ * reconstruction; the projective truncated signed distance fusion of
+ * 3DMatch that the paper cites).  Voxel (i, j, k), 0 <= i < nx etc., is the
+ * world point origin + voxel * (i, j, k) and has index
+ * i + nx * (j + ny * k) in the three device float32 arrays: tsdf (N),
+ * weight (N) and color (3 N, channel-major planes; NULL: no colour).
+ * N = nx ny nz must be below 2^31.  `trunc` is the truncation distance mu
+ * (world units). */
+typedef struct cgx_tsdf_volume {
+  float origin[3];
+  float voxel;
+  float trunc;
+  int32_t nx, ny, nz;
+  float* tsdf;
+  float* weight;
+  float* color;
+} cgx_tsdf_volume;
+
+/* Empty volume: tsdf = 1, weight = 0, color = 0 (a fill kernel, no memset,
+ * so it may be captured in a graph). */
+int32_t cgx_tsdf_init(cgx_ctx* ctx, const cgx_tsdf_volume* vol, void* stream);
+
+/* Fuse views into the volume, in order (Sec. 4).  `depth` (device float32,
+ * packed layout) holds each view's rendered z-depth (the unbiased depth
+ * of cgx_images); `rgb` (device float32, packed planar rgb layout) its
+ * colour, or NULL to leave the volume's colour alone.  Per voxel and view:
+ * the voxel's camera point p = R X + t is seen if p_z > z_near and its
+ * projection (fx p_x / p_z + cx, fy p_y / p_z + cy) lies in [0, W) x
+ * [0, H); the depth d at the pixel containing it is an observation if it is
+ * finite and > 0; with diff = d - p_z, a voxel with diff > -trunc is
+ * updated: f = min(1, diff / trunc), W' = W + 1, tsdf' = (tsdf W + f) / W',
+ * color' = (color W + c) / W' (c the pixel's rgb); others are left alone.
+ * Up to 16 views are applied per pass over the volume with the state in
+ * float64 registers (rounded to float32 when stored); the result does not
+ * depend on the batching beyond that rounding.  Decisions are float64 on a
+ * projection composed on the host.  Errors: CGX_ERR_INVALID_ARG for a bad
+ * view, a NULL tsdf / weight / depth, or a bad grid (sizes < 1,
+ * N >= 2^31, voxel or trunc not > 0 and finite, non-finite origin).  With
+ * color set and rgb NULL, or color NULL, colour is not updated. */
+int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const float* depth, const float* rgb, const cgx_tsdf_volume* vol,
+                           void* stream);
+
 /* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
  * images do not depend on the tile shape, only the speed does).  For each
  * supported shape (in the order 16x16, 8x8, 16x8, 32x8, 32x16) that fits

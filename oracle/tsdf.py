@@ -30,20 +30,23 @@ from .project import view_arrays
 FRAG = 1e-9
 
 
-def voxel_points(origin, voxel, dims):
-    """World positions of the grid points, index i + nx (j + ny k): (N, 3)."""
+def voxel_points(origin, voxel, dims, index=None):
+    """World positions of the grid points, index i + nx (j + ny k): (N, 3),
+    of every voxel or of the given indices."""
     nx, ny, nz = dims
-    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    idx = np.arange(nx * ny * nz) if index is None else np.asarray(index, np.int64)
+    i, j, k = idx % nx, (idx // nx) % ny, idx // (nx * ny)
     o = np.asarray(origin, np.float64)
-    return np.stack([o[0] + voxel * i.ravel(), o[1] + voxel * j.ravel(), o[2] + voxel * k.ravel()], 1)
+    return np.stack([o[0] + voxel * i, o[1] + voxel * j, o[2] + voxel * k], 1)
 
 
-def integrate(origin, voxel, dims, trunc, views, depth, rgb=None, state=None):
+def integrate(origin, voxel, dims, trunc, views, depth, rgb=None, state=None, voxels=None):
     """Fuse the views in order.  depth: list of (H*W,) z-depth maps; rgb:
     list of (3, H*W) planar images or None.  state: (T, W, C) to continue
-    from (C (3, N)), default T = 1, W = 0, C = 0.  Returns (T, W, C,
-    fragile) with fragile a bool per voxel."""
-    X = voxel_points(origin, float(voxel), dims)
+    from (C (3, N)), default T = 1, W = 0, C = 0.  voxels: optional indices
+    of the voxels to compute (each voxel is independent), N = their count.
+    Returns (T, W, C, fragile) with fragile a bool per voxel."""
+    X = voxel_points(origin, float(voxel), dims, voxels)
     N = X.shape[0]
     if state is None:
         T, Wt, C = np.ones(N), np.zeros(N), np.zeros((3, N))

@@ -64,6 +64,12 @@ class cgx_grads(C.Structure):
                                           "F", "W1", "b1", "W2", "b2")]
 
 
+class cgx_tsdf_volume(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("voxel", C.c_float), ("trunc", C.c_float),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("tsdf", C.c_void_p), ("weight", C.c_void_p), ("color", C.c_void_p)]
+
+
 class cgx_capacity(C.Structure):
     _fields_ = [("max_rows", C.c_int64), ("max_splats", C.c_int64), ("max_pairs", C.c_int64)]
 
@@ -128,6 +134,9 @@ def load_library(path: str = LIB_PATH):
                                               C.c_size_t, P, P, P]),
         "cgx_depth_prior_filter": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
                                                C.POINTER(C.c_int32), C.c_float, P, P]),
+        "cgx_tsdf_init": (C.c_int32, [P, C.POINTER(cgx_tsdf_volume), P]),
+        "cgx_tsdf_integrate": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
+                                           C.POINTER(cgx_tsdf_volume), P]),
         "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
                                             C.c_size_t, C.POINTER(cgx_images),
@@ -343,6 +352,36 @@ def cgx_depth_prior_filter(ctx, views, depth, nearby, tau, filtered, scale_shift
     rc = lib.cgx_depth_prior_filter(ctx, va, len(views), _ptr(depth), _ptr(scale_shift), nb, float(tau),
                                     _ptr(filtered), _stream())
     _check(ctx, rc, "cgx_depth_prior_filter")
+
+
+def make_volume(vol: dict) -> cgx_tsdf_volume:
+    """vol: origin (3 floats), voxel, trunc, dims (nx, ny, nz), device
+    float32 tensors tsdf (N), weight (N) and color (3, N) or None."""
+    v = cgx_tsdf_volume()
+    for k in range(3):
+        v.origin[k] = float(vol["origin"][k])
+    v.voxel = float(vol["voxel"])
+    v.trunc = float(vol["trunc"])
+    v.nx, v.ny, v.nz = (int(x) for x in vol["dims"])
+    v.tsdf = vol["tsdf"].data_ptr()
+    v.weight = vol["weight"].data_ptr()
+    v.color = vol["color"].data_ptr() if vol.get("color") is not None else None
+    return v
+
+
+def cgx_tsdf_init(ctx, vol):
+    lib = load_library()
+    rc = lib.cgx_tsdf_init(ctx, C.byref(make_volume(vol)), _stream())
+    _check(ctx, rc, "cgx_tsdf_init")
+
+
+def cgx_tsdf_integrate(ctx, views, depth, rgb, vol):
+    """Fuse the views' packed z-depth (and planar rgb, or None) into vol."""
+    lib = load_library()
+    va = make_views(views)
+    rc = lib.cgx_tsdf_integrate(ctx, va, len(views), _ptr(depth), _ptr(rgb), C.byref(make_volume(vol)),
+                                _stream())
+    _check(ctx, rc, "cgx_tsdf_integrate")
 
 
 TILE_SHAPES = [(16, 16), (8, 8), (16, 8), (32, 8), (32, 16)]

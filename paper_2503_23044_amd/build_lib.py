@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgx.so")
 SOURCES = ["api.hip", "k_util.hip", "k_sort.hip", "k_explicit.hip", "k_anchor.hip", "k_raster.hip",
-           "k_loss.hip", "k_depth.hip"]
+           "k_loss.hip", "k_depth.hip", "k_tsdf.hip"]
 ARCH = os.environ.get("CGX_OFFLOAD_ARCH", "gfx950")
 
 

@@ -918,6 +918,86 @@ int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_vi
   return CGX_OK;
 }
 
+static int32_t check_volume(cgx_ctx* ctx, const cgx_tsdf_volume* vol, int& n) {
+  if (!vol) return fail(ctx, CGX_ERR_INVALID_ARG, "volume is NULL");
+  if (!vol->tsdf || !vol->weight) return fail(ctx, CGX_ERR_INVALID_ARG, "tsdf and weight are required");
+  if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "grid %d x %d x %d", vol->nx, vol->ny, vol->nz);
+  const int64_t N = (int64_t)vol->nx * vol->ny * vol->nz;
+  if (N > (int64_t)INT32_MAX) return fail(ctx, CGX_ERR_INVALID_ARG, "grid has 2^31 voxels or more");
+  if (!(vol->voxel > 0.f) || !std::isfinite(vol->voxel) || !(vol->trunc > 0.f) ||
+      !std::isfinite(vol->trunc))
+    return fail(ctx, CGX_ERR_INVALID_ARG, "voxel and trunc must be finite and > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(vol->origin[k])) return fail(ctx, CGX_ERR_INVALID_ARG, "origin not finite");
+  n = (int)N;
+  return CGX_OK;
+}
+
+int32_t cgx_tsdf_init(cgx_ctx* ctx, const cgx_tsdf_volume* vol, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int n = 0;
+  int32_t rc = check_volume(ctx, vol, n);
+  if (rc) return rc;
+  rc = set_device(ctx);
+  if (rc) return rc;
+  launch_tsdf_init(n, vol->tsdf, vol->weight, vol->color, (hipStream_t)stream);
+  HIP_OK(ctx, hipGetLastError());
+  return CGX_OK;
+}
+
+int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                           const float* depth, const float* rgb, const cgx_tsdf_volume* vol,
+                           void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_views(ctx, views, n_views);
+  if (rc) return rc;
+  int n = 0;
+  rc = check_volume(ctx, vol, n);
+  if (rc) return rc;
+  if (!depth) return fail(ctx, CGX_ERR_INVALID_ARG, "depth is NULL");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  std::vector<HostCam> hc;
+  depth_cams(views, n_views, hc);
+  const double o[3] = {vol->origin[0], vol->origin[1], vol->origin[2]};
+  const double dv = vol->voxel;
+  float* color = rgb ? vol->color : nullptr;
+  for (int first = 0; first < n_views; first += kTsdfGroup) {
+    const int count = std::min(kTsdfGroup, n_views - first);
+    TsdfPack P;
+    memset(&P, 0, sizeof(P));
+    for (int i = 0; i < count; ++i) {
+      const HostCam& h = hc[first + i];
+      TsdfCam& c = P.v[i];
+      // camera point of voxel (i, j, k): (R dv) (i, j, k) + (R o + t); then K
+      double M[9], m[3];
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) M[3 * r + q] = h.R[3 * r + q] * dv;
+        m[r] = h.R[3 * r + 0] * o[0] + h.R[3 * r + 1] * o[1] + h.R[3 * r + 2] * o[2] + h.t[r];
+      }
+      for (int q = 0; q < 3; ++q) {
+        c.A[q] = h.fx * M[q] + h.cx * M[6 + q];
+        c.A[3 + q] = h.fy * M[3 + q] + h.cy * M[6 + q];
+        c.A[6 + q] = M[6 + q];
+      }
+      c.b[0] = h.fx * m[0] + h.cx * m[2];
+      c.b[1] = h.fy * m[1] + h.cy * m[2];
+      c.b[2] = m[2];
+      c.zn = h.zn;
+      c.Wd = h.W;
+      c.Hd = h.H;
+      c.W = h.W;
+      c.H = h.H;
+      c.pix_off = (int32_t)h.off;
+    }
+    launch_tsdf_integrate(P, count, vol->nx, vol->ny, n, (double)vol->trunc, depth, rgb, vol->tsdf,
+                          vol->weight, color, (hipStream_t)stream);
+  }
+  HIP_OK(ctx, hipGetLastError());
+  return CGX_OK;
+}
+
 int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                             const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
                             size_t workspace_bytes, const cgx_images* target,

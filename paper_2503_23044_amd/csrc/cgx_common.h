@@ -409,4 +409,20 @@ void launch_depth_filter(const FilterPack& cams, int first, int count, int max_p
                          const float* depth, const double* st, double tau2, float* out,
                          hipStream_t s);
 
+// TSDF fusion (Sec. 4): view v's camera folded with the voxel grid on the
+// host: K (R (origin + voxel (i, j, k)) + t) = A (i, j, k) + b (float64)
+struct TsdfCam {
+  double A[9], b[3];
+  double zn, Wd, Hd;
+  int32_t W, H, pix_off, pad;
+};
+constexpr int kTsdfGroup = 16;
+struct TsdfPack {
+  TsdfCam v[kTsdfGroup];
+};
+void launch_tsdf_init(int n, float* tsdf, float* weight, float* color, hipStream_t s);
+void launch_tsdf_integrate(const TsdfPack& cams, int count, int nx, int ny, int n, double mu,
+                           const float* depth, const float* rgb, float* tsdf, float* weight,
+                           float* color, hipStream_t s);
+
 }  // namespace cgx

@@ -1,0 +1,168 @@
+// Projective TSDF fusion of rendered depth and colour (Sec. 4, mesh
+// reconstruction, after the cited 3DMatch fusion): per voxel and view, the
+// signed distance d - z between the rendered z-depth d at the pixel the
+// voxel projects into and the voxel's own depth z, truncated to f =
+// min(1, (d - z) / mu), is averaged into the voxel with weight 1 when
+// d - z > -mu (voxels further behind the surface are occluded); colour is
+// averaged the same way.
+//
+// One thread per voxel, index i + nx (j + ny k), so that a wave walks a
+// row of voxels whose projections are neighbouring pixels.  All views of a
+// launch (up to 16) are applied in order to the voxel's state held in
+// float64 registers: the volume crosses HBM once per launch, not once per
+// view, and a voxel that no view updates is not written back.  Views are
+// taken 8 at a time in stages (projections, all depth gathers, all colour
+// gathers of the updating views, then the averages in order), so that a
+// wave waits for two memory round trips per 8 views instead of two per
+// view.
+//
+// The host composes, in float64, each view's intrinsics, rotation and the
+// voxel grid into one 3x3 matrix and offset: K (R (origin + voxel (i, j,
+// k)) + t) = A (i, j, k) + b, whose third component is the voxel's depth.
+// Against the camera-by-camera evaluation this moves a projection by
+// ~1e-12 px, so a decision (in front, inside, the pixel, d - z > -mu) can
+// differ only that close to its bound.  The update itself uses true
+// float64 divisions, as the running average is defined.
+#include "cgx_common.h"
+
+#pragma clang fp contract(off)
+
+namespace cgx {
+
+constexpr int kTsdfThreads = 256;
+constexpr int kTsdfStage = 8;
+constexpr double kTsdfInf = __builtin_inf();
+
+__device__ __forceinline__ double recip_refined(double z) {
+  double r = __builtin_amdgcn_rcp(z);
+  double e = fma(-z, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-z, r, 1.0);
+  return fma(r, e, r);
+}
+
+__global__ __launch_bounds__(kTsdfThreads) void k_tsdf_init(int n, float* __restrict__ tsdf,
+                                                            float* __restrict__ weight,
+                                                            float* __restrict__ color) {
+  const int i = blockIdx.x * kTsdfThreads + threadIdx.x;
+  if (i >= n) return;
+  tsdf[i] = 1.0f;
+  weight[i] = 0.0f;
+  if (color) {
+    color[i] = 0.0f;
+    color[(size_t)n + i] = 0.0f;
+    color[2 * (size_t)n + i] = 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate(
+    TsdfPack cams, int count, int nx, int ny, int n, double mu, const float* __restrict__ depth,
+    const float* __restrict__ rgb, float* __restrict__ tsdf, float* __restrict__ weight,
+    float* __restrict__ color) {
+  const int idx = blockIdx.x * kTsdfThreads + threadIdx.x;
+  if (idx >= n) return;
+  const int row = idx / nx;
+  const double gi = (double)(idx - row * nx), gj = (double)(row % ny), gk = (double)(row / ny);
+  double T = tsdf[idx], Wt = weight[idx];
+  const bool col = color != nullptr;
+  double C0 = 0.0, C1 = 0.0, C2 = 0.0;
+  if (col) {
+    C0 = color[idx];
+    C1 = color[(size_t)n + idx];
+    C2 = color[2 * (size_t)n + idx];
+  }
+  bool any = false;
+  // views in chunks of kTsdfStage: all depth gathers of a chunk in flight,
+  // then all colour gathers of the views that update, then the running
+  // averages in view order (two memory round trips per chunk, not per view)
+  for (int v0 = 0; v0 < count; v0 += kTsdfStage) {
+    int pix[kTsdfStage];
+    double zs[kTsdfStage];
+    float dv[kTsdfStage];
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      const int v = v0 + s;
+      pix[s] = -1;
+      zs[s] = 0.0;
+      if (v < count) {
+        const TsdfCam& c = cams.v[v];
+        const double z = fma(c.A[6], gi, fma(c.A[7], gj, fma(c.A[8], gk, c.b[2])));
+        const double h0 = fma(c.A[0], gi, fma(c.A[1], gj, fma(c.A[2], gk, c.b[0])));
+        const double h1 = fma(c.A[3], gi, fma(c.A[4], gj, fma(c.A[5], gk, c.b[1])));
+        const bool front = z > c.zn;
+        const double r = recip_refined(front ? z : 1.0);
+        const double u = h0 * r, w = h1 * r;
+        const bool inside = front && u >= 0.0 && u < c.Wd && w >= 0.0 && w < c.Hd;
+        pix[s] = inside ? (int)floor(w) * c.W + (int)floor(u) : -1;
+        zs[s] = z;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      const int v = v0 + s;
+      dv[s] = 0.0f;
+      if (v < count && pix[s] >= 0) dv[s] = depth[(size_t)cams.v[v].pix_off + pix[s]];
+    }
+    // observations that update: diff = d - z > -mu with a finite d > 0
+    double fs[kTsdfStage];
+    unsigned upd = 0;
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      const double d = (double)dv[s];
+      const double diff = d - zs[s];
+      fs[s] = fmin(1.0, diff / mu);
+      if (pix[s] >= 0 && d > 0.0 && d < kTsdfInf && diff > -mu) upd |= 1u << s;
+    }
+    float cr[kTsdfStage], cg[kTsdfStage], cb[kTsdfStage];
+    if (col) {
+#pragma unroll
+      for (int s = 0; s < kTsdfStage; ++s) {
+        cr[s] = cg[s] = cb[s] = 0.0f;
+        if (upd & (1u << s)) {
+          const TsdfCam& c = cams.v[v0 + s];
+          const float* src = rgb + 3 * (size_t)c.pix_off;
+          const size_t hw = (size_t)c.W * c.H;
+          cr[s] = src[pix[s]];
+          cg[s] = src[hw + pix[s]];
+          cb[s] = src[2 * hw + pix[s]];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      if (!(upd & (1u << s))) continue;
+      const double w1 = Wt + 1.0;
+      T = (T * Wt + fs[s]) / w1;
+      if (col) {
+        C0 = (C0 * Wt + (double)cr[s]) / w1;
+        C1 = (C1 * Wt + (double)cg[s]) / w1;
+        C2 = (C2 * Wt + (double)cb[s]) / w1;
+      }
+      Wt = w1;
+    }
+    any = any || upd != 0;
+  }
+  if (!any) return;
+  tsdf[idx] = (float)T;
+  weight[idx] = (float)Wt;
+  if (col) {
+    color[idx] = (float)C0;
+    color[(size_t)n + idx] = (float)C1;
+    color[2 * (size_t)n + idx] = (float)C2;
+  }
+}
+
+void launch_tsdf_init(int n, float* tsdf, float* weight, float* color, hipStream_t s) {
+  if (n > 0)
+    k_tsdf_init<<<(n + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(n, tsdf, weight, color);
+}
+
+void launch_tsdf_integrate(const TsdfPack& cams, int count, int nx, int ny, int n, double mu,
+                           const float* depth, const float* rgb, float* tsdf, float* weight,
+                           float* color, hipStream_t s) {
+  if (n > 0 && count > 0)
+    k_tsdf_integrate<<<(n + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(
+        cams, count, nx, ny, n, mu, depth, rgb, tsdf, weight, color);
+}
+
+}  // namespace cgx

@@ -286,6 +286,25 @@ class Renderer:
         B.cgx_depth_prior_filter(self.ctx, views, aligned, nearby, tau, filtered)
         return filtered, aligned, st
 
+    def tsdf_volume(self, origin, voxel, dims, trunc, color=True):
+        """An empty TSDF volume (Sec. 4 mesh reconstruction): a dict of the
+        grid and its device arrays tsdf = 1, weight = 0, color = 0 (3, N)."""
+        dev = f"cuda:{self.device}"
+        n = int(dims[0]) * int(dims[1]) * int(dims[2])
+        vol = dict(origin=tuple(float(x) for x in origin), voxel=float(voxel), trunc=float(trunc),
+                   dims=tuple(int(x) for x in dims),
+                   tsdf=torch.empty(n, dtype=torch.float32, device=dev),
+                   weight=torch.empty(n, dtype=torch.float32, device=dev),
+                   color=torch.empty(3, n, dtype=torch.float32, device=dev) if color else None)
+        B.cgx_tsdf_init(self.ctx, vol)
+        return vol
+
+    def tsdf_integrate(self, views, depth, vol, rgb=None):
+        """Fuse the views' rendered z-depth (packed float32, e.g. out["depth"]
+        of forward) and optional planar rgb into vol, in order."""
+        B.cgx_tsdf_integrate(self.ctx, views, depth, rgb, vol)
+        return vol
+
     def info(self):
         return B.cgx_read_info(self.ctx, self.ws)
 

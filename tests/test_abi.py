@@ -203,3 +203,36 @@ def test_depth_prior_entry_points_reject_bad_arguments(B):
         assert rc == B.CGX_ERR_INVALID_ARG
     finally:
         B.cgx_destroy(ctx)
+
+
+def test_tsdf_entry_points_reject_bad_arguments(B):
+    lib = B.load_library()
+    ctx = B.cgx_create(0, 16, 16)
+    try:
+        va = B.make_views([_view()])
+        fake = C.c_void_p(4096)                      # never dereferenced: every call below fails first
+
+        def vol(**kw):
+            v = B.cgx_tsdf_volume()
+            d = dict(voxel=0.1, trunc=0.3, nx=4, ny=5, nz=6, tsdf=4096, weight=8192, color=None)
+            d.update(kw)
+            for k, x in d.items():
+                setattr(v, k, x)
+            return v
+
+        assert lib.cgx_tsdf_init(ctx, None, None) == B.CGX_ERR_INVALID_ARG
+        for bad in (dict(tsdf=None), dict(weight=None), dict(nx=0), dict(nz=-1), dict(voxel=0.0),
+                    dict(trunc=-1.0), dict(trunc=float("inf")), dict(nx=2048, ny=2048, nz=512)):
+            v = vol(**bad)
+            assert lib.cgx_tsdf_init(ctx, C.byref(v), None) == B.CGX_ERR_INVALID_ARG, bad
+            assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        v = vol()
+        v.origin[1] = float("nan")
+        assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        assert b"origin" in lib.cgx_last_error(ctx)
+        v = vol()
+        assert lib.cgx_tsdf_integrate(ctx, va, 1, None, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        assert b"depth" in lib.cgx_last_error(ctx)
+        assert lib.cgx_tsdf_integrate(ctx, va, 0, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+    finally:
+        B.cgx_destroy(ctx)

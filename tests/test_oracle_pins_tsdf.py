@@ -114,6 +114,12 @@ def test_batching_does_not_matter():
     b = tsdf.integrate(origin, voxel, dims, 0.25, views[1:], depth[1:], rgb[1:], state=a[:3])
     for x, y in zip(full[:3], b[:3]):
         np.testing.assert_array_equal(x, y)
+    # each voxel is independent: a subset gives the same values
+    idx = np.random.default_rng(4).choice(int(np.prod(dims)), 500, replace=False)
+    sub = tsdf.integrate(origin, voxel, dims, 0.25, views, depth, rgb, voxels=idx)
+    for x, y in zip(full[:2], sub[:2]):
+        np.testing.assert_array_equal(x[idx], y)
+    np.testing.assert_array_equal(full[2][:, idx], sub[2])
 
 
 def test_brute_force_with_homogeneous_cameras():
