@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 4
+#define CGX_ABI_VERSION 5
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -374,13 +374,21 @@ int32_t cgx_tsdf_init(cgx_ctx* ctx, const cgx_tsdf_volume* vol, void* stream);
  * Up to 16 views are applied per pass over the volume with the state in
  * float64 registers (rounded to float32 when stored); the result does not
  * depend on the batching beyond that rounding.  Decisions are float64 on a
- * projection composed on the host.  Errors: CGX_ERR_INVALID_ARG for a bad
+ * projection composed on the host.  `workspace` (device, may be NULL):
+ * see cgx_tsdf_workspace_size.  Errors: CGX_ERR_INVALID_ARG for a bad
  * view, a NULL tsdf / weight / depth, or a bad grid (sizes < 1,
  * N >= 2^31, voxel or trunc not > 0 and finite, non-finite origin).  With
  * color set and rgb NULL, or color NULL, colour is not updated. */
 int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                            const float* depth, const float* rgb, const cgx_tsdf_volume* vol,
-                           void* stream);
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of the optional workspace of cgx_tsdf_integrate: 16 per pixel of
+ * the batch.  Given a (16-byte aligned) workspace that large, and colour,
+ * each pass first interleaves depth and colour into one 16-byte texel per
+ * pixel, so that a voxel reads one texel per view instead of four separate
+ * values; the results are identical.  Host arithmetic only. */
+size_t cgx_tsdf_workspace_size(const cgx_view* views, int32_t n_views);
 
 /* Tile-shape autotuner (batched rendering of uneven views, Sec. 3.3; the
  * images do not depend on the tile shape, only the speed does).  For each

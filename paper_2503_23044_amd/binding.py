@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 4
+CGX_ABI_VERSION = 5
 OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
@@ -136,7 +136,8 @@ def load_library(path: str = LIB_PATH):
                                                C.POINTER(C.c_int32), C.c_float, P, P]),
         "cgx_tsdf_init": (C.c_int32, [P, C.POINTER(cgx_tsdf_volume), P]),
         "cgx_tsdf_integrate": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
-                                           C.POINTER(cgx_tsdf_volume), P]),
+                                           C.POINTER(cgx_tsdf_volume), P, C.c_size_t, P]),
+        "cgx_tsdf_workspace_size": (C.c_size_t, [C.POINTER(cgx_view), C.c_int32]),
         "cgx_tune_tile_shape": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
                                             C.c_size_t, C.POINTER(cgx_images),
@@ -375,12 +376,18 @@ def cgx_tsdf_init(ctx, vol):
     _check(ctx, rc, "cgx_tsdf_init")
 
 
-def cgx_tsdf_integrate(ctx, views, depth, rgb, vol):
-    """Fuse the views' packed z-depth (and planar rgb, or None) into vol."""
+def cgx_tsdf_workspace_size(views):
+    return int(load_library().cgx_tsdf_workspace_size(make_views(views), len(views)))
+
+
+def cgx_tsdf_integrate(ctx, views, depth, rgb, vol, ws=None):
+    """Fuse the views' packed z-depth (and planar rgb, or None) into vol;
+    ws (device, cgx_tsdf_workspace_size bytes) enables the texel path."""
     lib = load_library()
     va = make_views(views)
+    nbytes = ws.numel() * ws.element_size() if ws is not None else 0
     rc = lib.cgx_tsdf_integrate(ctx, va, len(views), _ptr(depth), _ptr(rgb), C.byref(make_volume(vol)),
-                                _stream())
+                                _ptr(ws), nbytes, _stream())
     _check(ctx, rc, "cgx_tsdf_integrate")
 
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "cgx_common.h"
+#include "cgx_fusion.h"
 
 using namespace cgx;
 
@@ -946,9 +947,17 @@ int32_t cgx_tsdf_init(cgx_ctx* ctx, const cgx_tsdf_volume* vol, void* stream) {
   return CGX_OK;
 }
 
+size_t cgx_tsdf_workspace_size(const cgx_view* views, int32_t n_views) {
+  if (!views || n_views < 1) return 0;
+  size_t px = 0;
+  for (int i = 0; i < n_views; ++i)
+    px += (size_t)std::max(views[i].width, 0) * (size_t)std::max(views[i].height, 0);
+  return 16 * px;
+}
+
 int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                            const float* depth, const float* rgb, const cgx_tsdf_volume* vol,
-                           void* stream) {
+                           void* workspace, size_t workspace_bytes, void* stream) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   int32_t rc = check_views(ctx, views, n_views);
   if (rc) return rc;
@@ -963,6 +972,10 @@ int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
   const double o[3] = {vol->origin[0], vol->origin[1], vol->origin[2]};
   const double dv = vol->voxel;
   float* color = rgb ? vol->color : nullptr;
+  // texel path: depth and colour interleaved, one gather per (voxel, view)
+  const bool texel = color && workspace && workspace_bytes >= cgx_tsdf_workspace_size(views, n_views);
+  if (texel && (reinterpret_cast<uintptr_t>(workspace) & 15) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 16-byte aligned");
   for (int first = 0; first < n_views; first += kTsdfGroup) {
     const int count = std::min(kTsdfGroup, n_views - first);
     TsdfPack P;
@@ -991,8 +1004,17 @@ int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
       c.H = h.H;
       c.pix_off = (int32_t)h.off;
     }
-    launch_tsdf_integrate(P, count, vol->nx, vol->ny, n, (double)vol->trunc, depth, rgb, vol->tsdf,
-                          vol->weight, color, (hipStream_t)stream);
+    if (texel) {
+      float4* tx = reinterpret_cast<float4*>(workspace);
+      const int64_t px = hc[first + count - 1].off + (int64_t)hc[first + count - 1].W *
+                         hc[first + count - 1].H - hc[first].off;
+      launch_tsdf_pack((int)px, depth, rgb, P, count, tx, (hipStream_t)stream);
+      launch_tsdf_integrate_texels(P, count, vol->nx, vol->ny, n, (double)vol->trunc, tx,
+                                   vol->tsdf, vol->weight, color, (hipStream_t)stream);
+    } else {
+      launch_tsdf_integrate(P, count, vol->nx, vol->ny, n, (double)vol->trunc, depth, rgb,
+                            vol->tsdf, vol->weight, color, (hipStream_t)stream);
+    }
   }
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;

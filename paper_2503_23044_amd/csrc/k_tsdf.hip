@@ -23,7 +23,7 @@
 // ~1e-12 px, so a decision (in front, inside, the pixel, d - z > -mu) can
 // differ only that close to its bound.  The update itself uses true
 // float64 divisions, as the running average is defined.
-#include "cgx_common.h"
+#include "cgx_fusion.h"
 
 #pragma clang fp contract(off)
 
@@ -150,6 +150,102 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate(
     color[(size_t)n + idx] = (float)C1;
     color[2 * (size_t)n + idx] = (float)C2;
   }
+}
+
+// (d, r, g, b) texels of the views of one pass; a thread per pixel of the
+// pass's views (their pixels are contiguous in the packed layout)
+__global__ __launch_bounds__(kTsdfThreads) void k_tsdf_pack(int first_pix, int n_pixels,
+                                                            TsdfPack cams, int count,
+                                                            const float* __restrict__ depth,
+                                                            const float* __restrict__ rgb,
+                                                            float4* __restrict__ texels) {
+  const int p = first_pix + blockIdx.x * kTsdfThreads + threadIdx.x;
+  if (p >= first_pix + n_pixels) return;
+  int v = 0;
+  while (v + 1 < count && p >= cams.v[v + 1].pix_off) ++v;
+  const TsdfCam& c = cams.v[v];
+  const int q = p - c.pix_off;
+  const size_t hw = (size_t)c.W * c.H;
+  const float* src = rgb + 3 * (size_t)c.pix_off;
+  texels[p] = make_float4(depth[p], src[q], src[hw + q], src[2 * hw + q]);
+}
+
+// As k_tsdf_integrate with the colour always on, gathering one texel per
+// (voxel, view) instead of a depth and three colour planes.
+__global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate_texels(
+    TsdfPack cams, int count, int nx, int ny, int n, double mu, const float4* __restrict__ texels,
+    float* __restrict__ tsdf, float* __restrict__ weight, float* __restrict__ color) {
+  const int idx = blockIdx.x * kTsdfThreads + threadIdx.x;
+  if (idx >= n) return;
+  const int row = idx / nx;
+  const double gi = (double)(idx - row * nx), gj = (double)(row % ny), gk = (double)(row / ny);
+  double T = tsdf[idx], Wt = weight[idx];
+  double C0 = color[idx], C1 = color[(size_t)n + idx], C2 = color[2 * (size_t)n + idx];
+  bool any = false;
+  for (int v0 = 0; v0 < count; v0 += kTsdfStage) {
+    int pix[kTsdfStage];
+    double zs[kTsdfStage];
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      const int v = v0 + s;
+      pix[s] = -1;
+      zs[s] = 0.0;
+      if (v < count) {
+        const TsdfCam& c = cams.v[v];
+        const double z = fma(c.A[6], gi, fma(c.A[7], gj, fma(c.A[8], gk, c.b[2])));
+        const double h0 = fma(c.A[0], gi, fma(c.A[1], gj, fma(c.A[2], gk, c.b[0])));
+        const double h1 = fma(c.A[3], gi, fma(c.A[4], gj, fma(c.A[5], gk, c.b[1])));
+        const bool front = z > c.zn;
+        const double r = recip_refined(front ? z : 1.0);
+        const double u = h0 * r, w = h1 * r;
+        const bool inside = front && u >= 0.0 && u < c.Wd && w >= 0.0 && w < c.Hd;
+        pix[s] = inside ? c.pix_off + (int)floor(w) * c.W + (int)floor(u) : -1;
+        zs[s] = z;
+      }
+    }
+    float4 tx[kTsdfStage];
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      tx[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (pix[s] >= 0) tx[s] = texels[pix[s]];
+    }
+#pragma unroll
+    for (int s = 0; s < kTsdfStage; ++s) {
+      const double d = (double)tx[s].x;
+      const double diff = d - zs[s];
+      if (pix[s] >= 0 && d > 0.0 && d < kTsdfInf && diff > -mu) {
+        const double f = fmin(1.0, diff / mu);
+        const double w1 = Wt + 1.0;
+        T = (T * Wt + f) / w1;
+        C0 = (C0 * Wt + (double)tx[s].y) / w1;
+        C1 = (C1 * Wt + (double)tx[s].z) / w1;
+        C2 = (C2 * Wt + (double)tx[s].w) / w1;
+        Wt = w1;
+        any = true;
+      }
+    }
+  }
+  if (!any) return;
+  tsdf[idx] = (float)T;
+  weight[idx] = (float)Wt;
+  color[idx] = (float)C0;
+  color[(size_t)n + idx] = (float)C1;
+  color[2 * (size_t)n + idx] = (float)C2;
+}
+
+void launch_tsdf_pack(int n_pixels, const float* depth, const float* rgb, const TsdfPack& cams,
+                      int count, float4* texels, hipStream_t s) {
+  if (n_pixels > 0 && count > 0)
+    k_tsdf_pack<<<(n_pixels + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(
+        cams.v[0].pix_off, n_pixels, cams, count, depth, rgb, texels);
+}
+
+void launch_tsdf_integrate_texels(const TsdfPack& cams, int count, int nx, int ny, int n, double mu,
+                                  const float4* texels, float* tsdf, float* weight, float* color,
+                                  hipStream_t s) {
+  if (n > 0 && count > 0)
+    k_tsdf_integrate_texels<<<(n + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(
+        cams, count, nx, ny, n, mu, texels, tsdf, weight, color);
 }
 
 void launch_tsdf_init(int n, float* tsdf, float* weight, float* color, hipStream_t s) {

@@ -93,6 +93,7 @@ class Renderer:
         self.ctx = B.cgx_create(device, tile[0], tile[1])
         self.ws = None
         self.depth_ws = None
+        self.tsdf_ws = None
         self.cap = {}
 
     def __del__(self):
@@ -299,10 +300,19 @@ class Renderer:
         B.cgx_tsdf_init(self.ctx, vol)
         return vol
 
-    def tsdf_integrate(self, views, depth, vol, rgb=None):
+    def tsdf_integrate(self, views, depth, vol, rgb=None, texels=True):
         """Fuse the views' rendered z-depth (packed float32, e.g. out["depth"]
-        of forward) and optional planar rgb into vol, in order."""
-        B.cgx_tsdf_integrate(self.ctx, views, depth, rgb, vol)
+        of forward) and optional planar rgb into vol, in order; with colour
+        and texels=True depth and colour are first interleaved into a
+        workspace of 16 bytes per pixel (identical results, fewer gathers)."""
+        ws = None
+        if texels and rgb is not None and vol.get("color") is not None:
+            nbytes = B.cgx_tsdf_workspace_size(views)
+            if self.tsdf_ws is None or self.tsdf_ws.numel() * 16 < nbytes:
+                self.tsdf_ws = torch.empty((nbytes + 15) // 16, 4, dtype=torch.float32,
+                                           device=f"cuda:{self.device}")
+            ws = self.tsdf_ws
+        B.cgx_tsdf_integrate(self.ctx, views, depth, rgb, vol, ws)
         return vol
 
     def info(self):

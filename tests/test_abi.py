@@ -225,14 +225,16 @@ def test_tsdf_entry_points_reject_bad_arguments(B):
                     dict(trunc=-1.0), dict(trunc=float("inf")), dict(nx=2048, ny=2048, nz=512)):
             v = vol(**bad)
             assert lib.cgx_tsdf_init(ctx, C.byref(v), None) == B.CGX_ERR_INVALID_ARG, bad
-            assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+            assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None, 0, None) == B.CGX_ERR_INVALID_ARG
         v = vol()
         v.origin[1] = float("nan")
-        assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        assert lib.cgx_tsdf_integrate(ctx, va, 1, fake, None, C.byref(v), None, 0, None) == B.CGX_ERR_INVALID_ARG
         assert b"origin" in lib.cgx_last_error(ctx)
         v = vol()
-        assert lib.cgx_tsdf_integrate(ctx, va, 1, None, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        assert lib.cgx_tsdf_integrate(ctx, va, 1, None, None, C.byref(v), None, 0, None) == B.CGX_ERR_INVALID_ARG
         assert b"depth" in lib.cgx_last_error(ctx)
-        assert lib.cgx_tsdf_integrate(ctx, va, 0, fake, None, C.byref(v), None) == B.CGX_ERR_INVALID_ARG
+        assert lib.cgx_tsdf_integrate(ctx, va, 0, fake, None, C.byref(v), None, 0, None) == B.CGX_ERR_INVALID_ARG
+        assert lib.cgx_tsdf_workspace_size(va, 1) == 16 * 64 * 48
+        assert lib.cgx_tsdf_workspace_size(None, 1) == 0
     finally:
         B.cgx_destroy(ctx)

@@ -62,6 +62,12 @@ def test_small_uneven_views_match_oracle(rd):
     torch.cuda.synchronize()
     ref = tsdf.integrate(g["origin"], g["voxel"], g["dims"], g["trunc"], views, depth, rgb)
     _compare(vol, ref)
+    # the planar path (no texel workspace) gives the same bits
+    volp = rd.tsdf_volume(g["origin"], g["voxel"], g["dims"], g["trunc"])
+    rd.tsdf_integrate(views, _dev(depth), volp, rgb=_dev(rgb), texels=False)
+    torch.cuda.synchronize()
+    for k in ("tsdf", "weight", "color"):
+        np.testing.assert_array_equal(volp[k].cpu().numpy(), vol[k].cpu().numpy())
     # split into two calls: the same up to the float32 rounding between them
     vol2 = rd.tsdf_volume(g["origin"], g["voxel"], g["dims"], g["trunc"])
     rd.tsdf_integrate(views[:3], _dev(depth[:3]), vol2, rgb=_dev(rgb[:3]))
