@@ -6,8 +6,8 @@
 // d - z > -mu (voxels further behind the surface are occluded); colour is
 // averaged the same way.
 //
-// One thread per voxel, index i + nx (j + ny k), so that a wave walks a
-// row of voxels whose projections are neighbouring pixels.  All views of a
+// One thread per voxel (index i + nx (j + ny k)), a wave per 16 x 2 x 2
+// brick of voxels (see brick_voxel).  All views of a
 // launch (up to 16) are applied in order to the voxel's state held in
 // float64 registers: the volume crosses HBM once per launch, not once per
 // view, and a voxel that no view updates is not written back.  Views are
@@ -21,8 +21,9 @@
 // k)) + t) = A (i, j, k) + b, whose third component is the voxel's depth.
 // Against the camera-by-camera evaluation this moves a projection by
 // ~1e-12 px, so a decision (in front, inside, the pixel, d - z > -mu) can
-// differ only that close to its bound.  The update itself uses true
-// float64 divisions, as the running average is defined.
+// differ only that close to its bound.  The update multiplies by 1 / W'
+// and 1 / mu instead of dividing (within an ulp of float64, far below the
+// float32 the state is stored in).
 #include "cgx_fusion.h"
 
 #pragma clang fp contract(off)
@@ -39,6 +40,28 @@ __device__ __forceinline__ double recip_refined(double z) {
   r = fma(r, e, r);
   e = fma(-z, r, 1.0);
   return fma(r, e, r);
+}
+
+// Voxel of a thread: a block is a 16 x 4 x 4 brick and each wave a
+// 16 x 2 x 2 part of it, so that a wave's 64 voxels project onto a compact
+// patch of every view (fewer distinct cache lines per gather than a row of
+// 64 voxels) while each run of 16 voxels along x stays one 64-byte segment
+// of the state arrays.
+constexpr int kBrickX = 16, kBrickY = 4, kBrickZ = 4;
+__device__ __forceinline__ bool brick_voxel(int nx, int ny, int nz, int& i, int& j, int& k) {
+  const int bx = (nx + kBrickX - 1) / kBrickX, by = (ny + kBrickY - 1) / kBrickY;
+  const int g = blockIdx.x;
+  const int gx = g % bx, gy = (g / bx) % by, gz = g / (bx * by);
+  const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  i = gx * kBrickX + (l & 15);
+  j = gy * kBrickY + (w & 1) * 2 + ((l >> 4) & 1);
+  k = gz * kBrickZ + (w >> 1) * 2 + (l >> 5);
+  return i < nx && j < ny && k < nz;
+}
+
+inline int brick_blocks(int nx, int ny, int nz) {
+  return ((nx + kBrickX - 1) / kBrickX) * ((ny + kBrickY - 1) / kBrickY) *
+         ((nz + kBrickZ - 1) / kBrickZ);
 }
 
 __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_init(int n, float* __restrict__ tsdf,
@@ -59,10 +82,11 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate(
     TsdfPack cams, int count, int nx, int ny, int n, double mu, const float* __restrict__ depth,
     const float* __restrict__ rgb, float* __restrict__ tsdf, float* __restrict__ weight,
     float* __restrict__ color) {
-  const int idx = blockIdx.x * kTsdfThreads + threadIdx.x;
-  if (idx >= n) return;
-  const int row = idx / nx;
-  const double gi = (double)(idx - row * nx), gj = (double)(row % ny), gk = (double)(row / ny);
+  int vi, vj, vk;
+  if (!brick_voxel(nx, ny, n / (nx * ny), vi, vj, vk)) return;
+  const double inv_mu = 1.0 / mu;
+  const int idx = vi + nx * (vj + ny * vk);
+  const double gi = (double)vi, gj = (double)vj, gk = (double)vk;
   double T = tsdf[idx], Wt = weight[idx];
   const bool col = color != nullptr;
   double C0 = 0.0, C1 = 0.0, C2 = 0.0;
@@ -110,7 +134,7 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate(
     for (int s = 0; s < kTsdfStage; ++s) {
       const double d = (double)dv[s];
       const double diff = d - zs[s];
-      fs[s] = fmin(1.0, diff / mu);
+      fs[s] = fmin(1.0, diff * inv_mu);
       if (pix[s] >= 0 && d > 0.0 && d < kTsdfInf && diff > -mu) upd |= 1u << s;
     }
     float cr[kTsdfStage], cg[kTsdfStage], cb[kTsdfStage];
@@ -131,12 +155,12 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate(
 #pragma unroll
     for (int s = 0; s < kTsdfStage; ++s) {
       if (!(upd & (1u << s))) continue;
-      const double w1 = Wt + 1.0;
-      T = (T * Wt + fs[s]) / w1;
+      const double w1 = Wt + 1.0, rw = 1.0 / w1;
+      T = (T * Wt + fs[s]) * rw;
       if (col) {
-        C0 = (C0 * Wt + (double)cr[s]) / w1;
-        C1 = (C1 * Wt + (double)cg[s]) / w1;
-        C2 = (C2 * Wt + (double)cb[s]) / w1;
+        C0 = (C0 * Wt + (double)cr[s]) * rw;
+        C1 = (C1 * Wt + (double)cg[s]) * rw;
+        C2 = (C2 * Wt + (double)cb[s]) * rw;
       }
       Wt = w1;
     }
@@ -175,10 +199,11 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_pack(int first_pix, int n
 __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate_texels(
     TsdfPack cams, int count, int nx, int ny, int n, double mu, const float4* __restrict__ texels,
     float* __restrict__ tsdf, float* __restrict__ weight, float* __restrict__ color) {
-  const int idx = blockIdx.x * kTsdfThreads + threadIdx.x;
-  if (idx >= n) return;
-  const int row = idx / nx;
-  const double gi = (double)(idx - row * nx), gj = (double)(row % ny), gk = (double)(row / ny);
+  int vi, vj, vk;
+  if (!brick_voxel(nx, ny, n / (nx * ny), vi, vj, vk)) return;
+  const double inv_mu = 1.0 / mu;
+  const int idx = vi + nx * (vj + ny * vk);
+  const double gi = (double)vi, gj = (double)vj, gk = (double)vk;
   double T = tsdf[idx], Wt = weight[idx];
   double C0 = color[idx], C1 = color[(size_t)n + idx], C2 = color[2 * (size_t)n + idx];
   bool any = false;
@@ -214,12 +239,12 @@ __global__ __launch_bounds__(kTsdfThreads) void k_tsdf_integrate_texels(
       const double d = (double)tx[s].x;
       const double diff = d - zs[s];
       if (pix[s] >= 0 && d > 0.0 && d < kTsdfInf && diff > -mu) {
-        const double f = fmin(1.0, diff / mu);
-        const double w1 = Wt + 1.0;
-        T = (T * Wt + f) / w1;
-        C0 = (C0 * Wt + (double)tx[s].y) / w1;
-        C1 = (C1 * Wt + (double)tx[s].z) / w1;
-        C2 = (C2 * Wt + (double)tx[s].w) / w1;
+        const double f = fmin(1.0, diff * inv_mu);
+        const double w1 = Wt + 1.0, rw = 1.0 / w1;
+        T = (T * Wt + f) * rw;
+        C0 = (C0 * Wt + (double)tx[s].y) * rw;
+        C1 = (C1 * Wt + (double)tx[s].z) * rw;
+        C2 = (C2 * Wt + (double)tx[s].w) * rw;
         Wt = w1;
         any = true;
       }
@@ -244,7 +269,7 @@ void launch_tsdf_integrate_texels(const TsdfPack& cams, int count, int nx, int n
                                   const float4* texels, float* tsdf, float* weight, float* color,
                                   hipStream_t s) {
   if (n > 0 && count > 0)
-    k_tsdf_integrate_texels<<<(n + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(
+    k_tsdf_integrate_texels<<<brick_blocks(nx, ny, n / (nx * ny)), kTsdfThreads, 0, s>>>(
         cams, count, nx, ny, n, mu, texels, tsdf, weight, color);
 }
 
@@ -257,7 +282,7 @@ void launch_tsdf_integrate(const TsdfPack& cams, int count, int nx, int ny, int 
                            const float* depth, const float* rgb, float* tsdf, float* weight,
                            float* color, hipStream_t s) {
   if (n > 0 && count > 0)
-    k_tsdf_integrate<<<(n + kTsdfThreads - 1) / kTsdfThreads, kTsdfThreads, 0, s>>>(
+    k_tsdf_integrate<<<brick_blocks(nx, ny, n / (nx * ny)), kTsdfThreads, 0, s>>>(
         cams, count, nx, ny, n, mu, depth, rgb, tsdf, weight, color);
 }
 
