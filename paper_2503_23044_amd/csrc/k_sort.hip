@@ -426,6 +426,9 @@ __device__ __forceinline__ uint32_t kth_set_bit(uint32_t lo, uint32_t hi, uint32
   return pos;
 }
 
+constexpr int kEmitPerThread = 4;
+static_assert(256 * kEmitPerThread == kDupPairs, "one group of pairs per thread and block step");
+
 __global__ __launch_bounds__(256) void k_emit_pairs(
     const ViewDev* __restrict__ views, const Splat* __restrict__ splats,
     const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff,
@@ -473,22 +476,46 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
       s_mhi[t] = (uint32_t)(m >> 32);
     }
     __syncthreads();
-    for (uint32_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    // four consecutive pairs per thread (256 x 4 = kDupPairs): one binary
+    // search for the first, a forward walk for the others (every visible
+    // splat has at least one pair), one 16-byte store per array
+    const uint32_t i0 = p0 + kEmitPerThread * threadIdx.x;
+    if (i0 < p1) {
       uint32_t lo = 0, hi = m;
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= i) lo = mid + 1;
+        if (s_off[mid] <= i0) lo = mid + 1;
         else hi = mid;
       }
-      const uint32_t jl = lo > 0 ? lo - 1 : 0;
-      uint32_t k = i - s_off[jl];
-      const uint32_t nxm = s_nx[jl];
-      const uint32_t nx = nxm & 0xFFFF;
-      // a masked box: the k-th kept tile is the k-th set bit (row-major)
-      if (nxm >> 16) k = kth_set_bit(s_mlo[jl], s_mhi[jl], k);
-      const uint32_t ty = k / nx;
-      pkey[i] = s_base[jl] + ty * s_TX[jl] + (k - ty * nx);
-      pval[i] = s_slot[jl];
+      uint32_t jl = lo > 0 ? lo - 1 : 0;
+      uint32_t key[kEmitPerThread], val[kEmitPerThread];
+#pragma unroll
+      for (int q = 0; q < kEmitPerThread; ++q) {
+        const uint32_t i = i0 + q;
+        while (jl + 1 < m && s_off[jl + 1] <= i) ++jl;
+        uint32_t k = i - s_off[jl];
+        const uint32_t nxm = s_nx[jl];
+        const uint32_t nx = nxm & 0xFFFF;
+        // a masked box: the k-th kept tile is the k-th set bit (row-major)
+        if (nxm >> 16) k = kth_set_bit(s_mlo[jl], s_mhi[jl], k);
+        // ty = k / nx: a float estimate (within one for k < 2^22 nx),
+        // corrected to the exact quotient
+        uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)nx));
+        if (ty * nx > k) --ty;
+        else if ((ty + 1) * nx <= k) ++ty;
+        key[q] = s_base[jl] + ty * s_TX[jl] + (k - ty * nx);
+        val[q] = s_slot[jl];
+      }
+      if (i0 + kEmitPerThread <= p1) {
+        *reinterpret_cast<uint4*>(pkey + i0) = make_uint4(key[0], key[1], key[2], key[3]);
+        *reinterpret_cast<uint4*>(pval + i0) = make_uint4(val[0], val[1], val[2], val[3]);
+      } else {
+        for (int q = 0; q < kEmitPerThread; ++q)
+          if (i0 + q < p1) {
+            pkey[i0 + q] = key[q];
+            pval[i0 + q] = val[q];
+          }
+      }
     }
     __syncthreads();
   }
