@@ -6,7 +6,7 @@
 // second view's RGB is accumulated into a caller buffer that then seeds the
 // backward raster.
 //
-// One wave per (pair, patch): lane j < 49 owns patch pixel (j % 7 - 3,
+// One wave per (pair, patch), 16 per workgroup: lane j < 49 owns patch pixel (j % 7 - 3,
 // j / 7 - 3).  The homography is built per wave in float64 from the two
 // cameras: with X_s = R_rel X_r + t_rel and the plane n . X = -d of the
 // reference frame, H = K_s (R_rel - t_rel n^T / d) K_r^-1 on pixel centres.
@@ -35,28 +35,29 @@ __device__ __forceinline__ double gray_at(const float* rgb, size_t pv, uint32_t 
          3.0;
 }
 
-__global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ views,
-                                                    const float* __restrict__ rgb,
-                                                    const float* __restrict__ normal,
-                                                    const float* __restrict__ plane_d,
-                                                    const int32_t* __restrict__ centres,
-                                                    int n_patch, int n_pairs, float scale,
-                                                    float* __restrict__ grad_rgb,
-                                                    float* __restrict__ loss) {
-  const int lane = threadIdx.x;
-  const int pair = blockIdx.x / n_patch;
-  if (pair >= n_pairs) return;
+// patches per workgroup, one wave each; their loss terms are summed in LDS
+// and added with one atomic per workgroup (same-address atomics serialise)
+constexpr int kNccWaves = 16;
+
+// one patch on one wave: adds its RGB gradient, returns its loss term (0
+// for a skipped patch) on every lane
+__device__ float ncc_patch(const ViewDev* __restrict__ views, const float* __restrict__ rgb,
+                           const float* __restrict__ normal, const float* __restrict__ plane_d,
+                           const int32_t* __restrict__ centres, int n_patch, int n_pairs,
+                           float scale, float* __restrict__ grad_rgb, int patch, int lane) {
+  const int pair = patch / n_patch;
+  if (pair >= n_pairs) return 0.0f;
   const ViewDev& Vs = views[2 * pair];
   const ViewDev& Vr = views[2 * pair + 1];
-  const int cx = centres[2 * blockIdx.x], cy = centres[2 * blockIdx.x + 1];
+  const int cx = centres[2 * patch], cy = centres[2 * patch + 1];
   constexpr int h = kPatch / 2;
-  if (cx - h < 0 || cy - h < 0 || cx + h >= Vr.W || cy + h >= Vr.H) return;
-  if (Vs.W < 2 || Vs.H < 2) return;
+  if (cx - h < 0 || cy - h < 0 || cx + h >= Vr.W || cy + h >= Vr.H) return 0.0f;
+  if (Vs.W < 2 || Vs.H < 2) return 0.0f;
   const uint32_t HWr = (uint32_t)Vr.W * (uint32_t)Vr.H, HWs = (uint32_t)Vs.W * (uint32_t)Vs.H;
   const size_t pvr = (size_t)Vr.pix_off, pvs = (size_t)Vs.pix_off;
   const uint32_t pc = (uint32_t)cy * (uint32_t)Vr.W + (uint32_t)cx;
   const double d = plane_d[pvr + pc];
-  if (!(d > 0.0)) return;
+  if (!(d > 0.0)) return 0.0f;
   const double n[3] = {normal[3 * pvr + pc], normal[3 * pvr + HWr + pc], normal[3 * pvr + 2 * HWr + pc]};
 
   // H = K_s (R_rel - t_rel n^T / d) K_r^-1, R_rel = R_s R_r^T, t_rel = t_s - R_rel t_r
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ 
     sy = ((double)Vs.fy * X1 / X2 + Vs.cy) - 0.5;
     ok = sx >= 0.0 && sy >= 0.0 && sx <= (double)(Vs.W - 1) && sy <= (double)(Vs.H - 1);
   }
-  if (__ballot(mine && !ok) != 0) return;
+  if (__ballot(mine && !ok) != 0) return 0.0f;
 
   double a = 0.0, b = 0.0;
   if (mine) {
@@ -108,7 +109,6 @@ __global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ 
   const double sab = wave_sum(A * Bc), saa = wave_sum(A * A), sbb = wave_sum(Bc * Bc);
   const double den = sqrt(saa * sbb + kNccEps);
   const double ncc = sab / den;
-  if (lane == 0 && loss) atomic_add_f32(loss, (float)(scale * (1.0 - ncc)));
   if (mine) {
     // d NCC / d a_j = B_j / den - sab sbb A_j / den^3 (the B's sum to zero)
     const double dn = Bc / den - sab * sbb * A / (den * den * den);
@@ -120,6 +120,28 @@ __global__ __launch_bounds__(kWave) void k_ncc_loss(const ViewDev* __restrict__ 
       atomic_add_f32(grad_rgb + 3 * pvr + 2 * HWr + p, ga);
     }
   }
+  return (float)(scale * (1.0 - ncc));
+}
+
+__global__ __launch_bounds__(kWave * kNccWaves) void k_ncc_loss(const ViewDev* __restrict__ views,
+                                                                const float* __restrict__ rgb,
+                                                                const float* __restrict__ normal,
+                                                                const float* __restrict__ plane_d,
+                                                                const int32_t* __restrict__ centres,
+                                                                int n_patch, int n_pairs, float scale,
+                                                                float* __restrict__ grad_rgb,
+                                                                float* __restrict__ loss) {
+  __shared__ float part[kNccWaves];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const float l = ncc_patch(views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad_rgb,
+                            blockIdx.x * kNccWaves + wave, lane);
+  if (lane == 0) part[wave] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) {
+    float sum = 0.0f;
+    for (int w = 0; w < kNccWaves; ++w) sum += part[w];
+    if (sum != 0.0f) atomic_add_f32(loss, sum);
+  }
 }
 
 void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const float* normal,
@@ -128,7 +150,8 @@ void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const 
   const int n_pairs = n_views / 2;
   if (n_pairs == 0 || n_patch == 0) return;
   const float scale = weight / ((float)n_pairs * (float)n_patch);
-  hipLaunchKernelGGL(k_ncc_loss, dim3((uint32_t)n_pairs * (uint32_t)n_patch), dim3(kWave), 0, s,
+  const uint32_t n = (uint32_t)n_pairs * (uint32_t)n_patch;
+  hipLaunchKernelGGL(k_ncc_loss, dim3((n + kNccWaves - 1) / kNccWaves), dim3(kWave * kNccWaves), 0, s,
                      views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad_rgb, loss);
 }
 
