@@ -200,6 +200,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
     L.tord[b] = take(sizeof(uint32_t) * (size_t)tiles);
   }
   L.bstart = take(sizeof(uint32_t) * ((size_t)L.max_pairs / kDupPairs + 2));
+  L.stats = take(sizeof(StatSlot) * kStatSlots);
   L.px_T = take(sizeof(float) * (size_t)px);
   L.px_last = take(sizeof(uint32_t) * (size_t)px);
   L.sgrad = take(sizeof(SplatGrad) * (size_t)L.max_splats);
@@ -265,6 +266,7 @@ struct Ptrs {
   uint32_t* tkey[2];
   uint32_t* tord[2];
   uint32_t* bstart;
+  StatSlot* stats;
   float* px_T;
   uint32_t* px_last;
   SplatGrad* sgrad;
@@ -297,6 +299,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
     p.tord[b] = at<uint32_t>(ws, L.tord[b]);
   }
   p.bstart = at<uint32_t>(ws, L.bstart);
+  p.stats = at<StatSlot>(ws, L.stats);
   p.px_T = at<float>(ws, L.px_T);
   p.px_last = at<uint32_t>(ws, L.px_last);
   p.sgrad = at<SplatGrad>(ws, L.sgrad);
@@ -338,7 +341,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.n_views = B;
   h.kind = s->kind;
   h.sort_passes = sort_passes(L.tile_bits);   // passes over the pairs
-  launch_init_counters(P.ctr, expl ? (uint32_t)L.max_splats : 0u, h, st);
+  launch_init_counters(P.ctr, P.stats, expl ? (uint32_t)L.max_splats : 0u, h, st);
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
     phase_begin(c, CGX_PHASE_PROJECT, st);
@@ -403,9 +406,11 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.px_T = P.px_T;
   a.px_last = P.px_last;
   a.ctr = P.ctr;
+  a.stats = P.stats;
   phase_begin(c, CGX_PHASE_RASTER_FWD, st);
   launch_raster_forward(a, c->tw, c->th, st);
   phase_end(c, st);
+  launch_fold_stats(P.ctr, P.stats, st);
   HIP_OK(c, hipGetLastError());
   return CGX_OK;
 }
@@ -477,7 +482,9 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   }
   a.sgrad = P.sgrad;
   phase_begin(c, CGX_PHASE_RASTER_BWD, st);
+  a.stats = P.stats;
   launch_raster_backward(a, c->tw, c->th, st);
+  launch_fold_stats(P.ctr, P.stats, st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_PROJECT_BWD, st);
   if (expl) {

@@ -120,6 +120,7 @@ struct Layout {
   size_t hist, ranges, px_T, px_last, sgrad, dz;
   size_t tkey[2], tord[2];     // raster launch order: length keys and tile ids
   size_t bstart;               // first visible splat of each pair-emission block
+  size_t stats;                // kStatSlots raster statistics slots
   size_t total;
   int64_t max_rows, max_splats, max_pairs;
   int64_t n_tiles, n_pixels;
@@ -256,7 +257,21 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 // launchers (defined in the .hip files)
 // ----------------------------------------------------------------------
 void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStream_t s);
-void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s);
+// Per-launch statistics and the L1 loss of the raster kernels, spread over
+// kStatSlots cache lines (a wave adds into slot blockIdx.x % kStatSlots):
+// atomics to one address serialise in L2, and one per tile wave on a
+// single line cost about 4 % of a step.  launch_fold_stats adds the slots
+// into the counter block and clears them.
+constexpr int kStatSlots = 64;
+struct alignas(128) StatSlot {
+  unsigned long long entries_fwd, evals_fwd, entries_bwd, evals_bwd;
+  float loss;
+  uint32_t pad[23];
+};
+static_assert(sizeof(StatSlot) == 128, "one cache line per slot");
+void launch_init_counters(Counters* c, StatSlot* stats, uint32_t n_splats_host, const WsHeader& h,
+                          hipStream_t s);
+void launch_fold_stats(Counters* c, StatSlot* stats, hipStream_t s);
 
 // Pairs handled by one block of the pair emission.
 constexpr int kDupPairs = 1024;
@@ -324,6 +339,7 @@ struct RasterArgs {
   const uint32_t* vals;
   const uint2* ranges;
   const uint32_t* order;       // position in the launch order -> tile id
+  StatSlot* stats;             // kStatSlots statistics slots
   uint32_t n_tiles;
   uint32_t n_slots;            // capacity of the splat table (slot bound)
   float* rgb;

@@ -190,8 +190,8 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     walked_sum += __shfl_xor(walked_sum, o, kWave);
     evals += __shfl_xor(evals, o, kWave);
   }
-  if (lane == 0 && walked_sum) atomicAdd(&a.ctr->entries_fwd, (unsigned long long)walked_sum);
-  if (lane == 0 && evals) atomicAdd(&a.ctr->evals_fwd, (unsigned long long)evals);
+  if (lane == 0 && walked_sum) atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_fwd, (unsigned long long)walked_sum);
+  if (lane == 0 && evals) atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_fwd, (unsigned long long)evals);
 }
 
 __device__ __forceinline__ float sgnf(float e) { return e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f); }
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   if (a.l1) {
     float l = loss;
     for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, kWave);
-    if (lane == 0 && l != 0.0f) atomic_add_f32(&a.ctr->loss, l);
+    if (lane == 0 && l != 0.0f) atomic_add_f32(&a.stats[blockIdx.x % kStatSlots].loss, l);
   }
   // per sub-block: the largest last-contributor index (wave-uniform)
   uint32_t blast[PPL];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     maxlast = blast[k] > maxlast ? blast[k] : maxlast;
   }
   for (int o = 32; o > 0; o >>= 1) sumlast += __shfl_xor(sumlast, o, kWave);
-  if (lane == 0 && sumlast) atomicAdd(&a.ctr->entries_bwd, (unsigned long long)sumlast);
+  if (lane == 0 && sumlast) atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_bwd, (unsigned long long)sumlast);
 
   const uint32_t start = a.ranges[tile].x;
   uint32_t evals = 0;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, kWave);
-  if (lane == 0 && evals) atomicAdd(&a.ctr->evals_bwd, (unsigned long long)evals);
+  if (lane == 0 && evals) atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_bwd, (unsigned long long)evals);
 }
 
 template <int TW, int TH>

@@ -14,7 +14,7 @@ void launch_upload_views(const ViewPack& pack, int count, ViewDev* dst, hipStrea
   hipLaunchKernelGGL(k_upload_views, dim3(1), dim3(kWave), 0, s, pack, count, dst);
 }
 
-__global__ void k_init_counters(Counters* c, uint32_t n_splats, WsHeader h) {
+__global__ void k_init_counters(Counters* c, StatSlot* stats, uint32_t n_splats, WsHeader h) {
   if (threadIdx.x == 0) {
     Counters z = {};
     z.hdr = h;
@@ -22,10 +22,39 @@ __global__ void k_init_counters(Counters* c, uint32_t n_splats, WsHeader h) {
     z.n_tiles = (uint32_t)h.n_tiles;
     *c = z;
   }
+  for (int i = threadIdx.x; i < kStatSlots; i += blockDim.x) stats[i] = StatSlot{};
 }
 
-void launch_init_counters(Counters* c, uint32_t n_splats_host, const WsHeader& h, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(kWave), 0, s, c, n_splats_host, h);
+void launch_init_counters(Counters* c, StatSlot* stats, uint32_t n_splats_host, const WsHeader& h,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(kWave), 0, s, c, stats, n_splats_host, h);
+}
+
+// one wave: slot t is read by lane t, summed over the wave (a fixed xor
+// tree), added into the counter block; the slots are cleared
+__global__ void k_fold_stats(Counters* c, StatSlot* stats) {
+  const int t = threadIdx.x;
+  StatSlot v = t < kStatSlots ? stats[t] : StatSlot{};
+  for (int o = 32; o > 0; o >>= 1) {
+    v.entries_fwd += __shfl_xor(v.entries_fwd, o, kWave);
+    v.evals_fwd += __shfl_xor(v.evals_fwd, o, kWave);
+    v.entries_bwd += __shfl_xor(v.entries_bwd, o, kWave);
+    v.evals_bwd += __shfl_xor(v.evals_bwd, o, kWave);
+    v.loss += __shfl_xor(v.loss, o, kWave);
+  }
+  if (t == 0) {
+    c->entries_fwd += v.entries_fwd;
+    c->evals_fwd += v.evals_fwd;
+    c->entries_bwd += v.entries_bwd;
+    c->evals_bwd += v.evals_bwd;
+    c->loss += v.loss;
+  }
+  if (t < kStatSlots) stats[t] = StatSlot{};
+}
+
+void launch_fold_stats(Counters* c, StatSlot* stats, hipStream_t s) {
+  static_assert(kStatSlots <= kWave, "one lane per slot");
+  hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kWave), 0, s, c, stats);
 }
 
 // ---------------------------------------------------------------------
