@@ -183,3 +183,20 @@ def test_full_size_pairs_match_oracle(R, rd):
     np.testing.assert_array_equal(st3.cpu().numpy(), st)
     for a, b in zip(_split(fused, X.views), chained):
         np.testing.assert_array_equal(a, b)
+
+
+def test_many_views_span_argument_groups(R, rd):
+    """18 views: the alignment runs in two groups of cameras, the filter in
+    three; the first and last views have no nearby view."""
+    print("case: depth prior, 18 views", flush=True)
+    X = scenes.make_depth_prior(seed=11, n_pairs=9, n_points=4000, sizes=[(33, 25), (30, 22)] * 9)
+    nearby = list(X.nearby)
+    nearby[0] = -1
+    nearby[17] = -1
+    st_ref, al_ref, _ = dp.align_scale_shift(X.prior, X.points, X.views)
+    st, al = _align_gpu(R, rd, X.views, X.prior, X.points)
+    np.testing.assert_allclose(st, st_ref, rtol=1e-9, atol=1e-9)
+    _check_aligned(al, al_ref)
+    depth32 = [a.astype(np.float32) for a in al_ref]
+    ref, frag, _ = dp.reprojection_filter([d.astype(np.float64) for d in depth32], X.views, nearby)
+    _check_filtered(_filter_gpu(R, rd, X.views, depth32, nearby), ref, frag)
