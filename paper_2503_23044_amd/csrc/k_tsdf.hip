@@ -11,9 +11,9 @@
 // launch (up to 16) are applied in order to the voxel's state held in
 // float64 registers: the volume crosses HBM once per launch, not once per
 // view, and a voxel that no view updates is not written back.  Views are
-// taken 8 at a time in stages (projections, all depth gathers, all colour
+// taken 4 at a time in stages (projections, all depth gathers, all colour
 // gathers of the updating views, then the averages in order), so that a
-// wave waits for two memory round trips per 8 views instead of two per
+// wave waits for two memory round trips per 4 views instead of two per
 // view.
 //
 // The host composes, in float64, each view's intrinsics, rotation and the
@@ -31,7 +31,7 @@
 namespace cgx {
 
 constexpr int kTsdfThreads = 256;
-constexpr int kTsdfStage = 8;
+constexpr int kTsdfStage = 4;
 constexpr double kTsdfInf = __builtin_inf();
 
 __device__ __forceinline__ double recip_refined(double z) {
