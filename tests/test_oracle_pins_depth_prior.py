@@ -201,3 +201,19 @@ def test_filter_on_the_optical_axis_from_behind():
         out, frag, _ = dp.reprojection_filter([d0, d1], views, [-1, 0])
         assert not frag[1][p]
         assert (out[1][p] == d1p) == kept, (d1p, d0p)
+
+
+def test_exact_pixel_edges_are_flagged_fragile():
+    """On the shared optical axis with the principal point on the pixel
+    grid, the axis pixel re-projects exactly onto a pixel corner of the
+    nearby view: flagged fragile; the other pixels are not."""
+    I3 = np.eye(3, dtype=np.float32)
+    v0 = scenes.View(48, 40, 40.0, 44.0, 24.5, 20.5, I3, np.zeros(3, np.float32), 0.2)
+    v1 = scenes.View(48, 40, 36.0, 38.0, 24.0, 20.0, I3, np.array([0, 0, 3], np.float32), 0.2)
+    d0 = np.zeros(48 * 40)
+    d0[20 * 48 + 24] = 2.0
+    d0[5 * 48 + 7] = 2.0
+    d1 = np.full(48 * 40, 5.0)
+    _, frag, _ = dp.reprojection_filter([d0, d1], [v0, v1], [1, -1])
+    assert frag[0][20 * 48 + 24]
+    assert frag[0].sum() == 1

@@ -158,3 +158,20 @@ def test_brute_force_with_homogeneous_cameras():
                             n += 1
                 assert Wt[idx] == (1.0 if upd else 0.0), (i, j, k)
     assert n > 20
+
+
+def test_exact_pixel_edges_are_flagged_fragile():
+    """With the principal point on the pixel grid (cx = 20), voxel
+    (i, j, k) at x = (i - 10) / 10, z = (20 + k) / 10 projects to
+    u = 20 + 20 (i - 10) / (20 + k), exactly a pixel edge when 20 + k
+    divides 20 (i - 10) (integer arithmetic); cy = 15.3 in float32 keeps w
+    off the edges.  Exactly those voxels are flagged."""
+    origin, voxel, dims = _grid()
+    v = scenes.View(40, 30, 20.0, 22.0, 20.0, 15.3, I3, np.zeros(3, np.float32), 0.2)
+    _, _, _, frag = tsdf.integrate(origin, voxel, dims, 0.35, [v], [np.full(1200, 3.3)])
+    nx, ny, nz = dims
+    idx = np.arange(nx * ny * nz)
+    i, k = idx % nx, idx // (nx * ny)
+    edge = (20 * (i - 10)) % (20 + k) == 0
+    assert edge.sum() > nx * ny                     # the axis and more
+    np.testing.assert_array_equal(frag, edge)
