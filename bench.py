@@ -30,7 +30,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 # algorithmic work per evaluated (pixel, splat) pair, counted from the
-# method's arithmetic (the design doc lists the terms)
+# method's arithmetic: forward = offsets, quadratic form, exponential,
+# alpha, transmittance update and the 7-channel blend; backward = the
+# recomputed alpha, transmittance recovery, value / suffix terms and the
+# 13 gradient terms
 FLOPS_FWD_PER_EVAL = 29
 FLOPS_BWD_PER_EVAL = 70
 SORT_BYTES_PER_ELEM_PASS = 16     # read + write of a 32-bit key and a 32-bit value
@@ -433,7 +436,7 @@ def tsdf_leg(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
     if args.ncc_only:

@@ -114,7 +114,7 @@ static int32_t check_scene(cgx_ctx* c, const cgx_scene* s, int32_t B) {
     if (a.n_offsets < 1 || a.n_offsets > CGX_MAX_OFFSETS)
       return fail(c, CGX_ERR_UNSUPPORTED, "n_offsets %d not in 1..%d", a.n_offsets, CGX_MAX_OFFSETS);
     if (a.n_offsets != 10)
-      return fail(c, CGX_ERR_UNSUPPORTED, "this build decodes n_offsets = 10 Gaussians per anchor");
+      return fail(c, CGX_ERR_UNSUPPORTED, "the decoder is compiled for n_offsets = 10 Gaussians per anchor");
     if (a.opacity_act != CGX_OPACITY_SIGMOID && a.opacity_act != CGX_OPACITY_TANH_MASK)
       return fail(c, CGX_ERR_INVALID_ARG, "opacity_act %d is not a known activation", a.opacity_act);
     if (a.n_levels < 1 || a.n_levels > 16)

@@ -10,7 +10,7 @@ namespace cgx {
 constexpr int kIn = CGX_MLP_IN;          // 36
 constexpr int kHid = CGX_MLP_HIDDEN;     // 32
 constexpr int kGo = CGX_GAUSS_OUT;       // 11
-constexpr int kNOff = 10;                // Gaussians per anchor in this build
+constexpr int kNOff = 10;                // Gaussians per anchor (compiled in)
 constexpr int kOut = kNOff * kGo;        // 110
 // per row: z0, z1, dz1, dz2 (the weight-gradient operands), then z2 kept by
 // the forward decode for the Gaussian adjoint, then the row's terms of the
