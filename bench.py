@@ -49,6 +49,8 @@ def parse():
                    help="tile shape WxH (16x16 is the paper's patch), or 'auto' to time every "
                         "compiled shape with the autotuner and keep the fastest")
     p.add_argument("--no-per-view", action="store_true")
+    p.add_argument("--no-graph", action="store_true",
+                   help="skip the timing of the same step replayed from a captured hipGraph")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=4000)
     p.add_argument("--no-ncc", action="store_true",
@@ -129,6 +131,28 @@ def gpu_leg(args, wl):
         if c:
             log(f"[bench]   {k:12s} {t / c:8.3f} ms x {c // args.steps} per step")
 
+    # the same fused step replayed from a captured hipGraph (no phase events)
+    graph_ms = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            g = B.cgx_graph_capture_fwd_bwd_l1(rd.ctx, wl.views, sc, rd.cap, rd.ws, tgt, w3, out,
+                                               grads, loss, side)
+        try:
+            for _ in range(2):
+                B.cgx_graph_launch(g, side)
+            side.synchronize()
+            t0g = time.perf_counter()
+            for _ in range(args.steps):
+                B.cgx_graph_launch(g, side)
+            side.synchronize()
+            graph_ms = (time.perf_counter() - t0g) / args.steps * 1e3
+            rd.info()     # raises if a replay exceeded a capacity
+        finally:
+            B.cgx_graph_destroy(g)
+        log(f"[bench] hipGraph replay: {graph_ms:.3f} ms/step")
+
     per_view_ms = None
     if not args.no_per_view and len(wl.views) > 1:
         rv = render.Renderer(0, (tw, th))
@@ -156,7 +180,7 @@ def gpu_leg(args, wl):
         torch.cuda.synchronize()
         per_view_ms = (time.perf_counter() - t0) / reps * 1e3
         log(f"[bench] per-view loop: {per_view_ms:.3f} ms per batch ({len(wl.views)} calls)")
-    return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms,
+    return dict(ms=ms, info=info, phases=phases, per_view_ms=per_view_ms, graph_ms=graph_ms,
                 peak_bytes=peak_bytes, tile=f"{tw}x{th}",
                 tune_ms=({f"{a}x{b}": round(m, 4) for (a, b), m in tune_ms.items()}
                          if tune_ms else None))
@@ -481,6 +505,7 @@ def main():
                    "tile_autotune_ms": res["tune_ms"],
                    "rows": res["info"]["n_rows"], "pairs": res["info"]["n_pairs"]},
         "batched_vs_per_view": (round(res["per_view_ms"] / res["ms"], 3) if res["per_view_ms"] else None),
+        "ms_per_step_graph": round(res["graph_ms"], 4) if res["graph_ms"] else None,
         "per_view_ms": (round(res["per_view_ms"], 4) if res["per_view_ms"] else None),
         "phases_ms": {k: round(t / max(args.steps, 1), 4) for k, (t, c) in res["phases"].items() if c},
         "peak_hbm_gib": round(res["peak_bytes"] / 2**30, 3),
