@@ -25,6 +25,11 @@ view.  Readings of what the paper leaves open:
     masked Gaussian, like any with o < 1/255, draws nothing and gets no
     tiles, so the mask needs no separate decision;
   * mu_k = x + O_k * l elementwise, in float64;
+  * offset variant (row f3, decoder-emitted offsets): with offset_mode = 1
+    the decoder has 14 outputs per Gaussian, the 11 above followed by the
+    offset O_k itself (no activation), z2[14k+11 : 14k+14]; then
+    mu_k = x + O_k * l with that O_k, and the anchor table's offsets are
+    not used (their gradient is zero);
   * the feature F is rounded to bfloat16 (weights are given in bfloat16);
     every other decoder value is carried exactly (float64 here).
 """
@@ -37,6 +42,14 @@ GAUSS_OUT = 11
 FRAG = 1e-5
 OPACITY_SIGMOID = 0
 OPACITY_TANH_MASK = 1
+OFFSETS_LEARNED = 0
+OFFSETS_DECODED = 1
+
+
+def _per_gauss(scene):
+    """Decoder outputs per Gaussian: 11, or 14 with decoder-emitted offsets."""
+    return GAUSS_OUT + 3 if int(getattr(scene, "offset_mode", OFFSETS_LEARNED)) == OFFSETS_DECODED \
+        else GAUSS_OUT
 
 
 def select(scene, views):
@@ -106,11 +119,12 @@ def decode(scene, views, rows, emulate_bf16=True):
     z1 = np.maximum(pre1, 0.0)
     z2 = z1 @ W2 + b2
     r = rows.shape[0]
-    g = z2.reshape(r, n, GAUSS_OUT)
+    go = _per_gauss(scene)
+    g = z2.reshape(r, n, go)
     a = rows[:, 1]
     x = np.asarray(scene.x, np.float64)[a]
     l = np.asarray(scene.l, np.float64)[a]
-    O = np.asarray(scene.O, np.float64)[a]
+    O = g[..., 11:14] if go > GAUSS_OUT else np.asarray(scene.O, np.float64)[a]
     mu = x[:, None, :] + O * l[:, None, :]
     act = int(getattr(scene, "opacity_act", OPACITY_SIGMOID))
     op = np.tanh(g[..., 0]) if act == OPACITY_TANH_MASK else sigmoid(g[..., 0])
@@ -124,7 +138,7 @@ def decode(scene, views, rows, emulate_bf16=True):
         quats=quats.reshape(-1, 4), opacity=op.reshape(-1), rgb=rgb.reshape(-1, 3),
         frag_relu=frag_relu,
         _z0=z0, _pre1=pre1, _z1=z1, _z2=z2, _W1=W1, _W2=W2, _geo=geo, _l=l, _O=O,
-        _ssig=ssig, _op=op, _rgb=rgb, _act=act)
+        _ssig=ssig, _op=op, _rgb=rgb, _act=act, _go=go)
 
 
 def decode_backward(scene, D, g):
@@ -142,15 +156,19 @@ def decode_backward(scene, D, g):
     go = np.asarray(g["opacity"], np.float64).reshape(r, n)
     gc = np.asarray(g["rgb"], np.float64).reshape(r, n, 3)
     op, rgb, ssig, l, O = D["_op"], D["_rgb"], D["_ssig"], D["_l"], D["_O"]
-    dz2 = np.zeros((r, n, GAUSS_OUT))
+    go_ = D.get("_go", GAUSS_OUT)
+    dz2 = np.zeros((r, n, go_))
     dz2[..., 0] = go * ((1 - op * op) if D["_act"] == OPACITY_TANH_MASK else op * (1 - op))
     dz2[..., 1:4] = gc * rgb * (1 - rgb)
     dz2[..., 4:7] = gs * l[:, None, :] * ssig * (1 - ssig)
     dz2[..., 7:11] = gq
     dl = np.sum(gs * ssig, axis=1) + np.sum(gm * O, axis=1)
     dO = gm * l[:, None, :]
+    if go_ > GAUSS_OUT:                 # decoder-emitted offsets: dmu/dO_k = l
+        dz2[..., 11:14] = dO
+        dO = np.zeros_like(dO)
     dx = np.sum(gm, axis=1)
-    dz2 = dz2.reshape(r, n * GAUSS_OUT)
+    dz2 = dz2.reshape(r, n * go_)
     W1, W2 = D["_W1"], D["_W2"]
     dW2 = D["_z1"].T @ dz2
     db2 = dz2.sum(0)
