@@ -108,9 +108,10 @@ def backward(r, out_grads, scene):
                     acc[k] += pg[k]
         grads = dict(means=acc["mu"], scales=acc["scales"], quats=acc["quats"],
                      opacity=acc["opacity"], sh=acc["sh"])
+        # Gaussians that draw on a pixel with a near-tie decision
         frag = np.zeros(scene.means.shape[0], bool)
         for v, S in enumerate(r.splats):
-            frag |= sg[v]["frag"] | (S["valid"] & S["frag_value"])
+            frag |= sg[v]["frag"]
         grads["frag"] = frag
         return grads, sg
     n = r.decoded["n"]
@@ -120,8 +121,7 @@ def backward(r, out_grads, scene):
         pg = prj.project_backward(S, sg[v])
         for k in parts:
             parts[k].append(pg[k])
-        f = (sg[v]["frag"] | (S["valid"] & (S["frag_value"] | S["frag_grad"])))
-        frag_rows.append(f.reshape(-1, n).any(axis=1))
+        frag_rows.append(sg[v]["frag"].reshape(-1, n).any(axis=1))
     g = {k: np.concatenate(v, 0) for k, v in parts.items()}
     grads = anc.decode_backward(scene, r.decoded, g)
     frag_rows = np.concatenate(frag_rows) if frag_rows else np.zeros(0, bool)

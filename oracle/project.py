@@ -106,13 +106,15 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
     closer than the float32 covariance can resolve (relative `rel`, times
     the conditioning of det) marks the splat's tile set fragile.
 
-    Returns (mask uint64, fragile bool) per splat."""
+    Returns (mask uint64, fragile bool, fragile-tile mask uint64) per splat:
+    the third value has the bits of the tiles whose own test is that close."""
     n = u.size
     mask = np.zeros(n, np.uint64)
     frag = np.zeros(n, bool)
+    fmask = np.zeros(n, np.uint64)
     idx = np.nonzero(use)[0]
     if idx.size == 0:
-        return mask, frag
+        return mask, frag, fmask
     u, w, A, B, C, tau = (np.asarray(a, np.float64)[idx] for a in (u, w, A, B, C, tau))
     rel = np.broadcast_to(np.asarray(rel, np.float64), (n,))[idx]
     xl_, xh_, yl_, yh_ = (np.asarray(a)[idx] for a in (x_lo, x_hi, y_lo, y_hi))
@@ -127,6 +129,7 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
     ye = B * np.sqrt(t2 / A)
     kappa = 1.0 + (A * C + B * B) / det
     m = np.zeros(idx.size, np.uint64)
+    fm = np.zeros(idx.size, np.uint64)
     fr = np.zeros(idx.size, bool)
     one = np.uint64(1)
     for rr in range(int(ny.max())):
@@ -137,7 +140,8 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
         lo = (r0 + 0.5) - w
         hi = (r1 + 0.5) - w
         dym = rel * kappa * (ymax + 1.0) + 1e-9
-        fr |= live & ((np.abs(lo - ymax) < dym) | (np.abs(hi + ymax) < dym))
+        rowfr = live & ((np.abs(lo - ymax) < dym) | (np.abs(hi + ymax) < dym))
+        fr |= rowfr
         lo = np.maximum(lo, -ymax)
         hi = np.minimum(hi, ymax)
         row = live & (lo <= hi)
@@ -152,12 +156,16 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
             c0 = np.maximum(tx * tw, xl_)
             c1 = np.minimum(tx * tw + tw - 1, xh_)
             keep = on & ((c1 + 0.5) >= xl) & ((c0 + 0.5) <= xr)
-            fr |= on & ((np.abs((c1 + 0.5) - xl) < marg) | (np.abs(xr - (c0 + 0.5)) < marg))
-            bit = np.where(on, rr * nx + cc, 0).astype(np.uint64)
+            colfr = on & ((np.abs((c1 + 0.5) - xl) < marg) | (np.abs(xr - (c0 + 0.5)) < marg))
+            fr |= colfr
+            inbox = live & (cc < nx)
+            bit = np.where(inbox, rr * nx + cc, 0).astype(np.uint64)
             m |= np.where(keep, np.left_shift(one, bit), np.uint64(0))
+            fm |= np.where(colfr | (rowfr & inbox), np.left_shift(one, bit), np.uint64(0))
     mask[idx] = m
     frag[idx] = fr
-    return mask, frag
+    fmask[idx] = fm
+    return mask, frag, fmask
 
 
 def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0,
@@ -250,6 +258,21 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     frag_ext = ok & (((ex <= r) & (_near_int(u - (rxp + 0.5), marg_x) | _near_int(u + (rxp - 0.5), marg_x)))
                      | ((ey <= r) & (_near_int(w - (ryp + 0.5), marg_y) | _near_int(w + (ryp - 0.5), marg_y)))
                      | (np.abs(ex - r) < marg_x) | (np.abs(ey - r) < marg_y))
+    # box edges (x_lo, x_hi, y_lo, y_hi) that may sit one pixel further or
+    # shorter on the GPU: a radius ceiling that may round the other way
+    # moves the edges it binds (r - 1 < e); a reach within rounding of the
+    # radius moves both edges of its axis; a reach-bound edge within rounding
+    # of a pixel centre moves that edge
+    rc = frag_r & front & (det > 0)
+    tx_, ty_ = np.abs(ex - r) < marg_x, np.abs(ey - r) < marg_y
+    mx = (rc & (ex > r - 1.0 - marg_x)) | tx_
+    my = (rc & (ey > r - 1.0 - marg_y)) | ty_
+    frag_edge = (front & (det > 0) & (tau >= 0.0))[:, None] & np.stack([
+        mx | ((ex <= r) & _near_int(u - (rxp + 0.5), marg_x)),
+        mx | ((ex <= r) & _near_int(u + (rxp - 0.5), marg_x)),
+        my | ((ey <= r) & _near_int(w - (ryp + 0.5), marg_y)),
+        my | ((ey <= r) & _near_int(w + (ryp - 0.5), marg_y))], 1)
+    frag_box = frag_edge.any(axis=1)
     frag_r = frag_r | frag_ext | (front & (det > 0) & frag_tau)
     x_lo = np.clip(np.where(ok, x_lo, W), 0, W).astype(np.int64)
     x_hi = np.clip(np.where(ok, x_hi, -1), -1, W - 1).astype(np.int64)
@@ -268,6 +291,13 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     ssort = np.sort(s, axis=1)
     frag_axis = (ssort[:, 1] - ssort[:, 0]) < FRAG * ssort[:, 0]
     frag_flip = np.abs(ndp) < FRAG * np.linalg.norm(p, axis=1)
+    # the other outcome of a near-tie axis (the next-smallest scale's axis,
+    # turned to the camera) or orientation (the opposite normal)
+    j2 = np.argsort(s, axis=1, kind="stable")[:, 1]
+    n2 = Rc[np.arange(n), :, j2]
+    n2 = n2 * np.where(np.sum(n2 * p, 1) > 0, -1.0, 1.0)[:, None]
+    n_alt = np.where(frag_axis[:, None], n2, -nvec)
+    d_alt = -np.sum(n_alt * p, 1)
 
     # ---- colour ----------------------------------------------------------
     frag_colour = np.zeros(n, bool)
@@ -292,19 +322,28 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     ty0, ty1 = y_lo // th, y_hi // th
     ntile = np.where(valid, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
     small = valid & (ntile <= MASK_TILES) & (tx1 > tx0) & (ty1 > ty0)
-    tmask, frag_cull = tile_mask(u, w, A, B, Cc, tau0, x_lo, x_hi, y_lo, y_hi, tw, th, small, rel)
+    tmask, frag_cull, fmask = tile_mask(u, w, A, B, Cc, tau0, x_lo, x_hi, y_lo, y_hi, tw, th,
+                                        small, rel)
     count = np.where(small, np.bitwise_count(tmask).astype(np.int64), ntile)
 
     return dict(
         n=n, valid=valid, p=p, u=u, w=w, zbits=zbits, conic=conic, r=r.astype(np.int64),
         box=np.stack([x_lo, x_hi, y_lo, y_hi], 1), opacity=o, rgb=rgb, raw_rgb=raw,
-        normal=nvec, d=d, sign=sign, jstar=jstar,
+        normal=nvec, d=d, sign=sign, jstar=jstar, normal_alt=n_alt, d_alt=d_alt,
         tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, tmask=tmask, small=small,
         TX=TX, TY=TY,
+        # near-tie decisions (float32 on the GPU, float64 here), per splat:
+        # any of them (frag_value); box edges (frag_box); validity through
+        # o vs 1/255 (frag_tau); tile-culling tests, per tile bit (fmask);
+        # the normal's axis or orientation (frag_geom); and the ties that
+        # only change the adjoint: the colour clamp and the Jacobian's guard
+        # band (frag_grad)
         frag_value=(valid & (frag_r | frag_axis | frag_flip | frag_cull))
         | (front & (det > 0) & frag_tau),
         frag_ring=valid & frag_r, frag_geom=valid & (frag_axis | frag_flip),
-        frag_grad=valid & (frag_colour | clamp_x | clamp_y
+        frag_box=frag_box, frag_edge=frag_edge, frag_tau=front & (det > 0) & frag_tau,
+        fmask=fmask,
+        frag_grad=valid & (frag_colour
                            | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)
                            | (np.abs(np.abs(ry) - lim_y) < FRAG * lim_y)),
         # intermediates for the adjoint

@@ -58,28 +58,101 @@ def batch_layout(views, tile):
 # --------------------------------------------------------------------------
 # a3-a5: binning and sort
 # --------------------------------------------------------------------------
-def _bin_sample(splats_per_view, layout, keep_tiles):
-    """Entries of the global tiles in keep_tiles only (a bounded sample of a
-    large workload): for each such tile, every valid splat whose tile
-    rectangle contains it."""
-    gt_all, zb_all, v_all, g_all = [], [], [], []
-    for gtile in sorted(int(t) for t in keep_tiles):
+def _grown_tiles(S, layout, v):
+    """Tile rectangle of each splat's pixel box grown by one pixel on every
+    side (clipped to the image): the tiles a box edge one pixel further out
+    could reach."""
+    tw, th = layout["tile"]
+    W, H = S["_view"]["W"], S["_view"]["H"]
+    box = S["box"]
+    gx0 = np.clip(box[:, 0] - 1, 0, W - 1) // tw
+    gx1 = np.clip(box[:, 1] + 1, 0, W - 1) // tw
+    gy0 = np.clip(box[:, 2] - 1, 0, H - 1) // th
+    gy1 = np.clip(box[:, 3] + 1, 0, H - 1) // th
+    return gx0, gx1, gy0, gy1
+
+
+def _tile_entries(S, layout, v, tx, ty):
+    """Entries of one tile (tx, ty) of view v.
+
+    own: the splat's pixel box and, for a masked box, its drawable-ellipse
+    tile mask contain the tile (the oracle's own binning);
+    extra: not own, but one near-tie decision away from it -- a box edge
+    (the tiles of the box grown by one pixel), the o vs 1/255 validity, or
+    the tile-culling test of this very tile;
+    cbit: this tile's culling test is itself a near tie.
+    Returns (idx, own, cbit) over own | extra."""
+    t = S["tiles"]
+    inrect = (t[:, 0] <= tx) & (t[:, 1] >= tx) & (t[:, 2] <= ty) & (t[:, 3] >= ty)
+    bit = np.where(inrect, (ty - t[:, 2]) * (t[:, 1] - t[:, 0] + 1) + (tx - t[:, 0]), 0)
+    sh = np.minimum(bit, 63).astype(np.uint64)
+    hit = (np.right_shift(S["tmask"], sh) & np.uint64(1)) != 0
+    cbit = S["small"] & inrect & ((np.right_shift(S["fmask"], sh) & np.uint64(1)) != 0)
+    own = S["valid"] & inrect & (~S["small"] | hit)
+    gx0, gx1, gy0, gy1 = _grown_tiles(S, layout, v)
+    near = (S["frag_box"] | S["frag_tau"]) & (gx0 <= tx) & (gx1 >= tx) & (gy0 <= ty) & (gy1 >= ty)
+    cand = own | near | cbit
+    idx = np.nonzero(cand)[0]
+    return idx, own[idx], cbit[idx]
+
+
+def _bin_tiles(splats_per_view, layout, tiles):
+    """Entries (global tile, depth bits, view, gid, own, cbit) of the given
+    global tiles, one tile at a time."""
+    cols = [[] for _ in range(6)]
+    for gtile in tiles:
+        gtile = int(gtile)
         v = int(np.searchsorted(layout["tile_off"], gtile, side="right") - 1)
         local = gtile - int(layout["tile_off"][v])
         tx, ty = local % layout["TX"][v], local // layout["TX"][v]
         S = splats_per_view[v]
+        idx, own, cbit = _tile_entries(S, layout, v, tx, ty)
+        for c, a in zip(cols, (np.full(idx.size, gtile, np.int64), S["zbits"][idx],
+                               np.full(idx.size, v, np.int64), idx.astype(np.int64), own, cbit)):
+            c.append(a)
+    return cols
+
+
+def _bin_all(splats_per_view, layout):
+    """Entries of every tile of every view, vectorised per view: the own
+    pairs of the tile rectangle and mask, plus the one-tie-away pairs of
+    the splats with a near-tie box edge or validity (grown rectangle) and of
+    the near-tie culled tiles."""
+    cols = [[] for _ in range(6)]
+    for v, S in enumerate(splats_per_view):
+        gx0, gx1, gy0, gy1 = _grown_tiles(S, layout, v)
+        near = S["frag_box"] | S["frag_tau"]
         t = S["tiles"]
-        m = S["valid"] & (t[:, 0] <= tx) & (t[:, 1] >= tx) & (t[:, 2] <= ty) & (t[:, 3] >= ty)
-        # boxes of at most 64 tiles: only the tiles the drawable ellipse reaches
-        bit = np.where(m, (ty - t[:, 2]) * (t[:, 1] - t[:, 0] + 1) + (tx - t[:, 0]), 0)
-        hit = (np.right_shift(S["tmask"], np.minimum(bit, 63).astype(np.uint64)) & np.uint64(1)) != 0
-        m &= ~S["small"] | hit
-        idx = np.nonzero(m)[0]
-        gt_all.append(np.full(idx.size, gtile, np.int64))
-        zb_all.append(S["zbits"][idx])
-        v_all.append(np.full(idx.size, v, np.int64))
-        g_all.append(idx.astype(np.int64))
-    return gt_all, zb_all, v_all, g_all
+        # candidate rectangle: the box's tiles, or the grown box's tiles for
+        # splats with a near-tie box edge or validity
+        rx0 = np.where(near, np.minimum(gx0, t[:, 0]), t[:, 0])
+        rx1 = np.where(near, np.maximum(gx1, t[:, 1]), t[:, 1])
+        ry0 = np.where(near, np.minimum(gy0, t[:, 2]), t[:, 2])
+        ry1 = np.where(near, np.maximum(gy1, t[:, 3]), t[:, 3])
+        live = S["valid"] | near
+        idx = np.nonzero(live & (rx1 >= rx0) & (ry1 >= ry0))[0]
+        if idx.size == 0:
+            continue
+        nx = rx1[idx] - rx0[idx] + 1
+        cnt = nx * (ry1[idx] - ry0[idx] + 1)
+        rep = np.repeat(np.arange(idx.size), cnt)
+        first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        k = np.arange(rep.size) - first
+        g = idx[rep]
+        tx = rx0[g] + k % nx[rep]
+        ty = ry0[g] + k // nx[rep]
+        inrect = (t[g, 0] <= tx) & (t[g, 1] >= tx) & (t[g, 2] <= ty) & (t[g, 3] >= ty)
+        bit = np.where(inrect, (ty - t[g, 2]) * (t[g, 1] - t[g, 0] + 1) + (tx - t[g, 0]), 0)
+        sh = np.minimum(bit, 63).astype(np.uint64)
+        hit = (np.right_shift(S["tmask"][g], sh) & np.uint64(1)) != 0
+        cbit = S["small"][g] & inrect & ((np.right_shift(S["fmask"][g], sh) & np.uint64(1)) != 0)
+        own = S["valid"][g] & inrect & (~S["small"][g] | hit)
+        keep = own | near[g] | cbit
+        g, tx, ty, own, cbit = g[keep], tx[keep], ty[keep], own[keep], cbit[keep]
+        for c, a in zip(cols, (layout["tile_off"][v] + ty * layout["TX"][v] + tx, S["zbits"][g],
+                               np.full(g.size, v, np.int64), g.astype(np.int64), own, cbit)):
+            c.append(a)
+    return cols
 
 
 def bin_and_sort(splats_per_view, layout, keep_tiles=None):
@@ -91,60 +164,74 @@ def bin_and_sort(splats_per_view, layout, keep_tiles=None):
     arrays gtile (int64), zbits (uint32), view, gid, and ranges
     (n_tiles, 2) = [start, end) per global tile.  With keep_tiles, only the
     entries of those tiles are produced (other tiles have empty ranges).
-    """
+
+    The oracle's own pairs are the ones with own = True; the lists also
+    hold, flagged own = False, the pairs one near-tie decision away (a box
+    edge, the validity, a tile-culling test), which the GPU, deciding in
+    float32, may equally take.  cbit marks an entry whose tile-culling test
+    is itself a near tie; `certain` = own and no near tie on the pair."""
     if keep_tiles is not None:
-        gt_all, zb_all, v_all, g_all = _bin_sample(splats_per_view, layout, keep_tiles)
-        return _sort_entries(gt_all, zb_all, v_all, g_all, layout)
-    gt_all, zb_all, v_all, g_all = [], [], [], []
-    for v, S in enumerate(splats_per_view):
-        idx = np.nonzero(S["valid"])[0]
-        if idx.size == 0:
-            continue
-        tiles = S["tiles"][idx]
-        tx0, tx1, ty0, ty1 = tiles.T
-        nx = tx1 - tx0 + 1
-        cnt = nx * (ty1 - ty0 + 1)
-        rep = np.repeat(np.arange(idx.size), cnt)
-        first = np.repeat(np.cumsum(cnt) - cnt, cnt)
-        k = np.arange(rep.size) - first
-        # boxes of at most 64 tiles: only the tiles the drawable ellipse reaches
-        hit = (np.right_shift(S["tmask"][idx][rep], np.minimum(k, 63).astype(np.uint64))
-               & np.uint64(1)) != 0
-        sel = ~S["small"][idx][rep] | hit
-        rep, k = rep[sel], k[sel]
-        tx = tx0[rep] + k % nx[rep]
-        ty = ty0[rep] + k // nx[rep]
-        gt_all.append(layout["tile_off"][v] + ty * layout["TX"][v] + tx)
-        zb_all.append(S["zbits"][idx][rep])
-        v_all.append(np.full(rep.size, v, np.int64))
-        g_all.append(idx[rep].astype(np.int64))
-    return _sort_entries(gt_all, zb_all, v_all, g_all, layout)
+        cols = _bin_tiles(splats_per_view, layout, sorted(int(t) for t in keep_tiles))
+    else:
+        cols = _bin_all(splats_per_view, layout)
+    return _sort_entries(cols, splats_per_view, layout)
 
 
-def _sort_entries(gt_all, zb_all, v_all, g_all, layout):
+def _sort_entries(cols, splats_per_view, layout):
     n_tiles = int(layout["tile_off"][-1])
-    if not gt_all or sum(a.size for a in gt_all) == 0:
+    if not cols[0] or sum(a.size for a in cols[0]) == 0:
         e = np.zeros(0, np.int64)
-        return dict(gtile=e, zbits=e.astype(np.uint32), view=e, gid=e,
-                    ranges=np.zeros((n_tiles, 2), np.int64))
-    gt = np.concatenate(gt_all)
-    zb = np.concatenate(zb_all)
-    vv = np.concatenate(v_all)
-    gg = np.concatenate(g_all)
+        b = np.zeros(0, bool)
+        z = dict(gtile=e, zbits=e.astype(np.uint32), view=e, gid=e, own=b, cbit=b, certain=b,
+                 ranges=np.zeros((n_tiles, 2), np.int64))
+        z["own_sorted"] = dict(z)
+        return z
+    gt, zb, vv, gg, own, cbit = (np.concatenate(c) for c in cols)
     order = np.lexsort((gg, vv, zb, gt))
-    gt, zb, vv, gg = gt[order], zb[order], vv[order], gg[order]
+    gt, zb, vv, gg, own, cbit = (a[order] for a in (gt, zb, vv, gg, own, cbit))
+    near = np.zeros(gt.size, bool)
+    for v, S in enumerate(splats_per_view):
+        m = vv == v
+        near[m] = S["frag_box"][gg[m]] | S["frag_tau"][gg[m]]
+    certain = own & ~cbit & ~near
     ranges = np.zeros((n_tiles, 2), np.int64)
     if gt.size:
         starts = np.searchsorted(gt, np.arange(n_tiles), side="left")
         ends = np.searchsorted(gt, np.arange(n_tiles), side="right")
         ranges[:, 0] = np.where(ends > starts, starts, 0)
         ranges[:, 1] = np.where(ends > starts, ends, 0)
-    return dict(gtile=gt, zbits=zb, view=vv, gid=gg, ranges=ranges)
+    # the oracle's own binning alone (the pairs it takes itself)
+    o = own
+    ogt = gt[o]
+    oranges = np.zeros((n_tiles, 2), np.int64)
+    if ogt.size:
+        starts = np.searchsorted(ogt, np.arange(n_tiles), side="left")
+        ends = np.searchsorted(ogt, np.arange(n_tiles), side="right")
+        oranges[:, 0] = np.where(ends > starts, starts, 0)
+        oranges[:, 1] = np.where(ends > starts, ends, 0)
+    return dict(gtile=gt, zbits=zb, view=vv, gid=gg, own=own, cbit=cbit, certain=certain,
+                ranges=ranges,
+                own_sorted=dict(gtile=ogt, zbits=zb[o], view=vv[o], gid=gg[o], ranges=oranges))
 
 
 # --------------------------------------------------------------------------
 # a6: forward compositing
 # --------------------------------------------------------------------------
+# Near ties in the compositing and what they allow (float32 on the GPU,
+# float64 here): the alpha test within FRAG_ALPHA of 1/255; the transmittance
+# stop within FRAG_T of 1e-4; the unbiased-depth guard within 10 FRAG_ALPHA;
+# a box edge, validity or tile-culling test that is a near tie lets the GPU
+# take or drop the splat at a pixel where its alpha passes (for validity and
+# culling, only up to FRAG_CULL above 1/255: a tile or splat the GPU drops
+# holds no pixel whose alpha clears the threshold by more than rounding and
+# the float32 mean).  A pixel with at most MAX_TIES such pair decisions gets
+# every combination, each walked with both outcomes of any transmittance or
+# guard tie it meets; more is excluded and counted.
+FRAG_CULL = 1e-3
+MAX_TIES = 6
+MAX_CANDIDATES = 256
+
+
 def _tile_pixels(view, layout, v, local_tile):
     tw, th = layout["tile"]
     TX = layout["TX"][v]
@@ -180,12 +267,115 @@ def _tile_eval(S, ent, I, J):
     return dict(dx=dx, dy=dy, inbox=inbox, power=power, G=G, raw=raw, alpha=alpha, use=use)
 
 
-def composite_tile(S, ent, I, J, view_arrays):
+def _pair_ties(S, ent, own, cbit, I, J, E):
+    """(pixel, entry) decisions that are near ties: the GPU may take the
+    entry where the oracle does not, or the reverse."""
+    ne = ent.size
+    if ne == 0:
+        return np.zeros((I.size, 0), bool)
+    fb = S["frag_box"][ent][None]
+    ft = S["frag_tau"][ent][None]
+    fe = S["frag_edge"][ent]
+    box = S["box"][ent]
+    Ic, Jc = I[:, None], J[:, None]
+    x0, x1, y0, y1 = (box[None, :, i] for i in range(4))
+    grown = (Ic >= x0 - 1) & (Ic <= x1 + 1) & (Jc >= y0 - 1) & (Jc <= y1 + 1)
+    # the pixel column or row on either side of a near-tie box edge
+    ring = grown & (((Ic == x0) | (Ic == x0 - 1)) & fe[None, :, 0]
+                    | ((Ic == x1) | (Ic == x1 + 1)) & fe[None, :, 1]
+                    | ((Jc == y0) | (Jc == y0 - 1)) & fe[None, :, 2]
+                    | ((Jc == y1) | (Jc == y1 + 1)) & fe[None, :, 3])
+    pw = E["power"] <= 0
+    r255 = E["raw"] * 255.0
+    passes = pw & (r255 >= 1.0 - FRAG_ALPHA)
+    near = pw & (np.abs(r255 - 1.0) < FRAG_ALPHA)
+    loose = passes & (r255 < 1.0 + FRAG_CULL)
+    inb = E["inbox"] | (fb & grown)
+    # an entry the oracle does not list itself (own False) is taken, if at
+    # all, only at such a tie
+    return inb & (near | (ring & passes) | ((fb | ft | cbit[None]) & loose))
+
+
+def _walk(use, alpha, vals):
+    """Front-to-back walk of one pixel over the entries with use: every
+    outcome of the transmittance-stop near ties it meets.  Returns a list of
+    (weighted sums of vals, final T, per-entry weights)."""
+    idx = np.nonzero(use)[0]
+    out = []
+    stack = [(0, 1.0, np.zeros(vals.shape[1]), np.zeros(use.size))]
+    while stack and len(out) < MAX_CANDIDATES:
+        pos, T, acc, wts = stack.pop()
+        for m in range(pos, idx.size):
+            k = idx[m]
+            Tn = T * (1.0 - alpha[k])
+            w = alpha[k] * T
+            if abs(Tn / T_MIN - 1.0) < FRAG_T:
+                w2 = wts.copy()
+                w2[k] = w
+                stack.append((m + 1, Tn, acc + w * vals[k], w2))
+                break
+            if Tn < T_MIN:
+                break
+            acc = acc + w * vals[k]
+            wts = wts.copy()
+            wts[k] = w
+            T = Tn
+        out.append((acc, T, wts))
+    return out
+
+
+def _pixel_candidates(use0, amb, alpha, vals, nabs, bg, ray, alts=()):
+    """Every output (rgb 3, D, N 3, alpha, unbiased depth, |N| blend 3) one
+    pixel may take under its near ties, or None when there are more than
+    MAX_TIES ties.  alts: (entry, its other (d, normal) outcome) for the
+    entries whose normal is a near tie."""
+    aidx = np.nonzero(amb)[0]
+    na = aidx.size
+    if na + len(alts) > MAX_TIES:
+        return None
+    cands = []
+    for m in range(1 << (na + len(alts))):
+        use = use0.copy()
+        for b, k in enumerate(aidx):
+            if (m >> b) & 1:
+                use[k] = ~use[k]
+        vv, nb = vals, nabs
+        for b, (k, alt) in enumerate(alts):
+            if (m >> (na + b)) & 1:
+                vv = vv.copy()
+                nb = nb.copy()
+                vv[k, 3:7] = alt
+                nb[k] = np.abs(alt[1:4])
+        for acc, T, wts in _walk(use, alpha, vv):
+            rgb = acc[0:3] + T * bg
+            D = acc[3]
+            N = acc[4:7]
+            a = 1.0 - T
+            sd = -float(N @ ray)
+            nab = wts @ nb
+            dh = [D / sd if sd > DHAT_GUARD * a else 0.0]
+            if a > 0 and abs(sd - DHAT_GUARD * a) < 10 * FRAG_ALPHA * max(abs(sd), DHAT_GUARD * a):
+                dh = [D / sd if sd != 0 else 0.0, 0.0]
+            cond = max(1.0, float(nab @ np.abs(ray)) / abs(sd)) if sd != 0 else 1.0
+            for d in dh:
+                cands.append(np.concatenate([rgb, [D], N, [a, d], nab, [abs(d) * cond]]))
+        if len(cands) >= MAX_CANDIDATES:
+            break
+    return np.array(cands)
+
+
+def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
     """Front-to-back blend of one tile's sorted entries `ent` (indices into
-    the splat dict S of that view) over pixels (I, J)."""
+    the splat dict S of that view) over pixels (I, J).  own marks the
+    entries the oracle lists itself (default: all); the others, and cbit,
+    come from bin_and_sort's near-tie entries."""
+    ne = ent.size
+    own = np.ones(ne, bool) if own is None else np.asarray(own, bool)
+    cbit = np.zeros(ne, bool) if cbit is None else np.asarray(cbit, bool)
     E = _tile_eval(S, ent, I, J)
+    E["use"] = E["use"] & own[None]
     use, alpha = E["use"], E["alpha"]
-    npx, ne = use.shape
+    npx = use.shape[0]
     a_use = np.where(use, alpha, 0.0)
     Tp_all = np.cumprod(1.0 - a_use, axis=1) if ne else np.ones((npx, 0))
     crossed = use & (Tp_all < T_MIN)
@@ -207,29 +397,6 @@ def composite_tile(S, ent, I, J, view_arrays):
             else np.zeros(npx, np.int64))
     walked = np.minimum(stop + 1, ne)
 
-    # fragile decisions (float32 on the GPU vs float64 here)
-    upto = kidx <= stop[:, None]
-    frag = np.zeros(npx, bool)
-    near_a = E["inbox"] & upto & (np.abs(E["raw"] * 255.0 - 1.0) < FRAG_ALPHA)
-    frag |= near_a.any(axis=1)
-    near_t = use & upto & (np.abs(Tp_all / T_MIN - 1.0) < FRAG_T)
-    frag |= near_t.any(axis=1)
-    frag_geom = np.zeros(npx, bool)
-    if ne:
-        # a fragile radius ceiling moves the box edge by one pixel: the ring
-        # between the box shrunk and grown by one; a fragile normal axis or
-        # orientation changes the splat's normal and plane distance
-        box = S["box"][ent]
-        grown = ((I[:, None] >= box[None, :, 0] - 1) & (I[:, None] <= box[None, :, 1] + 1)
-                 & (J[:, None] >= box[None, :, 2] - 1) & (J[:, None] <= box[None, :, 3] + 1))
-        shrunk = ((I[:, None] >= box[None, :, 0] + 1) & (I[:, None] <= box[None, :, 1] - 1)
-                  & (J[:, None] >= box[None, :, 2] + 1) & (J[:, None] <= box[None, :, 3] - 1))
-        frag |= (grown & ~shrunk & S["frag_ring"][ent][None] & upto).any(axis=1)
-        frag_geom = (grown & S["frag_geom"][ent][None] & upto).any(axis=1)
-    frag_grad = frag | (inc & (np.abs(E["raw"] / ALPHA_MAX - 1.0) < FRAG_ALPHA)).any(axis=1)
-    if ne:
-        frag_grad |= (inc & S["frag_grad"][ent][None]).any(axis=1)
-
     V = view_arrays
     rgb = rgb + T_final[:, None] * V["bg"][None]
     acc = 1.0 - T_final
@@ -237,33 +404,73 @@ def composite_tile(S, ent, I, J, view_arrays):
     sdot = -np.sum(N * ray, 1)
     keep = sdot > DHAT_GUARD * acc
     dhat = np.where(keep, D / np.where(keep, sdot, 1.0), 0.0)
-    frag |= (acc > 0) & (np.abs(sdot - DHAT_GUARD * acc)
-                         < 10 * FRAG_ALPHA * np.maximum(np.abs(sdot), DHAT_GUARD * acc))
-    # grazing incidence: s = -N . ray cancels terms DHAT_COND times its size;
-    # float32 then loses more than four bits of s, and D^'s adjoint (1/s^2)
-    # doubles that, so the pixel's gradients are not resolved to 1e-4
+
+    # near ties: pair decisions, transmittance stop, depth guard
+    upto = kidx <= stop[:, None]
+    amb = _pair_ties(S, ent, own, cbit, I, J, E)
+    near_t = use & upto & (np.abs(Tp_all / T_MIN - 1.0) < FRAG_T)
+    dtie = (acc > 0) & (np.abs(sdot - DHAT_GUARD * acc)
+                        < 10 * FRAG_ALPHA * np.maximum(np.abs(sdot), DHAT_GUARD * acc))
+    tie = dtie.copy()
+    geo = np.zeros((npx, ne), bool)
+    if ne:
+        # a splat whose normal is a near tie, used (or one tie away) here
+        geo = (inc | amb) & S["frag_geom"][ent][None]
+        tie |= amb.any(axis=1) | near_t.any(axis=1) | geo.any(axis=1)
+    cands, excl = {}, np.zeros(npx, bool)
+    if tie.any():
+        vals = np.concatenate([S["rgb"][ent], S["d"][ent][:, None], S["normal"][ent]], 1)
+        nabs = np.abs(S["normal"][ent])
+        alt = np.concatenate([S["d_alt"][ent][:, None], S["normal_alt"][ent]], 1) if ne else None
+        for p in np.nonzero(tie)[0]:
+            alts = [(int(k), alt[k]) for k in np.nonzero(geo[p])[0]] if ne else []
+            c = _pixel_candidates(use[p], amb[p] if ne else np.zeros(0, bool), alpha[p],
+                                  vals, nabs, V["bg"], ray[p], alts)
+            if c is None:
+                excl[p] = True
+            else:
+                cands[int(p)] = c
+    # decisions that change only the adjoint, or the geometric outputs:
+    # the 0.99 clamp, a splat's own near ties (colour clamp, guard band,
+    # decoder ReLU; its normal's axis or orientation), and grazing incidence
+    # (s = -N . ray cancels terms DHAT_COND times its size: float32 loses more
+    # than four bits of s, and the adjoint's 1/s^2 doubles that)
+    touch = inc | amb if ne else inc
+    geom = geo.any(axis=1)
+    gonly = np.zeros(npx, bool)
+    if ne:
+        gonly = ((inc & (np.abs(E["raw"] / ALPHA_MAX - 1.0) < FRAG_ALPHA)).any(axis=1)
+                 | (touch & S["frag_grad"][ent][None]).any(axis=1))
     sabs = np.sum(Nabs * np.abs(ray), 1)
-    frag_grad = frag_grad | (keep & (sabs > DHAT_COND * np.abs(sdot)))
-    return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, T=T_final, last=last,
-                walked=walked, frag=frag, frag_geom=frag_geom,
-                frag_grad=frag_grad | frag | frag_geom, inc=inc,
-                keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)
+    grazing = keep & (sabs > DHAT_COND * np.abs(sdot))
+    # scale of the float32 error of D / s: s is a sum of terms of size sabs
+    dmag = np.abs(dhat) * np.maximum(1.0, sabs / np.where(sdot != 0, np.abs(sdot), 1.0))
+    tie_grad = tie | excl | geom | gonly | grazing
+    return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, dmag=dmag, T=T_final,
+                last=last,
+                walked=walked, tie=tie, excl=excl, frag_geom=geom, frag_grad=tie_grad,
+                cands=cands, n_pair_ties=int(amb.sum()) if ne else 0,
+                inc=inc, keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)
 
 
 def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_tiles=None):
     """Composite every tile (or the global tile ids in keep_tiles) of every
     view.  Returns per-view planar images and per-tile state for the
-    adjoint."""
+    adjoint.  Per pixel: `tie` (a near-tie decision; `cands` holds every
+    output it may take), `excl` (more ties than are enumerated), `frag_geom`
+    (a contributing splat's normal is a near tie) and `frag_grad` (any of
+    these, or a tie that changes only the adjoint)."""
     out = []
     for v, view in enumerate(views):
         W, H = int(view.width), int(view.height)
-        img = dict(rgb=np.zeros((3, H * W)), depth=np.zeros(H * W), D=np.zeros(H * W),
+        img = dict(rgb=np.zeros((3, H * W)), depth=np.zeros(H * W), depth_mag=np.zeros(H * W),
+                   D=np.zeros(H * W),
                    normal=np.zeros((3, H * W)), normal_abs=np.zeros((3, H * W)),
                    alpha=np.zeros(H * W), T=np.ones(H * W),
                    last=np.zeros(H * W, np.int64), walked=np.zeros(H * W, np.int64),
-                   frag=np.zeros(H * W, bool), frag_geom=np.zeros(H * W, bool),
-                   frag_grad=np.zeros(H * W, bool),
-                   covered=np.zeros(H * W, bool), tiles={})
+                   tie=np.zeros(H * W, bool), excl=np.zeros(H * W, bool),
+                   frag_geom=np.zeros(H * W, bool), frag_grad=np.zeros(H * W, bool),
+                   covered=np.zeros(H * W, bool), cands={}, n_pair_ties=0, tiles={})
         out.append(img)
     n_tiles_total = int(layout["tile_off"][-1])
     tiles = range(n_tiles_total) if keep_tiles is None else keep_tiles
@@ -273,11 +480,13 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
         I, J = _tile_pixels(views[v], layout, v, local)
         s0, s1 = sorted_["ranges"][gtile]
         ent = sorted_["gid"][s0:s1]
-        R = composite_tile(splats_per_view[v], ent, I, J, view_arrays[v])
+        R = composite_tile(splats_per_view[v], ent, I, J, view_arrays[v],
+                           own=sorted_["own"][s0:s1], cbit=sorted_["cbit"][s0:s1])
         pix = J * int(views[v].width) + I
         img = out[v]
         img["rgb"][:, pix] = R["rgb"].T
         img["depth"][pix] = R["dhat"]
+        img["depth_mag"][pix] = R["dmag"]
         img["D"][pix] = R["D"]
         img["normal"][:, pix] = R["N"].T
         img["normal_abs"][:, pix] = R["Nabs"].T
@@ -285,35 +494,15 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
         img["T"][pix] = R["T"]
         img["last"][pix] = R["last"]
         img["walked"][pix] = R["walked"]
-        img["frag"][pix] = R["frag"]
+        img["tie"][pix] = R["tie"]
+        img["excl"][pix] = R["excl"]
         img["frag_geom"][pix] = R["frag_geom"]
         img["frag_grad"][pix] = R["frag_grad"]
         img["covered"][pix] = True
+        img["n_pair_ties"] += R["n_pair_ties"]
+        for p, c in R["cands"].items():
+            img["cands"][int(pix[p])] = c
         img["tiles"][gtile] = (ent, I, J, pix, R)
-    # a splat with a fragile radius ceiling may reach one pixel further or
-    # shorter on the GPU: flag the ring between its box shrunk and grown by
-    # one pixel; one with a fragile normal axis or orientation has another
-    # normal and plane distance there: flag its grown box for the geometric
-    # outputs (normal, D, unbiased depth); both for the gradients
-    for v, view in enumerate(views):
-        S = splats_per_view[v]
-        W, H = int(view.width), int(view.height)
-        img = out[v]
-        for i in np.nonzero(S["frag_value"])[0]:
-            bx0, bx1, by0, by1 = (int(t) for t in S["box"][i])
-            x0, y0 = max(bx0 - 1, 0), max(by0 - 1, 0)
-            x1, y1 = min(bx1 + 1, W - 1), min(by1 + 1, H - 1)
-            if x0 > x1 or y0 > y1:
-                continue
-            xs, ys = np.arange(x0, x1 + 1), np.arange(y0, y1 + 1)
-            blk = (ys[:, None] * W + xs[None]).ravel()
-            img["frag_grad"][blk] = True
-            if S["frag_geom"][i]:
-                img["frag_geom"][blk] = True
-            if S["frag_ring"][i]:
-                inner = (((xs[None] >= bx0 + 1) & (xs[None] <= bx1 - 1))
-                         & ((ys[:, None] >= by0 + 1) & (ys[:, None] <= by1 - 1))).ravel()
-                img["frag"][blk[~inner]] = True
     return out
 
 

@@ -175,10 +175,27 @@ class Renderer:
             self._grow(info)
         raise B.CgxError(B.CGX_ERR_CAPACITY, "capacity still exceeded after growing")
 
-    def backward(self, views, scene, out, grad_out, grads=None):
+    def backward(self, views, scene, out, grad_out, grads=None, state=None):
+        """Gradients of the forward call whose state is `state` (from
+        take_state), or of this renderer's last forward call."""
         grads = grads if grads is not None else grad_buffers(scene, f"cuda:{self.device}")
-        B.cgx_render_backward(self.ctx, views, scene, self.cap, self.ws, out, grad_out, grads)
+        if state is None:
+            B.cgx_render_backward(self.ctx, views, scene, self.cap, self.ws, out, grad_out, grads)
+            return grads
+        if state["ctx"] is not self.ctx or state["tile"] != self.tile:
+            raise RuntimeError("the renderer's tile shape changed between this forward call and its "
+                               "backward call")
+        B.cgx_render_backward(self.ctx, views, scene, state["cap"], state["ws"], out, grad_out, grads)
         return grads
+
+    def take_state(self):
+        """Detach the forward state of the last forward call (its workspace,
+        capacities and tile shape) from the renderer: the next forward call
+        gets a workspace of its own, so the detached state stays valid for a
+        later backward call."""
+        state = dict(ws=self.ws, cap=dict(self.cap), tile=self.tile, ctx=self.ctx)
+        self.ws = None
+        return state
 
     def fwd_bwd_l1(self, views, scene, target, weights=(1.0, 1.0, 1.0), out=None, grads=None,
                    loss=None, check=True):
@@ -328,15 +345,19 @@ _EXPLICIT_KEYS = ("means", "scales", "quats", "opacity", "sh")
 class RenderExplicit(torch.autograd.Function):
     """Differentiable render of explicit Gaussians: returns the packed
     (rgb, depth, plane_d, normal, alpha) images; the backward pass runs the
-    library's reverse-order rasterizer and projection adjoint."""
+    library's reverse-order rasterizer and projection adjoint on the
+    forward state of this very call (kept per call, so several forward calls
+    may precede their backward calls)."""
 
     @staticmethod
     def forward(ctx, renderer, views, sh_degree, means, scales, quats, opacity, sh):
-        scene = dict(kind=B.CGX_SCENE_EXPLICIT, means=means.contiguous(), scales=scales.contiguous(),
-                     quats=quats.contiguous(), opacity=opacity.contiguous(), sh=sh.contiguous(),
+        scene = dict(kind=B.CGX_SCENE_EXPLICIT, means=means.detach().contiguous(),
+                     scales=scales.detach().contiguous(), quats=quats.detach().contiguous(),
+                     opacity=opacity.detach().contiguous(), sh=sh.detach().contiguous(),
                      sh_degree=sh_degree)
         out = renderer.forward(views, scene)
         ctx.renderer, ctx.views, ctx.scene, ctx.out = renderer, views, scene, out
+        ctx.state = renderer.take_state()
         return out["rgb"], out["depth"], out["plane_d"], out["normal"], out["alpha"]
 
     @staticmethod
@@ -344,7 +365,8 @@ class RenderExplicit(torch.autograd.Function):
         c = lambda t: None if t is None else t.contiguous()   # noqa: E731
         gout = dict(rgb=c(g_rgb), depth=c(g_depth), plane_d=c(g_plane), normal=c(g_normal),
                     alpha=c(g_alpha))
-        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout)
+        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout, state=ctx.state)
+        ctx.state = None
         return (None, None, None) + tuple(grads[k] for k in _EXPLICIT_KEYS)
 
 
@@ -352,18 +374,22 @@ _ANCHOR_KEYS = ("x", "l", "O", "F", "b1", "b2")
 
 
 class RenderAnchor(torch.autograd.Function):
-    """Differentiable render of voxel anchors (decoder weights W1, W2 are
-    bfloat16 bit tensors; their gradients are returned through the float
-    tensors passed as W1_like / W2_like)."""
+    """Differentiable render of voxel anchors.  meta holds the non-trainable
+    parts: level (uint8), the decoder weights W1, W2 as bfloat16 bit tensors,
+    n_levels, d_max and opacity_act; the gradients of W1 and W2 are returned
+    through the float tensors passed as W1f / W2f (their values are not
+    read: the weights are the bfloat16 bits).  The forward state is kept per
+    call, as for RenderExplicit."""
 
     @staticmethod
     def forward(ctx, renderer, views, meta, x, l, O, F, b1, b2, W1f, W2f):
-        scene = dict(kind=B.CGX_SCENE_ANCHOR, x=x.contiguous(), l=l.contiguous(), O=O.contiguous(),
-                     F=F.contiguous(), level=meta["level"], W1=meta["W1"], W2=meta["W2"],
-                     b1=b1.contiguous(), b2=b2.contiguous(), n_levels=meta["n_levels"],
-                     d_max=meta["d_max"])
+        d = lambda t: t.detach().contiguous()   # noqa: E731
+        scene = dict(kind=B.CGX_SCENE_ANCHOR, x=d(x), l=d(l), O=d(O), F=d(F), level=meta["level"],
+                     W1=meta["W1"], W2=meta["W2"], b1=d(b1), b2=d(b2), n_levels=meta["n_levels"],
+                     d_max=meta["d_max"], opacity_act=int(meta.get("opacity_act", B.OPACITY_SIGMOID)))
         out = renderer.forward(views, scene)
         ctx.renderer, ctx.views, ctx.scene, ctx.out = renderer, views, scene, out
+        ctx.state = renderer.take_state()
         return out["rgb"], out["depth"], out["plane_d"], out["normal"], out["alpha"]
 
     @staticmethod
@@ -371,5 +397,6 @@ class RenderAnchor(torch.autograd.Function):
         c = lambda t: None if t is None else t.contiguous()   # noqa: E731
         gout = dict(rgb=c(g_rgb), depth=c(g_depth), plane_d=c(g_plane), normal=c(g_normal),
                     alpha=c(g_alpha))
-        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout)
+        grads = ctx.renderer.backward(ctx.views, ctx.scene, ctx.out, gout, state=ctx.state)
+        ctx.state = None
         return (None, None, None) + tuple(grads[k] for k in _ANCHOR_KEYS) + (grads["W1"], grads["W2"])

@@ -1,5 +1,19 @@
 """Helpers shared by the GPU parity tests: run the HIP path through the C ABI
-and compare with the FP64 oracle on the same seeded inputs."""
+and compare with the FP64 oracle on the same seeded inputs.
+
+Near ties.  A decision fed by float32 on the GPU and float64 in the oracle
+(a box edge, the alpha threshold, the transmittance stop, the depth guard, a
+splat's normal axis) is a near tie when the oracle's margin is below the
+stated bound; then both outcomes are correct.  The oracle certifies every
+such tie and enumerates the outputs a pixel may take under them
+(`cands`); the GPU's pixel must equal one of those outputs.  Pixels with
+more ties than the oracle enumerates are excluded and counted, within a
+budget of 1e-4 of the compared pixels.  For gradients, the output gradients
+of the pixels with a tie (`frag_grad`) are zero on both sides (the linear
+losses of the gradient tests), so every gradient element is compared; the
+fused L1 tests, whose seed the GPU computes itself, give those pixels'
+share of each element as slack instead.
+"""
 import numpy as np
 
 RTOL = 1e-4          # images and gradients, relative (fp32 GPU vs fp64 oracle)
@@ -7,14 +21,16 @@ RTOL = 1e-4          # images and gradients, relative (fp32 GPU vs fp64 oracle)
 # the tensor.  Signed channels (normal x/y, gradients) are sums whose float32
 # error scales with the sum of |terms|, not with the net value, so elements
 # that cancel to a small fraction of the tensor's range get this slack.
-FLOOR = 1e-2
+FLOOR = 1e-3
 NORM_RTOL = 1e-5     # norm-wise relative error over the compared elements
+EXCL_BUDGET = 1e-4   # pixels excluded (more ties than enumerated), per compared pixel
 
 
-def check_close(name, got, ref, exclude=None, rtol=RTOL, floor=FLOOR, report=None, mag=None):
+def check_close(name, got, ref, exclude=None, rtol=RTOL, floor=FLOOR, report=None, mag=None,
+                quiet=False):
     """Element-wise |got - ref| <= rtol * max(m, floor * max|ref|) on every
-    element not excluded (excluded = touched by a fragile decision), where m
-    is |ref| or, for a blended signed quantity, the blend of |terms| (mag)."""
+    element not excluded, where m is |ref| or, for a blended signed quantity,
+    the blend of |terms| (mag)."""
     got = np.asarray(got, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     assert got.shape == ref.shape, (name, got.shape, ref.shape)
@@ -27,12 +43,17 @@ def check_close(name, got, ref, exclude=None, rtol=RTOL, floor=FLOOR, report=Non
     bad = (err > tol) & keep
     assert np.all(np.isfinite(got[keep])), f"{name}: non-finite values"
     rel = np.max(err[keep] / np.maximum(m[keep], floor * scale + 1e-300)) if keep.any() else 0.0
-    nrm = np.linalg.norm(ref[keep])
-    nrel = float(np.linalg.norm((got - ref)[keep]) / nrm) if nrm > 0 else float(np.linalg.norm(got[keep]))
+    # the norm-wise error is taken over the elements whose float32 error scale
+    # is their own size (a blend of |terms| more than 10x the net value, as at
+    # grazing incidence, is held to the element-wise bound only)
+    wc = keep & (m <= 10.0 * np.maximum(np.abs(ref), floor * scale))
+    nrm = np.linalg.norm(ref[wc])
+    nrel = float(np.linalg.norm((got - ref)[wc]) / nrm) if nrm > 0 else float(np.linalg.norm(got[wc]))
     if report is not None:
         report[name] = dict(max_rel=float(rel), norm_rel=nrel, excluded=int(ex.sum()), n=int(ref.size))
-    print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, "
-          f"excluded {int(ex.sum())}/{ref.size}", flush=True)
+    if not quiet:
+        print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, "
+              f"set aside {int(ex.sum())}/{ref.size}", flush=True)
     if bad.any():
         i = np.argmax(np.where(bad, err / np.maximum(tol, 1e-300), 0))
         raise AssertionError(f"{name}: {int(bad.sum())}/{keep.sum()} elements out of tolerance; "
@@ -41,89 +62,177 @@ def check_close(name, got, ref, exclude=None, rtol=RTOL, floor=FLOOR, report=Non
     return rel
 
 
-def oracle_images_packed(r, key, channels):
-    """Oracle per-view images packed like the library's planar layout."""
-    parts = []
-    for img in r.images:
-        a = img[key]
-        parts.append(a.reshape(channels, -1).ravel() if channels > 1 else a.ravel())
-    return np.concatenate(parts)
+# Image channels: (key in the library's output, key in the oracle image,
+# channels, columns of an oracle candidate row).  A candidate row holds
+# rgb 3, plane distance D, normal 3, alpha, unbiased depth, |normal| blend 3,
+# and the unbiased depth's error scale (|D^| times the cancellation of its
+# denominator s = -N . ray, the sum of |terms| over |s|).
+CHANNELS = (("rgb", "rgb", 3, slice(0, 3)), ("plane_d", "D", 1, slice(3, 4)),
+            ("normal", "normal", 3, slice(4, 7)), ("alpha", "alpha", 1, slice(7, 8)),
+            ("depth", "depth", 1, slice(8, 9)))
+NABS = slice(9, 12)
+DMAG = slice(12, 13)
 
 
-def oracle_mask_packed(r, key, channels):
-    parts = []
-    for img in r.images:
-        m = img[key]
-        parts.append(np.tile(m, channels) if channels > 1 else m)
-    return np.concatenate(parts)
+def _np(a):
+    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
 
 
-def compare_images(out, r, report=None):
-    """out: dict of packed GPU images (torch or numpy); r: oracle result."""
-    chans = dict(rgb=("rgb", 3), depth=("depth", 1), plane_d=("D", 1), normal=("normal", 3),
-                 alpha=("alpha", 1))
-    for k, (ok, c) in chans.items():
-        g = out[k].detach().cpu().numpy() if hasattr(out[k], "detach") else out[k]
-        mag = oracle_images_packed(r, "normal_abs", 3) if k == "normal" else None
-        check_close(k, g, oracle_images_packed(r, ok, c), image_fragile(r, k, c),
-                    report=report, mag=mag)
+def _gather(out, r, covered_only):
+    """Per channel: GPU and oracle values (pixels x channels) over the
+    compared pixels of every view, with the tie / exclusion masks and the
+    global pixel ids (view, pixel)."""
+    pix_off = r.layout["pix_off"]
+    res = {}
+    ids = []
+    for v, img in enumerate(r.images):
+        HW = img["depth"].size
+        pix = np.nonzero(img["covered"])[0] if covered_only else np.arange(HW)
+        ids.append(np.stack([np.full(pix.size, v), pix], 1))
+    ids = np.concatenate(ids)
+    for key, okey, c, _ in CHANNELS:
+        g = _np(out[key]).astype(np.float64)
+        gv, rv = [], []
+        for v, img in enumerate(r.images):
+            HW = img["depth"].size
+            pix = ids[ids[:, 0] == v, 1]
+            base = c * int(pix_off[v])
+            gv.append(np.stack([g[base + ch * HW + pix] for ch in range(c)], 1))
+            a = img[okey].reshape(c, HW) if c > 1 else img[okey].reshape(1, HW)
+            rv.append(a[:, pix].T)
+        res[key] = (np.concatenate(gv), np.concatenate(rv))
+    nab = np.concatenate([img["normal_abs"].reshape(3, -1)[:, ids[ids[:, 0] == v, 1]].T
+                          for v, img in enumerate(r.images)])
+    dmag = np.concatenate([img["depth_mag"][ids[ids[:, 0] == v, 1]][:, None]
+                           for v, img in enumerate(r.images)])
+    tie = np.concatenate([img["tie"][ids[ids[:, 0] == v, 1]] for v, img in enumerate(r.images)])
+    excl = np.concatenate([img["excl"][ids[ids[:, 0] == v, 1]] for v, img in enumerate(r.images)])
+    return res, nab, dmag, tie, excl, ids
 
 
-GEOMETRIC = ("normal", "plane_d", "depth")
+def compare_images(out, r, report=None, covered_only=False):
+    """out: dict of packed GPU images (torch or numpy) for the views of the
+    oracle result r.  Pixels without a near tie are compared element-wise
+    with the oracle's own outputs; a pixel with ties must match one of the
+    oracle's candidate outputs in every channel; pixels with more ties than
+    enumerated are excluded, within EXCL_BUDGET.  Returns the counts."""
+    res, nab, dmag, tie, excl, ids = _gather(out, r, covered_only)
+    npx = ids.shape[0]
+    aside = tie | excl
+    scales = {}
+    for key, okey, c, _ in CHANNELS:
+        got, ref = res[key]
+        mag = nab if key == "normal" else (dmag if key == "depth" else None)
+        check_close(key, got, ref, np.repeat(aside[:, None], c, 1), report=report, mag=mag)
+        keep = ~aside
+        scales[key] = np.max(np.abs(ref[keep])) if keep.any() else 0.0
+    # tie pixels: one of the oracle's candidates, all channels at once
+    worst = 0.0
+    for i in np.nonzero(tie & ~excl)[0]:
+        v, p = ids[i]
+        C = r.images[v]["cands"][int(p)]
+        ok = np.ones(C.shape[0], bool)
+        ratio = np.zeros(C.shape[0])
+        for key, okey, c, cols in CHANNELS:
+            g = res[key][0][i]
+            ref = C[:, cols]
+            m = np.abs(ref)
+            if key == "normal":
+                m = np.maximum(m, C[:, NABS])
+            if key == "depth":
+                m = np.maximum(m, C[:, DMAG])
+            tol = RTOL * np.maximum(m, FLOOR * scales[key]) + 1e-300
+            q = np.max(np.abs(g[None] - ref) / tol, axis=1)
+            ratio = np.maximum(ratio, q)
+        best = float(ratio.min())
+        assert best <= 1.0, (f"pixel {p} of view {v}: no oracle outcome of its {C.shape[0]} "
+                             f"candidates matches (best error {best:.3g} x tolerance); "
+                             f"got rgb {res['rgb'][0][i]} alpha {res['alpha'][0][i]}")
+        worst = max(worst, best)
+        assert ok.any()
+    n_tie, n_ex = int((tie & ~excl).sum()), int(excl.sum())
+    print(f"  near-tie pixels matched to an oracle outcome: {n_tie}/{npx} (worst {worst:.2f} x tol); "
+          f"excluded {n_ex}", flush=True)
+    assert n_ex <= EXCL_BUDGET * npx, f"excluded pixels {n_ex} > {EXCL_BUDGET} of {npx}"
+    if report is not None:
+        report["pixels"] = dict(n=npx, ties=n_tie, excluded=n_ex)
+    return dict(n=npx, ties=n_tie, excluded=n_ex)
 
 
-def image_fragile(r, key, channels):
-    """Packed mask of pixels with a fragile decision for output `key`: the
-    geometric outputs also exclude pixels whose splat normal is fragile."""
-    m = oracle_mask_packed(r, "frag", channels)
-    if key in GEOMETRIC:
-        m = m | oracle_mask_packed(r, "frag_geom", channels)
-    return m
+def compare_sorted(dbg, r, slot_to_view_gid, tiles=None):
+    """Sorted pairs, nothing dropped.  For every tile (or the given global
+    tiles) the GPU's list must hold every pair the oracle is certain of, only
+    pairs the oracle lists (its own, or one near tie away), with depth keys
+    bit-identical to the oracle's, in (depth bits, view, id) order, with the
+    ranges of the GPU's sorted tile ids.  Returns (pairs checked, near-tie
+    pairs the GPU took, near-tie pairs it left)."""
+    gt = dbg["tile"].astype(np.int64)
+    gz = dbg["zbits"].astype(np.int64)
+    slots = dbg["slot"].astype(np.int64)
+    gr = dbg["ranges"].astype(np.int64)
+    o = r.sorted
+    n_tiles = o["ranges"].shape[0]
+    if tiles is None:
+        tiles = np.arange(n_tiles)
+        assert np.all(np.diff(gt) >= 0), "GPU tile ids not sorted"
+        starts = np.searchsorted(gt, np.arange(n_tiles), side="left")
+        ends = np.searchsorted(gt, np.arange(n_tiles), side="right")
+        want = np.stack([np.where(ends > starts, starts, 0), np.where(ends > starts, ends, 0)], 1)
+        # an empty tile's range may be any [s, s)
+        norm = np.where((gr[:, 1] > gr[:, 0])[:, None], gr, 0)
+        np.testing.assert_array_equal(norm, want, err_msg="tile ranges")
+    n_checked = n_took = n_left = 0
+    for t in tiles:
+        t = int(t)
+        g0, g1 = gr[t]
+        g1 = max(g1, g0)
+        o0, o1 = o["ranges"][t]
+        assert np.all(gt[g0:g1] == t), f"tile {t}: foreign pairs in its range"
+        v, gid = slot_to_view_gid(slots[g0:g1])
+        got = np.stack([gz[g0:g1], v, gid], 1)
+        # the GPU list is in (depth bits, view, id) order
+        order = np.lexsort((got[:, 2], got[:, 1], got[:, 0]))
+        np.testing.assert_array_equal(order, np.arange(got.shape[0]), err_msg=f"tile {t}: order")
+        ref = np.stack([o["zbits"][o0:o1].astype(np.int64), o["view"][o0:o1], o["gid"][o0:o1]], 1)
+        own, cert = o["own"][o0:o1], o["certain"][o0:o1]
+        rk = {(int(a), int(b)): i for i, (a, b) in enumerate(ref[:, 1:])}
+        idx = np.array([rk.get((int(a), int(b)), -1) for a, b in got[:, 1:]], np.int64)
+        assert np.all(idx >= 0), (f"tile {t}: GPU pairs the oracle does not list: "
+                                  f"{got[idx < 0][:5].tolist()}")
+        np.testing.assert_array_equal(got[:, 0], ref[idx, 0], err_msg=f"tile {t}: depth keys")
+        taken = np.zeros(ref.shape[0], bool)
+        taken[idx] = True
+        assert np.all(taken[cert]), (f"tile {t}: GPU lacks certain pairs "
+                                     f"{ref[cert & ~taken][:5].tolist()}")
+        n_checked += got.shape[0]
+        n_took += int((taken & ~cert).sum())
+        n_left += int((~taken & own & ~cert).sum())
+    return n_checked, n_took, n_left
 
 
 def compare_sort_explicit(dbg, r, N):
-    """Sorted pairs: bit-exact against the oracle's (tile, depth bits, view,
-    id) order, after dropping the pairs of splats with a fragile tile set."""
-    slot = dbg["slot"].astype(np.int64)
-    g_view, g_id = slot // N, slot % N
-    frag = np.zeros((len(r.splats), N), bool)
-    for v, S in enumerate(r.splats):
-        frag[v] = S["frag_value"]
-    keep_g = ~frag[g_view, g_id]
-    o = r.sorted
-    keep_o = ~frag[o["view"], o["gid"]]
-    got = np.stack([dbg["tile"].astype(np.int64)[keep_g], dbg["zbits"].astype(np.int64)[keep_g],
-                    g_view[keep_g], g_id[keep_g]], 1)
-    ref = np.stack([o["gtile"][keep_o], o["zbits"].astype(np.int64)[keep_o], o["view"][keep_o],
-                    o["gid"][keep_o]], 1)
-    assert got.shape == ref.shape, (got.shape, ref.shape)
-    np.testing.assert_array_equal(got, ref)
-    if not frag.any():
-        np.testing.assert_array_equal(dbg["ranges"].astype(np.int64), o["ranges"])
-    return int((~keep_g).sum())
+    """Explicit scenes: slot = view * N + Gaussian."""
+    n, took, left = compare_sorted(dbg, r, lambda s: (s // N, s % N))
+    assert n == int(dbg["tile"].size), (n, dbg["tile"].size)
+    print(f"  sorted pairs: {n} bit-exact (near-tie pairs taken {took}, left {left})", flush=True)
+    return n
 
 
 def compare_sort_anchor(dbg, r, n_off):
-    """Anchor path: rows bit-exact; sorted pairs bit-exact after mapping each
-    slot (row * n + k) to its view-local id (row - first row of the view) * n + k
-    and dropping the pairs of splats with a fragile tile set."""
+    """Anchor path: rows bit-exact; each slot (row * n + k) maps to its
+    view-local id (row - first row of the view) * n + k."""
     rows = dbg["rows"].astype(np.int64)
     np.testing.assert_array_equal(rows, r.rows)
-    slot = dbg["slot"].astype(np.int64)
-    row, k = slot // n_off, slot % n_off
-    view = rows[row, 0]
-    gid = (row - r.row_off[view]) * n_off + k
-    frag = [S["frag_value"] for S in r.splats]
-    keep_g = np.array([not frag[v][g] for v, g in zip(view, gid)], bool)
-    o = r.sorted
-    keep_o = np.array([not frag[v][g] for v, g in zip(o["view"], o["gid"])], bool)
-    got = np.stack([dbg["tile"].astype(np.int64)[keep_g], dbg["zbits"].astype(np.int64)[keep_g],
-                    view[keep_g], gid[keep_g]], 1)
-    ref = np.stack([o["gtile"][keep_o], o["zbits"].astype(np.int64)[keep_o], o["view"][keep_o],
-                    o["gid"][keep_o]], 1)
-    assert got.shape == ref.shape, (got.shape, ref.shape)
-    np.testing.assert_array_equal(got, ref)
-    return int((~keep_g).sum())
+
+    def s2vg(slot):
+        row, k = slot // n_off, slot % n_off
+        view = rows[row, 0]
+        return view, (row - r.row_off[view]) * n_off + k
+
+    n, took, left = compare_sorted(dbg, r, s2vg)
+    assert n == int(dbg["tile"].size), (n, dbg["tile"].size)
+    print(f"  sorted pairs: {n} bit-exact (near-tie pairs taken {took}, left {left})", flush=True)
+    return n
 
 
 # ---------------------------------------------------------------------------
@@ -132,23 +241,28 @@ def compare_sort_anchor(dbg, r, n_off):
 SENS_EPS = 2.0 ** -24      # relative input perturbation of float32 rounding size
 SENS_K = 16.0              # float32 rounding events the GPU chain may accumulate per input one
 GRAD_NORM_RTOL = 1e-4
+MIN_WELL = 0.9             # well-conditioned share of the elements that must be met
 
 
-def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=None):
+def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=None,
+               min_well=MIN_WELL):
     """|got - ref| <= rtol * max(|ref|, floor * max|ref|) + slack, where delta
     is a dict {"sens": d, "frag": f}: d is how far the FP64 oracle's own
     gradient moves when every float input is perturbed at float32 rounding
     size (the element's conditioning) and f is the share of the element that
-    comes from pixels with a fragile decision; slack = SENS_K d + 2 f.  The
-    norm-wise relative error must also stay <= GRAD_NORM_RTOL."""
+    comes from pixels with a near tie (zero when their output gradients are
+    zero); slack = SENS_K d + 2 f.  At least min_well of the elements must
+    be well conditioned (slack below the relative bound), and over those the
+    norm-wise relative error must stay <= GRAD_NORM_RTOL."""
     if isinstance(delta, dict):
-        delta = SENS_K * np.asarray(delta["sens"], np.float64) + 2.0 * np.asarray(delta["frag"], np.float64)
+        frag = np.asarray(delta.get("frag", 0.0), np.float64)
+        delta = SENS_K * np.asarray(delta["sens"], np.float64) + 2.0 * frag
     else:
         delta = SENS_K * np.asarray(delta, np.float64)
     got = np.asarray(got, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
-    d = np.asarray(delta, np.float64).ravel()
-    assert got.shape == ref.shape == d.shape, (name, got.shape, ref.shape, d.shape)
+    d = np.broadcast_to(np.asarray(delta, np.float64).ravel(), ref.shape)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
     ex = np.zeros(ref.shape, bool) if exclude is None else np.asarray(exclude, bool).ravel()
     keep = ~ex
     scale = np.max(np.abs(ref[keep])) if keep.any() else 0.0
@@ -162,19 +276,32 @@ def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=No
     nrm = np.linalg.norm(ref[wc])
     nrel = float(np.linalg.norm((got - ref)[wc]) / nrm) if nrm > 0 else float(np.linalg.norm(got[wc]))
     cond = int((keep & ~wc).sum())
+    nb = int((keep & ((ref != 0) | (got != 0))).sum())
     print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, excluded "
-          f"{int(ex.sum())}/{ref.size}, ill-conditioned {cond}", flush=True)
+          f"{int(ex.sum())}/{ref.size}, gradient-bearing {nb}, ill-conditioned {cond}", flush=True)
+    if report is not None:
+        report[name] = dict(max_rel=float(rel), norm_rel=nrel, excluded=int(ex.sum()),
+                            ill=cond, n=int(ref.size))
     if bad.any():
         i = np.argmax(np.where(bad, err / np.maximum(tol, 1e-300), 0))
         raise AssertionError(f"{name}: {int(bad.sum())}/{keep.sum()} elements out of tolerance; "
                              f"worst idx {i}: got {got[i]!r} ref {ref[i]!r} tol {tol[i]:.3g} "
                              f"delta {d[i]:.3g}")
+    # the elements that carry a gradient (on either side) must be mostly well
+    # conditioned, so that the norm-wise check is not over an empty set
+    bearing = keep & ((ref != 0) | (got != 0))
+    if bearing.any():
+        assert (wc & bearing).sum() >= min_well * bearing.sum(), (
+            f"{name}: only {int((wc & bearing).sum())}/{int(bearing.sum())} gradient-bearing "
+            f"elements well conditioned")
     assert nrel <= GRAD_NORM_RTOL, f"{name}: norm-wise relative error {nrel:.3g}"
     return rel
 
 
-def _without_fragile(r, og):
-    """Output gradients with the pixels of fragile decisions zeroed."""
+def zero_ties(r, og):
+    """Output gradients with the pixels of near-tie decisions zeroed: the
+    linear loss of a gradient test then has no term whose gradient depends on
+    a tie's outcome."""
     out = []
     for img, g in zip(r.images, og):
         m = img["frag_grad"]
@@ -190,6 +317,43 @@ def _without_fragile(r, og):
     return out
 
 
+def tie_fraction(r):
+    """Share of the composited pixels whose output gradients a tie zeroes."""
+    n = sum(int(img["covered"].sum()) for img in r.images)
+    t = sum(int((img["frag_grad"] & img["covered"]).sum()) for img in r.images)
+    return t / max(n, 1)
+
+
+# kept for the older name used by the full-size tests
+_without_fragile = zero_ties
+
+
+def linear_grads(r, rng, covered_only=False):
+    """Linear-loss output gradients w ~ N(0, 1) on every output, zero at the
+    pixels with a near tie (and, with covered_only, outside the composited
+    tiles)."""
+    out = []
+    for img in r.images:
+        npx = img["depth"].size
+        m = img["covered"] if covered_only else np.ones(npx, bool)
+        g = dict(rgb=rng.standard_normal((3, npx)) * m, depth=rng.standard_normal(npx) * m,
+                 D=rng.standard_normal(npx) * m, normal=rng.standard_normal((3, npx)) * m,
+                 alpha=rng.standard_normal(npx) * m)
+        out.append(g)
+    return zero_ties(r, out)
+
+
+def packed_grads(og, device="cuda"):
+    """Per-view oracle output gradients packed like the library's images."""
+    import torch
+    d = {}
+    for key, okey in (("rgb", "rgb"), ("depth", "depth"), ("plane_d", "D"), ("normal", "normal"),
+                      ("alpha", "alpha")):
+        d[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
+                                 device=device)
+    return d
+
+
 def _perturbed(a, rng):
     a = np.asarray(a)
     if a.dtype.kind != "f":
@@ -197,41 +361,64 @@ def _perturbed(a, rng):
     return (a.astype(np.float64) * (1.0 + SENS_EPS * rng.standard_normal(a.shape)))
 
 
-def explicit_sensitivity(scene, views, og, tile=(16, 16), seed=4321):
-    """|g(inputs) - g(inputs perturbed at float32 rounding size)| of the
-    oracle, per gradient element (explicit scenes)."""
+EXPLICIT_KEYS = ("means", "scales", "quats", "opacity", "sh")
+ANCHOR_KEYS = ("x", "l", "O", "F", "W1", "b1", "W2", "b2")
+
+
+def explicit_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), keep_tiles=None,
+                         r0=None):
+    """Per gradient element: the larger response of the oracle's gradient to
+    two independent float32-size perturbations of every float input (one
+    draw can miss an element's worst direction), and the share of the
+    element from pixels with a near tie."""
     import copy
 
     from oracle import pipeline
-    rng = np.random.default_rng(seed)
-    r0 = pipeline.render_explicit(scene, views, tile=tile)
+    r0 = r0 or pipeline.render_explicit(scene, views, tile=tile, keep_tiles=keep_tiles)
     g0, _ = pipeline.backward(r0, og, scene)
-    sc = copy.copy(scene)
-    for k in ("means", "scales", "quats", "opacity", "sh"):
-        setattr(sc, k, _perturbed(getattr(scene, k), rng))
-    r1 = pipeline.render_explicit(sc, views, tile=tile)
-    g1, _ = pipeline.backward(r1, og, sc)
-    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), scene)
-    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
-            for k in ("means", "scales", "quats", "opacity", "sh")}
+    sens = None
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        sc = copy.copy(scene)
+        for k in EXPLICIT_KEYS:
+            setattr(sc, k, _perturbed(getattr(scene, k), rng))
+        r1 = pipeline.render_explicit(sc, views, tile=tile, keep_tiles=keep_tiles)
+        g1, _ = pipeline.backward(r1, og, sc)
+        d = {k: np.abs(g0[k] - g1[k]) for k in EXPLICIT_KEYS}
+        sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    g2, _ = pipeline.backward(r0, zero_ties(r0, og), scene)
+    return {k: dict(sens=sens[k], frag=np.abs(g0[k] - g2[k])) for k in EXPLICIT_KEYS}
 
 
-def anchor_sensitivity(scene, views, og, tile=(16, 16), seed=4321):
+def anchor_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), keep_tiles=None,
+                       r0=None):
     """Same for anchor scenes (features, offsets, positions, scalings,
     biases and the decoder weights' values)."""
     import copy
 
     from oracle import pipeline
-    rng = np.random.default_rng(seed)
-    r0 = pipeline.render_anchor(scene, views, tile=tile)
+    r0 = r0 or pipeline.render_anchor(scene, views, tile=tile, keep_tiles=keep_tiles)
     g0, _ = pipeline.backward(r0, og, scene)
-    sc = copy.copy(scene)
-    for k in ("x", "l", "O", "b1", "b2"):
-        setattr(sc, k, _perturbed(getattr(scene, k), rng))
-    sc.W1_exact = _perturbed(scene.W1, rng)
-    sc.W2_exact = _perturbed(scene.W2, rng)
-    r1 = pipeline.render_anchor(sc, views, tile=tile)
-    g1, _ = pipeline.backward(r1, og, sc)
-    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), scene)
-    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
-            for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
+    sens = None
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        sc = copy.copy(scene)
+        for k in ("x", "l", "O", "b1", "b2"):
+            setattr(sc, k, _perturbed(getattr(scene, k), rng))
+        sc.W1_exact = _perturbed(scene.W1, rng)
+        sc.W2_exact = _perturbed(scene.W2, rng)
+        r1 = pipeline.render_anchor(sc, views, tile=tile, keep_tiles=keep_tiles)
+        g1, _ = pipeline.backward(r1, og, sc)
+        d = {k: np.abs(g0[k] - g1[k]) for k in ANCHOR_KEYS}
+        sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    g2, _ = pipeline.backward(r0, zero_ties(r0, og), scene)
+    return {k: dict(sens=sens[k], frag=np.abs(g0[k] - g2[k])) for k in ANCHOR_KEYS}
+
+
+def oracle_images_packed(r, key, channels):
+    """Oracle per-view images packed like the library's planar layout."""
+    parts = []
+    for img in r.images:
+        a = img[key]
+        parts.append(a.reshape(channels, -1).ravel() if channels > 1 else a.ravel())
+    return np.concatenate(parts)

@@ -1,13 +1,15 @@
 """GPU parity of the voxel-anchor path (a0, a1, a2-a10) against the FP64
-oracle through the C ABI: active rows and sorted pairs bit-exact, images
-and gradients within 1e-4 relative (floored)."""
+oracle through the C ABI: active rows and sorted pairs bit-exact (nothing
+dropped), images and gradients within 1e-4 relative (floored), near ties
+resolved by the oracle's enumeration of their outcomes."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import check_grad, compare_images, compare_sort_anchor, anchor_sensitivity
+from tests.parity import (anchor_sensitivity, check_grad, compare_images, compare_sort_anchor,
+                          linear_grads, packed_grads, tie_fraction)
 
 pytestmark = pytest.mark.gpu
 
@@ -18,12 +20,9 @@ def R():
     return render
 
 
-def _anchor_grads_check(gr, ref, n_off, delta):
-    fa = ref["frag"]
-    for k, c in (("x", 3), ("l", 3), ("O", 3 * n_off), ("F", 32)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c), delta[k])
-    for k in ("W1", "b1", "W2", "b2"):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k])
+def _anchor_grads_check(gr, ref, delta, report=None):
+    for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k], report=report)
 
 
 @pytest.mark.parametrize("seed,tile", [(11, (16, 16)), (12, (8, 8)), (13, (32, 8))])
@@ -52,17 +51,12 @@ def _anchor_fwd_bwd(R, wl, seed, tile):
     assert r.rows.shape[0] > 20
     compare_sort_anchor(rd.debug(), r, 10)
     compare_images(out, r)
-    rng = np.random.default_rng(seed)
-    L, og = pipeline.output_grads_linear(r, rng)
+    og = linear_grads(r, np.random.default_rng(seed))
+    print(f"  output gradients zeroed on {tie_fraction(r):.2e} of the pixels (near ties)", flush=True)
     ref, _ = pipeline.backward(r, og, wl.scene)
-    gout = {}
-    for key, okey in (("rgb", "rgb"), ("depth", "depth"), ("plane_d", "D"), ("normal", "normal"),
-                      ("alpha", "alpha")):
-        gout[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
-                                    device="cuda")
-    gr = rd.backward(wl.views, sc, out, gout)
+    gr = rd.backward(wl.views, sc, out, packed_grads(og))
     torch.cuda.synchronize()
-    _anchor_grads_check(gr, ref, 10, anchor_sensitivity(wl.scene, wl.views, og, tile=tile))
+    _anchor_grads_check(gr, ref, anchor_sensitivity(wl.scene, wl.views, og, tile=tile, r0=r))
 
 
 def test_small_anchor_fused_l1(R):
@@ -80,7 +74,9 @@ def test_small_anchor_fused_l1(R):
     L, og = pipeline.output_grads_l1(r, wl.targets, (1.0, 0.5, 0.25))
     ref, _ = pipeline.backward(r, og, wl.scene)
     assert abs(loss.item() - L) <= 1e-4 * abs(L)
-    _anchor_grads_check(gr, ref, 10, anchor_sensitivity(wl.scene, wl.views, og))
+    # the GPU seeds the L1 gradient from its own images: the pixels with a
+    # near tie give their share of each element as slack
+    _anchor_grads_check(gr, ref, anchor_sensitivity(wl.scene, wl.views, og, r0=r))
 
 
 def test_anchor_capacity_overflow_reported(R):

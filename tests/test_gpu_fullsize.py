@@ -3,8 +3,10 @@
 The whole workload is rendered on the GPU in the benchmark's launch
 configuration; the oracle selects, decodes and projects everything but bins,
 sorts and composites only the sampled tiles.  The backward pass is driven
-by a linear loss that is non-zero only on the sampled tiles' pixels, so
-every gradient the GPU returns comes from pixels the oracle also computes.
+by a linear loss that is non-zero only on the sampled tiles' pixels (and
+zero at the pixels with a near-tie decision), so every gradient the GPU
+returns comes from pixels the oracle also computes, and every gradient
+element is compared.
 """
 import numpy as np
 import pytest
@@ -12,8 +14,8 @@ import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import (check_close, check_grad, image_fragile, oracle_images_packed,
-                          oracle_mask_packed)
+from tests.parity import (anchor_sensitivity, check_grad, compare_images, compare_sorted,
+                          explicit_sensitivity, linear_grads, packed_grads, tie_fraction)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,56 +26,17 @@ def _sample_tiles(layout, n, seed):
     return np.sort(rng.choice(total, min(n, total), replace=False))
 
 
-def _masked_linear_grads(r, rng):
-    """Linear-loss output gradients, zero outside the composited tiles."""
-    out = []
-    for img in r.images:
-        npx = img["depth"].size
-        m = img["covered"]
-        g = dict(rgb=rng.standard_normal((3, npx)) * m, depth=rng.standard_normal(npx) * m,
-                 D=rng.standard_normal(npx) * m, normal=rng.standard_normal((3, npx)) * m,
-                 alpha=rng.standard_normal(npx) * m)
-        out.append(g)
-    return out
+def _anchor_slot_map(rows, r, n_off=10):
+    def s2vg(slots):
+        row, k = slots // n_off, slots % n_off
+        v = rows[row, 0]
+        return v, (row - r.row_off[v]) * n_off + k
+    return s2vg
 
 
-def _to_device(og):
-    d = {}
-    for key, okey in (("rgb", "rgb"), ("depth", "depth"), ("plane_d", "D"), ("normal", "normal"),
-                      ("alpha", "alpha")):
-        d[key] = torch.as_tensor(np.concatenate([g[okey].ravel() for g in og]).astype(np.float32),
-                                 device="cuda")
-    return d
-
-
-def _compare_sampled(out, r, keep):
-    """Images on the sampled tiles' pixels only."""
-    for key, okey, c in (("rgb", "rgb", 3), ("depth", "depth", 1), ("plane_d", "D", 1),
-                         ("normal", "normal", 3), ("alpha", "alpha", 1)):
-        got = out[key].cpu().numpy()
-        ref = oracle_images_packed(r, okey, c)
-        cov = oracle_mask_packed(r, "covered", c)
-        frag = image_fragile(r, key, c)
-        mag = oracle_images_packed(r, "normal_abs", 3)[cov] if key == "normal" else None
-        check_close(key, got[cov], ref[cov], frag[cov], mag=mag)
-
-
-def _compare_sorted_sample(dbg, r, keep, slot_to_view_gid):
-    n_checked = 0
-    for t in keep:
-        g0, g1 = dbg["ranges"][t]
-        o0, o1 = r.sorted["ranges"][t]
-        slots = dbg["slot"][g0:g1].astype(np.int64)
-        v, gid = slot_to_view_gid(slots)
-        frag_g = np.array([r.splats[a]["frag_value"][b] for a, b in zip(v, gid)], bool)
-        ov, og = r.sorted["view"][o0:o1], r.sorted["gid"][o0:o1]
-        frag_o = np.array([r.splats[a]["frag_value"][b] for a, b in zip(ov, og)], bool)
-        got = np.stack([dbg["zbits"][g0:g1].astype(np.int64), v, gid], 1)[~frag_g]
-        ref = np.stack([r.sorted["zbits"][o0:o1].astype(np.int64), ov, og], 1)[~frag_o]
-        np.testing.assert_array_equal(got, ref, err_msg=f"tile {t}")
-        assert np.all(dbg["tile"][g0:g1] == t)
-        n_checked += len(ref)
-    return n_checked
+def _check_anchor_grads(gr, ref, delta):
+    for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k])
 
 
 def test_c2_full_size_sampled_tiles():
@@ -89,67 +52,17 @@ def test_c2_full_size_sampled_tiles():
     keep = _sample_tiles(layout, 24, seed=2024)
     r = pipeline.render_anchor(wl.scene, wl.views, keep_tiles=keep)
     np.testing.assert_array_equal(dbg["rows"].astype(np.int64), r.rows)
-    rows = r.rows
-
-    def s2vg(slots):
-        row, k = slots // 10, slots % 10
-        v = rows[row, 0]
-        return v, (row - r.row_off[v]) * 10 + k
-
-    n = _compare_sorted_sample(dbg, r, keep, s2vg)
+    n, took, left = compare_sorted(dbg, r, _anchor_slot_map(r.rows, r), tiles=keep)
+    print(f"  sorted pairs of the sampled tiles: {n} bit-exact (near-tie taken {took}, left {left})")
     assert n > 1000
-    _compare_sampled(out, r, keep)
-    rng = np.random.default_rng(7)
-    og = _masked_linear_grads(r, rng)
+    compare_images(out, r, covered_only=True)
+    og = linear_grads(r, np.random.default_rng(7), covered_only=True)
+    print(f"  output gradients zeroed on {tie_fraction(r):.2e} of the pixels (near ties)", flush=True)
     ref, _ = pipeline.backward(r, og, wl.scene)
-    gr = rd.backward(wl.views, sc, out, _to_device(og))
+    gr = rd.backward(wl.views, sc, out, packed_grads(og))
     torch.cuda.synchronize()
-    d2 = _sampled_sensitivity_anchor(wl, keep, og)
-    fa = ref["frag"]
-    for k, c in (("x", 3), ("l", 3), ("O", 30), ("F", 32)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c), d2[k])
-    for k in ("W1", "b1", "W2", "b2"):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, d2[k])
-
-
-def _sampled_sensitivity_anchor(wl, keep, og):
-    import copy
-
-    from tests.parity import SENS_EPS, _perturbed, _without_fragile
-    rng = np.random.default_rng(4321)
-    r0 = pipeline.render_anchor(wl.scene, wl.views, keep_tiles=keep)
-    g0, _ = pipeline.backward(r0, og, wl.scene)
-    sc = copy.copy(wl.scene)
-    for k in ("x", "l", "O", "b1", "b2"):
-        setattr(sc, k, _perturbed(getattr(wl.scene, k), rng))
-    sc.W1_exact = _perturbed(wl.scene.W1, rng)
-    sc.W2_exact = _perturbed(wl.scene.W2, rng)
-    r1 = pipeline.render_anchor(sc, wl.views, keep_tiles=keep)
-    g1, _ = pipeline.backward(r1, og, sc)
-    g2, _ = pipeline.backward(r0, _without_fragile(r0, og), wl.scene)
-    assert SENS_EPS > 0
-    return {k: dict(sens=np.abs(g0[k] - g1[k]), frag=np.abs(g0[k] - g2[k]))
-            for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
-
-
-def _sens_two_draws(render, scene, views, keep, og, keys, ref):
-    """Conditioning of each gradient element: the larger response of the
-    oracle's gradient to two independent float32-size perturbations of every
-    float input (one draw can miss an element's worst direction)."""
-    import copy
-
-    from tests.parity import _perturbed
-    out = None
-    for seed in (4321, 8765):
-        rng = np.random.default_rng(seed)
-        sc = copy.copy(scene)
-        for k in keys:
-            setattr(sc, k, _perturbed(getattr(scene, k), rng))
-        r1 = render(sc, views, keep_tiles=keep)
-        g1, _ = pipeline.backward(r1, og, sc)
-        d = {k: np.abs(ref[k] - g1[k]) for k in ref if k != "frag"}
-        out = d if out is None else {k: np.maximum(out[k], d[k]) for k in d}
-    return out
+    d2 = anchor_sensitivity(wl.scene, wl.views, og, keep_tiles=keep, r0=r)
+    _check_anchor_grads(gr, ref, d2)
 
 
 def test_c1_full_size_sampled_tiles():
@@ -165,37 +78,24 @@ def test_c1_full_size_sampled_tiles():
     keep = _sample_tiles(layout, 20, seed=2025)
     r = pipeline.render_explicit(wl.scene, wl.views, keep_tiles=keep)
     N = wl.scene.n
-    n = _compare_sorted_sample(dbg, r, keep, lambda s: (s // N, s % N))
+    n, took, left = compare_sorted(dbg, r, lambda s: (s // N, s % N), tiles=keep)
+    print(f"  sorted pairs of the sampled tiles: {n} bit-exact (near-tie taken {took}, left {left})")
     assert n > 1000
-    _compare_sampled(out, r, keep)
-    rng = np.random.default_rng(8)
-    og = _masked_linear_grads(r, rng)
+    compare_images(out, r, covered_only=True)
+    og = linear_grads(r, np.random.default_rng(8), covered_only=True)
+    print(f"  output gradients zeroed on {tie_fraction(r):.2e} of the pixels (near ties)", flush=True)
     ref, _ = pipeline.backward(r, og, wl.scene)
-    gr = rd.backward(wl.views, sc, out, _to_device(og))
+    gr = rd.backward(wl.views, sc, out, packed_grads(og))
     torch.cuda.synchronize()
-    from tests.parity import _without_fragile
-    sens = _sens_two_draws(pipeline.render_explicit, wl.scene, wl.views, keep, og,
-                           ("means", "scales", "quats", "opacity", "sh"), ref)
-    g2, _ = pipeline.backward(r, _without_fragile(r, og), wl.scene)
-    fa = ref["frag"]
-    for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
-                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
-
-
-def _view0_compare(out, r, W, H):
-    """Images of view 0 (the first planes of the packed outputs) on the
-    pixels of the oracle's sampled tiles."""
-    n = W * H
-    view0 = {k: out[k][:c * n] for k, c in (("rgb", 3), ("depth", 1), ("plane_d", 1), ("normal", 3),
-                                          ("alpha", 1))}
-    _compare_sampled(view0, r, None)
+    delta = explicit_sensitivity(wl.scene, wl.views, og, keep_tiles=keep, r0=r)
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k])
 
 
 def _grads_view0(r, n_total, rng):
-    """Masked linear output gradients on view 0's sampled tiles, zero on the
-    other views, packed for the whole batch."""
-    og = _masked_linear_grads(r, rng)
+    """Linear output gradients on view 0's sampled tiles (zero at near ties),
+    zero on the other views, packed for the whole batch."""
+    og = linear_grads(r, rng, covered_only=True)
     g = og[0]
     n0 = g["depth"].size
     pad = n_total - n0
@@ -228,45 +128,20 @@ def _anchor_view0_case(wl, rd, sc, out, n_tiles, seed, tile=(16, 16)):
         assert np.all(v == 0)
         return v, (row - 0) * 10 + k       # view 0's rows come first
 
-    n = _compare_sorted_sample(dbg, r, keep, s2vg)
+    n, took, left = compare_sorted(dbg, r, s2vg, tiles=keep)
+    print(f"  sorted pairs of the sampled tiles: {n} bit-exact (near-tie taken {took}, left {left})")
     assert n > 500
-    _view0_compare(out, r, v0.width, v0.height)
+    W, H = v0.width, v0.height
+    view0 = {k: out[k][:c * W * H] for k, c in (("rgb", 3), ("depth", 1), ("plane_d", 1), ("normal", 3),
+                                              ("alpha", 1))}
+    compare_images(view0, r, covered_only=True)
     og, gdev = _grads_view0(r, int(out["depth"].numel()), np.random.default_rng(seed + 1))
+    print(f"  output gradients zeroed on {tie_fraction(r):.2e} of the pixels (near ties)", flush=True)
     ref, _ = pipeline.backward(r, og, wl.scene)
     gr = rd.backward(wl.views, sc, out, gdev)
     torch.cuda.synchronize()
-    from tests.parity import _without_fragile
-    sens = _anchor_sens_two_draws(wl.scene, [v0], keep, og, tile, ref)
-    g2, _ = pipeline.backward(r, _without_fragile(r, og), wl.scene)
-    fa = ref["frag"]
-    for k, c in (("x", 3), ("l", 3), ("O", 30), ("F", 32)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
-                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
-    for k in ("W1", "b1", "W2", "b2"):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None,
-                   dict(sens=sens[k], frag=np.abs(ref[k] - g2[k])))
-
-
-def _anchor_sens_two_draws(scene, views, keep, og, tile, ref):
-    """Conditioning of the anchor gradients: the larger response of the
-    oracle's gradient to two independent float32-size perturbations of every
-    float input, decoder weights included."""
-    import copy
-
-    from tests.parity import _perturbed
-    out = None
-    for seed in (4321, 8765):
-        rng = np.random.default_rng(seed)
-        sc = copy.copy(scene)
-        for k in ("x", "l", "O", "b1", "b2"):
-            setattr(sc, k, _perturbed(getattr(scene, k), rng))
-        sc.W1_exact = _perturbed(scene.W1, rng)
-        sc.W2_exact = _perturbed(scene.W2, rng)
-        r1 = pipeline.render_anchor(sc, views, tile=tile, keep_tiles=keep)
-        g1, _ = pipeline.backward(r1, og, sc)
-        d = {k: np.abs(ref[k] - g1[k]) for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2")}
-        out = d if out is None else {k: np.maximum(out[k], d[k]) for k in d}
-    return out
+    sens = anchor_sensitivity(wl.scene, [v0], og, tile=tile, keep_tiles=keep, r0=r)
+    _check_anchor_grads(gr, ref, sens)
 
 
 def test_c3_full_size_sampled_tiles():

@@ -10,7 +10,8 @@ import torch
 
 from oracle import ncc, pipeline
 from synth import scenes
-from tests.parity import (SENS_EPS, _perturbed, check_close, check_grad, oracle_images_packed)
+from tests.parity import (SENS_EPS, _perturbed, check_close, check_grad, compare_images,
+                          oracle_images_packed)
 
 pytestmark = pytest.mark.gpu
 
@@ -77,8 +78,8 @@ def test_ncc_kernel_on_oracle_images():
     assert abs(loss2.item() - 2 * loss.item()) <= 1e-6 * abs(loss.item()) + 1e-12
 
 
-def _chain_grads(scene, views, centres, weight):
-    r = pipeline.render_explicit(scene, views)
+def _chain_grads(scene, views, centres, weight, r=None):
+    r = r or pipeline.render_explicit(scene, views)
     _, g_rgb, info = _oracle_ncc(r, centres, weight)
     og = []
     for img, gr in zip(r.images, g_rgb):
@@ -86,6 +87,44 @@ def _chain_grads(scene, views, centres, weight):
         og.append(dict(rgb=gr, depth=np.zeros(n), D=np.zeros(n), normal=np.zeros((3, n)), alpha=np.zeros(n)))
     g, _ = pipeline.backward(r, og, scene)
     return g, r, og, info
+
+
+def _tied_patches(r, centres, patch=7):
+    """Patches that read a pixel with a near-tie decision: in their
+    reference window (view 2i+1) or in the bilinear footprint of their
+    warped window in the source view (2i).  The GPU seeds the NCC gradient
+    from its own images, which may resolve those ties the other way."""
+    h = patch // 2
+    n_pairs = len(r.images) // 2
+    centres = np.asarray(centres).reshape(n_pairs, -1, 2)
+    tied = np.zeros(centres.shape[:2], bool)
+    oy, ox = np.mgrid[-h:h + 1, -h:h + 1]
+    for i in range(n_pairs):
+        s_, t_ = 2 * i, 2 * i + 1
+        vr, vs = r.varr[t_], r.varr[s_]
+        ref_tie, src_tie = r.images[t_]["frag_grad"], r.images[s_]["frag_grad"]
+        for k, (cx, cy) in enumerate(centres[i]):
+            px, py = (cx + ox).ravel(), (cy + oy).ravel()
+            ok = (px >= 0) & (py >= 0) & (px < vr["W"]) & (py < vr["H"])
+            if ref_tie[(py * vr["W"] + px)[ok]].any():
+                tied[i, k] = True
+                continue
+            if not ok.all():
+                continue
+            pc = cy * vr["W"] + cx
+            n = r.images[t_]["normal"][:, pc]
+            d = float(r.images[t_]["D"][pc])
+            if not d > 0:
+                continue
+            q = ncc.homography(vr, vs, n, d) @ np.stack([px + 0.5, py + 0.5, np.ones(px.size)])
+            if not np.all(q[2] > 0):
+                continue
+            sx, sy = q[0] / q[2] - 0.5, q[1] / q[2] - 0.5
+            x0 = np.clip(np.floor(sx).astype(np.int64), 0, vs["W"] - 2)
+            y0 = np.clip(np.floor(sy).astype(np.int64), 0, vs["H"] - 2)
+            foot = np.concatenate([y * vs["W"] + x for y in (y0, y0 + 1) for x in (x0, x0 + 1)])
+            tied[i, k] = bool(src_tie[foot].any())
+    return tied
 
 
 def test_ncc_through_backward_matches_oracle():
@@ -98,21 +137,34 @@ def test_ncc_through_backward_matches_oracle():
     rd = render.Renderer(0, (16, 16))
     sc = render.scene_from(wl.scene)
     out = rd.forward(wl.views, sc)
+    compare_images(out, r)
     g_rgb, loss = rd.ncc_loss(wl.views, out, torch.as_tensor(centres), weight)
     zero = torch.zeros_like(out["depth"])
     gout = dict(rgb=g_rgb, depth=zero, plane_d=zero, normal=torch.zeros_like(out["normal"]), alpha=zero)
     gr = rd.backward(wl.views, sc, out, gout)
     torch.cuda.synchronize()
     loss_ref, _, _ = _oracle_ncc(r, centres, weight)
-    assert abs(loss.item() - loss_ref) <= 1e-4 * abs(loss_ref) + 1e-6, (loss.item(), loss_ref)
+    # the patches that read a near-tie pixel give their share as slack
+    tied = _tied_patches(r, centres)
+    print(f"  patches reading a near-tie pixel: {int(tied.sum())}/{tied.size}", flush=True)
+    assert tied.mean() < 0.2
+    scale = weight / (tied.shape[0] * tied.shape[1])
+    assert abs(loss.item() - loss_ref) <= 1e-4 * abs(loss_ref) + 1e-6 + 2 * scale * tied.sum(), \
+        (loss.item(), loss_ref)
+    c_tied = np.asarray(centres).reshape(tied.shape[0], -1, 2).copy()
+    c_tied[~tied] = -100                     # outside the image: an invalid patch adds nothing
+    share, _, _, _ = _chain_grads(wl.scene, wl.views, c_tied, weight, r=r)
     # conditioning of the whole chain: the oracle's gradient under float32-size input perturbation
-    rng = np.random.default_rng(4321)
-    sc2 = copy.copy(wl.scene)
-    for k in ("means", "scales", "quats", "opacity", "sh"):
-        setattr(sc2, k, _perturbed(getattr(wl.scene, k), rng))
-    g1, _, _, _ = _chain_grads(sc2, wl.views, centres, weight)
+    sens = None
+    for seed in (4321, 8765):
+        rng = np.random.default_rng(seed)
+        sc2 = copy.copy(wl.scene)
+        for k in ("means", "scales", "quats", "opacity", "sh"):
+            setattr(sc2, k, _perturbed(getattr(wl.scene, k), rng))
+        g1, _, _, _ = _chain_grads(sc2, wl.views, centres, weight)
+        d = {k: np.abs(ref[k] - g1[k]) for k in ("means", "scales", "quats", "opacity", "sh")}
+        sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
     assert SENS_EPS > 0
-    fa = ref["frag"]
-    for k, c in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("sh", 3)):
-        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], np.repeat(fa, c),
-                   dict(sens=np.abs(ref[k] - g1[k]), frag=np.zeros_like(ref[k])))
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None,
+                   dict(sens=sens[k], frag=np.abs(share[k])))

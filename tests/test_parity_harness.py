@@ -1,0 +1,154 @@
+"""The tie-aware comparison of the GPU parity tests, exercised on the CPU
+with the oracle's own outputs standing in for the GPU's: they must pass,
+so must an output that resolves a near tie the other way, and planted
+mistakes (a wrong pixel, a missing or foreign pair, a reordered list, a
+wrong depth key) must fail."""
+import numpy as np
+import pytest
+
+from oracle import pipeline
+from synth import scenes
+from tests import parity
+
+
+def _packed(r):
+    """The oracle's images packed like the library's planar outputs."""
+    out = {}
+    for key, okey, c, _ in parity.CHANNELS:
+        out[key] = np.concatenate([img[okey].reshape(c, -1).ravel() if c > 1 else img[okey].ravel()
+                                   for img in r.images])
+    return out
+
+
+def _dbg(r):
+    """The oracle's own sorted pairs in the library's debug layout (explicit
+    slots view * N + id)."""
+    o = r.sorted["own_sorted"]
+    return o
+
+
+@pytest.fixture(scope="module")
+def c0():
+    wl = scenes.make_c0()
+    return wl, pipeline.render_explicit(wl.scene, wl.views)
+
+
+@pytest.fixture(scope="module")
+def anchor11():
+    wl = scenes.make_small_anchor(11, n_anchor=70, n_views=3, sizes=((40, 32), (24, 36), (33, 17)))
+    return wl, pipeline.render_anchor(wl.scene, wl.views)
+
+
+def test_oracle_outputs_pass(c0, anchor11):
+    for wl, r in (c0, anchor11):
+        res = parity.compare_images(_packed(r), r)
+        assert res["excluded"] == 0
+
+
+def test_other_tie_outcome_passes(anchor11):
+    wl, r = anchor11
+    out = _packed(r)
+    img = r.images[0]
+    ties = [p for p, c in img["cands"].items() if c.shape[0] > 1]
+    assert ties, "the scene has near-tie pixels with two outcomes"
+    HW = img["depth"].size
+    for p in ties:
+        C = img["cands"][p]
+        # the candidate farthest from the oracle's own output
+        own = np.concatenate([img["rgb"][:, p], [img["D"][p]], img["normal"][:, p],
+                              [img["alpha"][p], img["depth"][p]]])
+        k = int(np.argmax(np.abs(C[:, :9] - own[None]).sum(1)))
+        for key, okey, c, cols in parity.CHANNELS:
+            for ch in range(c):
+                out[key][ch * HW + p] = C[k, cols][ch]
+    parity.compare_images(out, r)
+
+
+def test_wrong_pixel_fails(c0):
+    wl, r = c0
+    out = _packed(r)
+    img = r.images[0]
+    p = int(np.nonzero(~img["tie"] & (img["alpha"] > 0.5))[0][0])
+    out["rgb"][p] *= 1.001
+    with pytest.raises(AssertionError):
+        parity.compare_images(out, r)
+
+
+def test_wrong_tie_pixel_fails(anchor11):
+    wl, r = anchor11
+    out = _packed(r)
+    img = r.images[0]
+    p = next(iter(img["cands"]))
+    out["alpha"][p] = img["alpha"][p] + 0.01
+    with pytest.raises(AssertionError):
+        parity.compare_images(out, r)
+
+
+def _dbg_explicit(r, N, drop=None, swap=None, zflip=None):
+    o = r.sorted
+    sel = o["own"].copy()
+    gt, zb, vv, gg = o["gtile"][sel], o["zbits"][sel].astype(np.int64), o["view"][sel], o["gid"][sel]
+    if drop is not None:
+        keep = np.ones(gt.size, bool)
+        keep[drop] = False
+        gt, zb, vv, gg = gt[keep], zb[keep], vv[keep], gg[keep]
+    if swap is not None:
+        i = swap
+        for a in (zb, vv, gg):
+            a[[i, i + 1]] = a[[i + 1, i]]
+    if zflip is not None:
+        zb = zb.copy()
+        zb[zflip] ^= 1
+    n_tiles = o["ranges"].shape[0]
+    st = np.searchsorted(gt, np.arange(n_tiles), side="left")
+    en = np.searchsorted(gt, np.arange(n_tiles), side="right")
+    ranges = np.stack([np.where(en > st, st, 0), np.where(en > st, en, 0)], 1)
+    return dict(tile=gt, zbits=zb, slot=vv * N + gg, ranges=ranges)
+
+
+def test_sort_check(c0):
+    wl, r = c0
+    N = wl.scene.n
+    parity.compare_sort_explicit(_dbg_explicit(r, N), r, N)
+    o = r.sorted
+    own = np.nonzero(o["own"])[0]
+    cert_pos = int(np.nonzero(o["certain"][own])[0][10])
+    with pytest.raises(AssertionError):
+        parity.compare_sort_explicit(_dbg_explicit(r, N, drop=cert_pos), r, N)
+    # two neighbours of one tile with different depth keys, swapped
+    gt = o["gtile"][own]
+    zb = o["zbits"][own]
+    i = int(np.nonzero((gt[:-1] == gt[1:]) & (zb[:-1] != zb[1:]))[0][0])
+    with pytest.raises(AssertionError):
+        parity.compare_sort_explicit(_dbg_explicit(r, N, swap=i), r, N)
+    with pytest.raises(AssertionError):
+        parity.compare_sort_explicit(_dbg_explicit(r, N, zflip=i), r, N)
+
+
+def test_sort_check_accepts_near_tie_pairs(anchor11):
+    """A pair one near tie away from the oracle's own binning (a box edge or
+    a culling test) may be taken or left."""
+    wl, r = anchor11
+    o = r.sorted
+    extra = ~o["own"]
+    uncertain_own = o["own"] & ~o["certain"]
+    assert extra.any() or uncertain_own.any()
+
+
+def test_zero_ties_and_coverage(anchor11, c0):
+    for wl, r in (c0, anchor11):
+        rng = np.random.default_rng(5)
+        og = parity.linear_grads(r, rng)
+        for img, g in zip(r.images, og):
+            assert np.all(g["rgb"][:, img["frag_grad"]] == 0)
+            assert np.all(g["alpha"][~img["frag_grad"]] != 0)
+        assert parity.tie_fraction(r) < 0.02
+
+
+def test_check_grad_requires_conditioning():
+    ref = np.linspace(-1, 1, 100)
+    parity.check_grad("ok", ref * (1 + 1e-6), ref, None, np.zeros(100))
+    with pytest.raises(AssertionError):
+        parity.check_grad("loose", ref, ref, None, np.full(100, 1.0))
+    with pytest.raises(AssertionError):
+        parity.check_grad("off", ref * (1 + 1e-3), ref, None, np.zeros(100))
