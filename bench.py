@@ -29,13 +29,14 @@ sys.path.insert(0, ROOT)
 # published MI355X peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-# algorithmic work per evaluated (pixel, splat) pair, counted from the
-# method's arithmetic: forward = offsets, quadratic form, exponential,
-# alpha, transmittance update and the 7-channel blend; backward = the
-# recomputed alpha, transmittance recovery, value / suffix terms and the
-# 13 gradient terms
-FLOPS_FWD_PER_EVAL = 29
-FLOPS_BWD_PER_EVAL = 70
+# algorithmic work per list entry walked (pixel, splat), counted from the
+# method's arithmetic, with a transcendental counted as one flop: forward =
+# offsets, quadratic form, exponential, alpha, transmittance update and the
+# 7-channel blend (26 + exp); backward = the recomputed alpha, the
+# transmittance recovered by a reciprocal, the value / suffix terms and the
+# 13 gradient terms (90 + exp + rcp)
+FLOPS_FWD_PER_ENTRY = 27
+FLOPS_BWD_PER_ENTRY = 92
 SORT_BYTES_PER_ELEM_PASS = 16     # read + write of a 32-bit key and a 32-bit value
 
 
@@ -106,8 +107,6 @@ def gpu_leg(args, wl):
     info0 = dict(rd.last_info)
     log(f"[bench] rows {info0['n_rows']} splats {info0['n_splats']} pairs {info0['n_pairs']} "
         f"loss {info0['loss']:.6f} workspace {rd.ws.numel() / 2**30:.2f} GiB")
-    log(f"[bench] per step: list entries walked fwd {info0['entries_fwd']} bwd {info0['entries_bwd']}, "
-        f"opacity evaluations fwd {info0['evals_fwd']} bwd {info0['evals_bwd']}")
     for _ in range(max(args.warmup, 1)):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()
@@ -125,6 +124,17 @@ def gpu_leg(args, wl):
     phases = B.cgx_timing_read(rd.ctx)
     B.cgx_timing_enable(rd.ctx, 0)
     info = rd.info()      # raises if a capacity was exceeded inside the timed region
+    # the work counts of the roofline: one more step, untimed, with the
+    # raster kernels' counting variants
+    rd.count_work(True)
+    rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
+    torch.cuda.synchronize()
+    counts = rd.info()
+    rd.count_work(False)
+    for k in ("entries_fwd", "evals_fwd", "evals_bwd"):
+        info[k] = counts[k]
+    log(f"[bench] per step: list entries walked fwd {info['entries_fwd']} bwd {info['entries_bwd']}, "
+        f"opacity evaluations fwd {info['evals_fwd']} bwd {info['evals_bwd']}")
     ms = (t1 - t0) / args.steps * 1e3
     log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step")
     for k, (t, c) in phases.items():
@@ -216,7 +226,7 @@ def kernel_source_digest():
 
 
 def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` (e.g. 'k_raster_bwd<16, 16>') from the
+    """HBM bytes per launch of `kernel` (e.g. 'k_raster_bwd<16, 16, false>') from the
     committed FETCH_SIZE / WRITE_SIZE summary, or None when there is none or
     it was taken from other raster sources than the ones built now."""
     if not os.path.exists(PROFILE_BYTES):
@@ -236,15 +246,19 @@ def roofline(res, steps):
     t, c = ph["raster_bwd"]
     if c:
         d = t / c * 1e-3
-        fl = info["evals_bwd"] * FLOPS_BWD_PER_EVAL if "evals_bwd" in info else info["entries_bwd"] * FLOPS_BWD_PER_EVAL
+        fl = info["entries_bwd"] * FLOPS_BWD_PER_ENTRY
         cands.append((t / steps, dict(kernel="raster_bwd", bound="alu", achieved=fl / d / 1e12,
-                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")))
+                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                                      work=f"{FLOPS_BWD_PER_ENTRY} flops x {info['entries_bwd']} "
+                                           f"list entries walked backward")))
     t, c = ph["raster_fwd"]
     if c:
         d = t / c * 1e-3
-        fl = info["evals_fwd"] * FLOPS_FWD_PER_EVAL if "evals_fwd" in info else info["entries_fwd"] * FLOPS_FWD_PER_EVAL
+        fl = info["entries_fwd"] * FLOPS_FWD_PER_ENTRY
         cands.append((t / steps, dict(kernel="raster_fwd", bound="alu", achieved=fl / d / 1e12,
-                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")))
+                                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                                      work=f"{FLOPS_FWD_PER_ENTRY} flops x {info['entries_fwd']} "
+                                           f"list entries walked forward")))
     t, c = ph["sort"]
     if c:
         # both sorts of a step: 4 passes over the visible splats' depth keys,
@@ -260,7 +274,8 @@ def roofline(res, steps):
     r = cands[0][1]
     r["frac"] = r["achieved"] / r["peak"]
     tw, th = res["tile"].split("x")
-    r["traffic"] = profiled_traffic(f"k_{r['kernel']}<{tw}, {th}>") if r["kernel"].startswith("raster") else None
+    r["traffic"] = (profiled_traffic(f"k_{r['kernel']}<{tw}, {th}, false>")
+                    if r["kernel"].startswith("raster") else None)
     return r
 
 

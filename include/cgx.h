@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 5
+#define CGX_ABI_VERSION 6
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -179,12 +179,12 @@ typedef struct cgx_run_info {
   int32_t reserved;
   int64_t need_rows, need_splats, need_pairs;
   double loss;          /* L1 loss of the last fused call */
-  uint64_t entries_fwd; /* sum over pixels of list entries walked forward */
+  uint64_t entries_fwd; /* sum over pixels of list entries walked forward (counting on) */
   uint64_t entries_bwd; /* sum over pixels of list entries walked backward */
   int64_t n_tiles;
   int64_t n_pixels;
-  uint64_t evals_fwd;   /* (pixel, splat) opacity evaluations, forward */
-  uint64_t evals_bwd;   /* (pixel, splat) opacity evaluations, backward */
+  uint64_t evals_fwd;   /* (pixel, splat) opacity evaluations, forward (counting on) */
+  uint64_t evals_bwd;   /* (pixel, splat) opacity evaluations, backward (counting on) */
   int32_t sort_passes;  /* radix passes over the pairs (tile-id digits) */
   int32_t n_visible;    /* splats with at least one pair (depth-sorted, 32 bits) */
 } cgx_run_info;
@@ -249,6 +249,20 @@ int32_t cgx_read_info(cgx_ctx* ctx, const void* workspace, void* stream, cgx_run
 int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream,
                        uint32_t* tile_ids, uint32_t* depth_bits, uint32_t* slots,
                        uint32_t* ranges, int32_t* rows, uint32_t* counts);
+
+/* Debug / parity access to the per-splat state between the rasterizer and
+ * the projection (synchronises): copies to HOST buffers, for each of the
+ * n_splats slots of cgx_read_info, the 64-byte splat record the compositing
+ * of Eq. 5 reads (records: 16 little-endian words per slot: u, w; the
+ * base-2 exponent coefficients log2(e) (-a/2, -b, -c/2) of the conic
+ * (a, b, c); log2(o); colour r, g, b; plane distance d; normal x, y, z;
+ * pixel box x_lo | x_hi << 16 and y_lo | y_hi << 16 as uint32; 1/o) and
+ * the 16-float gradient record the backward raster accumulated (grads:
+ * d/du, d/dw, d/d(-a/2), d/d(-b), d/d(-c/2), d/do, d/dr, d/dg, d/db, d/dd,
+ * d/dnx, d/dny, d/dnz, 3 zeros).  Either pointer may be NULL.  Slot order:
+ * explicit scenes view * N + Gaussian; anchor scenes row * 10 + k. */
+int32_t cgx_debug_splats(cgx_ctx* ctx, const void* workspace, void* stream, void* records,
+                         float* grads);
 
 /* hipGraph of the fused chain (Sec. 3.3 batch rendering as one launch).
  * cgx_graph_capture_fwd_bwd_l1 records exactly the launches of
@@ -436,6 +450,17 @@ enum {
 int32_t cgx_timing_enable(cgx_ctx* ctx, int32_t n_records);
 int32_t cgx_timing_read(cgx_ctx* ctx, double* ms_per_phase, int32_t* count_per_phase,
                         int32_t n_phases);
+
+/* Work counters of the raster kernels (the roofline's units of work, Sec.
+ * 3.3 compositing of Eq. 5): with counting on (on != 0), later launch chains
+ * also add to cgx_run_info.entries_fwd (list entries walked forward until
+ * each pixel saturates or its list ends), evals_fwd and evals_bwd (pixel /
+ * splat pairs inside the pixel box whose opacity was evaluated).  These
+ * run in separate kernel variants, slower by the counting; with counting
+ * off (the default) the three stay 0 and only entries_bwd (the sum over
+ * pixels of last contributing index + 1, read from the forward state) is
+ * counted.  Images and gradients do not depend on the setting. */
+int32_t cgx_count_enable(cgx_ctx* ctx, int32_t on);
 
 #ifdef __cplusplus
 }

@@ -92,11 +92,15 @@ def linear_loss(r, gs):
     return L
 
 
-def backward(r, out_grads, scene):
+def backward(r, out_grads, scene, sg_hook=None):
     """Adjoint of the whole chain.  Returns (scene gradients, per-view splat
     gradients).  Explicit: means, scales, quats, opacity, sh (summed over
-    views).  Anchor: x, l, O, F, W1, b1, W2, b2."""
+    views).  Anchor: x, l, O, F, W1, b1, W2, b2.  sg_hook (tests'
+    conditioning probes) may replace the per-view splat gradients before the
+    projection adjoint."""
     sg = ras.composite_backward(r.splats, r.views, r.images, out_grads, r.varr)
+    if sg_hook is not None:
+        sg = sg_hook(sg)
     if r.kind == "explicit":
         acc = None
         for v, S in enumerate(r.splats):

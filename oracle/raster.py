@@ -395,7 +395,10 @@ def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
     Nabs = wgt @ np.abs(S["normal"][ent]) if ne else np.zeros((npx, 3))
     last = (np.where(inc.any(axis=1), ne - np.argmax(inc[:, ::-1], axis=1), 0) if ne
             else np.zeros(npx, np.int64))
-    walked = np.minimum(stop + 1, ne)
+    # list entries walked (the work measure): the oracle's own entries up to
+    # and including the one that stops the pixel, or all of them
+    own_before = np.concatenate([[0], np.cumsum(own)])
+    walked = own_before[np.minimum(stop + 1, ne)]
 
     V = view_arrays
     rgb = rgb + T_final[:, None] * V["bg"][None]
@@ -548,10 +551,17 @@ def l1_seed(images, targets, weights=(1.0, 1.0, 1.0)):
 # --------------------------------------------------------------------------
 # a8: compositing adjoint
 # --------------------------------------------------------------------------
-def composite_backward(splats_per_view, views, images, grads, view_arrays):
+def composite_backward(splats_per_view, views, images, grads, view_arrays, magnitude=False):
     """Per-splat gradients (mean2d, conic, opacity, rgb, d, normal) for every
     view, from per-pixel output gradients.  Transmittances come from the
-    forward products (no division)."""
+    forward products (no division).
+
+    magnitude=True (the tests' conditioning model) returns instead, per
+    element, the same sums taken over the absolute values of every term
+    that enters them, cancelling differences included (the alpha adjoint
+    T val - suffix / (1 - alpha) counts |T val| + |suffix| / (1 - alpha)):
+    the scale of the rounding error a float32 evaluation of the element may
+    make."""
     res = []
     for v, S in enumerate(splats_per_view):
         n = S["n"]
@@ -566,38 +576,47 @@ def composite_backward(splats_per_view, views, images, grads, view_arrays):
         for gtile, (ent, I, J, pix, R) in img["tiles"].items():
             if ent.size == 0:
                 continue
-            GC = g["rgb"][:, pix].T.copy()
-            GD = g["D"][pix].copy()
-            GN = g["normal"][:, pix].T.copy()
-            GA = g["alpha"][pix].copy()
-            Gh = g["depth"][pix]
+            ab = np.abs if magnitude else (lambda x: x)
+            GC = ab(g["rgb"][:, pix].T.copy())
+            GD = ab(g["D"][pix].copy())
+            GN = ab(g["normal"][:, pix].T.copy())
+            GA = ab(g["alpha"][pix].copy())
+            Gh = ab(g["depth"][pix])
             keep = R["keep"]
-            sd = np.where(keep, R["sdot"], 1.0)
+            sd = ab(np.where(keep, R["sdot"], 1.0))
             GD += np.where(keep, Gh / sd, 0.0)
-            GN += np.where(keep, Gh * R["D"] / sd ** 2, 0.0)[:, None] * R["ray"]
-            dT = GC @ Vv["bg"] - GA
+            GN += np.where(keep, Gh * ab(R["D"]) / sd ** 2, 0.0)[:, None] * ab(R["ray"])
+            dT = (GC @ Vv["bg"] + GA) if magnitude else (GC @ Vv["bg"] - GA)
             E = R["E"]
             inc = R["inc"]
             a_inc, Tb, wgt = R["a_inc"], R["Tb"], R["wgt"]
-            rgb, d, nrm = S["rgb"][ent], S["d"][ent], S["normal"][ent]
+            rgb, d, nrm = ab(S["rgb"][ent]), ab(S["d"][ent]), ab(S["normal"][ent])
             val = GC @ rgb.T + GD[:, None] * d[None] + GN @ nrm.T
             wv = wgt * val
             suffix = np.cumsum(wv[:, ::-1], axis=1)[:, ::-1] - wv
             one_m = 1.0 - a_inc
-            dalpha = Tb * val - suffix / one_m - (R["T"] * dT)[:, None] / one_m
+            if magnitude:
+                dalpha = Tb * val + suffix / one_m + (R["T"] * dT)[:, None] / one_m
+            else:
+                dalpha = Tb * val - suffix / one_m - (R["T"] * dT)[:, None] / one_m
             dalpha = np.where(inc, dalpha, 0.0)
             unclamped = inc & (E["raw"] < ALPHA_MAX)
             op = S["opacity"][ent][None]
             dop = np.where(unclamped, dalpha * E["G"], 0.0)
             dpower = np.where(unclamped, dalpha * op * E["G"], 0.0)
-            a, b, c = S["conic"][ent].T
-            dx, dy = E["dx"], E["dy"]
-            du = dpower * (-(a[None] * dx + b[None] * dy))
-            dw = dpower * (-(c[None] * dy + b[None] * dx))
+            a, b, c = ab(S["conic"][ent].T)
+            dx, dy = ab(E["dx"]), ab(E["dy"])
+            if magnitude:
+                du = dpower * (a[None] * dx + b[None] * dy)
+                dw = dpower * (c[None] * dy + b[None] * dx)
+            else:
+                du = dpower * (-(a[None] * dx + b[None] * dy))
+                dw = dpower * (-(c[None] * dy + b[None] * dx))
             np.add.at(acc["mean2d"], ent, np.stack([du.sum(0), dw.sum(0)], 1))
-            np.add.at(acc["conic"], ent, np.stack([(-0.5 * dx * dx * dpower).sum(0),
-                                                   (-dx * dy * dpower).sum(0),
-                                                   (-0.5 * dy * dy * dpower).sum(0)], 1))
+            sg_ = 1.0 if magnitude else -1.0
+            np.add.at(acc["conic"], ent, np.stack([(sg_ * 0.5 * dx * dx * dpower).sum(0),
+                                                   (sg_ * dx * dy * dpower).sum(0),
+                                                   (sg_ * 0.5 * dy * dy * dpower).sum(0)], 1))
             np.add.at(acc["opacity"], ent, dop.sum(0))
             np.add.at(acc["rgb"], ent, wgt.T @ GC)
             np.add.at(acc["d"], ent, wgt.T @ GD)

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 5
+CGX_ABI_VERSION = 6
 OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
@@ -146,6 +146,8 @@ def load_library(path: str = LIB_PATH):
                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_float)]),
         "cgx_timing_enable": (C.c_int32, [P, C.c_int32]),
+        "cgx_count_enable": (C.c_int32, [P, C.c_int32]),
+        "cgx_debug_splats": (C.c_int32, [P, P, P, P, P]),
         "cgx_timing_read": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]),
     }
     for name, (res, args) in sig.items():
@@ -440,12 +442,36 @@ def cgx_debug_copy(ctx, ws):
     return dict(tile=tiles, zbits=zb, slot=slots, ranges=ranges, rows=rows, counts=counts, info=info)
 
 
+SPLAT_RECORD = np.dtype([("u", "<f4"), ("w", "<f4"), ("pa", "<f4"), ("pb", "<f4"), ("pc", "<f4"),
+                         ("lno", "<f4"), ("rgb", "<f4", 3), ("d", "<f4"), ("normal", "<f4", 3),
+                         ("bx", "<u4"), ("by", "<u4"), ("inv_o", "<f4")])
+
+
+def cgx_debug_splats(ctx, ws):
+    """Per-slot splat records (structured array) and 16-float gradient
+    records of the last chain."""
+    lib = load_library()
+    info = cgx_read_info(ctx, ws)
+    S = info["n_splats"]
+    rec = np.zeros(S, SPLAT_RECORD)
+    grads = np.zeros((S, 16), np.float32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)   # noqa: E731
+    _check(ctx, lib.cgx_debug_splats(ctx, C.c_void_p(ws.data_ptr()), _stream(), p(rec), p(grads)),
+           "cgx_debug_splats")
+    return rec, grads
+
+
 PHASES = ["select", "project", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "project_bwd", "wgrad"]
 
 
 def cgx_timing_enable(ctx, n_records):
     _check(ctx, load_library().cgx_timing_enable(ctx, int(n_records)), "cgx_timing_enable")
+
+
+def cgx_count_enable(ctx, on):
+    """Switch the raster work counters (entries_fwd, evals_fwd, evals_bwd)."""
+    _check(ctx, load_library().cgx_count_enable(ctx, 1 if on else 0), "cgx_count_enable")
 
 
 def cgx_timing_read(ctx):

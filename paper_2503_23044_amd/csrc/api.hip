@@ -25,6 +25,7 @@ struct cgx_ctx {
   int ev_next = 0;
   int ev_cap = 0;
   int open_phase = -1;
+  int count = 0;     // raster work counters (cgx_count_enable)
 };
 
 static void phase_begin(cgx_ctx* c, int phase, hipStream_t s) {
@@ -333,6 +334,8 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.ranges = L.ranges;
   h.rows = L.rows;
   h.counts = L.counts;
+  h.splats = L.splats;
+  h.sgrad = L.sgrad;
   h.n_tiles = L.n_tiles;
   h.n_pixels = L.n_pixels;
   h.max_rows = L.max_rows;
@@ -407,6 +410,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   a.px_last = P.px_last;
   a.ctr = P.ctr;
   a.stats = P.stats;
+  a.count = c->count;
   phase_begin(c, CGX_PHASE_RASTER_FWD, st);
   launch_raster_forward(a, c->tw, c->th, st);
   phase_end(c, st);
@@ -483,6 +487,7 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
   a.sgrad = P.sgrad;
   phase_begin(c, CGX_PHASE_RASTER_BWD, st);
   a.stats = P.stats;
+  a.count = c->count;
   launch_raster_backward(a, c->tw, c->th, st);
   launch_fold_stats(P.ctr, P.stats, st);
   phase_end(c, st);
@@ -550,6 +555,12 @@ int32_t cgx_timing_enable(cgx_ctx* ctx, int32_t n_records) {
   for (auto& e : ctx->ev) HIP_OK(ctx, hipEventCreate(&e));
   ctx->ev_cap = n_records;
   ctx->ev_next = 0;
+  return CGX_OK;
+}
+
+int32_t cgx_count_enable(cgx_ctx* ctx, int32_t on) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  ctx->count = on ? 1 : 0;
   return CGX_OK;
 }
 
@@ -1150,6 +1161,22 @@ int32_t cgx_debug_copy(cgx_ctx* ctx, const void* workspace, void* stream, uint32
   if (rows && h.n_rows) HIP_OK(ctx, hipMemcpy(rows, base + h.hdr.rows, 8 * (size_t)h.n_rows, hipMemcpyDeviceToHost));
   if (counts && h.n_splats)
     HIP_OK(ctx, hipMemcpy(counts, base + h.hdr.counts, 4 * (size_t)h.n_splats, hipMemcpyDeviceToHost));
+  return CGX_OK;
+}
+
+int32_t cgx_debug_splats(cgx_ctx* ctx, const void* workspace, void* stream, void* records,
+                         float* grads) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!workspace) return fail(ctx, CGX_ERR_INVALID_ARG, "workspace is NULL");
+  Counters h;
+  int32_t rc = read_counters(ctx, workspace, stream, h);
+  if (rc) return rc;
+  const char* base = reinterpret_cast<const char*>(workspace);
+  const size_t S = h.n_splats;
+  if (records && S)
+    HIP_OK(ctx, hipMemcpy(records, base + h.hdr.splats, sizeof(Splat) * S, hipMemcpyDeviceToHost));
+  if (grads && S)
+    HIP_OK(ctx, hipMemcpy(grads, base + h.hdr.sgrad, sizeof(SplatGrad) * S, hipMemcpyDeviceToHost));
   return CGX_OK;
 }
 

@@ -33,7 +33,9 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxRadixBits = 9;    // digit width bound of the LSD passes
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
-constexpr float kLnAlphaMin = -5.541263545158426f;   // log(1/255)
+constexpr float kLog2AlphaMin = -7.994353436858858f;  // log2(1/255)
+constexpr float kLog2E = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kDilation = 0.3f;
@@ -58,7 +60,7 @@ struct ViewDev {
 // workspace pointer.
 struct WsHeader {
   uint64_t total;
-  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts, zkey;
+  uint64_t keys_hi, keys_lo, vals, ranges, rows, counts, zkey, splats, sgrad;
   int64_t n_tiles, n_pixels, max_rows, max_splats, max_pairs;
   int32_t n_views, kind;
   int32_t sort_passes, pad;
@@ -83,10 +85,12 @@ struct Counters {
   uint32_t pad[3];
 };
 
-// 64-byte splat record.  power = pa dx^2 + pb dx dy + pc dy^2 with
-// (pa, pb, pc) = (-a/2, -b, -c/2) of the conic (exact scalings); the raw
-// opacity is exp(power + lno) with lno = log(o), so alpha < 1/255 is decided
-// before the exponential.  The depth key lives in its own array.
+// 64-byte splat record, exponents in base 2: the Gaussian's exponent is
+// power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 with the conic (a, b, c), and
+// (pa, pb, pc) = log2(e) (-a/2, -b, -c/2), lno = log2(o), so that
+// q = pa dx^2 + pb dx dy + pc dy^2 + lno = log2(o exp(power)) and the raw
+// opacity is exp2(q): one hardware exp2 per evaluation, and alpha < 1/255
+// is decided on q before it.  The depth key lives in its own array.
 struct alignas(16) Splat {
   float u, w;
   float pa, pb, pc;
@@ -100,8 +104,9 @@ struct alignas(16) Splat {
 };
 static_assert(sizeof(Splat) == 64, "splat record is one 64-byte line");
 
-// Per-slot gradient accumulator: du, dw, dpa, dpb, dpc, dop, dcr, dcg,
-// dcb, dd, dnx, dny, dnz, 3 unused.
+// Per-slot gradient accumulator: du, dw, the gradients wrt (-a/2, -b, -c/2)
+// of the conic (natural-log units), dop, dcr, dcg, dcb, dd, dnx, dny, dnz,
+// 3 unused.
 struct alignas(16) SplatGrad {
   float g[16];
 };
@@ -165,23 +170,19 @@ __device__ __forceinline__ double box_hi64(double u, double r) {
 }
 
 // ---------------------------------------------------------------------
-// The per-(pixel, splat) opacity shared by the forward and backward raster
-// kernels: one function so both compile to the same instruction sequence
-// and take the same decisions.  Returns alpha (0 when skipped) and the
-// unclamped product o * exp(power) in raw.
+// The per-(pixel, splat) exponent shared by the forward and backward raster
+// kernels: one function, so both compile to the same instruction sequence
+// and take the same decisions.  q = log2(o exp(power)); the pair is drawn
+// iff power <= 0 (q <= lno) and o exp(power) >= 1/255 (q >= log2(1/255)),
+// and then alpha = min(exp2(q), 0.99).
 // ---------------------------------------------------------------------
-__device__ __forceinline__ float splat_alpha(float pa, float pb, float pc, float lno, float dx,
-                                             float dy, float& raw) {
+__device__ __forceinline__ float splat_q(float pa, float pb, float pc, float lno, float dx,
+                                         float dy) {
 #pragma clang fp contract(off)
-  const float power = __builtin_fmaf(pa * dx, dx, __builtin_fmaf(pc * dy, dy, (pb * dx) * dy));
-  const float q = power + lno;
-  // alpha = o exp(power) >= 1/255  <=>  power + log(o) >= log(1/255)
-  if (power > 0.0f || !(q >= kLnAlphaMin)) {
-    raw = 0.0f;
-    return 0.0f;
-  }
-  raw = __expf(q);
-  return raw < kAlphaMax ? raw : kAlphaMax;
+  return __builtin_fmaf(__builtin_fmaf(pa, dx, pb * dy), dx, __builtin_fmaf(pc * dy, dy, lno));
+}
+__device__ __forceinline__ bool splat_drawn(float q, float lno) {
+  return (q <= lno) & (q >= kLog2AlphaMin);
 }
 
 // Sum of a float over the 64 lanes of a wave, result valid in lane 63.
@@ -212,10 +213,25 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // mirror and two quad permutations, all DPP) each send half of a lane's
 // partial sums to its partner and keep the other half; partner masks never
 // flip an earlier step's keep bit, so partners always hold the same slots.
-// The four rows are then summed with two cross-row exchanges.
+// The four rows are then summed with two row swaps (wave_sum_rows).
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the four 16-lane rows, in every lane: (row 0 + row 1) + (row 2 +
+// row 3) lane by lane, with gfx950's row swaps (v_permlane16_swap exchanges
+// the odd rows of one operand with the even rows of the other,
+// v_permlane32_swap the upper half of one with the lower half of the other;
+// with both operands holding x, the two results add to the pairwise sums).
+// No LDS traffic, so no wait on the LDS / scalar-load counter.
+__device__ __forceinline__ float wave_sum_rows(float d) {
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(d), __float_as_uint(d), false,
+                                                    false);
+  d = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d), __float_as_uint(d), false,
+                                                    false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 
 __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int lane) {
@@ -241,9 +257,7 @@ __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int
     c[i] = keep + dpp_read<0x4E>(send);             // quad_perm(2,3,0,1): lane ^ 2
   }
   float d = (f4 ? c[1] : c[0]) + dpp_read<0xB1>(f4 ? c[0] : c[1]);   // quad_perm(1,0,3,2)
-  d += __shfl_xor(d, 16, kWave);
-  d += __shfl_xor(d, 32, kWave);
-  return d;
+  return wave_sum_rows(d);
 }
 
 // float atomic add without return (global_atomic_add_f32).
@@ -361,6 +375,7 @@ struct RasterArgs {
   const float* t_normal;
   float w_rgb, w_depth, w_normal;
   int l1;                      // 1: seed from L1 against targets
+  int count;                   // 1: count list entries walked and opacity evaluations
   SplatGrad* sgrad;
 };
 void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s);

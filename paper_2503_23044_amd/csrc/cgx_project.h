@@ -205,10 +205,12 @@ __device__ __forceinline__ uint32_t project_splat(const ViewDev& V, const ProjIn
   const float idet = 1.0f / st.det;
   o.u = (float)u64;
   o.w = (float)w64;
-  o.pa = -0.5f * (st.C * idet);
-  o.pb = st.B * idet;            // -b with b = -B/det
-  o.pc = -0.5f * (st.A * idet);
-  o.lno = __logf(in.op);
+  // base-2 exponent coefficients: log2(e) (-a/2, -b, -c/2) with the conic
+  // (a, b, c) = (C, -B, A) / det
+  o.pa = (-0.5f * kLog2E) * (st.C * idet);
+  o.pb = kLog2E * (st.B * idet);
+  o.pc = (-0.5f * kLog2E) * (st.A * idet);
+  o.lno = __log2f(in.op);
   o.inv_o = 1.0f / in.op;
   o.cr = in.col[0];
   o.cg = in.col[1];
@@ -240,8 +242,9 @@ __device__ __forceinline__ void project_state(const ViewDev& V, const ProjIn& in
   proj_normal(V, in, st);
 }
 
-// a9: adjoint of the projection.  g = the 13 splat gradients (du, dw, dpa,
-// dpb, dpc, dop, dcr, dcg, dcb, dd, dnx, dny, dnz).  Outputs d(mean),
+// a9: adjoint of the projection.  g = the 13 splat gradients (du, dw, then
+// the gradients wrt (-a/2, -b, -c/2) of the conic, dop, dcr, dcg, dcb, dd,
+// dnx, dny, dnz).  Outputs d(mean),
 // d(scales), d(raw quaternion).
 __device__ __forceinline__ void project_backward(const ViewDev& V, const ProjIn& in,
                                                  const ProjState& st, const float* g,
@@ -249,7 +252,7 @@ __device__ __forceinline__ void project_backward(const ViewDev& V, const ProjIn&
   const float* R = V.R;
   const float fx = V.fx, fy = V.fy, iz = st.iz, iz2 = iz * iz;
   const float du = g[0], dw = g[1];
-  // conic gradients from the power coefficients (pa, pb, pc) = (-a/2, -b, -c/2)
+  // conic gradients from the gradients wrt (-a/2, -b, -c/2)
   const float dca = -0.5f * g[2], dcb = -g[3], dcc = -0.5f * g[4];
   float dp[3];
   dp[0] = du * fx * iz;

@@ -3,17 +3,24 @@
 //
 // One wave per tile.  A TW x TH tile is cut into PPL = TW*TH/64 sub-blocks
 // of 8 x 8 pixels; lane l owns pixel (l % 8, l / 8) of every sub-block.
-// Splat records of the tile's sorted list are staged 64 at a time in LDS
-// (one 64-byte gather per lane) and the wave walks them front to back.  For
-// each splat the pixel box is tested against every sub-block with scalar
-// (wave-uniform) compares, so sub-blocks the splat misses cost no vector
-// work and the lanes of a hit sub-block are mostly inside the box.  A wave
-// stops as soon as a ballot shows that all its pixels have saturated.  The
-// forward pass keeps 8 bytes per pixel (final transmittance, last
-// contributing list index); the backward pass re-walks the same list from
-// that index towards the front, recovering the transmittance by division,
-// and reduce-scatters each splat's 13 gradient terms across the wave so
-// that one 13-lane atomic instruction adds them to the splat's record.
+// The wave walks the tile's sorted list one splat at a time.  The list
+// index and the splat's 64-byte record are wave-uniform, so they are read
+// with scalar loads into scalar registers (the record of the next splat is
+// requested while the current one is composited) and every vector
+// instruction takes the splat's fields as scalar operands: no LDS staging,
+// no barriers.  Per splat, scalar arithmetic on its pixel box gives the set
+// of sub-blocks it touches; only those are evaluated, so sub-blocks the
+// splat misses cost no vector work.  A wave stops as soon as all its pixels
+// have saturated.  The forward pass keeps 8 bytes per pixel (final
+// transmittance, last contributing list index); the backward pass re-walks
+// the same list from the largest last index towards the front, recovering
+// the transmittance by division, and reduce-scatters each splat's 13
+// gradient terms across the wave so that one 13-lane atomic instruction
+// adds them to the splat's record.
+//
+// STATS variants also count the list entries walked and the opacity
+// evaluations (the work measures of the roofline); the production variants
+// count only the backward's entries, from the per-pixel last indices.
 #include "cgx_common.h"
 
 namespace cgx {
@@ -23,16 +30,6 @@ __device__ __forceinline__ int find_view(const ViewDev* views, int B, uint32_t t
   for (int i = 1; i < B; ++i)
     if ((uint32_t)views[i].tile_off <= tile) v = i;
   return v;
-}
-
-__device__ __forceinline__ void load_splat(Splat* dst, const Splat* src) {
-  const float4* s = reinterpret_cast<const float4*>(src);
-  float4* d = reinterpret_cast<float4*>(dst);
-  float4 a = s[0], b = s[1], c = s[2], e = s[3];
-  d[0] = a;
-  d[1] = b;
-  d[2] = c;
-  d[3] = e;
 }
 
 // box-test column of a finished pixel: left of every pixel box
@@ -49,23 +46,159 @@ __device__ __forceinline__ int sub_x0(int tx, int k) { return tx * TW + (k % (TW
 template <int TW>
 __device__ __forceinline__ int sub_y0(int ty, int TH, int k) { return ty * TH + (k / (TW / 8)) * 8; }
 
-// pixel box (inclusive) of a staged splat, read as wave-uniform scalars
+// pixel box (inclusive) of a splat record held in scalar registers
 struct Box {
   int xlo, xhi, ylo, yhi;
 };
-__device__ __forceinline__ Box uniform_box(const Splat& s) {
-  const uint32_t bx = __builtin_amdgcn_readfirstlane(s.bx);
-  const uint32_t by = __builtin_amdgcn_readfirstlane(s.by);
-  return Box{(int)(bx & 0xFFFF), (int)(bx >> 16), (int)(by & 0xFFFF), (int)(by >> 16)};
+template <typename R>
+__device__ __forceinline__ Box splat_box(const R& s) {
+  return Box{(int)(s.bx & 0xFFFF), (int)(s.bx >> 16), (int)(s.by & 0xFFFF), (int)(s.by >> 16)};
 }
-__device__ __forceinline__ bool box_misses_block(const Box& b, int x0, int y0) {
-  return b.xhi < x0 || b.xlo > x0 + 7 || b.yhi < y0 || b.ylo > y0 + 7;
+
+// Bit k set iff the pixel box meets sub-block k of the tile whose first
+// pixel is (X0, Y0) (scalar arithmetic, wave-uniform).  A splat in the
+// tile's list has a box that meets the tile (x_lo <= X0 + TW - 1,
+// x_hi >= X0, and likewise in y), so the first column needs only the test
+// on x_lo, the last only the one on x_hi.  For a box that does not meet
+// the tile (an empty record) the mask may hold sub-blocks it misses; the
+// per-pixel box test then draws nothing there.
+// 1 iff a <= b, for operands far from overflow (|a|, |b| < 2^30), from
+// the sign of b - a: plain scalar arithmetic (a compare-and-select of a
+// wave-uniform flag is materialised through a vector register).
+__device__ __forceinline__ uint32_t le_bit(int a, int b) {
+  return ((uint32_t)(b - a) >> 31) ^ 1u;
 }
 
 template <int TW, int TH>
+__device__ __forceinline__ uint32_t sub_hits(const Box& b, int X0, int Y0) {
+  constexpr int SX = TW / 8, SY = TH / 8;
+  uint32_t cols = 0, rows = 0;
+#pragma unroll
+  for (int j = 0; j < SX; ++j) {
+    const uint32_t lo = j == SX - 1 ? 1u : le_bit(b.xlo, X0 + 8 * j + 7);
+    const uint32_t hi = j == 0 ? 1u : le_bit(X0 + 8 * j, b.xhi);
+    cols |= (lo & hi) << j;
+  }
+#pragma unroll
+  for (int r = 0; r < SY; ++r) {
+    const uint32_t lo = r == SY - 1 ? 1u : le_bit(b.ylo, Y0 + 8 * r + 7);
+    const uint32_t hi = r == 0 ? 1u : le_bit(Y0 + 8 * r, b.yhi);
+    rows |= ((lo & hi) * ((1u << SX) - 1u)) << (r * SX);
+  }
+  uint32_t rep = 0;
+#pragma unroll
+  for (int r = 0; r < SY; ++r) rep |= cols << (r * SX);
+  return rep & rows;
+}
+
+// The sorted slots and the splat records are read-only while the raster
+// kernels run; reading them through the constant address space lets the
+// compiler use scalar loads for them even in the backward kernel, whose
+// gradient atomics it could not otherwise prove to leave them unchanged.
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  typedef const __attribute__((address_space(4))) uint32_t* ConstWords;
+  const ConstWords q = (ConstWords)p;
+  T r;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return r;
+}
+
+// Slot of list position i (a scalar load), or n_slots past the end.
+__device__ __forceinline__ uint32_t list_slot(const RasterArgs& a, uint32_t i, uint32_t end) {
+  return i < end ? load_const(a.vals + i) : a.n_slots;
+}
+
+// Mask of a slot's validity, folded into the sub-block mask: an invalid slot
+// (past the end of the list) touches nothing.
+__device__ __forceinline__ uint32_t slot_mask(const RasterArgs& a, uint32_t slot) {
+  return slot < a.n_slots ? ~0u : 0u;
+}
+
+// 64-byte record of a slot (scalar loads).  An invalid slot reads record 0
+// instead, so the load needs no branch; its slot_mask is 0.  Called only
+// while the list being walked is non-empty, so record 0 exists.
+__device__ __forceinline__ Splat fetch_record(const RasterArgs& a, uint32_t slot) {
+  return load_const(a.splats + (slot < a.n_slots ? slot : 0u));
+}
+
+// The fields of a record that the forward pass reads (all but 1/o).  Scalar
+// loads may complete out of order, so while a load is in flight any of its
+// destination registers the compiler reuses costs a full wait; the forward
+// pass therefore loads only the 60 bytes it uses.
+struct SplatFwd {
+  float u, w, pa, pb, pc, lno, cr, cg, cb, d, nx, ny, nz;
+  uint32_t bx, by;
+};
+static_assert(sizeof(SplatFwd) == 60, "record prefix");
+__device__ __forceinline__ SplatFwd fetch_record_fwd(const RasterArgs& a, uint32_t slot) {
+  return load_const(reinterpret_cast<const SplatFwd*>(a.splats + (slot < a.n_slots ? slot : 0u)));
+}
+
+// Front-to-back compositing of one splat (list index idx, 1-based) into the
+// wave's pixels; live is the mask of sub-blocks with an unfinished pixel.
+template <int TW, int TH, bool STATS, int PPL = TW * TH / kWave>
+__device__ __forceinline__ void composite_fwd(const SplatFwd& s, uint32_t valid, uint32_t idx,
+                                              int ty, int X0, int Y0, int ly, uint32_t& live,
+                                              float (&T)[PPL],
+                                              float (&C0)[PPL], float (&C1)[PPL], float (&C2)[PPL],
+                                              float (&D)[PPL], float (&N0)[PPL], float (&N1)[PPL],
+                                              float (&N2)[PPL], uint32_t (&last)[PPL],
+                                              uint32_t (&walked)[PPL], int (&xb)[PPL],
+                                              const float (&xc)[PPL], const float (&yc)[PPL],
+                                              uint32_t& evals) {
+  const Box b = splat_box(s);
+  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & live & valid;
+  if (hit == 0) return;
+  bool stopped = false;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    if (!(hit & (1u << k))) continue;
+    const int x = xb[k], y = sub_y0<TW>(ty, TH, k) + ly;
+    const float dx = s.u - xc[k];
+    const float dy = s.w - yc[k];
+    const float q = splat_q(s.pa, s.pb, s.pc, s.lno, dx, dy);
+    // Every lane of a touched sub-block takes the same instructions (no
+    // lane-divergent branch, so no exec-mask bookkeeping on the scalar
+    // unit): a pixel the splat does not reach gets alpha = 0, which leaves
+    // T (fma(-T, 0, T) = T) and every sum unchanged and cannot stop it.
+    const bool in = (x >= b.xlo) & (x <= b.xhi) & (y >= b.ylo) & (y <= b.yhi);
+    if (STATS && in) ++evals;
+    const bool ok = in & splat_drawn(q, s.lno);
+    const float raw = __builtin_amdgcn_exp2f(q);
+    const float alpha = ok ? (raw < kAlphaMax ? raw : kAlphaMax) : 0.0f;
+    // a pixel that would fall below the transmittance floor stops without
+    // taking the splat
+    const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
+    const bool stop = Tn < kTMin;
+    if (STATS && stop) walked[k] = idx;
+    xb[k] = stop ? kDoneX : xb[k];
+    stopped = stopped | stop;
+    const float w = stop ? 0.0f : alpha * T[k];
+    C0[k] += w * s.cr;
+    C1[k] += w * s.cg;
+    C2[k] += w * s.cb;
+    D[k] += w * s.d;
+    N0[k] += w * s.nx;
+    N1[k] += w * s.ny;
+    N2[k] += w * s.nz;
+    T[k] = stop ? T[k] : Tn;
+    last[k] = (ok & !stop) ? idx : last[k];
+  }
+  if (__ballot(stopped) != 0) {
+    live = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k)
+      if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
+  }
+}
+
+template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
-  __shared__ Splat sh[kWave];
   const uint32_t tile = launch_tile(a);
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
@@ -74,6 +207,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   const ViewDev& V = a.views[v];
   const int local = (int)tile - V.tile_off;
   const int tx = local % V.TX, ty = local / V.TX;
+  const int X0 = tx * TW, Y0 = ty * TH;
 
   float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
   uint32_t last[PPL], walked[PPL];
@@ -96,59 +230,34 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
   uint32_t evals = 0;
+  // sub-blocks with a live pixel (wave-uniform bit mask)
+  uint32_t live = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k)
+    if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
 
-  for (uint32_t base = start; base < end; base += kWave) {
-    // sub-blocks with a live pixel (wave-uniform bit mask)
-    uint32_t live = 0;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k)
-      if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
-    if (live == 0) break;
-    const uint32_t n = (end - base) < (uint32_t)kWave ? (end - base) : (uint32_t)kWave;
-    if ((uint32_t)lane < n) {
-      const uint32_t slot = a.vals[base + lane];
-      if (slot < a.n_slots) load_splat(&sh[lane], &a.splats[slot]);
-      else sh[lane].bx = 0xFFFFu;     // empty box: never drawn
-    }
-    __syncthreads();
-    for (uint32_t j = 0; j < n; ++j) {
-      const Splat& s = sh[j];
-      const Box b = uniform_box(s);
-      const uint32_t idx = base - start + j + 1;
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
-        if (!(live & (1u << k)) || box_misses_block(b, x0, y0)) continue;
-        const int x = xb[k], y = y0 + ly;
-        if (x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
-        const float dx = s.u - xc[k];
-        const float dy = s.w - yc[k];
-        float raw;
-        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
-        ++evals;
-        // selects rather than branches: a zero alpha leaves every sum and T
-        // unchanged (weight 0, T (1 - 0) = T); a pixel that would fall below
-        // the transmittance floor stops without taking the splat
-        const float Tn = T[k] * (1.0f - alpha);
-        const bool stop = Tn < kTMin;
-        const bool take = alpha != 0.0f && !stop;
-        if (stop) {
-          xb[k] = kDoneX;
-          walked[k] = idx;
-        }
-        const float w = take ? alpha * T[k] : 0.0f;
-        C0[k] += w * s.cr;
-        C1[k] += w * s.cg;
-        C2[k] += w * s.cb;
-        D[k] += w * s.d;
-        N0[k] += w * s.nx;
-        N1[k] += w * s.ny;
-        N2[k] += w * s.nz;
-        T[k] = take ? Tn : T[k];
-        last[k] = take ? idx : last[k];
-      }
-    }
-    __syncthreads();
+  // Software pipeline over two record buffers: the record of list position
+  // i + 1 and the slot of i + 2 are requested before splat i is
+  // composited.  Scalar loads may complete out of order, so each buffer is
+  // waited for in full (together with the slot that names the next record)
+  // before the other buffer's loads are issued.
+  // records are read only for a non-empty list (then the splat table holds
+  // at least one slot, which past-the-end positions read instead)
+  uint32_t slot_a = list_slot(a, start, end), slot_b = list_slot(a, start + 1, end);
+  SplatFwd sa = {}, sb;
+  if (start < end) sa = fetch_record_fwd(a, slot_a);
+  for (uint32_t i = start; i < end && live != 0; i += 2) {
+    sb = fetch_record_fwd(a, slot_b);
+    const uint32_t next_a = list_slot(a, i + 2, end);
+    composite_fwd<TW, TH, STATS>(sa, slot_mask(a, slot_a), i - start + 1, ty, X0, Y0, ly, live, T,
+                                 C0, C1, C2, D, N0, N1, N2, last, walked, xb, xc, yc, evals);
+    if (i + 1 >= end || live == 0) break;
+    slot_a = next_a;
+    sa = fetch_record_fwd(a, slot_a);
+    const uint32_t next_b = list_slot(a, i + 3, end);
+    composite_fwd<TW, TH, STATS>(sb, slot_mask(a, slot_b), i - start + 2, ty, X0, Y0, ly, live, T,
+                                 C0, C1, C2, D, N0, N1, N2, last, walked, xb, xc, yc, evals);
+    slot_b = next_b;
   }
 
   const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
@@ -158,8 +267,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   for (int k = 0; k < PPL; ++k) {
     const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
     if (!(x < V.W && y < V.H)) continue;
-    if (walked[k] == 0) walked[k] = end - start;
-    walked_sum += walked[k];
+    if (STATS) walked_sum += walked[k] == 0 ? end - start : walked[k];
     const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
     const float r = C0[k] + T[k] * V.bg[0];
     const float g = C1[k] + T[k] * V.bg[1];
@@ -185,22 +293,113 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
     a.px_T[pv + p] = T[k];
     a.px_last[pv + p] = last[k];
   }
-  // statistics: list entries walked and opacity evaluations, one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) {
-    walked_sum += __shfl_xor(walked_sum, o, kWave);
-    evals += __shfl_xor(evals, o, kWave);
+  if (STATS) {
+    // list entries walked and opacity evaluations, one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+      walked_sum += __shfl_xor(walked_sum, o, kWave);
+      evals += __shfl_xor(evals, o, kWave);
+    }
+    if (lane == 0 && walked_sum)
+      atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_fwd, (unsigned long long)walked_sum);
+    if (lane == 0 && evals)
+      atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_fwd, (unsigned long long)evals);
   }
-  if (lane == 0 && walked_sum) atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_fwd, (unsigned long long)walked_sum);
-  if (lane == 0 && evals) atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_fwd, (unsigned long long)evals);
 }
 
 __device__ __forceinline__ float sgnf(float e) { return e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f); }
 
-template <int TW, int TH>
+// Reverse-order adjoint of one splat (list entry j, 0-based, in `slot`):
+// recovers each pixel's transmittance before the entry, accumulates the
+// splat's 13 gradient terms over the wave's pixels and adds their wave
+// totals to the splat's gradient record.
+template <int TW, int TH, bool STATS, int PPL = TW * TH / kWave>
+__device__ __forceinline__ void composite_bwd(
+    const RasterArgs& a, const Splat& s, uint32_t slot, int j, int tx, int ty, int X0, int Y0,
+    int lx, int ly, int lane, const uint32_t (&blast)[PPL], const uint32_t (&last)[PPL],
+    const float (&xc)[PPL], const float (&yc)[PPL], float (&T)[PPL], float (&S)[PPL],
+    const float (&GC0)[PPL], const float (&GC1)[PPL], const float (&GC2)[PPL],
+    const float (&GD)[PPL], const float (&GN0)[PPL], const float (&GN1)[PPL],
+    const float (&GN2)[PPL], uint32_t& evals) {
+  const Box b = splat_box(s);
+  // sub-blocks whose pixels may hold list entry j (0-based) before their
+  // last: j < blast[k], read off the sign of j - blast[k] (scalar ops)
+  uint32_t alive = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) alive |= (le_bit((int)blast[k], j) ^ 1u) << k;
+  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & alive & slot_mask(a, slot);
+  if (hit == 0) return;
+  float g[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) g[i] = 0.0f;
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    if (!(hit & (1u << k))) continue;
+    const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
+    const float dx = s.u - xc[k];
+    const float dy = s.w - yc[k];
+    const float q = splat_q(s.pa, s.pb, s.pc, s.lno, dx, dy);
+    // Every lane of a touched sub-block takes the same instructions:
+    // a pixel the splat does not reach (outside the box, past its last
+    // entry, or alpha < 1/255) gets alpha = 0, for which every update below
+    // is exact: T is kept, w = 0 leaves S and the colour terms, and
+    // d alpha / d power is 0.  No lane-divergent branches, so
+    // the accumulators need no copies at branch joins.
+    const bool in = ((uint32_t)j < last[k]) & (x >= b.xlo) & (x <= b.xhi) & (y >= b.ylo) &
+                    (y <= b.yhi);
+    if (STATS && in) ++evals;
+    const bool ok = in & splat_drawn(q, s.lno);
+    const float raw = __builtin_amdgcn_exp2f(q);
+    const float alpha = ok ? (raw < kAlphaMax ? raw : kAlphaMax) : 0.0f;
+    const float om = 1.0f - alpha;
+    const float rom = __builtin_amdgcn_rcpf(om);
+    const float Tk = ok ? T[k] * rom : T[k];
+    const float w = alpha * Tk;
+    const float val = s.cr * GC0[k] + s.cg * GC1[k] + s.cb * GC2[k] + s.d * GD[k] +
+                      s.nx * GN0[k] + s.ny * GN1[k] + s.nz * GN2[k];
+    const float da = Tk * val - S[k] * rom;
+    S[k] += w * val;
+    T[k] = Tk;
+    g[6] += w * GC0[k];
+    g[7] += w * GC1[k];
+    g[8] += w * GC2[k];
+    g[9] += w * GD[k];
+    g[10] += w * GN0[k];
+    g[11] += w * GN1[k];
+    g[12] += w * GN2[k];
+    // d alpha / d power = o exp(power) = raw; none where alpha is clamped at
+    // kAlphaMax (no gradient through o or the power) or not drawn
+    const float dpw = (ok & (raw < kAlphaMax)) ? da * raw : 0.0f;
+    // moments of dpw; the opacity term (d alpha / d o = exp(power) =
+    // dpw / o) and the mean's terms take the splat's uniform 1/o and
+    // conic once per splat below
+    g[5] += dpw;
+    const float px = dpw * dx, py = dpw * dy;
+    g[0] += px;
+    g[1] += py;
+    g[2] += px * dx;
+    g[3] += px * dy;
+    g[4] += py * dy;
+    any = any | ok;
+  }
+  if (__ballot(any) == 0) return;
+  {
+    // d power / d u = 2 (-a/2) dx - b dy = ln2 (2 pa dx + pb dy) with the
+    // base-2 coefficients of the record; likewise d power / d w
+    const float m0 = g[0], m1 = g[1];
+    g[0] = kLn2 * (2.0f * s.pa * m0 + s.pb * m1);
+    g[1] = kLn2 * (2.0f * s.pc * m1 + s.pb * m0);
+    g[5] *= s.inv_o;
+  }
+  // wave totals of the 13 terms land in lanes 0..12; one atomic
+  // instruction then adds them to the splat's 64-byte gradient record
+  const float r = wave_reduce_scatter16(g, lane);
+  if (lane < 13 && r != 0.0f) atomic_add_f32(a.sgrad[slot].g + lane, r);
+}
+
+template <int TW, int TH, bool STATS>
 __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   constexpr int PPL = TW * TH / kWave;
-  __shared__ Splat sh[kWave];
-  __shared__ uint32_t sslot[kWave];
   const uint32_t tile = launch_tile(a);
   if (tile >= a.n_tiles) return;
   const int lane = threadIdx.x;
@@ -209,17 +408,21 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
   const ViewDev& V = a.views[v];
   const int local = (int)tile - V.tile_off;
   const int tx = local % V.TX, ty = local / V.TX;
+  const int X0 = tx * TW, Y0 = ty * TH;
   const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
   const size_t pv = (size_t)V.pix_off;
   const float inv_px = 1.0f / ((float)a.B * (float)HW);
 
   float T[PPL], S[PPL], GC0[PPL], GC1[PPL], GC2[PPL], GD[PPL], GN0[PPL], GN1[PPL], GN2[PPL];
   uint32_t last[PPL];
+  float xc[PPL], yc[PPL];
   float loss = 0.0f;
   uint32_t sumlast = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
+    xc[k] = (float)x + 0.5f;
+    yc[k] = (float)y + 0.5f;
     last[k] = 0;
     T[k] = 1.0f;
     S[k] = GC0[k] = GC1[k] = GC2[k] = GD[k] = GN0[k] = GN1[k] = GN2[k] = 0.0f;
@@ -298,101 +501,60 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
     blast[k] = __builtin_amdgcn_readfirstlane(m);
     maxlast = blast[k] > maxlast ? blast[k] : maxlast;
   }
+  // list entries walked backward: sum over pixels of (last index + 1)
   for (int o = 32; o > 0; o >>= 1) sumlast += __shfl_xor(sumlast, o, kWave);
-  if (lane == 0 && sumlast) atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_bwd, (unsigned long long)sumlast);
+  if (lane == 0 && sumlast)
+    atomicAdd(&a.stats[blockIdx.x % kStatSlots].entries_bwd, (unsigned long long)sumlast);
 
   const uint32_t start = a.ranges[tile].x;
   uint32_t evals = 0;
-  for (int hi = (int)maxlast; hi > 0; hi -= kWave) {
-    const int lo = hi - kWave > 0 ? hi - kWave : 0;
-    const int n = hi - lo;
-    if (lane < n) {
-      const uint32_t slot = a.vals[start + lo + lane];
-      const bool ok = slot < a.n_slots;
-      sslot[lane] = ok ? slot : 0u;
-      if (ok) load_splat(&sh[lane], &a.splats[slot]);
-      else sh[lane].bx = 0xFFFFu;     // empty box: never drawn
-    }
-    __syncthreads();
-    for (int j = n - 1; j >= 0; --j) {
-      const Splat& s = sh[j];
-      const Box b = uniform_box(s);
-      const uint32_t idx = (uint32_t)(lo + j);   // 0-based list index
-      float g[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) g[i] = 0.0f;
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const int x0 = sub_x0<TW>(tx, k), y0 = sub_y0<TW>(ty, TH, k);
-        if (idx >= blast[k] || box_misses_block(b, x0, y0)) continue;
-        const int x = x0 + lx, y = y0 + ly;
-        if (idx >= last[k] || x < b.xlo || x > b.xhi || y < b.ylo || y > b.yhi) continue;
-        const float dx = s.u - ((float)x + 0.5f);
-        const float dy = s.w - ((float)y + 0.5f);
-        float raw;
-        const float alpha = splat_alpha(s.pa, s.pb, s.pc, s.lno, dx, dy, raw);
-        ++evals;
-        // selects rather than branches: a zero alpha (then raw = 0 too)
-        // leaves T, S and every gradient term unchanged
-        const bool hit = alpha != 0.0f;
-        const float om = 1.0f - alpha;
-        const float rom = __builtin_amdgcn_rcpf(om);
-        const float Tk = hit ? T[k] * rom : T[k];
-        const float w = alpha * Tk;
-        const float val = s.cr * GC0[k] + s.cg * GC1[k] + s.cb * GC2[k] + s.d * GD[k] +
-                          s.nx * GN0[k] + s.ny * GN1[k] + s.nz * GN2[k];
-        const float da = Tk * val - S[k] * rom;
-        S[k] += w * val;
-        T[k] = Tk;
-        g[6] += w * GC0[k];
-        g[7] += w * GC1[k];
-        g[8] += w * GC2[k];
-        g[9] += w * GD[k];
-        g[10] += w * GN0[k];
-        g[11] += w * GN1[k];
-        g[12] += w * GN2[k];
-        // alpha clamped at kAlphaMax: no gradient through o or the power
-        const float dg = raw < kAlphaMax ? da : 0.0f;
-        const float dpw = dg * raw;           // d alpha / d power = o exp(power)
-        // moments of dpw; the opacity term (d alpha / d o = exp(power) =
-        // dpw / o) and the mean's terms take the splat's uniform 1/o and
-        // conic once per splat below
-        g[5] += dpw;
-        const float px = dpw * dx, py = dpw * dy;
-        g[0] += px;
-        g[1] += py;
-        g[2] += px * dx;
-        g[3] += px * dy;
-        g[4] += py * dy;
-        any = any || hit;
-      }
-      if (__ballot(any) == 0) continue;
-      {
-        // d power / d u = 2 pa dx + pb dy, d power / d w = 2 pc dy + pb dx
-        const float m0 = g[0], m1 = g[1];
-        g[0] = 2.0f * s.pa * m0 + s.pb * m1;
-        g[1] = 2.0f * s.pc * m1 + s.pb * m0;
-        g[5] *= s.inv_o;
-      }
-      // wave totals of the 13 terms land in lanes 0..12; one atomic
-      // instruction then adds them to the splat's 64-byte gradient record
-      const float r = wave_reduce_scatter16(g, lane);
-      if (lane < 13 && r != 0.0f) atomic_add_f32(a.sgrad[sslot[j]].g + lane, r);
-    }
-    __syncthreads();
+  // Software pipeline over two record buffers, walking towards the front:
+  // the record of the next entry and the slot of the one after it are
+  // requested before the current entry's adjoint (scalar loads may complete
+  // out of order, so each buffer is waited for in full before the other's
+  // loads are issued).
+  auto slot_at = [&](int j) -> uint32_t {
+    return j >= 0 ? load_const(a.vals + start + (uint32_t)j) : a.n_slots;
+  };
+  // records are read only for a non-empty walk (then the splat table holds
+  // at least one slot, which positions before the list's front read instead)
+  int j = (int)maxlast - 1;
+  uint32_t slot_a = slot_at(j), slot_b = slot_at(j - 1), slot_n;
+  Splat sa = {}, sb;
+  if (j >= 0) sa = fetch_record(a, slot_a);
+  for (; j >= 0; j -= 2) {
+    sb = fetch_record(a, slot_b);
+    slot_n = slot_at(j - 2);
+    composite_bwd<TW, TH, STATS>(a, sa, slot_a, j, tx, ty, X0, Y0, lx, ly, lane, blast, last, xc,
+                                 yc, T, S, GC0, GC1, GC2, GD, GN0, GN1, GN2, evals);
+    if (j - 1 < 0) break;
+    slot_a = slot_n;
+    sa = fetch_record(a, slot_a);
+    slot_n = slot_at(j - 3);
+    composite_bwd<TW, TH, STATS>(a, sb, slot_b, j - 1, tx, ty, X0, Y0, lx, ly, lane, blast, last,
+                                 xc, yc, T, S, GC0, GC1, GC2, GD, GN0, GN1, GN2, evals);
+    slot_b = slot_n;
   }
-  for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, kWave);
-  if (lane == 0 && evals) atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_bwd, (unsigned long long)evals);
+  if (STATS) {
+    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, kWave);
+    if (lane == 0 && evals)
+      atomicAdd(&a.stats[blockIdx.x % kStatSlots].evals_bwd, (unsigned long long)evals);
+  }
 }
 
 template <int TW, int TH>
 static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  if (a.count)
+    hipLaunchKernelGGL((k_raster_fwd<TW, TH, true>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_raster_fwd<TW, TH, false>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
 }
 template <int TW, int TH>
 static void launch_bwd_t(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  if (a.count)
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH, true>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH, false>), dim3(a.n_tiles), dim3(kWave), 0, s, a);
 }
 
 void launch_raster_forward(const RasterArgs& a, int tw, int th, hipStream_t s) {

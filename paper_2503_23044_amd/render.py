@@ -335,6 +335,11 @@ class Renderer:
     def info(self):
         return B.cgx_read_info(self.ctx, self.ws)
 
+    def count_work(self, on=True):
+        """Count the raster work (list entries walked, opacity evaluations)
+        in the following launches; slower, for measurement only."""
+        B.cgx_count_enable(self.ctx, on)
+
     def debug(self):
         return B.cgx_debug_copy(self.ctx, self.ws)
 

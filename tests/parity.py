@@ -14,6 +14,9 @@ losses of the gradient tests), so every gradient element is compared; the
 fused L1 tests, whose seed the GPU computes itself, give those pixels'
 share of each element as slack instead.
 """
+import os
+import re
+
 import numpy as np
 
 RTOL = 1e-4          # images and gradients, relative (fp32 GPU vs fp64 oracle)
@@ -211,11 +214,12 @@ def compare_sorted(dbg, r, slot_to_view_gid, tiles=None):
 
 
 def compare_sort_explicit(dbg, r, N):
-    """Explicit scenes: slot = view * N + Gaussian."""
+    """Explicit scenes: slot = view * N + Gaussian.  Returns (pairs checked,
+    near-tie pairs the GPU took, near-tie pairs it left)."""
     n, took, left = compare_sorted(dbg, r, lambda s: (s // N, s % N))
     assert n == int(dbg["tile"].size), (n, dbg["tile"].size)
     print(f"  sorted pairs: {n} bit-exact (near-tie pairs taken {took}, left {left})", flush=True)
-    return n
+    return n, took, left
 
 
 def compare_sort_anchor(dbg, r, n_off):
@@ -240,23 +244,34 @@ def compare_sort_anchor(dbg, r, n_off):
 # ---------------------------------------------------------------------------
 SENS_EPS = 2.0 ** -24      # relative input perturbation of float32 rounding size
 SENS_K = 16.0              # float32 rounding events the GPU chain may accumulate per input one
+ROUND_K = 4.0              # multiple of the per-splat rounding-scale probe (rounding_sensitivity)
 GRAD_NORM_RTOL = 1e-4
-MIN_WELL = 0.9             # well-conditioned share of the elements that must be met
+# At most this share of a gradient tensor's gradient-bearing elements (and
+# at least SLACK_MIN elements of a small tensor) may lie beyond the plain
+# 1e-4 bound, inside their conditioning slack.  Measured on MI355X over the
+# whole GPU suite: at most 0.9 % of a tensor's elements needed it (sums
+# whose terms cancel, e.g. the first-layer decoder weights), at most 1 of
+# the 32 first-layer biases.
+SLACK_SHARE = 0.02
+SLACK_MIN = 2
 
 
-def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=None,
-               min_well=MIN_WELL):
-    """|got - ref| <= rtol * max(|ref|, floor * max|ref|) + slack, where delta
-    is a dict {"sens": d, "frag": f}: d is how far the FP64 oracle's own
-    gradient moves when every float input is perturbed at float32 rounding
-    size (the element's conditioning) and f is the share of the element that
-    comes from pixels with a near tie (zero when their output gradients are
-    zero); slack = SENS_K d + 2 f.  At least min_well of the elements must
-    be well conditioned (slack below the relative bound), and over those the
-    norm-wise relative error must stay <= GRAD_NORM_RTOL."""
+def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=None):
+    """Every element: |got - ref| <= rtol * max(|ref|, floor * max|ref|) + slack,
+    where delta is a dict {"sens": d, "round": e, "frag": f}: d is how far
+    the FP64 oracle's own gradient moves when every float input is perturbed
+    at float32 rounding size (the element's conditioning), e its response to
+    rounding-size errors of the per-splat gradient sums (rounding_sensitivity)
+    and f the share of the element that comes from pixels with a near tie
+    (zero when their output gradients are zero); slack = SENS_K d + ROUND_K e
+    + 2 f.  The slack may carry
+    at most SLACK_SHARE of the gradient-bearing elements (those beyond the
+    plain relative bound), and the norm-wise relative error over all of them
+    must stay <= GRAD_NORM_RTOL."""
     if isinstance(delta, dict):
         frag = np.asarray(delta.get("frag", 0.0), np.float64)
-        delta = SENS_K * np.asarray(delta["sens"], np.float64) + 2.0 * frag
+        delta = (SENS_K * np.asarray(delta["sens"], np.float64) + 2.0 * frag
+                 + ROUND_K * np.asarray(delta.get("round", 0.0), np.float64))
     else:
         delta = SENS_K * np.asarray(delta, np.float64)
     got = np.asarray(got, np.float64).ravel()
@@ -266,36 +281,76 @@ def check_grad(name, got, ref, exclude, delta, rtol=RTOL, floor=FLOOR, report=No
     ex = np.zeros(ref.shape, bool) if exclude is None else np.asarray(exclude, bool).ravel()
     keep = ~ex
     scale = np.max(np.abs(ref[keep])) if keep.any() else 0.0
-    tol = rtol * np.maximum(np.abs(ref), floor * scale) + d
+    plain = rtol * np.maximum(np.abs(ref), floor * scale)
+    tol = plain + d
     err = np.abs(got - ref)
     bad = (err > tol) & keep
     assert np.all(np.isfinite(got[keep])), f"{name}: non-finite values"
     rel = np.max(err[keep] / np.maximum(np.abs(ref[keep]), floor * scale + 1e-300)) if keep.any() else 0.0
-    # norm-wise error over the elements whose conditioning allows 1e-4
-    wc = keep & (d <= rtol * np.maximum(np.abs(ref), floor * scale))
-    nrm = np.linalg.norm(ref[wc])
-    nrel = float(np.linalg.norm((got - ref)[wc]) / nrm) if nrm > 0 else float(np.linalg.norm(got[wc]))
-    cond = int((keep & ~wc).sum())
-    nb = int((keep & ((ref != 0) | (got != 0))).sum())
-    print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, excluded "
-          f"{int(ex.sum())}/{ref.size}, gradient-bearing {nb}, ill-conditioned {cond}", flush=True)
+    bearing = keep & ((ref != 0) | (got != 0))
+    nrm = np.linalg.norm(ref[bearing])
+    nrel = (float(np.linalg.norm((got - ref)[bearing]) / nrm) if nrm > 0
+            else float(np.linalg.norm(got[bearing])))
+    beyond = bearing & (err > plain)
+    n_b, n_bear = int(beyond.sum()), int(bearing.sum())
+    print(f"  {name}: max floored rel err {rel:.2e}, norm rel err {nrel:.2e}, gradient-bearing "
+          f"{n_bear}/{ref.size}, beyond the plain bound {n_b} (within their conditioning slack)",
+          flush=True)
     if report is not None:
         report[name] = dict(max_rel=float(rel), norm_rel=nrel, excluded=int(ex.sum()),
-                            ill=cond, n=int(ref.size))
+                            beyond=n_b, bearing=n_bear, n=int(ref.size))
+    dump = os.environ.get("CGX_PARITY_DUMP")
+    if dump:
+        # diagnostic mode: keep the compared arrays
+        test = os.environ.get("PYTEST_CURRENT_TEST", "run").split(" ")[0]
+        tag = re.sub(r"[^A-Za-z0-9_.-]+", "_", test)
+        os.makedirs(dump, exist_ok=True)
+        np.savez_compressed(os.path.join(dump, f"{tag}__{name}.npz"), got=got, ref=ref, d=d,
+                            keep=keep)
     if bad.any():
         i = np.argmax(np.where(bad, err / np.maximum(tol, 1e-300), 0))
         raise AssertionError(f"{name}: {int(bad.sum())}/{keep.sum()} elements out of tolerance; "
                              f"worst idx {i}: got {got[i]!r} ref {ref[i]!r} tol {tol[i]:.3g} "
                              f"delta {d[i]:.3g}")
-    # the elements that carry a gradient (on either side) must be mostly well
-    # conditioned, so that the norm-wise check is not over an empty set
-    bearing = keep & ((ref != 0) | (got != 0))
-    if bearing.any():
-        assert (wc & bearing).sum() >= min_well * bearing.sum(), (
-            f"{name}: only {int((wc & bearing).sum())}/{int(bearing.sum())} gradient-bearing "
-            f"elements well conditioned")
+    assert n_b <= max(SLACK_MIN, SLACK_SHARE * n_bear), (
+        f"{name}: {n_b}/{n_bear} gradient-bearing elements need the conditioning slack")
     assert nrel <= GRAD_NORM_RTOL, f"{name}: norm-wise relative error {nrel:.3g}"
     return rel
+
+
+def targets_at_ties(out, r, targets):
+    """L1 targets whose near-tie pixels hold the GPU's own outputs: the
+    pixels of frag_grad, and those where a target lies within the L1 sign's
+    near-tie bound of the oracle's output.  The GPU's fused L1 seed is then
+    exactly zero there (sign(0) = 0), as the linear-loss tests zero those
+    pixels' output gradients; the pixels join frag_grad, so zero_ties zeroes
+    the oracle's seed at the same pixels."""
+    from oracle.raster import FRAG_SIGN
+    pix_off = r.layout["pix_off"]
+    new = {k: [np.array(t, np.float32, copy=True) for t in targets[k]] for k in targets}
+    for v, img in enumerate(r.images):
+        HW = img["depth"].size
+        near = np.zeros(HW, bool)
+        with np.errstate(invalid="ignore"):
+            near |= (np.abs(img["rgb"] - np.asarray(targets["rgb"][v], np.float64).reshape(3, HW))
+                     < FRAG_SIGN).any(axis=0)
+            near |= (np.abs(img["normal"] - np.asarray(targets["normal"][v], np.float64).reshape(3, HW))
+                     < FRAG_SIGN).any(axis=0)
+            near |= np.abs(img["depth"] - np.asarray(targets["depth"][v], np.float64).ravel()) < FRAG_SIGN
+        img["frag_grad"] = img["frag_grad"] | near
+        m = img["frag_grad"]
+        for key, c in (("rgb", 3), ("depth", 1), ("normal", 3)):
+            if key not in new:
+                continue
+            g = _np(out[key]).astype(np.float32).ravel()
+            base = c * int(pix_off[v])
+            vals = g[base:base + c * HW].reshape(c, HW)
+            t = new[key][v]
+            shape = t.shape
+            t = t.reshape(c, HW)
+            t[:, m] = vals[:, m]
+            new[key][v] = t.reshape(shape)
+    return new
 
 
 def zero_ties(r, og):
@@ -365,6 +420,40 @@ EXPLICIT_KEYS = ("means", "scales", "quats", "opacity", "sh")
 ANCHOR_KEYS = ("x", "l", "O", "F", "W1", "b1", "W2", "b2")
 
 
+def rounding_sensitivity(r, og, scene, keys, seeds=(4321, 8765), g0=None):
+    """Response of the oracle's scene gradient to rounding-size errors in the
+    per-splat gradients: each per-splat element moves by SENS_EPS times its
+    rounding scale (the sum of |terms| it is formed from, cancelling
+    differences included; oracle.raster.composite_backward(magnitude=True))
+    with a random sign, and the projection / decoder adjoint carries that
+    to the scene gradient.  Models the float32 error of the sums the GPU's
+    backward raster forms, which input perturbations do not reach when a
+    pixel's alpha adjoint cancels large terms."""
+    from oracle import pipeline
+    from oracle import raster as ras
+    M = ras.composite_backward(r.splats, r.views, r.images, og, r.varr, magnitude=True)
+    if g0 is None:
+        g0, _ = pipeline.backward(r, og, scene)
+    sens = None
+    for seed in seeds:
+        rng = np.random.default_rng(seed + 17)
+
+        def hook(sg):
+            out = []
+            for d, m in zip(sg, M):
+                e = dict(d)
+                for k, a in d.items():
+                    if k in m and k != "frag":
+                        e[k] = a + SENS_EPS * np.asarray(m[k]) * rng.standard_normal(np.shape(a))
+                out.append(e)
+            return out
+
+        g1, _ = pipeline.backward(r, og, scene, sg_hook=hook)
+        d = {k: np.abs(g0[k] - g1[k]) for k in keys}
+        sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    return sens
+
+
 def explicit_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), keep_tiles=None,
                          r0=None):
     """Per gradient element: the larger response of the oracle's gradient to
@@ -386,8 +475,9 @@ def explicit_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), ke
         g1, _ = pipeline.backward(r1, og, sc)
         d = {k: np.abs(g0[k] - g1[k]) for k in EXPLICIT_KEYS}
         sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    sr = rounding_sensitivity(r0, og, scene, EXPLICIT_KEYS, seeds, g0=g0)
     g2, _ = pipeline.backward(r0, zero_ties(r0, og), scene)
-    return {k: dict(sens=sens[k], frag=np.abs(g0[k] - g2[k])) for k in EXPLICIT_KEYS}
+    return {k: dict(sens=sens[k], round=sr[k], frag=np.abs(g0[k] - g2[k])) for k in EXPLICIT_KEYS}
 
 
 def anchor_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), keep_tiles=None,
@@ -411,8 +501,9 @@ def anchor_sensitivity(scene, views, og, tile=(16, 16), seeds=(4321, 8765), keep
         g1, _ = pipeline.backward(r1, og, sc)
         d = {k: np.abs(g0[k] - g1[k]) for k in ANCHOR_KEYS}
         sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    sr = rounding_sensitivity(r0, og, scene, ANCHOR_KEYS, seeds, g0=g0)
     g2, _ = pipeline.backward(r0, zero_ties(r0, og), scene)
-    return {k: dict(sens=sens[k], frag=np.abs(g0[k] - g2[k])) for k in ANCHOR_KEYS}
+    return {k: dict(sens=sens[k], round=sr[k], frag=np.abs(g0[k] - g2[k])) for k in ANCHOR_KEYS}
 
 
 def oracle_images_packed(r, key, channels):
