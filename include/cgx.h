@@ -329,6 +329,19 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
                               void* workspace, size_t workspace_bytes, double* scale_shift,
                               float* aligned, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): cgx_depth_prior_align
+ * without a workspace.  Same arguments, results and errors, except that the
+ * partial sums live in a fixed device array of the library sized for
+ * CGX_MAX_VIEWS views (640 KiB, held on every device the call runs on
+ * until the process ends).  n_views above that bound returns
+ * CGX_ERR_CAPACITY.  The call allocates nothing.  Calls that overlap on one
+ * GPU (concurrent streams or threads) share that array and race; the
+ * array's contents are rewritten by every call and need no clearing. */
+int32_t cgx_depth_prior_align_noalloc(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                      const float* prior, const float* points, int32_t n_points,
+                                      double* scale_shift, float* aligned, void* stream);
+
 /* Depth prior, step 2 of 2 (Sec. 3.4, Step 2; tau_d = 1 in Sec. 4):
  * multi-view consistency filter.  For pixel p = (i + 1/2, j + 1/2) of view
  * v with depth d > 0 (device float32, packed layout) and its nearby view

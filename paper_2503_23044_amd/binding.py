@@ -132,6 +132,8 @@ def load_library(path: str = LIB_PATH):
         "cgx_depth_align_workspace_size": (C.c_size_t, [C.c_int32]),
         "cgx_depth_prior_align": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P, C.c_int32, P,
                                               C.c_size_t, P, P, P]),
+        "cgx_depth_prior_align_noalloc": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
+                                                      C.c_int32, P, P, P]),
         "cgx_depth_prior_filter": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, P,
                                                C.POINTER(C.c_int32), C.c_float, P, P]),
         "cgx_tsdf_init": (C.c_int32, [P, C.POINTER(cgx_tsdf_volume), P]),
@@ -342,6 +344,18 @@ def cgx_depth_prior_align(ctx, views, prior, points, ws, scale_shift, aligned):
                                    C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                    _ptr(scale_shift), _ptr(aligned), _stream())
     _check(ctx, rc, "cgx_depth_prior_align")
+
+
+def cgx_depth_prior_align_noalloc(ctx, views, prior, points, scale_shift, aligned):
+    """cgx_depth_prior_align with the library's fixed partial-sum array (no
+    workspace; for callers that cannot allocate)."""
+    lib = load_library()
+    va = make_views(views)
+    n = int(points.numel() // 3) if points is not None else 0
+    rc = lib.cgx_depth_prior_align_noalloc(ctx, va, len(views), _ptr(prior),
+                                           _ptr(points) if n else None, n, _ptr(scale_shift),
+                                           _ptr(aligned), _stream())
+    _check(ctx, rc, "cgx_depth_prior_align_noalloc")
 
 
 def cgx_depth_prior_filter(ctx, views, depth, nearby, tau, filtered, scale_shift=None):

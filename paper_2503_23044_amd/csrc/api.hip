@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -833,31 +834,31 @@ size_t cgx_depth_align_workspace_size(int32_t n_views) {
   return n_views < 1 ? 0 : depth_align_scratch_bytes(n_views);
 }
 
-int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
-                              const float* prior, const float* points, int32_t n_points,
-                              void* workspace, size_t workspace_bytes, double* scale_shift,
-                              float* aligned, void* stream) {
-  if (!ctx) return CGX_ERR_INVALID_ARG;
+// Checks shared by both alignment entry points (everything but the
+// partial-sum buffer).
+static int32_t check_depth_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                 const float* prior, const float* points, int32_t n_points,
+                                 const double* scale_shift) {
   int32_t rc = check_views(ctx, views, n_views);
   if (rc) return rc;
   if (n_points < 0 || n_points > INT32_MAX / 3)
     return fail(ctx, CGX_ERR_INVALID_ARG, "n_points %d outside 0..%d", n_points, INT32_MAX / 3);
-  if (!prior || !scale_shift || !workspace)
-    return fail(ctx, CGX_ERR_INVALID_ARG, "prior, workspace and scale_shift are required");
+  if (!prior || !scale_shift)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "prior and scale_shift are required");
   if (n_points > 0 && !points) return fail(ctx, CGX_ERR_INVALID_ARG, "points is NULL");
-  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0)
-    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
   if ((reinterpret_cast<uintptr_t>(scale_shift) & 7) != 0)
     return fail(ctx, CGX_ERR_INVALID_ARG, "scale_shift must be 8-byte aligned");
-  if (workspace_bytes < depth_align_scratch_bytes(n_views))
-    return fail(ctx, CGX_ERR_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes,
-                depth_align_scratch_bytes(n_views));
-  rc = set_device(ctx);
-  if (rc) return rc;
+  return CGX_OK;
+}
+
+// The launches of the alignment: partial sums into `partial`, then the
+// per-view solve (and the aligned image when asked for).
+static int32_t launch_depth_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                  const float* prior, const float* points, int32_t n_points,
+                                  double* partial, double* scale_shift, float* aligned,
+                                  hipStream_t st) {
   std::vector<HostCam> hc;
   const int max_pix = depth_cams(views, n_views, hc);
-  hipStream_t st = (hipStream_t)stream;
-  double* partial = reinterpret_cast<double*>(workspace);
   for (int first = 0; first < n_views; first += kAlignGroup) {
     const int count = std::min(kAlignGroup, n_views - first);
     AlignPack P;
@@ -881,6 +882,74 @@ int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
   }
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;
+}
+
+int32_t cgx_depth_prior_align(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                              const float* prior, const float* points, int32_t n_points,
+                              void* workspace, size_t workspace_bytes, double* scale_shift,
+                              float* aligned, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_depth_align(ctx, views, n_views, prior, points, n_points, scale_shift);
+  if (rc) return rc;
+  if (!workspace) return fail(ctx, CGX_ERR_INVALID_ARG, "workspace is required");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+  if (workspace_bytes < depth_align_scratch_bytes(n_views))
+    return fail(ctx, CGX_ERR_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes,
+                depth_align_scratch_bytes(n_views));
+  rc = set_device(ctx);
+  if (rc) return rc;
+  return launch_depth_align(ctx, views, n_views, prior, points, n_points,
+                            reinterpret_cast<double*>(workspace), scale_shift, aligned,
+                            (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// Partial sums of cgx_depth_prior_align_noalloc: a fixed device array of
+// kNoAllocAlignViews views (640 KiB), which every GPU the library runs on
+// holds until the process ends.  Host code never names it in a launch: its
+// device address, looked up once per device with that device current, is
+// what the kernels receive.
+constexpr int kNoAllocAlignViews = CGX_MAX_VIEWS;
+static __device__ __align__(256) double scratch[kNoAllocAlignViews * kAlignBlocks * kAlignSums];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;     // per device ordinal (null until looked up)
+
+static int32_t scratch_address(cgx_ctx* ctx, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= ctx->device) g_scratch_dev.resize(ctx->device + 1, nullptr);
+  if (!g_scratch_dev[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ctx, CGX_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s",
+                  ctx->device, hipGetErrorString(e));
+    g_scratch_dev[ctx->device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[ctx->device];
+  return CGX_OK;
+}
+
+extern "C" {
+
+int32_t cgx_depth_prior_align_noalloc(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                                      const float* prior, const float* points, int32_t n_points,
+                                      double* scale_shift, float* aligned, void* stream) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  int32_t rc = check_depth_align(ctx, views, n_views, prior, points, n_points, scale_shift);
+  if (rc) return rc;
+  if (depth_align_scratch_bytes(n_views) > sizeof(scratch))
+    return fail(ctx, CGX_ERR_CAPACITY,
+                "n_views %d: the allocation-free alignment holds partial sums of at most %d views",
+                n_views, kNoAllocAlignViews);
+  rc = set_device(ctx);
+  if (rc) return rc;
+  double* partial = nullptr;
+  rc = scratch_address(ctx, &partial);
+  if (rc) return rc;
+  return launch_depth_align(ctx, views, n_views, prior, points, n_points, partial, scale_shift,
+                            aligned, (hipStream_t)stream);
 }
 
 int32_t cgx_depth_prior_filter(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
