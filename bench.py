@@ -54,6 +54,11 @@ def parse():
                    help="skip the timing of the same step replayed from a captured hipGraph")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=4000)
+    p.add_argument("--cpu-workers", type=int, default=0,
+                   help="processes of the N-core oracle timing (0: the host's cores, at most 16)")
+    p.add_argument("--configs", type=str, default="3,4",
+                   help="further workloads timed after C2 (comma list of 3, 4; empty for none)")
+    p.add_argument("--config-steps", type=int, default=10)
     p.add_argument("--no-ncc", action="store_true",
                    help="skip the timing of the batch geometric loss (Eq. 10)")
     p.add_argument("--ncc-patches", type=int, default=4096,
@@ -78,7 +83,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_leg(args, wl):
+def gpu_leg(args, wl, tile=None, steps=None, warmup=None, per_view=None, graph=None, count=True):
+    """The fused step on workload wl: tile shape (WxH or 'auto'), `steps`
+    timed steps after `warmup`, the same step replayed from a hipGraph, the
+    per-view loop, peak HBM, and (count) one untimed counting step."""
+    tile = args.tile if tile is None else tile
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    per_view = (not args.no_per_view) if per_view is None else per_view
+    graph = (not args.no_graph) if graph is None else graph
     import numpy as np
     import torch
 
@@ -92,13 +105,13 @@ def gpu_leg(args, wl):
                normal=cat(wl.targets["normal"]))
     w3 = (1.0, 1.0, 1.0)
     tune_ms = None
-    if args.tile == "auto":
+    if tile == "auto":
         rd = render.Renderer(0, (16, 16))
         (tw, th), tune_ms = rd.autotune(wl.views, sc, tgt, w3, reps=3)
         log(f"[bench] autotuned tile {tw}x{th}: " +
             ", ".join(f"{a}x{b} {m:.3f} ms" for (a, b), m in tune_ms.items()))
     else:
-        tw, th = (int(x) for x in args.tile.split("x"))
+        tw, th = (int(x) for x in tile.split("x"))
         rd = render.Renderer(0, (tw, th))
     loss = torch.zeros(1, device=dev)
     # capacity discovery (grows the pair / row capacity on overflow)
@@ -107,16 +120,16 @@ def gpu_leg(args, wl):
     info0 = dict(rd.last_info)
     log(f"[bench] rows {info0['n_rows']} splats {info0['n_splats']} pairs {info0['n_pairs']} "
         f"loss {info0['loss']:.6f} workspace {rd.ws.numel() / 2**30:.2f} GiB")
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done; capacities {rd.cap}, workspace {rd.ws.numel() / 2**30:.2f} GiB")
+    log(f"[bench] warmup {warmup} done; capacities {rd.cap}, workspace {rd.ws.numel() / 2**30:.2f} GiB")
     torch.cuda.reset_peak_memory_stats()
 
-    B.cgx_timing_enable(rd.ctx, 16 * args.steps + 16)
+    B.cgx_timing_enable(rd.ctx, 16 * steps + 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -126,24 +139,25 @@ def gpu_leg(args, wl):
     info = rd.info()      # raises if a capacity was exceeded inside the timed region
     # the work counts of the roofline: one more step, untimed, with the
     # raster kernels' counting variants
-    rd.count_work(True)
-    rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
-    torch.cuda.synchronize()
-    counts = rd.info()
-    rd.count_work(False)
-    for k in ("entries_fwd", "evals_fwd", "evals_bwd"):
-        info[k] = counts[k]
+    if count:
+        rd.count_work(True)
+        rd.fwd_bwd_l1(wl.views, sc, tgt, w3, out=out, grads=grads, loss=loss, check=False)
+        torch.cuda.synchronize()
+        counts = rd.info()
+        rd.count_work(False)
+        for k in ("entries_fwd", "evals_fwd", "evals_bwd"):
+            info[k] = counts[k]
     log(f"[bench] per step: list entries walked fwd {info['entries_fwd']} bwd {info['entries_bwd']}, "
         f"opacity evaluations fwd {info['evals_fwd']} bwd {info['evals_bwd']}")
-    ms = (t1 - t0) / args.steps * 1e3
-    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step")
+    ms = (t1 - t0) / steps * 1e3
+    log(f"[bench] timed {steps} steps: {ms:.3f} ms/step")
     for k, (t, c) in phases.items():
         if c:
-            log(f"[bench]   {k:12s} {t / c:8.3f} ms x {c // args.steps} per step")
+            log(f"[bench]   {k:12s} {t / c:8.3f} ms x {c // steps} per step")
 
     # the same fused step replayed from a captured hipGraph (no phase events)
     graph_ms = None
-    if not args.no_graph:
+    if graph:
         side = torch.cuda.Stream()
         torch.cuda.synchronize()
         with torch.cuda.stream(side):
@@ -154,17 +168,17 @@ def gpu_leg(args, wl):
                 B.cgx_graph_launch(g, side)
             side.synchronize()
             t0g = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(steps):
                 B.cgx_graph_launch(g, side)
             side.synchronize()
-            graph_ms = (time.perf_counter() - t0g) / args.steps * 1e3
+            graph_ms = (time.perf_counter() - t0g) / steps * 1e3
             rd.info()     # raises if a replay exceeded a capacity
         finally:
             B.cgx_graph_destroy(g)
         log(f"[bench] hipGraph replay: {graph_ms:.3f} ms/step")
 
     per_view_ms = None
-    if not args.no_per_view and len(wl.views) > 1:
+    if per_view and len(wl.views) > 1:
         rv = render.Renderer(0, (tw, th))
         rv.cap = dict(rd.cap)
         offs = render.pixel_offsets(wl.views)
@@ -182,7 +196,7 @@ def gpu_leg(args, wl):
             for (views1, t1v), (o1, g1) in zip(singles, bufs):
                 rv.fwd_bwd_l1(views1, sc, t1v, w3, out=o1, grads=g1, loss=loss, check=False)
         torch.cuda.synchronize()
-        reps = max(3, args.steps // 2)
+        reps = max(3, steps // 2)
         t0 = time.perf_counter()
         for _ in range(reps):
             for (views1, t1v), (o1, g1) in zip(singles, bufs):
@@ -279,17 +293,49 @@ def roofline(res, steps):
     return r
 
 
-def cpu_baseline(wl, n_sample_tiles):
+_ORACLE_JOB = None     # (splats, views, layout, sorted, view arrays, targets), inherited by fork
+
+
+def _oracle_tiles(tiles):
+    """Compositing + L1 + compositing adjoint of view 0 on the given tiles
+    (one thread); the rest of the job comes from _ORACLE_JOB."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import raster as oras
+    S, views, layout, srt, varr, targets = _ORACLE_JOB
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        imgs = oras.render_images([S], views, layout, srt, varr, keep_tiles=tiles)
+        L, og = oras.l1_seed(imgs, targets)
+        oras.composite_backward([S], views, imgs, og, varr)
+        return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, n_sample_tiles, workers):
     """The FP64 oracle on a bounded sample of the workload: view 0 only;
     selection, decode, projection and sort of all of view 0, compositing and
     its adjoint on a seeded sample of view 0's tiles, the projection and
     decoder adjoint of all of view 0; the tile part is scaled to all of
-    view 0's tiles.  One thread (BLAS pinned to 1)."""
+    view 0's tiles.  Timed on one thread (BLAS pinned to 1), then with the
+    tile part split over `workers` processes (forked before the GPU is
+    touched, one thread each)."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import anchors as oanc
-    from oracle import pipeline as opipe
     from oracle import project as oprj
     from oracle import raster as oras
 
@@ -308,25 +354,72 @@ def cpu_baseline(wl, n_sample_tiles):
         rng = np.random.default_rng(1234)
         sample = np.sort(rng.choice(n_tiles, min(n_sample_tiles, n_tiles), replace=False))
         varr = [oprj.view_arrays(views[0])]
-        t0 = time.perf_counter()
-        imgs = oras.render_images([S], views, layout, srt, varr, keep_tiles=sample)
         tg = {k: [wl.targets[k][0]] for k in ("rgb", "depth", "normal")}
+        global _ORACLE_JOB
+        _ORACLE_JOB = (S, views, layout, srt, varr, tg)
+        t_tiles = _oracle_tiles(sample)
+        t0 = time.perf_counter()
+        imgs = oras.render_images([S], views, layout, srt, varr, keep_tiles=sample[:1])
         L, og = oras.l1_seed(imgs, tg)
         sg = oras.composite_backward([S], views, imgs, og, varr)
-        t_tiles = time.perf_counter() - t0
-        t0 = time.perf_counter()
         pg = oprj.project_backward(S, sg[0])
         gparts = {k: pg[k] for k in ("mu", "scales", "quats", "opacity", "rgb")}
         oanc.decode_backward(sc, D, gparts)
         t_fixed += time.perf_counter() - t0
     px = int(views[0].width) * int(views[0].height)
-    t_est = t_fixed + t_tiles * n_tiles / len(sample)
-    return dict(value=px / t_est / 1e6, unit="Mpixels/s", cores=1, kind="oracle",
+    scale = n_tiles / len(sample)
+    t_1 = t_fixed + t_tiles * scale
+    # the tile part over `workers` processes: wall time of the pool
+    shares = [sample[i::workers] for i in range(workers)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))         # the workers are up before the clock starts
+        t0 = time.perf_counter()
+        pool.map(_oracle_tiles, [sh for sh in shares if sh.size])
+        t_par = time.perf_counter() - t0
+    t_n = t_fixed + t_par * scale
+    return dict(value=px / t_n / 1e6, unit="Mpixels/s", cores=workers, kind="oracle",
+                value_1core=px / t_1 / 1e6, cpu=cpu_model(), cpu_count=os.cpu_count(),
                 sample=(f"view 0 of C2 ({views[0].width}x{views[0].height}, {rows.shape[0]} rows): "
                         f"select/decode/project/sort and the projection+decoder adjoint in full "
-                        f"({t_fixed:.1f} s), compositing + L1 + compositing adjoint on {len(sample)} "
-                        f"of {n_tiles} tiles ({t_tiles:.1f} s) scaled to all tiles; float64 NumPy, "
-                        f"1 thread"))
+                        f"({t_fixed:.1f} s, one thread), compositing + L1 + compositing adjoint on "
+                        f"{len(sample)} of {n_tiles} tiles scaled to all tiles ({t_tiles:.1f} s on one "
+                        f"thread, {t_par:.1f} s over {workers} processes); float64 NumPy"))
+
+
+def config_leg(args, k):
+    """Throughput of the fused step on workload C3 or C4 (batched vs per
+    view, peak HBM).  C4 runs with the autotuned tile shape and reports its
+    hipGraph replay."""
+    import torch
+
+    from synth import scenes
+    t0 = time.perf_counter()
+    wl = scenes.make(k)
+    log(f"[bench] workload {wl.name}: {len(wl.views)} views, {wl.pixels} pixels "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    res = gpu_leg(args, wl, tile="auto" if k == 4 else args.tile, steps=args.config_steps, warmup=2,
+                  per_view=True, graph=(k == 4), count=False)
+    desc = {3: "C3: 600,000 voxel anchors x 10 Gaussians (6M), 4 views 3840x2160, per-view LoD, "
+               "fused fwd+L1+bwd",
+            4: "C4: 2,000,000 voxel anchors x 10 Gaussians (20M) over 1x1 km, 16 nadir/oblique views "
+               "1600x1200, autotuned tile, fused fwd+L1+bwd"}[k]
+    out = {"workload": desc, "views": len(wl.views), "pixels": wl.pixels, "tile": res["tile"],
+           "ms_per_step": round(res["ms"], 4),
+           "Mpixels_per_s": round(wl.pixels / (res["ms"] * 1e-3) / 1e6, 3),
+           "per_view_ms": round(res["per_view_ms"], 4) if res["per_view_ms"] else None,
+           "batched_vs_per_view": (round(res["per_view_ms"] / res["ms"], 3)
+                                   if res["per_view_ms"] else None),
+           "ms_per_step_graph": round(res["graph_ms"], 4) if res["graph_ms"] else None,
+           "peak_hbm_gib": round(res["peak_bytes"] / 2**30, 3),
+           "rows": res["info"]["n_rows"], "pairs": res["info"]["n_pairs"],
+           "phases_ms": {p: round(t / max(args.config_steps, 1), 4)
+                         for p, (t, c) in res["phases"].items() if c}}
+    log(f"[bench] {wl.name}: {out['ms_per_step']} ms/step, {out['Mpixels_per_s']} Mpixels/s, "
+        f"batched vs per-view {out['batched_vs_per_view']}, peak HBM {out['peak_hbm_gib']} GiB")
+    del wl, res
+    torch.cuda.empty_cache()
+    return out
 
 
 def ncc_leg(args):
@@ -494,6 +587,14 @@ def main():
     from synth import scenes
     t0 = time.perf_counter()
     wl = scenes.make(args.config)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the worker processes are forked
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        cpu = cpu_baseline(wl, args.cpu_sample_tiles, workers)
+        log(f"[bench] cpu baseline took {time.perf_counter() - t1:.1f} s: "
+            f"{cpu['value_1core']:.4f} Mpixels/s on one thread, {cpu['value']:.4f} on {workers}")
     log(f"[bench] workload {wl.name}: {len(wl.views)} views, {wl.pixels} pixels "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
     if args.copy_calibration:
@@ -532,10 +633,12 @@ def main():
         line["depth_prior"] = depth_prior_leg(args)
     if not args.no_tsdf:
         line["tsdf_fusion"] = tsdf_leg(args)
-    if not args.no_cpu_baseline:
-        t0 = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tiles)
-        log(f"[bench] cpu baseline took {time.perf_counter() - t0:.1f} s")
+    extra = [int(c) for c in args.configs.split(",") if c.strip()]
+    if extra and args.config == 2:
+        del res
+        line["configs"] = {f"C{k}": config_leg(args, k) for k in extra if k in (3, 4)}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
