@@ -30,6 +30,17 @@ view.  Readings of what the paper leaves open:
     offset O_k itself (no activation), z2[14k+11 : 14k+14]; then
     mu_k = x + O_k * l with that O_k, and the anchor table's offsets are
     not used (their gradient is zero);
+  * head variant (row f3, "a set of shared Gaussian Decoders"): with
+    decoder_heads = 3 each attribute group has an MLP of its own, 36 -> 32
+    (ReLU) -> n * width: opacity (width 1), colour (3), covariance (scale
+    and quaternion, 7), and with decoded offsets a fourth, the offsets (3).
+    Their weights sit side by side: W1 is 36 x 32H with head h reading
+    hidden columns 32h .. 32h+31, b1 has 32H entries, and W2 (32 x n*G)
+    and b2 keep the per-Gaussian output count G of the shared decoder but
+    group their columns by head: head h owns the n * width_h columns that
+    start at n * first_h, and Gaussian k's attribute first_h + j is its
+    column n * first_h + k * width_h + j.  With one head this is the
+    shared decoder's layout (column k * G + j);
   * the feature F is rounded to bfloat16 (weights are given in bfloat16);
     every other decoder value is carried exactly (float64 here).
 """
@@ -44,12 +55,31 @@ OPACITY_SIGMOID = 0
 OPACITY_TANH_MASK = 1
 OFFSETS_LEARNED = 0
 OFFSETS_DECODED = 1
+DECODER_SHARED = 1
+DECODER_PER_ATTRIBUTE = 3
+HIDDEN = 32
 
 
 def _per_gauss(scene):
     """Decoder outputs per Gaussian: 11, or 14 with decoder-emitted offsets."""
     return GAUSS_OUT + 3 if int(getattr(scene, "offset_mode", OFFSETS_LEARNED)) == OFFSETS_DECODED \
         else GAUSS_OUT
+
+
+def head_groups(scene):
+    """(first attribute, width) of the per-Gaussian outputs of each decoder
+    head: one shared head of all G outputs, or one head per attribute group
+    (opacity, colour, covariance, and the offsets when they are decoded)."""
+    go = _per_gauss(scene)
+    heads = int(getattr(scene, "decoder_heads", DECODER_SHARED))
+    if heads == DECODER_SHARED:
+        return [(0, go)]
+    if heads != DECODER_PER_ATTRIBUTE:
+        raise ValueError(f"decoder_heads {heads} is neither 1 nor 3")
+    groups = [(0, 1), (1, 3), (4, 7)]
+    if go > GAUSS_OUT:
+        groups.append((GAUSS_OUT, 3))
+    return groups
 
 
 def select(scene, views):
@@ -115,12 +145,24 @@ def decode(scene, views, rows, emulate_bf16=True):
     W2 = bfmod.from_bits(scene.W2_bits) if W2 is None else np.asarray(W2, np.float64)
     b1 = np.asarray(scene.b1, np.float64)
     b2 = np.asarray(scene.b2, np.float64)
-    pre1 = z0 @ W1 + b1
-    z1 = np.maximum(pre1, 0.0)
-    z2 = z1 @ W2 + b2
     r = rows.shape[0]
     go = _per_gauss(scene)
-    g = z2.reshape(r, n, go)
+    heads = head_groups(scene)
+    # each head is an MLP of its own: hidden block h of W1 / b1, then its
+    # column block of W2 / b2; g collects the per-Gaussian outputs
+    g = np.empty((r, n, go))
+    pre1, z1, z2 = [], [], []
+    for h, (first, width) in enumerate(heads):
+        hid = slice(HIDDEN * h, HIDDEN * (h + 1))
+        cols = slice(n * first, n * (first + width))
+        p = z0 @ W1[:, hid] + b1[hid]
+        z = np.maximum(p, 0.0)
+        y = z @ W2[:, cols] + b2[cols]
+        g[..., first:first + width] = y.reshape(r, n, width)
+        pre1.append(p)
+        z1.append(z)
+        z2.append(y)
+    pre1, z1, z2 = (np.concatenate(t, 1) for t in (pre1, z1, z2))
     a = rows[:, 1]
     x = np.asarray(scene.x, np.float64)[a]
     l = np.asarray(scene.l, np.float64)[a]
@@ -138,7 +180,7 @@ def decode(scene, views, rows, emulate_bf16=True):
         quats=quats.reshape(-1, 4), opacity=op.reshape(-1), rgb=rgb.reshape(-1, 3),
         frag_relu=frag_relu,
         _z0=z0, _pre1=pre1, _z1=z1, _z2=z2, _W1=W1, _W2=W2, _geo=geo, _l=l, _O=O,
-        _ssig=ssig, _op=op, _rgb=rgb, _act=act, _go=go)
+        _ssig=ssig, _op=op, _rgb=rgb, _act=act, _go=go, _heads=heads)
 
 
 def decode_backward(scene, D, g):
@@ -168,14 +210,21 @@ def decode_backward(scene, D, g):
         dz2[..., 11:14] = dO
         dO = np.zeros_like(dO)
     dx = np.sum(gm, axis=1)
-    dz2 = dz2.reshape(r, n * go_)
     W1, W2 = D["_W1"], D["_W2"]
-    dW2 = D["_z1"].T @ dz2
-    db2 = dz2.sum(0)
-    dz1 = (dz2 @ W2.T) * (D["_pre1"] > 0)
-    dW1 = D["_z0"].T @ dz1
-    db1 = dz1.sum(0)
-    dz0 = dz1 @ W1.T
+    z0, z1, pre1 = D["_z0"], D["_z1"], D["_pre1"]
+    dW1, db1 = np.zeros_like(W1), np.zeros(W1.shape[1])
+    dW2, db2 = np.zeros_like(W2), np.zeros(W2.shape[1])
+    dz0 = np.zeros_like(z0)
+    for h, (first, width) in enumerate(D.get("_heads", [(0, go_)])):
+        hid = slice(HIDDEN * h, HIDDEN * (h + 1))
+        cols = slice(n * first, n * (first + width))
+        dy = dz2[..., first:first + width].reshape(r, n * width)
+        dW2[:, cols] = z1[:, hid].T @ dy
+        db2[cols] = dy.sum(0)
+        dz1 = (dy @ W2[:, cols].T) * (pre1[:, hid] > 0)
+        dW1[:, hid] = z0.T @ dz1
+        db1[hid] = dz1.sum(0)
+        dz0 += dz1 @ W1[:, hid].T
     geo = D["_geo"]
     dF = dz0[:, :32]
     ddir, ddel = dz0[:, 32:35], dz0[:, 35]

@@ -169,13 +169,15 @@ class AnchorScene:
     O: np.ndarray           # (A, n, 3) f32 learnable offsets
     F: np.ndarray           # (A, 32) f32 features
     level: np.ndarray       # (A,) u8 LoD level, 0 = coarsest
-    W1_bits: np.ndarray     # (36, 32) u16 bf16 bit patterns (input-major)
-    b1: np.ndarray          # (32,) f32
-    W2_bits: np.ndarray     # (32, 110) u16 bf16 bit patterns
-    b2: np.ndarray          # (110,) f32
+    W1_bits: np.ndarray     # (36, 32H) u16 bf16 bit patterns (input-major), H decoder heads
+    b1: np.ndarray          # (32H,) f32
+    W2_bits: np.ndarray     # (32, n G) u16 bf16 bit patterns, G = 11 or 14 outputs per Gaussian
+    b2: np.ndarray          # (n G,) f32
     n_levels: int
     d_max: float
     opacity_act: int = 0    # 0: sigmoid; 1: tanh with non-positive opacities masked
+    offset_mode: int = 0    # 0: offsets from the table O; 1: decoded (14 outputs per Gaussian)
+    decoder_heads: int = 1  # 1: one shared MLP; 3: one MLP per attribute group
 
     @property
     def n(self):
@@ -515,12 +517,58 @@ def make_small_explicit(seed, n=40, width=48, height=40, sh_degree=0,
     return wl
 
 
+def head_layout(offset_mode, decoder_heads, n=N_OFFSETS):
+    """(first attribute, width) per decoder head, and the decoder's output
+    count per Gaussian: one shared head, or one head per attribute group
+    (opacity 1, colour 3, scale and quaternion 7, decoded offsets 3)."""
+    go = GAUSS_OUT + 3 if offset_mode else GAUSS_OUT
+    if decoder_heads == 1:
+        return [(0, go)], go
+    groups = [(0, 1), (1, 3), (4, 7)] + ([(GAUSS_OUT, 3)] if offset_mode else [])
+    return groups, go
+
+
+def attribute_columns(offset_mode, decoder_heads, m, n=N_OFFSETS):
+    """Decoder output columns of attribute m of Gaussians 0..n-1: head h
+    owns the n * width columns from n * first, Gaussian k's attribute
+    first + j at n * first + k * width + j."""
+    for first, width in head_layout(offset_mode, decoder_heads, n)[0]:
+        if first <= m < first + width:
+            return n * first + np.arange(n) * width + (m - first)
+    raise ValueError(m)
+
+
+def decoder_variant(rng, scene, offset_mode=0, decoder_heads=1):
+    """Fresh decoder weights for a variant: W1 36 x 32H, W2 32 x n*G with the
+    head-grouped columns, uniform(+-1/sqrt(fan-in)) like the shared
+    decoder; decoded offsets get biases of the table's spread and weights
+    at half scale."""
+    heads, go = head_layout(offset_mode, decoder_heads)
+    n = scene.O.shape[1]
+    hid = MLP_HIDDEN * len(heads)
+    lim1, lim2 = 1.0 / np.sqrt(MLP_IN), 1.0 / np.sqrt(MLP_HIDDEN)
+    W1 = rng.uniform(-lim1, lim1, (MLP_IN, hid)).astype(np.float32)
+    b1 = rng.uniform(-lim1, lim1, hid).astype(np.float32)
+    W2 = rng.uniform(-lim2, lim2, (MLP_HIDDEN, n * go)).astype(np.float32)
+    b2 = rng.uniform(-lim2, lim2, n * go).astype(np.float32)
+    if offset_mode:
+        for c in range(3):
+            cols = attribute_columns(offset_mode, decoder_heads, GAUSS_OUT + c, n)
+            W2[:, cols] *= 0.5
+            b2[cols] = rng.normal(0.0, 0.4, n).astype(np.float32)
+    scene.W1_bits, scene.b1 = bf16_bits(W1), b1
+    scene.W2_bits, scene.b2 = bf16_bits(W2), b2
+    scene.offset_mode, scene.decoder_heads = int(offset_mode), int(decoder_heads)
+
+
 def make_small_anchor(seed, n_anchor=60, n_views=2, sizes=((40, 32), (24, 36)),
-                      d_max=12.0, opacity_act=0) -> Workload:
+                      d_max=12.0, opacity_act=0, offset_mode=0, decoder_heads=1) -> Workload:
     """A small anchor scene with two LoD levels and views of different
     sizes at different distances.  opacity_act = 1 selects the tanh opacity
     with non-positive opacities masked; the opacity biases are then spread
-    around zero so that about half of the Gaussians are masked."""
+    around zero so that about half of the Gaussians are masked.
+    offset_mode = 1 (decoded offsets) or decoder_heads = 3 (one MLP per
+    attribute group) draw decoder weights of that shape."""
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1.0, 1.0, (n_anchor, 3)).astype(np.float32)
     x[:, 2] *= 0.3
@@ -529,10 +577,13 @@ def make_small_anchor(seed, n_anchor=60, n_views=2, sizes=((40, 32), (24, 36)),
     scene = _anchor_attrs(rng, x, level, delta, d_max, n_levels=3)
     # keep the decoded Gaussians small relative to the views
     scene.O[:] = (scene.O * 0.8).astype(np.float32)
+    if offset_mode or decoder_heads != 1:
+        decoder_variant(np.random.default_rng(seed + 7000), scene, offset_mode, decoder_heads)
     if opacity_act:
         scene.opacity_act = int(opacity_act)
         n_off = scene.O.shape[1]
-        scene.b2[0::11] = rng.normal(0.0, 0.8, n_off).astype(np.float32)
+        cols = attribute_columns(scene.offset_mode, scene.decoder_heads, 0, n_off)
+        scene.b2[cols] = rng.normal(0.0, 0.8, n_off).astype(np.float32)
     views = []
     for i in range(n_views):
         W, H = sizes[i % len(sizes)]

@@ -225,10 +225,13 @@ def _select(scene, views):
     return np.concatenate(rows).astype(np.int64)
 
 
-def _decode(scene, views, rows, x, l, O, F, W1, b1, W2, b2, act):
+def _decode(scene, views, rows, x, l, O, F, W1, b1, W2, b2, act, offsets=0, heads=1):
     """Eq. 4 per active (view, anchor) row: z0 = [bf16(F), direction to the
     camera, distance / d_max] -> 32 (ReLU) -> 11 per Gaussian (opacity, rgb,
-    scale, quaternion); mu = x + O * l."""
+    scale, quaternion); mu = x + O * l.  offsets = 1: 3 more outputs per
+    Gaussian are its offset O.  heads = 3: one such MLP per attribute group
+    (opacity, colour, scale + quaternion, offsets), each with 32 hidden
+    units of W1 and a block of n * width columns of W2."""
     a = torch.tensor(rows[:, 1], dtype=torch.long)
     cams = torch.stack([-(_view(v)["R"].T @ _view(v)["t"]) for v in views])
     delta = cams[torch.tensor(rows[:, 0], dtype=torch.long)] - x[a]
@@ -238,19 +241,33 @@ def _decode(scene, views, rows, x, l, O, F, W1, b1, W2, b2, act):
     Fa = F[a]
     Fb = Fa + (Fa.detach().to(torch.float32).to(torch.bfloat16).to(f64) - Fa.detach())
     z0 = torch.cat([Fb, delta / dist[:, None], (dist / dmax)[:, None]], 1)
-    z1 = torch.relu(z0 @ W1 + b1)
     n = O.shape[1]
-    g = (z1 @ W2 + b2).reshape(-1, n, 11)
+    go = 14 if offsets else 11
+    if heads == 1:
+        g = (torch.relu(z0 @ W1 + b1) @ W2 + b2).reshape(-1, n, go)
+    else:
+        widths = [1, 3, 7] + ([3] if offsets else [])
+        parts, c0 = [], 0
+        for h, w in enumerate(widths):
+            z1 = torch.relu(z0 @ W1[:, 32 * h:32 * h + 32] + b1[32 * h:32 * h + 32])
+            y = z1 @ W2[:, c0:c0 + n * w] + b2[c0:c0 + n * w]
+            parts.append(y.reshape(-1, n, w))
+            c0 += n * w
+        g = torch.cat(parts, 2)
     op = torch.tanh(g[..., 0]) if act == 1 else torch.sigmoid(g[..., 0])
     rgb = torch.sigmoid(g[..., 1:4])
     s = l[a][:, None, :] * torch.sigmoid(g[..., 4:7])
-    mu = x[a][:, None, :] + O[a] * l[a][:, None, :]
+    off = g[..., 11:14] if offsets else O[a]
+    mu = x[a][:, None, :] + off * l[a][:, None, :]
     return mu, s, g[..., 7:11], op, rgb
 
 
-@pytest.mark.parametrize("seed,act", [(46, 0), (50, 0), (41, 1), (54, 1)])
-def test_anchor_adjoint_equals_autograd(seed, act):
-    wl = scenes.make_small_anchor(seed, n_anchor=16, opacity_act=act)
+@pytest.mark.parametrize("seed,act,offsets,heads", [(46, 0, 0, 1), (50, 0, 0, 1), (41, 1, 0, 1),
+                                                   (54, 1, 0, 1), (53, 0, 1, 1), (55, 0, 0, 3),
+                                                   (58, 1, 1, 3)])
+def test_anchor_adjoint_equals_autograd(seed, act, offsets, heads):
+    wl = scenes.make_small_anchor(seed, n_anchor=16, opacity_act=act, offset_mode=offsets,
+                                  decoder_heads=heads)
     sc = wl.scene
     r = pipeline.render_anchor(sc, wl.views)
     _no_ties(r)
@@ -266,12 +283,15 @@ def test_anchor_adjoint_equals_autograd(seed, act):
     imgs = []
     for v, view in enumerate(wl.views):
         rows = all_rows[all_rows[:, 0] == v]
-        mu, s, q, o, rgb = _decode(sc, wl.views, rows, x, l, O, F, W1, b1, W2, b2, act)
+        mu, s, q, o, rgb = _decode(sc, wl.views, rows, x, l, O, F, W1, b1, W2, b2, act,
+                                   offsets, heads)
         imgs.append(render_view(mu.reshape(-1, 3), s.reshape(-1, 3), q.reshape(-1, 4),
                                 o.reshape(-1), rgb.reshape(-1, 3), _view(view)))
     for a, b in zip(imgs, r.images):
         for key in ("rgb", "D", "normal", "alpha", "depth"):
             _close(key, a[key].detach().numpy(), b[key])
-    grads = torch.autograd.grad(_loss(imgs, og), leaves)
-    for name, g in zip(names, grads):
+    # with decoded offsets the table O is unused: its gradient is zero
+    grads = torch.autograd.grad(_loss(imgs, og), leaves, allow_unused=bool(offsets))
+    for name, g, leaf in zip(names, grads, leaves):
+        g = torch.zeros_like(leaf) if g is None else g
         _close("d_" + name, ref[name], g.numpy())
