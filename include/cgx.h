@@ -51,12 +51,12 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 6
+#define CGX_ABI_VERSION 7
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
-#define CGX_MLP_HIDDEN 32
-#define CGX_GAUSS_OUT 11       /* per Gaussian: opacity 1, rgb 3, scale 3, quaternion 4 */
+#define CGX_MLP_HIDDEN 32      /* hidden units per decoder head */
+#define CGX_GAUSS_OUT 11       /* per Gaussian: opacity 1, rgb 3, scale 3, quaternion 4 (14 with decoded offsets) */
 #define CGX_MAX_OFFSETS 16
 
 typedef enum cgx_status {
@@ -102,28 +102,46 @@ typedef struct cgx_explicit_scene {
 
 /* Voxel anchors (Sec. 3.2, Eq. 4; device arrays, anchor-major):
  *   x [A][3], l [A][3], O [A][n][3], F [A][32] float32, level [A] uint8
- *   (0 = coarsest).  Decoder: W1 [36][32] and W2 [32][11 n] as bfloat16 bit
- *   patterns (input-major: out = in . W + b), b1 [32], b2 [11 n] float32.
+ *   (0 = coarsest).  Decoder (H heads, G outputs per Gaussian, below):
+ *   W1 [36][32 H] and W2 [32][G n] as bfloat16 bit patterns (input-major:
+ *   out = in . W + b), b1 [32 H], b2 [G n] float32.
  * Anchor a is active in view v when level[a] == 0 or
  *   |x_a - c_v|^2 4^level[a] <= d_max^2 (that is, level[a] <=
  *   floor(log2(d_max / |x_a - c_v|)), clamped to [0, K-1]), and its centre
  *   passes the frustum test p_z > z_near, |p_x| <= 1.3 W/(2 fx) p_z,
  *   |p_y| <= 1.3 H/(2 fy) p_z; both in float64.
- * Decoder input z0 = [bf16(F), (c_v - x_a)/|c_v - x_a|, |c_v - x_a|/d_max],
- *   z1 = relu(z0 W1 + b1), z2 = z1 W2 + b2; Gaussian k reads z2[11k..11k+10]
- *   as opacity = sigmoid, rgb = sigmoid, scale = l * sigmoid, quaternion
- *   (normalised at projection); mu_k = x + O_k * l.
+ * Decoder input z0 = [bf16(F), (c_v - x_a)/|c_v - x_a|, |c_v - x_a|/d_max].
+ *   Per Gaussian k the G = 11 attributes are opacity (1), rgb (3), scale
+ *   (3), quaternion (4), read as opacity = sigmoid, rgb = sigmoid,
+ *   scale = l * sigmoid, quaternion (normalised at projection);
+ *   mu_k = x + O_k * l.
+ * decoder_heads = CGX_DECODER_SHARED: one MLP, z1 = relu(z0 W1 + b1),
+ *   z2 = z1 W2 + b2, Gaussian k's attribute j is z2[G k + j].
+ * decoder_heads = CGX_DECODER_PER_ATTRIBUTE ("a set of shared Gaussian
+ *   Decoders", Sec. 3.2): one MLP per attribute group, opacity (first
+ *   attribute 0, width 1), colour (1, 3), scale + quaternion (4, 7), and
+ *   with decoded offsets the offset (11, 3).  Head h uses hidden units
+ *   32h..32h+31 (W1 columns, b1 entries) and the W2 / b2 columns
+ *   n first_h .. n (first_h + width_h) - 1; Gaussian k's attribute
+ *   first_h + j is column n first_h + k width_h + j.
+ * offset_mode = CGX_OFFSETS_DECODED: G = 14, attributes 11..13 of Gaussian
+ *   k are its offset O_k (no activation), used in place of the table's;
+ *   O may then be NULL and its gradient buffer too (else it is zeroed).
  * opacity_act = CGX_OPACITY_TANH_MASK reads the opacity as tanh instead and
  *   masks out (draws nothing of, gives no tiles and zero gradient to) the
- *   Gaussians with opacity <= 0, the masked-opacity decoder variant; any
- *   other value than the two is CGX_ERR_INVALID_ARG. */
+ *   Gaussians with opacity <= 0, the masked-opacity decoder variant.
+ * Any other value of the three selectors is CGX_ERR_INVALID_ARG. */
 enum { CGX_OPACITY_SIGMOID = 0, CGX_OPACITY_TANH_MASK = 1 };
+enum { CGX_OFFSETS_TABLE = 0, CGX_OFFSETS_DECODED = 1 };
+enum { CGX_DECODER_SHARED = 1, CGX_DECODER_PER_ATTRIBUTE = 3 };
 typedef struct cgx_anchor_scene {
   int64_t n_anchor;
   int32_t n_offsets;            /* n, 1..16 */
   int32_t n_levels;             /* K */
   float d_max;
   int32_t opacity_act;          /* CGX_OPACITY_SIGMOID or CGX_OPACITY_TANH_MASK */
+  int32_t offset_mode;          /* CGX_OFFSETS_TABLE or CGX_OFFSETS_DECODED */
+  int32_t decoder_heads;        /* CGX_DECODER_SHARED or CGX_DECODER_PER_ATTRIBUTE */
   const float* x;
   const float* l;
   const float* O;
@@ -155,7 +173,7 @@ typedef struct cgx_images {
 } cgx_images;
 
 /* Gradients (device), same layouts as the scene arrays; W1 / W2 gradients
- * are float32 [36][32] and [32][11 n].  The backward call overwrites them. */
+ * are float32 [36][32 H] and [32][G n].  The backward call overwrites them. */
 typedef struct cgx_grads {
   float* means; float* scales; float* quats; float* opacity; float* sh;
   float* x; float* l; float* O; float* F;
@@ -223,19 +241,32 @@ int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
                             const cgx_images* out, const cgx_images* grad_out,
                             const cgx_grads* grads, void* stream);
 
+/* The batch geometric loss term of Eq. 10 in the fused chain (Sec. 3.4):
+ * patch centres and weight exactly as for cgx_ncc_loss below (device int32
+ * (x, y) pairs, pair-major, n_patch per view pair). */
+typedef struct cgx_ncc_term {
+  const int32_t* centres;
+  int32_t n_patch;
+  float weight;
+} cgx_ncc_term;
+
 /* One launch chain: forward, the batch L1 loss of Eq. 8 against `target`
  * (rgb, depth and normal, weights w[0..2]; per-image mean over pixels,
  * averaged over the batch, sign(0) = 0) and the backward pass.  loss_dev:
  * one float on the device receiving the loss (may be NULL).  The depth
  * target is the filtered depth prior of Sec. 3.4, Step 2: a target depth
  * that is not positive (or NaN) marks a pixel without a prior, which adds
- * no depth loss and no depth gradient (the per-image mean still counts it). */
+ * no depth loss and no depth gradient (the per-image mean still counts it).
+ * ncc (host struct, may be NULL or have n_patch = 0): adds the geometric
+ * loss of Eq. 10 on the forward images (the loss and gradient of
+ * cgx_ncc_loss); its per-pixel gradient stays in the workspace and is
+ * folded into the RGB seed of the backward raster beside the L1 terms. */
 int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                               const cgx_scene* scene, const cgx_capacity* cap,
                               void* workspace, size_t workspace_bytes,
                               const cgx_images* target, const float* w3_host,
-                              const cgx_images* out, const cgx_grads* grads,
-                              float* loss_dev, void* stream);
+                              const cgx_ncc_term* ncc, const cgx_images* out,
+                              const cgx_grads* grads, float* loss_dev, void* stream);
 
 /* Synchronise `stream` and read the counters of the last chain enqueued on
  * this workspace.  Returns CGX_ERR_CAPACITY if a capacity was exceeded. */
@@ -277,8 +308,9 @@ int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_
                                      const cgx_scene* scene, const cgx_capacity* cap,
                                      void* workspace, size_t workspace_bytes,
                                      const cgx_images* target, const float* w3_host,
-                                     const cgx_images* out, const cgx_grads* grads,
-                                     float* loss_dev, void* stream, cgx_graph** graph);
+                                     const cgx_ncc_term* ncc, const cgx_images* out,
+                                     const cgx_grads* grads, float* loss_dev, void* stream,
+                                     cgx_graph** graph);
 int32_t cgx_graph_launch(cgx_graph* graph, void* stream);
 int32_t cgx_graph_destroy(cgx_graph* graph);
 

@@ -42,7 +42,18 @@ view.  Readings of what the paper leaves open:
     column n * first_h + k * width_h + j.  With one head this is the
     shared decoder's layout (column k * G + j);
   * the feature F is rounded to bfloat16 (weights are given in bfloat16);
-    every other decoder value is carried exactly (float64 here).
+    every other decoder value is carried exactly (float64 here);
+  * decoded offsets move the mean by the decoder's own float32 error, which
+    the GPU cannot avoid.  Each decoder output is a float32 sum of at most
+    97 terms (hidden units times split terms, and the bias); its error is
+    taken as at most DEC_ERR = 2^-20 (16 unit roundoffs) of the sum of the
+    terms' magnitudes, plus the hidden layer's own error of that size
+    carried through |W2|.  That is a margin, like the other near-tie
+    margins, not a worst-case bound (recursive summation allows 97 unit
+    roundoffs): float32 evaluations in BLAS and sequential order stay below
+    one unit roundoff of it.  decode() returns it on the mean, l times the
+    offset's, as mu_tol; the decisions and depth keys that depend on the
+    mean treat it as rounding (near ties, key tolerance).
 """
 import numpy as np
 
@@ -58,6 +69,7 @@ OFFSETS_DECODED = 1
 DECODER_SHARED = 1
 DECODER_PER_ATTRIBUTE = 3
 HIDDEN = 32
+DEC_ERR = 2.0 ** -20
 
 
 def _per_gauss(scene):
@@ -175,10 +187,25 @@ def decode(scene, views, rows, emulate_bf16=True):
     scales = l[:, None, :] * ssig
     quats = g[..., 7:11]
     frag_relu = np.any(np.abs(pre1) < FRAG * (np.abs(z0) @ np.abs(W1) + np.abs(b1)), axis=1)
+    mu_tol = None
+    if go > GAUSS_OUT:
+        e1 = DEC_ERR * (np.abs(z0) @ np.abs(W1) + np.abs(b1))       # hidden-layer error bound
+        eO = np.zeros((r, n, 3))
+        for h, (first, width) in enumerate(heads):
+            hid = slice(HIDDEN * h, HIDDEN * (h + 1))
+            for c in range(3):
+                m = GAUSS_OUT + c
+                if not first <= m < first + width:
+                    continue
+                cols = n * first + np.arange(n) * width + (m - first)
+                aW = np.abs(W2[:, cols])
+                eO[..., c] = (DEC_ERR * (np.abs(z1[:, hid]) @ aW + np.abs(b2[cols]))
+                              + e1[:, hid] @ aW)
+        mu_tol = (eO * l[:, None, :]).reshape(-1, 3)
     return dict(
         n=n, rows=rows, mu=mu.reshape(-1, 3), scales=scales.reshape(-1, 3),
         quats=quats.reshape(-1, 4), opacity=op.reshape(-1), rgb=rgb.reshape(-1, 3),
-        frag_relu=frag_relu,
+        frag_relu=frag_relu, mu_tol=mu_tol,
         _z0=z0, _pre1=pre1, _z1=z1, _z2=z2, _W1=W1, _W2=W2, _geo=geo, _l=l, _O=O,
         _ssig=ssig, _op=op, _rgb=rgb, _act=act, _go=go, _heads=heads)
 

@@ -47,7 +47,8 @@ def render_anchor(scene, views, tile=(16, 16), emulate_bf16=True, keep_tiles=Non
     for v, view in enumerate(views):
         sl = slice(offs[v] * n, offs[v + 1] * n)
         S = prj.project(D["mu"][sl], D["scales"][sl], D["quats"][sl], D["opacity"][sl],
-                        view, tile, colour=D["rgb"][sl], opacity_exact=False)
+                        view, tile, colour=D["rgb"][sl], opacity_exact=False,
+                        mu_tol=None if D["mu_tol"] is None else D["mu_tol"][sl])
         rfr = np.repeat(D["frag_relu"][offs[v]:offs[v + 1]], n)
         S["frag_grad"] = S["frag_grad"] | (S["valid"] & rfr)
         splats.append(S)

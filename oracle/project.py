@@ -84,7 +84,7 @@ def quat_to_rot_backward(qn, dR):
 MASK_TILES = 64     # boxes of 2 x 2 up to this many tiles carry a tile mask
 
 
-def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
+def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel, du=0.0, dw=0.0):
     """Tiles of the pixel box that the drawable ellipse reaches (reading of
     the tile binning, Sec. 3.3; row f3's ellipse-tile culling): bit
     r * nx + c for tile row r and tile column c of the box, for the splats in
@@ -104,7 +104,8 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
     drawable pixel centre is never dropped.  Decisions are float64 in this
     operation order (the GPU evaluates the same expressions); a comparison
     closer than the float32 covariance can resolve (relative `rel`, times
-    the conditioning of det) marks the splat's tile set fragile.
+    the conditioning of det), widened by the mean's error bound (du, dw
+    pixels), marks the splat's tile set fragile.
 
     Returns (mask uint64, fragile bool, fragile-tile mask uint64) per splat:
     the third value has the bits of the tiles whose own test is that close."""
@@ -117,6 +118,8 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
         return mask, frag, fmask
     u, w, A, B, C, tau = (np.asarray(a, np.float64)[idx] for a in (u, w, A, B, C, tau))
     rel = np.broadcast_to(np.asarray(rel, np.float64), (n,))[idx]
+    du = np.broadcast_to(np.asarray(du, np.float64), (n,))[idx]
+    dw = np.broadcast_to(np.asarray(dw, np.float64), (n,))[idx]
     xl_, xh_, yl_, yh_ = (np.asarray(a)[idx] for a in (x_lo, x_hi, y_lo, y_hi))
     tx0, tx1, ty0, ty1 = xl_ // tw, xh_ // tw, yl_ // th, yh_ // th
     nx, ny = tx1 - tx0 + 1, ty1 - ty0 + 1
@@ -139,7 +142,7 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
         r1 = np.minimum(ty * th + th - 1, yh_)
         lo = (r0 + 0.5) - w
         hi = (r1 + 0.5) - w
-        dym = rel * kappa * (ymax + 1.0) + 1e-9
+        dym = rel * kappa * (ymax + 1.0) + 1e-9 + dw
         rowfr = live & ((np.abs(lo - ymax) < dym) | (np.abs(hi + ymax) < dym))
         fr |= rowfr
         lo = np.maximum(lo, -ymax)
@@ -149,7 +152,7 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
         dr = np.minimum(np.maximum(ye, lo), hi)
         xl = u + (k * dl - np.sqrt(np.maximum(t2 - dl * dl * ic, 0.0) * s))
         xr = u + (k * dr + np.sqrt(np.maximum(t2 - dr * dr * ic, 0.0) * s))
-        marg = rel * kappa * (np.abs(xl - u) + np.abs(xr - u) + np.sqrt(t2 * A) + 1.0) + 1e-9
+        marg = rel * kappa * (np.abs(xl - u) + np.abs(xr - u) + np.sqrt(t2 * A) + 1.0) + 1e-9 + du
         for cc in range(int(nx.max())):
             on = row & (cc < nx)
             tx = tx0 + cc
@@ -169,7 +172,7 @@ def tile_mask(u, w, A, B, C, tau, x_lo, x_hi, y_lo, y_hi, tw, th, use, rel):
 
 
 def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_degree=0,
-            opacity_exact=True):
+            opacity_exact=True, mu_tol=None):
     """Project N Gaussians into one view.
 
     mu: (N,3) float64 centres (for explicit Gaussians the float32 inputs
@@ -178,7 +181,10 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     (N,3) or evaluated from sh (N,K,3).  tile = (tw, th).  opacity_exact:
     the GPU sees the same opacity (an input) rather than one it decoded
     itself in float32 (anchor Gaussians), which widens the fragile margin
-    of the opacity-aware box.
+    of the opacity-aware box.  mu_tol (N,3), optional: a bound on the
+    error of the GPU's mean (decoded offsets); the decisions that depend on
+    the mean widen their fragile margins by its image in pixels (du, dw)
+    and the depth key may differ by ztol units in the last place.
 
     Returns a dict of per-Gaussian arrays; `valid` marks the splats that
     survive culling and touch at least one tile.
@@ -200,6 +206,15 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     u = (fx * p[:, 0]) / pz + cx
     w = (fy * p[:, 1]) / pz + cy
     zbits = p[:, 2].astype(np.float32).view(np.uint32)
+    if mu_tol is None:
+        du = dw = np.zeros(n)
+        ztol = np.zeros(n, np.int64)
+    else:
+        dp = np.asarray(mu_tol, np.float64) @ np.abs(R).T      # camera-frame error bound
+        du = abs(fx) * (dp[:, 0] / pz + np.abs(p[:, 0]) * dp[:, 2] / (pz * pz))
+        dw = abs(fy) * (dp[:, 1] / pz + np.abs(p[:, 1]) * dp[:, 2] / (pz * pz))
+        ulp = np.spacing(np.abs(p[:, 2]).astype(np.float32)).astype(np.float64)
+        ztol = np.where(front, np.ceil(dp[:, 2] / ulp) + 1, 0).astype(np.int64)
 
     # ---- EWA covariance --------------------------------------------------
     lim_x = (GUARD * W) / (2.0 * fx)
@@ -251,8 +266,8 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     # across a pixel centre: fragile when an edge is that close to one
     # (relative error of the reach ~ dA/2A + (do/o)/(2 tau))
     rel = FRAG + (0.0 if opacity_exact else FRAG / (2.0 * np.maximum(tau0, 1e-3)))
-    marg_x = rel * rxp + 1e-9
-    marg_y = rel * ryp + 1e-9
+    marg_x = rel * rxp + 1e-9 + du
+    marg_y = rel * ryp + 1e-9 + dw
     def _near_int(e, m):
         return np.abs(e - np.round(e)) < m
     frag_ext = ok & (((ex <= r) & (_near_int(u - (rxp + 0.5), marg_x) | _near_int(u + (rxp - 0.5), marg_x)))
@@ -323,11 +338,12 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
     ntile = np.where(valid, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
     small = valid & (ntile <= MASK_TILES) & (tx1 > tx0) & (ty1 > ty0)
     tmask, frag_cull, fmask = tile_mask(u, w, A, B, Cc, tau0, x_lo, x_hi, y_lo, y_hi, tw, th,
-                                        small, rel)
+                                        small, rel, du, dw)
     count = np.where(small, np.bitwise_count(tmask).astype(np.int64), ntile)
 
     return dict(
-        n=n, valid=valid, p=p, u=u, w=w, zbits=zbits, conic=conic, r=r.astype(np.int64),
+        n=n, valid=valid, p=p, u=u, w=w, zbits=zbits, ztol=ztol, du=du, dw=dw,
+        conic=conic, r=r.astype(np.int64),
         box=np.stack([x_lo, x_hi, y_lo, y_hi], 1), opacity=o, rgb=rgb, raw_rgb=raw,
         normal=nvec, d=d, sign=sign, jstar=jstar, normal_alt=n_alt, d_alt=d_alt,
         tiles=np.stack([tx0, tx1, ty0, ty1], 1), count=count, tmask=tmask, small=small,
@@ -344,8 +360,8 @@ def project(mu, scales, quats, opacity, view, tile, colour=None, sh=None, sh_deg
         frag_box=frag_box, frag_edge=frag_edge, frag_tau=front & (det > 0) & frag_tau,
         fmask=fmask,
         frag_grad=valid & (frag_colour
-                           | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x)
-                           | (np.abs(np.abs(ry) - lim_y) < FRAG * lim_y)),
+                           | (np.abs(np.abs(rx) - lim_x) < FRAG * lim_x + du / abs(fx))
+                           | (np.abs(np.abs(ry) - lim_y) < FRAG * lim_y + dw / abs(fy))),
         # intermediates for the adjoint
         _s=s, _q=q, _qn=qn, _qnorm=qnorm, _Rq=Rq, _M=M, _T0=T0, _T1=T1, _V0=V0, _V1=V1,
         _A=A, _B=B, _C=Cc, _det=dets, _pz=pz, _txz=txz, _tyz=tyz,

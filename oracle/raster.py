@@ -169,7 +169,9 @@ def bin_and_sort(splats_per_view, layout, keep_tiles=None):
     hold, flagged own = False, the pairs one near-tie decision away (a box
     edge, the validity, a tile-culling test), which the GPU, deciding in
     float32, may equally take.  cbit marks an entry whose tile-culling test
-    is itself a near tie; `certain` = own and no near tie on the pair."""
+    is itself a near tie; `certain` = own and no near tie on the pair;
+    ztol is the depth key's tolerance in units in the last place (nonzero
+    only for means that carry a decode error)."""
     if keep_tiles is not None:
         cols = _bin_tiles(splats_per_view, layout, sorted(int(t) for t in keep_tiles))
     else:
@@ -183,16 +185,18 @@ def _sort_entries(cols, splats_per_view, layout):
         e = np.zeros(0, np.int64)
         b = np.zeros(0, bool)
         z = dict(gtile=e, zbits=e.astype(np.uint32), view=e, gid=e, own=b, cbit=b, certain=b,
-                 ranges=np.zeros((n_tiles, 2), np.int64))
+                 ranges=np.zeros((n_tiles, 2), np.int64), ztol=e)
         z["own_sorted"] = dict(z)
         return z
     gt, zb, vv, gg, own, cbit = (np.concatenate(c) for c in cols)
     order = np.lexsort((gg, vv, zb, gt))
     gt, zb, vv, gg, own, cbit = (a[order] for a in (gt, zb, vv, gg, own, cbit))
     near = np.zeros(gt.size, bool)
+    ztol = np.zeros(gt.size, np.int64)
     for v, S in enumerate(splats_per_view):
         m = vv == v
         near[m] = S["frag_box"][gg[m]] | S["frag_tau"][gg[m]]
+        ztol[m] = S["ztol"][gg[m]]
     certain = own & ~cbit & ~near
     ranges = np.zeros((n_tiles, 2), np.int64)
     if gt.size:
@@ -210,7 +214,7 @@ def _sort_entries(cols, splats_per_view, layout):
         oranges[:, 0] = np.where(ends > starts, starts, 0)
         oranges[:, 1] = np.where(ends > starts, ends, 0)
     return dict(gtile=gt, zbits=zb, view=vv, gid=gg, own=own, cbit=cbit, certain=certain,
-                ranges=ranges,
+                ranges=ranges, ztol=ztol,
                 own_sorted=dict(gtile=ogt, zbits=zb[o], view=vv[o], gid=gg[o], ranges=oranges))
 
 
@@ -264,7 +268,12 @@ def _tile_eval(S, ent, I, J):
     raw = S["opacity"][ent][None] * G
     alpha = np.minimum(ALPHA_MAX, raw)
     use = inbox & (power <= 0) & (alpha >= ALPHA_MIN)
-    return dict(dx=dx, dy=dy, inbox=inbox, power=power, G=G, raw=raw, alpha=alpha, use=use)
+    # how far the power (the log of the raw opacity) may move with the mean's
+    # error bound (decoded offsets; zero otherwise)
+    du, dw = S["du"][ent][None], S["dw"][ent][None]
+    dpw = np.abs(a[None] * dx + b[None] * dy) * du + np.abs(b[None] * dx + c[None] * dy) * dw
+    return dict(dx=dx, dy=dy, inbox=inbox, power=power, G=G, raw=raw, alpha=alpha, use=use,
+                dpw=dpw)
 
 
 def _pair_ties(S, ent, own, cbit, I, J, E):
@@ -287,8 +296,9 @@ def _pair_ties(S, ent, own, cbit, I, J, E):
                     | ((Jc == y1) | (Jc == y1 + 1)) & fe[None, :, 3])
     pw = E["power"] <= 0
     r255 = E["raw"] * 255.0
-    passes = pw & (r255 >= 1.0 - FRAG_ALPHA)
-    near = pw & (np.abs(r255 - 1.0) < FRAG_ALPHA)
+    band = FRAG_ALPHA + E["dpw"]
+    passes = pw & (r255 >= 1.0 - band)
+    near = pw & (np.abs(r255 - 1.0) < band)
     loose = passes & (r255 < 1.0 + FRAG_CULL)
     inb = E["inbox"] | (fb & grown)
     # an entry the oracle does not list itself (own False) is taken, if at
@@ -296,23 +306,32 @@ def _pair_ties(S, ent, own, cbit, I, J, E):
     return inb & (near | (ring & passes) | ((fb | ft | cbit[None]) & loose))
 
 
-def _walk(use, alpha, vals):
+def _t_err(alpha, dpw):
+    """Relative error bound that the mean's error (dpw on the power) puts on
+    each factor 1 - alpha of the transmittance (none where alpha is clamped)."""
+    return np.where(alpha < ALPHA_MAX, alpha * dpw / np.maximum(1.0 - alpha, 1e-12), 0.0)
+
+
+def _walk(use, alpha, vals, dpw=None):
     """Front-to-back walk of one pixel over the entries with use: every
-    outcome of the transmittance-stop near ties it meets.  Returns a list of
-    (weighted sums of vals, final T, per-entry weights)."""
+    outcome of the transmittance-stop near ties it meets (widened by the
+    transmittance's share of the mean's error bound, dpw).  Returns a list
+    of (weighted sums of vals, final T, per-entry weights)."""
     idx = np.nonzero(use)[0]
+    te = np.zeros(use.size) if dpw is None else _t_err(alpha, dpw)
     out = []
-    stack = [(0, 1.0, np.zeros(vals.shape[1]), np.zeros(use.size))]
+    stack = [(0, 1.0, np.zeros(vals.shape[1]), np.zeros(use.size), 0.0)]
     while stack and len(out) < MAX_CANDIDATES:
-        pos, T, acc, wts = stack.pop()
+        pos, T, acc, wts, err = stack.pop()
         for m in range(pos, idx.size):
             k = idx[m]
             Tn = T * (1.0 - alpha[k])
             w = alpha[k] * T
-            if abs(Tn / T_MIN - 1.0) < FRAG_T:
+            err = err + te[k]
+            if abs(Tn / T_MIN - 1.0) < FRAG_T + err:
                 w2 = wts.copy()
                 w2[k] = w
-                stack.append((m + 1, Tn, acc + w * vals[k], w2))
+                stack.append((m + 1, Tn, acc + w * vals[k], w2, err))
                 break
             if Tn < T_MIN:
                 break
@@ -324,17 +343,19 @@ def _walk(use, alpha, vals):
     return out
 
 
-def _pixel_candidates(use0, amb, alpha, vals, nabs, bg, ray, alts=()):
+def _pixel_candidates(use0, amb, alpha, vals, nabs, bg, ray, alts=(), dpw=None, swaps=()):
     """Every output (rgb 3, D, N 3, alpha, unbiased depth, |N| blend 3) one
     pixel may take under its near ties, or None when there are more than
     MAX_TIES ties.  alts: (entry, its other (d, normal) outcome) for the
-    entries whose normal is a near tie."""
+    entries whose normal is a near tie; swaps: entry pairs (i, j) whose
+    depth keys may sort either way (walked in both orders)."""
     aidx = np.nonzero(amb)[0]
-    na = aidx.size
-    if na + len(alts) > MAX_TIES:
+    na, nl = aidx.size, len(alts)
+    if na + nl + len(swaps) > MAX_TIES:
         return None
     cands = []
-    for m in range(1 << (na + len(alts))):
+    ne = use0.size
+    for m in range(1 << (na + nl + len(swaps))):
         use = use0.copy()
         for b, k in enumerate(aidx):
             if (m >> b) & 1:
@@ -346,13 +367,19 @@ def _pixel_candidates(use0, amb, alpha, vals, nabs, bg, ray, alts=()):
                 nb = nb.copy()
                 vv[k, 3:7] = alt
                 nb[k] = np.abs(alt[1:4])
-        for acc, T, wts in _walk(use, alpha, vv):
+        perm = np.arange(ne)
+        for b, (i, j) in enumerate(swaps):
+            if (m >> (na + nl + b)) & 1:
+                pi, pj = int(np.nonzero(perm == i)[0][0]), int(np.nonzero(perm == j)[0][0])
+                perm[pi], perm[pj] = perm[pj], perm[pi]
+        dp = None if dpw is None else dpw[perm]
+        for acc, T, wts in _walk(use[perm], alpha[perm], vv[perm], dp):
             rgb = acc[0:3] + T * bg
             D = acc[3]
             N = acc[4:7]
             a = 1.0 - T
             sd = -float(N @ ray)
-            nab = wts @ nb
+            nab = wts @ nb[perm]
             dh = [D / sd if sd > DHAT_GUARD * a else 0.0]
             if a > 0 and abs(sd - DHAT_GUARD * a) < 10 * FRAG_ALPHA * max(abs(sd), DHAT_GUARD * a):
                 dh = [D / sd if sd != 0 else 0.0, 0.0]
@@ -411,7 +438,8 @@ def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
     # near ties: pair decisions, transmittance stop, depth guard
     upto = kidx <= stop[:, None]
     amb = _pair_ties(S, ent, own, cbit, I, J, E)
-    near_t = use & upto & (np.abs(Tp_all / T_MIN - 1.0) < FRAG_T)
+    terr = np.cumsum(np.where(use, _t_err(alpha, E["dpw"]), 0.0), axis=1) if ne else Tp_all
+    near_t = use & upto & (np.abs(Tp_all / T_MIN - 1.0) < FRAG_T + terr)
     dtie = (acc > 0) & (np.abs(sdot - DHAT_GUARD * acc)
                         < 10 * FRAG_ALPHA * np.maximum(np.abs(sdot), DHAT_GUARD * acc))
     tie = dtie.copy()
@@ -421,6 +449,23 @@ def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
         geo = (inc | amb) & S["frag_geom"][ent][None]
         tie |= amb.any(axis=1) | near_t.any(axis=1) | geo.any(axis=1)
     cands, excl = {}, np.zeros(npx, bool)
+    # entries whose depth keys lie within their tolerance of each other
+    # (decoded offsets) may be sorted either way: a pixel that blends both
+    # takes either order
+    swaps = {}
+    if ne > 1 and S["ztol"][ent].any():
+        zb = S["zbits"][ent].astype(np.int64)
+        zt = S["ztol"][ent]
+        ztmax = int(zt.max())
+        blended = inc | amb
+        for i in range(ne - 1):
+            j = i + 1
+            while j < ne and zb[j] - zb[i] <= zt[i] + ztmax:
+                if zb[j] - zb[i] <= zt[i] + zt[j]:
+                    for p in np.nonzero(blended[:, i] & blended[:, j])[0]:
+                        swaps.setdefault(int(p), []).append((i, j))
+                        tie[p] = True
+                j += 1
     if tie.any():
         vals = np.concatenate([S["rgb"][ent], S["d"][ent][:, None], S["normal"][ent]], 1)
         nabs = np.abs(S["normal"][ent])
@@ -428,7 +473,8 @@ def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
         for p in np.nonzero(tie)[0]:
             alts = [(int(k), alt[k]) for k in np.nonzero(geo[p])[0]] if ne else []
             c = _pixel_candidates(use[p], amb[p] if ne else np.zeros(0, bool), alpha[p],
-                                  vals, nabs, V["bg"], ray[p], alts)
+                                  vals, nabs, V["bg"], ray[p], alts, E["dpw"][p] if ne else None,
+                                  swaps.get(int(p), ()))
             if c is None:
                 excl[p] = True
             else:
@@ -452,7 +498,7 @@ def composite_tile(S, ent, I, J, view_arrays, own=None, cbit=None):
     return dict(rgb=rgb, D=D, N=N, Nabs=Nabs, alpha=acc, dhat=dhat, dmag=dmag, T=T_final,
                 last=last,
                 walked=walked, tie=tie, excl=excl, frag_geom=geom, frag_grad=tie_grad,
-                cands=cands, n_pair_ties=int(amb.sum()) if ne else 0,
+                cands=cands, n_pair_ties=int(amb.sum()) if ne else 0, n_order_ties=len(swaps),
                 inc=inc, keep=keep, sdot=sdot, ray=ray, E=E, Tb=Tb, wgt=wgt, a_inc=a_inc)
 
 
@@ -473,7 +519,8 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
                    last=np.zeros(H * W, np.int64), walked=np.zeros(H * W, np.int64),
                    tie=np.zeros(H * W, bool), excl=np.zeros(H * W, bool),
                    frag_geom=np.zeros(H * W, bool), frag_grad=np.zeros(H * W, bool),
-                   covered=np.zeros(H * W, bool), cands={}, n_pair_ties=0, tiles={})
+                   covered=np.zeros(H * W, bool), cands={}, n_pair_ties=0, n_order_ties=0,
+                   tiles={})
         out.append(img)
     n_tiles_total = int(layout["tile_off"][-1])
     tiles = range(n_tiles_total) if keep_tiles is None else keep_tiles
@@ -503,6 +550,7 @@ def render_images(splats_per_view, views, layout, sorted_, view_arrays, keep_til
         img["frag_grad"][pix] = R["frag_grad"]
         img["covered"][pix] = True
         img["n_pair_ties"] += R["n_pair_ties"]
+        img["n_order_ties"] += R["n_order_ties"]
         for p, c in R["cands"].items():
             img["cands"][int(pix[p])] = c
         img["tiles"][gtile] = (ent, I, J, pix, R)

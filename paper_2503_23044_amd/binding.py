@@ -16,8 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 6
+CGX_ABI_VERSION = 7
 OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
+OFFSETS_TABLE, OFFSETS_DECODED = 0, 1
+DECODER_SHARED, DECODER_PER_ATTRIBUTE = 1, 3
 CGX_OK = 0
 CGX_ERR_INVALID_ARG = 1
 CGX_ERR_UNSUPPORTED = 2
@@ -44,10 +46,15 @@ class cgx_explicit_scene(C.Structure):
 
 class cgx_anchor_scene(C.Structure):
     _fields_ = [("n_anchor", C.c_int64), ("n_offsets", C.c_int32), ("n_levels", C.c_int32),
-                ("d_max", C.c_float), ("opacity_act", C.c_int32), ("x", C.c_void_p),
+                ("d_max", C.c_float), ("opacity_act", C.c_int32), ("offset_mode", C.c_int32),
+                ("decoder_heads", C.c_int32), ("x", C.c_void_p),
                 ("l", C.c_void_p), ("O", C.c_void_p),
                 ("F", C.c_void_p), ("level", C.c_void_p), ("W1", C.c_void_p), ("b1", C.c_void_p),
                 ("W2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class cgx_ncc_term(C.Structure):
+    _fields_ = [("centres", C.c_void_p), ("n_patch", C.c_int32), ("weight", C.c_float)]
 
 
 class cgx_scene(C.Structure):
@@ -116,15 +123,16 @@ def load_library(path: str = LIB_PATH):
         "cgx_render_fwd_bwd_l1": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                               C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
                                               C.c_size_t, C.POINTER(cgx_images),
-                                              C.POINTER(C.c_float), C.POINTER(cgx_images),
-                                              C.POINTER(cgx_grads), P, P]),
+                                              C.POINTER(C.c_float), C.POINTER(cgx_ncc_term),
+                                              C.POINTER(cgx_images), C.POINTER(cgx_grads), P, P]),
         "cgx_read_info": (C.c_int32, [P, P, P, C.POINTER(cgx_run_info)]),
         "cgx_debug_copy": (C.c_int32, [P, P, P, P, P, P, P, P, P]),
         "cgx_graph_capture_fwd_bwd_l1": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
                                                      C.POINTER(cgx_scene), C.POINTER(cgx_capacity),
                                                      P, C.c_size_t, C.POINTER(cgx_images),
-                                                     C.POINTER(C.c_float), C.POINTER(cgx_images),
-                                                     C.POINTER(cgx_grads), P, P, C.POINTER(P)]),
+                                                     C.POINTER(C.c_float), C.POINTER(cgx_ncc_term),
+                                                     C.POINTER(cgx_images), C.POINTER(cgx_grads),
+                                                     P, P, C.POINTER(P)]),
         "cgx_graph_launch": (C.c_int32, [P, P]),
         "cgx_graph_destroy": (C.c_int32, [P]),
         "cgx_ncc_loss": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32, P, C.POINTER(cgx_images), P,
@@ -226,7 +234,8 @@ def _ptr(t):
 def make_scene(scene: dict) -> cgx_scene:
     """scene: dict of device tensors.  Explicit: kind=0, means, scales, quats,
     opacity, sh, sh_degree.  Anchor: kind=1, x, l, O, F, level (uint8), W1,
-    W2 (int16 tensors holding bfloat16 bits), b1, b2, n_levels, d_max."""
+    W2 (int16 tensors holding bfloat16 bits), b1, b2, n_levels, d_max and
+    optionally opacity_act, offset_mode, decoder_heads."""
     s = cgx_scene()
     s.kind = int(scene["kind"])
     if s.kind == CGX_SCENE_EXPLICIT:
@@ -240,6 +249,8 @@ def make_scene(scene: dict) -> cgx_scene:
         s.an.n_levels = int(scene["n_levels"])
         s.an.d_max = float(scene["d_max"])
         s.an.opacity_act = int(scene.get("opacity_act", OPACITY_SIGMOID))
+        s.an.offset_mode = int(scene.get("offset_mode", OFFSETS_TABLE))
+        s.an.decoder_heads = int(scene.get("decoder_heads", DECODER_SHARED))
         for k in ("x", "l", "O", "F", "level", "W1", "b1", "W2", "b2"):
             setattr(s.an, k, _ptr(scene[k]))
     return s
@@ -306,15 +317,34 @@ def cgx_render_backward(ctx, views, scene, cap, ws, out, grad_out, grads):
     _check(ctx, rc, "cgx_render_backward")
 
 
-def cgx_render_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grads, loss_dev=None):
+def make_ncc(ncc):
+    """ncc: None, or dict(centres=int32 device tensor of (x, y) pairs,
+    pair-major, n_patch=patches per view pair, weight=float)."""
+    if ncc is None:
+        return None
+    t = cgx_ncc_term()
+    t.centres = _ptr(ncc["centres"])
+    t.n_patch = int(ncc["n_patch"])
+    t.weight = float(ncc["weight"])
+    return t
+
+
+def _byref_or_null(x):
+    return C.byref(x) if x is not None else None
+
+
+def cgx_render_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grads, loss_dev=None,
+                          ncc=None):
     lib = load_library()
     va = make_views(views)
     sc = make_scene(scene)
     w = (C.c_float * 3)(*[float(x) for x in weights])
+    nt = make_ncc(ncc)
     rc = lib.cgx_render_fwd_bwd_l1(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
                                    C.c_void_p(ws.data_ptr()), ws.numel(),
-                                   C.byref(make_images(target)), w, C.byref(make_images(out)),
-                                   C.byref(make_grads(grads)), _ptr(loss_dev), _stream())
+                                   C.byref(make_images(target)), w, _byref_or_null(nt),
+                                   C.byref(make_images(out)), C.byref(make_grads(grads)),
+                                   _ptr(loss_dev), _stream())
     _check(ctx, rc, "cgx_render_fwd_bwd_l1")
 
 
@@ -497,19 +527,21 @@ def cgx_timing_read(ctx):
 
 
 def cgx_graph_capture_fwd_bwd_l1(ctx, views, scene, cap, ws, target, weights, out, grads,
-                                 loss_dev, stream):
+                                 loss_dev, stream, ncc=None):
     """Capture the fused chain on `stream` (a torch.cuda.Stream, not the
     default stream) into a graph handle."""
     lib = load_library()
     va = make_views(views)
     sc = make_scene(scene)
     w = (C.c_float * 3)(*[float(x) for x in weights])
+    nt = make_ncc(ncc)
     g = C.c_void_p()
     rc = lib.cgx_graph_capture_fwd_bwd_l1(ctx, va, len(views), C.byref(sc),
                                           C.byref(make_capacity(cap)), C.c_void_p(ws.data_ptr()),
                                           ws.numel(), C.byref(make_images(target)), w,
-                                          C.byref(make_images(out)), C.byref(make_grads(grads)),
-                                          _ptr(loss_dev), C.c_void_p(stream.cuda_stream), C.byref(g))
+                                          _byref_or_null(nt), C.byref(make_images(out)),
+                                          C.byref(make_grads(grads)), _ptr(loss_dev),
+                                          C.c_void_p(stream.cuda_stream), C.byref(g))
     _check(ctx, rc, "cgx_graph_capture_fwd_bwd_l1")
     return g
 

@@ -97,6 +97,13 @@ static int32_t check_views(cgx_ctx* c, const cgx_view* views, int32_t B) {
   return CGX_OK;
 }
 
+// every anchor gradient buffer, the offsets' only when the table's offsets
+// are used
+static bool anchor_grads_ok(const cgx_anchor_scene& a, const cgx_grads& g) {
+  return g.x && g.l && (g.O || a.offset_mode == CGX_OFFSETS_DECODED) && g.F && g.W1 && g.b1 &&
+         g.W2 && g.b2;
+}
+
 static int32_t check_scene(cgx_ctx* c, const cgx_scene* s, int32_t B) {
   if (!s) return fail(c, CGX_ERR_INVALID_ARG, "scene is NULL");
   if (s->kind == CGX_SCENE_EXPLICIT) {
@@ -119,11 +126,16 @@ static int32_t check_scene(cgx_ctx* c, const cgx_scene* s, int32_t B) {
       return fail(c, CGX_ERR_UNSUPPORTED, "the decoder is compiled for n_offsets = 10 Gaussians per anchor");
     if (a.opacity_act != CGX_OPACITY_SIGMOID && a.opacity_act != CGX_OPACITY_TANH_MASK)
       return fail(c, CGX_ERR_INVALID_ARG, "opacity_act %d is not a known activation", a.opacity_act);
+    if (a.offset_mode != CGX_OFFSETS_TABLE && a.offset_mode != CGX_OFFSETS_DECODED)
+      return fail(c, CGX_ERR_INVALID_ARG, "offset_mode %d is neither 0 nor 1", a.offset_mode);
+    if (a.decoder_heads != CGX_DECODER_SHARED && a.decoder_heads != CGX_DECODER_PER_ATTRIBUTE)
+      return fail(c, CGX_ERR_INVALID_ARG, "decoder_heads %d is neither 1 nor 3", a.decoder_heads);
     if (a.n_levels < 1 || a.n_levels > 16)
       return fail(c, CGX_ERR_INVALID_ARG, "n_levels %d not in 1..16", a.n_levels);
     if (!(a.d_max > 0.f) || !std::isfinite(a.d_max))
       return fail(c, CGX_ERR_INVALID_ARG, "d_max must be > 0");
-    if (a.n_anchor > 0 && (!a.x || !a.l || !a.O || !a.F || !a.level || !a.W1 || !a.b1 || !a.W2 || !a.b2))
+    if (a.n_anchor > 0 && (!a.x || !a.l || (!a.O && a.offset_mode != CGX_OFFSETS_DECODED) || !a.F ||
+                           !a.level || !a.W1 || !a.b1 || !a.W2 || !a.b2))
       return fail(c, CGX_ERR_INVALID_ARG, "anchor scene: NULL array");
     if ((int64_t)a.n_anchor * B > (int64_t)INT32_MAX)
       return fail(c, CGX_ERR_INVALID_ARG, "n_anchor * n_views exceeds 2^31");
@@ -205,8 +217,9 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.stats = take(sizeof(StatSlot) * kStatSlots);
   L.px_T = take(sizeof(float) * (size_t)px);
   L.px_last = take(sizeof(uint32_t) * (size_t)px);
+  L.ncc_g = take(sizeof(float) * (size_t)px);
   L.sgrad = take(sizeof(SplatGrad) * (size_t)L.max_splats);
-  L.dz = take(s->kind == CGX_SCENE_ANCHOR ? anchor_scratch_bytes(L.max_rows) : 1);
+  L.dz = take(s->kind == CGX_SCENE_ANCHOR ? anchor_scratch_bytes(L.max_rows, s->an) : 1);
   L.total = o;
   return CGX_OK;
 }
@@ -271,6 +284,7 @@ struct Ptrs {
   StatSlot* stats;
   float* px_T;
   uint32_t* px_last;
+  float* ncc_g;
   SplatGrad* sgrad;
   float* dz;
 };
@@ -304,6 +318,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
   p.stats = at<StatSlot>(ws, L.stats);
   p.px_T = at<float>(ws, L.px_T);
   p.px_last = at<uint32_t>(ws, L.px_last);
+  p.ncc_g = at<float>(ws, L.ncc_g);
   p.sgrad = at<SplatGrad>(ws, L.sgrad);
   p.dz = at<float>(ws, L.dz);
   return p;
@@ -442,7 +457,7 @@ __global__ void k_copy_loss(const Counters* c, float* dst) {
 static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const cgx_scene* s,
                               const Layout& L, void* ws, const cgx_images* out,
                               const cgx_images* gout, const cgx_images* target, const float* w3,
-                              const cgx_grads* g, hipStream_t st) {
+                              const cgx_grads* g, hipStream_t st, bool ncc_seed = false) {
   Ptrs P = pointers(ws, L);
   const bool expl = s->kind == CGX_SCENE_EXPLICIT;
   const uint32_t n_slots = (uint32_t)L.max_splats;
@@ -478,6 +493,7 @@ static int32_t backward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, cons
     a.w_rgb = w3[0];
     a.w_depth = w3[1];
     a.w_normal = w3[2];
+    if (ncc_seed) a.g_ncc = P.ncc_g;
   } else if (gout) {
     a.g_rgb = gout->rgb;
     a.g_depth = gout->depth;
@@ -638,9 +654,7 @@ int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
   if (grad_out && grad_out->depth == nullptr && grad_out->rgb == nullptr &&
       grad_out->normal == nullptr && grad_out->plane_d == nullptr && grad_out->alpha == nullptr)
     grad_out = nullptr;
-  if (scene->kind == CGX_SCENE_ANCHOR &&
-      (!grads->x || !grads->l || !grads->O || !grads->F || !grads->W1 || !grads->b1 ||
-       !grads->W2 || !grads->b2))
+  if (scene->kind == CGX_SCENE_ANCHOR && !anchor_grads_ok(scene->an, *grads))
     return fail(ctx, CGX_ERR_INVALID_ARG, "anchor backward needs every gradient buffer");
   cgx_images zero_g;
   memset(&zero_g, 0, sizeof(zero_g));
@@ -649,11 +663,27 @@ int32_t cgx_render_backward(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
                         (hipStream_t)stream);
 }
 
+// a fill kernel rather than hipMemsetAsync: the chain may be captured
+__global__ void k_zero_f32(float* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+static int32_t check_ncc(cgx_ctx* c, const cgx_ncc_term* ncc, int32_t n_views) {
+  if (!ncc) return CGX_OK;
+  if (ncc->n_patch < 0 || (int64_t)ncc->n_patch * (n_views / 2) > (int64_t)INT32_MAX)
+    return fail(c, CGX_ERR_INVALID_ARG, "n_patch %d out of range", ncc->n_patch);
+  if (!std::isfinite(ncc->weight)) return fail(c, CGX_ERR_INVALID_ARG, "NCC weight is not finite");
+  if (ncc->n_patch > 0 && !ncc->centres) return fail(c, CGX_ERR_INVALID_ARG, "NCC centres is NULL");
+  return CGX_OK;
+}
+
 int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                               const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
                               size_t workspace_bytes, const cgx_images* target,
-                              const float* w3_host, const cgx_images* out,
-                              const cgx_grads* grads, float* loss_dev, void* stream) {
+                              const float* w3_host, const cgx_ncc_term* ncc,
+                              const cgx_images* out, const cgx_grads* grads, float* loss_dev,
+                              void* stream) {
   Layout L;
   int32_t rc = common_checks(ctx, views, n_views, scene, cap, workspace, workspace_bytes, L);
   if (rc) return rc;
@@ -662,16 +692,28 @@ int32_t cgx_render_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_t n_vie
   if (!out || !out->rgb || !out->depth || !out->normal || !out->plane_d)
     return fail(ctx, CGX_ERR_INVALID_ARG, "fused call needs rgb, depth, plane_d and normal outputs");
   if (!grads) return fail(ctx, CGX_ERR_INVALID_ARG, "grads is NULL");
-  if (scene->kind == CGX_SCENE_ANCHOR &&
-      (!grads->x || !grads->l || !grads->O || !grads->F || !grads->W1 || !grads->b1 ||
-       !grads->W2 || !grads->b2))
+  if (scene->kind == CGX_SCENE_ANCHOR && !anchor_grads_ok(scene->an, *grads))
     return fail(ctx, CGX_ERR_INVALID_ARG, "anchor backward needs every gradient buffer");
+  rc = check_ncc(ctx, ncc, n_views);
+  if (rc) return rc;
+  const bool with_ncc = ncc && ncc->n_patch > 0 && n_views >= 2;
   const float ones[3] = {1.f, 1.f, 1.f};
   const float* w = w3_host ? w3_host : ones;
   hipStream_t st = (hipStream_t)stream;
   rc = forward_chain(ctx, views, n_views, scene, L, workspace, out, st);
   if (rc) return rc;
-  rc = backward_chain(ctx, views, n_views, scene, L, workspace, out, nullptr, target, w, grads, st);
+  if (with_ncc) {
+    // Eq. 10 on the forward images: its per-pixel gradient (of the mean
+    // intensity) into the workspace plane, its loss into the counter block
+    Ptrs P = pointers(workspace, L);
+    const uint32_t zb = (uint32_t)std::min<int64_t>(div_up((uint64_t)L.n_pixels, 256), 4096);
+    hipLaunchKernelGGL(k_zero_f32, dim3(std::max<uint32_t>(zb, 1)), dim3(256), 0, st, P.ncc_g,
+                       (size_t)L.n_pixels);
+    launch_ncc_loss(P.views, n_views, out->rgb, out->normal, out->plane_d, ncc->centres,
+                    ncc->n_patch, ncc->weight, P.ncc_g, true, &P.ctr->loss, st);
+  }
+  rc = backward_chain(ctx, views, n_views, scene, L, workspace, out, nullptr, target, w, grads, st,
+                      with_ncc);
   if (rc) return rc;
   if (loss_dev) {
     Ptrs P = pointers(workspace, L);
@@ -699,8 +741,9 @@ int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_
                                      const cgx_scene* scene, const cgx_capacity* cap,
                                      void* workspace, size_t workspace_bytes,
                                      const cgx_images* target, const float* w3_host,
-                                     const cgx_images* out, const cgx_grads* grads,
-                                     float* loss_dev, void* stream, cgx_graph** graph) {
+                                     const cgx_ncc_term* ncc, const cgx_images* out,
+                                     const cgx_grads* grads, float* loss_dev, void* stream,
+                                     cgx_graph** graph) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   if (!graph) return fail(ctx, CGX_ERR_INVALID_ARG, "graph is NULL");
   *graph = nullptr;
@@ -714,7 +757,7 @@ int32_t cgx_graph_capture_fwd_bwd_l1(cgx_ctx* ctx, const cgx_view* views, int32_
   ctx->ev_cap = 0;
   HIP_OK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   rc = cgx_render_fwd_bwd_l1(ctx, views, n_views, scene, cap, workspace, workspace_bytes, target,
-                             w3_host, out, grads, loss_dev, stream);
+                             w3_host, ncc, out, grads, loss_dev, stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(st, &g);
   ctx->ev_cap = saved_cap;
@@ -769,7 +812,7 @@ int32_t cgx_ncc_loss(cgx_ctx* ctx, const cgx_view* views, int32_t n_views, const
   const ViewDev* vt = reinterpret_cast<const ViewDev*>(
       reinterpret_cast<const char*>(workspace) + align_up(sizeof(Counters)));
   launch_ncc_loss(vt, n_views, images->rgb, images->normal, images->plane_d, centres, n_patch,
-                  weight, grad_rgb, loss_dev, (hipStream_t)stream);
+                  weight, grad_rgb, false, loss_dev, (hipStream_t)stream);
   HIP_OK(ctx, hipGetLastError());
   return CGX_OK;
 }
@@ -1132,7 +1175,7 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
     if (L.total > workspace_bytes) continue;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes, target,
-                               w3_host, out, grads, loss_dev, stream);
+                               w3_host, nullptr, out, grads, loss_dev, stream);
     if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
     Counters h;
     rc = read_counters(&c, workspace, stream, h);
@@ -1149,7 +1192,7 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
     hipEventRecord(e0, st);
     for (int r = 0; r < reps && rc == CGX_OK; ++r)
       rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes,
-                                 target, w3_host, out, grads, loss_dev, stream);
+                                 target, w3_host, nullptr, out, grads, loss_dev, stream);
     hipEventRecord(e1, st);
     float ms = 0.f;
     const hipError_t e = hipEventSynchronize(e1);

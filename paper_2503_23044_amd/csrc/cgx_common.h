@@ -123,6 +123,7 @@ struct Layout {
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
+  size_t ncc_g;                // per-pixel gradient of the Eq. 10 loss (fused chain)
   size_t tkey[2], tord[2];     // raster launch order: length keys and tile ids
   size_t bstart;               // first visible splat of each pair-emission block
   size_t stats;                // kStatSlots raster statistics slots
@@ -374,6 +375,7 @@ struct RasterArgs {
   const float* t_depth;
   const float* t_normal;
   float w_rgb, w_depth, w_normal;
+  const float* g_ncc;          // fused mode: Eq. 10 gradient of the mean intensity, or NULL
   int l1;                      // 1: seed from L1 against targets
   int count;                   // 1: count list entries walked and opacity evaluations
   SplatGrad* sgrad;
@@ -389,10 +391,10 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
                                     const uint32_t* counts, const SplatGrad* sgrad,
                                     const Counters* ctr, const cgx_grads& g, float* scratch,
                                     hipStream_t s);
-size_t anchor_scratch_bytes(int64_t max_rows);
+size_t anchor_scratch_bytes(int64_t max_rows, const cgx_anchor_scene& sc);
 void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const float* normal,
                      const float* plane_d, const int32_t* centres, int n_patch, float weight,
-                     float* grad_rgb, float* loss, hipStream_t s);
+                     float* grad, bool gray, float* loss, hipStream_t s);
 
 // Depth prior (Sec. 3.4, Step 2).  Camera constants travel in the kernel
 // arguments as float64, prepared on the host from the float32 views, in

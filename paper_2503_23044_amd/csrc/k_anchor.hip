@@ -8,24 +8,83 @@
 namespace cgx {
 
 constexpr int kIn = CGX_MLP_IN;          // 36
-constexpr int kHid = CGX_MLP_HIDDEN;     // 32
-constexpr int kGo = CGX_GAUSS_OUT;       // 11
+constexpr int kHead = CGX_MLP_HIDDEN;    // hidden units per decoder head
 constexpr int kNOff = 10;                // Gaussians per anchor (compiled in)
-constexpr int kOut = kNOff * kGo;        // 110
-// per row: z0, z1, dz1, dz2 (the weight-gradient operands), then z2 kept by
-// the forward decode for the Gaussian adjoint, then the row's terms of the
-// anchor gradients: per Gaussian d(mu) and the scale term (6 values), the
-// feature gradient (32) and the direction term of x (3)
-constexpr int kRowUsed = kIn + kHid + kHid + kOut;
-constexpr int kZ2 = kRowUsed;
-constexpr int kGSum = kZ2 + kOut;
-constexpr int kDF = kGSum + 6 * kNOff;
-constexpr int kDX = kDF + CGX_FEAT_DIM;
-constexpr int kRowScratch = kDX + 4;
-static_assert(kRowUsed % 2 == 0 && kRowScratch % 4 == 0, "row scratch is read in float pairs");
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-constexpr int kWGrad = kIn * kHid + kHid * kOut + kHid + kOut;   // 4814
 constexpr int kRedBlocks = 512;  // weight-gradient partials (one per reduction block)
+
+// Decoder shape (Sec. 3.2, Eq. 4): H heads of 32 hidden units and G outputs
+// per Gaussian (11: opacity, rgb, scale, quaternion; 14: and the decoded
+// offset).  One head maps to all G outputs; per-attribute heads (H = 3, or
+// 4 with decoded offsets) own the attribute groups opacity (1), colour
+// (3), scale + quaternion (7) and offset (3).  Head h reads hidden units
+// 32h .. 32h+31 and writes the n * width_h output columns from
+// n * first_h, Gaussian k's attribute first_h + j at column
+// n * first_h + k * width_h + j (with one head: k * G + j).
+template <int H, int G>
+struct Dec {
+  static_assert((H == 1 && (G == 11 || G == 14)) || (H == 3 && G == 11) || (H == 4 && G == 14),
+                "decoder shapes: one head, or one head per attribute group");
+  static constexpr int kHeads = H;
+  static constexpr int kGo = G;
+  static constexpr int kHid = kHead * H;
+  static constexpr int kOut = kNOff * G;
+  static constexpr int first(int h) { return H == 1 ? 0 : (h == 0 ? 0 : h == 1 ? 1 : h == 2 ? 4 : 11); }
+  static constexpr int width(int h) { return H == 1 ? G : (h == 0 ? 1 : h == 1 ? 3 : h == 2 ? 7 : 3); }
+  static constexpr int col0(int h) { return kNOff * first(h); }
+  static constexpr int ncols(int h) { return kNOff * width(h); }
+  static constexpr int tiles(int h) { return (ncols(h) + 15) / 16; }
+  static constexpr int tile0(int h) {
+    int t = 0;
+    for (int i = 0; i < h; ++i) t += tiles(i);
+    return t;
+  }
+  static constexpr int head_of(int m) {
+    int h = 0;
+    while (h + 1 < H && first(h + 1) <= m) ++h;
+    return h;
+  }
+  static constexpr int head_of_tile(int T) {
+    int h = 0;
+    while (h + 1 < H && tile0(h + 1) <= T) ++h;
+    return h;
+  }
+  // output column of attribute m of Gaussian k
+  static constexpr int zcol(int k, int m) {
+    return col0(head_of(m)) + k * width(head_of(m)) + (m - first(head_of(m)));
+  }
+  static constexpr int kTiles = tile0(H);      // 16-column tiles, each head padded to whole tiles
+  static constexpr int kN2 = 16 * kTiles;
+  // Row scratch, per active row: z0, z1, dz1, dz2 (the weight-gradient
+  // operands), then z2 kept by the forward decode for the Gaussian adjoint,
+  // then the row's terms of the anchor gradients: per Gaussian d(mu) and
+  // the scale term (6 values), the feature gradient (32) and the direction
+  // term of x (3).  z2 and dz2 are in output-column order.
+  static constexpr int kZ1 = kIn;
+  static constexpr int kDZ1 = kZ1 + kHid;
+  static constexpr int kDZ2 = kDZ1 + kHid;
+  static constexpr int kRowUsed = kDZ2 + kOut;
+  static constexpr int kZ2 = kRowUsed;
+  static constexpr int kGSum = kZ2 + kOut;
+  static constexpr int kDF = kGSum + 6 * kNOff;
+  static constexpr int kDX = kDF + CGX_FEAT_DIM;
+  static constexpr int kRowScratch = kDX + 4;
+  static_assert(kRowUsed % 2 == 0 && kRowScratch % 4 == 0, "row scratch is read in float pairs");
+  // weight gradients: W1 (36 x kHid), W2 (32 x kOut), b1, b2
+  static constexpr int kWGrad = kIn * kHid + kHead * kOut + kHid + kOut;
+};
+
+// the decoder shapes built, chosen from the scene
+template <class F>
+static void with_decoder(const cgx_anchor_scene& sc, F&& f) {
+  if (sc.decoder_heads == CGX_DECODER_PER_ATTRIBUTE) {
+    if (sc.offset_mode == CGX_OFFSETS_DECODED) f(Dec<4, 14>{});
+    else f(Dec<3, 11>{});
+  } else {
+    if (sc.offset_mode == CGX_OFFSETS_DECODED) f(Dec<1, 14>{});
+    else f(Dec<1, 11>{});
+  }
+}
 
 // ---------------------------------------------------------------------
 // a0: decisions in float64, fixed operation order, contraction off
@@ -216,31 +275,43 @@ __device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor
 // decoder weights for the adjoint, float32 in LDS; rows padded to an odd
 // stride so that the 32 lanes of a row, which read 32 different weight rows
 // at the same column, hit 32 different banks
-constexpr int kW1s = kHid + 1;
-constexpr int kW2s = kOut + 1;
+template <class D>
 struct DecWT {
+  static constexpr int kW1s = D::kHid + 1;
+  static constexpr int kW2s = D::kOut + 1;
   float W1[kIn * kW1s];
-  float W2[kHid * kW2s];
+  float W2[kHead * kW2s];
 };
-
-static_assert(sizeof(DecWT) % 16 == 0, "copied in 16-byte pieces");
 
 // block-wide copy of a weight image laid out in global memory by
 // k_prep_weights (16-byte pieces)
 template <typename T>
 __device__ __forceinline__ void copy_weights(T& dst, const T* src) {
+  static_assert(sizeof(T) % 16 == 0, "copied in 16-byte pieces");
   const uint4* s = reinterpret_cast<const uint4*>(src);
   uint4* d = reinterpret_cast<uint4*>(&dst);
   for (int i = threadIdx.x; i < (int)(sizeof(T) / 16); i += blockDim.x) d[i] = s[i];
 }
 
-// decoded attributes of Gaussian k of a row, in projection form
+// the G outputs of Gaussian k of a row, gathered from its output columns
+template <class D>
+__device__ __forceinline__ void gaussian_outputs(const float* z2row, int k, float* z2) {
+#pragma unroll
+  for (int m = 0; m < D::kGo; ++m) z2[m] = z2row[D::zcol(k, m)];
+}
+
+// decoded attributes of Gaussian k of a row, in projection form; O gets
+// the offset used (decoded, or the anchor table's)
+template <class D>
 __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uint32_t a, int k,
-                                                 const float* z2, ProjIn& in, float* sig_s) {
+                                                 const float* z2, ProjIn& in, float* sig_s,
+                                                 float* O) {
 #pragma clang fp contract(off)
   const float* X = sc.x + 3 * (size_t)a;
   const float* L = sc.l + 3 * (size_t)a;
-  const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    O[c] = D::kGo > CGX_GAUSS_OUT ? z2[CGX_GAUSS_OUT + c] : sc.O[((size_t)a * kNOff + k) * 3 + c];
   in.m0 = (double)X[0] + (double)O[0] * (double)L[0];
   in.m1 = (double)X[1] + (double)O[1] * (double)L[1];
   in.m2 = (double)X[2] + (double)O[2] * (double)L[2];
@@ -260,17 +331,19 @@ __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uin
 
 // ---------------------------------------------------------------------
 // a1 + a2 on MFMA.  One wave decodes 64 rows as four 16-row groups with
-// v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32 accumulation):
+// v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32 accumulation), one head
+// at a time:
 //   layer 1: [bf16(F) | 3-term bf16 split of (d~, Delta)] (K = 64) x W1'
-//            (64 x 32: W1's feature rows, then its last four rows once per
-//            split term), 2 k-steps x 2 column tiles;
-//   layer 2: 3-term bf16 split of z1 (K = 96) x [W2; W2; W2] (96 x 112),
-//            3 k-steps x 7 column tiles.
+//            (64 x 32: the head's W1 feature rows, then its last four rows
+//            once per split term), 2 k-steps x 2 column tiles;
+//   layer 2: 3-term bf16 split of the head's z1 (K = 96) x [W2; W2; W2]
+//            restricted to the head's columns (96 x 16 per tile), 3
+//            k-steps per column tile.
 // A value x is carried as h + m + l with h = bf16(x), m = bf16(x - h),
 // l = bf16(x - h - m) (residual below 2^-26 |x|), so only the features
 // take a bfloat16 rounding; the rest keeps float32 accuracy.  z1 and the
-// 110 outputs z2 go to the row's scratch (the adjoint reads them too), and
-// a second kernel projects the 10 Gaussians of every row, one thread each.
+// outputs z2 go to the row's scratch (the adjoint reads them too), and a
+// second kernel projects the 10 Gaussians of every row, one thread each.
 //
 // Fragment layout of the 16x16x32 bf16 MFMA (lane l): A holds row l % 16,
 // k = 8 (l / 16) .. +7; B holds column l % 16, the same k; C holds column
@@ -280,8 +353,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
 constexpr int kK1 = 64;    // layer-1 reduction (padded)
-constexpr int kK2 = 96;    // layer-2 reduction: 3 split terms of 32
-constexpr int kN2 = 112;   // layer-2 columns (110 padded)
+constexpr int kK2 = 96;    // layer-2 reduction: 3 split terms of a head's 32 hidden units
 
 __device__ __forceinline__ uint16_t bf16_bits_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -296,18 +368,21 @@ __device__ __forceinline__ void split3(float x, uint16_t& h, uint16_t& m, uint16
   l = bf16_bits_rne(r2);
 }
 
+// B operands and biases of the decode; layer-2 columns in tiles, each
+// head's columns padded to whole tiles (padding columns zero)
+template <class D>
 struct DecWB {
-  uint16_t w1t[kHid][kK1];      // B of layer 1, column-major (n, k)
-  uint16_t w2t[kN2][kK2];       // B of layer 2, column-major (n, k)
-  float b1[kHid];
-  float b2[kN2];
+  uint16_t w1t[D::kHid][kK1];   // B of layer 1, column-major (n, k)
+  uint16_t w2t[D::kN2][kK2];    // B of layer 2, column-major (tile column, k)
+  float b1[D::kHid];
+  float b2[D::kN2];
 };
-static_assert(sizeof(DecWB) % 16 == 0, "copied in 16-byte pieces");
 
+template <class D>
 struct MfmaLds {
-  DecWB w;
+  DecWB<D> w;
   uint16_t a1[64][kK1];         // A of layer 1 for the wave's 64 rows
-  uint16_t a2[64][kK2];         // A of layer 2
+  uint16_t a2[64][kK2];         // A of layer 2 (one head at a time)
 };
 
 __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
@@ -324,13 +399,14 @@ __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
   return r;
 }
 
+template <class D>
 __global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ views,
                                                     cgx_anchor_scene sc,
                                                     const int2* __restrict__ rows,
                                                     const Counters* ctr,
-                                                    const DecWB* __restrict__ wimg,
+                                                    const DecWB<D>* __restrict__ wimg,
                                                     float* __restrict__ row_scratch) {
-  __shared__ MfmaLds L;
+  __shared__ MfmaLds<D> L;
   const int lane = threadIdx.x;
   const uint32_t n_rows = ctr->n_rows;
   const uint32_t r0 = blockIdx.x * 64;
@@ -360,59 +436,66 @@ __global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ 
   __syncthreads();
 
   const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
-  // layer 1 -> z1 (fp32), split into three bf16 terms for layer 2
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int h = 0; h < D::kHeads; ++h) {
+    // layer 1 -> the head's z1 (fp32), split into three bf16 terms for layer 2
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < 4; ++g) {
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const bf16x8_t av = load8(&L.a1[g * 16 + col][ks * 32 + kq]);
-        const bf16x8_t bv = load8(&L.w.w1t[t * 16 + col][ks * 32 + kq]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-      }
-      const int n = t * 16 + col;
+      for (int t = 0; t < 2; ++t) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float z = fmaxf(acc[i] + L.w.b1[n], 0.0f);
-        uint16_t h, m, lo;
-        split3(z, h, m, lo);
-        uint16_t* a2 = L.a2[g * 16 + rq + i];
-        a2[n] = h;
-        a2[32 + n] = m;
-        a2[64 + n] = lo;
-        // z1 kept for the adjoint (relu' = z1 > 0)
-        const uint32_t rr = r0 + g * 16 + rq + i;
-        if (rr < n_rows) row_scratch[(size_t)rr * kRowScratch + kIn + n] = z;
+        for (int ks = 0; ks < 2; ++ks) {
+          const bf16x8_t av = load8(&L.a1[g * 16 + col][ks * 32 + kq]);
+          const bf16x8_t bv = load8(&L.w.w1t[kHead * h + t * 16 + col][ks * 32 + kq]);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+        const int n = t * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float z = fmaxf(acc[i] + L.w.b1[kHead * h + n], 0.0f);
+          uint16_t zh, zm, zl;
+          split3(z, zh, zm, zl);
+          uint16_t* a2 = L.a2[g * 16 + rq + i];
+          a2[n] = zh;
+          a2[32 + n] = zm;
+          a2[64 + n] = zl;
+          // z1 kept for the adjoint (relu' = z1 > 0)
+          const uint32_t rr = r0 + g * 16 + rq + i;
+          if (rr < n_rows) row_scratch[(size_t)rr * D::kRowScratch + D::kZ1 + kHead * h + n] = z;
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 
-  for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < 4; ++g) {
 #pragma unroll
-    for (int t = 0; t < kN2 / 16; ++t) {
-      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < D::tiles(h); ++t) {
+        const int T = D::tile0(h) + t;
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < 3; ++ks) {
-        const bf16x8_t av = load8(&L.a2[g * 16 + col][ks * 32 + kq]);
-        const bf16x8_t bv = load8(&L.w.w2t[t * 16 + col][ks * 32 + kq]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-      }
-      const int n = t * 16 + col;
+        for (int ks = 0; ks < 3; ++ks) {
+          const bf16x8_t av = load8(&L.a2[g * 16 + col][ks * 32 + kq]);
+          const bf16x8_t bv = load8(&L.w.w2t[T * 16 + col][ks * 32 + kq]);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+        const int c = t * 16 + col;            // column within the head
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float z = acc[i] + L.w.b2[n];
-        const uint32_t rr = r0 + g * 16 + rq + i;
-        if (n < kOut && rr < n_rows) row_scratch[(size_t)rr * kRowScratch + kZ2 + n] = z;
+        for (int i = 0; i < 4; ++i) {
+          const float z = acc[i] + L.w.b2[T * 16 + col];
+          const uint32_t rr = r0 + g * 16 + rq + i;
+          if (c < D::ncols(h) && rr < n_rows)
+            row_scratch[(size_t)rr * D::kRowScratch + D::kZ2 + D::col0(h) + c] = z;
+        }
       }
     }
+    if (h + 1 < D::kHeads) __syncthreads();   // a2 is refilled by the next head
   }
 }
 
 // a1 activations + a2: one thread per (row, Gaussian) projects the decoded
 // Gaussian from the outputs z2 the decode kept in row scratch.
+template <class D>
 __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restrict__ views,
                                                          cgx_anchor_scene sc,
                                                          const int2* __restrict__ rows,
@@ -428,13 +511,11 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
   if (r >= ctr->n_rows) return;
   const int2 row = rows[r];
   const ViewDev& V = views[row.x];
-  const float* zp = row_scratch + (size_t)r * kRowScratch + kZ2 + k * kGo;
-  float z2[kGo];
-#pragma unroll
-  for (int m = 0; m < kGo; ++m) z2[m] = zp[m];
+  float z2[D::kGo];
+  gaussian_outputs<D>(row_scratch + (size_t)r * D::kRowScratch + D::kZ2, k, z2);
   ProjIn in;
-  float sig_s[3];
-  decoded_gaussian(sc, (uint32_t)row.y, k, z2, in, sig_s);
+  float sig_s[3], O[3];
+  decoded_gaussian<D>(sc, (uint32_t)row.y, k, z2, in, sig_s, O);
   Splat o;
   uint32_t zb = 0;
   uint64_t tm = 0;
@@ -449,16 +530,32 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
 
 // The decoder weights in the layouts the decode and its adjoint stage in
 // LDS, written once per forward call:
-//   decode: W1 transposed to (column, k) with K = 64 (the feature rows,
-//   then the last four rows once per split term, zero padding), W2
-//   transposed to (column, k) with its 32 rows once per split term and
-//   zero columns 110..111, the biases (b2 zero-padded);
-//   adjoint: W1 and W2 as float32 rows at odd strides 33 and 111.
-constexpr int kPrepItems = kHid * kK1 + kN2 * kK2 + kHid + kN2 + kIn * kW1s + kHid * kW2s;
+//   decode: W1 transposed to (hidden unit, k) with K = 64 (the feature
+//   rows, then the last four rows once per split term, zero padding), W2
+//   transposed to (tile column, k) with its 32 rows once per split term,
+//   each head's columns padded to whole tiles with zeros, the biases (b2
+//   padded likewise);
+//   adjoint: W1 and W2 as float32 rows at odd strides.
+template <class D>
+constexpr int prep_items() {
+  return D::kHid * kK1 + D::kN2 * kK2 + D::kHid + D::kN2 + kIn * DecWT<D>::kW1s +
+         kHead * DecWT<D>::kW2s;
+}
 
-__global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB* __restrict__ wb,
-                                                      DecWT* __restrict__ wt) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPrepItems; i += gridDim.x * blockDim.x) {
+// the output column of tile column p, or -1 for padding
+template <class D>
+__device__ __forceinline__ int tile_column(int p) {
+  const int h = D::head_of_tile(p / 16);
+  const int c = p - 16 * D::tile0(h);
+  return c < D::ncols(h) ? D::col0(h) + c : -1;
+}
+
+template <class D>
+__global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB<D>* __restrict__ wb,
+                                                      DecWT<D>* __restrict__ wt) {
+  constexpr int kHid = D::kHid, kOut = D::kOut;
+  constexpr int kW1s = DecWT<D>::kW1s, kW2s = DecWT<D>::kW2s;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < prep_items<D>(); i += gridDim.x * blockDim.x) {
     int j = i;
     if (j < kHid * kK1) {
       const int n = j / kK1, k = j % kK1;
@@ -469,22 +566,24 @@ __global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB
       continue;
     }
     j -= kHid * kK1;
-    if (j < kN2 * kK2) {
-      const int n = j / kK2, k = j % kK2;
-      wb->w2t[n][k] = n < kOut ? sc.W2[(k % kHid) * kOut + n] : (uint16_t)0;
+    if (j < D::kN2 * kK2) {
+      const int p = j / kK2, k = j % kK2;
+      const int c = tile_column<D>(p);
+      wb->w2t[p][k] = c >= 0 ? sc.W2[(k % kHead) * kOut + c] : (uint16_t)0;
       continue;
     }
-    j -= kN2 * kK2;
+    j -= D::kN2 * kK2;
     if (j < kHid) {
       wb->b1[j] = sc.b1[j];
       continue;
     }
     j -= kHid;
-    if (j < kN2) {
-      wb->b2[j] = j < kOut ? sc.b2[j] : 0.0f;
+    if (j < D::kN2) {
+      const int c = tile_column<D>(j);
+      wb->b2[j] = c >= 0 ? sc.b2[c] : 0.0f;
       continue;
     }
-    j -= kN2;
+    j -= D::kN2;
     if (j < kIn * kW1s) {
       const int r = j / kW1s, c = j % kW1s;
       wt->W1[j] = c < kHid ? bf16_to_f32(sc.W1[r * kHid + c]) : 0.0f;
@@ -497,13 +596,15 @@ __global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB
 }
 
 // weight images, after the row scratch and the weight-gradient partials
-static DecWB* decode_weights(float* scratch, uint32_t max_rows) {
-  return reinterpret_cast<DecWB*>(scratch + (size_t)max_rows * kRowScratch +
-                                  (size_t)kRedBlocks * kWGrad);
+template <class D>
+static DecWB<D>* decode_weights(float* scratch, uint32_t max_rows) {
+  return reinterpret_cast<DecWB<D>*>(scratch + (size_t)max_rows * D::kRowScratch +
+                                     (size_t)kRedBlocks * D::kWGrad);
 }
-static DecWT* adjoint_weights(float* scratch, uint32_t max_rows) {
-  return reinterpret_cast<DecWT*>(reinterpret_cast<char*>(decode_weights(scratch, max_rows)) +
-                                  sizeof(DecWB));
+template <class D>
+static DecWT<D>* adjoint_weights(float* scratch, uint32_t max_rows) {
+  return reinterpret_cast<DecWT<D>*>(reinterpret_cast<char*>(decode_weights<D>(scratch, max_rows)) +
+                                     sizeof(DecWB<D>));
 }
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
@@ -513,23 +614,27 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
-  DecWB* wb = decode_weights(row_scratch, max_rows);
-  hipLaunchKernelGGL(k_prep_weights, dim3(div_up(kPrepItems, 256)), dim3(256), 0, s, sc, wb,
-                     adjoint_weights(row_scratch, max_rows));
-  hipLaunchKernelGGL(k_decode_mfma, dim3(blocks), dim3(64), 0, s, views, sc, rows,
-                     (const Counters*)ctr, (const DecWB*)wb, row_scratch);
-  hipLaunchKernelGGL(k_project_decoded, dim3(div_up((uint64_t)max_rows * kNOff, 256)), dim3(256),
-                     0, s, views, sc, rows, (const Counters*)ctr, tw, th,
-                     (const float*)row_scratch, splats, counts, zkey, tmask);
+  with_decoder(sc, [&](auto dec) {
+    using D = decltype(dec);
+    DecWB<D>* wb = decode_weights<D>(row_scratch, max_rows);
+    hipLaunchKernelGGL(k_prep_weights<D>, dim3(div_up(prep_items<D>(), 256)), dim3(256), 0, s, sc,
+                       wb, adjoint_weights<D>(row_scratch, max_rows));
+    hipLaunchKernelGGL(k_decode_mfma<D>, dim3(blocks), dim3(64), 0, s, views, sc, rows,
+                       (const Counters*)ctr, (const DecWB<D>*)wb, row_scratch);
+    hipLaunchKernelGGL(k_project_decoded<D>, dim3(div_up((uint64_t)max_rows * kNOff, 256)),
+                       dim3(256), 0, s, views, sc, rows, (const Counters*)ctr, tw, th,
+                       (const float*)row_scratch, splats, counts, zkey, tmask);
+  });
 }
 
 // ---------------------------------------------------------------------
 // a10, part 1: one thread per (row, Gaussian).  Takes the Gaussian's
 // decoder outputs z2 kept by the forward decode, runs the projection
-// adjoint, writes dz2 for the row's 11 outputs of this Gaussian and keeps
+// adjoint, writes dz2 for the row's G outputs of this Gaussian and keeps
 // the row's terms of the anchor gradients, d(mu) (which gives x and, times
 // l, the offset O) and d(mu) O + ds sigma(s) (which gives l), for part 3.
 // ---------------------------------------------------------------------
+template <class D>
 __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restrict__ views,
                                                           cgx_anchor_scene sc,
                                                           const int2* __restrict__ rows,
@@ -542,13 +647,13 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   const uint32_t r = item / kNOff;
   const int k = (int)(item - r * kNOff);
   if (r >= n_rows) return;
-  float* rs = scratch + (size_t)r * kRowScratch;
-  float* dz2 = rs + kIn + 2 * kHid + k * kGo;
-  float* gs = rs + kGSum + 6 * k;
+  float* rs = scratch + (size_t)r * D::kRowScratch;
+  float* dz2 = rs + D::kDZ2;
+  float* gs = rs + D::kGSum + 6 * k;
   const uint32_t slot = item;
   if (counts[slot] == 0) {
 #pragma unroll
-    for (int m = 0; m < kGo; ++m) dz2[m] = 0.0f;
+    for (int m = 0; m < D::kGo; ++m) dz2[D::zcol(k, m)] = 0.0f;
 #pragma unroll
     for (int m = 0; m < 6; ++m) gs[m] = 0.0f;
     return;
@@ -556,12 +661,11 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   const int2 row = rows[r];
   const ViewDev& V = views[row.x];
   const uint32_t a = (uint32_t)row.y;
-  float z2[kGo];
-#pragma unroll
-  for (int m = 0; m < kGo; ++m) z2[m] = rs[kZ2 + k * kGo + m];     // kept by the forward decode
+  float z2[D::kGo];
+  gaussian_outputs<D>(rs + D::kZ2, k, z2);     // kept by the forward decode
   ProjIn in;
-  float sig_s[3];
-  decoded_gaussian(sc, a, k, z2, in, sig_s);
+  float sig_s[3], O[3];
+  decoded_gaussian<D>(sc, a, k, z2, in, sig_s, O);
   float gg[16];
   const float4* gp = reinterpret_cast<const float4*>(&sgrad[slot]);
 #pragma unroll
@@ -574,41 +678,49 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
   float dmu[3], ds[3], dq[4];
   project_backward(V, in, st, gg, dmu, ds, dq);
   const float* L = sc.l + 3 * (size_t)a;
-  const float* O = sc.O + ((size_t)a * kNOff + k) * 3;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     gs[c] = dmu[c];
     gs[3 + c] = ds[c] * sig_s[c] + dmu[c] * O[c];
   }
-  dz2[0] = gg[5] * (sc.opacity_act == CGX_OPACITY_TANH_MASK ? 1.0f - in.op * in.op
-                                                            : in.op * (1.0f - in.op));
+  dz2[D::zcol(k, 0)] = gg[5] * (sc.opacity_act == CGX_OPACITY_TANH_MASK ? 1.0f - in.op * in.op
+                                                                        : in.op * (1.0f - in.op));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    dz2[1 + c] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);
-    dz2[4 + c] = ds[c] * L[c] * sig_s[c] * (1.0f - sig_s[c]);
+    dz2[D::zcol(k, 1 + c)] = gg[6 + c] * in.col[c] * (1.0f - in.col[c]);
+    dz2[D::zcol(k, 4 + c)] = ds[c] * L[c] * sig_s[c] * (1.0f - sig_s[c]);
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) dz2[7 + c] = dq[c];
+  for (int c = 0; c < 4; ++c) dz2[D::zcol(k, 7 + c)] = dq[c];
+  if constexpr (D::kGo > CGX_GAUSS_OUT) {
+    // decoded offset: mu = x + O l, so dO = d(mu) l
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dz2[D::zcol(k, CGX_GAUSS_OUT + c)] = dmu[c] * L[c];
+  }
 }
 
 // ---------------------------------------------------------------------
 // a10, part 2: 32 threads per row, 8 rows at a time, 32 rows per block
-// (one weight staging).  Thread j of a row forms dz1[j] = (dz2 W2^T)[j] *
-// [z1[j] > 0] from the row's dz2 staged in LDS, then dz0[j] = (dz1 W1^T)[j]
-// for the 32 features (the row's term of dF) and, in threads 0..3, the four
+// (one weight staging).  Thread j of a row forms, for each head h,
+// dz1[32h + j] = (dz2_h W2_h^T)[j] * [z1[32h + j] > 0] from the row's dz2
+// staged in LDS (head h's columns only), then dz0[j] = (dz1 W1^T)[j] for
+// the 32 features (the row's term of dF) and, in threads 0..3, the four
 // direction / distance inputs, which one thread takes back to the row's
 // term of dx.  z0 and dz1 are kept for the weight-gradient reduction.
 // ---------------------------------------------------------------------
 constexpr int kMlpRows = 8;      // rows in flight per block (32 threads each)
 constexpr int kMlpGroups = 4;    // row groups per block, sharing one weight staging
 
+template <class D>
 __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
                                                         cgx_anchor_scene sc,
                                                         const int2* __restrict__ rows,
                                                         const Counters* ctr,
-                                                        const DecWT* __restrict__ wimg,
+                                                        const DecWT<D>* __restrict__ wimg,
                                                         float* __restrict__ scratch) {
-  __shared__ DecWT w;
+  constexpr int kHid = D::kHid, kOut = D::kOut;
+  constexpr int kW1s = DecWT<D>::kW1s, kW2s = DecWT<D>::kW2s;
+  __shared__ DecWT<D> w;
   __shared__ float s_dz2[kMlpRows][kOut];
   __shared__ float s_dz1[kMlpRows][kHid];
   __shared__ float s_tail[kMlpRows][4];
@@ -616,26 +728,31 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
   const uint32_t rb = blockIdx.x * (kMlpRows * kMlpGroups);
   if (rb >= n_rows) return;                    // the grid covers the row capacity
   copy_weights(w, wimg);
-  const int rl = threadIdx.x / kHid, j = threadIdx.x % kHid;
+  const int rl = threadIdx.x / kHead, j = threadIdx.x % kHead;
   for (int grp = 0; grp < kMlpGroups; ++grp) {
     const uint32_t r0 = rb + grp * kMlpRows;
     if (r0 >= n_rows) break;                   // uniform over the block
     for (int e = threadIdx.x; e < kMlpRows * kOut; e += blockDim.x) {
       const int rr = e / kOut, c = e - rr * kOut;
       s_dz2[rr][c] = r0 + rr < n_rows
-                         ? scratch[(size_t)(r0 + rr) * kRowScratch + kIn + 2 * kHid + c]
+                         ? scratch[(size_t)(r0 + rr) * D::kRowScratch + D::kDZ2 + c]
                          : 0.0f;
     }
     __syncthreads();
     const uint32_t r = r0 + rl;
     const bool live = r < n_rows;
-    float* rs = scratch + (size_t)r * kRowScratch;
+    float* rs = scratch + (size_t)r * D::kRowScratch;
     if (live) {
-      float acc = 0.0f;
-      for (int c = 0; c < kOut; ++c) acc += s_dz2[rl][c] * w.W2[j * kW2s + c];
-      acc = rs[kIn + j] > 0.0f ? acc : 0.0f;
-      s_dz1[rl][j] = acc;
-      rs[kIn + kHid + j] = acc;
+#pragma unroll
+      for (int h = 0; h < D::kHeads; ++h) {
+        float acc = 0.0f;
+        for (int c = D::col0(h); c < D::col0(h) + D::ncols(h); ++c)
+          acc += s_dz2[rl][c] * w.W2[j * kW2s + c];
+        const int J = kHead * h + j;
+        acc = rs[D::kZ1 + J] > 0.0f ? acc : 0.0f;
+        s_dz1[rl][J] = acc;
+        rs[D::kDZ1 + J] = acc;
+      }
     }
     __syncthreads();
     uint32_t a = 0;
@@ -645,7 +762,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
       float acc = 0.0f;
 #pragma unroll 8
       for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kW1s + k];
-      rs[kDF + j] = acc;
+      rs[D::kDF + j] = acc;
       if (j < 4) {
         float t = 0.0f;
 #pragma unroll 8
@@ -669,7 +786,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
-        rs[kDX + c] = -ddelta;
+        rs[D::kDX + c] = -ddelta;
       }
     }
     __syncthreads();
@@ -685,7 +802,9 @@ __global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restric
 // its scale-term partner, lanes 0..2 the direction term of x.  When the
 // anchor changes, x_c and l_c add the ten offsets' sums in k order and the
 // anchor is written.  Every sum runs in a fixed order, so the result is
-// deterministic.  Anchors no view selects get zeros.
+// deterministic.  Anchors no view selects get zeros.  With decoded offsets
+// the table's offsets take no part and their gradient (if asked for) is
+// zero.
 constexpr int kGatherPerWave = 8;
 constexpr int kGatherList = kGatherPerWave * CGX_MAX_VIEWS;
 constexpr int kGatherUnroll = 8;
@@ -695,10 +814,12 @@ constexpr int kEntryShift = 29;
 constexpr uint32_t kEntryRow = (1u << kEntryShift) - 1;
 static_assert(kGatherPerWave <= (1 << (32 - kEntryShift)), "anchor index field");
 
+template <class D>
 __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int B,
                                                        const uint32_t* __restrict__ rinv,
                                                        const float* __restrict__ scratch,
                                                        cgx_grads gr) {
+  constexpr bool kTableO = D::kGo == CGX_GAUSS_OUT;
   __shared__ uint32_t s_e[kGatherList];
   const uint32_t A = (uint32_t)sc.n_anchor;
   const uint32_t a0 = blockIdx.x * kGatherPerWave;
@@ -706,8 +827,9 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
   const int j = threadIdx.x;
   const int t = j - CGX_FEAT_DIM;
   const bool off = t >= 0 && t < 3 * kNOff;
-  const int src = j < CGX_FEAT_DIM ? kDF + j : off ? kGSum + 6 * (t / 3) + t % 3 : kDF;
-  const int xs = kDX + (j < 3 ? j : 0);
+  const bool write_o = off && gr.O != nullptr;
+  const int src = j < CGX_FEAT_DIM ? D::kDF + j : off ? D::kGSum + 6 * (t / 3) + t % 3 : D::kDF;
+  const int xs = D::kDX + (j < 3 ? j : 0);
   // the wave's rows, (anchor, view) order
   const int np = kGatherPerWave * B;
   uint32_t n = 0;
@@ -735,7 +857,8 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
       gl += __shfl(accl, from, kWave);
     }
     if (j < CGX_FEAT_DIM) gr.F[(size_t)a * CGX_FEAT_DIM + j] = acc;
-    else if (off) gr.O[(size_t)a * 3 * kNOff + t] = acc * sc.l[3 * (size_t)a + t % 3];
+    else if (write_o)
+      gr.O[(size_t)a * 3 * kNOff + t] = kTableO ? acc * sc.l[3 * (size_t)a + t % 3] : 0.0f;
     if (j < 3) {
       gr.x[3 * (size_t)a + j] = gx;
       gr.l[3 * (size_t)a + j] = gl;
@@ -750,7 +873,7 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
       // past the end: repeat entry i (loaded, never added)
       const uint32_t e = __builtin_amdgcn_readfirstlane(s_e[i + u < n ? i + u : i]);
       eg[u] = e >> kEntryShift;
-      const float* rs = scratch + (size_t)(e & kEntryRow) * kRowScratch;
+      const float* rs = scratch + (size_t)(e & kEntryRow) * D::kRowScratch;
       vs[u] = rs[src];
       vl[u] = rs[src + 3];
       vx[u] = rs[xs];
@@ -773,7 +896,7 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
     const uint32_t a = a0 + g;
     if ((done >> g & 1u) || a >= A) continue;
     if (j < CGX_FEAT_DIM) gr.F[(size_t)a * CGX_FEAT_DIM + j] = 0.0f;
-    else if (off) gr.O[(size_t)a * 3 * kNOff + t] = 0.0f;
+    else if (write_o) gr.O[(size_t)a * 3 * kNOff + t] = 0.0f;
     if (j < 3) {
       gr.x[3 * (size_t)a + j] = 0.0f;
       gr.l[3 * (size_t)a + j] = 0.0f;
@@ -781,26 +904,27 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
   }
 }
 
-// Weight gradients on MFMA: dW1 = Z0^T dZ1 (36 x 32) and dW2 = Z1^T dZ2
-// (32 x 110), reductions over the rows.  Each block (four waves) owns a
-// contiguous chunk of rows and walks it 32 rows (one MFMA k-step) at a
-// time: the chunk's z0, z1, dz1 and dz2 are staged transposed in LDS as
-// float32, each wave computes 5 of the 20 16x16 output tiles, and each
-// fragment is split on load into three bf16 terms
-// (h + m + l, as in the forward decode); the six products h*h, h*m, m*h,
-// h*l, l*h, m*m (the dropped ones are below 2^-26 relative) accumulate in
-// fp32.  The biases' gradients are column sums of the staged values.  Every
-// block writes one partial of 4814 values; k_wgrad_final adds the partials
-// in a fixed order (deterministic).
+// Weight gradients on MFMA: dW1 = Z0^T dZ1 (36 x 32H) and, per head h,
+// dW2_h = Z1_h^T dZ2_h (32 x the head's columns), reductions over the
+// rows.  Each block (four waves) owns a contiguous chunk of rows and walks
+// it 32 rows (one MFMA k-step) at a time: the chunk's z0, z1, dz1 and dz2
+// are staged transposed in LDS as float32 (dz2 in tile columns, each
+// head's columns padded to whole tiles), the waves share the 16x16 output
+// tiles round-robin, and each fragment is split on load into three bf16
+// terms (h + m + l, as in the forward decode); the six products h*h, h*m,
+// m*h, h*l, l*h, m*m (the dropped ones are below 2^-26 relative)
+// accumulate in fp32.  The biases' gradients are column sums of the staged
+// values.  Every block writes one partial of all weight gradients;
+// k_wgrad_final adds the partials in a fixed order (deterministic).
 constexpr int kWR = 32;          // rows per MFMA k-step
 constexpr int kM1 = 48;          // dW1 rows (36 padded)
-constexpr int kN2w = 112;        // dW2 columns (110 padded)
 
+template <class D>
 struct WgradLds {
   float z0t[kM1][kWR + 4];       // A of dW1: (i, r); rows padded against bank conflicts
-  float dz1t[kHid][kWR + 4];     // B of dW1: (j, r)
-  float z1t[kHid][kWR + 4];      // A of dW2: (j, r)
-  float dz2t[kN2w][kWR + 4];     // B of dW2: (c, r)
+  float dz1t[D::kHid][kWR + 4];  // B of dW1: (j, r)
+  float z1t[D::kHid][kWR + 4];   // A of dW2: (j, r)
+  float dz2t[D::kN2][kWR + 4];   // B of dW2: (tile column, r)
 };
 
 struct Split8 {
@@ -836,132 +960,193 @@ __device__ __forceinline__ f32x4_t mfma_split6(const Split8& A, const Split8& B,
 }
 
 constexpr int kWgWaves = 4;
-constexpr int kTiles1 = 3 * 2;   // dW1: 3 row tiles (36 rows padded to 48) x 2 column tiles
-constexpr int kTiles2 = 2 * 7;   // dW2: 2 row tiles x 7 column tiles (110 padded to 112)
-constexpr int kTilesPerWave = (kTiles1 + kTiles2) / kWgWaves;
-static_assert((kTiles1 + kTiles2) % kWgWaves == 0, "tiles split evenly over the waves");
 
-// output tile ti of the block: A rows from a, B columns from b (LDS rows)
-__device__ __forceinline__ void wgrad_tile(const WgradLds& L, int ti, int& m, int& t,
+template <class D>
+struct WgradTiles {
+  static constexpr int kCols1 = D::kHid / 16;              // dW1 column tiles
+  static constexpr int kTiles1 = 3 * kCols1;               // 36 rows padded to 48
+  static constexpr int kTiles2 = 2 * D::kTiles;            // dW2: 2 row tiles x tile columns
+  static constexpr int kTotal = kTiles1 + kTiles2;
+  static constexpr int kPerWave = (kTotal + kWgWaves - 1) / kWgWaves;
+};
+
+// output tile ti of the block: A rows from a, B columns from b (LDS rows);
+// m, t: row and column tile (dW2: t is the tile column index, head h)
+template <class D>
+__device__ __forceinline__ void wgrad_tile(const WgradLds<D>& L, int ti, int& m, int& t, int& h,
                                            const float*& a, const float*& b, int col, int kq) {
-  if (ti < kTiles1) {
-    m = ti / 2;
-    t = ti % 2;
+  using W = WgradTiles<D>;
+  if (ti < W::kTiles1) {
+    m = ti / W::kCols1;
+    t = ti % W::kCols1;
+    h = 0;
     a = &L.z0t[m * 16 + col][kq];
     b = &L.dz1t[t * 16 + col][kq];
   } else {
-    m = (ti - kTiles1) / 7;
-    t = (ti - kTiles1) % 7;
-    a = &L.z1t[m * 16 + col][kq];
+    m = (ti - W::kTiles1) / D::kTiles;
+    t = (ti - W::kTiles1) % D::kTiles;
+    h = D::head_of_tile(t);
+    a = &L.z1t[kHead * h + m * 16 + col][kq];
     b = &L.dz2t[t * 16 + col][kq];
   }
 }
 
+template <class D>
 __global__ __launch_bounds__(kWgWaves * kWave) void k_wgrad_mfma(const float* __restrict__ scratch,
                                                                 const Counters* ctr,
                                                                 float* __restrict__ partial) {
-  __shared__ WgradLds L;
+  using W = WgradTiles<D>;
+  constexpr int kHid = D::kHid, kOut = D::kOut;
+  __shared__ WgradLds<D> L;
   const int tid = threadIdx.x, lane = tid % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const uint32_t n = ctr->n_rows;
   uint64_t b0, b1;
   chunk_range(n, b0, b1);
   const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
-  f32x4_t acc[kTilesPerWave];
+  f32x4_t acc[W::kPerWave];
 #pragma unroll
-  for (int q = 0; q < kTilesPerWave; ++q) acc[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  // bias gradients: thread c < 142 owns column c of [dz1 | dz2]
-  float bsum = 0.0f;
+  for (int q = 0; q < W::kPerWave; ++q) acc[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // bias gradients: thread c owns columns c and c + 256 of [dz1 | dz2]
+  constexpr int kBias = kHid + kOut;
+  static_assert(kBias <= 2 * kWgWaves * kWave, "two bias columns per thread at most");
+  float bsum[2] = {0.0f, 0.0f};
   // zero the padding rows once (never written by the staging)
   for (int e = tid; e < (kM1 - kIn) * kWR; e += blockDim.x) L.z0t[kIn + e / kWR][e % kWR] = 0.0f;
-  for (int e = tid; e < (kN2w - kOut) * kWR; e += blockDim.x) L.dz2t[kOut + e / kWR][e % kWR] = 0.0f;
+  for (int e = tid; e < D::kN2 * kWR; e += blockDim.x)
+    if (tile_column<D>(e / kWR) < 0) L.dz2t[e / kWR][e % kWR] = 0.0f;
 
   for (uint64_t base = b0; base < b1; base += kWR) {
     const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
-    const float* src = scratch + base * kRowScratch;
+    const float* src = scratch + base * D::kRowScratch;
     // stage: element pair e of the chunk is values q0, q0 + 1 of row r, over
     // the kRowUsed leading values of each row (even counts and strides, so a
     // pair never straddles two rows and stays 8-byte aligned)
-    constexpr int kHalf = kRowUsed / 2;
+    constexpr int kHalf = D::kRowUsed / 2;
     constexpr int kPairs = kWR * kHalf;
 #pragma unroll 4
     for (int e = tid; e < kPairs; e += kWgWaves * kWave) {
       const int r = e / kHalf, q0 = 2 * (e - r * kHalf);
-      const float2 x = r < nr ? *reinterpret_cast<const float2*>(src + (size_t)r * kRowScratch + q0)
+      const float2 x = r < nr ? *reinterpret_cast<const float2*>(src + (size_t)r * D::kRowScratch + q0)
                               : float2{0.0f, 0.0f};
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int q = q0 + h;
-        const float v = h ? x.y : x.x;
-        if (q < kIn) L.z0t[q][r] = v;
-        else if (q < kIn + kHid) L.z1t[q - kIn][r] = v;
-        else if (q < kIn + 2 * kHid) L.dz1t[q - kIn - kHid][r] = v;
-        else L.dz2t[q - kIn - 2 * kHid][r] = v;
+      for (int hh = 0; hh < 2; ++hh) {
+        const int q = q0 + hh;
+        const float v = hh ? x.y : x.x;
+        if (q < D::kZ1) {
+          L.z0t[q][r] = v;
+        } else if (q < D::kDZ1) {
+          L.z1t[q - D::kZ1][r] = v;
+        } else if (q < D::kDZ2) {
+          L.dz1t[q - D::kDZ1][r] = v;
+        } else {
+          // output column u -> its tile column
+          const int u = q - D::kDZ2;
+          int h = 0;
+#pragma unroll
+          for (int i = 1; i < D::kHeads; ++i) h += u >= D::col0(i);
+          int p = u;
+#pragma unroll
+          for (int i = 0; i < D::kHeads; ++i)
+            if (i == h) p = 16 * D::tile0(i) + (u - D::col0(i));
+          L.dz2t[p][r] = v;
+        }
       }
     }
     __syncthreads();
-    if (tid < kHid + kOut) {
-      const float* row = tid < kHid ? L.dz1t[tid] : L.dz2t[tid - kHid];
-      float sum = 0.0f;
-      for (int r = 0; r < kWR; ++r) sum += row[r];
-      bsum += sum;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = tid + u * kWgWaves * kWave;
+      if (c < kBias) {
+        const float* row = c < kHid ? L.dz1t[c] : L.dz2t[0];
+        int p = 0;
+        if (c >= kHid) {
+          const int o = c - kHid;
+          int h = 0;
+#pragma unroll
+          for (int i = 1; i < D::kHeads; ++i) h += o >= D::col0(i);
+#pragma unroll
+          for (int i = 0; i < D::kHeads; ++i)
+            if (i == h) p = 16 * D::tile0(i) + (o - D::col0(i));
+          row = L.dz2t[p];
+        }
+        float sum = 0.0f;
+        for (int r = 0; r < kWR; ++r) sum += row[r];
+        bsum[u] += sum;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kTilesPerWave; ++q) {
-      int m, t;
-      const float *a, *b;
-      wgrad_tile(L, wave + kWgWaves * q, m, t, a, b, col, kq);
-      acc[q] = mfma_split6(split8(a), split8(b), acc[q]);
+    for (int q = 0; q < W::kPerWave; ++q) {
+      const int ti = wave + kWgWaves * q;
+      if (ti < W::kTotal) {                    // uniform over the wave
+        int m, t, h;
+        const float *a, *b;
+        wgrad_tile<D>(L, ti, m, t, h, a, b, col, kq);
+        acc[q] = mfma_split6(split8(a), split8(b), acc[q]);
+      }
     }
     __syncthreads();
   }
   // partial layout: W1 (i, j) row-major, W2 (j, c) row-major, b1, b2
-  float* out = partial + (size_t)blockIdx.x * kWGrad;
+  float* out = partial + (size_t)blockIdx.x * D::kWGrad;
 #pragma unroll
-  for (int q = 0; q < kTilesPerWave; ++q) {
+  for (int q = 0; q < W::kPerWave; ++q) {
     const int ti = wave + kWgWaves * q;
-    int m, t;
+    if (ti >= W::kTotal) continue;
+    int m, t, h;
     const float *a, *b;
-    wgrad_tile(L, ti, m, t, a, b, col, kq);
+    wgrad_tile<D>(L, ti, m, t, h, a, b, col, kq);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rr = m * 16 + rq + i, cc = t * 16 + col;
-      if (ti < kTiles1) {
-        if (rr < kIn) out[rr * kHid + cc] = acc[q][i];
-      } else if (cc < kOut) {
-        out[kIn * kHid + rr * kOut + cc] = acc[q][i];
+      const int rr = m * 16 + rq + i;
+      if (ti < W::kTiles1) {
+        if (rr < kIn) out[rr * kHid + t * 16 + col] = acc[q][i];
+      } else {
+        const int c = tile_column<D>(t * 16 + col);
+        if (c >= 0) out[kIn * kHid + rr * kOut + c] = acc[q][i];
       }
     }
   }
-  if (tid < kHid + kOut) out[kIn * kHid + kHid * kOut + tid] = bsum;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int c = tid + u * kWgWaves * kWave;
+    if (c < kBias) out[kIn * kHid + kHead * kOut + c] = bsum[u];
+  }
 }
 
 // Sum of the block partials: a block reduces 32 outputs; thread (o, g) adds
 // partials g, g + 8, g + 16, ... of output o, then the 8 group sums are
 // added in group order (fixed order, deterministic).
+template <class D>
 __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ partial, int nb,
                                                      cgx_grads gr) {
+  constexpr int kW1n = kIn * D::kHid, kW2n = kHead * D::kOut, kB1n = D::kHid;
   __shared__ float red[8][33];
   const int ol = threadIdx.x & 31, g = threadIdx.x >> 5;
   const int o = blockIdx.x * 32 + ol;
   float s = 0.0f;
-  if (o < kWGrad)
-    for (int b = g; b < nb; b += 8) s += partial[(size_t)b * kWGrad + o];
+  if (o < D::kWGrad)
+    for (int b = g; b < nb; b += 8) s += partial[(size_t)b * D::kWGrad + o];
   red[g][ol] = s;
   __syncthreads();
-  if (g != 0 || o >= kWGrad) return;
+  if (g != 0 || o >= D::kWGrad) return;
   float t = 0.0f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) t += red[k][ol];
-  if (o < kIn * kHid) gr.W1[o] = t;
-  else if (o < kIn * kHid + kHid * kOut) gr.W2[o - kIn * kHid] = t;
-  else if (o < kIn * kHid + kHid * kOut + kHid) gr.b1[o - kIn * kHid - kHid * kOut] = t;
-  else gr.b2[o - kIn * kHid - kHid * kOut - kHid] = t;
+  if (o < kW1n) gr.W1[o] = t;
+  else if (o < kW1n + kW2n) gr.W2[o - kW1n] = t;
+  else if (o < kW1n + kW2n + kB1n) gr.b1[o - kW1n - kW2n] = t;
+  else gr.b2[o - kW1n - kW2n - kB1n] = t;
 }
 
-size_t anchor_scratch_bytes(int64_t max_rows) {
-  return sizeof(float) * ((size_t)max_rows * kRowScratch + (size_t)kRedBlocks * kWGrad) +
-         sizeof(DecWB) + sizeof(DecWT);
+size_t anchor_scratch_bytes(int64_t max_rows, const cgx_anchor_scene& sc) {
+  size_t bytes = 0;
+  with_decoder(sc, [&](auto dec) {
+    using D = decltype(dec);
+    bytes = sizeof(float) * ((size_t)max_rows * D::kRowScratch + (size_t)kRedBlocks * D::kWGrad) +
+            sizeof(DecWB<D>) + sizeof(DecWT<D>);
+  });
+  return bytes;
 }
 
 void launch_decode_project_backward(const ViewDev* views, int B, const cgx_anchor_scene& sc,
@@ -969,24 +1154,26 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
                                     const uint32_t* counts, const SplatGrad* sgrad,
                                     const Counters* ctr, const cgx_grads& g, float* scratch,
                                     hipStream_t s) {
-  float* partial = scratch + (size_t)max_rows * kRowScratch;
-  const uint32_t gblocks = div_up((uint64_t)max_rows * kNOff, 256);
-  if (gblocks)
-    hipLaunchKernelGGL(k_decode_bwd_gauss, dim3(gblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                       counts, sgrad, scratch);
-  const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
-  if (rblocks)
-    hipLaunchKernelGGL(k_decode_bwd_mlp, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                       (const DecWT*)adjoint_weights(scratch, max_rows), scratch);
-  const uint32_t ablocks = div_up((uint64_t)sc.n_anchor, kGatherPerWave);
-  if (ablocks)
-    hipLaunchKernelGGL(k_anchor_grad, dim3(ablocks), dim3(kWave), 0, s, sc, B, rinv,
-                       (const float*)scratch, g);
-  hipLaunchKernelGGL(k_wgrad_mfma, dim3(kRedBlocks), dim3(kWgWaves * kWave), 0, s,
-                     (const float*)scratch, ctr,
-                     partial);
-  hipLaunchKernelGGL(k_wgrad_final, dim3(div_up(kWGrad, 32)), dim3(256), 0, s,
-                     (const float*)partial, kRedBlocks, g);
+  with_decoder(sc, [&](auto dec) {
+    using D = decltype(dec);
+    float* partial = scratch + (size_t)max_rows * D::kRowScratch;
+    const uint32_t gblocks = div_up((uint64_t)max_rows * kNOff, 256);
+    if (gblocks)
+      hipLaunchKernelGGL(k_decode_bwd_gauss<D>, dim3(gblocks), dim3(256), 0, s, views, sc, rows,
+                         ctr, counts, sgrad, scratch);
+    const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
+    if (rblocks)
+      hipLaunchKernelGGL(k_decode_bwd_mlp<D>, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
+                         (const DecWT<D>*)adjoint_weights<D>(scratch, max_rows), scratch);
+    const uint32_t ablocks = div_up((uint64_t)sc.n_anchor, kGatherPerWave);
+    if (ablocks)
+      hipLaunchKernelGGL(k_anchor_grad<D>, dim3(ablocks), dim3(kWave), 0, s, sc, B, rinv,
+                         (const float*)scratch, g);
+    hipLaunchKernelGGL(k_wgrad_mfma<D>, dim3(kRedBlocks), dim3(kWgWaves * kWave), 0, s,
+                       (const float*)scratch, ctr, partial);
+    hipLaunchKernelGGL(k_wgrad_final<D>, dim3(div_up(D::kWGrad, 32)), dim3(256), 0, s,
+                       (const float*)partial, kRedBlocks, g);
+  });
 }
 
 }  // namespace cgx

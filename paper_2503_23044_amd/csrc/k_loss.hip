@@ -4,7 +4,9 @@
 // second view's rendered normal N and plane distance D at the patch centre
 // (stop-gradient on the first view).  Its gradient with respect to the
 // second view's RGB is accumulated into a caller buffer that then seeds the
-// backward raster.
+// backward raster, or, in the fused chain, its gradient with respect to the
+// mean intensity into a one-channel plane that the backward prologue folds
+// into the RGB seed (a third of it per channel).
 //
 // One wave per (pair, patch), 16 per workgroup: lane j < 49 owns patch pixel (j % 7 - 3,
 // j / 7 - 3).  The homography is built per wave in float64 from the two
@@ -39,12 +41,13 @@ __device__ __forceinline__ double gray_at(const float* rgb, size_t pv, uint32_t 
 // and added with one atomic per workgroup (same-address atomics serialise)
 constexpr int kNccWaves = 16;
 
-// one patch on one wave: adds its RGB gradient, returns its loss term (0
-// for a skipped patch) on every lane
+// one patch on one wave: adds its gradient (RGB planes, or the one-channel
+// intensity plane when gray), returns its loss term (0 for a skipped
+// patch) on every lane
 __device__ float ncc_patch(const ViewDev* __restrict__ views, const float* __restrict__ rgb,
                            const float* __restrict__ normal, const float* __restrict__ plane_d,
                            const int32_t* __restrict__ centres, int n_patch, int n_pairs,
-                           float scale, float* __restrict__ grad_rgb, int patch, int lane) {
+                           float scale, float* __restrict__ grad, bool gray, int patch, int lane) {
   const int pair = patch / n_patch;
   if (pair >= n_pairs) return 0.0f;
   const ViewDev& Vs = views[2 * pair];
@@ -112,12 +115,17 @@ __device__ float ncc_patch(const ViewDev* __restrict__ views, const float* __res
   if (mine) {
     // d NCC / d a_j = B_j / den - sab sbb A_j / den^3 (the B's sum to zero)
     const double dn = Bc / den - sab * sbb * A / (den * den * den);
-    const float ga = (float)(-(double)scale * dn / 3.0);
-    if (ga != 0.0f) {
-      const uint32_t p = (uint32_t)y * (uint32_t)Vr.W + (uint32_t)x;
-      atomic_add_f32(grad_rgb + 3 * pvr + p, ga);
-      atomic_add_f32(grad_rgb + 3 * pvr + HWr + p, ga);
-      atomic_add_f32(grad_rgb + 3 * pvr + 2 * HWr + p, ga);
+    const uint32_t p = (uint32_t)y * (uint32_t)Vr.W + (uint32_t)x;
+    if (gray) {
+      const float gi = (float)(-(double)scale * dn);
+      if (gi != 0.0f) atomic_add_f32(grad + pvr + p, gi);
+    } else {
+      const float ga = (float)(-(double)scale * dn / 3.0);
+      if (ga != 0.0f) {
+        atomic_add_f32(grad + 3 * pvr + p, ga);
+        atomic_add_f32(grad + 3 * pvr + HWr + p, ga);
+        atomic_add_f32(grad + 3 * pvr + 2 * HWr + p, ga);
+      }
     }
   }
   return (float)(scale * (1.0 - ncc));
@@ -129,12 +137,12 @@ __global__ __launch_bounds__(kWave * kNccWaves) void k_ncc_loss(const ViewDev* _
                                                                 const float* __restrict__ plane_d,
                                                                 const int32_t* __restrict__ centres,
                                                                 int n_patch, int n_pairs, float scale,
-                                                                float* __restrict__ grad_rgb,
+                                                                float* __restrict__ grad, bool gray,
                                                                 float* __restrict__ loss) {
   __shared__ float part[kNccWaves];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const float l = ncc_patch(views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad_rgb,
-                            blockIdx.x * kNccWaves + wave, lane);
+  const float l = ncc_patch(views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad,
+                            gray, blockIdx.x * kNccWaves + wave, lane);
   if (lane == 0) part[wave] = l;
   __syncthreads();
   if (threadIdx.x == 0 && loss) {
@@ -146,13 +154,13 @@ __global__ __launch_bounds__(kWave * kNccWaves) void k_ncc_loss(const ViewDev* _
 
 void launch_ncc_loss(const ViewDev* views, int n_views, const float* rgb, const float* normal,
                      const float* plane_d, const int32_t* centres, int n_patch, float weight,
-                     float* grad_rgb, float* loss, hipStream_t s) {
+                     float* grad, bool gray, float* loss, hipStream_t s) {
   const int n_pairs = n_views / 2;
   if (n_pairs == 0 || n_patch == 0) return;
   const float scale = weight / ((float)n_pairs * (float)n_patch);
   const uint32_t n = (uint32_t)n_pairs * (uint32_t)n_patch;
   hipLaunchKernelGGL(k_ncc_loss, dim3((n + kNccWaves - 1) / kNccWaves), dim3(kWave * kNccWaves), 0, s,
-                     views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad_rgb, loss);
+                     views, rgb, normal, plane_d, centres, n_patch, n_pairs, scale, grad, gray, loss);
 }
 
 }  // namespace cgx

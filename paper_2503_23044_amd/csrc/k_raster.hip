@@ -454,6 +454,12 @@ __global__ __launch_bounds__(kWave) void k_raster_bwd(RasterArgs a) {
         gn[c] = a.w_normal * inv_px * sgnf(e);
         loss += a.w_normal * inv_px * fabsf(e);
       }
+      // Eq. 10 term of the fused chain: the gradient of the mean intensity,
+      // a third of it per channel
+      if (a.g_ncc) {
+        const float gi = a.g_ncc[pv + p] * (1.0f / 3.0f);
+        for (int c = 0; c < 3; ++c) gc[c] += gi;
+      }
     } else {
       if (a.g_rgb)
         for (int c = 0; c < 3; ++c) gc[c] = a.g_rgb[3 * pv + c * HW + p];

@@ -25,16 +25,21 @@ def explicit_scene(means, scales, quats, opacity, sh, sh_degree, device="cuda"):
 
 
 def anchor_scene(x, l, O, F, level, W1_bits, b1, W2_bits, b2, n_levels, d_max, device="cuda",
-                 opacity_act=B.OPACITY_SIGMOID):
+                 opacity_act=B.OPACITY_SIGMOID, offset_mode=B.OFFSETS_TABLE,
+                 decoder_heads=B.DECODER_SHARED):
     """Device tensors of a voxel-anchor scene; decoder weights as bfloat16
     bit patterns (held in int16 tensors).  opacity_act: B.OPACITY_SIGMOID or
-    B.OPACITY_TANH_MASK (tanh, non-positive opacities masked)."""
+    B.OPACITY_TANH_MASK (tanh, non-positive opacities masked); offset_mode:
+    B.OFFSETS_TABLE (O) or B.OFFSETS_DECODED (14 decoder outputs per
+    Gaussian); decoder_heads: B.DECODER_SHARED (W1 36 x 32) or
+    B.DECODER_PER_ATTRIBUTE (W1 36 x 96, or 36 x 128 with decoded offsets)."""
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)  # noqa: E731
     bits = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.uint16).view(np.int16), device=device)  # noqa: E731
     return dict(kind=B.CGX_SCENE_ANCHOR, x=f(x), l=f(l), O=f(O), F=f(F),
                 level=torch.as_tensor(np.ascontiguousarray(level, np.uint8), device=device),
                 W1=bits(W1_bits), b1=f(b1), W2=bits(W2_bits), b2=f(b2),
-                n_levels=int(n_levels), d_max=float(d_max), opacity_act=int(opacity_act))
+                n_levels=int(n_levels), d_max=float(d_max), opacity_act=int(opacity_act),
+                offset_mode=int(offset_mode), decoder_heads=int(decoder_heads))
 
 
 def scene_from(obj, device="cuda"):
@@ -43,7 +48,9 @@ def scene_from(obj, device="cuda"):
         return explicit_scene(obj.means, obj.scales, obj.quats, obj.opacity, obj.sh, obj.sh_degree, device)
     return anchor_scene(obj.x, obj.l, obj.O, obj.F, obj.level, obj.W1_bits, obj.b1, obj.W2_bits,
                         obj.b2, obj.n_levels, obj.d_max, device,
-                        getattr(obj, "opacity_act", B.OPACITY_SIGMOID))
+                        getattr(obj, "opacity_act", B.OPACITY_SIGMOID),
+                        getattr(obj, "offset_mode", B.OFFSETS_TABLE),
+                        getattr(obj, "decoder_heads", B.DECODER_SHARED))
 
 
 def pixel_offsets(views):
@@ -198,13 +205,20 @@ class Renderer:
         return state
 
     def fwd_bwd_l1(self, views, scene, target, weights=(1.0, 1.0, 1.0), out=None, grads=None,
-                   loss=None, check=True):
+                   loss=None, check=True, ncc=None):
+        """Fused forward, L1 loss (Eq. 8) and backward; ncc=(centres, weight)
+        adds the geometric loss of Eq. 10 with patch centres given as an
+        int32 device tensor (n_views // 2, n_patch, 2)."""
+        nt = None
+        if ncc is not None:
+            c = ncc[0].to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+            nt = dict(centres=c, n_patch=int(c.shape[1]), weight=float(ncc[1]))
         for _ in range(4):
             ws = self.ensure_workspace(views, scene)
             out = out if out is not None else self.alloc_images(views)
             grads = grads if grads is not None else grad_buffers(scene, f"cuda:{self.device}")
             B.cgx_render_fwd_bwd_l1(self.ctx, views, scene, self.cap, ws, target, weights, out,
-                                    grads, loss)
+                                    grads, loss, ncc=nt)
             if not check:
                 return out, grads
             info = B.cgx_read_info(self.ctx, ws, raise_on_capacity=False)
@@ -381,7 +395,8 @@ _ANCHOR_KEYS = ("x", "l", "O", "F", "b1", "b2")
 class RenderAnchor(torch.autograd.Function):
     """Differentiable render of voxel anchors.  meta holds the non-trainable
     parts: level (uint8), the decoder weights W1, W2 as bfloat16 bit tensors,
-    n_levels, d_max and opacity_act; the gradients of W1 and W2 are returned
+    n_levels, d_max, opacity_act, offset_mode and decoder_heads; the
+    gradients of W1 and W2 are returned
     through the float tensors passed as W1f / W2f (their values are not
     read: the weights are the bfloat16 bits).  The forward state is kept per
     call, as for RenderExplicit."""
@@ -391,7 +406,9 @@ class RenderAnchor(torch.autograd.Function):
         d = lambda t: t.detach().contiguous()   # noqa: E731
         scene = dict(kind=B.CGX_SCENE_ANCHOR, x=d(x), l=d(l), O=d(O), F=d(F), level=meta["level"],
                      W1=meta["W1"], W2=meta["W2"], b1=d(b1), b2=d(b2), n_levels=meta["n_levels"],
-                     d_max=meta["d_max"], opacity_act=int(meta.get("opacity_act", B.OPACITY_SIGMOID)))
+                     d_max=meta["d_max"], opacity_act=int(meta.get("opacity_act", B.OPACITY_SIGMOID)),
+                     offset_mode=int(meta.get("offset_mode", B.OFFSETS_TABLE)),
+                     decoder_heads=int(meta.get("decoder_heads", B.DECODER_SHARED)))
         out = renderer.forward(views, scene)
         ctx.renderer, ctx.views, ctx.scene, ctx.out = renderer, views, scene, out
         ctx.state = renderer.take_state()

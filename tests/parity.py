@@ -166,8 +166,9 @@ def compare_sorted(dbg, r, slot_to_view_gid, tiles=None):
     """Sorted pairs, nothing dropped.  For every tile (or the given global
     tiles) the GPU's list must hold every pair the oracle is certain of, only
     pairs the oracle lists (its own, or one near tie away), with depth keys
-    bit-identical to the oracle's, in (depth bits, view, id) order, with the
-    ranges of the GPU's sorted tile ids.  Returns (pairs checked, near-tie
+    bit-identical to the oracle's (within the oracle's key tolerance where
+    the mean carries a decode error), in (depth bits, view, id) order, with
+    the ranges of the GPU's sorted tile ids.  Returns (pairs checked, near-tie
     pairs the GPU took, near-tie pairs it left)."""
     gt = dbg["tile"].astype(np.int64)
     gz = dbg["zbits"].astype(np.int64)
@@ -202,7 +203,12 @@ def compare_sorted(dbg, r, slot_to_view_gid, tiles=None):
         idx = np.array([rk.get((int(a), int(b)), -1) for a, b in got[:, 1:]], np.int64)
         assert np.all(idx >= 0), (f"tile {t}: GPU pairs the oracle does not list: "
                                   f"{got[idx < 0][:5].tolist()}")
-        np.testing.assert_array_equal(got[:, 0], ref[idx, 0], err_msg=f"tile {t}: depth keys")
+        # bit-identical, or within the key's tolerance where the mean carries
+        # a decode error (decoded offsets)
+        ztol = o["ztol"][o0:o1][idx]
+        bad = np.abs(got[:, 0] - ref[idx, 0]) > ztol
+        assert not bad.any(), (f"tile {t}: depth keys {got[bad, 0][:5].tolist()} vs "
+                               f"{ref[idx, 0][bad][:5].tolist()} (tolerance {ztol[bad][:5].tolist()})")
         taken = np.zeros(ref.shape[0], bool)
         taken[idx] = True
         assert np.all(taken[cert]), (f"tile {t}: GPU lacks certain pairs "

@@ -105,7 +105,22 @@ def test_workspace_size_validation(B):
         assert _status(B, B.cgx_workspace_size, ctx, [_view()], sc) == "CGX_ERR_INVALID_ARG"
         sc["opacity_act"] = B.OPACITY_TANH_MASK
         assert B.cgx_workspace_size(ctx, [_view()], sc) > 0
-        assert B.cgx_workspace_size(ctx, [_view()], _anchor()) > 0
+        base = B.cgx_workspace_size(ctx, [_view()], _anchor())
+        assert base > 0
+        for key, bad in (("offset_mode", 2), ("offset_mode", -1), ("decoder_heads", 2),
+                         ("decoder_heads", 4), ("decoder_heads", 0)):
+            sc = _anchor()
+            sc[key] = bad
+            assert _status(B, B.cgx_workspace_size, ctx, [_view()], sc) == "CGX_ERR_INVALID_ARG", (key, bad)
+        # wider decoders keep more per row: the workspace grows with them
+        sizes = []
+        for mode, heads in ((B.OFFSETS_TABLE, B.DECODER_SHARED), (B.OFFSETS_DECODED, B.DECODER_SHARED),
+                            (B.OFFSETS_TABLE, B.DECODER_PER_ATTRIBUTE),
+                            (B.OFFSETS_DECODED, B.DECODER_PER_ATTRIBUTE)):
+            sc = _anchor()
+            sc["offset_mode"], sc["decoder_heads"] = mode, heads
+            sizes.append(B.cgx_workspace_size(ctx, [_view()], sc))
+        assert sizes[0] == base and sizes[0] < sizes[1] < sizes[3] and sizes[0] < sizes[2] < sizes[3]
     finally:
         B.cgx_destroy(ctx)
 

@@ -42,6 +42,18 @@ def test_small_anchor_tanh_masked_opacity(R):
     _anchor_fwd_bwd(R, wl, 17, (16, 16))
 
 
+@pytest.mark.parametrize("offsets,heads,seed", [(1, 1, 61), (0, 3, 62), (1, 3, 63)])
+def test_small_anchor_decoder_variants(R, offsets, heads, seed):
+    """Decoder variants: decoded offsets (14 outputs per Gaussian), one MLP
+    per attribute group, and both (four heads)."""
+    print(f"case: small anchor offset_mode={offsets} decoder_heads={heads} seed {seed}", flush=True)
+    wl = scenes.make_small_anchor(seed, n_anchor=70, n_views=3,
+                                  sizes=((40, 32), (24, 36), (33, 17)), offset_mode=offsets,
+                                  decoder_heads=heads)
+    assert wl.scene.W1_bits.shape == (36, 32 * (heads + (offsets if heads > 1 else 0)))
+    _anchor_fwd_bwd(R, wl, seed, (16, 16))
+
+
 def _anchor_fwd_bwd(R, wl, seed, tile):
     rd = R.Renderer(0, tile)
     sc = R.scene_from(wl.scene)

@@ -56,7 +56,8 @@ def test_autograd_explicit(R):
 
 def _anchor_meta(sc):
     return dict(level=sc["level"], W1=sc["W1"], W2=sc["W2"], n_levels=sc["n_levels"],
-                d_max=sc["d_max"], opacity_act=sc["opacity_act"])
+                d_max=sc["d_max"], opacity_act=sc["opacity_act"], offset_mode=sc["offset_mode"],
+                decoder_heads=sc["decoder_heads"])
 
 
 def _anchor_leaves(sc):
@@ -66,14 +67,16 @@ def _anchor_leaves(sc):
     return leaves + [W1f, W2f]
 
 
-@pytest.mark.parametrize("act", [0, 1])
-def test_autograd_anchor(R, act):
-    print(f"case: autograd through RenderAnchor, opacity_act={act}", flush=True)
+@pytest.mark.parametrize("act,offsets,heads", [(0, 0, 1), (1, 0, 1), (1, 1, 3)])
+def test_autograd_anchor(R, act, offsets, heads):
+    print(f"case: autograd through RenderAnchor, opacity_act={act} offset_mode={offsets} "
+          f"decoder_heads={heads}", flush=True)
     wl = scenes.make_small_anchor(17 if act else 12, n_anchor=70, n_views=3,
-                                  sizes=((40, 32), (24, 36), (33, 17)), opacity_act=act)
+                                  sizes=((40, 32), (24, 36), (33, 17)), opacity_act=act,
+                                  offset_mode=offsets, decoder_heads=heads)
     rd = R.Renderer(0, (16, 16))
     sc = R.scene_from(wl.scene)
-    assert sc["opacity_act"] == act
+    assert (sc["opacity_act"], sc["offset_mode"], sc["decoder_heads"]) == (act, offsets, heads)
     leaves = _anchor_leaves(sc)
     outs = R.RenderAnchor.apply(rd, wl.views, _anchor_meta(sc), *leaves)
     r = pipeline.render_anchor(wl.scene, wl.views)

@@ -10,17 +10,28 @@ from synth import scenes
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replays_match_eager():
-    print("case: graph replay, small anchor scene", flush=True)
+@pytest.mark.parametrize("case", ["anchor", "explicit_ncc"])
+def test_graph_replays_match_eager(case):
+    """anchor: a small anchor scene; explicit_ncc: two view pairs with the
+    Eq. 10 term in the chain (its gradient plane is cleared by a kernel of
+    the graph on every replay)."""
+    print(f"case: graph replay, {case}", flush=True)
     from paper_2503_23044_amd import binding as B
     from paper_2503_23044_amd import render
-    wl = scenes.make_small_anchor(31, n_anchor=80, n_views=3, sizes=((40, 32), (24, 36), (33, 17)))
+    nt = None
+    if case == "anchor":
+        wl = scenes.make_small_anchor(31, n_anchor=80, n_views=3, sizes=((40, 32), (24, 36), (33, 17)))
+    else:
+        wl = scenes.make_view_pairs(25)
+        c = torch.as_tensor(scenes.patch_centres(26, wl.views, 48), dtype=torch.int32, device="cuda")
+        nt = dict(centres=c, n_patch=int(c.shape[1]), weight=0.5)
     rd = render.Renderer(0, (16, 16))
     sc = render.scene_from(wl.scene)
     cat = lambda xs: torch.as_tensor(np.concatenate([x.ravel() for x in xs]), device="cuda")  # noqa: E731
     tgt = dict(rgb=cat(wl.targets["rgb"]), depth=cat(wl.targets["depth"]), normal=cat(wl.targets["normal"]))
     loss = torch.zeros(1, device="cuda")
-    out, gr = rd.fwd_bwd_l1(wl.views, sc, tgt, (1.0, 1.0, 1.0), loss=loss)
+    out, gr = rd.fwd_bwd_l1(wl.views, sc, tgt, (1.0, 1.0, 1.0), loss=loss,
+                            ncc=None if nt is None else (nt["centres"], nt["weight"]))
     torch.cuda.synchronize()
     ref_out = {k: v.clone() for k, v in out.items()}
     ref_gr = {k: v.clone() for k, v in gr.items()}
@@ -28,7 +39,7 @@ def test_graph_replays_match_eager():
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g = B.cgx_graph_capture_fwd_bwd_l1(rd.ctx, wl.views, sc, rd.cap, rd.ws, tgt, (1.0, 1.0, 1.0),
-                                           out, gr, loss, side)
+                                           out, gr, loss, side, ncc=nt)
     side.synchronize()
     try:
         for rep in range(3):

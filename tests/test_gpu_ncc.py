@@ -172,3 +172,62 @@ def test_ncc_through_backward_matches_oracle():
     sr = rounding_sensitivity(r, og, wl.scene, keys, g0=ref)
     for k in keys:
         check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, dict(sens=sens[k], round=sr[k]))
+
+
+def test_ncc_fused_in_chain_matches_oracle():
+    """The fused chain with the Eq. 10 term: forward, then the L1 seeds and
+    the NCC gradient folded into one backward prologue; against the oracle's
+    L1 + NCC output gradients through its backward pass."""
+    print("case: fused chain forward -> L1 + NCC -> backward, 2 pairs x 48 patches", flush=True)
+    from paper_2503_23044_amd import render
+    from tests.parity import targets_at_ties, zero_ties
+    wl = scenes.make_view_pairs(23)
+    centres = scenes.patch_centres(24, wl.views, 48)
+    weight, w3 = 0.5, (1.0, 0.5, 0.25)
+    r = pipeline.render_explicit(wl.scene, wl.views)
+    _, _, info0 = _oracle_ncc(r, centres, weight)
+    tied = _tied_patches(r, centres) | info0["fragile"].reshape(-1, centres.shape[1])
+    print(f"  patches reading a near-tie pixel: {int(tied.sum())}/{tied.size}", flush=True)
+    assert tied.mean() < 0.2
+    c_eff = np.asarray(centres).reshape(tied.shape[0], -1, 2).copy()
+    c_eff[tied] = -100
+    rd = render.Renderer(0, (16, 16))
+    sc = render.scene_from(wl.scene)
+    out0 = rd.forward(wl.views, sc)
+    torch.cuda.synchronize()
+    compare_images(out0, r)
+    targets = targets_at_ties(out0, r, wl.targets)
+    cat = lambda xs: torch.as_tensor(np.concatenate([np.asarray(x).ravel() for x in xs]), device="cuda")  # noqa: E731
+    tgt = dict(rgb=cat(targets["rgb"]), depth=cat(targets["depth"]), normal=cat(targets["normal"]))
+    loss = torch.zeros(1, device="cuda")
+    out, gr = rd.fwd_bwd_l1(wl.views, sc, tgt, w3, loss=loss, ncc=(torch.as_tensor(c_eff), weight))
+    torch.cuda.synchronize()
+    for k in out:
+        assert torch.equal(out[k], out0[k]), k
+    c_flat = c_eff.reshape(np.asarray(centres).shape)
+
+    def fused_ref(scene, r=None):
+        r = r or pipeline.render_explicit(scene, wl.views)
+        L, og = pipeline.output_grads_l1(r, targets, w3)
+        og = zero_ties(r, og)
+        Ln, g_rgb, _ = _oracle_ncc(r, c_flat, weight)
+        for o, g in zip(og, g_rgb):
+            o["rgb"] = o["rgb"] + g
+        g, _ = pipeline.backward(r, og, scene)
+        return g, L + Ln, og
+
+    ref, L_ref, og = fused_ref(wl.scene, r)
+    assert abs(loss.item() - L_ref) <= 1e-4 * abs(L_ref), (loss.item(), L_ref)
+    keys = ("means", "scales", "quats", "opacity", "sh")
+    sens = None
+    for seed in (4321, 8765):
+        rng = np.random.default_rng(seed)
+        sc2 = copy.copy(wl.scene)
+        for k in keys:
+            setattr(sc2, k, _perturbed(getattr(wl.scene, k), rng))
+        g1, _, _ = fused_ref(sc2)
+        d = {k: np.abs(ref[k] - g1[k]) for k in keys}
+        sens = d if sens is None else {k: np.maximum(sens[k], d[k]) for k in d}
+    sr = rounding_sensitivity(r, og, wl.scene, keys, g0=ref)
+    for k in keys:
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, dict(sens=sens[k], round=sr[k]))

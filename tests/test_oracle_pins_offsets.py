@@ -107,3 +107,45 @@ def test_decoded_offsets_adjoint_matches_finite_differences():
             np.testing.assert_allclose(g[key][a, j], (lp - lm) / (2 * h), rtol=2e-5, atol=1e-6)
     np.testing.assert_array_equal(g["O"], 0.0)        # the table's offsets are unused
     assert n == d.O.shape[1]
+
+
+def test_decoded_offset_error_bound_holds_in_float32():
+    """The oracle's margin for a decoded offset's float32 error (mu_tol / l)
+    covers float32 evaluations of the decoder in two summation orders
+    (BLAS and strictly sequential) at least four times over, and is not
+    vacuous (within 2^8 of the largest error)."""
+    wl = scenes.make_small_anchor(61, n_anchor=70, n_views=3, sizes=((40, 32), (24, 36), (33, 17)),
+                                  offset_mode=1)
+    sc = wl.scene
+    rows, _ = anchors.select(sc, wl.views)
+    D = anchors.decode(sc, wl.views, rows)
+    n = sc.O.shape[1]
+    l = np.asarray(sc.l, np.float64)[rows[:, 1]]
+    bound = (D["mu_tol"].reshape(-1, n, 3) / l[:, None, :])
+    O64 = D["_O"]
+    f32 = np.float32
+    z0, W1, b1 = D["_z0"].astype(f32), D["_W1"].astype(f32), np.asarray(sc.b1, f32)
+    W2, b2 = D["_W2"].astype(f32), np.asarray(sc.b2, f32)
+    cols = (np.arange(n)[:, None] * 14 + 11 + np.arange(3)[None]).ravel()
+    z1 = np.maximum(z0 @ W1 + b1, f32(0))
+    O_blas = (z1 @ W2[:, cols] + b2[cols]).reshape(-1, n, 3)
+    # strictly sequential float32 accumulation (first 40 rows)
+    m = 40
+    z1s = np.zeros((m, 32), f32)
+    for j in range(32):
+        acc = np.full(m, b1[j], f32)
+        for i in range(36):
+            acc = f32(acc + z0[:m, i] * W1[i, j])
+        z1s[:, j] = np.maximum(acc, f32(0))
+    O_seq = np.zeros((m, cols.size), f32)
+    for q, c in enumerate(cols):
+        acc = np.full(m, b2[c], f32)
+        for j in range(32):
+            acc = f32(acc + z1s[:, j] * W2[j, c])
+        O_seq[:, q] = acc
+    O_seq = O_seq.reshape(m, n, 3)
+    worst = 0.0
+    for O32, sl in ((O_blas, slice(None)), (O_seq, slice(0, m))):
+        ratio = np.abs(O32.astype(np.float64) - O64[sl]) / bound[sl]
+        worst = max(worst, float(ratio.max()))
+    assert 2.0 ** -8 < worst <= 0.25, worst
