@@ -357,6 +357,10 @@ class Renderer:
     def debug(self):
         return B.cgx_debug_copy(self.ctx, self.ws)
 
+    def debug_splats(self):
+        """(splat records, gradient records) of the last chain, per slot."""
+        return B.cgx_debug_splats(self.ctx, self.ws)
+
 
 _EXPLICIT_KEYS = ("means", "scales", "quats", "opacity", "sh")
 

@@ -219,6 +219,72 @@ def compare_sorted(dbg, r, slot_to_view_gid, tiles=None):
     return n_checked, n_took, n_left
 
 
+def check_sort_properties(dbg, rec, views, tile, slot_view):
+    """The sort stage over every tile, from properties that hold at any
+    size (no oracle, nothing set aside): the pairs are in strictly
+    increasing (tile, depth bits, slot) order, the tile ranges delimit the
+    tile ids, each visible splat has exactly its tile count of pairs, all
+    with one depth key, each in the tile rectangle of its pixel box, and
+    only splats whose box spans at least 2 x 2 and at most 64 tiles (those
+    that carry a tile mask) have fewer pairs than their rectangle holds.
+    rec: the splat records of cgx_debug_splats; slot_view(slots) -> views.
+    Returns the number of pairs checked."""
+    tw, th = tile
+    gt = dbg["tile"].astype(np.int64)
+    zb = dbg["zbits"].astype(np.int64)
+    sl = dbg["slot"].astype(np.int64)
+    counts = dbg["counts"].astype(np.int64)
+    P = gt.size
+    if P > 1:
+        dt, dz, ds = np.diff(gt), np.diff(zb), np.diff(sl)
+        inc = (dt > 0) | ((dt == 0) & ((dz > 0) | ((dz == 0) & (ds > 0))))
+        bad = np.nonzero(~inc)[0]
+        assert bad.size == 0, f"pairs out of (tile, depth, slot) order at {bad[:5].tolist()}"
+    TX = np.array([-(-int(v.width) // tw) for v in views], np.int64)
+    TY = np.array([-(-int(v.height) // th) for v in views], np.int64)
+    tile_off = np.concatenate([[0], np.cumsum(TX * TY)])
+    n_tiles = int(tile_off[-1])
+    gr = dbg["ranges"].astype(np.int64)
+    assert gr.shape[0] == n_tiles
+    starts = np.searchsorted(gt, np.arange(n_tiles), side="left")
+    ends = np.searchsorted(gt, np.arange(n_tiles), side="right")
+    want = np.stack([np.where(ends > starts, starts, 0), np.where(ends > starts, ends, 0)], 1)
+    norm = np.where((gr[:, 1] > gr[:, 0])[:, None], gr, 0)
+    np.testing.assert_array_equal(norm, want, err_msg="tile ranges")
+    assert P == 0 or (gt[0] >= 0 and gt[-1] < n_tiles)
+    # per splat: the pair count and one depth key
+    np.testing.assert_array_equal(np.bincount(sl, minlength=counts.size)[:counts.size], counts,
+                                  err_msg="pairs per splat vs its tile count")
+    assert P == 0 or sl.max() < counts.size
+    order = np.argsort(sl, kind="stable")
+    s_sorted, z_sorted = sl[order], zb[order]
+    same = s_sorted[1:] == s_sorted[:-1]
+    assert np.all(z_sorted[1:][same] == z_sorted[:-1][same]), "a splat's pairs carry two depth keys"
+    # each pair in the tile rectangle of its splat's pixel box
+    v = np.asarray(slot_view(sl), np.int64)
+    bx, by = rec["bx"][sl].astype(np.int64), rec["by"][sl].astype(np.int64)
+    x0, x1, y0, y1 = bx & 0xFFFF, bx >> 16, by & 0xFFFF, by >> 16
+    local = gt - tile_off[v]
+    tx, ty = local % TX[v], local // TX[v]
+    inside = (local >= 0) & (local < TX[v] * TY[v]) & (tx >= x0 // tw) & (tx <= x1 // tw) \
+        & (ty >= y0 // th) & (ty <= y1 // th)
+    bad = np.nonzero(~inside)[0]
+    assert bad.size == 0, f"pairs outside their splat's tile rectangle at {bad[:5].tolist()}"
+    # fewer pairs than the rectangle only where a tile mask is carried
+    vis = np.nonzero(counts > 0)[0]
+    bxv, byv = rec["bx"][vis].astype(np.int64), rec["by"][vis].astype(np.int64)
+    nx = (bxv >> 16) // tw - (bxv & 0xFFFF) // tw + 1
+    ny = (byv >> 16) // th - (byv & 0xFFFF) // th + 1
+    masked = (nx > 1) & (ny > 1) & (nx * ny <= 64)
+    assert np.all(counts[vis] <= nx * ny), "more pairs than the rectangle"
+    full = ~masked
+    assert np.all(counts[vis][full] == (nx * ny)[full]), "unmasked splat without its full rectangle"
+    print(f"  sort stage, every tile: {P} pairs of {vis.size} splats in order, ranges, "
+          f"counts and rectangles consistent ({int(masked.sum())} splats with a tile mask)",
+          flush=True)
+    return P
+
+
 def compare_sort_explicit(dbg, r, N):
     """Explicit scenes: slot = view * N + Gaussian.  Returns (pairs checked,
     near-tie pairs the GPU took, near-tie pairs it left)."""

@@ -10,9 +10,9 @@ import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import (check_grad, compare_images, compare_sort_explicit,
-                          explicit_sensitivity, linear_grads, packed_grads, targets_at_ties,
-                          tie_fraction, zero_ties)
+from tests.parity import (check_grad, check_sort_properties, compare_images,
+                          compare_sort_explicit, explicit_sensitivity, linear_grads, packed_grads,
+                          targets_at_ties, tie_fraction, zero_ties)
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,9 @@ def test_c0_forward_and_sort(R):
     compare_images(out, r)
     dbg = rd.debug()
     n, took, left = compare_sort_explicit(dbg, r, wl.scene.n)
+    rec, _ = rd.debug_splats()
+    N = wl.scene.n
+    assert check_sort_properties(dbg, rec, wl.views, rd.tile, lambda s: s // N) == n
     # work counters (off by default): entries walked forward equal the
     # oracle's count over its own lists, up to the pixels of near ties and
     # the near-tie pairs the GPU took (each adds at most one entry to each of

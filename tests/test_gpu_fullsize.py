@@ -14,8 +14,9 @@ import torch
 
 from oracle import pipeline
 from synth import scenes
-from tests.parity import (anchor_sensitivity, check_grad, compare_images, compare_sorted,
-                          explicit_sensitivity, linear_grads, packed_grads, tie_fraction)
+from tests.parity import (anchor_sensitivity, check_grad, check_sort_properties, compare_images,
+                          compare_sorted, explicit_sensitivity, linear_grads, packed_grads,
+                          tie_fraction)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +49,9 @@ def test_c2_full_size_sampled_tiles():
     out = rd.forward(wl.views, sc)
     torch.cuda.synchronize()
     dbg = rd.debug()
+    rows_gpu = dbg["rows"].astype(np.int64)
+    rec, _ = rd.debug_splats()
+    assert check_sort_properties(dbg, rec, wl.views, (16, 16), lambda s: rows_gpu[s // 10, 0]) > 10**6
     layout = pipeline.ras.batch_layout(wl.views, (16, 16))
     keep = _sample_tiles(layout, 24, seed=2024)
     r = pipeline.render_anchor(wl.scene, wl.views, keep_tiles=keep)
@@ -115,6 +119,9 @@ def _anchor_view0_case(wl, rd, sc, out, n_tiles, seed, tile=(16, 16)):
     the output gradients vanish elsewhere)."""
     v0 = wl.views[0]
     dbg = rd.debug()
+    rows_all = dbg["rows"].astype(np.int64)
+    rec, _ = rd.debug_splats()
+    check_sort_properties(dbg, rec, wl.views, tile, lambda s: rows_all[s // 10, 0])
     layout = pipeline.ras.batch_layout([v0], tile)
     keep = _sample_tiles(layout, n_tiles, seed=seed)
     r = pipeline.render_anchor(wl.scene, [v0], tile=tile, keep_tiles=keep)

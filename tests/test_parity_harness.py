@@ -186,3 +186,56 @@ def test_check_grad_slack_budget():
     # without slack, one element off fails
     with pytest.raises(AssertionError):
         parity.check_grad("off", ref * (1 + 1e-3), ref, None, np.zeros(1000))
+
+
+def _prop_inputs(r, N):
+    """The oracle's own binning of C0 in the layout the sort-stage property
+    check reads from the library (pairs, ranges, per-slot counts, records
+    with the pixel box)."""
+    o = r.sorted["own_sorted"]
+    n_views = len(r.splats)
+    counts = np.zeros(n_views * N, np.int64)
+    rec = np.zeros(n_views * N, [("bx", "<u4"), ("by", "<u4")])
+    for v, S in enumerate(r.splats):
+        counts[v * N:(v + 1) * N] = np.where(S["valid"], S["count"], 0)
+        b = S["box"]
+        rec["bx"][v * N:(v + 1) * N] = (np.clip(b[:, 0], 0, None) | (np.clip(b[:, 1], 0, None) << 16))
+        rec["by"][v * N:(v + 1) * N] = (np.clip(b[:, 2], 0, None) | (np.clip(b[:, 3], 0, None) << 16))
+    dbg = dict(tile=o["gtile"].copy(), zbits=o["zbits"].astype(np.int64), slot=o["view"] * N + o["gid"],
+               ranges=o["ranges"].copy(), counts=counts)
+    return dbg, rec
+
+
+def test_sort_property_check(c0):
+    wl, r = c0
+    N = wl.scene.n
+    view = lambda s: s // N   # noqa: E731
+    dbg, rec = _prop_inputs(r, N)
+    assert parity.check_sort_properties(dbg, rec, wl.views, (16, 16), view) > 1000
+    # planted mistakes: two pairs of a tile swapped, a pair dropped, a depth
+    # key changed, a pair moved outside its splat's rectangle
+    gt, zb = dbg["tile"], dbg["zbits"]
+    i = int(np.nonzero((gt[:-1] == gt[1:]) & (zb[:-1] != zb[1:]))[0][0])
+    bad = {k: v.copy() for k, v in dbg.items()}
+    for k in ("zbits", "slot"):
+        bad[k][[i, i + 1]] = bad[k][[i + 1, i]]
+    with pytest.raises(AssertionError):
+        parity.check_sort_properties(bad, rec, wl.views, (16, 16), view)
+    bad = {k: v.copy() for k, v in dbg.items()}
+    bad["counts"][bad["slot"][i]] += 1
+    with pytest.raises(AssertionError):
+        parity.check_sort_properties(bad, rec, wl.views, (16, 16), view)
+    bad = {k: v.copy() for k, v in dbg.items()}
+    s = bad["slot"][i]
+    j = int(np.nonzero(bad["slot"] == s)[0][-1])
+    if j != i:
+        bad["zbits"][j] += 1
+    else:
+        bad["zbits"][i] += 1
+        bad["counts"][s] += 1      # (a lone pair: fail on the count instead)
+    with pytest.raises(AssertionError):
+        parity.check_sort_properties(bad, rec, wl.views, (16, 16), view)
+    bad_rec = rec.copy()
+    bad_rec["bx"][dbg["slot"][i]] = 0          # box shrunk to column 0
+    with pytest.raises(AssertionError):
+        parity.check_sort_properties(dbg, bad_rec, wl.views, (16, 16), view)
