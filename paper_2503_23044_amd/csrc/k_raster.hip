@@ -32,8 +32,8 @@ __device__ __forceinline__ int find_view(const ViewDev* views, int B, uint32_t t
   return v;
 }
 
-// box-test column of a finished pixel: left of every pixel box
-constexpr int kDoneX = -(1 << 20);
+// last-entry mark of a pixel that has not stopped
+constexpr uint32_t kNoStop = 0xFFFFFFFFu;
 
 // tile of this block in the launch order
 __device__ __forceinline__ uint32_t launch_tile(const RasterArgs& a) {
@@ -138,61 +138,96 @@ __device__ __forceinline__ SplatFwd fetch_record_fwd(const RasterArgs& a, uint32
   return load_const(reinterpret_cast<const SplatFwd*>(a.splats + (slot < a.n_slots ? slot : 0u)));
 }
 
+// Packed pixel coordinates, x | y << 16, and the box test on them: pixel
+// (x, y) lies in the box [lo, lo + wid] (per half) iff (xy - lo) mod 2^16 <=
+// wid in both halves, two packed 16-bit instructions and one compare.  A
+// finished pixel (saturated, or outside the image) holds kDoneXY, which no
+// box holds (boxes end below 65535).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t kDoneXY = 0xFFFFFFFFu;
+__device__ __forceinline__ bool in_box(uint32_t xy, uint32_t lo, uint32_t wid) {
+  const u16x2 t = __builtin_bit_cast(u16x2, xy) - __builtin_bit_cast(u16x2, lo);
+  const u16x2 m = __builtin_elementwise_max(t, __builtin_bit_cast(u16x2, wid));
+  return __builtin_bit_cast(uint32_t, m) == wid;
+}
+
+// Per-pixel state of the forward walk.
+template <int PPL>
+struct FwdPx {
+  float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
+  uint32_t xy[PPL];      // packed coordinates, kDoneXY once finished
+  uint32_t last[PPL];    // entries before the stop (set when the pixel stops)
+  uint32_t walked[PPL];  // counting variants: the stop entry
+  float xc[PPL], yc[PPL];
+};
+
+// One sub-block pass of one splat.  Every lane takes the same instructions
+// (no lane-divergent branch): a pixel the splat does not reach gets
+// alpha = 0, which leaves T (fma(-T, 0, T) = T) and every sum unchanged and
+// cannot stop it.  The transmittance stop is rare (once per pixel), so the
+// common path takes no select for it: a wave-uniform branch handles the
+// passes where a pixel stops (it then takes nothing of the splat and keeps
+// its T).
+template <bool STATS, int PPL>
+__device__ __forceinline__ bool fwd_pass(const SplatFwd& s, uint32_t lo, uint32_t wid,
+                                         uint32_t idx, int k, FwdPx<PPL>& P, uint32_t& evals) {
+  const float dx = s.u - P.xc[k];
+  const float dy = s.w - P.yc[k];
+  const float q = splat_q(s.pa, s.pb, s.pc, s.lno, dx, dy);
+  const bool in = in_box(P.xy[k], lo, wid);
+  if (STATS && in) ++evals;
+  const bool ok = in & splat_drawn(q, s.lno);
+  const float raw = __builtin_amdgcn_exp2f(q);
+  const float alpha = ok ? (raw < kAlphaMax ? raw : kAlphaMax) : 0.0f;
+  const float w0 = alpha * P.T[k];
+  const float Tn = __builtin_fmaf(-P.T[k], alpha, P.T[k]);
+  const bool stop = Tn < kTMin;
+  float w = w0;
+  P.T[k] = Tn;
+  bool any_stop = false;
+  if (__ballot(stop) != 0) {
+    // a stopping pixel keeps its transmittance before the splat (Tn + w0,
+    // within an ulp of it) and takes nothing
+    any_stop = true;
+    P.T[k] = stop ? Tn + w0 : Tn;
+    w = stop ? 0.0f : w0;
+    P.xy[k] = stop ? kDoneXY : P.xy[k];
+    P.last[k] = stop ? idx - 1 : P.last[k];
+    if (STATS) P.walked[k] = stop ? idx : P.walked[k];
+  }
+  P.C0[k] += w * s.cr;
+  P.C1[k] += w * s.cg;
+  P.C2[k] += w * s.cb;
+  P.D[k] += w * s.d;
+  P.N0[k] += w * s.nx;
+  P.N1[k] += w * s.ny;
+  P.N2[k] += w * s.nz;
+  return any_stop;
+}
+
 // Front-to-back compositing of one splat (list index idx, 1-based) into the
-// wave's pixels; live is the mask of sub-blocks with an unfinished pixel.
+// wave's pixels; live is the mask of sub-blocks with an unfinished pixel
+// (wave-uniform).
 template <int TW, int TH, bool STATS, int PPL = TW * TH / kWave>
 __device__ __forceinline__ void composite_fwd(const SplatFwd& s, uint32_t valid, uint32_t idx,
-                                              int ty, int X0, int Y0, int ly, uint32_t& live,
-                                              float (&T)[PPL],
-                                              float (&C0)[PPL], float (&C1)[PPL], float (&C2)[PPL],
-                                              float (&D)[PPL], float (&N0)[PPL], float (&N1)[PPL],
-                                              float (&N2)[PPL], uint32_t (&last)[PPL],
-                                              uint32_t (&walked)[PPL], int (&xb)[PPL],
-                                              const float (&xc)[PPL], const float (&yc)[PPL],
+                                              int X0, int Y0, uint32_t& live, FwdPx<PPL>& P,
                                               uint32_t& evals) {
   const Box b = splat_box(s);
   const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & live & valid;
   if (hit == 0) return;
+  const uint32_t lo = (s.bx & 0xFFFFu) | (s.by << 16);
+  const uint32_t wid = ((s.bx >> 16) | (s.by & 0xFFFF0000u)) - lo;
   bool stopped = false;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     if (!(hit & (1u << k))) continue;
-    const int x = xb[k], y = sub_y0<TW>(ty, TH, k) + ly;
-    const float dx = s.u - xc[k];
-    const float dy = s.w - yc[k];
-    const float q = splat_q(s.pa, s.pb, s.pc, s.lno, dx, dy);
-    // Every lane of a touched sub-block takes the same instructions (no
-    // lane-divergent branch, so no exec-mask bookkeeping on the scalar
-    // unit): a pixel the splat does not reach gets alpha = 0, which leaves
-    // T (fma(-T, 0, T) = T) and every sum unchanged and cannot stop it.
-    const bool in = (x >= b.xlo) & (x <= b.xhi) & (y >= b.ylo) & (y <= b.yhi);
-    if (STATS && in) ++evals;
-    const bool ok = in & splat_drawn(q, s.lno);
-    const float raw = __builtin_amdgcn_exp2f(q);
-    const float alpha = ok ? (raw < kAlphaMax ? raw : kAlphaMax) : 0.0f;
-    // a pixel that would fall below the transmittance floor stops without
-    // taking the splat
-    const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
-    const bool stop = Tn < kTMin;
-    if (STATS && stop) walked[k] = idx;
-    xb[k] = stop ? kDoneX : xb[k];
-    stopped = stopped | stop;
-    const float w = stop ? 0.0f : alpha * T[k];
-    C0[k] += w * s.cr;
-    C1[k] += w * s.cg;
-    C2[k] += w * s.cb;
-    D[k] += w * s.d;
-    N0[k] += w * s.nx;
-    N1[k] += w * s.ny;
-    N2[k] += w * s.nz;
-    T[k] = stop ? T[k] : Tn;
-    last[k] = (ok & !stop) ? idx : last[k];
+    stopped |= fwd_pass<STATS>(s, lo, wid, idx, k, P, evals);
   }
-  if (__ballot(stopped) != 0) {
+  if (stopped) {
     live = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
-      if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
+      if (__ballot(P.xy[k] != kDoneXY) != 0) live |= 1u << k;
   }
 }
 
@@ -209,23 +244,17 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   const int tx = local % V.TX, ty = local / V.TX;
   const int X0 = tx * TW, Y0 = ty * TH;
 
-  float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], N0[PPL], N1[PPL], N2[PPL];
-  uint32_t last[PPL], walked[PPL];
-  // box-test column of each pixel; a finished pixel (saturated, or outside
-  // the image) gets kDoneX, which every pixel box excludes, so one compare
-  // serves both tests.  The pixel centres used by the blend are separate.
-  int xb[PPL];
-  float xc[PPL], yc[PPL];
+  FwdPx<PPL> P;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    T[k] = 1.0f;
-    C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
-    last[k] = 0;
-    walked[k] = 0;
+    P.T[k] = 1.0f;
+    P.C0[k] = P.C1[k] = P.C2[k] = P.D[k] = P.N0[k] = P.N1[k] = P.N2[k] = 0.0f;
+    P.last[k] = kNoStop;
+    P.walked[k] = 0;
     const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
-    xb[k] = (x < V.W && y < V.H) ? x : kDoneX;
-    xc[k] = (float)x + 0.5f;
-    yc[k] = (float)y + 0.5f;
+    P.xy[k] = (x < V.W && y < V.H) ? ((uint32_t)x | ((uint32_t)y << 16)) : kDoneXY;
+    P.xc[k] = (float)x + 0.5f;
+    P.yc[k] = (float)y + 0.5f;
   }
   const uint2 rg = a.ranges[tile];
   const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
@@ -234,7 +263,7 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   uint32_t live = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k)
-    if (__ballot(xb[k] != kDoneX) != 0) live |= 1u << k;
+    if (__ballot(P.xy[k] != kDoneXY) != 0) live |= 1u << k;
 
   // Software pipeline over two record buffers: the record of list position
   // i + 1 and the slot of i + 2 are requested before splat i is
@@ -249,49 +278,51 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   for (uint32_t i = start; i < end && live != 0; i += 2) {
     sb = fetch_record_fwd(a, slot_b);
     const uint32_t next_a = list_slot(a, i + 2, end);
-    composite_fwd<TW, TH, STATS>(sa, slot_mask(a, slot_a), i - start + 1, ty, X0, Y0, ly, live, T,
-                                 C0, C1, C2, D, N0, N1, N2, last, walked, xb, xc, yc, evals);
+    composite_fwd<TW, TH, STATS>(sa, slot_mask(a, slot_a), i - start + 1, X0, Y0, live, P, evals);
     if (i + 1 >= end || live == 0) break;
     slot_a = next_a;
     sa = fetch_record_fwd(a, slot_a);
     const uint32_t next_b = list_slot(a, i + 3, end);
-    composite_fwd<TW, TH, STATS>(sb, slot_mask(a, slot_b), i - start + 2, ty, X0, Y0, ly, live, T,
-                                 C0, C1, C2, D, N0, N1, N2, last, walked, xb, xc, yc, evals);
+    composite_fwd<TW, TH, STATS>(sb, slot_mask(a, slot_b), i - start + 2, X0, Y0, live, P, evals);
     slot_b = next_b;
   }
 
   const uint32_t HW = (uint32_t)V.W * (uint32_t)V.H;
   const size_t pv = (size_t)V.pix_off;
+  const uint32_t n = end - start;
   uint32_t walked_sum = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
     if (!(x < V.W && y < V.H)) continue;
-    if (STATS) walked_sum += walked[k] == 0 ? end - start : walked[k];
+    if (STATS) walked_sum += P.walked[k] == 0 ? n : P.walked[k];
     const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
-    const float r = C0[k] + T[k] * V.bg[0];
-    const float g = C1[k] + T[k] * V.bg[1];
-    const float bl = C2[k] + T[k] * V.bg[2];
-    const float acc = 1.0f - T[k];
+    const float T = P.T[k];
+    const float r = P.C0[k] + T * V.bg[0];
+    const float g = P.C1[k] + T * V.bg[1];
+    const float bl = P.C2[k] + T * V.bg[2];
+    const float acc = 1.0f - T;
     const float rx = ((float)x + 0.5f - V.cx) / V.fx;
     const float ry = ((float)y + 0.5f - V.cy) / V.fy;
-    const float sd = -(N0[k] * rx + N1[k] * ry + N2[k]);
-    const float dh = sd > kDhatGuard * acc ? D[k] / sd : 0.0f;
+    const float sd = -(P.N0[k] * rx + P.N1[k] * ry + P.N2[k]);
+    const float dh = sd > kDhatGuard * acc ? P.D[k] / sd : 0.0f;
     if (a.rgb) {
       a.rgb[3 * pv + p] = r;
       a.rgb[3 * pv + HW + p] = g;
       a.rgb[3 * pv + 2 * HW + p] = bl;
     }
     if (a.depth) a.depth[pv + p] = dh;
-    if (a.plane_d) a.plane_d[pv + p] = D[k];
+    if (a.plane_d) a.plane_d[pv + p] = P.D[k];
     if (a.normal) {
-      a.normal[3 * pv + p] = N0[k];
-      a.normal[3 * pv + HW + p] = N1[k];
-      a.normal[3 * pv + 2 * HW + p] = N2[k];
+      a.normal[3 * pv + p] = P.N0[k];
+      a.normal[3 * pv + HW + p] = P.N1[k];
+      a.normal[3 * pv + 2 * HW + p] = P.N2[k];
     }
     if (a.alpha) a.alpha[pv + p] = acc;
-    a.px_T[pv + p] = T[k];
-    a.px_last[pv + p] = last[k];
+    a.px_T[pv + p] = T;
+    // entries the backward walks for this pixel: those before its stop, or
+    // the whole list
+    a.px_last[pv + p] = P.last[k] == kNoStop ? n : P.last[k];
   }
   if (STATS) {
     // list entries walked and opacity evaluations, one atomic per wave
