@@ -185,12 +185,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(
       const bool valid = idx < b1;
       const uint32_t k = rkey[it];
       const int d = (int)((k >> shift) & (R - 1));
+      // lanes with the same digit: per bit, the ballot of the lanes that
+      // have it set, complemented on the scalar unit, and each lane keeps
+      // m or ~m as its own bit says (sel = 0 or -1: ~m ^ sel)
       uint64_t peers = __ballot(valid);
 #pragma unroll
       for (int b = 0; b < BITS; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t m = __ballot(valid && bit);
-        peers &= bit ? m : ~m;
+        const int32_t sel = ((int32_t)((uint32_t)d << (31 - b))) >> 31;
+        const uint64_t nm = ~__ballot(sel != 0);
+        const uint32_t lo = (uint32_t)nm ^ (uint32_t)sel;
+        const uint32_t hi = (uint32_t)(nm >> 32) ^ (uint32_t)sel;
+        peers &= ((uint64_t)hi << 32) | lo;
       }
       const uint32_t prev = valid ? wave_cnt[wave][d] : 0u;
       const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
