@@ -291,39 +291,58 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   const size_t pv = (size_t)V.pix_off;
   const uint32_t n = end - start;
   uint32_t walked_sum = 0;
+  // the 11 per-pixel outputs of the wave's pixels
+  float o_r[PPL], o_g[PPL], o_b[PPL], o_dh[PPL], o_acc[PPL], o_last[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int x = sub_x0<TW>(tx, k) + lx, y = sub_y0<TW>(ty, TH, k) + ly;
-    if (!(x < V.W && y < V.H)) continue;
-    if (STATS) walked_sum += P.walked[k] == 0 ? n : P.walked[k];
-    const uint32_t p = (uint32_t)y * (uint32_t)V.W + (uint32_t)x;
+    const bool inside = x < V.W && y < V.H;
+    if (STATS && inside) walked_sum += P.walked[k] == 0 ? n : P.walked[k];
     const float T = P.T[k];
-    const float r = P.C0[k] + T * V.bg[0];
-    const float g = P.C1[k] + T * V.bg[1];
-    const float bl = P.C2[k] + T * V.bg[2];
-    const float acc = 1.0f - T;
+    o_r[k] = P.C0[k] + T * V.bg[0];
+    o_g[k] = P.C1[k] + T * V.bg[1];
+    o_b[k] = P.C2[k] + T * V.bg[2];
+    o_acc[k] = 1.0f - T;
     const float rx = ((float)x + 0.5f - V.cx) / V.fx;
     const float ry = ((float)y + 0.5f - V.cy) / V.fy;
     const float sd = -(P.N0[k] * rx + P.N1[k] * ry + P.N2[k]);
-    const float dh = sd > kDhatGuard * acc ? P.D[k] / sd : 0.0f;
-    if (a.rgb) {
-      a.rgb[3 * pv + p] = r;
-      a.rgb[3 * pv + HW + p] = g;
-      a.rgb[3 * pv + 2 * HW + p] = bl;
-    }
-    if (a.depth) a.depth[pv + p] = dh;
-    if (a.plane_d) a.plane_d[pv + p] = P.D[k];
-    if (a.normal) {
-      a.normal[3 * pv + p] = P.N0[k];
-      a.normal[3 * pv + HW + p] = P.N1[k];
-      a.normal[3 * pv + 2 * HW + p] = P.N2[k];
-    }
-    if (a.alpha) a.alpha[pv + p] = acc;
-    a.px_T[pv + p] = T;
+    o_dh[k] = sd > kDhatGuard * o_acc[k] ? P.D[k] / sd : 0.0f;
     // entries the backward walks for this pixel: those before its stop, or
     // the whole list
-    a.px_last[pv + p] = P.last[k] == kNoStop ? n : P.last[k];
+    o_last[k] = __uint_as_float(P.last[k] == kNoStop ? n : P.last[k]);
   }
+  // Written one plane at a time through LDS: a pass covers an 8 x 8
+  // sub-block, so a direct store writes 32-byte row pieces and a tile row
+  // reaches HBM in two halves; staged, each store writes whole tile rows.
+  __shared__ float s_plane[TW * TH];
+  auto emit = [&](float* dst, const float (&val)[PPL]) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k)
+      s_plane[((k / (TW / 8)) * 8 + ly) * TW + (k % (TW / 8)) * 8 + lx] = val[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int e = j * kWave + lane;
+      const int x = X0 + e % TW, y = Y0 + e / TW;
+      if (x < V.W && y < V.H) dst[(uint32_t)y * (uint32_t)V.W + (uint32_t)x] = s_plane[e];
+    }
+    __syncthreads();
+  };
+  if (a.rgb) {
+    emit(a.rgb + 3 * pv, o_r);
+    emit(a.rgb + 3 * pv + HW, o_g);
+    emit(a.rgb + 3 * pv + 2 * HW, o_b);
+  }
+  if (a.depth) emit(a.depth + pv, o_dh);
+  if (a.plane_d) emit(a.plane_d + pv, P.D);
+  if (a.normal) {
+    emit(a.normal + 3 * pv, P.N0);
+    emit(a.normal + 3 * pv + HW, P.N1);
+    emit(a.normal + 3 * pv + 2 * HW, P.N2);
+  }
+  if (a.alpha) emit(a.alpha + pv, o_acc);
+  emit(a.px_T + pv, P.T);
+  emit(reinterpret_cast<float*>(a.px_last) + pv, o_last);
   if (STATS) {
     // list entries walked and opacity evaluations, one atomic per wave
     for (int o = 32; o > 0; o >>= 1) {

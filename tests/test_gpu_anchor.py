@@ -118,3 +118,30 @@ def test_anchor_capacity_overflow_reported(R):
     out = rd.forward(wl.views, sc)
     torch.cuda.synchronize()
     compare_images(out, r)
+
+
+@pytest.mark.parametrize("seed", [46, 50])
+def test_tiny_anchor_gradients_without_tie_allowance(R, seed):
+    """A tiny anchor scene with no near-tie decision at all: every gradient,
+    the decoder's weights and biases included, is compared element by
+    element with no allowance for ties (zero output gradients nowhere, no
+    near-tie share); the only slack is each element's own conditioning (a
+    sum whose terms cancel, e.g. first-layer weights)."""
+    print(f"case: tiny anchor scene seed {seed}, no tie allowance", flush=True)
+    wl = scenes.make_small_anchor(seed, n_anchor=16)
+    r = pipeline.render_anchor(wl.scene, wl.views)
+    assert tie_fraction(r) == 0.0 and not any(img["frag_grad"].any() for img in r.images)
+    rd = R.Renderer(0, (16, 16))
+    sc = R.scene_from(wl.scene)
+    out = rd.forward(wl.views, sc)
+    torch.cuda.synchronize()
+    compare_sort_anchor(rd.debug(), r, 10)
+    compare_images(out, r)
+    og = linear_grads(r, np.random.default_rng(seed))
+    ref, _ = pipeline.backward(r, og, wl.scene)
+    gr = rd.backward(wl.views, sc, out, packed_grads(og))
+    torch.cuda.synchronize()
+    delta = anchor_sensitivity(wl.scene, wl.views, og, r0=r)
+    for k in ("x", "l", "O", "F", "W1", "b1", "W2", "b2"):
+        assert not np.any(delta[k]["frag"]), k
+        check_grad("d_" + k, gr[k].cpu().numpy(), ref[k], None, delta[k])

@@ -239,3 +239,22 @@ def test_sort_property_check(c0):
     bad_rec["bx"][dbg["slot"][i]] = 0          # box shrunk to column 0
     with pytest.raises(AssertionError):
         parity.check_sort_properties(dbg, bad_rec, wl.views, (16, 16), view)
+
+
+def test_magnitude_mode_bounds_the_signed_sums(c0, anchor11):
+    """composite_backward(magnitude=True) takes the same sums over |terms|:
+    every element is at least the absolute value of the signed one, and
+    strictly more where terms cancel."""
+    from oracle import raster as ras
+    for wl, r in (c0, anchor11):
+        og = parity.linear_grads(r, np.random.default_rng(9))
+        S = ras.composite_backward(r.splats, r.views, r.images, og, r.varr)
+        M = ras.composite_backward(r.splats, r.views, r.images, og, r.varr, magnitude=True)
+        for s_v, m_v in zip(S, M):
+            for k in ("mean2d", "conic", "opacity", "rgb", "d", "normal"):
+                a, b = np.abs(np.asarray(s_v[k])), np.asarray(m_v[k])
+                assert np.all(b >= a * (1 - 1e-12) - 1e-300), k
+                assert np.all(b >= 0), k
+        # some element does cancel: the magnitude strictly exceeds it
+        assert any(np.any(np.asarray(m_v["mean2d"]) > np.abs(np.asarray(s_v["mean2d"])) * 1.01)
+                   for s_v, m_v in zip(S, M))
