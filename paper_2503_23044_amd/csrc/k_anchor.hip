@@ -11,7 +11,16 @@ constexpr int kIn = CGX_MLP_IN;          // 36
 constexpr int kHead = CGX_MLP_HIDDEN;    // hidden units per decoder head
 constexpr int kNOff = 10;                // Gaussians per anchor (compiled in)
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-constexpr int kRedBlocks = 512;  // weight-gradient partials (one per reduction block)
+constexpr int kRedBlocks = 2048;  // weight-gradient partials at most (one per reduction block)
+
+// reduction blocks for a row capacity: 512 up to 1 M rows (each block's
+// chunk is short, and fewer partials keep the final sum short), then one
+// per 2,048 rows up to kRedBlocks (at 4 M rows a block of 512 walked 280
+// k-steps one after another)
+static uint32_t red_blocks(uint32_t max_rows) {
+  const uint32_t b = (max_rows + 2047) / 2048;
+  return b < 512 ? 512 : b > (uint32_t)kRedBlocks ? (uint32_t)kRedBlocks : b;
+}
 
 // Decoder shape (Sec. 3.2, Eq. 4): H heads of 32 hidden units and G outputs
 // per Gaussian (11: opacity, rgb, scale, quaternion; 14: and the decoded
@@ -272,15 +281,27 @@ __device__ __forceinline__ void decoder_input(const ViewDev& V, const cgx_anchor
   d.z0[35] = d.dist / sc.d_max;
 }
 
-// decoder weights for the adjoint, float32 in LDS; rows padded to an odd
-// stride so that the 32 lanes of a row, which read 32 different weight rows
-// at the same column, hit 32 different banks
+// B operands of the adjoint's per-row products on MFMA, bf16 bit patterns
+// (exact: the weights are bfloat16):
+//   w2a, per head h: (hidden unit j, column k of the head) = W2[j][col0(h) + k],
+//       k padded with zeros to a multiple of 32;
+//   w1a: (input i, hidden unit J) = W1[i][J], i padded with zeros to 48.
+// Rows are 8 elements longer than used (16 bytes), which spreads the 16
+// rows one 16-byte fragment load reads over distinct LDS banks.
+constexpr int kAdjIn = 48;               // decoder inputs (36) padded to three 16-column tiles
 template <class D>
-struct DecWT {
-  static constexpr int kW1s = D::kHid + 1;
-  static constexpr int kW2s = D::kOut + 1;
-  float W1[kIn * kW1s];
-  float W2[kHead * kW2s];
+struct DecAdj {
+  static constexpr int kA2(int h) { return (D::ncols(h) + 31) / 32 * 32; }
+  static constexpr int kS2(int h) { return kA2(h) + 8; }
+  static constexpr int off2(int h) {
+    int o = 0;
+    for (int i = 0; i < h; ++i) o += kHead * kS2(i);
+    return o;
+  }
+  static constexpr int kW2n = off2(D::kHeads);
+  static constexpr int kS1 = D::kHid + 8;
+  uint16_t w2a[kW2n];
+  uint16_t w1a[kAdjIn * kS1];
 };
 
 // block-wide copy of a weight image laid out in global memory by
@@ -535,11 +556,11 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
 //   transposed to (tile column, k) with its 32 rows once per split term,
 //   each head's columns padded to whole tiles with zeros, the biases (b2
 //   padded likewise);
-//   adjoint: W1 and W2 as float32 rows at odd strides.
+//   adjoint: the DecAdj operands (W2 per head as (j, k), W1 as (i, J)).
 template <class D>
 constexpr int prep_items() {
-  return D::kHid * kK1 + D::kN2 * kK2 + D::kHid + D::kN2 + kIn * DecWT<D>::kW1s +
-         kHead * DecWT<D>::kW2s;
+  return D::kHid * kK1 + D::kN2 * kK2 + D::kHid + D::kN2 + DecAdj<D>::kW2n +
+         kAdjIn * DecAdj<D>::kS1;
 }
 
 // the output column of tile column p, or -1 for padding
@@ -552,9 +573,9 @@ __device__ __forceinline__ int tile_column(int p) {
 
 template <class D>
 __global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB<D>* __restrict__ wb,
-                                                      DecWT<D>* __restrict__ wt) {
+                                                      DecAdj<D>* __restrict__ wa) {
   constexpr int kHid = D::kHid, kOut = D::kOut;
-  constexpr int kW1s = DecWT<D>::kW1s, kW2s = DecWT<D>::kW2s;
+  using A = DecAdj<D>;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < prep_items<D>(); i += gridDim.x * blockDim.x) {
     int j = i;
     if (j < kHid * kK1) {
@@ -584,14 +605,29 @@ __global__ __launch_bounds__(256) void k_prep_weights(cgx_anchor_scene sc, DecWB
       continue;
     }
     j -= D::kN2;
-    if (j < kIn * kW1s) {
-      const int r = j / kW1s, c = j % kW1s;
-      wt->W1[j] = c < kHid ? bf16_to_f32(sc.W1[r * kHid + c]) : 0.0f;
+    if (j < A::kW2n) {
+      int h = 0;
+#pragma unroll
+      for (int q = 1; q < D::kHeads; ++q) h += j >= A::off2(q);
+      int o = j;
+#pragma unroll
+      for (int q = 0; q < D::kHeads; ++q)
+        if (q == h) o = j - A::off2(q);
+      int ncols = 0, col0 = 0, s2 = 1;
+#pragma unroll
+      for (int q = 0; q < D::kHeads; ++q)
+        if (q == h) {
+          s2 = A::kS2(q);
+          ncols = D::ncols(q);
+          col0 = D::col0(q);
+        }
+      const int r = o / s2, k = o - r * s2;
+      wa->w2a[j] = k < ncols ? sc.W2[r * kOut + col0 + k] : (uint16_t)0;
       continue;
     }
-    j -= kIn * kW1s;
-    const int r = j / kW2s, c = j % kW2s;
-    wt->W2[j] = c < kOut ? bf16_to_f32(sc.W2[r * kOut + c]) : 0.0f;
+    j -= A::kW2n;
+    const int ri = j / A::kS1, c = j % A::kS1;
+    wa->w1a[j] = (ri < kIn && c < kHid) ? sc.W1[ri * kHid + c] : (uint16_t)0;
   }
 }
 
@@ -602,8 +638,8 @@ static DecWB<D>* decode_weights(float* scratch, uint32_t max_rows) {
                                      (size_t)kRedBlocks * D::kWGrad);
 }
 template <class D>
-static DecWT<D>* adjoint_weights(float* scratch, uint32_t max_rows) {
-  return reinterpret_cast<DecWT<D>*>(reinterpret_cast<char*>(decode_weights<D>(scratch, max_rows)) +
+static DecAdj<D>* adjoint_weights(float* scratch, uint32_t max_rows) {
+  return reinterpret_cast<DecAdj<D>*>(reinterpret_cast<char*>(decode_weights<D>(scratch, max_rows)) +
                                      sizeof(DecWB<D>));
 }
 
@@ -696,100 +732,6 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
     // decoded offset: mu = x + O l, so dO = d(mu) l
 #pragma unroll
     for (int c = 0; c < 3; ++c) dz2[D::zcol(k, CGX_GAUSS_OUT + c)] = dmu[c] * L[c];
-  }
-}
-
-// ---------------------------------------------------------------------
-// a10, part 2: 32 threads per row, 8 rows at a time, 32 rows per block
-// (one weight staging).  Thread j of a row forms, for each head h,
-// dz1[32h + j] = (dz2_h W2_h^T)[j] * [z1[32h + j] > 0] from the row's dz2
-// staged in LDS (head h's columns only), then dz0[j] = (dz1 W1^T)[j] for
-// the 32 features (the row's term of dF) and, in threads 0..3, the four
-// direction / distance inputs, which one thread takes back to the row's
-// term of dx.  z0 and dz1 are kept for the weight-gradient reduction.
-// ---------------------------------------------------------------------
-constexpr int kMlpRows = 8;      // rows in flight per block (32 threads each)
-constexpr int kMlpGroups = 4;    // row groups per block, sharing one weight staging
-
-template <class D>
-__global__ __launch_bounds__(256) void k_decode_bwd_mlp(const ViewDev* __restrict__ views,
-                                                        cgx_anchor_scene sc,
-                                                        const int2* __restrict__ rows,
-                                                        const Counters* ctr,
-                                                        const DecWT<D>* __restrict__ wimg,
-                                                        float* __restrict__ scratch) {
-  constexpr int kHid = D::kHid, kOut = D::kOut;
-  constexpr int kW1s = DecWT<D>::kW1s, kW2s = DecWT<D>::kW2s;
-  __shared__ DecWT<D> w;
-  __shared__ float s_dz2[kMlpRows][kOut];
-  __shared__ float s_dz1[kMlpRows][kHid];
-  __shared__ float s_tail[kMlpRows][4];
-  const uint32_t n_rows = ctr->n_rows;
-  const uint32_t rb = blockIdx.x * (kMlpRows * kMlpGroups);
-  if (rb >= n_rows) return;                    // the grid covers the row capacity
-  copy_weights(w, wimg);
-  const int rl = threadIdx.x / kHead, j = threadIdx.x % kHead;
-  for (int grp = 0; grp < kMlpGroups; ++grp) {
-    const uint32_t r0 = rb + grp * kMlpRows;
-    if (r0 >= n_rows) break;                   // uniform over the block
-    for (int e = threadIdx.x; e < kMlpRows * kOut; e += blockDim.x) {
-      const int rr = e / kOut, c = e - rr * kOut;
-      s_dz2[rr][c] = r0 + rr < n_rows
-                         ? scratch[(size_t)(r0 + rr) * D::kRowScratch + D::kDZ2 + c]
-                         : 0.0f;
-    }
-    __syncthreads();
-    const uint32_t r = r0 + rl;
-    const bool live = r < n_rows;
-    float* rs = scratch + (size_t)r * D::kRowScratch;
-    if (live) {
-#pragma unroll
-      for (int h = 0; h < D::kHeads; ++h) {
-        float acc = 0.0f;
-        for (int c = D::col0(h); c < D::col0(h) + D::ncols(h); ++c)
-          acc += s_dz2[rl][c] * w.W2[j * kW2s + c];
-        const int J = kHead * h + j;
-        acc = rs[D::kZ1 + J] > 0.0f ? acc : 0.0f;
-        s_dz1[rl][J] = acc;
-        rs[D::kDZ1 + J] = acc;
-      }
-    }
-    __syncthreads();
-    uint32_t a = 0;
-    if (live) {
-      a = (uint32_t)rows[r].y;
-      rs[j] = bf16_round(sc.F[(size_t)a * CGX_FEAT_DIM + j]);    // z0 feature part
-      float acc = 0.0f;
-#pragma unroll 8
-      for (int k = 0; k < kHid; ++k) acc += s_dz1[rl][k] * w.W1[j * kW1s + k];
-      rs[D::kDF + j] = acc;
-      if (j < 4) {
-        float t = 0.0f;
-#pragma unroll 8
-        for (int k = 0; k < kHid; ++k) t += s_dz1[rl][k] * w.W1[(CGX_FEAT_DIM + j) * kW1s + k];
-        s_tail[rl][j] = t;
-      }
-    }
-    __syncthreads();
-    if (live && j == 0) {
-      const ViewDev& V = views[rows[r].x];
-      float dir[3], dist;
-      decoder_dir(V, sc, a, dir, dist);
-      rs[CGX_FEAT_DIM + 0] = dir[0];
-      rs[CGX_FEAT_DIM + 1] = dir[1];
-      rs[CGX_FEAT_DIM + 2] = dir[2];
-      rs[CGX_FEAT_DIM + 3] = dist / sc.d_max;
-      // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
-      const float* dz0 = s_tail[rl];
-      const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
-      const float il = 1.0f / dist;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
-        rs[D::kDX + c] = -ddelta;
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -957,6 +899,208 @@ __device__ __forceinline__ f32x4_t mfma_split6(const Split8& A, const Split8& B,
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[2], B.t[0], acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[1], B.t[1], acc, 0, 0, 0);
   return acc;
+}
+
+// ---------------------------------------------------------------------
+// a10, part 2: the per-row products of the decoder adjoint on MFMA.  A wave
+// takes 64 rows (four 16-row tiles) and, head by head,
+//   dz1_h = (dz2_h W2_h^T) * [z1_h > 0]: A = the rows' dz2 over the head's
+//           columns (K padded to 32), B = W2_h as (j, k), 2 column tiles;
+//   dz0  += dz1_h W1_h^T: A = dz1_h (K = 32, one k-step), B = W1 as
+//           (i, J), 3 column tiles (the 36 inputs padded to 48).
+// The A operands are float32 carried as three bf16 terms h + m + l (as in
+// the forward decode), B is exact, so each product costs three MFMAs and
+// keeps float32 accuracy.  dz2 comes straight from the row scratch; dz1_h
+// goes through LDS (the C layout of the first product is not the A layout
+// of the second) and to the row scratch for the weight gradients.  Then
+// the first 32 columns of dz0 are the row's term of dF; the last four (the
+// direction / distance inputs) are taken back to the row's term of dx by
+// one lane per row, which also writes the row's z0 (bf16 features,
+// direction, distance) for the weight gradients.  Blocks of kAdjWaves waves
+// share one weight staging and loop over row groups.
+// ---------------------------------------------------------------------
+constexpr int kAdjWaves = 4;
+constexpr int kAdjBlocks = 1024;         // grid bound (blocks loop over row groups)
+
+template <class D>
+struct AdjLds {
+  DecAdj<D> w;
+  float dz1[kAdjWaves][64][kHead + 4];   // one head's dz1 of the wave's rows
+  float tail[kAdjWaves][64][4];          // dz0 of the direction / distance inputs
+  uint32_t anchor[kAdjWaves][64];
+};
+
+// 8 float32 -> three bf16x8 terms h, m, l
+__device__ __forceinline__ Split8 split8v(const float (&v)[8]) {
+  Split8 o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint16_t h, m, l;
+    split3(v[i], h, m, l);
+    o.t[0][i] = __builtin_bit_cast(__bf16, h);
+    o.t[1][i] = __builtin_bit_cast(__bf16, m);
+    o.t[2][i] = __builtin_bit_cast(__bf16, l);
+  }
+  return o;
+}
+
+// A (three terms) times an exact B
+__device__ __forceinline__ f32x4_t mfma_split3(const Split8& A, const bf16x8_t& B, f32x4_t acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[0], B, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[1], B, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.t[2], B, acc, 0, 0, 0);
+  return acc;
+}
+
+template <class D>
+__global__ __launch_bounds__(kAdjWaves * kWave) void k_decode_bwd_mlp(
+    const ViewDev* __restrict__ views, cgx_anchor_scene sc, const int2* __restrict__ rows,
+    const Counters* ctr, const DecAdj<D>* __restrict__ wimg, float* __restrict__ scratch) {
+  using A = DecAdj<D>;
+  constexpr int kRS = D::kRowScratch;
+  __shared__ AdjLds<D> L;
+  const uint32_t n_rows = ctr->n_rows;
+  if ((uint64_t)blockIdx.x * kAdjWaves * 64 >= n_rows) return;   // uniform over the block
+  copy_weights(L.w, wimg);
+  __syncthreads();
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  float (*s_dz1)[kHead + 4] = L.dz1[wave];
+  float (*s_tail)[4] = L.tail[wave];
+  uint32_t* s_anchor = L.anchor[wave];
+
+  for (uint64_t grp = (uint64_t)blockIdx.x * kAdjWaves + wave; grp * 64 < n_rows;
+       grp += (uint64_t)gridDim.x * kAdjWaves) {
+    const uint32_t r0 = (uint32_t)(grp * 64);
+    {
+      const uint32_t r = r0 + lane;
+      s_anchor[lane] = r < n_rows ? (uint32_t)rows[r].y : 0u;
+    }
+    f32x4_t acc0[4][3];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int u = 0; u < 3; ++u) acc0[g][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int h = 0; h < D::kHeads; ++h) {
+      const int ncols = D::ncols(h);
+      // dz1_h before the mask
+      f32x4_t a1[4][2];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) a1[g][0] = a1[g][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < A::kA2(h) / 32; ++st) {
+        const int k0 = 32 * st + kq;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const uint32_t row = r0 + 16 * g + col;
+          const float* src = scratch + (size_t)row * kRS + D::kDZ2 + D::col0(h);
+          float v[8];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            // the head's column count is even: a pair is valid or padding
+            const bool ok = row < n_rows && k0 + 2 * p < ncols;
+            const float2 x = ok ? *reinterpret_cast<const float2*>(src + k0 + 2 * p) : float2{0.f, 0.f};
+            v[2 * p] = x.x;
+            v[2 * p + 1] = x.y;
+          }
+          const Split8 av = split8v(v);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const bf16x8_t bv = load8(&L.w.w2a[A::off2(h) + (16 * t + col) * A::kS2(h) + k0]);
+            a1[g][t] = mfma_split3(av, bv, a1[g][t]);
+          }
+        }
+      }
+      // mask by z1 > 0, stage in LDS (row, j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rr = 16 * g + rq + i;
+            const int j = 16 * t + col;
+            const uint32_t row = r0 + rr;
+            const float z1 = row < n_rows ? scratch[(size_t)row * kRS + D::kZ1 + kHead * h + j] : 0.0f;
+            s_dz1[rr][j] = z1 > 0.0f ? a1[g][t][i] : 0.0f;
+          }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // dz1_h to the row scratch: element e = lane + 64 q is (row e / 32, j e % 32)
+#pragma unroll 8
+      for (int q = 0; q < 32; ++q) {
+        const int rr = (lane >> 5) + 2 * q, j = lane & 31;
+        const uint32_t row = r0 + rr;
+        if (row < n_rows) scratch[(size_t)row * kRS + D::kDZ1 + kHead * h + j] = s_dz1[rr][j];
+      }
+      // dz0 += dz1_h W1_h^T
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const Split8 av = split8(&s_dz1[16 * g + col][kq]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const bf16x8_t bv = load8(&L.w.w1a[(16 * u + col) * A::kS1 + kHead * h + kq]);
+          acc0[g][u] = mfma_split3(av, bv, acc0[g][u]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // dz0: columns 0..31 are the row's term of dF, 32..35 the tail
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = 16 * g + rq + i;
+        const uint32_t row = r0 + rr;
+        if (row < n_rows) {
+          scratch[(size_t)row * kRS + D::kDF + col] = acc0[g][0][i];
+          scratch[(size_t)row * kRS + D::kDF + 16 + col] = acc0[g][1][i];
+        }
+        if (col < 4) s_tail[rr][col] = acc0[g][2][i];
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // z0 feature part, bf16(F): element e = lane + 64 q is (row e / 32, feature e % 32)
+#pragma unroll 8
+    for (int q = 0; q < 32; ++q) {
+      const int rr = (lane >> 5) + 2 * q, j = lane & 31;
+      const uint32_t row = r0 + rr;
+      if (row < n_rows)
+        scratch[(size_t)row * kRS + j] = bf16_round(sc.F[(size_t)s_anchor[rr] * CGX_FEAT_DIM + j]);
+    }
+    // one lane per row: the direction / distance inputs, and their term of dx
+    const uint32_t r = r0 + lane;
+    if (r < n_rows) {
+      float* rs = scratch + (size_t)r * kRS;
+      const ViewDev& V = views[rows[r].x];
+      const uint32_t a = s_anchor[lane];
+      float dir[3], dist;
+      decoder_dir(V, sc, a, dir, dist);
+      rs[CGX_FEAT_DIM + 0] = dir[0];
+      rs[CGX_FEAT_DIM + 1] = dir[1];
+      rs[CGX_FEAT_DIM + 2] = dir[2];
+      rs[CGX_FEAT_DIM + 3] = dist / sc.d_max;
+      // d~ = (c - x)/|c - x|, Delta = |c - x| / d_max; x enters through c - x
+      const float* dz0 = s_tail[lane];
+      const float dd = dz0[0] * dir[0] + dz0[1] * dir[1] + dz0[2] * dir[2];
+      const float il = 1.0f / dist;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float ddelta = (dz0[c] - dir[c] * dd) * il + dz0[3] / sc.d_max * dir[c];
+        rs[D::kDX + c] = -ddelta;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 constexpr int kWgWaves = 4;
@@ -1144,7 +1288,7 @@ size_t anchor_scratch_bytes(int64_t max_rows, const cgx_anchor_scene& sc) {
   with_decoder(sc, [&](auto dec) {
     using D = decltype(dec);
     bytes = sizeof(float) * ((size_t)max_rows * D::kRowScratch + (size_t)kRedBlocks * D::kWGrad) +
-            sizeof(DecWB<D>) + sizeof(DecWT<D>);
+            sizeof(DecWB<D>) + sizeof(DecAdj<D>);
   });
   return bytes;
 }
@@ -1161,18 +1305,20 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
     if (gblocks)
       hipLaunchKernelGGL(k_decode_bwd_gauss<D>, dim3(gblocks), dim3(256), 0, s, views, sc, rows,
                          ctr, counts, sgrad, scratch);
-    const uint32_t rblocks = div_up(max_rows, kMlpRows * kMlpGroups);
+    const uint32_t rblocks = std::min<uint32_t>(div_up(max_rows, kAdjWaves * 64), kAdjBlocks);
     if (rblocks)
-      hipLaunchKernelGGL(k_decode_bwd_mlp<D>, dim3(rblocks), dim3(256), 0, s, views, sc, rows, ctr,
-                         (const DecWT<D>*)adjoint_weights<D>(scratch, max_rows), scratch);
+      hipLaunchKernelGGL(k_decode_bwd_mlp<D>, dim3(rblocks), dim3(kAdjWaves * kWave), 0, s, views,
+                         sc, rows, ctr, (const DecAdj<D>*)adjoint_weights<D>(scratch, max_rows),
+                         scratch);
     const uint32_t ablocks = div_up((uint64_t)sc.n_anchor, kGatherPerWave);
     if (ablocks)
       hipLaunchKernelGGL(k_anchor_grad<D>, dim3(ablocks), dim3(kWave), 0, s, sc, B, rinv,
                          (const float*)scratch, g);
-    hipLaunchKernelGGL(k_wgrad_mfma<D>, dim3(kRedBlocks), dim3(kWgWaves * kWave), 0, s,
+    const uint32_t nred = red_blocks(max_rows);
+    hipLaunchKernelGGL(k_wgrad_mfma<D>, dim3(nred), dim3(kWgWaves * kWave), 0, s,
                        (const float*)scratch, ctr, partial);
     hipLaunchKernelGGL(k_wgrad_final<D>, dim3(div_up(D::kWGrad, 32)), dim3(256), 0, s,
-                       (const float*)partial, kRedBlocks, g);
+                       (const float*)partial, (int)nred, g);
   });
 }
 
