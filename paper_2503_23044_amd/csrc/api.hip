@@ -198,7 +198,7 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   L.counts = take(sizeof(uint32_t) * (size_t)L.max_splats);
   L.offsets = take(sizeof(uint32_t) * (size_t)L.max_splats);
   L.zkey = take(sizeof(uint32_t) * (size_t)L.max_splats);
-  L.tmask = take(sizeof(uint64_t) * (size_t)L.max_splats);
+  L.erec = take(sizeof(EmitRec) * (size_t)L.max_splats);
   for (int b = 0; b < 2; ++b) {
     L.vkey[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
     L.vslot[b] = take(sizeof(uint32_t) * (size_t)L.max_splats);
@@ -271,7 +271,7 @@ struct Ptrs {
   uint32_t* counts;
   uint32_t* offsets;
   uint32_t* zkey;
-  uint64_t* tmask;
+  EmitRec* erec;               // emission records, by slot
   uint32_t* vkey[2];
   uint32_t* vslot[2];
   uint32_t* pkey[2];
@@ -301,7 +301,7 @@ static Ptrs pointers(void* ws, const Layout& L) {
   p.counts = at<uint32_t>(ws, L.counts);
   p.offsets = at<uint32_t>(ws, L.offsets);
   p.zkey = at<uint32_t>(ws, L.zkey);
-  p.tmask = at<uint64_t>(ws, L.tmask);
+  p.erec = at<EmitRec>(ws, L.erec);
   for (int b = 0; b < 2; ++b) {
     p.vkey[b] = at<uint32_t>(ws, L.vkey[b]);
     p.vslot[b] = at<uint32_t>(ws, L.vslot[b]);
@@ -364,7 +364,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
     phase_begin(c, CGX_PHASE_PROJECT, st);
-    launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, P.zkey, P.tmask,
+    launch_project_explicit(P.views, B, s->ex, c->tw, c->th, P.splats, P.counts, P.zkey, P.erec,
                             st);
     phase_end(c, st);
   } else {
@@ -374,7 +374,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
     phase_end(c, st);
     phase_begin(c, CGX_PHASE_PROJECT, st);
     launch_decode_project(P.views, B, s->an, P.rows, (uint32_t)L.max_rows, c->tw, c->th,
-                          P.splats, P.counts, P.zkey, P.tmask, P.ctr, P.dz, st);
+                          P.splats, P.counts, P.zkey, P.erec, P.ctr, P.dz, st);
     phase_end(c, st);
   }
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
@@ -390,11 +390,8 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   phase_begin(c, CGX_PHASE_DUPLICATE, st);
   launch_scan_counts(P.counts, P.vslot[vb], P.offsets, P.part, &P.ctr->n_visible, n_slots,
                      (uint32_t)L.max_pairs, P.ctr, P.bstart, st);
-  launch_emit_pairs(P.views, P.splats, P.tmask, P.vslot[vb], P.offsets, P.bstart, P.ctr,
-                    expl ? 1 : s->an.n_offsets,
-                    expl ? nullptr : P.rows,
-                    expl ? (uint32_t)std::max<int64_t>(s->ex.n, 1) : 1u, c->tw, c->th,
-                    (uint32_t)L.max_pairs, P.pkey[0], P.pval[0], st);
+  launch_emit_pairs(P.erec, P.vslot[vb], P.offsets, P.bstart, P.ctr, (uint32_t)L.max_pairs,
+                    P.pkey[0], P.pval[0], st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
   const int fb = launch_sort_kv(P.pkey, P.pval, &P.ctr->n_pairs, (uint32_t)L.max_pairs, P.hist,

@@ -119,7 +119,7 @@ struct ViewPack {
 };
 
 struct Layout {
-  size_t views, counters, scan_part, rows, row_off, rinv, splats, counts, offsets, zkey, tmask;
+  size_t views, counters, scan_part, rows, row_off, rinv, splats, counts, offsets, zkey, erec;
   size_t vkey[2], vslot[2];    // visible splats: depth bits and slot, double-buffered
   size_t pkey[2], pval[2];     // pairs: tile id and slot, double-buffered
   size_t hist, ranges, px_T, px_last, sgrad, dz;
@@ -299,6 +299,33 @@ __host__ __device__ inline bool mask_box(int nx, int ny) {
   return nx >= 2 && ny >= 2 && nx * ny <= kMaskTiles;
 }
 
+// What the pair emission needs of a splat: its slot, the global id of its
+// pixel box's first tile, the box's tiles per row (| 1 << 16 when the box
+// carries a tile mask), its view's tiles per row and the mask.  Written by
+// the projection next to the splat record, so that the emission stages one
+// 24-byte record per visible splat instead of gathering the view, the
+// splat's box and its mask.
+struct alignas(8) EmitRec {
+  uint32_t slot, base, nx, TX, mlo, mhi;
+};
+__device__ __forceinline__ EmitRec emit_rec_of(const ViewDev& V, uint32_t bx, uint32_t by,
+                                               uint64_t tm, uint32_t slot, int tw, int th) {
+  const int x_lo = bx & 0xFFFF, x_hi = bx >> 16;
+  const int y_lo = by & 0xFFFF, y_hi = by >> 16;
+  const int tx0 = x_lo / tw, ty0 = y_lo / th;
+  const int nx = x_hi / tw - tx0 + 1, ny = y_hi / th - ty0 + 1;
+  const bool masked = mask_box(nx, ny);
+  const uint64_t m = masked ? tm : 0ull;
+  EmitRec r;
+  r.slot = slot;
+  r.base = (uint32_t)(V.tile_off + ty0 * V.TX + tx0);
+  r.nx = (uint32_t)nx | (masked ? 1u << 16 : 0u);
+  r.TX = (uint32_t)V.TX;
+  r.mlo = (uint32_t)m;
+  r.mhi = (uint32_t)(m >> 32);
+  return r;
+}
+
 // device-wide exclusive scan of counts[idx[i]] (idx may be NULL) for
 // i < n (n from *n_dev if non-null, else n_host) into offsets clamped to
 // cap; the total becomes the pair count (overflow bit 2 above cap).  With
@@ -310,11 +337,8 @@ void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* o
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s);
-void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint64_t* tmask,
-                       const uint32_t* vslot,
-                       const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
-                       int n_per_row, const int2* rows,
-                       uint32_t N_explicit, int tw, int th, uint32_t cap, uint32_t* pkey,
+void launch_emit_pairs(const EmitRec* erec, const uint32_t* vslot, const uint32_t* voff,
+                       const uint32_t* bstart, const Counters* ctr, uint32_t cap, uint32_t* pkey,
                        uint32_t* pval, hipStream_t s);
 void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
@@ -327,13 +351,13 @@ int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, 
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
                              int tw, int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
-                             uint64_t* tmask, hipStream_t s);
+                             EmitRec* erec, hipStream_t s);
 void launch_select_anchors(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            unsigned long long* part, int2* rows, uint32_t* row_off,
                            uint32_t* rinv, uint32_t max_rows, Counters* ctr, hipStream_t s);
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, uint32_t* zkey, uint64_t* tmask, Counters* ctr,
+                           uint32_t* counts, uint32_t* zkey, EmitRec* erec, Counters* ctr,
                            float* row_scratch, hipStream_t s);
 
 

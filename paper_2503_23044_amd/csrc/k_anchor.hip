@@ -525,7 +525,7 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
                                                          Splat* __restrict__ splats,
                                                          uint32_t* __restrict__ counts,
                                                          uint32_t* __restrict__ zkey,
-                                                         uint64_t* __restrict__ tmask) {
+                                                         EmitRec* __restrict__ erec) {
   const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = item / kNOff;
   const int k = (int)(item - r * kNOff);
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_project_decoded(const ViewDev* __restri
   if (cnt) {
     splats[item] = o;
     zkey[item] = zb;
-    tmask[item] = tm;
+    erec[item] = emit_rec_of(V, o.bx, o.by, tm, item, tw, th);
   }
 }
 
@@ -645,7 +645,7 @@ static DecAdj<D>* adjoint_weights(float* scratch, uint32_t max_rows) {
 
 void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& sc,
                            const int2* rows, uint32_t max_rows, int tw, int th, Splat* splats,
-                           uint32_t* counts, uint32_t* zkey, uint64_t* tmask, Counters* ctr,
+                           uint32_t* counts, uint32_t* zkey, EmitRec* erec, Counters* ctr,
                            float* row_scratch, hipStream_t s) {
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
@@ -659,7 +659,7 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
                        (const Counters*)ctr, (const DecWB<D>*)wb, row_scratch);
     hipLaunchKernelGGL(k_project_decoded<D>, dim3(div_up((uint64_t)max_rows * kNOff, 256)),
                        dim3(256), 0, s, views, sc, rows, (const Counters*)ctr, tw, th,
-                       (const float*)row_scratch, splats, counts, zkey, tmask);
+                       (const float*)row_scratch, splats, counts, zkey, erec);
   });
 }
 

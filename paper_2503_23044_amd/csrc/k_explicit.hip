@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_project_explicit(const ViewDev* __restr
                                                           Splat* __restrict__ splats,
                                                           uint32_t* __restrict__ counts,
                                                           uint32_t* __restrict__ zkey,
-                                                          uint64_t* __restrict__ tmask) {
+                                                          EmitRec* __restrict__ erec) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const uint64_t N = (uint64_t)sc.n;
   const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,21 +119,21 @@ __global__ __launch_bounds__(256) void k_project_explicit(const ViewDev* __restr
   if (cnt) {
     splats[slot] = o;
     zkey[slot] = zb;
-    tmask[slot] = tm;
+    erec[slot] = emit_rec_of(V, o.bx, o.by, tm, slot, tw, th);
   }
 }
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc, int tw,
                              int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
-                             uint64_t* tmask, hipStream_t s) {
+                             EmitRec* erec, hipStream_t s) {
   const uint64_t n = (uint64_t)sc.n * (uint64_t)B;
   const uint32_t blocks = div_up(n, 256);
   if (blocks == 0) return;
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_explicit<0>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
-    case 1: hipLaunchKernelGGL(k_project_explicit<1>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
-    case 2: hipLaunchKernelGGL(k_project_explicit<2>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
-    default: hipLaunchKernelGGL(k_project_explicit<3>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, tmask); break;
+    case 0: hipLaunchKernelGGL(k_project_explicit<0>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, erec); break;
+    case 1: hipLaunchKernelGGL(k_project_explicit<1>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, erec); break;
+    case 2: hipLaunchKernelGGL(k_project_explicit<2>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, erec); break;
+    default: hipLaunchKernelGGL(k_project_explicit<3>, dim3(blocks), dim3(256), 0, s, views, B, sc, tw, th, splats, counts, zkey, erec); break;
   }
 }
 

@@ -436,12 +436,13 @@ __device__ __forceinline__ uint32_t kth_set_bit(uint32_t lo, uint32_t hi, uint32
 constexpr int kEmitPerThread = 4;
 static_assert(256 * kEmitPerThread == kDupPairs, "one group of pairs per thread and block step");
 
-__global__ __launch_bounds__(256) void k_emit_pairs(
-    const ViewDev* __restrict__ views, const Splat* __restrict__ splats,
-    const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ vslot, const uint32_t* __restrict__ voff,
-    const uint32_t* __restrict__ bstart, const Counters* ctr, int n_per_row,
-    const int2* __restrict__ rows, uint32_t N_explicit, int tw, int th,
-    uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+__global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ erec,
+                                                    const uint32_t* __restrict__ vslot,
+                                                    const uint32_t* __restrict__ voff,
+                                                    const uint32_t* __restrict__ bstart,
+                                                    const Counters* ctr,
+                                                    uint32_t* __restrict__ pkey,
+                                                    uint32_t* __restrict__ pval) {
   constexpr int M = kDupPairs + 2;
   __shared__ uint32_t s_off[M];    // first pair of each visible splat of the block
   __shared__ uint32_t s_slot[M];
@@ -462,25 +463,16 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint32_t j1 = j1r < nv ? j1r : nv - 1;
     const uint32_t span = j1 >= j0 ? j1 - j0 + 1 : 1;
     const uint32_t m = span <= (uint32_t)M ? span : (uint32_t)M;
-    // the block's splats, once: their pair offsets and tile rectangles
+    // the block's splats, once: their pair offsets and emission records
     for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) {
-      const uint32_t slot = vslot[j0 + t];
-      const int v = rows ? rows[slot / n_per_row].x : (int)(slot / N_explicit);
-      const ViewDev& V = views[v];
-      const Splat& sp = splats[slot];
-      const int x_lo = sp.bx & 0xFFFF, x_hi = sp.bx >> 16;
-      const int y_lo = sp.by & 0xFFFF, y_hi = sp.by >> 16;
-      const int tx0 = x_lo / tw, ty0 = y_lo / th;
-      const int nx = x_hi / tw - tx0 + 1, ny = y_hi / th - ty0 + 1;
-      const bool masked = mask_box(nx, ny);
-      const uint64_t m = masked ? tmask[slot] : 0ull;
+      const EmitRec r = erec[vslot[j0 + t]];
       s_off[t] = voff[j0 + t];
-      s_slot[t] = slot;
-      s_base[t] = (uint32_t)(V.tile_off + ty0 * V.TX + tx0);
-      s_nx[t] = (uint32_t)nx | (masked ? 1u << 16 : 0u);
-      s_TX[t] = (uint32_t)V.TX;
-      s_mlo[t] = (uint32_t)m;
-      s_mhi[t] = (uint32_t)(m >> 32);
+      s_slot[t] = r.slot;
+      s_base[t] = r.base;
+      s_nx[t] = r.nx;
+      s_TX[t] = r.TX;
+      s_mlo[t] = r.mlo;
+      s_mhi[t] = r.mhi;
     }
     __syncthreads();
     // four consecutive pairs per thread (256 x 4 = kDupPairs): one binary
@@ -528,16 +520,14 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
   }
 }
 
-void launch_emit_pairs(const ViewDev* views, const Splat* splats, const uint64_t* tmask,
-                       const uint32_t* vslot,
-                       const uint32_t* voff, const uint32_t* bstart, const Counters* ctr,
-                       int n_per_row, const int2* rows, uint32_t N_explicit, int tw, int th,
-                       uint32_t cap, uint32_t* pkey, uint32_t* pval, hipStream_t s) {
+void launch_emit_pairs(const EmitRec* erec, const uint32_t* vslot, const uint32_t* voff,
+                       const uint32_t* bstart, const Counters* ctr, uint32_t cap, uint32_t* pkey,
+                       uint32_t* pval, hipStream_t s) {
   // the pair count is read on the device; the grid strides over blocks of
   // kDupPairs pairs
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, kDupPairs), 4096));
-  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, views, splats, tmask, vslot, voff,
-                     bstart, ctr, n_per_row, rows, N_explicit, tw, th, pkey, pval);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, erec, vslot, voff, bstart, ctr,
+                     pkey, pval);
 }
 
 // depth bits of every sorted pair (for the debug copy only)
