@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CGX_ABI_VERSION 7
+#define CGX_ABI_VERSION 8
 #define CGX_MAX_VIEWS 32       /* batch bound (Sec. 3.3: up to 32 views) */
 #define CGX_FEAT_DIM 32        /* anchor feature width (Sec. 3.2) */
 #define CGX_MLP_IN 36          /* [F (32), direction to camera (3), relative distance (1)] */
@@ -460,8 +460,9 @@ size_t cgx_tsdf_workspace_size(const cgx_view* views, int32_t n_views);
  * On return *best_tw x *best_th is the fastest shape; the outputs, grads and
  * loss hold that last shape's results, not necessarily the best one's.
  * Returns CGX_ERR_CAPACITY if no shape ran within capacity, and
- * CGX_ERR_WORKSPACE if no shape fits.  `ctx` gives the device and receives
- * the error message; its own tile shape is neither used nor changed.
+ * CGX_ERR_WORKSPACE if no shape fits.  `ctx` gives the device and the sort
+ * digit width and receives the error message; its own tile shape is neither
+ * used nor changed.
  * Allocates no device memory. */
 #define CGX_N_TILE_SHAPES 5
 int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
@@ -471,6 +472,39 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
                             const cgx_images* out, const cgx_grads* grads, float* loss_dev,
                             int32_t reps, void* stream, int32_t* best_tw, int32_t* best_th,
                             float* ms_per_shape);
+
+/* Digit width of the radix sorts (binning, Sec. 3.3): each LSD sort splits
+ * its significant bits (32 for the depth keys, the tile-id bits for the
+ * pairs, 16 for the raster launch order) into equal digits of at most
+ * `bits` bits, CGX_SORT_DIGIT_BITS_MIN..MAX (default 9).  Wider digits mean
+ * fewer passes over the keys but more digit values per pass; the sorted
+ * result does not depend on the setting, nor do workspace sizes.  Later
+ * launch chains of ctx use it.  Returns CGX_ERR_INVALID_ARG outside the
+ * range.  Host only. */
+#define CGX_SORT_DIGIT_BITS_MIN 6
+#define CGX_SORT_DIGIT_BITS_MAX 9
+int32_t cgx_set_sort_digit_bits(cgx_ctx* ctx, int32_t bits);
+int32_t cgx_get_sort_digit_bits(cgx_ctx* ctx, int32_t* bits);
+
+/* Sort digit-width autotuner: like cgx_tune_tile_shape, for the context's
+ * tile shape and the digit widths 9, 8 and 7 (in that order): one untimed
+ * and `reps` timed fused chains each; ms_per_choice[CGX_N_DIGIT_CHOICES]
+ * (host, may be NULL) gets the mean milliseconds per chain; *best_bits the
+ * fastest width (pass it to cgx_set_sort_digit_bits).  The outputs hold the
+ * last choice's results (identical for every choice).  Returns
+ * CGX_ERR_CAPACITY if a run exceeded a capacity.  With the tile shape, this
+ * covers the launch knobs of the chain: the pixels per lane follow the tile
+ * shape (a tile is one wavefront), the raster kernels stage no LDS batches
+ * (splat records come through scalar loads) and one-wave blocks leave the
+ * blocks per CU to the register budget.  Allocates no device memory. */
+#define CGX_N_DIGIT_CHOICES 3
+int32_t cgx_tune_sort_digits(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                             const cgx_scene* scene, const cgx_capacity* cap,
+                             void* workspace, size_t workspace_bytes,
+                             const cgx_images* target, const float* w3_host,
+                             const cgx_images* out, const cgx_grads* grads, float* loss_dev,
+                             int32_t reps, void* stream, int32_t* best_bits,
+                             float* ms_per_choice);
 
 /* Phases of a launch chain, for cgx_timing_read. */
 enum {

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
-CGX_ABI_VERSION = 7
+CGX_ABI_VERSION = 8
 OPACITY_SIGMOID, OPACITY_TANH_MASK = 0, 1
 OFFSETS_TABLE, OFFSETS_DECODED = 0, 1
 DECODER_SHARED, DECODER_PER_ATTRIBUTE = 1, 3
@@ -155,6 +155,14 @@ def load_library(path: str = LIB_PATH):
                                             C.POINTER(cgx_grads), P, C.c_int32, P,
                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_float)]),
+        "cgx_tune_sort_digits": (C.c_int32, [P, C.POINTER(cgx_view), C.c_int32,
+                                             C.POINTER(cgx_scene), C.POINTER(cgx_capacity), P,
+                                             C.c_size_t, C.POINTER(cgx_images),
+                                             C.POINTER(C.c_float), C.POINTER(cgx_images),
+                                             C.POINTER(cgx_grads), P, C.c_int32, P,
+                                             C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+        "cgx_set_sort_digit_bits": (C.c_int32, [P, C.c_int32]),
+        "cgx_get_sort_digit_bits": (C.c_int32, [P, C.POINTER(C.c_int32)]),
         "cgx_timing_enable": (C.c_int32, [P, C.c_int32]),
         "cgx_count_enable": (C.c_int32, [P, C.c_int32]),
         "cgx_debug_splats": (C.c_int32, [P, P, P, P, P]),
@@ -457,6 +465,38 @@ def cgx_tune_tile_shape(ctx, views, scene, cap, ws, target, weights, out, grads,
                                  C.byref(tw), C.byref(th), ms)
     _check(ctx, rc, "cgx_tune_tile_shape")
     return (tw.value, th.value), {s: ms[i] for i, s in enumerate(TILE_SHAPES)}
+
+
+DIGIT_CHOICES = [9, 8, 7]
+
+
+def cgx_tune_sort_digits(ctx, views, scene, cap, ws, target, weights, out, grads, loss_dev=None,
+                         reps=3):
+    """Time the fused chain per sort digit width at the context's tile
+    shape; returns (bits, {bits: ms})."""
+    lib = load_library()
+    va = make_views(views)
+    sc = make_scene(scene)
+    w = (C.c_float * 3)(*[float(x) for x in weights])
+    bits = C.c_int32(0)
+    ms = (C.c_float * len(DIGIT_CHOICES))()
+    rc = lib.cgx_tune_sort_digits(ctx, va, len(views), C.byref(sc), C.byref(make_capacity(cap)),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(),
+                                  C.byref(make_images(target)), w, C.byref(make_images(out)),
+                                  C.byref(make_grads(grads)), _ptr(loss_dev), int(reps), _stream(),
+                                  C.byref(bits), ms)
+    _check(ctx, rc, "cgx_tune_sort_digits")
+    return bits.value, {b: ms[i] for i, b in enumerate(DIGIT_CHOICES)}
+
+
+def cgx_set_sort_digit_bits(ctx, bits):
+    _check(ctx, load_library().cgx_set_sort_digit_bits(ctx, int(bits)), "cgx_set_sort_digit_bits")
+
+
+def cgx_get_sort_digit_bits(ctx):
+    b = C.c_int32(0)
+    _check(ctx, load_library().cgx_get_sort_digit_bits(ctx, C.byref(b)), "cgx_get_sort_digit_bits")
+    return b.value
 
 
 def cgx_read_info(ctx, ws, raise_on_capacity=True):

@@ -19,6 +19,7 @@ using namespace cgx;
 struct cgx_ctx {
   int device;
   int tw, th;
+  int digit_bits = cgx::kMaxRadixBits;   // digit width bound of the radix sorts
   std::string err;
   // phase timing: a pool of (begin, end) event pairs recorded on the stream
   std::vector<hipEvent_t> ev;
@@ -177,10 +178,11 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   int bits = 1;
   while ((int64_t(1) << bits) < tiles) ++bits;
   L.tile_bits = bits;
-  L.n_passes = sort_passes(32) + sort_passes(bits);
-  L.vis_buf = sort_passes(32) & 1;
-  L.final_buf = sort_passes(bits) & 1;
-  L.order_buf = sort_passes(kTileOrderBits) & 1;
+  const int db = c->digit_bits;
+  L.n_passes = sort_passes(32, db) + sort_passes(bits, db);
+  L.vis_buf = sort_passes(32, db) & 1;
+  L.final_buf = sort_passes(bits, db) & 1;
+  L.order_buf = sort_passes(kTileOrderBits, db) & 1;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -359,7 +361,7 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   h.max_pairs = L.max_pairs;
   h.n_views = B;
   h.kind = s->kind;
-  h.sort_passes = sort_passes(L.tile_bits);   // passes over the pairs
+  h.sort_passes = sort_passes(L.tile_bits, c->digit_bits);   // passes over the pairs
   launch_init_counters(P.ctr, P.stats, expl ? (uint32_t)L.max_splats : 0u, h, st);
   const uint32_t n_slots = (uint32_t)L.max_splats;
   if (expl) {
@@ -384,7 +386,8 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
                          st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
-  const int vb = launch_sort_kv(P.vkey, P.vslot, &P.ctr->n_visible, n_slots, P.hist, 32, st);
+  const int vb = launch_sort_kv(P.vkey, P.vslot, &P.ctr->n_visible, n_slots, P.hist, 32,
+                                c->digit_bits, st);
   phase_end(c, st);
   // pair offsets in depth order, pair emission, then the tile-id bits
   phase_begin(c, CGX_PHASE_DUPLICATE, st);
@@ -395,13 +398,14 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
   const int fb = launch_sort_kv(P.pkey, P.pval, &P.ctr->n_pairs, (uint32_t)L.max_pairs, P.hist,
-                                L.tile_bits, st);
+                                L.tile_bits, c->digit_bits, st);
   phase_end(c, st);
   (void)vb;
   (void)fb;
   phase_begin(c, CGX_PHASE_RANGES, st);
   launch_ranges(P.pkey[L.final_buf], P.ctr, P.ranges, (uint32_t)L.n_tiles, (uint32_t)L.max_pairs, st);
-  launch_tile_order(P.ranges, P.ctr, (uint32_t)L.n_tiles, P.tkey, P.tord, P.hist, st);
+  launch_tile_order(P.ranges, P.ctr, (uint32_t)L.n_tiles, P.tkey, P.tord, P.hist, c->digit_bits,
+                    st);
   phase_end(c, st);
 
   RasterArgs a;
@@ -575,6 +579,21 @@ int32_t cgx_timing_enable(cgx_ctx* ctx, int32_t n_records) {
 int32_t cgx_count_enable(cgx_ctx* ctx, int32_t on) {
   if (!ctx) return CGX_ERR_INVALID_ARG;
   ctx->count = on ? 1 : 0;
+  return CGX_OK;
+}
+
+int32_t cgx_set_sort_digit_bits(cgx_ctx* ctx, int32_t bits) {
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (bits < CGX_SORT_DIGIT_BITS_MIN || bits > CGX_SORT_DIGIT_BITS_MAX)
+    return fail(ctx, CGX_ERR_INVALID_ARG, "sort digit bits %d outside %d..%d", bits,
+                CGX_SORT_DIGIT_BITS_MIN, CGX_SORT_DIGIT_BITS_MAX);
+  ctx->digit_bits = bits;
+  return CGX_OK;
+}
+
+int32_t cgx_get_sort_digit_bits(cgx_ctx* ctx, int32_t* bits) {
+  if (!ctx || !bits) return CGX_ERR_INVALID_ARG;
+  *bits = ctx->digit_bits;
   return CGX_OK;
 }
 
@@ -1147,6 +1166,48 @@ int32_t cgx_tsdf_integrate(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
   return CGX_OK;
 }
 
+// Times the fused chain with the settings of c on the caller's buffers: one
+// untimed run (which also checks the capacities), then `reps` runs between
+// HIP events.  *ms gets the mean milliseconds per chain, or -2 when the
+// untimed run exceeded a capacity (then CGX_OK with nothing timed).
+static int32_t time_chain(cgx_ctx* c, const cgx_view* views, int32_t n_views,
+                          const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                          size_t workspace_bytes, const cgx_images* target, const float* w3_host,
+                          const cgx_images* out, const cgx_grads* grads, float* loss_dev,
+                          int32_t reps, void* stream, float* ms) {
+  hipStream_t st = (hipStream_t)stream;
+  *ms = -1.f;
+  int32_t rc = cgx_render_fwd_bwd_l1(c, views, n_views, scene, cap, workspace, workspace_bytes,
+                                     target, w3_host, nullptr, out, grads, loss_dev, stream);
+  if (rc) return rc;
+  Counters h;
+  rc = read_counters(c, workspace, stream, h);
+  if (rc) return rc;
+  if (h.overflow) {
+    *ms = -2.f;
+    return CGX_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return fail(c, CGX_ERR_HIP, "hipEventCreate failed");
+  }
+  hipEventRecord(e0, st);
+  for (int r = 0; r < reps && rc == CGX_OK; ++r)
+    rc = cgx_render_fwd_bwd_l1(c, views, n_views, scene, cap, workspace, workspace_bytes, target,
+                               w3_host, nullptr, out, grads, loss_dev, stream);
+  hipEventRecord(e1, st);
+  float t = 0.f;
+  const hipError_t e = hipEventSynchronize(e1);
+  if (e == hipSuccess) hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(c, CGX_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+  *ms = t / (float)reps;
+  return CGX_OK;
+}
+
 int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
                             const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
                             size_t workspace_bytes, const cgx_images* target,
@@ -1157,7 +1218,6 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
   if (!ctx) return CGX_ERR_INVALID_ARG;
   if (!best_tw || !best_th) return fail(ctx, CGX_ERR_INVALID_ARG, "best_tw / best_th is NULL");
   if (reps < 1 || reps > 1000) return fail(ctx, CGX_ERR_INVALID_ARG, "reps %d outside 1..1000", reps);
-  hipStream_t st = (hipStream_t)stream;
   float best = -1.f;
   int32_t last_rc = CGX_ERR_WORKSPACE;
   for (int i = 0; i < CGX_N_TILE_SHAPES; ++i) {
@@ -1166,40 +1226,20 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
     c.device = ctx->device;
     c.tw = kShapes[i][0];
     c.th = kShapes[i][1];
+    c.digit_bits = ctx->digit_bits;
     Layout L;
     int32_t rc = make_layout(&c, views, n_views, scene, cap, L);
     if (rc) return fail(ctx, rc, "%s", c.err.c_str());   // not shape-dependent
     if (L.total > workspace_bytes) continue;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes, target,
-                               w3_host, nullptr, out, grads, loss_dev, stream);
+    float ms = -1.f;
+    rc = time_chain(&c, views, n_views, scene, cap, workspace, workspace_bytes, target, w3_host,
+                    out, grads, loss_dev, reps, stream, &ms);
     if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
-    Counters h;
-    rc = read_counters(&c, workspace, stream, h);
-    if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
-    if (h.overflow) {
-      if (ms_per_shape) ms_per_shape[i] = -2.f;
+    if (ms_per_shape) ms_per_shape[i] = ms;
+    if (ms == -2.f) {
       last_rc = CGX_ERR_CAPACITY;
       continue;
     }
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-      if (e0) hipEventDestroy(e0);
-      return fail(ctx, CGX_ERR_HIP, "hipEventCreate failed");
-    }
-    hipEventRecord(e0, st);
-    for (int r = 0; r < reps && rc == CGX_OK; ++r)
-      rc = cgx_render_fwd_bwd_l1(&c, views, n_views, scene, cap, workspace, workspace_bytes,
-                                 target, w3_host, nullptr, out, grads, loss_dev, stream);
-    hipEventRecord(e1, st);
-    float ms = 0.f;
-    const hipError_t e = hipEventSynchronize(e1);
-    if (e == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (rc) return fail(ctx, rc, "%dx%d: %s", c.tw, c.th, c.err.c_str());
-    if (e != hipSuccess) return fail(ctx, CGX_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
-    ms /= (float)reps;
-    if (ms_per_shape) ms_per_shape[i] = ms;
     if (best < 0.f || ms < best) {
       best = ms;
       *best_tw = kShapes[i][0];
@@ -1209,6 +1249,38 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
   if (best < 0.f)
     return fail(ctx, last_rc, last_rc == CGX_ERR_CAPACITY ? "every tile shape exceeded a capacity"
                                                           : "no tile shape fits the workspace");
+  return CGX_OK;
+}
+
+int32_t cgx_tune_sort_digits(cgx_ctx* ctx, const cgx_view* views, int32_t n_views,
+                             const cgx_scene* scene, const cgx_capacity* cap, void* workspace,
+                             size_t workspace_bytes, const cgx_images* target,
+                             const float* w3_host, const cgx_images* out, const cgx_grads* grads,
+                             float* loss_dev, int32_t reps, void* stream, int32_t* best_bits,
+                             float* ms_per_choice) {
+  static const int kChoices[CGX_N_DIGIT_CHOICES] = {9, 8, 7};
+  if (!ctx) return CGX_ERR_INVALID_ARG;
+  if (!best_bits) return fail(ctx, CGX_ERR_INVALID_ARG, "best_bits is NULL");
+  if (reps < 1 || reps > 1000) return fail(ctx, CGX_ERR_INVALID_ARG, "reps %d outside 1..1000", reps);
+  float best = -1.f;
+  for (int i = 0; i < CGX_N_DIGIT_CHOICES; ++i) {
+    if (ms_per_choice) ms_per_choice[i] = -1.f;
+    cgx_ctx c;
+    c.device = ctx->device;
+    c.tw = ctx->tw;
+    c.th = ctx->th;
+    c.digit_bits = kChoices[i];
+    float ms = -1.f;
+    const int32_t rc = time_chain(&c, views, n_views, scene, cap, workspace, workspace_bytes,
+                                  target, w3_host, out, grads, loss_dev, reps, stream, &ms);
+    if (rc) return fail(ctx, rc, "%d-bit digits: %s", kChoices[i], c.err.c_str());
+    if (ms_per_choice) ms_per_choice[i] = ms;
+    if (ms == -2.f) return fail(ctx, CGX_ERR_CAPACITY, "a capacity was exceeded");
+    if (best < 0.f || ms < best) {
+      best = ms;
+      *best_bits = kChoices[i];
+    }
+  }
   return CGX_OK;
 }
 

@@ -343,11 +343,13 @@ void launch_emit_pairs(const EmitRec* erec, const uint32_t* vslot, const uint32_
 void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
 size_t sort_hist_words();
-int sort_passes(int bits);
+// passes of an LSD sort on `bits` bits with digits of at most max_digit
+// (<= kMaxRadixBits) bits, split into equal widths
+int sort_passes(int bits, int max_digit);
 // stable LSD sort of 32-bit keys with 32-bit values on bits [0, bits);
 // returns the buffer index holding the result
 int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, uint32_t cap,
-                   uint32_t* hist, int bits, hipStream_t s);
+                   uint32_t* hist, int bits, int max_digit, hipStream_t s);
 
 void launch_project_explicit(const ViewDev* views, int B, const cgx_explicit_scene& sc,
                              int tw, int th, Splat* splats, uint32_t* counts, uint32_t* zkey,
@@ -367,7 +369,7 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
 // holding the order.
 constexpr int kTileOrderBits = 16;
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
-                      uint32_t* order[2], uint32_t* hist, hipStream_t s);
+                      uint32_t* order[2], uint32_t* hist, int max_digit, hipStream_t s);
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
                    uint32_t cap, hipStream_t s);
 

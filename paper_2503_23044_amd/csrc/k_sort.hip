@@ -296,12 +296,12 @@ static void one_pass(uint32_t* kin, uint32_t* vin, uint32_t* kout, uint32_t* vou
 
 size_t sort_hist_words() { return (size_t)(1 << kMaxRadixBits) * (kSortBlocks + 1); }
 
-int sort_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; }
+int sort_passes(int bits, int max_digit) { return (bits + max_digit - 1) / max_digit; }
 
 int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, uint32_t cap,
-                   uint32_t* hist, int bits, hipStream_t s) {
-  // split the significant bits into equal digits of at most kMaxRadixBits
-  const int passes = sort_passes(bits);
+                   uint32_t* hist, int bits, int max_digit, hipStream_t s) {
+  // split the significant bits into equal digits of at most max_digit
+  const int passes = sort_passes(bits, max_digit);
   const int width = (bits + passes - 1) / passes;
   int src = 0, shift = 0;
   for (int p = 0; p < passes; ++p) {
@@ -568,10 +568,10 @@ __global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ran
 }
 
 int launch_tile_order(const uint2* ranges, Counters* ctr, uint32_t n_tiles, uint32_t* keys[2],
-                      uint32_t* order[2], uint32_t* hist, hipStream_t s) {
+                      uint32_t* order[2], uint32_t* hist, int max_digit, hipStream_t s) {
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_tiles, 256), 4096));
   hipLaunchKernelGGL(k_tile_keys, dim3(blocks), dim3(256), 0, s, ranges, n_tiles, keys[0], order[0]);
-  return launch_sort_kv(keys, order, &ctr->n_tiles, n_tiles, hist, kTileOrderBits, s);
+  return launch_sort_kv(keys, order, &ctr->n_tiles, n_tiles, hist, kTileOrderBits, max_digit, s);
 }
 
 }  // namespace cgx

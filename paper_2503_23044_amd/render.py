@@ -98,6 +98,8 @@ class Renderer:
         self.device = device
         self.tile = tuple(tile)
         self.ctx = B.cgx_create(device, tile[0], tile[1])
+        self.digit_bits = B.cgx_get_sort_digit_bits(self.ctx)
+        self.digit_ms = {}
         self.ws = None
         self.depth_ws = None
         self.tsdf_ws = None
@@ -233,21 +235,32 @@ class Renderer:
         tile = tuple(int(t) for t in tile)
         if tile != self.tile:
             ctx = B.cgx_create(self.device, tile[0], tile[1])
+            B.cgx_set_sort_digit_bits(ctx, self.digit_bits)
             B.cgx_destroy(self.ctx)
             self.ctx, self.tile = ctx, tile
 
+    def set_sort_digit_bits(self, bits):
+        B.cgx_set_sort_digit_bits(self.ctx, int(bits))
+        self.digit_bits = int(bits)
+
     def autotune(self, views, scene, target, weights=(1.0, 1.0, 1.0), reps=3, cache=None):
         """Switch to the fastest tile shape for this workload, timed by
-        cgx_tune_tile_shape on the fused chain.  `cache` is an optional JSON
-        file keyed by the workload signature.  Returns (shape, {shape: ms}),
-        with an empty dict when the shape came from the cache."""
+        cgx_tune_tile_shape on the fused chain, then to the fastest sort
+        digit width at that shape (cgx_tune_sort_digits; its timings are kept
+        in self.digit_ms).  `cache` is an optional JSON file keyed by the
+        workload signature, holding [tw, th, digit bits].  Returns
+        (shape, {shape: ms}), with an empty dict when the choice came from
+        the cache."""
         key = workload_key(views, scene)
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
             if key in table:
-                self.set_tile(table[key])
+                entry = table[key]
+                if len(entry) > 2:
+                    self.set_sort_digit_bits(entry[2])
+                self.set_tile(entry[:2])
                 return self.tile, {}
         out, grads = self.fwd_bwd_l1(views, scene, target, weights)   # capacities for this shape
         loss = torch.zeros(1, device=f"cuda:{self.device}")
@@ -272,8 +285,11 @@ class Renderer:
             cap["max_pairs"] = 2 * max(int(cap.get("max_pairs", 0)), int(self.last_info["n_pairs"]), 1024)
             self.cap = cap
         self.set_tile(best)
+        bits, self.digit_ms = B.cgx_tune_sort_digits(self.ctx, views, scene, self.cap, self.ws,
+                                                     target, weights, out, grads, loss, reps)
+        self.set_sort_digit_bits(bits)
         if cache:
-            table[key] = list(best)
+            table[key] = list(best) + [bits]
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
         return self.tile, ms

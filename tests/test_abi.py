@@ -172,6 +172,22 @@ def test_entry_points_reject_bad_arguments_before_any_launch(B):
                                      C.byref(img), C.byref(g), None, 3, None, C.byref(tw), C.byref(th),
                                      None)
         assert rc == B.CGX_ERR_INVALID_ARG
+        bits = C.c_int32(0)
+        rc = lib.cgx_tune_sort_digits(ctx, va, 1, C.byref(sc), C.byref(cap), None, 0, C.byref(img),
+                                      None, C.byref(img), C.byref(g), None, 0, None, C.byref(bits),
+                                      None)
+        assert rc == B.CGX_ERR_INVALID_ARG and b"reps" in lib.cgx_last_error(ctx)
+        rc = lib.cgx_tune_sort_digits(ctx, va, 1, C.byref(sc), C.byref(cap), None, 0, C.byref(img),
+                                      None, C.byref(img), C.byref(g), None, 3, None, None, None)
+        assert rc == B.CGX_ERR_INVALID_ARG
+        # sort digit width: 6..9, default 9, per context
+        assert lib.cgx_get_sort_digit_bits(ctx, C.byref(bits)) == B.CGX_OK and bits.value == 9
+        for bad in (5, 10, 0, -1):
+            assert lib.cgx_set_sort_digit_bits(ctx, bad) == B.CGX_ERR_INVALID_ARG
+            assert b"digit" in lib.cgx_last_error(ctx)
+        assert lib.cgx_set_sort_digit_bits(ctx, 7) == B.CGX_OK
+        assert lib.cgx_get_sort_digit_bits(ctx, C.byref(bits)) == B.CGX_OK and bits.value == 7
+        assert lib.cgx_set_sort_digit_bits(None, 8) == B.CGX_ERR_INVALID_ARG
         assert lib.cgx_timing_enable(ctx, -1) == B.CGX_ERR_INVALID_ARG
         assert lib.cgx_graph_launch(None, None) == B.CGX_ERR_INVALID_ARG
         assert lib.cgx_graph_destroy(None) == B.CGX_OK
