@@ -903,31 +903,34 @@ __device__ __forceinline__ f32x4_t mfma_split6(const Split8& A, const Split8& B,
 
 // ---------------------------------------------------------------------
 // a10, part 2: the per-row products of the decoder adjoint on MFMA.  A wave
-// takes 64 rows (four 16-row tiles) and, head by head,
+// takes 16 rows (one MFMA row tile) and, head by head,
 //   dz1_h = (dz2_h W2_h^T) * [z1_h > 0]: A = the rows' dz2 over the head's
 //           columns (K padded to 32), B = W2_h as (j, k), 2 column tiles;
 //   dz0  += dz1_h W1_h^T: A = dz1_h (K = 32, one k-step), B = W1 as
 //           (i, J), 3 column tiles (the 36 inputs padded to 48).
 // The A operands are float32 carried as three bf16 terms h + m + l (as in
 // the forward decode), B is exact, so each product costs three MFMAs and
-// keeps float32 accuracy.  dz2 comes straight from the row scratch; dz1_h
+// keeps float32 accuracy.  All of a group's reads (its rows, dz2, z1, then
+// the features of its anchors) are issued before the first product, so a
+// group waits on memory about twice rather than once per step.  dz1_h
 // goes through LDS (the C layout of the first product is not the A layout
 // of the second) and to the row scratch for the weight gradients.  Then
 // the first 32 columns of dz0 are the row's term of dF; the last four (the
 // direction / distance inputs) are taken back to the row's term of dx by
-// one lane per row, which also writes the row's z0 (bf16 features,
+// one lane per row; the wave also writes the rows' z0 (bf16 features,
 // direction, distance) for the weight gradients.  Blocks of kAdjWaves waves
 // share one weight staging and loop over row groups.
 // ---------------------------------------------------------------------
 constexpr int kAdjWaves = 4;
-constexpr int kAdjBlocks = 1024;         // grid bound (blocks loop over row groups)
+constexpr int kAdjRows = 16;             // rows per wave and group
+constexpr int kAdjBlocks = 2048;         // grid bound (blocks loop over row groups)
 
 template <class D>
 struct AdjLds {
   DecAdj<D> w;
-  float dz1[kAdjWaves][64][kHead + 4];   // one head's dz1 of the wave's rows
-  float tail[kAdjWaves][64][4];          // dz0 of the direction / distance inputs
-  uint32_t anchor[kAdjWaves][64];
+  float dz1[kAdjWaves][kAdjRows][kHead + 4];   // one head's dz1 of the wave's rows
+  float tail[kAdjWaves][kAdjRows][4];          // dz0 of the direction / distance inputs
+  uint32_t anchor[kAdjWaves][kAdjRows];
 };
 
 // 8 float32 -> three bf16x8 terms h, m, l
@@ -958,9 +961,14 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void k_decode_bwd_mlp(
     const Counters* ctr, const DecAdj<D>* __restrict__ wimg, float* __restrict__ scratch) {
   using A = DecAdj<D>;
   constexpr int kRS = D::kRowScratch;
+  constexpr int kSteps = [] {
+    int n = 0;
+    for (int h = 0; h < D::kHeads; ++h) n += A::kA2(h) / 32;
+    return n;
+  }();
   __shared__ AdjLds<D> L;
   const uint32_t n_rows = ctr->n_rows;
-  if ((uint64_t)blockIdx.x * kAdjWaves * 64 >= n_rows) return;   // uniform over the block
+  if ((uint64_t)blockIdx.x * kAdjWaves * kAdjRows >= n_rows) return;   // uniform over the block
   copy_weights(L.w, wimg);
   __syncthreads();
   const int lane = threadIdx.x % kWave;
@@ -970,81 +978,125 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void k_decode_bwd_mlp(
   float (*s_tail)[4] = L.tail[wave];
   uint32_t* s_anchor = L.anchor[wave];
 
-  for (uint64_t grp = (uint64_t)blockIdx.x * kAdjWaves + wave; grp * 64 < n_rows;
+  for (uint64_t grp = (uint64_t)blockIdx.x * kAdjWaves + wave; grp * kAdjRows < n_rows;
        grp += (uint64_t)gridDim.x * kAdjWaves) {
-    const uint32_t r0 = (uint32_t)(grp * 64);
+    const uint32_t r0 = (uint32_t)(grp * kAdjRows);
+    // reads, all issued up front: the row (lane % 16), the A fragments of
+    // dz2 of every head and k-step, and z1 at the C positions of dz1
+    // Loads take a row index clamped to the last row and a column inside
+    // the row's scratch (a padding column of a head reads the next values
+    // of the row), and the values are zeroed afterwards: no branch around
+    // a load, so they all stay in flight together.
+    const uint32_t last = n_rows - 1;
+    const uint32_t ra = r0 + col;
+    const bool live_a = ra < n_rows;
+    const uint32_t rac = live_a ? ra : last;
+    const int2 rw0 = rows[rac];
+    float v2[kSteps][8];
     {
-      const uint32_t r = r0 + lane;
-      s_anchor[lane] = r < n_rows ? (uint32_t)rows[r].y : 0u;
-    }
-    f32x4_t acc0[4][3];
+      int st = 0;
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+      for (int h = 0; h < D::kHeads; ++h) {
+        const float* src = scratch + (size_t)rac * kRS + D::kDZ2 + D::col0(h);
 #pragma unroll
-      for (int u = 0; u < 3; ++u) acc0[g][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-    for (int h = 0; h < D::kHeads; ++h) {
-      const int ncols = D::ncols(h);
-      // dz1_h before the mask
-      f32x4_t a1[4][2];
-#pragma unroll
-      for (int g = 0; g < 4; ++g) a1[g][0] = a1[g][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int st = 0; st < A::kA2(h) / 32; ++st) {
-        const int k0 = 32 * st + kq;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const uint32_t row = r0 + 16 * g + col;
-          const float* src = scratch + (size_t)row * kRS + D::kDZ2 + D::col0(h);
-          float v[8];
+        for (int k = 0; k < A::kA2(h) / 32; ++k, ++st) {
+          const int k0 = 32 * k + kq;
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            // the head's column count is even: a pair is valid or padding
-            const bool ok = row < n_rows && k0 + 2 * p < ncols;
-            const float2 x = ok ? *reinterpret_cast<const float2*>(src + k0 + 2 * p) : float2{0.f, 0.f};
-            v[2 * p] = x.x;
-            v[2 * p + 1] = x.y;
+            const float2 x = *reinterpret_cast<const float2*>(src + k0 + 2 * p);
+            v2[st][2 * p] = x.x;
+            v2[st][2 * p + 1] = x.y;
           }
-          const Split8 av = split8v(v);
+        }
+      }
+    }
+    float z1v[D::kHeads][2][4];
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const bf16x8_t bv = load8(&L.w.w2a[A::off2(h) + (16 * t + col) * A::kS2(h) + k0]);
-            a1[g][t] = mfma_split3(av, bv, a1[g][t]);
+    for (int h = 0; h < D::kHeads; ++h)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t row = r0 + rq + i;
+          z1v[h][t][i] = scratch[(size_t)(row < n_rows ? row : last) * kRS + D::kZ1 + kHead * h +
+                                 16 * t + col];
+        }
+    {
+      // zero what the clamped loads read for dead rows and padding columns
+      // (the head's column count is even: a pair is valid or padding)
+      int st = 0;
+#pragma unroll
+      for (int h = 0; h < D::kHeads; ++h)
+#pragma unroll
+        for (int k = 0; k < A::kA2(h) / 32; ++k, ++st)
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const bool ok = live_a && 32 * k + kq + 2 * p < D::ncols(h);
+            v2[st][2 * p] = ok ? v2[st][2 * p] : 0.0f;
+            v2[st][2 * p + 1] = ok ? v2[st][2 * p + 1] : 0.0f;
           }
+#pragma unroll
+      for (int h = 0; h < D::kHeads; ++h)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) z1v[h][t][i] = r0 + rq + i < n_rows ? z1v[h][t][i] : 0.0f;
+    }
+    const int2 rw = live_a ? rw0 : make_int2(0, 0);
+    if (lane < kAdjRows) s_anchor[lane] = (uint32_t)rw.y;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the features of the rows' anchors, for z0: element e = lane + 64 q is
+    // (row e / 32, feature e % 32)
+    constexpr int kFq = kAdjRows * CGX_FEAT_DIM / kWave;
+    float fv[kFq];
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      // a dead row's anchor is 0 (read, never written back)
+      const int rr = (lane >> 5) + 2 * q;
+      fv[q] = sc.F[(size_t)s_anchor[rr] * CGX_FEAT_DIM + (lane & 31)];
+    }
+
+    f32x4_t acc0[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) acc0[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    int st = 0;
+#pragma unroll
+    for (int h = 0; h < D::kHeads; ++h) {
+      // dz1_h before the mask
+      f32x4_t a1[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int k = 0; k < A::kA2(h) / 32; ++k, ++st) {
+        const Split8 av = split8v(v2[st]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const bf16x8_t bv = load8(&L.w.w2a[A::off2(h) + (16 * t + col) * A::kS2(h) + 32 * k + kq]);
+          a1[t] = mfma_split3(av, bv, a1[t]);
         }
       }
       // mask by z1 > 0, stage in LDS (row, j)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int rr = 16 * g + rq + i;
-            const int j = 16 * t + col;
-            const uint32_t row = r0 + rr;
-            const float z1 = row < n_rows ? scratch[(size_t)row * kRS + D::kZ1 + kHead * h + j] : 0.0f;
-            s_dz1[rr][j] = z1 > 0.0f ? a1[g][t][i] : 0.0f;
-          }
+        for (int i = 0; i < 4; ++i) s_dz1[rq + i][16 * t + col] = z1v[h][t][i] > 0.0f ? a1[t][i] : 0.0f;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // dz1_h to the row scratch: element e = lane + 64 q is (row e / 32, j e % 32)
-#pragma unroll 8
-      for (int q = 0; q < 32; ++q) {
+#pragma unroll
+      for (int q = 0; q < kAdjRows * kHead / kWave; ++q) {
         const int rr = (lane >> 5) + 2 * q, j = lane & 31;
         const uint32_t row = r0 + rr;
         if (row < n_rows) scratch[(size_t)row * kRS + D::kDZ1 + kHead * h + j] = s_dz1[rr][j];
       }
       // dz0 += dz1_h W1_h^T
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const Split8 av = split8(&s_dz1[16 * g + col][kq]);
+      {
+        const Split8 av = split8(&s_dz1[col][kq]);
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
           const bf16x8_t bv = load8(&L.w.w1a[(16 * u + col) * A::kS1 + kHead * h + kq]);
-          acc0[g][u] = mfma_split3(av, bv, acc0[g][u]);
+          acc0[u] = mfma_split3(av, bv, acc0[u]);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1053,34 +1105,30 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void k_decode_bwd_mlp(
     }
     // dz0: columns 0..31 are the row's term of dF, 32..35 the tail
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rr = 16 * g + rq + i;
-        const uint32_t row = r0 + rr;
-        if (row < n_rows) {
-          scratch[(size_t)row * kRS + D::kDF + col] = acc0[g][0][i];
-          scratch[(size_t)row * kRS + D::kDF + 16 + col] = acc0[g][1][i];
-        }
-        if (col < 4) s_tail[rr][col] = acc0[g][2][i];
+    for (int i = 0; i < 4; ++i) {
+      const int rr = rq + i;
+      const uint32_t row = r0 + rr;
+      if (row < n_rows) {
+        scratch[(size_t)row * kRS + D::kDF + col] = acc0[0][i];
+        scratch[(size_t)row * kRS + D::kDF + 16 + col] = acc0[1][i];
       }
+      if (col < 4) s_tail[rr][col] = acc0[2][i];
+    }
+    // z0 feature part, bf16(F)
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int rr = (lane >> 5) + 2 * q;
+      const uint32_t row = r0 + rr;
+      if (row < n_rows) scratch[(size_t)row * kRS + (lane & 31)] = bf16_round(fv[q]);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // z0 feature part, bf16(F): element e = lane + 64 q is (row e / 32, feature e % 32)
-#pragma unroll 8
-    for (int q = 0; q < 32; ++q) {
-      const int rr = (lane >> 5) + 2 * q, j = lane & 31;
-      const uint32_t row = r0 + rr;
-      if (row < n_rows)
-        scratch[(size_t)row * kRS + j] = bf16_round(sc.F[(size_t)s_anchor[rr] * CGX_FEAT_DIM + j]);
-    }
     // one lane per row: the direction / distance inputs, and their term of dx
-    const uint32_t r = r0 + lane;
-    if (r < n_rows) {
-      float* rs = scratch + (size_t)r * kRS;
-      const ViewDev& V = views[rows[r].x];
-      const uint32_t a = s_anchor[lane];
+    if (lane < kAdjRows && live_a) {
+      float* rs = scratch + (size_t)ra * kRS;
+      const ViewDev& V = views[rw.x];
+      const uint32_t a = (uint32_t)rw.y;
       float dir[3], dist;
       decoder_dir(V, sc, a, dir, dist);
       rs[CGX_FEAT_DIM + 0] = dir[0];
@@ -1305,7 +1353,7 @@ void launch_decode_project_backward(const ViewDev* views, int B, const cgx_ancho
     if (gblocks)
       hipLaunchKernelGGL(k_decode_bwd_gauss<D>, dim3(gblocks), dim3(256), 0, s, views, sc, rows,
                          ctr, counts, sgrad, scratch);
-    const uint32_t rblocks = std::min<uint32_t>(div_up(max_rows, kAdjWaves * 64), kAdjBlocks);
+    const uint32_t rblocks = std::min<uint32_t>(div_up(max_rows, kAdjWaves * kAdjRows), kAdjBlocks);
     if (rblocks)
       hipLaunchKernelGGL(k_decode_bwd_mlp<D>, dim3(rblocks), dim3(kAdjWaves * kWave), 0, s, views,
                          sc, rows, ctr, (const DecAdj<D>*)adjoint_weights<D>(scratch, max_rows),
