@@ -1208,19 +1208,36 @@ __global__ __launch_bounds__(kWgWaves * kWave) void k_wgrad_mfma(const float* __
   for (int e = tid; e < D::kN2 * kWR; e += blockDim.x)
     if (tile_column<D>(e / kWR) < 0) L.dz2t[e / kWR][e % kWR] = 0.0f;
 
-  for (uint64_t base = b0; base < b1; base += kWR) {
+  // Staging: element pair e of a step is values q0, q0 + 1 of row r, over
+  // the kRowUsed leading values of each row (even counts and strides, so a
+  // pair never straddles two rows and stays 8-byte aligned).  A step's pairs
+  // are loaded into registers while the previous step's products run (from
+  // clamped addresses; pairs past the chunk are zeroed when stored).
+  constexpr int kHalf = D::kRowUsed / 2;
+  constexpr int kPairs = kWR * kHalf;
+  constexpr int kPer = (kPairs + kWgWaves * kWave - 1) / (kWgWaves * kWave);
+  float2 nx[kPer];
+  auto load_step = [&](uint64_t base) {
     const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
     const float* src = scratch + base * D::kRowScratch;
-    // stage: element pair e of the chunk is values q0, q0 + 1 of row r, over
-    // the kRowUsed leading values of each row (even counts and strides, so a
-    // pair never straddles two rows and stays 8-byte aligned)
-    constexpr int kHalf = D::kRowUsed / 2;
-    constexpr int kPairs = kWR * kHalf;
-#pragma unroll 4
-    for (int e = tid; e < kPairs; e += kWgWaves * kWave) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + i * kWgWaves * kWave;
       const int r = e / kHalf, q0 = 2 * (e - r * kHalf);
-      const float2 x = r < nr ? *reinterpret_cast<const float2*>(src + (size_t)r * D::kRowScratch + q0)
-                              : float2{0.0f, 0.0f};
+      const bool ok = e < kPairs && r < nr;
+      nx[i] = *reinterpret_cast<const float2*>(src + (size_t)(ok ? r : 0) * D::kRowScratch +
+                                               (ok ? q0 : 0));
+    }
+  };
+  if (b0 < b1) load_step(b0);
+  for (uint64_t base = b0; base < b1; base += kWR) {
+    const int nr = (int)((b1 - base) < (uint64_t)kWR ? (b1 - base) : (uint64_t)kWR);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + i * kWgWaves * kWave;
+      if (e >= kPairs) continue;
+      const int r = e / kHalf, q0 = 2 * (e - r * kHalf);
+      const float2 x = r < nr ? nx[i] : float2{0.0f, 0.0f};
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         const int q = q0 + hh;
@@ -1236,16 +1253,17 @@ __global__ __launch_bounds__(kWgWaves * kWave) void k_wgrad_mfma(const float* __
           const int u = q - D::kDZ2;
           int h = 0;
 #pragma unroll
-          for (int i = 1; i < D::kHeads; ++i) h += u >= D::col0(i);
-          int p = u;
+          for (int j = 1; j < D::kHeads; ++j) h += u >= D::col0(j);
+          int pp = u;
 #pragma unroll
-          for (int i = 0; i < D::kHeads; ++i)
-            if (i == h) p = 16 * D::tile0(i) + (u - D::col0(i));
-          L.dz2t[p][r] = v;
+          for (int j = 0; j < D::kHeads; ++j)
+            if (j == h) pp = 16 * D::tile0(j) + (u - D::col0(j));
+          L.dz2t[pp][r] = v;
         }
       }
     }
     __syncthreads();
+    if (base + kWR < b1) load_step(base + kWR);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int c = tid + u * kWgWaves * kWave;
@@ -1307,8 +1325,9 @@ __global__ __launch_bounds__(kWgWaves * kWave) void k_wgrad_mfma(const float* __
 }
 
 // Sum of the block partials: a block reduces 32 outputs; thread (o, g) adds
-// partials g, g + 8, g + 16, ... of output o, then the 8 group sums are
-// added in group order (fixed order, deterministic).
+// partials g, g + 8, g + 16, ... of output o, eight loads in flight (into
+// eight running sums, added in order), then the 8 group sums are added in
+// group order (fixed order, deterministic).
 template <class D>
 __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ partial, int nb,
                                                      cgx_grads gr) {
@@ -1317,8 +1336,20 @@ __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ p
   const int ol = threadIdx.x & 31, g = threadIdx.x >> 5;
   const int o = blockIdx.x * 32 + ol;
   float s = 0.0f;
-  if (o < D::kWGrad)
-    for (int b = g; b < nb; b += 8) s += partial[(size_t)b * D::kWGrad + o];
+  if (o < D::kWGrad) {
+    float run[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int b = g;
+    for (; b + 56 < nb; b += 64) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(b + 8 * u) * D::kWGrad + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) run[u] += v[u];
+    }
+    for (; b < nb; b += 8) run[0] += partial[(size_t)b * D::kWGrad + o];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += run[u];
+  }
   red[g][ol] = s;
   __syncthreads();
   if (g != 0 || o >= D::kWGrad) return;
