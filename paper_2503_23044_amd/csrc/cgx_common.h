@@ -174,8 +174,12 @@ __device__ __forceinline__ double box_hi64(double u, double r) {
 // The per-(pixel, splat) exponent shared by the forward and backward raster
 // kernels: one function, so both compile to the same instruction sequence
 // and take the same decisions.  q = log2(o exp(power)); the pair is drawn
-// iff power <= 0 (q <= lno) and o exp(power) >= 1/255 (q >= log2(1/255)),
-// and then alpha = min(exp2(q), 0.99).
+// iff power <= 0 and o exp(power) >= 1/255 (q >= log2(1/255)), and then
+// alpha = min(exp2(q), 0.99).  power <= 0 holds by construction: the conic
+// is positive definite (a covariance plus the dilation), so the quadratic
+// form is never negative.  It is not tested: in float32 a nearly degenerate
+// conic can give the form a wrong sign by rounding, and the test would then
+// skip a pixel the exact value draws (with alpha near o).
 // ---------------------------------------------------------------------
 __device__ __forceinline__ float splat_q(float pa, float pb, float pc, float lno, float dx,
                                          float dy) {
@@ -183,7 +187,8 @@ __device__ __forceinline__ float splat_q(float pa, float pb, float pc, float lno
   return __builtin_fmaf(__builtin_fmaf(pa, dx, pb * dy), dx, __builtin_fmaf(pc * dy, dy, lno));
 }
 __device__ __forceinline__ bool splat_drawn(float q, float lno) {
-  return (q <= lno) & (q >= kLog2AlphaMin);
+  (void)lno;
+  return q >= kLog2AlphaMin;        // false for NaN
 }
 
 // Sum of a float over the 64 lanes of a wave, result valid in lane 63.
