@@ -351,9 +351,10 @@ __device__ __forceinline__ void decoded_gaussian(const cgx_anchor_scene& sc, uin
 }
 
 // ---------------------------------------------------------------------
-// a1 + a2 on MFMA.  One wave decodes 64 rows as four 16-row groups with
-// v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32 accumulation), one head
-// at a time:
+// a1 + a2 on MFMA.  A wave decodes a group of 16 rows (one MFMA row tile)
+// with v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32 accumulation), one
+// head at a time; the four waves of a block share one staging of the
+// weights and loop over the row groups:
 //   layer 1: [bf16(F) | 3-term bf16 split of (d~, Delta)] (K = 64) x W1'
 //            (64 x 32: the head's W1 feature rows, then its last four rows
 //            once per split term), 2 k-steps x 2 column tiles;
@@ -399,11 +400,15 @@ struct DecWB {
   float b2[D::kN2];
 };
 
+constexpr int kDecWaves = 4;       // waves per block, sharing one weight staging
+constexpr int kDecRows = 16;       // rows per wave and group (one MFMA row tile)
+constexpr int kDecBlocks = 2048;   // grid bound (blocks loop over row groups)
+
 template <class D>
 struct MfmaLds {
   DecWB<D> w;
-  uint16_t a1[64][kK1];         // A of layer 1 for the wave's 64 rows
-  uint16_t a2[64][kK2];         // A of layer 2 (one head at a time)
+  uint16_t a1[kDecWaves][kDecRows][kK1];   // A of layer 1 for a wave's 16 rows
+  uint16_t a2[kDecWaves][kDecRows][kK2];   // A of layer 2 (one head at a time)
 };
 
 __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
@@ -421,53 +426,62 @@ __device__ __forceinline__ bf16x8_t load8(const uint16_t* p) {
 }
 
 template <class D>
-__global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ views,
-                                                    cgx_anchor_scene sc,
-                                                    const int2* __restrict__ rows,
-                                                    const Counters* ctr,
-                                                    const DecWB<D>* __restrict__ wimg,
-                                                    float* __restrict__ row_scratch) {
+__global__ __launch_bounds__(kDecWaves * kWave) void k_decode_mfma(
+    const ViewDev* __restrict__ views, cgx_anchor_scene sc, const int2* __restrict__ rows,
+    const Counters* ctr, const DecWB<D>* __restrict__ wimg, float* __restrict__ row_scratch) {
   __shared__ MfmaLds<D> L;
-  const int lane = threadIdx.x;
   const uint32_t n_rows = ctr->n_rows;
-  const uint32_t r0 = blockIdx.x * 64;
-  if (r0 >= n_rows) return;
+  if ((uint64_t)blockIdx.x * kDecWaves * kDecRows >= n_rows) return;   // uniform over the block
   copy_weights(L.w, wimg);
-
-  // layer-1 operands of this lane's row
-  const uint32_t r = r0 + lane;
-  {
-    uint16_t* a = L.a1[lane];
-    if (r < n_rows) {
-      const int2 row = rows[r];
-      const ViewDev& V = views[row.x];
-      DecIn d;
-      decoder_input(V, sc, (uint32_t)row.y, d);
-#pragma unroll
-      for (int i = 0; i < 32; ++i) a[i] = bf16_bits_rne(d.z0[i]);   // exact: z0[i] is bf16
-#pragma unroll
-      for (int i = 0; i < 4; ++i) split3(d.z0[32 + i], a[32 + i], a[36 + i], a[40 + i]);
-#pragma unroll
-      for (int i = 44; i < kK1; ++i) a[i] = 0;
-    } else {
-#pragma unroll
-      for (int i = 0; i < kK1; ++i) a[i] = 0;
-    }
-  }
   __syncthreads();
-
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
   const int col = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  uint16_t (*a1)[kK1] = L.a1[wave];
+  uint16_t (*a2)[kK2] = L.a2[wave];
+  const uint32_t last = n_rows - 1;
+
+  for (uint64_t grp = (uint64_t)blockIdx.x * kDecWaves + wave; grp * kDecRows < n_rows;
+       grp += (uint64_t)gridDim.x * kDecWaves) {
+    const uint32_t r0 = (uint32_t)(grp * kDecRows);
+    // layer-1 operands: four lanes per row, lane part p takes features
+    // 8p .. 8p + 7 (exact in bf16: F is rounded to bf16 by definition), part
+    // 0 also the direction / distance inputs as three bf16 terms each.  A
+    // row past the count reads the last row and is never written back.
+    {
+      const int rl = lane >> 2, part = lane & 3;
+      const uint32_t rr = r0 + rl;
+      const int2 row = rows[rr < n_rows ? rr : last];
+      const float4* F4 = reinterpret_cast<const float4*>(sc.F + (size_t)row.y * CGX_FEAT_DIM) + 2 * part;
+      const float4 f0 = F4[0], f1 = F4[1];
+      const float fv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+      uint16_t* a = a1[rl];
 #pragma unroll
-  for (int h = 0; h < D::kHeads; ++h) {
-    // layer 1 -> the head's z1 (fp32), split into three bf16 terms for layer 2
+      for (int i = 0; i < 8; ++i) a[8 * part + i] = bf16_bits_rne(fv[i]);
+      if (part == 0) {
+        float dir[3], dist;
+        decoder_dir(views[row.x], sc, (uint32_t)row.y, dir, dist);
+        const float z[4] = {dir[0], dir[1], dir[2], dist / sc.d_max};
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+        for (int i = 0; i < 4; ++i) split3(z[i], a[32 + i], a[36 + i], a[40 + i]);
+      } else if (part == 1) {
+#pragma unroll
+        for (int i = 44; i < kK1; ++i) a[i] = 0;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+#pragma unroll
+    for (int h = 0; h < D::kHeads; ++h) {
+      // layer 1 -> the head's z1 (fp32), split into three bf16 terms for layer 2
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const bf16x8_t av = load8(&L.a1[g * 16 + col][ks * 32 + kq]);
+          const bf16x8_t av = load8(&a1[col][ks * 32 + kq]);
           const bf16x8_t bv = load8(&L.w.w1t[kHead * h + t * 16 + col][ks * 32 + kq]);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
         }
@@ -477,26 +491,25 @@ __global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ 
           const float z = fmaxf(acc[i] + L.w.b1[kHead * h + n], 0.0f);
           uint16_t zh, zm, zl;
           split3(z, zh, zm, zl);
-          uint16_t* a2 = L.a2[g * 16 + rq + i];
-          a2[n] = zh;
-          a2[32 + n] = zm;
-          a2[64 + n] = zl;
+          uint16_t* z2a = a2[rq + i];
+          z2a[n] = zh;
+          z2a[32 + n] = zm;
+          z2a[64 + n] = zl;
           // z1 kept for the adjoint (relu' = z1 > 0)
-          const uint32_t rr = r0 + g * 16 + rq + i;
+          const uint32_t rr = r0 + rq + i;
           if (rr < n_rows) row_scratch[(size_t)rr * D::kRowScratch + D::kZ1 + kHead * h + n] = z;
         }
       }
-    }
-    __syncthreads();
-
-    for (int g = 0; g < 4; ++g) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int t = 0; t < D::tiles(h); ++t) {
         const int T = D::tile0(h) + t;
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 3; ++ks) {
-          const bf16x8_t av = load8(&L.a2[g * 16 + col][ks * 32 + kq]);
+          const bf16x8_t av = load8(&a2[col][ks * 32 + kq]);
           const bf16x8_t bv = load8(&L.w.w2t[T * 16 + col][ks * 32 + kq]);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
         }
@@ -504,13 +517,16 @@ __global__ __launch_bounds__(64) void k_decode_mfma(const ViewDev* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float z = acc[i] + L.w.b2[T * 16 + col];
-          const uint32_t rr = r0 + g * 16 + rq + i;
+          const uint32_t rr = r0 + rq + i;
           if (c < D::ncols(h) && rr < n_rows)
             row_scratch[(size_t)rr * D::kRowScratch + D::kZ2 + D::col0(h) + c] = z;
         }
       }
+      // a2 is refilled by the next head, a1 by the next group
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (h + 1 < D::kHeads) __syncthreads();   // a2 is refilled by the next head
   }
 }
 
@@ -650,13 +666,15 @@ void launch_decode_project(const ViewDev* views, int B, const cgx_anchor_scene& 
   (void)B;
   const uint32_t blocks = div_up(max_rows, 64);
   if (blocks == 0) return;
+  const uint32_t dblocks =
+      std::min<uint32_t>(div_up(max_rows, kDecWaves * kDecRows), kDecBlocks);
   with_decoder(sc, [&](auto dec) {
     using D = decltype(dec);
     DecWB<D>* wb = decode_weights<D>(row_scratch, max_rows);
     hipLaunchKernelGGL(k_prep_weights<D>, dim3(div_up(prep_items<D>(), 256)), dim3(256), 0, s, sc,
                        wb, adjoint_weights<D>(row_scratch, max_rows));
-    hipLaunchKernelGGL(k_decode_mfma<D>, dim3(blocks), dim3(64), 0, s, views, sc, rows,
-                       (const Counters*)ctr, (const DecWB<D>*)wb, row_scratch);
+    hipLaunchKernelGGL(k_decode_mfma<D>, dim3(dblocks), dim3(kDecWaves * kWave), 0, s, views, sc,
+                       rows, (const Counters*)ctr, (const DecWB<D>*)wb, row_scratch);
     hipLaunchKernelGGL(k_project_decoded<D>, dim3(div_up((uint64_t)max_rows * kNOff, 256)),
                        dim3(256), 0, s, views, sc, rows, (const Counters*)ctr, tw, th,
                        (const float*)row_scratch, splats, counts, zkey, erec);
