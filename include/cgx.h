@@ -475,8 +475,9 @@ int32_t cgx_tune_tile_shape(cgx_ctx* ctx, const cgx_view* views, int32_t n_views
 
 /* Digit width of the radix sorts (binning, Sec. 3.3): each LSD sort splits
  * its significant bits (32 for the depth keys, the tile-id bits for the
- * pairs, 16 for the raster launch order) into equal digits of at most
- * `bits` bits, CGX_SORT_DIGIT_BITS_MIN..MAX (default 9).  Wider digits mean
+ * pairs, 16 for the raster launch order) into the fewest digits of at
+ * most `bits` bits, as equal as they go, the narrower ones first;
+ * CGX_SORT_DIGIT_BITS_MIN..MAX (default 9).  Wider digits mean
  * fewer passes over the keys but more digit values per pass; the sorted
  * result does not depend on the setting, nor do workspace sizes.  Later
  * launch chains of ctx use it.  Returns CGX_ERR_INVALID_ARG outside the

@@ -349,7 +349,7 @@ void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Count
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
 size_t sort_hist_words();
 // passes of an LSD sort on `bits` bits with digits of at most max_digit
-// (<= kMaxRadixBits) bits, split into equal widths
+// (<= kMaxRadixBits) bits, split as equally as they go (narrower first)
 int sort_passes(int bits, int max_digit);
 // stable LSD sort of 32-bit keys with 32-bit values on bits [0, bits);
 // returns the buffer index holding the result

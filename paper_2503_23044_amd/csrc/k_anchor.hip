@@ -98,18 +98,45 @@ static void with_decoder(const cgx_anchor_scene& sc, F&& f) {
 // ---------------------------------------------------------------------
 // a0: decisions in float64, fixed operation order, contraction off
 // ---------------------------------------------------------------------
-__device__ __forceinline__ bool anchor_active(const ViewDev& V, const float* X, const uint8_t* level,
-                                              uint32_t a, double dmax2) {
+// anchor at x (float32 values) with LoD level lv, active in view V
+__device__ __forceinline__ bool anchor_active(const ViewDev& V, double x0, double x1, double x2,
+                                              int lv, double dmax2) {
 #pragma clang fp contract(off)
-  const double x0 = X[3 * a], x1 = X[3 * a + 1], x2 = X[3 * a + 2];
   const double d0 = V.c[0] - x0, d1 = V.c[1] - x1, d2 = V.c[2] - x2;
   const double dist2 = (d0 * d0 + d1 * d1) + d2 * d2;
-  const int lv = level[a];
   const bool lod = (lv == 0) || (dist2 * (double)(1ull << (2 * lv)) <= dmax2);
-  if (!lod) return false;
   double p0, p1, p2;
   camera_point64(V, x0, x1, x2, p0, p1, p2);
-  return (p2 > (double)V.z_near) && (fabs(p0) <= V.gx * p2) && (fabs(p1) <= V.gy * p2);
+  return lod && (p2 > (double)V.z_near) && (fabs(p0) <= V.gx * p2) && (fabs(p1) <= V.gy * p2);
+}
+
+// Items (view, anchor) i = v A + a, kSelItems consecutive ones per thread
+// and step: their anchor loads are all issued before the tests (one item
+// per thread and step left the selection latency-bound on the loads).
+constexpr int kSelItems = 8;
+
+template <int N>
+__device__ __forceinline__ void select_flags(const ViewDev* __restrict__ views,
+                                             const cgx_anchor_scene& sc, uint64_t A, uint64_t i0,
+                                             uint64_t b1, double dmax2, uint32_t (&f)[N]) {
+  float x[N][3];
+  int lv[N];
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const uint64_t i = i0 + e;
+    const uint64_t ic = i < b1 ? i : i0;      // i0 < b1 whenever this is called
+    const uint32_t a = (uint32_t)(ic % A);
+    x[e][0] = sc.x[3 * (size_t)a];
+    x[e][1] = sc.x[3 * (size_t)a + 1];
+    x[e][2] = sc.x[3 * (size_t)a + 2];
+    lv[e] = sc.level[a];
+  }
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const uint64_t i = i0 + e;
+    const int v = (int)((i < b1 ? i : i0) / A);
+    f[e] = i < b1 && anchor_active(views[v], x[e][0], x[e][1], x[e][2], lv[e], dmax2) ? 1u : 0u;
+  }
 }
 
 __device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& b0, uint64_t& b1) {
@@ -148,9 +175,11 @@ __global__ __launch_bounds__(256) void k_select_count(const ViewDev* __restrict_
   uint64_t b0, b1;
   chunk_range(A * (uint64_t)B, b0, b1);
   unsigned long long cnt = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += 256) {
-    const int v = (int)(i / A);
-    cnt += anchor_active(views[v], sc.x, sc.level, (uint32_t)(i - (uint64_t)v * A), dmax2);
+  for (uint64_t i0 = b0 + (uint64_t)kSelItems * threadIdx.x; i0 < b1; i0 += (uint64_t)kSelItems * 256) {
+    uint32_t f[kSelItems];
+    select_flags(views, sc, A, i0, b1, dmax2, f);
+#pragma unroll
+    for (int e = 0; e < kSelItems; ++e) cnt += f[e];
   }
   unsigned long long tot;
   block_incl_scan256<unsigned long long>(cnt, lw, tot);
@@ -200,24 +229,28 @@ __global__ __launch_bounds__(256) void k_select_write(const ViewDev* __restrict_
   uint64_t b0, b1;
   chunk_range(A * (uint64_t)B, b0, b1);
   unsigned long long carry = part[blockIdx.x];
-  for (uint64_t base = b0; base < b1; base += 256) {
-    const uint64_t i = base + threadIdx.x;
-    int v = 0;
-    uint32_t a = 0;
-    unsigned long long f = 0;
-    if (i < b1) {
-      v = (int)(i / A);
-      a = (uint32_t)(i - (uint64_t)v * A);
-      f = anchor_active(views[v], sc.x, sc.level, a, dmax2);
-    }
+  for (uint64_t base = b0; base < b1; base += (uint64_t)kSelItems * 256) {
+    const uint64_t i0 = base + (uint64_t)kSelItems * threadIdx.x;
+    uint32_t f[kSelItems] = {};
+    if (i0 < b1) select_flags(views, sc, A, i0, b1, dmax2, f);
+    unsigned long long mine = 0;
+#pragma unroll
+    for (int e = 0; e < kSelItems; ++e) mine += f[e];
     unsigned long long tot;
-    const unsigned long long inc = block_incl_scan256<unsigned long long>(f, lw, tot);
-    if (i < b1) {
-      const unsigned long long pos = carry + inc - f;
-      if (a == 0) row_off[v] = (uint32_t)(pos < max_rows ? pos : max_rows);
-      const bool kept = f && pos < max_rows;
-      if (kept) rows[pos] = make_int2(v, (int)a);
-      rinv[i] = kept ? (uint32_t)pos : kNoRow;     // inverse map, index v * A + a
+    const unsigned long long inc = block_incl_scan256<unsigned long long>(mine, lw, tot);
+    unsigned long long pos = carry + inc - mine;
+#pragma unroll
+    for (int e = 0; e < kSelItems; ++e) {
+      const uint64_t i = i0 + e;
+      if (i < b1) {
+        const int v = (int)(i / A);
+        const uint32_t a = (uint32_t)(i - (uint64_t)v * A);
+        if (a == 0) row_off[v] = (uint32_t)(pos < max_rows ? pos : max_rows);
+        const bool kept = f[e] && pos < max_rows;
+        if (kept) rows[pos] = make_int2(v, (int)a);
+        rinv[i] = kept ? (uint32_t)pos : kNoRow;   // inverse map, index v * A + a
+      }
+      pos += f[e];
     }
     carry += tot;
   }
