@@ -436,18 +436,27 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   return CGX_OK;
 }
 
-__global__ void k_zero_sgrad(SplatGrad* g, const uint32_t* counts, const uint32_t* n_dev,
-                             uint32_t n_host) {
+// clears the gradient record of every splat that covers a tile; a wave
+// takes 64 records and writes them as four runs of 1 KB, lane l storing
+// float4 q * 64 + l of the 4 KB
+__global__ __launch_bounds__(256) void k_zero_sgrad(SplatGrad* g, const uint32_t* counts,
+                                                    const uint32_t* n_dev, uint32_t n_host) {
+  static_assert(sizeof(SplatGrad) == 4 * sizeof(float4), "four float4 per record");
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (counts[i] == 0) continue;
-    float4* p = reinterpret_cast<float4*>(&g[i]);
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    p[0] = z;
-    p[1] = z;
-    p[2] = z;
-    p[3] = z;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (uint32_t base = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; base < n;
+       base += waves * kWave) {
+    const uint32_t i = base + lane;
+    const uint64_t covered = __ballot(i < n && counts[i] != 0);
+    float4* p = reinterpret_cast<float4*>(g + base);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t f = q * kWave + lane;
+      if ((covered >> (f >> 2)) & 1ull) p[f] = z;
+    }
   }
 }
 

@@ -160,32 +160,69 @@ void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* o
 // ---------------------------------------------------------------------
 // a5: [start, end) of each global tile in the sorted pairs
 // ---------------------------------------------------------------------
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t n, uint32_t x) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] < x) lo = mid + 1;
-    else hi = mid;
+// Lower bounds of several keys at once, one group of kRangeLanes lanes per
+// key: each round a group probes kRangeLanes positions that cut its open
+// interval into kRangeLanes + 1 parts, and the number of probes below the
+// key (a ballot: the probes are monotone) names the part that holds the
+// bound. 27.5 M pairs take 8 dependent rounds instead of the 25 of a binary
+// search, and the rounds of the wave's groups overlap.
+constexpr int kRangeLanes = 8;
+
+__device__ __forceinline__ uint32_t probe_at(uint32_t lo, uint32_t len, uint32_t k) {
+  return lo + (uint32_t)(((uint64_t)len * (k + 1)) / (kRangeLanes + 1));
+}
+
+__device__ uint32_t group_lower_bound(const uint32_t* a, uint32_t n, uint32_t x) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t j = lane % kRangeLanes;
+  const uint32_t gshift = lane - j;
+  uint32_t lo = 0, hi = n;  // the bound lies in [lo, hi]
+  while (__any(lo < hi)) {
+    const uint32_t len = hi - lo;
+    const bool small = len <= kRangeLanes;
+    const uint32_t p = small ? lo + j : probe_at(lo, len, j);
+    const bool live = lo < hi && (!small || j < len);
+    const bool below = live && a[p] < x;
+    const uint32_t c = __popcll((__ballot(below) >> gshift) & ((1ull << kRangeLanes) - 1));
+    if (lo < hi) {
+      if (small) {
+        lo = hi = lo + c;
+      } else {
+        const uint32_t nlo = c > 0 ? probe_at(lo, len, c - 1) + 1 : lo;
+        hi = c < kRangeLanes ? probe_at(lo, len, c) : hi;
+        lo = nlo;
+      }
+    }
   }
   return lo;
 }
 
-// one thread per tile: its pairs are [lower_bound(t), lower_bound(t + 1))
-// of the tile-sorted keys; an empty tile gets [0, 0)
+// one wave per kRangeGroups - 1 tiles: group g takes the lower bound of tile
+// base + g in the tile-sorted keys, so tile base + g owns [bound(g),
+// bound(g + 1)); an empty tile gets [0, 0)
+constexpr int kRangeGroups = kWave / kRangeLanes;
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* keys_hi, const Counters* ctr,
                                                 uint2* ranges, uint32_t n_tiles) {
   const uint32_t P = ctr->n_pairs;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
-    const uint32_t s = lower_bound_u32(keys_hi, P, t);
-    const uint32_t e = s < P && keys_hi[s] == t ? lower_bound_u32(keys_hi + s, P - s, t + 1) + s : s;
-    ranges[t] = e > s ? make_uint2(s, e) : make_uint2(0u, 0u);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t g = lane / kRangeLanes;
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+       (uint64_t)w * (kRangeGroups - 1) < n_tiles; w += waves) {
+    const uint32_t t = w * (kRangeGroups - 1) + g;
+    const uint32_t s = group_lower_bound(keys_hi, P, t);
+    const uint32_t e = __shfl(s, lane + kRangeLanes, kWave);
+    if (lane % kRangeLanes == 0 && g + 1 < kRangeGroups && t < n_tiles)
+      ranges[t] = e > s ? make_uint2(s, e) : make_uint2(0u, 0u);
   }
 }
 
 void launch_ranges(const uint32_t* keys_hi, const Counters* ctr, uint2* ranges, uint32_t n_tiles,
                    uint32_t cap, hipStream_t s) {
   (void)cap;
-  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(n_tiles, 256), 8192));
+  const uint32_t waves = div_up(n_tiles, kRangeGroups - 1);
+  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(waves, 4), 16384));
   hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, keys_hi, ctr, ranges, n_tiles);
 }
 
