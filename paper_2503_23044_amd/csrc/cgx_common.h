@@ -213,13 +213,7 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Wave sum of 16 per-lane values, scattered over the lanes: on return lane l
-// holds the total of slot l & 15.  Within each 16-lane row, four halving
-// exchanges (partner lane = lane XOR 15, 7, 2, 1: row mirror, half-row
-// mirror and two quad permutations, all DPP) each send half of a lane's
-// partial sums to its partner and keep the other half; partner masks never
-// flip an earlier step's keep bit, so partners always hold the same slots.
-// The four rows are then summed with two row swaps (wave_sum_rows).
+// One lane's view of another lane's register within its 16-lane row (DPP).
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -240,30 +234,47 @@ __device__ __forceinline__ float wave_sum_rows(float d) {
   return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 
+// Sum of two registers' halves (v_permlane32_swap) or rows (v_permlane16_swap)
+// after the swap: lanes of the lower half (even rows) get x's pairwise sum,
+// those of the upper half (odd rows) y's.
+__device__ __forceinline__ float swap32_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sum of 16 per-lane values, scattered over the lanes: on return lane l
+// holds the total of slot (l >> 2) & 15, the same in the four lanes of a
+// quad.  Four halving exchanges each fold pairs of partial-sum registers
+// into one: a lane keeps one slot of the pair and its partner the other, so
+// the slot of a lane is fixed bit by bit (bits 5, 4, 3, 2 of the lane).
+// Partners are lane ^ 32 and lane ^ 16 (the row swaps above: one swap and
+// one add per pair) and lane ^ 15 and lane ^ 7 (row mirror and half-row
+// mirror, DPP: the lane sends the slot its partner keeps); no partner flips
+// an earlier exchange's keep bit, so partners always hold the same slots.
+// The two lane bits left are summed with two quad permutations.
 __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int lane) {
-  const bool f1 = (lane & 8) != 0, f2 = (lane & 4) != 0, f3 = (lane & 2) != 0,
-             f4 = (lane & 1) != 0;
+  const bool f3 = (lane & 8) != 0, f2 = (lane & 4) != 0;
   float a[8], b[4], c[2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const float send = f1 ? g[i] : g[8 + i];
-    const float keep = f1 ? g[8 + i] : g[i];
-    a[i] = keep + dpp_read<0x140>(send);            // row_mirror: lane ^ 15
-  }
+  for (int i = 0; i < 8; ++i) a[i] = swap32_add(g[i], g[8 + i]);   // slot i + 8 bit5
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float send = f2 ? a[i] : a[4 + i];
-    const float keep = f2 ? a[4 + i] : a[i];
-    b[i] = keep + dpp_read<0x141>(send);            // row_half_mirror: lane ^ 7
-  }
+  for (int i = 0; i < 4; ++i) b[i] = swap16_add(a[i], a[4 + i]);   // + 4 bit4
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const float send = f3 ? b[i] : b[2 + i];
     const float keep = f3 ? b[2 + i] : b[i];
-    c[i] = keep + dpp_read<0x4E>(send);             // quad_perm(2,3,0,1): lane ^ 2
+    c[i] = keep + dpp_read<0x140>(send);            // row_mirror: lane ^ 15; + 2 bit3
   }
-  float d = (f4 ? c[1] : c[0]) + dpp_read<0xB1>(f4 ? c[0] : c[1]);   // quad_perm(1,0,3,2)
-  return wave_sum_rows(d);
+  float d = (f2 ? c[1] : c[0]) + dpp_read<0x141>(f2 ? c[0] : c[1]);  // lane ^ 7; + bit2
+  d += dpp_read<0x4E>(d);                           // quad_perm(2,3,0,1): lane ^ 2
+  d += dpp_read<0xB1>(d);                           // quad_perm(1,0,3,2): lane ^ 1
+  return d;
 }
 
 // float atomic add without return (global_atomic_add_f32).

@@ -403,7 +403,8 @@ __device__ __forceinline__ void composite_bwd(
     const float alpha = ok ? (raw < kAlphaMax ? raw : kAlphaMax) : 0.0f;
     const float om = 1.0f - alpha;
     const float rom = __builtin_amdgcn_rcpf(om);
-    const float Tk = ok ? T[k] * rom : T[k];
+    // not drawn: alpha = 0, so om = 1, whose reciprocal is exactly 1
+    const float Tk = T[k] * rom;
     const float w = alpha * Tk;
     const float val = s.cr * GC0[k] + s.cg * GC1[k] + s.cb * GC2[k] + s.d * GD[k] +
                       s.nx * GN0[k] + s.ny * GN1[k] + s.nz * GN2[k];
@@ -441,10 +442,12 @@ __device__ __forceinline__ void composite_bwd(
     g[1] = kLn2 * (2.0f * s.pc * m1 + s.pb * m0);
     g[5] *= s.inv_o;
   }
-  // wave totals of the 13 terms land in lanes 0..12; one atomic
-  // instruction then adds them to the splat's 64-byte gradient record
+  // wave totals of the 13 terms land in the quads of lanes 0..51; one
+  // atomic instruction from each quad's first lane then adds them to the
+  // splat's 64-byte gradient record
   const float r = wave_reduce_scatter16(g, lane);
-  if (lane < 13 && r != 0.0f) atomic_add_f32(a.sgrad[slot].g + lane, r);
+  const int term = lane >> 2;
+  if ((lane & 3) == 0 && term < 13 && r != 0.0f) atomic_add_f32(a.sgrad[slot].g + term, r);
 }
 
 template <int TW, int TH, bool STATS>
