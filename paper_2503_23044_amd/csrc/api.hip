@@ -391,8 +391,10 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   phase_end(c, st);
   // pair offsets in depth order, pair emission, then the tile-id bits
   phase_begin(c, CGX_PHASE_DUPLICATE, st);
+  // the sorted depth keys are not read again: their buffer takes the counts
+  // gathered in depth order
   launch_scan_counts(P.counts, P.vslot[vb], P.offsets, P.part, &P.ctr->n_visible, n_slots,
-                     (uint32_t)L.max_pairs, P.ctr, P.bstart, st);
+                     (uint32_t)L.max_pairs, P.ctr, P.bstart, P.vkey[vb], st);
   launch_emit_pairs(P.erec, P.vslot[vb], P.offsets, P.bstart, P.ctr, (uint32_t)L.max_pairs,
                     P.pkey[0], P.pval[0], st);
   phase_end(c, st);

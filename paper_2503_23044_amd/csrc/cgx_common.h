@@ -349,7 +349,8 @@ __device__ __forceinline__ EmitRec emit_rec_of(const ViewDev& V, uint32_t bx, ui
 // below cap) the index i whose pair range holds that first pair.
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
-                        uint32_t cap, Counters* ctr, uint32_t* bstart, hipStream_t s);
+                        uint32_t cap, Counters* ctr, uint32_t* bstart, uint32_t* gathered,
+                        hipStream_t s);
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
                             uint32_t* vkey, uint32_t* vslot, hipStream_t s);

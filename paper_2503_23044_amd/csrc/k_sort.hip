@@ -325,6 +325,11 @@ int launch_sort_kv(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, 
 // ---------------------------------------------------------------------
 // 1: compact the visible splats (count > 0) in slot order, key = depth bits
 // ---------------------------------------------------------------------
+// A block walks its chunk in steps of 256 x kVisItems slots: a thread loads
+// the counts (and depth keys) of kVisItems slots 256 apart together, and the
+// step's kVisItems ballots share one LDS exchange of the wave counts.
+constexpr int kVisItems = 8;
+
 __global__ __launch_bounds__(256) void k_vis_partial(const uint32_t* __restrict__ counts,
                                                      const uint32_t* n_dev, uint32_t n_host,
                                                      unsigned long long* part) {
@@ -335,7 +340,17 @@ __global__ __launch_bounds__(256) void k_vis_partial(const uint32_t* __restrict_
   const uint64_t b0 = (uint64_t)blockIdx.x * per;
   const uint64_t b1 = b0 + per < n ? b0 + per : n;
   uint32_t c = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += 256) c += counts[i] != 0u;
+  for (uint64_t base = b0; base < b1; base += 256 * kVisItems) {
+    uint32_t v[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+      const uint64_t i = base + j * 256 + threadIdx.x;
+      v[j] = counts[i < b1 ? i : b1 - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j)
+      c += (base + j * 256 + threadIdx.x < b1) & (v[j] != 0u);
+  }
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
   if ((threadIdx.x & 63) == 0) lw[threadIdx.x / 64] = c;
   __syncthreads();
@@ -369,32 +384,47 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
                                                    const unsigned long long* part,
                                                    uint32_t* __restrict__ vkey,
                                                    uint32_t* __restrict__ vslot) {
-  __shared__ uint32_t lw[4];
+  __shared__ uint32_t lw[kVisItems][4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
   const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * per;
   const uint64_t b1 = b0 + per < n ? b0 + per : n;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint64_t lanes_below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   uint64_t carry = part[blockIdx.x];
-  for (uint64_t base = b0; base < b1; base += 256) {
-    const uint64_t i = base + threadIdx.x;
-    const bool f = i < b1 && counts[i] != 0u;
-    const uint64_t m = __ballot(f);
-    const uint32_t below = (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-    if (lane == 0) lw[wave] = (uint32_t)__popcll(m);
+  for (uint64_t base = b0; base < b1; base += 256 * kVisItems) {
+    uint32_t cnt[kVisItems], z[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+      const uint64_t i = base + j * 256 + threadIdx.x;
+      const uint64_t ic = i < b1 ? i : b1 - 1;
+      cnt[j] = counts[ic];
+      z[j] = zkey[ic];
+    }
+    uint64_t m[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+      m[j] = __ballot((base + j * 256 + threadIdx.x < b1) & (cnt[j] != 0u));
+      if (lane == 0) lw[j][wave] = (uint32_t)__popcll(m[j]);
+    }
     __syncthreads();
-    uint32_t wc = 0, tot = 0;
-    for (int w = 0; w < 4; ++w) {
-      if (w < wave) wc += lw[w];
-      tot += lw[w];
+    uint64_t pos0 = carry;
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+      uint32_t wc = 0, tot = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (w < wave) wc += lw[j][w];
+        tot += lw[j][w];
+      }
+      if ((m[j] >> lane) & 1ull) {
+        const uint64_t pos = pos0 + wc + (uint32_t)__popcll(m[j] & lanes_below);
+        vkey[pos] = z[j];
+        vslot[pos] = (uint32_t)(base + j * 256 + threadIdx.x);
+      }
+      pos0 += tot;
     }
-    if (f) {
-      const uint64_t pos = carry + wc + below;
-      vkey[pos] = zkey[i];
-      vslot[pos] = (uint32_t)i;
-    }
-    carry += tot;
+    carry = pos0;
     __syncthreads();
   }
 }

@@ -83,10 +83,38 @@ __device__ T block_inclusive_scan(T v, T* lds_waves, T& block_total) {
   return v + carry;
 }
 
-// phase 1: per-block sums of counts over a contiguous chunk
+// Each thread takes kScanItems consecutive elements of its block's chunk
+// and issues their loads together (the count of a visible splat is a gather
+// through its slot), so a block has 2,048 elements' loads in flight per step
+// instead of 256 chains of two dependent loads.
+constexpr int kScanItems = 8;
+
+// counts of elements i0 .. i0 + kScanItems - 1 (0 at and past b1; the chunk
+// [b0, b1) is non-empty, so the clamped index stays in it)
+__device__ __forceinline__ void load_counts(const uint32_t* counts, const uint32_t* idx,
+                                            uint64_t i0, uint64_t b1,
+                                            unsigned long long (&c)[kScanItems]) {
+  uint32_t id[kScanItems];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const uint64_t i = i0 + j < b1 ? i0 + j : b1 - 1;
+    id[j] = idx ? idx[i] : (uint32_t)i;
+  }
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) c[j] = counts[id[j]];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (i0 + j >= b1) c[j] = 0;
+}
+
+// phase 1: per-block sums of counts over a contiguous chunk; with an index
+// the gathered counts are also stored in index order (`gathered`), so that
+// phase 3 reads them coalesced instead of gathering a cache line per element
+// a second time
 __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, const uint32_t* idx,
                                                       const uint32_t* n_dev, uint32_t n_host,
-                                                      unsigned long long* part) {
+                                                      unsigned long long* part,
+                                                      uint32_t* gathered) {
   __shared__ unsigned long long lw[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -94,7 +122,16 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, co
   uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   unsigned long long sum = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) sum += counts[idx ? idx[i] : i];
+  for (uint64_t i0 = b0 + (uint64_t)threadIdx.x * kScanItems; i0 < b1;
+       i0 += (uint64_t)blockDim.x * kScanItems) {
+    unsigned long long c[kScanItems];
+    load_counts(counts, idx, i0, b1, c);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      sum += c[j];
+      if (gathered && i0 + j < b1) gathered[i0 + j] = (uint32_t)c[j];
+    }
+  }
   unsigned long long tot;
   block_inclusive_scan<unsigned long long>(sum, lw, tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -115,7 +152,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, uin
   }
 }
 
-// phase 3: scan within each chunk, offsets clamped to cap
+// phase 3: scan within each chunk, offsets clamped to cap; a thread scans
+// its kScanItems elements serially and the block scans the threads' sums
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, const uint32_t* idx,
                                                     uint32_t* offsets,
                                                     const uint32_t* n_dev, uint32_t n_host,
@@ -128,20 +166,34 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
   uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   unsigned long long carry = part[blockIdx.x];
-  for (uint64_t base = b0; base < b1; base += blockDim.x) {
-    uint64_t i = base + threadIdx.x;
-    unsigned long long c = i < b1 ? counts[idx ? idx[i] : i] : 0ull;
+  for (uint64_t base = b0; base < b1; base += (uint64_t)blockDim.x * kScanItems) {
+    const uint64_t i0 = base + (uint64_t)threadIdx.x * kScanItems;
+    unsigned long long c[kScanItems];
+    if (i0 < b1) {
+      load_counts(counts, idx, i0, b1, c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanItems; ++j) c[j] = 0;
+    }
+    unsigned long long run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) run += c[j];
     unsigned long long tot;
-    unsigned long long inc = block_inclusive_scan<unsigned long long>(c, lw, tot);
-    if (i < b1) {
-      unsigned long long off = carry + inc - c;
-      offsets[i] = (uint32_t)(off < cap ? off : cap);
-      if (bstart && c) {
-        // emission blocks whose first pair falls in [off, off + c)
-        const unsigned long long end = off + c < cap ? off + c : cap;
-        for (unsigned long long b = (off + kDupPairs - 1) / kDupPairs; b * kDupPairs < end; ++b)
-          bstart[b] = (uint32_t)i;
+    const unsigned long long inc = block_inclusive_scan<unsigned long long>(run, lw, tot);
+    unsigned long long off = carry + inc - run;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const uint64_t i = i0 + j;
+      if (i < b1) {
+        offsets[i] = (uint32_t)(off < cap ? off : cap);
+        if (bstart && c[j]) {
+          // emission blocks whose first pair falls in [off, off + c)
+          const unsigned long long end = off + c[j] < cap ? off + c[j] : cap;
+          for (unsigned long long b = (off + kDupPairs - 1) / kDupPairs; b * kDupPairs < end; ++b)
+            bstart[b] = (uint32_t)i;
+        }
       }
+      off += c[j];
     }
     carry += tot;
   }
@@ -149,12 +201,16 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
 
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
-                        uint32_t cap, Counters* ctr, uint32_t* bstart, hipStream_t s) {
+                        uint32_t cap, Counters* ctr, uint32_t* bstart, uint32_t* gathered,
+                        hipStream_t s) {
+  if (!idx) gathered = nullptr;
   hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, n_dev,
-                     n_host, part);
+                     n_host, part, gathered);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, part, cap, ctr);
-  hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, offsets,
-                     n_dev, n_host, (const unsigned long long*)part, cap, bstart);
+  hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s,
+                     gathered ? (const uint32_t*)gathered : counts,
+                     gathered ? nullptr : idx, offsets, n_dev, n_host,
+                     (const unsigned long long*)part, cap, bstart);
 }
 
 // ---------------------------------------------------------------------
