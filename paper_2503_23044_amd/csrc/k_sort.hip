@@ -522,6 +522,10 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ 
       }
       uint32_t jl = lo > 0 ? lo - 1 : 0;
       uint32_t key[kEmitPerThread], val[kEmitPerThread];
+      // the kept tiles of the current masked splat not yet emitted by this
+      // thread: its next pair takes the lowest set bit
+      uint32_t prev_j = 0xFFFFFFFFu;
+      uint64_t rest = 0;
 #pragma unroll
       for (int q = 0; q < kEmitPerThread; ++q) {
         const uint32_t i = i0 + q;
@@ -530,7 +534,17 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ 
         const uint32_t nxm = s_nx[jl];
         const uint32_t nx = nxm & 0xFFFF;
         // a masked box: the k-th kept tile is the k-th set bit (row-major)
-        if (nxm >> 16) k = kth_set_bit(s_mlo[jl], s_mhi[jl], k);
+        if (nxm >> 16) {
+          if (jl != prev_j) {
+            // a splat's first pair in this thread: its k-th set bit onwards
+            // (k = 0, the splat's first pair, unless it is the thread's first)
+            rest = ((uint64_t)s_mhi[jl] << 32) | s_mlo[jl];
+            if (k != 0) rest &= ~0ull << kth_set_bit(s_mlo[jl], s_mhi[jl], k);
+            prev_j = jl;
+          }
+          k = (uint32_t)__builtin_ctzll(rest);
+          rest &= rest - 1;
+        }
         // ty = k / nx: a float estimate (within one for k < 2^22 nx),
         // corrected to the exact quotient
         uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)nx));
