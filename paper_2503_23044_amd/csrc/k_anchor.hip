@@ -799,6 +799,12 @@ __global__ __launch_bounds__(256) void k_decode_bwd_gauss(const ViewDev* __restr
 // the table's offsets take no part and their gradient (if asked for) is
 // zero.
 constexpr int kGatherPerWave = 8;
+static_assert(kGatherPerWave * CGX_FEAT_DIM == 4 * kWave, "one float4 of F per lane");
+static_assert((kGatherPerWave * 3 * kNOff) % 4 == 0 && (kGatherPerWave * 3) % 4 == 0,
+              "whole float4 runs of O, x and l");
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return p == nullptr || ((uintptr_t)p & 15u) == 0;
+}
 constexpr int kGatherList = kGatherPerWave * CGX_MAX_VIEWS;
 constexpr int kGatherUnroll = 8;
 // list entry: row | anchor-in-wave << 29; rows number at most 2^31 / 10
@@ -836,6 +842,22 @@ __global__ __launch_bounds__(kWave) void k_anchor_grad(cgx_anchor_scene sc, int 
     n += (uint32_t)__popcll(m);
   }
   __syncthreads();
+  if (n == 0 && a0 + kGatherPerWave <= A && aligned16(gr.F) && aligned16(gr.O) &&
+      aligned16(gr.x) && aligned16(gr.l)) {
+    // no view selects any of the wave's anchors: their zeros as 16-byte
+    // stores over the contiguous rows of the group (1 KB of F, 960 B of O,
+    // 96 B each of x and l; a0 is a multiple of 8, so all start 16-byte
+    // aligned)
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    reinterpret_cast<float4*>(gr.F + (size_t)a0 * CGX_FEAT_DIM)[j] = z;
+    if (gr.O && j < kGatherPerWave * 3 * kNOff / 4)
+      reinterpret_cast<float4*>(gr.O + (size_t)a0 * 3 * kNOff)[j] = z;
+    if (j < kGatherPerWave * 3 / 4) {
+      reinterpret_cast<float4*>(gr.x + 3 * (size_t)a0)[j] = z;
+      reinterpret_cast<float4*>(gr.l + 3 * (size_t)a0)[j] = z;
+    }
+    return;
+  }
   float acc = 0.0f, accl = 0.0f, accx = 0.0f;
   int cur = -1;                                // anchor being summed (uniform)
   uint32_t done = 0;
