@@ -191,52 +191,17 @@ __device__ __forceinline__ bool splat_drawn(float q, float lno) {
   return q >= kLog2AlphaMin;        // false for NaN
 }
 
-// Sum of a float over the 64 lanes of a wave, result valid in lane 63.
-// Row-local shifts accumulate each 16-lane row into its lane 15, then the
-// row broadcasts of lane 15 and lane 31 carry the row totals to lane 63.
-__device__ __forceinline__ float wave_sum_lane63(float v) {
-  int x;
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true);  // row_shr:1
-  v += __int_as_float(x);
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true);  // row_shr:2
-  v += __int_as_float(x);
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true);  // row_shr:4
-  v += __int_as_float(x);
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true);  // row_shr:8
-  v += __int_as_float(x);
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false); // row_bcast:15
-  v += __int_as_float(x);
-  x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false); // row_bcast:31
-  v += __int_as_float(x);
-  return v;
-}
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
 // One lane's view of another lane's register within its 16-lane row (DPP).
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the four 16-lane rows, in every lane: (row 0 + row 1) + (row 2 +
-// row 3) lane by lane, with gfx950's row swaps (v_permlane16_swap exchanges
-// the odd rows of one operand with the even rows of the other,
-// v_permlane32_swap the upper half of one with the lower half of the other;
-// with both operands holding x, the two results add to the pairwise sums).
-// No LDS traffic, so no wait on the LDS / scalar-load counter.
-__device__ __forceinline__ float wave_sum_rows(float d) {
-  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(d), __float_as_uint(d), false,
-                                                    false);
-  d = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d), __float_as_uint(d), false,
-                                                    false);
-  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
-}
-
-// Sum of two registers' halves (v_permlane32_swap) or rows (v_permlane16_swap)
-// after the swap: lanes of the lower half (even rows) get x's pairwise sum,
-// those of the upper half (odd rows) y's.
+// Sum of two registers' halves or rows after a gfx950 row swap
+// (v_permlane32_swap exchanges the upper half of one operand with the lower
+// half of the other, v_permlane16_swap the odd rows of one with the even rows
+// of the other): lanes of the lower half (even rows) get x's pairwise sum,
+// those of the upper half (odd rows) y's.  No LDS traffic.
 __device__ __forceinline__ float swap32_add(float x, float y) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
                                                   false);
