@@ -382,8 +382,9 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   const uint32_t* n_dev = expl ? nullptr : &P.ctr->n_splats;
   // low 32 bits of the (tile | depth) keys: visible splats sorted by depth
   phase_begin(c, CGX_PHASE_SCAN, st);
+  const SlotPack pk = SlotPack::for_slots(n_slots);
   launch_compact_visible(P.counts, P.zkey, n_dev, n_slots, P.part, P.ctr, P.vkey[0], P.vslot[0],
-                         st);
+                         pk, st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
   const int vb = launch_sort_kv(P.vkey, P.vslot, &P.ctr->n_visible, n_slots, P.hist, 32,
@@ -394,9 +395,9 @@ static int32_t forward_chain(cgx_ctx* c, const cgx_view* views, int32_t B, const
   // the sorted depth keys are not read again: their buffer takes the counts
   // gathered in depth order
   launch_scan_counts(P.counts, P.vslot[vb], P.offsets, P.part, &P.ctr->n_visible, n_slots,
-                     (uint32_t)L.max_pairs, P.ctr, P.bstart, P.vkey[vb], st);
+                     (uint32_t)L.max_pairs, P.ctr, P.bstart, P.vkey[vb], pk, st);
   launch_emit_pairs(P.erec, P.vslot[vb], P.offsets, P.bstart, P.ctr, (uint32_t)L.max_pairs,
-                    P.pkey[0], P.pval[0], st);
+                    P.pkey[0], P.pval[0], pk, st);
   phase_end(c, st);
   phase_begin(c, CGX_PHASE_SORT, st);
   const int fb = launch_sort_kv(P.pkey, P.pval, &P.ctr->n_pairs, (uint32_t)L.max_pairs, P.hist,

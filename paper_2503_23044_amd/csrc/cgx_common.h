@@ -312,16 +312,40 @@ __device__ __forceinline__ EmitRec emit_rec_of(const ViewDev& V, uint32_t bx, ui
 // cap; the total becomes the pair count (overflow bit 2 above cap).  With
 // bstart, also records for every emission block b (first pair b * kDupPairs
 // below cap) the index i whose pair range holds that first pair.
+// A visible splat's entry in the depth sort: its slot in the low `bits`
+// bits and its tile count above them (counts that do not fit hold the
+// all-ones escape, and the count is then read from the splat's slot).  The
+// sort moves the entry with its key, so the offset scan finds the counts in
+// depth order without a gather per splat.  bits = 32 disables the packing.
+struct SlotPack {
+  uint32_t bits;
+  __host__ __device__ static SlotPack for_slots(uint32_t n_slots) {
+    uint32_t b = 1;
+    while (b < 32 && (n_slots - 1) >> b) ++b;
+    return SlotPack{32 - b >= 4 ? b : 32u};
+  }
+  __device__ uint32_t escape() const { return bits < 32 ? (1u << (32 - bits)) - 1u : 0u; }
+  __device__ uint32_t slot(uint32_t e) const { return bits < 32 ? e & ((1u << bits) - 1u) : e; }
+  __device__ uint32_t pack(uint32_t slot, uint32_t count) const {
+    return bits < 32 ? slot | (count < escape() ? count : escape()) << bits : slot;
+  }
+  // the packed count, or 0 where the count is to be read from the slot
+  __device__ uint32_t count(uint32_t e) const {
+    const uint32_t c = bits < 32 ? e >> bits : escape();
+    return c == escape() ? 0u : c;
+  }
+};
+
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
                         uint32_t cap, Counters* ctr, uint32_t* bstart, uint32_t* gathered,
-                        hipStream_t s);
+                        SlotPack pk, hipStream_t s);
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
-                            uint32_t* vkey, uint32_t* vslot, hipStream_t s);
+                            uint32_t* vkey, uint32_t* vslot, SlotPack pk, hipStream_t s);
 void launch_emit_pairs(const EmitRec* erec, const uint32_t* vslot, const uint32_t* voff,
                        const uint32_t* bstart, const Counters* ctr, uint32_t cap, uint32_t* pkey,
-                       uint32_t* pval, hipStream_t s);
+                       uint32_t* pval, SlotPack pk, hipStream_t s);
 void launch_gather_depth(const uint32_t* pval, const uint32_t* zkey, const Counters* ctr,
                          uint32_t n_slots, uint32_t cap, uint32_t* out, hipStream_t s);
 size_t sort_hist_words();

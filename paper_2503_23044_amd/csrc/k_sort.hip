@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
                                                    const uint32_t* n_dev, uint32_t n_host,
                                                    const unsigned long long* part,
                                                    uint32_t* __restrict__ vkey,
-                                                   uint32_t* __restrict__ vslot) {
+                                                   uint32_t* __restrict__ vslot, SlotPack pk) {
   __shared__ uint32_t lw[kVisItems][4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
       if ((m[j] >> lane) & 1ull) {
         const uint64_t pos = pos0 + wc + (uint32_t)__popcll(m[j] & lanes_below);
         vkey[pos] = z[j];
-        vslot[pos] = (uint32_t)(base + j * 256 + threadIdx.x);
+        vslot[pos] = pk.pack((uint32_t)(base + j * 256 + threadIdx.x), cnt[j]);
       }
       pos0 += tot;
     }
@@ -431,11 +431,11 @@ __global__ __launch_bounds__(256) void k_vis_write(const uint32_t* __restrict__ 
 
 void launch_compact_visible(const uint32_t* counts, const uint32_t* zkey, const uint32_t* n_dev,
                             uint32_t n_host, unsigned long long* part, Counters* ctr,
-                            uint32_t* vkey, uint32_t* vslot, hipStream_t s) {
+                            uint32_t* vkey, uint32_t* vslot, SlotPack pk, hipStream_t s) {
   hipLaunchKernelGGL(k_vis_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, n_dev, n_host, part);
   hipLaunchKernelGGL(k_vis_top, dim3(1), dim3(kScanBlocks), 0, s, part, ctr);
   hipLaunchKernelGGL(k_vis_write, dim3(kScanBlocks), dim3(256), 0, s, counts, zkey, n_dev,
-                     n_host, (const unsigned long long*)part, vkey, vslot);
+                     n_host, (const unsigned long long*)part, vkey, vslot, pk);
 }
 
 // ---------------------------------------------------------------------
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ 
                                                     const uint32_t* __restrict__ bstart,
                                                     const Counters* ctr,
                                                     uint32_t* __restrict__ pkey,
-                                                    uint32_t* __restrict__ pval) {
+                                                    uint32_t* __restrict__ pval, SlotPack pk) {
   constexpr int M = kDupPairs + 2;
   __shared__ uint32_t s_off[M];    // first pair of each visible splat of the block
   __shared__ uint32_t s_slot[M];
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ 
     const uint32_t m = span <= (uint32_t)M ? span : (uint32_t)M;
     // the block's splats, once: their pair offsets and emission records
     for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) {
-      const EmitRec r = erec[vslot[j0 + t]];
+      const EmitRec r = erec[pk.slot(vslot[j0 + t])];
       s_off[t] = voff[j0 + t];
       s_slot[t] = r.slot;
       s_base[t] = r.base;
@@ -570,12 +570,12 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const EmitRec* __restrict__ 
 
 void launch_emit_pairs(const EmitRec* erec, const uint32_t* vslot, const uint32_t* voff,
                        const uint32_t* bstart, const Counters* ctr, uint32_t cap, uint32_t* pkey,
-                       uint32_t* pval, hipStream_t s) {
+                       uint32_t* pval, SlotPack pk, hipStream_t s) {
   // the pair count is read on the device; the grid strides over blocks of
   // kDupPairs pairs
   const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, kDupPairs), 4096));
   hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(256), 0, s, erec, vslot, voff, bstart, ctr,
-                     pkey, pval);
+                     pkey, pval, pk);
 }
 
 // depth bits of every sorted pair (for the debug copy only)

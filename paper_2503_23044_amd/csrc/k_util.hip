@@ -92,7 +92,7 @@ constexpr int kScanItems = 8;
 // counts of elements i0 .. i0 + kScanItems - 1 (0 at and past b1; the chunk
 // [b0, b1) is non-empty, so the clamped index stays in it)
 __device__ __forceinline__ void load_counts(const uint32_t* counts, const uint32_t* idx,
-                                            uint64_t i0, uint64_t b1,
+                                            SlotPack pk, uint64_t i0, uint64_t b1,
                                             unsigned long long (&c)[kScanItems]) {
   uint32_t id[kScanItems];
 #pragma unroll
@@ -100,8 +100,12 @@ __device__ __forceinline__ void load_counts(const uint32_t* counts, const uint32
     const uint64_t i = i0 + j < b1 ? i0 + j : b1 - 1;
     id[j] = idx ? idx[i] : (uint32_t)i;
   }
+  // an index entry carries its count unless it holds the escape
 #pragma unroll
-  for (int j = 0; j < kScanItems; ++j) c[j] = counts[id[j]];
+  for (int j = 0; j < kScanItems; ++j) {
+    const uint32_t pc = idx ? pk.count(id[j]) : 0u;
+    c[j] = pc ? pc : counts[idx ? pk.slot(id[j]) : id[j]];
+  }
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j)
     if (i0 + j >= b1) c[j] = 0;
@@ -114,7 +118,7 @@ __device__ __forceinline__ void load_counts(const uint32_t* counts, const uint32
 __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, const uint32_t* idx,
                                                       const uint32_t* n_dev, uint32_t n_host,
                                                       unsigned long long* part,
-                                                      uint32_t* gathered) {
+                                                      uint32_t* gathered, SlotPack pk) {
   __shared__ unsigned long long lw[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t* counts, co
   for (uint64_t i0 = b0 + (uint64_t)threadIdx.x * kScanItems; i0 < b1;
        i0 += (uint64_t)blockDim.x * kScanItems) {
     unsigned long long c[kScanItems];
-    load_counts(counts, idx, i0, b1, c);
+    load_counts(counts, idx, pk, i0, b1, c);
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
       sum += c[j];
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
                                                     uint32_t* offsets,
                                                     const uint32_t* n_dev, uint32_t n_host,
                                                     const unsigned long long* part, uint32_t cap,
-                                                    uint32_t* bstart) {
+                                                    uint32_t* bstart, SlotPack pk) {
   __shared__ unsigned long long lw[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   if (n > n_host) n = n_host;
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
     const uint64_t i0 = base + (uint64_t)threadIdx.x * kScanItems;
     unsigned long long c[kScanItems];
     if (i0 < b1) {
-      load_counts(counts, idx, i0, b1, c);
+      load_counts(counts, idx, pk, i0, b1, c);
     } else {
 #pragma unroll
       for (int j = 0; j < kScanItems; ++j) c[j] = 0;
@@ -202,15 +206,15 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* counts, cons
 void launch_scan_counts(const uint32_t* counts, const uint32_t* idx, uint32_t* offsets,
                         unsigned long long* part, const uint32_t* n_dev, uint32_t n_host,
                         uint32_t cap, Counters* ctr, uint32_t* bstart, uint32_t* gathered,
-                        hipStream_t s) {
+                        SlotPack pk, hipStream_t s) {
   if (!idx) gathered = nullptr;
   hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, s, counts, idx, n_dev,
-                     n_host, part, gathered);
+                     n_host, part, gathered, pk);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, part, cap, ctr);
   hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(256), 0, s,
                      gathered ? (const uint32_t*)gathered : counts,
                      gathered ? nullptr : idx, offsets, n_dev, n_host,
-                     (const unsigned long long*)part, cap, bstart);
+                     (const unsigned long long*)part, cap, bstart, pk);
 }
 
 // ---------------------------------------------------------------------
