@@ -149,6 +149,7 @@ def _anchor_view0_case(wl, rd, sc, out, n_tiles, seed, tile=(16, 16)):
     torch.cuda.synchronize()
     sens = anchor_sensitivity(wl.scene, [v0], og, tile=tile, keep_tiles=keep, r0=r)
     _check_anchor_grads(gr, ref, sens)
+    return dbg
 
 
 def test_c3_full_size_sampled_tiles():
@@ -201,4 +202,16 @@ def test_c4_graph_autotuned_sampled_tiles():
     finally:
         B.cgx_graph_destroy(g)
     # the replayed images against the oracle, view 0, in the tuned tile shape
-    _anchor_view0_case(wl, rd, sc, out, 16, seed=2040, tile=tuple(tile))
+    dbg = _anchor_view0_case(wl, rd, sc, out, 16, seed=2040, tile=tuple(tile))
+    # With this many slots a depth-sort entry keeps 7 bits for the splat's
+    # tile count above its slot; larger counts hold the escape and are read
+    # from the slot. Both kinds occur here, and every splat's pair count was
+    # checked above.
+    n_slots = int(rd.cap["max_rows"]) * 10
+    bits = max(1, (n_slots - 1).bit_length())
+    esc = (1 << (32 - bits)) - 1
+    counts = np.asarray(dbg["counts"]).astype(np.int64)
+    print(f"  slot bits {bits}: {int((counts >= esc).sum())} splats at the count escape {esc}",
+          flush=True)
+    assert 32 - bits >= 4
+    assert (counts >= esc).any() and ((counts > 0) & (counts < esc)).any()
