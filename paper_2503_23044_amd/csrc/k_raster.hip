@@ -112,15 +112,11 @@ __device__ __forceinline__ uint32_t list_slot(const RasterArgs& a, uint32_t i, u
   return i < end ? load_const(a.vals + i) : a.n_slots;
 }
 
-// Mask of a slot's validity, folded into the sub-block mask: an invalid slot
-// (past the end of the list) touches nothing.
-__device__ __forceinline__ uint32_t slot_mask(const RasterArgs& a, uint32_t slot) {
-  return slot < a.n_slots ? ~0u : 0u;
-}
-
-// 64-byte record of a slot (scalar loads).  An invalid slot reads record 0
-// instead, so the load needs no branch; its slot_mask is 0.  Called only
-// while the list being walked is non-empty, so record 0 exists.
+// 64-byte record of a slot (scalar loads).  An invalid slot (the prefetch
+// past the end of a list) reads record 0 instead, so the load needs no
+// branch; such a record is never composited: the walks composite only list
+// positions before the end, and every sorted pair holds a valid slot.
+// Called only while the list being walked is non-empty, so record 0 exists.
 __device__ __forceinline__ Splat fetch_record(const RasterArgs& a, uint32_t slot) {
   return load_const(a.splats + (slot < a.n_slots ? slot : 0u));
 }
@@ -209,11 +205,11 @@ __device__ __forceinline__ bool fwd_pass(const SplatFwd& s, uint32_t lo, uint32_
 // wave's pixels; live is the mask of sub-blocks with an unfinished pixel
 // (wave-uniform).
 template <int TW, int TH, bool STATS, int PPL = TW * TH / kWave>
-__device__ __forceinline__ void composite_fwd(const SplatFwd& s, uint32_t valid, uint32_t idx,
+__device__ __forceinline__ void composite_fwd(const SplatFwd& s, uint32_t idx,
                                               int X0, int Y0, uint32_t& live, FwdPx<PPL>& P,
                                               uint32_t& evals) {
   const Box b = splat_box(s);
-  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & live & valid;
+  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & live;
   if (hit == 0) return;
   const uint32_t lo = (s.bx & 0xFFFFu) | (s.by << 16);
   const uint32_t wid = ((s.bx >> 16) | (s.by & 0xFFFF0000u)) - lo;
@@ -278,12 +274,12 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   for (uint32_t i = start; i < end && live != 0; i += 2) {
     sb = fetch_record_fwd(a, slot_b);
     const uint32_t next_a = list_slot(a, i + 2, end);
-    composite_fwd<TW, TH, STATS>(sa, slot_mask(a, slot_a), i - start + 1, X0, Y0, live, P, evals);
+    composite_fwd<TW, TH, STATS>(sa, i - start + 1, X0, Y0, live, P, evals);
     if (i + 1 >= end || live == 0) break;
     slot_a = next_a;
     sa = fetch_record_fwd(a, slot_a);
     const uint32_t next_b = list_slot(a, i + 3, end);
-    composite_fwd<TW, TH, STATS>(sb, slot_mask(a, slot_b), i - start + 2, X0, Y0, live, P, evals);
+    composite_fwd<TW, TH, STATS>(sb, i - start + 2, X0, Y0, live, P, evals);
     slot_b = next_b;
   }
 
@@ -376,7 +372,7 @@ __device__ __forceinline__ void composite_bwd(
   uint32_t alive = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) alive |= (le_bit((int)blast[k], j) ^ 1u) << k;
-  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & alive & slot_mask(a, slot);
+  const uint32_t hit = sub_hits<TW, TH>(b, X0, Y0) & alive;
   if (hit == 0) return;
   float g[16];
 #pragma unroll
