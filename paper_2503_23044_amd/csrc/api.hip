@@ -207,7 +207,9 @@ static int32_t make_layout(cgx_ctx* c, const cgx_view* views, int32_t B, const c
   }
   for (int b = 0; b < 2; ++b) {
     L.pkey[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
-    L.pval[b] = take(sizeof(uint32_t) * (size_t)L.max_pairs);
+    // the forward raster prefetches the slots of list positions up to two
+    // past a list's end without a bounds test: a tail of kListPad entries
+    L.pval[b] = take(sizeof(uint32_t) * ((size_t)L.max_pairs + kListPad));
   }
   L.hist = take(sizeof(uint32_t) * sort_hist_words());
   L.ranges = take(sizeof(uint2) * (size_t)tiles);

@@ -26,6 +26,7 @@ namespace cgx {
 
 constexpr int kWave = 64;
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
+constexpr int kListPad = 4;         // entries after the pair values, read but never used
 constexpr int kSortBlocks = 2048;   // largest grid of a radix-sort pass
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;      // keys per thread per sort tile

@@ -107,9 +107,13 @@ __device__ __forceinline__ T load_const(const T* p) {
   return r;
 }
 
-// Slot of list position i (a scalar load), or n_slots past the end.
-__device__ __forceinline__ uint32_t list_slot(const RasterArgs& a, uint32_t i, uint32_t end) {
-  return i < end ? load_const(a.vals + i) : a.n_slots;
+// Slot of list position i (a scalar load), taken without a bounds test: the
+// walk asks for positions at most two past its list's end, which the value
+// buffer's tail of kListPad entries covers.  What a position past the end
+// holds (the next list's slot, or an unwritten tail entry) is only
+// prefetched, never composited; fetch_record_fwd clamps it to a record.
+__device__ __forceinline__ uint32_t list_slot(const RasterArgs& a, uint32_t i) {
+  return load_const(a.vals + i);
 }
 
 // 64-byte record of a slot (scalar loads).  An invalid slot (the prefetch
@@ -268,17 +272,17 @@ __global__ __launch_bounds__(kWave) void k_raster_fwd(RasterArgs a) {
   // before the other buffer's loads are issued.
   // records are read only for a non-empty list (then the splat table holds
   // at least one slot, which past-the-end positions read instead)
-  uint32_t slot_a = list_slot(a, start, end), slot_b = list_slot(a, start + 1, end);
+  uint32_t slot_a = list_slot(a, start), slot_b = list_slot(a, start + 1);
   SplatFwd sa = {}, sb;
   if (start < end) sa = fetch_record_fwd(a, slot_a);
   for (uint32_t i = start; i < end && live != 0; i += 2) {
     sb = fetch_record_fwd(a, slot_b);
-    const uint32_t next_a = list_slot(a, i + 2, end);
+    const uint32_t next_a = list_slot(a, i + 2);
     composite_fwd<TW, TH, STATS>(sa, i - start + 1, X0, Y0, live, P, evals);
     if (i + 1 >= end || live == 0) break;
     slot_a = next_a;
     sa = fetch_record_fwd(a, slot_a);
-    const uint32_t next_b = list_slot(a, i + 3, end);
+    const uint32_t next_b = list_slot(a, i + 3);
     composite_fwd<TW, TH, STATS>(sb, i - start + 2, X0, Y0, live, P, evals);
     slot_b = next_b;
   }
